@@ -1,0 +1,238 @@
+/*
+ * oceansim.h -- C ABI of the MI355X (gfx950) OceanSim image-formation library.
+ *
+ * Computes, on the GPU, the data-parallel part of the sensor models of
+ * "OceanSim: A GPU-Accelerated Underwater Robot Perception Simulation
+ * Framework" (arXiv 2503.01074):
+ *
+ *   - imaging-sonar image formation from ray-cast returns (Sec. III-A.2):
+ *     per-return intensity (Eq. 2), range x azimuth binning by summation,
+ *     a scalar gain, speckle noise (Eq. 3-6, or a gamma-distributed
+ *     multiplicative speckle), and a polar-to-Cartesian fan image;
+ *   - the underwater colour image-formation model (Sec. III-A.1, Eq. 1).
+ *
+ * plus the adjoints of both with respect to their physical parameters.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  - Every pointer named *_dev or held in a frame descriptor is DEVICE memory
+ *    of the current HIP device.  Descriptors and sizes are host memory and are
+ *    not retained after the call returns (plans excepted, see below).
+ *  - The caller owns and frees every buffer.  Plain calls allocate nothing:
+ *    scratch memory is the caller's workspace, sized by the matching
+ *    *_workspace_size query; it must be 256-byte aligned.
+ *  - Calls are asynchronous on `stream` (a hipStream_t; NULL = the null
+ *    stream) and never synchronise it.
+ *  - Arguments are validated before anything is enqueued.  On error nothing
+ *    is enqueued, a negative oceansim_status is returned and
+ *    oceansim_last_error() (per thread) describes it.  No call aborts or
+ *    throws.  Faults of enqueued kernels surface as OCEANSIM_E_HIP from a
+ *    later call or from the caller's own synchronisation.
+ *  - Image and polar buffers, J, depth and gradient images must be 16-byte
+ *    aligned (float4 access); misalignment is OCEANSIM_E_INVALID_ARG.
+ *  - Gradient outputs are overwritten, never accumulated.
+ *  - Physical parameters live in device-resident rows so that an optimiser
+ *    can update them in place between calls; the library reads them on the
+ *    device and does not check their values (a non-finite value gives
+ *    non-finite outputs, never an out-of-bounds access).
+ */
+#ifndef OCEANSIM_H
+#define OCEANSIM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define OCEANSIM_ABI_VERSION 1
+
+typedef enum {
+    OCEANSIM_OK = 0,
+    OCEANSIM_E_INVALID_ARG = -1,  /* NULL / misaligned pointer, bad enum, bad value */
+    OCEANSIM_E_SHAPE = -2,        /* sizes out of range or inconsistent            */
+    OCEANSIM_E_WORKSPACE = -3,    /* workspace too small or misaligned            */
+    OCEANSIM_E_UNSUPPORTED = -4,  /* valid request beyond this build's limits     */
+    OCEANSIM_E_HIP = -5           /* a HIP runtime call failed                     */
+} oceansim_status;
+
+/* Text for the last non-OK status returned on the calling thread. */
+const char *oceansim_last_error(void);
+
+/* OCEANSIM_ABI_VERSION of the loaded library. */
+int oceansim_abi_version(void);
+
+/* ======================================================================== */
+/* Imaging sonar (Sec. III-A.2)                                             */
+/* ======================================================================== */
+
+/* Speckle model applied after binning and gain.
+ *  OFF   : out = Q                                (no noise)
+ *  PAPER : out = Q (0.5 + w_sm) + w~_sa           Eq. (3)-(6)
+ *  GAMMA : out = Q m + w~_sa,  m ~ Gamma(k, 1/k)  (unit-mean multiplicative
+ *          speckle of integer shape k in 1..8, additive term of Eq. 3-4)
+ * where Q = G P is the gained bin sum and
+ *   w~_sa = (r_i^2 / r_max^2) (1 + 0.5 exp(-phi_j^2 / sigma_phi) w_sa),
+ *   w_sa ~ Rayleigh(sigma_sa),  w_sm ~ N(0, sigma_sm^2),
+ * at the bin centre (r_i, phi_j).  Random numbers come from Philox4x32-10
+ * (Salmon et al., SC'11) keyed by (seed_lo, seed_hi); bin b = i N_phi + j of
+ * frame frame_id draws
+ *   additive  : counter (b/4, frame_id, 0, 0), word b%4
+ *   gaussian  : counter (b/2, frame_id, 1, 0), words 2(b%2), 2(b%2)+1
+ *               (Box-Muller, cosine branch)
+ *   gamma     : counter (b, frame_id, 2, g), words 0..3, g = 0, 1
+ * each word w mapping to the uniform ((w >> 8) + 1) 2^-24 in (0, 1].      */
+enum {
+    OCEANSIM_SPECKLE_OFF = 0,
+    OCEANSIM_SPECKLE_PAPER = 1,
+    OCEANSIM_SPECKLE_GAMMA = 2
+};
+
+/* One DEVICE-resident row of differentiable sonar parameters (32 bytes).
+ * Frames select a row with oceansim_sonar_frame.param_row.               */
+typedef struct {
+    float alpha;      /* Eq. 2 attenuation coefficient [1/m]             */
+    float gain;       /* G, applied to the bin sums                      */
+    float sigma_phi;  /* Eq. 3 beam-pattern parameter [rad^2]            */
+    float sigma_sa;   /* Eq. 4 Rayleigh parameter of the additive speckle */
+    float sigma_sm;   /* Eq. 6 std. dev. of the multiplicative speckle   */
+    float reserved[3];
+} oceansim_sonar_params;
+
+/* Columns of a sonar gradient row (one row per parameter row). */
+enum {
+    OCEANSIM_SONAR_GRAD_ALPHA = 0,
+    OCEANSIM_SONAR_GRAD_GAIN = 1,
+    OCEANSIM_SONAR_GRAD_SIGMA_PHI = 2,
+    OCEANSIM_SONAR_GRAD_SIGMA_SA = 3,
+    OCEANSIM_SONAR_GRAD_SIGMA_SM = 4,
+    OCEANSIM_SONAR_GRAD_WIDTH = 8
+};
+
+/* One sonar frame: its returns, sensor geometry, RNG key and outputs.
+ *
+ * Returns (the paper's point set Q of in-view, unoccluded ray hits) are a
+ * structure of arrays in the sensor frame: x forward, y left, z up, metres.
+ * (nx, ny, nz) is the surface normal (any length; normalised internally).
+ * mat[k] indexes the reflectivity table (A_r of Eq. 2, one entry per
+ * material or semantic class); mat < 0 or mat >= n_materials is a miss.
+ *
+ * A hit counts if r = |x| lies in [r_min, r_max), the azimuth
+ * phi = atan2(y, x) in [-fov_az/2, fov_az/2) and |z| <= r sin(fov_el/2).
+ * Its intensity is refl[mat] * max(0, -x.n / (|x||n|)) * exp(-path_factor
+ * alpha r) (Eq. 2; path_factor 2 = two-way travel, 1 = Eq. 2 literally).
+ * It is summed into bin (i, j), i = floor((r - r_min) N_r / (r_max - r_min)),
+ * j = floor((phi + fov_az/2) N_phi / fov_az); bins are row-major [N_r][N_phi].
+ *
+ * Fan (fan_h x fan_w > 0): apex at the bottom centre, boresight up, the
+ * sensor's left on the image's left, square pixels of side
+ * s = max(r_max / fan_h, 2 r_max sin(fov_az/2) / fan_w) (needs fov_az <= pi);
+ * pixel (v, u) at x_c = (u + 1/2 - fan_w/2) s, y_c = (fan_h - v - 1/2) s,
+ * rho = hypot(x_c, y_c), phi = atan2(-x_c, y_c).  Pixels with rho outside
+ * [r_min, r_max] or |phi| > fov_az/2 are 0; others are the bilinear
+ * interpolation of the polar image at bin centres, clamped to the grid.
+ */
+typedef struct {
+    const float *x, *y, *z;          /* [n_returns] device                   */
+    const float *nx, *ny, *nz;       /* [n_returns] device                   */
+    const int32_t *mat;              /* [n_returns] device                   */
+    int64_t n_returns;               /* >= 0 (0 = an empty scene)            */
+    float r_min, r_max;              /* metres, 0 <= r_min < r_max           */
+    float fov_az, fov_el;            /* radians, full angles (0, 2pi], (0, pi] */
+    float path_factor;               /* kappa >= 0                           */
+    int32_t n_range, n_azimuth;      /* polar bins, N_r x N_phi              */
+    int32_t fan_h, fan_w;            /* fan pixels, 0 x 0 = no fan           */
+    int32_t speckle_mode;            /* OCEANSIM_SPECKLE_*                   */
+    int32_t gamma_k;                 /* GAMMA shape, 1..8                    */
+    int32_t param_row;               /* row of the parameter table           */
+    uint32_t seed_lo, seed_hi;       /* Philox key                           */
+    uint32_t frame_id;               /* Philox counter word 1                */
+    float *polar;                    /* out [N_r][N_phi] or NULL             */
+    float *fan;                      /* out [fan_h][fan_w] or NULL           */
+    int32_t *bin_of_return;          /* out [n_returns] bin or -1, or NULL   */
+    const float *grad_polar;         /* backward in [N_r][N_phi] or NULL (0) */
+    const float *grad_fan;           /* backward in [fan_h][fan_w] or NULL   */
+} oceansim_sonar_frame;
+
+/* Workspace bytes for oceansim_sonar_render (with_backward = 0) or for
+ * oceansim_sonar_render_backward (with_backward = 1) on these frames. */
+int oceansim_sonar_workspace_size(const oceansim_sonar_frame *frames, int32_t n_frames,
+                                  int32_t n_materials, int32_t with_backward, size_t *bytes);
+
+/* Forward sonar rendering of n_frames frames (uneven sizes allowed) in one
+ * set of launches.  params_dev: [n_param_rows] device rows; refl_dev:
+ * [n_materials] device reflectivities.  For every frame, polar and/or fan
+ * must be non-NULL.  Bin sums are accumulated in float32 in an order that
+ * may change between runs (results may differ in the last bits). */
+int oceansim_sonar_render(const oceansim_sonar_frame *frames, int32_t n_frames,
+                          const oceansim_sonar_params *params_dev, int32_t n_param_rows,
+                          const float *refl_dev, int32_t n_materials,
+                          void *workspace, size_t workspace_bytes, void *stream);
+
+/* Gradient of L = sum_f <grad_polar_f, polar_f> + <grad_fan_f, fan_f> with
+ * respect to the reflectivity table (grad_refl_dev [n_materials]) and every
+ * parameter row (grad_params_dev [n_param_rows][OCEANSIM_SONAR_GRAD_WIDTH],
+ * columns OCEANSIM_SONAR_GRAD_*; unused columns are written 0).  The forward
+ * pass is recomputed from the returns and the RNG counters; nothing is saved
+ * between the calls.  Reductions use a fixed order: repeated calls on the
+ * same inputs give bit-identical gradients when n_materials <= 64. */
+int oceansim_sonar_render_backward(const oceansim_sonar_frame *frames, int32_t n_frames,
+                                   const oceansim_sonar_params *params_dev, int32_t n_param_rows,
+                                   const float *refl_dev, int32_t n_materials,
+                                   float *grad_refl_dev, float *grad_params_dev,
+                                   void *workspace, size_t workspace_bytes, void *stream);
+
+/* ======================================================================== */
+/* Underwater colour image formation (Sec. III-A.1, Eq. 1)                  */
+/*   I_c = J_c exp(-beta_D,c d) + B_inf,c (1 - exp(-beta_B,c d))            */
+/* beta_D is the paper's beta_attn and beta_B its beta_bs; beta*d is taken  */
+/* as 0 when beta = 0.                                                      */
+/* ======================================================================== */
+
+/* One DEVICE-resident row of water parameters (48 bytes), channels R, G, B. */
+typedef struct {
+    float beta_d[3];
+    float beta_b[3];
+    float b_inf[3];
+    float reserved[3];
+} oceansim_water_params;
+
+/* Columns of a water gradient row: beta_d[0..2], beta_b[0..2], b_inf[0..2]. */
+#define OCEANSIM_WATER_GRAD_WIDTH 9
+
+/* One camera frame.  J and out are planar [3][H][W] float32; depth [H][W]. */
+typedef struct {
+    const float *J;            /* in-air image                            */
+    const float *depth;        /* metres                                  */
+    float *out;                /* forward output (may alias nothing)      */
+    int32_t H, W;
+    int32_t param_row;         /* row of the water table                  */
+    const float *grad_out;     /* backward input [3][H][W]                */
+    float *grad_J;             /* backward output [3][H][W] or NULL       */
+    float *grad_depth;         /* backward output [H][W] or NULL          */
+} oceansim_uw_frame;
+
+/* Eq. (1) on n_frames images (uneven sizes allowed) in one launch. */
+int oceansim_uw_form(const oceansim_uw_frame *frames, int32_t n_frames,
+                     const oceansim_water_params *params_dev, int32_t n_param_rows,
+                     void *workspace, size_t workspace_bytes, void *stream);
+
+/* Workspace bytes for oceansim_uw_form (with_backward = 0) or
+ * oceansim_uw_form_backward (with_backward = 1). */
+int oceansim_uw_workspace_size(const oceansim_uw_frame *frames, int32_t n_frames,
+                               int32_t with_backward, size_t *bytes);
+
+/* Gradient of L = sum_f <grad_out_f, out_f> with respect to every water row
+ * (grad_params_dev [n_param_rows][OCEANSIM_WATER_GRAD_WIDTH]) and, where
+ * requested, to J and depth.  Fixed-order reductions: bit-reproducible. */
+int oceansim_uw_form_backward(const oceansim_uw_frame *frames, int32_t n_frames,
+                              const oceansim_water_params *params_dev, int32_t n_param_rows,
+                              float *grad_params_dev, void *workspace, size_t workspace_bytes,
+                              void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* OCEANSIM_H */

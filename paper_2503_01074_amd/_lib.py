@@ -1,0 +1,163 @@
+"""ctypes binding of liboceansim.so: structures mirroring include/oceansim.h and
+the entry points under their C names.  Argument marshalling only; every step of
+the computation runs in the library's HIP kernels.  There is no fallback: if
+the library is missing the import fails.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "liboceansim.so")
+
+OCEANSIM_OK = 0
+OCEANSIM_E_INVALID_ARG = -1
+OCEANSIM_E_SHAPE = -2
+OCEANSIM_E_WORKSPACE = -3
+OCEANSIM_E_UNSUPPORTED = -4
+OCEANSIM_E_HIP = -5
+STATUS_NAMES = {0: "OK", -1: "E_INVALID_ARG", -2: "E_SHAPE", -3: "E_WORKSPACE", -4: "E_UNSUPPORTED",
+                -5: "E_HIP"}
+
+SPECKLE_OFF, SPECKLE_PAPER, SPECKLE_GAMMA = 0, 1, 2
+SONAR_GRAD_WIDTH = 8
+SONAR_GRAD_COLUMNS = ("alpha", "gain", "sigma_phi", "sigma_sa", "sigma_sm")
+WATER_GRAD_WIDTH = 9
+
+_P = C.c_void_p
+
+
+class SonarParams(C.Structure):
+    _fields_ = [("alpha", C.c_float), ("gain", C.c_float), ("sigma_phi", C.c_float),
+                ("sigma_sa", C.c_float), ("sigma_sm", C.c_float), ("reserved", C.c_float * 3)]
+
+
+class SonarFrame(C.Structure):
+    _fields_ = [("x", _P), ("y", _P), ("z", _P), ("nx", _P), ("ny", _P), ("nz", _P), ("mat", _P),
+                ("n_returns", C.c_int64),
+                ("r_min", C.c_float), ("r_max", C.c_float), ("fov_az", C.c_float),
+                ("fov_el", C.c_float), ("path_factor", C.c_float),
+                ("n_range", C.c_int32), ("n_azimuth", C.c_int32),
+                ("fan_h", C.c_int32), ("fan_w", C.c_int32),
+                ("speckle_mode", C.c_int32), ("gamma_k", C.c_int32), ("param_row", C.c_int32),
+                ("seed_lo", C.c_uint32), ("seed_hi", C.c_uint32), ("frame_id", C.c_uint32),
+                ("polar", _P), ("fan", _P), ("bin_of_return", _P),
+                ("grad_polar", _P), ("grad_fan", _P)]
+
+
+class WaterParams(C.Structure):
+    _fields_ = [("beta_d", C.c_float * 3), ("beta_b", C.c_float * 3), ("b_inf", C.c_float * 3),
+                ("reserved", C.c_float * 3)]
+
+
+class UwFrame(C.Structure):
+    _fields_ = [("J", _P), ("depth", _P), ("out", _P), ("H", C.c_int32), ("W", C.c_int32),
+                ("param_row", C.c_int32), ("grad_out", _P), ("grad_J", _P), ("grad_depth", _P)]
+
+
+class OceansimError(RuntimeError):
+    def __init__(self, status: int, where: str, text: str):
+        super().__init__("%s: %s (%s)" % (where, STATUS_NAMES.get(status, status), text))
+        self.status = status
+
+
+def _load() -> C.CDLL:
+    if not os.path.exists(LIB_PATH):
+        raise ImportError("liboceansim.so is not built (run __graft_entry__.build() or "
+                          "python -m paper_2503_01074_amd.build): %s" % LIB_PATH)
+    lib = C.CDLL(LIB_PATH)
+    lib.oceansim_last_error.restype = C.c_char_p
+    lib.oceansim_last_error.argtypes = []
+    lib.oceansim_abi_version.restype = C.c_int
+    lib.oceansim_abi_version.argtypes = []
+    SF, UF = C.POINTER(SonarFrame), C.POINTER(UwFrame)
+    sig = {
+        "oceansim_sonar_workspace_size": [SF, C.c_int32, C.c_int32, C.c_int32, C.POINTER(C.c_size_t)],
+        "oceansim_sonar_render": [SF, C.c_int32, _P, C.c_int32, _P, C.c_int32, _P, C.c_size_t, _P],
+        "oceansim_sonar_render_backward": [SF, C.c_int32, _P, C.c_int32, _P, C.c_int32, _P, _P, _P,
+                                           C.c_size_t, _P],
+        "oceansim_uw_workspace_size": [UF, C.c_int32, C.c_int32, C.POINTER(C.c_size_t)],
+        "oceansim_uw_form": [UF, C.c_int32, _P, C.c_int32, _P, C.c_size_t, _P],
+        "oceansim_uw_form_backward": [UF, C.c_int32, _P, C.c_int32, _P, _P, C.c_size_t, _P],
+    }
+    for name, args in sig.items():
+        fn = getattr(lib, name)
+        fn.argtypes = args
+        fn.restype = C.c_int
+    return lib
+
+
+lib = _load()
+
+EXPORTED = ("oceansim_last_error", "oceansim_abi_version", "oceansim_sonar_workspace_size",
+            "oceansim_sonar_render", "oceansim_sonar_render_backward", "oceansim_uw_workspace_size",
+            "oceansim_uw_form", "oceansim_uw_form_backward")
+
+
+def last_error() -> str:
+    return lib.oceansim_last_error().decode()
+
+
+def check(status: int, where: str) -> None:
+    if status != OCEANSIM_OK:
+        raise OceansimError(status, where, last_error())
+
+
+def _frames(frames, cls):
+    if isinstance(frames, cls):
+        return C.pointer(frames), 1, frames
+    arr = (cls * len(frames))(*frames)
+    return arr, len(frames), arr
+
+
+# --- entry points under their C names (raise OceansimError on failure) ------ #
+
+def oceansim_abi_version() -> int:
+    return lib.oceansim_abi_version()
+
+
+def oceansim_sonar_workspace_size(frames, n_materials: int, with_backward: bool) -> int:
+    ptr, n, _keep = _frames(frames, SonarFrame)
+    out = C.c_size_t(0)
+    check(lib.oceansim_sonar_workspace_size(ptr, n, n_materials, int(with_backward), C.byref(out)),
+          "oceansim_sonar_workspace_size")
+    return out.value
+
+
+def oceansim_sonar_render(frames, params_dev: int, n_param_rows: int, refl_dev: int, n_materials: int,
+                          workspace: int, workspace_bytes: int, stream: int) -> None:
+    ptr, n, _keep = _frames(frames, SonarFrame)
+    check(lib.oceansim_sonar_render(ptr, n, params_dev, n_param_rows, refl_dev, n_materials, workspace,
+                                    workspace_bytes, stream), "oceansim_sonar_render")
+
+
+def oceansim_sonar_render_backward(frames, params_dev: int, n_param_rows: int, refl_dev: int,
+                                   n_materials: int, grad_refl_dev: int, grad_params_dev: int,
+                                   workspace: int, workspace_bytes: int, stream: int) -> None:
+    ptr, n, _keep = _frames(frames, SonarFrame)
+    check(lib.oceansim_sonar_render_backward(ptr, n, params_dev, n_param_rows, refl_dev, n_materials,
+                                             grad_refl_dev, grad_params_dev, workspace, workspace_bytes,
+                                             stream), "oceansim_sonar_render_backward")
+
+
+def oceansim_uw_workspace_size(frames, with_backward: bool) -> int:
+    ptr, n, _keep = _frames(frames, UwFrame)
+    out = C.c_size_t(0)
+    check(lib.oceansim_uw_workspace_size(ptr, n, int(with_backward), C.byref(out)),
+          "oceansim_uw_workspace_size")
+    return out.value
+
+
+def oceansim_uw_form(frames, params_dev: int, n_param_rows: int, workspace: int, workspace_bytes: int,
+                     stream: int) -> None:
+    ptr, n, _keep = _frames(frames, UwFrame)
+    check(lib.oceansim_uw_form(ptr, n, params_dev, n_param_rows, workspace, workspace_bytes, stream),
+          "oceansim_uw_form")
+
+
+def oceansim_uw_form_backward(frames, params_dev: int, n_param_rows: int, grad_params_dev: int,
+                              workspace: int, workspace_bytes: int, stream: int) -> None:
+    ptr, n, _keep = _frames(frames, UwFrame)
+    check(lib.oceansim_uw_form_backward(ptr, n, params_dev, n_param_rows, grad_params_dev, workspace,
+                                        workspace_bytes, stream), "oceansim_uw_form_backward")

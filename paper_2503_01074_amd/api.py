@@ -1,0 +1,268 @@
+"""Torch-facing API: device buffers in, device images out.
+
+PyTorch provides device memory and the current stream; every step of the
+computation runs in liboceansim.so.  The autograd functions wrap the
+hand-written adjoint kernels for calibration loops.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass
+from typing import List, Optional, Sequence
+
+import torch
+
+from . import _lib
+from ._lib import (SONAR_GRAD_WIDTH, WATER_GRAD_WIDTH, SonarFrame, UwFrame)
+
+SONAR_PARAM_WIDTH = 8     # alpha, gain, sigma_phi, sigma_sa, sigma_sm, 3 reserved
+WATER_PARAM_WIDTH = 12    # beta_d[3], beta_b[3], b_inf[3], 3 reserved
+
+
+def _ptr(t: Optional[torch.Tensor]) -> int:
+    return 0 if t is None else t.data_ptr()
+
+
+def _stream(device) -> int:
+    return torch.cuda.current_stream(device).cuda_stream
+
+
+def _workspace(nbytes: int, device) -> torch.Tensor:
+    # 256-byte alignment: torch's caching allocator returns 512-byte aligned blocks
+    return torch.empty(max(int(nbytes), 256), dtype=torch.uint8, device=device)
+
+
+@dataclass
+class SonarGeometry:
+    """Host-side description of one sonar frame (grid, field of view, RNG key)."""
+    r_min: float
+    r_max: float
+    n_range: int
+    n_azimuth: int
+    fov_az: float
+    fov_el: float
+    path_factor: float = 2.0
+    fan_h: int = 0
+    fan_w: int = 0
+    speckle_mode: int = _lib.SPECKLE_GAMMA
+    gamma_k: int = 4
+    seed_lo: int = 0
+    seed_hi: int = 0
+    frame_id: int = 0
+    param_row: int = 0
+
+    @classmethod
+    def from_spec(cls, spec, param_row: int = 0) -> "SonarGeometry":
+        return cls(r_min=spec.r_min, r_max=spec.r_max, n_range=spec.n_range, n_azimuth=spec.n_azimuth,
+                   fov_az=spec.fov_az, fov_el=spec.fov_el, path_factor=spec.kappa, fan_h=spec.fan_h,
+                   fan_w=spec.fan_w, speckle_mode=spec.speckle_mode, gamma_k=spec.gamma_k,
+                   seed_lo=spec.seed_lo, seed_hi=spec.seed_hi, frame_id=spec.frame_id,
+                   param_row=param_row)
+
+
+@dataclass
+class DeviceHits:
+    """Structure-of-arrays hit buffer on the device."""
+    x: torch.Tensor
+    y: torch.Tensor
+    z: torch.Tensor
+    nx: torch.Tensor
+    ny: torch.Tensor
+    nz: torch.Tensor
+    mat: torch.Tensor
+
+    @property
+    def n(self) -> int:
+        return int(self.x.numel())
+
+    @classmethod
+    def from_host(cls, hits, device="cuda") -> "DeviceHits":
+        f = lambda a, dt: torch.as_tensor(a).to(device=device, dtype=dt).contiguous()
+        return cls(f(hits.x, torch.float32), f(hits.y, torch.float32), f(hits.z, torch.float32),
+                   f(hits.nx, torch.float32), f(hits.ny, torch.float32), f(hits.nz, torch.float32),
+                   f(hits.mat, torch.int32))
+
+
+def sonar_params(rows: Sequence[dict], device="cuda") -> torch.Tensor:
+    """[n_rows, 8] float32 device table of oceansim_sonar_params rows."""
+    t = torch.zeros(len(rows), SONAR_PARAM_WIDTH, dtype=torch.float32)
+    for r, d in enumerate(rows):
+        for c, name in enumerate(_lib.SONAR_GRAD_COLUMNS):
+            t[r, c] = float(d.get(name, 0.0))
+    return t.to(device)
+
+
+def sonar_params_from_spec(spec) -> dict:
+    return {k: float(getattr(spec, k)) for k in _lib.SONAR_GRAD_COLUMNS}
+
+
+def water_params(rows: Sequence, device="cuda") -> torch.Tensor:
+    """[n_rows, 12] float32 device table of oceansim_water_params rows; each
+    row is (beta_d[3], beta_b[3], b_inf[3])."""
+    t = torch.zeros(len(rows), WATER_PARAM_WIDTH, dtype=torch.float32)
+    for r, (bd, bb, bi) in enumerate(rows):
+        t[r, 0:3] = torch.as_tensor(bd, dtype=torch.float32)
+        t[r, 3:6] = torch.as_tensor(bb, dtype=torch.float32)
+        t[r, 6:9] = torch.as_tensor(bi, dtype=torch.float32)
+    return t.to(device)
+
+
+def _sonar_struct(g: SonarGeometry, h: DeviceHits, polar=None, fan=None, bins=None, grad_polar=None,
+                  grad_fan=None) -> SonarFrame:
+    s = SonarFrame()
+    s.x, s.y, s.z = _ptr(h.x), _ptr(h.y), _ptr(h.z)
+    s.nx, s.ny, s.nz = _ptr(h.nx), _ptr(h.ny), _ptr(h.nz)
+    s.mat = _ptr(h.mat)
+    s.n_returns = h.n
+    s.r_min, s.r_max = g.r_min, g.r_max
+    s.fov_az, s.fov_el = g.fov_az, g.fov_el
+    s.path_factor = g.path_factor
+    s.n_range, s.n_azimuth = g.n_range, g.n_azimuth
+    s.fan_h, s.fan_w = g.fan_h, g.fan_w
+    s.speckle_mode, s.gamma_k = g.speckle_mode, g.gamma_k
+    s.param_row = g.param_row
+    s.seed_lo, s.seed_hi, s.frame_id = g.seed_lo & 0xFFFFFFFF, g.seed_hi & 0xFFFFFFFF, g.frame_id & 0xFFFFFFFF
+    s.polar, s.fan, s.bin_of_return = _ptr(polar), _ptr(fan), _ptr(bins)
+    s.grad_polar, s.grad_fan = _ptr(grad_polar), _ptr(grad_fan)
+    return s
+
+
+def render_sonar(geoms: Sequence[SonarGeometry], hits: Sequence[DeviceHits], params: torch.Tensor,
+                 refl: torch.Tensor, *, polar: bool = True, fan: bool = True, bins: bool = False,
+                 workspace: Optional[torch.Tensor] = None) -> List[dict]:
+    """Forward sonar image formation of one or many frames in one call."""
+    device = params.device
+    outs, structs = [], []
+    for g, h in zip(geoms, hits):
+        o = {}
+        if polar or not (fan and g.fan_h > 0):
+            o["polar"] = torch.empty(g.n_range, g.n_azimuth, dtype=torch.float32, device=device)
+        if fan and g.fan_h > 0 and g.fan_w > 0:
+            o["fan"] = torch.empty(g.fan_h, g.fan_w, dtype=torch.float32, device=device)
+        if bins:
+            o["bins"] = torch.empty(h.n, dtype=torch.int32, device=device)
+        outs.append(o)
+        structs.append(_sonar_struct(g, h, o.get("polar"), o.get("fan"), o.get("bins")))
+    n_mat = int(refl.numel())
+    need = _lib.oceansim_sonar_workspace_size(structs, n_mat, False)
+    ws = workspace if workspace is not None and workspace.numel() >= need else _workspace(need, device)
+    _lib.oceansim_sonar_render(structs, _ptr(params), int(params.shape[0]), _ptr(refl), n_mat, _ptr(ws),
+                               ws.numel(), _stream(device))
+    return outs
+
+
+def render_sonar_backward(geoms: Sequence[SonarGeometry], hits: Sequence[DeviceHits], params: torch.Tensor,
+                          refl: torch.Tensor, grad_polar: Sequence[Optional[torch.Tensor]],
+                          grad_fan: Sequence[Optional[torch.Tensor]],
+                          workspace: Optional[torch.Tensor] = None):
+    """Gradients (refl [M], params [rows, 8]) of sum <grad_polar, polar> + <grad_fan, fan>."""
+    device = params.device
+    structs = [_sonar_struct(g, h, grad_polar=gp, grad_fan=gf)
+               for g, h, gp, gf in zip(geoms, hits, grad_polar, grad_fan)]
+    n_mat = int(refl.numel())
+    need = _lib.oceansim_sonar_workspace_size(structs, n_mat, True)
+    ws = workspace if workspace is not None and workspace.numel() >= need else _workspace(need, device)
+    g_refl = torch.empty(n_mat, dtype=torch.float32, device=device)
+    g_par = torch.empty(params.shape[0], SONAR_GRAD_WIDTH, dtype=torch.float32, device=device)
+    _lib.oceansim_sonar_render_backward(structs, _ptr(params), int(params.shape[0]), _ptr(refl), n_mat,
+                                        _ptr(g_refl), _ptr(g_par), _ptr(ws), ws.numel(), _stream(device))
+    return g_refl, g_par
+
+
+def _uw_struct(J, depth, out=None, row=0, grad_out=None, grad_J=None, grad_depth=None) -> UwFrame:
+    s = UwFrame()
+    s.J, s.depth, s.out = _ptr(J), _ptr(depth), _ptr(out)
+    s.H, s.W = int(depth.shape[-2]), int(depth.shape[-1])
+    s.param_row = row
+    s.grad_out, s.grad_J, s.grad_depth = _ptr(grad_out), _ptr(grad_J), _ptr(grad_depth)
+    return s
+
+
+def uw_form(Js: Sequence[torch.Tensor], depths: Sequence[torch.Tensor], water: torch.Tensor,
+            rows: Optional[Sequence[int]] = None) -> List[torch.Tensor]:
+    """Eq. (1) on planar [3, H, W] images with depths [H, W] (one launch)."""
+    rows = rows or [0] * len(Js)
+    outs = [torch.empty_like(J) for J in Js]
+    structs = [_uw_struct(J, d, o, r) for J, d, o, r in zip(Js, depths, outs, rows)]
+    need = _lib.oceansim_uw_workspace_size(structs, False)
+    ws = _workspace(need, water.device) if len(Js) > 1 else None
+    _lib.oceansim_uw_form(structs, _ptr(water), int(water.shape[0]), _ptr(ws), 0 if ws is None else ws.numel(),
+                          _stream(water.device))
+    return outs
+
+
+def uw_form_backward(Js, depths, water: torch.Tensor, grad_outs, rows=None, want_image_grads=True):
+    """(grad_water [rows, 9], grad_J list, grad_depth list)."""
+    rows = rows or [0] * len(Js)
+    gJ = [torch.empty_like(J) if want_image_grads else None for J in Js]
+    gd = [torch.empty_like(d) if want_image_grads else None for d in depths]
+    structs = [_uw_struct(J, d, None, r, go, a, b)
+               for J, d, r, go, a, b in zip(Js, depths, rows, grad_outs, gJ, gd)]
+    need = _lib.oceansim_uw_workspace_size(structs, True)
+    ws = _workspace(need, water.device)
+    g_w = torch.empty(water.shape[0], WATER_GRAD_WIDTH, dtype=torch.float32, device=water.device)
+    _lib.oceansim_uw_form_backward(structs, _ptr(water), int(water.shape[0]), _ptr(g_w), _ptr(ws), ws.numel(),
+                                   _stream(water.device))
+    return g_w, gJ, gd
+
+
+# --------------------------------------------------------------------------- #
+# autograd                                                                    #
+# --------------------------------------------------------------------------- #
+class SonarRender(torch.autograd.Function):
+    """(refl [M], params [rows, 8]) -> polar images and fans of every frame.
+
+    Outputs: a tuple with, per frame, the polar image followed by the fan
+    (when the frame has one).  Gradients flow to refl and params."""
+
+    @staticmethod
+    def forward(ctx, refl, params, geoms, hits):
+        outs = render_sonar(geoms, hits, params, refl, polar=True, fan=True)
+        ctx.geoms, ctx.hits = geoms, hits
+        ctx.save_for_backward(refl, params)
+        flat = []
+        for g, o in zip(geoms, outs):
+            flat.append(o["polar"])
+            if "fan" in o:
+                flat.append(o["fan"])
+        return tuple(flat)
+
+    @staticmethod
+    def backward(ctx, *grads):
+        refl, params = ctx.saved_tensors
+        gp, gf, k = [], [], 0
+        for g in ctx.geoms:
+            gpol = grads[k]
+            k += 1
+            gp.append(None if gpol is None else gpol.contiguous())
+            if g.fan_h > 0 and g.fan_w > 0:
+                gfan = grads[k]
+                k += 1
+                gf.append(None if gfan is None else gfan.contiguous())
+            else:
+                gf.append(None)
+        g_refl, g_par = render_sonar_backward(ctx.geoms, ctx.hits, params, refl, gp, gf)
+        return g_refl, g_par, None, None
+
+
+class UwForm(torch.autograd.Function):
+    """(water [rows, 12], J_0, d_0, J_1, d_1, ...) -> underwater images."""
+
+    @staticmethod
+    def forward(ctx, water, rows, *images):
+        Js, ds = list(images[0::2]), list(images[1::2])
+        ctx.rows = rows
+        ctx.save_for_backward(water, *images)
+        return tuple(uw_form(Js, ds, water, rows))
+
+    @staticmethod
+    def backward(ctx, *grads):
+        water, *images = ctx.saved_tensors
+        Js, ds = images[0::2], images[1::2]
+        gos = [torch.zeros_like(J) if g is None else g.contiguous() for g, J in zip(grads, Js)]
+        g_w, gJ, gd = uw_form_backward(Js, ds, water, gos, ctx.rows, want_image_grads=True)
+        gw = torch.zeros_like(water)
+        gw[:, :WATER_GRAD_WIDTH] = g_w
+        img_grads = []
+        for a, b in zip(gJ, gd):
+            img_grads += [a, b]
+        return (gw, None, *img_grads)

@@ -1,0 +1,488 @@
+// C ABI of the OceanSim gfx950 library: argument validation, launch planning,
+// workspace carving and dispatch.  See include/oceansim.h for the contract.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/oceansim.h"
+#include "device.hpp"
+#include "launch.hpp"
+
+using namespace osim;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const char *fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return code;
+}
+
+int ok() {
+    g_err.clear();
+    return OCEANSIM_OK;
+}
+
+int hip_fail(hipError_t e, const char *what) {
+    return fail(OCEANSIM_E_HIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+bool aligned(const void *p, size_t a) { return ((uintptr_t)p % a) == 0; }
+size_t round_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+constexpr size_t kWsAlign = 256;
+constexpr long long kMaxReturns = (1LL << 31) - 1;
+constexpr int kMaxFanSide = 32768;
+
+// --------------------------------------------------------------------------
+// Sonar planning
+// --------------------------------------------------------------------------
+struct SonarPlan {
+    std::vector<SonarDev> dev;
+    SonarGrid grid{};
+    size_t bytes = 0;
+    // workspace offsets
+    size_t off_table = 0;
+    std::vector<size_t> off_pairs, off_chunk_off, off_polar, off_grad_img;
+    size_t off_part = 0, off_part_row = 0, off_refl_part = 0;
+    int n_slots = 0;
+};
+
+int check_frame(const oceansim_sonar_frame &fr, int idx, int n_param_rows, bool backward) {
+    if (fr.n_returns < 0) return fail(OCEANSIM_E_SHAPE, "frame %d: n_returns < 0", idx);
+    if (fr.n_returns > kMaxReturns)
+        return fail(OCEANSIM_E_UNSUPPORTED, "frame %d: more than 2^31-1 returns", idx);
+    if (fr.n_returns > 0 && (!fr.x || !fr.y || !fr.z || !fr.nx || !fr.ny || !fr.nz || !fr.mat))
+        return fail(OCEANSIM_E_INVALID_ARG, "frame %d: NULL return buffer", idx);
+    const void *rp[7] = {fr.x, fr.y, fr.z, fr.nx, fr.ny, fr.nz, fr.mat};
+    for (auto p : rp)
+        if (!aligned(p, 4)) return fail(OCEANSIM_E_INVALID_ARG, "frame %d: misaligned return buffer", idx);
+    if (fr.n_range < 1 || fr.n_azimuth < 1)
+        return fail(OCEANSIM_E_SHAPE, "frame %d: n_range and n_azimuth must be >= 1", idx);
+    if (fr.n_azimuth > kMaxTileBins)
+        return fail(OCEANSIM_E_UNSUPPORTED, "frame %d: n_azimuth > %d", idx, kMaxTileBins);
+    if ((long long)fr.n_range * fr.n_azimuth > (long long)kMaxTiles * kMaxTileBins)
+        return fail(OCEANSIM_E_UNSUPPORTED, "frame %d: more than %d polar bins", idx,
+                    kMaxTiles * kMaxTileBins);
+    if (!(std::isfinite(fr.r_min) && std::isfinite(fr.r_max) && fr.r_min >= 0.0f && fr.r_max > fr.r_min))
+        return fail(OCEANSIM_E_INVALID_ARG, "frame %d: need finite 0 <= r_min < r_max", idx);
+    if (!(fr.fov_az > 0.0f && fr.fov_az <= 6.2831855f))
+        return fail(OCEANSIM_E_INVALID_ARG, "frame %d: fov_az must be in (0, 2pi]", idx);
+    if (!(fr.fov_el > 0.0f && fr.fov_el <= 3.1415927f))
+        return fail(OCEANSIM_E_INVALID_ARG, "frame %d: fov_el must be in (0, pi]", idx);
+    if (!(std::isfinite(fr.path_factor) && fr.path_factor >= 0.0f))
+        return fail(OCEANSIM_E_INVALID_ARG, "frame %d: path_factor must be finite and >= 0", idx);
+    if (fr.speckle_mode < OCEANSIM_SPECKLE_OFF || fr.speckle_mode > OCEANSIM_SPECKLE_GAMMA)
+        return fail(OCEANSIM_E_INVALID_ARG, "frame %d: unknown speckle_mode %d", idx, fr.speckle_mode);
+    if (fr.speckle_mode == OCEANSIM_SPECKLE_GAMMA && (fr.gamma_k < 1 || fr.gamma_k > 8))
+        return fail(OCEANSIM_E_UNSUPPORTED, "frame %d: gamma_k must be an integer in 1..8", idx);
+    if (fr.param_row < 0 || fr.param_row >= n_param_rows)
+        return fail(OCEANSIM_E_INVALID_ARG, "frame %d: param_row %d outside [0, %d)", idx, fr.param_row,
+                    n_param_rows);
+    const bool has_fan = fr.fan_h != 0 || fr.fan_w != 0;
+    if (has_fan) {
+        if (fr.fan_h < 1 || fr.fan_w < 1 || fr.fan_h > kMaxFanSide || fr.fan_w > kMaxFanSide)
+            return fail(OCEANSIM_E_SHAPE, "frame %d: fan size must be 0x0 or in 1..%d", idx, kMaxFanSide);
+        if (!(fr.fov_az <= 3.1415927f))
+            return fail(OCEANSIM_E_INVALID_ARG, "frame %d: a fan needs fov_az <= pi", idx);
+    }
+    if (!backward) {
+        if (!fr.polar && !fr.fan)
+            return fail(OCEANSIM_E_INVALID_ARG, "frame %d: polar and fan outputs are both NULL", idx);
+        if (fr.fan && !has_fan) return fail(OCEANSIM_E_SHAPE, "frame %d: fan output given but fan is 0x0", idx);
+        if (!aligned(fr.polar, 16) || !aligned(fr.fan, 16))
+            return fail(OCEANSIM_E_INVALID_ARG, "frame %d: polar/fan must be 16-byte aligned", idx);
+        if (!aligned(fr.bin_of_return, 4))
+            return fail(OCEANSIM_E_INVALID_ARG, "frame %d: misaligned bin_of_return", idx);
+    } else {
+        if (fr.grad_fan && !has_fan)
+            return fail(OCEANSIM_E_SHAPE, "frame %d: grad_fan given but fan is 0x0", idx);
+        if (!aligned(fr.grad_polar, 16) || !aligned(fr.grad_fan, 16))
+            return fail(OCEANSIM_E_INVALID_ARG, "frame %d: grad_polar/grad_fan must be 16-byte aligned", idx);
+    }
+    return OCEANSIM_OK;
+}
+
+int pow2_at_least(long long v) {
+    int p = 1;
+    while (p < v && p < (1 << 30)) p <<= 1;
+    return p;
+}
+
+int plan_sonar(const oceansim_sonar_frame *frames, int n_frames, int n_param_rows, int n_mat, bool backward,
+               SonarPlan &P) {
+    if (n_frames < 0) return fail(OCEANSIM_E_INVALID_ARG, "n_frames < 0");
+    if (n_frames > 0 && !frames) return fail(OCEANSIM_E_INVALID_ARG, "frames is NULL");
+    if (n_mat < 1) return fail(OCEANSIM_E_INVALID_ARG, "n_materials must be >= 1");
+    if (n_param_rows < 1) return fail(OCEANSIM_E_INVALID_ARG, "n_param_rows must be >= 1");
+    P.dev.assign(n_frames, SonarDev{});
+    int max_tiles = 1, max_tile_bins = 1;
+    // first pass: validation and tiling
+    for (int i = 0; i < n_frames; ++i) {
+        const oceansim_sonar_frame &fr = frames[i];
+        int rc = check_frame(fr, i, n_param_rows, backward);
+        if (rc) return rc;
+        SonarDev &d = P.dev[i];
+        int rpt = std::max(1, std::min(fr.n_range, kMaxTileBins / fr.n_azimuth));
+        int n_tiles = (fr.n_range + rpt - 1) / rpt;
+        if (n_tiles > kMaxTiles) return fail(OCEANSIM_E_UNSUPPORTED, "frame %d: too many polar rows", i);
+        d.rows_per_tile = rpt;
+        d.tile_bins = rpt * fr.n_azimuth;
+        d.n_tiles = n_tiles;
+        max_tiles = std::max(max_tiles, n_tiles);
+        max_tile_bins = std::max(max_tile_bins, d.tile_bins);
+    }
+    // one chunk size per call: >= 4 pairs per (chunk, tile) cell on average
+    int chunk = std::min(4096, std::max(1024, pow2_at_least(4LL * max_tiles)));
+    P.grid.chunk = chunk;
+    P.grid.ret_chunk = chunk;
+    P.grid.max_tiles = max_tiles;
+    P.grid.max_tile_bins = max_tile_bins;
+
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        size_t o = off;
+        off = round_up(off + bytes, kWsAlign);
+        return o;
+    };
+    P.off_table = n_frames > 1 ? take(sizeof(SonarDev) * n_frames) : 0;
+    P.off_pairs.assign(n_frames, 0);
+    P.off_chunk_off.assign(n_frames, 0);
+    P.off_polar.assign(n_frames, (size_t)-1);
+    P.off_grad_img.assign(n_frames, 0);
+    int bin_blocks = 0, tile_blocks = 0, fan_blocks = 0, ret_blocks = 0;
+    for (int i = 0; i < n_frames; ++i) {
+        const oceansim_sonar_frame &fr = frames[i];
+        SonarDev &d = P.dev[i];
+        const long long nb = (long long)fr.n_range * fr.n_azimuth;
+        d.n = fr.n_returns;
+        d.n_range = fr.n_range;
+        d.n_az = fr.n_azimuth;
+        d.fan_h = fr.fan_h;
+        d.fan_w = fr.fan_w;
+        d.chunk = chunk;
+        d.n_chunks = (int)((fr.n_returns + chunk - 1) / chunk);
+        d.ret_chunk = chunk;
+        d.n_ret_chunks = d.n_chunks;
+        d.fan_bpr = (((fr.fan_w + 1) / 2) + kBlock - 1) / kBlock;
+        const bool fan_out = fr.fan_h > 0 && fr.fan_w > 0 && (backward ? true : fr.fan != nullptr);
+        d.fan_blocks = (!backward && fan_out) ? fr.fan_h * d.fan_bpr : 0;
+        d.speckle = fr.speckle_mode;
+        d.gamma_k = fr.gamma_k;
+        d.param_row = fr.param_row;
+        d.seed_lo = fr.seed_lo;
+        d.seed_hi = fr.seed_hi;
+        d.frame_id = fr.frame_id;
+        d.blk[KBIN] = bin_blocks;
+        d.blk[KTILE] = tile_blocks;
+        d.blk[KFAN] = fan_blocks;
+        d.blk[KRET] = ret_blocks;
+        bin_blocks += d.n_chunks;
+        tile_blocks += d.n_tiles;
+        fan_blocks += d.fan_blocks;
+        ret_blocks += d.n_ret_chunks;
+        // geometry in double
+        d.r_min = fr.r_min;
+        d.r_max = fr.r_max;
+        d.fov_az = fr.fov_az;
+        d.half_az = 0.5 * (double)fr.fov_az;
+        d.sin_half_el = std::sin(0.5 * (double)fr.fov_el);
+        d.kappa = fr.path_factor;
+        d.scale_r = (double)fr.n_range / ((double)fr.r_max - (double)fr.r_min);
+        d.scale_phi = (double)fr.n_azimuth / (double)fr.fov_az;
+        d.dr = ((double)fr.r_max - (double)fr.r_min) / fr.n_range;
+        d.dphi = (double)fr.fov_az / fr.n_azimuth;
+        if (fr.fan_h > 0 && fr.fan_w > 0) {
+            const double s1 = (double)fr.r_max / fr.fan_h;
+            const double s2 = 2.0 * (double)fr.r_max * std::sin(d.half_az) / fr.fan_w;
+            d.fan_s = s1 > s2 ? s1 : s2;
+            d.tan_half_az = std::tan(std::min(d.half_az, 1.5707963267948966));
+        }
+        d.scale_phi_f = (float)d.scale_phi;
+        d.half_az_f = (float)d.half_az;
+        // FP32 azimuth error, in cells, is below ~3.3e-7 N_phi (see return_bin)
+        d.az_fast = (3.5e-7 * fr.n_azimuth < 1e-3) ? 1 : 0;
+        // pointers
+        d.x = fr.x; d.y = fr.y; d.z = fr.z;
+        d.nx = fr.nx; d.ny = fr.ny; d.nz = fr.nz;
+        d.mat = fr.mat;
+        d.polar = fr.polar;
+        d.fan = fr.fan;
+        d.bin_of_return = fr.bin_of_return;
+        d.grad_polar = fr.grad_polar;
+        d.grad_fan = fr.grad_fan;
+        if (!backward) {
+            P.off_pairs[i] = take(sizeof(uint2) * (size_t)d.n_chunks * chunk);
+            P.off_chunk_off[i] = take(sizeof(int) * (size_t)d.n_chunks * (d.n_tiles + 1));
+            if (!fr.polar) P.off_polar[i] = take(sizeof(float) * (size_t)nb);
+        } else {
+            P.off_grad_img[i] = take(sizeof(float) * (size_t)nb);
+        }
+    }
+    P.grid.bin_blocks = bin_blocks;
+    P.grid.tile_blocks = tile_blocks;
+    P.grid.fan_blocks = fan_blocks;
+    P.grid.ret_blocks = ret_blocks;
+    if (backward) {
+        P.n_slots = tile_blocks + ret_blocks;
+        P.off_part = take(sizeof(double) * 5 * (size_t)std::max(1, P.n_slots));
+        P.off_part_row = take(sizeof(int) * (size_t)std::max(1, P.n_slots));
+        if (n_mat <= kLaneHistMats)
+            P.off_refl_part = take(sizeof(double) * (size_t)std::max(1, ret_blocks) * n_mat);
+    }
+    P.bytes = std::max<size_t>(off, kWsAlign);
+    return OCEANSIM_OK;
+}
+
+void carve_sonar(SonarPlan &P, char *ws, bool backward) {
+    for (size_t i = 0; i < P.dev.size(); ++i) {
+        SonarDev &d = P.dev[i];
+        if (!backward) {
+            d.pairs = reinterpret_cast<uint2 *>(ws + P.off_pairs[i]);
+            d.chunk_off = reinterpret_cast<int *>(ws + P.off_chunk_off[i]);
+            if (P.off_polar[i] != (size_t)-1) d.polar = reinterpret_cast<float *>(ws + P.off_polar[i]);
+        } else {
+            d.grad_img = reinterpret_cast<float *>(ws + P.off_grad_img[i]);
+        }
+    }
+}
+
+int check_ws(void *ws, size_t have, size_t need) {
+    if (need > have)
+        return fail(OCEANSIM_E_WORKSPACE, "workspace of %zu bytes is smaller than the %zu required", have, need);
+    if (!ws) return fail(OCEANSIM_E_WORKSPACE, "workspace is NULL");
+    if (!aligned(ws, kWsAlign)) return fail(OCEANSIM_E_WORKSPACE, "workspace must be 256-byte aligned");
+    return OCEANSIM_OK;
+}
+
+// --------------------------------------------------------------------------
+// Camera planning
+// --------------------------------------------------------------------------
+struct UwPlan {
+    std::vector<UwDev> dev;
+    int blocks = 0;
+    size_t bytes = 0, off_table = 0, off_part = 0, off_part_row = 0;
+};
+
+int plan_uw(const oceansim_uw_frame *frames, int n_frames, int n_param_rows, bool backward, UwPlan &P) {
+    if (n_frames < 0) return fail(OCEANSIM_E_INVALID_ARG, "n_frames < 0");
+    if (n_frames > 0 && !frames) return fail(OCEANSIM_E_INVALID_ARG, "frames is NULL");
+    if (n_param_rows < 1) return fail(OCEANSIM_E_INVALID_ARG, "n_param_rows must be >= 1");
+    P.dev.assign(n_frames, UwDev{});
+    int blocks = 0;
+    for (int i = 0; i < n_frames; ++i) {
+        const oceansim_uw_frame &fr = frames[i];
+        if (fr.H < 1 || fr.W < 1) return fail(OCEANSIM_E_SHAPE, "camera frame %d: H and W must be >= 1", i);
+        const long long npix = (long long)fr.H * fr.W;
+        if (npix * 3 > kMaxReturns)
+            return fail(OCEANSIM_E_UNSUPPORTED, "camera frame %d: image too large", i);
+        if (fr.param_row < 0 || fr.param_row >= n_param_rows)
+            return fail(OCEANSIM_E_INVALID_ARG, "camera frame %d: param_row %d outside [0, %d)", i,
+                        fr.param_row, n_param_rows);
+        if (!fr.J || !fr.depth) return fail(OCEANSIM_E_INVALID_ARG, "camera frame %d: NULL J or depth", i);
+        if (!backward && !fr.out) return fail(OCEANSIM_E_INVALID_ARG, "camera frame %d: NULL out", i);
+        if (backward && !fr.grad_out) return fail(OCEANSIM_E_INVALID_ARG, "camera frame %d: NULL grad_out", i);
+        const void *ps[6] = {fr.J, fr.depth, fr.out, fr.grad_out, fr.grad_J, fr.grad_depth};
+        for (auto p : ps)
+            if (!aligned(p, 16))
+                return fail(OCEANSIM_E_INVALID_ARG, "camera frame %d: image buffers must be 16-byte aligned", i);
+        UwDev &d = P.dev[i];
+        d.J = fr.J;
+        d.depth = fr.depth;
+        d.out = fr.out;
+        d.grad_out = fr.grad_out;
+        d.grad_J = fr.grad_J;
+        d.grad_depth = fr.grad_depth;
+        d.npix = npix;
+        d.param_row = fr.param_row;
+        d.n_blocks = (int)((npix + kUwPixelsPerBlock - 1) / kUwPixelsPerBlock);
+        d.blk = blocks;
+        blocks += d.n_blocks;
+    }
+    P.blocks = blocks;
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        size_t o = off;
+        off = round_up(off + bytes, kWsAlign);
+        return o;
+    };
+    P.off_table = n_frames > 1 ? take(sizeof(UwDev) * n_frames) : 0;
+    if (backward) {
+        P.off_part = take(sizeof(double) * 9 * (size_t)std::max(1, blocks));
+        P.off_part_row = take(sizeof(int) * (size_t)std::max(1, blocks));
+    }
+    P.bytes = off;
+    return OCEANSIM_OK;
+}
+
+template <class T>
+hipError_t upload_table(const std::vector<T> &v, char *ws, size_t off, hipStream_t st) {
+    return hipMemcpyAsync(ws + off, v.data(), sizeof(T) * v.size(), hipMemcpyHostToDevice, st);
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *oceansim_last_error(void) { return g_err.c_str(); }
+
+int oceansim_abi_version(void) { return OCEANSIM_ABI_VERSION; }
+
+int oceansim_sonar_workspace_size(const oceansim_sonar_frame *frames, int32_t n_frames, int32_t n_materials,
+                                  int32_t with_backward, size_t *bytes) {
+    if (!bytes) return fail(OCEANSIM_E_INVALID_ARG, "bytes is NULL");
+    SonarPlan P;
+    // the row count is not known here: accept any row index for sizing
+    int rc = plan_sonar(frames, n_frames, 0x7fffffff, n_materials, with_backward != 0, P);
+    if (rc) return rc;
+    *bytes = P.bytes;
+    return ok();
+}
+
+int oceansim_sonar_render(const oceansim_sonar_frame *frames, int32_t n_frames,
+                          const oceansim_sonar_params *params_dev, int32_t n_param_rows, const float *refl_dev,
+                          int32_t n_materials, void *workspace, size_t workspace_bytes, void *stream) {
+    if (!params_dev) return fail(OCEANSIM_E_INVALID_ARG, "params_dev is NULL");
+    if (!refl_dev) return fail(OCEANSIM_E_INVALID_ARG, "refl_dev is NULL");
+    SonarPlan P;
+    int rc = plan_sonar(frames, n_frames, n_param_rows, n_materials, false, P);
+    if (rc) return rc;
+    if (n_frames == 0) return ok();
+    rc = check_ws(workspace, workspace_bytes, P.bytes);
+    if (rc) return rc;
+    char *ws = static_cast<char *>(workspace);
+    carve_sonar(P, ws, false);
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    hipError_t e;
+    if (n_frames == 1) {
+        e = sonar_forward_one(P.dev[0], P.grid, params_dev, refl_dev, n_materials, st);
+    } else {
+        e = upload_table(P.dev, ws, P.off_table, st);
+        if (e != hipSuccess) return hip_fail(e, "frame table upload");
+        e = sonar_forward_table(reinterpret_cast<const SonarDev *>(ws + P.off_table), n_frames, P.grid,
+                                params_dev, refl_dev, n_materials, st);
+    }
+    if (e != hipSuccess) return hip_fail(e, "sonar forward launch");
+    return ok();
+}
+
+int oceansim_sonar_render_backward(const oceansim_sonar_frame *frames, int32_t n_frames,
+                                   const oceansim_sonar_params *params_dev, int32_t n_param_rows,
+                                   const float *refl_dev, int32_t n_materials, float *grad_refl_dev,
+                                   float *grad_params_dev, void *workspace, size_t workspace_bytes,
+                                   void *stream) {
+    if (!params_dev) return fail(OCEANSIM_E_INVALID_ARG, "params_dev is NULL");
+    if (!refl_dev) return fail(OCEANSIM_E_INVALID_ARG, "refl_dev is NULL");
+    if (!grad_refl_dev || !grad_params_dev) return fail(OCEANSIM_E_INVALID_ARG, "gradient output is NULL");
+    if (!aligned(grad_refl_dev, 4) || !aligned(grad_params_dev, 4))
+        return fail(OCEANSIM_E_INVALID_ARG, "misaligned gradient output");
+    SonarPlan P;
+    int rc = plan_sonar(frames, n_frames, n_param_rows, n_materials, true, P);
+    if (rc) return rc;
+    rc = check_ws(workspace, workspace_bytes, P.bytes);
+    if (rc) return rc;
+    char *ws = static_cast<char *>(workspace);
+    carve_sonar(P, ws, true);
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    double *part = reinterpret_cast<double *>(ws + P.off_part);
+    int *part_row = reinterpret_cast<int *>(ws + P.off_part_row);
+    const bool lane_hist = n_materials <= kLaneHistMats;
+    double *refl_part = lane_hist ? reinterpret_cast<double *>(ws + P.off_refl_part) : nullptr;
+    hipError_t e = hipSuccess;
+    if (n_frames == 1) {
+        e = sonar_backward_one(P.dev[0], P.grid, params_dev, refl_dev, n_materials, part, part_row, refl_part,
+                               grad_refl_dev, st);
+    } else if (n_frames > 1) {
+        e = upload_table(P.dev, ws, P.off_table, st);
+        if (e != hipSuccess) return hip_fail(e, "frame table upload");
+        e = sonar_backward_table(reinterpret_cast<const SonarDev *>(ws + P.off_table), n_frames, P.grid,
+                                 params_dev, refl_dev, n_materials, part, part_row, refl_part, grad_refl_dev,
+                                 st);
+    }
+    if (e != hipSuccess) return hip_fail(e, "sonar backward launch");
+    e = reduce_rows(part, part_row, P.n_slots, 5, n_param_rows, grad_params_dev, OCEANSIM_SONAR_GRAD_WIDTH, st);
+    if (e != hipSuccess) return hip_fail(e, "sonar gradient reduction");
+    if (lane_hist) {
+        e = reduce_cols(refl_part, P.grid.ret_blocks, n_materials, grad_refl_dev, st);
+        if (e != hipSuccess) return hip_fail(e, "reflectivity gradient reduction");
+    }
+    return ok();
+}
+
+int oceansim_uw_workspace_size(const oceansim_uw_frame *frames, int32_t n_frames, int32_t with_backward,
+                               size_t *bytes) {
+    if (!bytes) return fail(OCEANSIM_E_INVALID_ARG, "bytes is NULL");
+    UwPlan P;
+    std::vector<oceansim_uw_frame> tmp(frames, frames + std::max(0, n_frames));
+    for (auto &f : tmp) f.param_row = 0;   // sizing does not depend on rows
+    int rc = plan_uw(frames ? tmp.data() : nullptr, n_frames, 1, with_backward != 0, P);
+    if (rc) return rc;
+    *bytes = P.bytes;
+    return ok();
+}
+
+int oceansim_uw_form(const oceansim_uw_frame *frames, int32_t n_frames, const oceansim_water_params *params_dev,
+                     int32_t n_param_rows, void *workspace, size_t workspace_bytes, void *stream) {
+    if (!params_dev) return fail(OCEANSIM_E_INVALID_ARG, "params_dev is NULL");
+    UwPlan P;
+    int rc = plan_uw(frames, n_frames, n_param_rows, false, P);
+    if (rc) return rc;
+    if (n_frames == 0 || P.blocks == 0) return ok();
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    hipError_t e;
+    if (n_frames == 1) {
+        e = uw_forward_one(P.dev[0], P.blocks, params_dev, st);
+    } else {
+        rc = check_ws(workspace, workspace_bytes, P.bytes);
+        if (rc) return rc;
+        char *ws = static_cast<char *>(workspace);
+        e = upload_table(P.dev, ws, P.off_table, st);
+        if (e != hipSuccess) return hip_fail(e, "frame table upload");
+        e = uw_forward_table(reinterpret_cast<const UwDev *>(ws + P.off_table), n_frames, P.blocks, params_dev, st);
+    }
+    if (e != hipSuccess) return hip_fail(e, "uw_form launch");
+    return ok();
+}
+
+int oceansim_uw_form_backward(const oceansim_uw_frame *frames, int32_t n_frames,
+                              const oceansim_water_params *params_dev, int32_t n_param_rows,
+                              float *grad_params_dev, void *workspace, size_t workspace_bytes, void *stream) {
+    if (!params_dev) return fail(OCEANSIM_E_INVALID_ARG, "params_dev is NULL");
+    if (!grad_params_dev) return fail(OCEANSIM_E_INVALID_ARG, "grad_params_dev is NULL");
+    UwPlan P;
+    int rc = plan_uw(frames, n_frames, n_param_rows, true, P);
+    if (rc) return rc;
+    rc = check_ws(workspace, workspace_bytes, P.bytes);
+    if (rc) return rc;
+    char *ws = static_cast<char *>(workspace);
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    double *part = reinterpret_cast<double *>(ws + P.off_part);
+    int *part_row = reinterpret_cast<int *>(ws + P.off_part_row);
+    hipError_t e = hipSuccess;
+    if (n_frames == 1 && P.blocks > 0) {
+        e = uw_backward_one(P.dev[0], P.blocks, params_dev, part, part_row, st);
+    } else if (n_frames > 1 && P.blocks > 0) {
+        e = upload_table(P.dev, ws, P.off_table, st);
+        if (e != hipSuccess) return hip_fail(e, "frame table upload");
+        e = uw_backward_table(reinterpret_cast<const UwDev *>(ws + P.off_table), n_frames, P.blocks, params_dev,
+                              part, part_row, st);
+    }
+    if (e != hipSuccess) return hip_fail(e, "uw_form backward launch");
+    e = reduce_rows(part, part_row, P.blocks, 9, n_param_rows, grad_params_dev, OCEANSIM_WATER_GRAD_WIDTH, st);
+    if (e != hipSuccess) return hip_fail(e, "water gradient reduction");
+    return ok();
+}
+
+}  // extern "C"

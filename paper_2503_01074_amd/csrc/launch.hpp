@@ -1,0 +1,53 @@
+// Host-side launchers of the gfx950 kernels (internal to the library).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "../../include/oceansim.h"
+#include "device.hpp"
+
+namespace osim {
+
+// Launch geometry of one sonar call (all frames).
+struct SonarGrid {
+    int bin_blocks;      // binning workgroups over all frames
+    int tile_blocks;     // polar-tile workgroups over all frames
+    int fan_blocks;      // fan workgroups over all frames
+    int ret_blocks;      // backward return-gather workgroups over all frames
+    int chunk;           // returns per binning workgroup (256 * R)
+    int ret_chunk;       // returns per return-gather workgroup (256 * R)
+    int max_tiles;       // largest tile count of a frame
+    int max_tile_bins;   // largest tile of a frame, in bins
+};
+
+hipError_t sonar_forward_one(const SonarDev &f, const SonarGrid &g, const oceansim_sonar_params *params,
+                             const float *refl, int n_mat, hipStream_t st);
+hipError_t sonar_forward_table(const SonarDev *t, int n, const SonarGrid &g,
+                               const oceansim_sonar_params *params, const float *refl, int n_mat,
+                               hipStream_t st);
+hipError_t sonar_backward_one(const SonarDev &f, const SonarGrid &g, const oceansim_sonar_params *params,
+                              const float *refl, int n_mat, double *part, int *part_row,
+                              double *refl_part, float *grad_refl, hipStream_t st);
+hipError_t sonar_backward_table(const SonarDev *t, int n, const SonarGrid &g,
+                                const oceansim_sonar_params *params, const float *refl, int n_mat,
+                                double *part, int *part_row, double *refl_part, float *grad_refl,
+                                hipStream_t st);
+
+constexpr int kUwPixelsPerBlock = kBlock * 16;
+
+hipError_t uw_forward_one(const UwDev &f, int blocks, const oceansim_water_params *params, hipStream_t st);
+hipError_t uw_forward_table(const UwDev *t, int n, int blocks, const oceansim_water_params *params,
+                            hipStream_t st);
+hipError_t uw_backward_one(const UwDev &f, int blocks, const oceansim_water_params *params, double *part,
+                           int *part_row, hipStream_t st);
+hipError_t uw_backward_table(const UwDev *t, int n, int blocks, const oceansim_water_params *params,
+                             double *part, int *part_row, hipStream_t st);
+
+// out[r * out_stride + c] = sum over slots s with row[s] == r of part[s * width + c]
+// (c < width; columns width..out_stride-1 are written 0), in a fixed order.
+hipError_t reduce_rows(const double *part, const int *row, int n_slots, int width, int n_rows,
+                       float *out, int out_stride, hipStream_t st);
+// out[c] = sum over s of part[s * width + c], fixed order.
+hipError_t reduce_cols(const double *part, int n_slots, int width, float *out, hipStream_t st);
+
+}  // namespace osim

@@ -1,0 +1,366 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 oracle.
+
+Bins are compared bit-exactly; images element by element to 1e-5 relative
+(floor 1e-3 of the peak); gradients to 1e-5 of the oracle's analytic FP64
+gradient and 1e-3 of FP64 central differences of the oracle's forward pass.
+"""
+import copy
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle import SonarConfig
+import workloads as W
+from _cases import build_hits, hit_at, tiny_golden
+from _tol import (GRAD_RTOL_FD, GRAD_RTOL_ORACLE, assert_grad_close, assert_image_close)
+
+pytestmark = pytest.mark.gpu
+
+
+def _osm():
+    import torch  # noqa: F401
+    import paper_2503_01074_amd as osm
+    return osm
+
+
+def _say(msg):
+    print("[case] " + msg, flush=True)
+    sys.stdout.flush()
+
+
+def merged(frames):
+    """Frames sharing one reflectivity table: per-frame tables concatenated,
+    material ids offset (misses stay negative)."""
+    out, tables, base = [], [], 0
+    for f in frames:
+        h = copy.copy(f.hits)
+        h.mat = np.where(f.hits.mat >= 0, f.hits.mat + base, f.hits.mat).astype(np.int32)
+        tables.append(f.hits.refl)
+        base += f.hits.refl.shape[0]
+        out.append(W.SonarFrame(f.spec, h))
+    refl = np.concatenate(tables).astype(np.float32)
+    for f in out:
+        f.hits.refl = refl
+    return out, refl
+
+
+def gpu_forward(frames, refl, fan=True, bins=True):
+    import torch
+    osm = _osm()
+    geoms = [osm.SonarGeometry.from_spec(f.spec, param_row=i) for i, f in enumerate(frames)]
+    hits = [osm.DeviceHits.from_host(f.hits) for f in frames]
+    params = osm.sonar_params([osm.sonar_params_from_spec(f.spec) for f in frames])
+    refl_d = torch.as_tensor(refl).cuda()
+    outs = osm.render_sonar(geoms, hits, params, refl_d, polar=True, fan=fan, bins=bins)
+    torch.cuda.synchronize()
+    return [{k: v.cpu().numpy() for k, v in o.items()} for o in outs]
+
+
+def oracle_forward(frame, refl):
+    return oracle.sonar_forward(SonarConfig.from_spec(frame.spec), frame.hits, refl)
+
+
+def check_frame(got, want, what, fan=True):
+    np.testing.assert_array_equal(got["bins"], want["bins"], err_msg=what + " bins")
+    assert_image_close(got["polar"], want["out"], what + " polar")
+    if fan and "fan" in want:
+        assert_image_close(got["fan"], want["fan"], what + " fan", mask=~want["ambiguous"])
+
+
+# --------------------------------------------------------------------------- #
+# forward                                                                     #
+# --------------------------------------------------------------------------- #
+def test_tiny_golden():
+    _say("tiny golden frame")
+    spec, hits, bins, expected = tiny_golden()
+    got = gpu_forward([W.SonarFrame(spec, hits)], hits.refl, fan=False)[0]
+    np.testing.assert_array_equal(got["bins"], bins)
+    np.testing.assert_allclose(got["polar"], expected, rtol=1e-6, atol=1e-7)
+
+
+@pytest.mark.parametrize("name", ["c1", "c2"])
+def test_workload_forward(name):
+    frames = W.sonar_c1() if name == "c1" else W.sonar_c2()
+    f = frames[0]
+    _say("%s forward: %d returns, %dx%d bins, fan %dx%d" % (name, f.hits.n, f.spec.n_range,
+                                                          f.spec.n_azimuth, f.spec.fan_h, f.spec.fan_w))
+    got = gpu_forward(frames, f.hits.refl)[0]
+    want = oracle_forward(f, f.hits.refl)
+    check_frame(got, want, name)
+    assert want["ambiguous"].sum() == 0
+
+
+SMALL_SHAPES = [
+    # (n_range, n_azimuth, fan_h, fan_w, n_returns)
+    (37, 29, 41, 83, 3000),      # ragged everything, several tiles, odd fan width
+    (1, 17, 8, 16, 200),         # single range row
+    (23, 1, 9, 9, 200),          # single azimuth column
+    (300, 4096, 64, 128, 20000),  # one row per tile (widest supported grid)
+    (4100, 2, 16, 16, 5000),     # more range rows than the tile height many times over
+]
+
+
+@pytest.mark.parametrize("shape", SMALL_SHAPES)
+@pytest.mark.parametrize("mode", [W.SPECKLE_OFF, W.SPECKLE_PAPER, W.SPECKLE_GAMMA])
+def test_shapes_and_modes(shape, mode):
+    Nr, Np, H, Wd, n = shape
+    _say("shape %s mode %d" % (shape, mode))
+    st = W.Stream(1234, Nr * 7 + Np + mode)
+    spec = W.SonarSpec(r_min=0.7, r_max=13.0, n_range=Nr, n_azimuth=Np, fan_h=H, fan_w=Wd,
+                       speckle_mode=mode, gamma_k=3, sigma_sm=0.15, sigma_sa=0.12, sigma_phi=0.3,
+                       alpha=0.09, gain=1.3, seed_lo=77, seed_hi=5, frame_id=9)
+    hits = W.make_hits(st, spec, n, n_materials=5, outside_frac=0.1)
+    frame = W.SonarFrame(spec, hits)
+    got = gpu_forward([frame], hits.refl)[0]
+    want = oracle_forward(frame, hits.refl)
+    check_frame(got, want, "shape %s mode %d" % (shape, mode))
+
+
+@pytest.mark.parametrize("k", [1, 2, 4, 5, 8])
+def test_gamma_shapes(k):
+    _say("gamma k=%d" % k)
+    st = W.Stream(55, k)
+    spec = W.SonarSpec(r_min=0.5, r_max=20.0, n_range=128, n_azimuth=96, fan_h=64, fan_w=128,
+                       speckle_mode=W.SPECKLE_GAMMA, gamma_k=k, seed_lo=k, frame_id=3)
+    hits = W.make_hits(st, spec, 5000)
+    f = W.SonarFrame(spec, hits)
+    check_frame(gpu_forward([f], hits.refl)[0], oracle_forward(f, hits.refl), "gamma k=%d" % k)
+
+
+def test_empty_and_all_miss():
+    _say("empty and all-miss frames")
+    spec = W.SonarSpec(r_min=0.5, r_max=20.0, n_range=64, n_azimuth=64, fan_h=32, fan_w=64,
+                       speckle_mode=W.SPECKLE_GAMMA, seed_lo=3)
+    empty = build_hits([], refl=[1.0])
+    st = W.Stream(8, 8)
+    misses = W.make_hits(st, spec, 1000, miss_frac=1.0)
+    for hits, what in [(empty, "empty"), (misses, "all misses")]:
+        f = W.SonarFrame(spec, hits)
+        got = gpu_forward([f], hits.refl)[0]
+        want = oracle_forward(f, hits.refl)
+        check_frame(got, want, what)
+        assert np.all(want["P"] == 0)
+
+
+def test_kappa_one_and_material_ids():
+    _say("path factor 1 and out-of-table material ids")
+    st = W.Stream(9, 9)
+    spec = W.SonarSpec(r_min=0.5, r_max=20.0, n_range=100, n_azimuth=80, kappa=1.0,
+                       speckle_mode=W.SPECKLE_OFF)
+    hits = W.make_hits(st, spec, 4000, n_materials=10)
+    hits.mat[::7] = 10          # one past the table: a miss
+    hits.mat[::11] = 1 << 30    # far outside the table: a miss
+    f = W.SonarFrame(spec, hits)
+    check_frame(gpu_forward([f], hits.refl, fan=False)[0], oracle_forward(f, hits.refl), "kappa 1", fan=False)
+
+
+def test_dense_collisions():
+    """Many returns per bin (the dense shape of the paper's qualitative figure:
+    3000 x 460 rays on 350 x 220 bins, here at a tenth of the rays)."""
+    _say("dense collisions")
+    st = W.Stream(10, 10)
+    spec = W.SonarSpec(r_min=0.5, r_max=20.0, n_range=350, n_azimuth=220, fan_h=350, fan_w=700,
+                       speckle_mode=W.SPECKLE_GAMMA, seed_lo=1)
+    hits = W.make_hits(st, spec, 138000)
+    f = W.SonarFrame(spec, hits)
+    check_frame(gpu_forward([f], hits.refl)[0], oracle_forward(f, hits.refl), "dense")
+
+
+def test_batched_equals_plain_and_oracle():
+    _say("batched uneven frames")
+    frames = W.sonar_c3(n_frames=6)
+    frames, refl = merged(frames)
+    batched = gpu_forward(frames, refl)
+    for i, f in enumerate(frames):
+        plain = gpu_forward([f], refl)[0]
+        want = oracle_forward(f, refl)
+        check_frame(batched[i], want, "batched frame %d" % i)
+        np.testing.assert_array_equal(batched[i]["bins"], plain["bins"])
+        assert_image_close(batched[i]["polar"], plain["polar"], "batched vs plain %d" % i, rtol=1e-6)
+        assert_image_close(batched[i]["fan"], plain["fan"], "batched vs plain fan %d" % i, rtol=1e-6)
+
+
+# --------------------------------------------------------------------------- #
+# backward                                                                    #
+# --------------------------------------------------------------------------- #
+def gpu_backward(frames, refl, gpol, gfan):
+    import torch
+    osm = _osm()
+    geoms = [osm.SonarGeometry.from_spec(f.spec, param_row=0) for f in frames]
+    hits = [osm.DeviceHits.from_host(f.hits) for f in frames]
+    params = osm.sonar_params([osm.sonar_params_from_spec(frames[0].spec)])
+    refl_d = torch.as_tensor(refl).cuda()
+    gp = [None if g is None else torch.as_tensor(g, dtype=torch.float32).cuda() for g in gpol]
+    gf = [None if g is None else torch.as_tensor(g, dtype=torch.float32).cuda() for g in gfan]
+    g_refl, g_par = osm.render_sonar_backward(geoms, hits, params, refl_d, gp, gf)
+    torch.cuda.synchronize()
+    return g_refl.cpu().numpy().astype(np.float64), g_par.cpu().numpy().astype(np.float64)
+
+
+def oracle_backward(frames, refl, gpol, gfan):
+    g_refl = np.zeros(refl.shape[0])
+    g_par = np.zeros(5)
+    for f, gp, gf in zip(frames, gpol, gfan):
+        a, b, _ = oracle.sonar_backward(SonarConfig.from_spec(f.spec), f.hits, refl, gp, gf)
+        g_refl += a
+        g_par += b
+    return g_refl, g_par
+
+
+def _bwd_case(mode, n_mat, n_frames=1, fan=True, polar=True, seed=0):
+    st = W.Stream(4321 + seed, mode * 10 + n_frames)
+    frames = []
+    for k in range(n_frames):
+        spec = W.SonarSpec(r_min=0.5, r_max=10.0, n_range=48 + 8 * k, n_azimuth=40 + 4 * k,
+                           fan_h=(40 if fan else 0), fan_w=(72 + 2 * k if fan else 0),
+                           alpha=0.11, gain=1.2, sigma_phi=0.3, sigma_sa=0.15, sigma_sm=0.1,
+                           speckle_mode=mode, gamma_k=4, seed_lo=17, frame_id=k)
+        frames.append(W.SonarFrame(spec, W.make_hits(st, spec, 3000, n_materials=n_mat)))
+    frames, refl = merged(frames) if n_mat is None else (frames, frames[0].hits.refl)
+    if n_mat is not None:
+        for f in frames:
+            f.hits.refl = refl
+    gpol = [W.loss_weights((7, 2 * k), (f.spec.n_range, f.spec.n_azimuth)) if polar else None
+            for k, f in enumerate(frames)]
+    gfan = [W.loss_weights((7, 2 * k + 1), (f.spec.fan_h, f.spec.fan_w)) if fan else None
+            for k, f in enumerate(frames)]
+    return frames, refl, gpol, gfan
+
+
+def _oracle_loss(frames, refl, gpol, gfan, **over):
+    L = 0.0
+    for f, gp, gf in zip(frames, gpol, gfan):
+        res = oracle.sonar_forward(SonarConfig.from_spec(f.spec, **over), f.hits, refl)
+        if gp is not None:
+            L += float((gp.astype(np.float64) * res["out"]).sum())
+        if gf is not None:
+            L += float((gf.astype(np.float64) * res["fan"]).sum())
+    return L
+
+
+@pytest.mark.parametrize("mode", [W.SPECKLE_OFF, W.SPECKLE_PAPER, W.SPECKLE_GAMMA])
+@pytest.mark.parametrize("n_mat", [6, 64])
+def test_sonar_backward_vs_oracle_and_fd(mode, n_mat):
+    _say("sonar backward mode %d n_mat %d" % (mode, n_mat))
+    frames, refl, gpol, gfan = _bwd_case(mode, n_mat, n_frames=2)
+    g_refl, g_par = gpu_backward(frames, refl, gpol, gfan)
+    o_refl, o_par = oracle_backward(frames, refl, gpol, gfan)
+    assert_grad_close(g_refl, o_refl, GRAD_RTOL_ORACLE, "refl vs oracle")
+    assert_grad_close(g_par[0, :5], o_par, GRAD_RTOL_ORACLE, "params vs oracle")
+    assert np.all(g_par[0, 5:] == 0)
+    # FP64 central differences of the oracle's forward pass, one parameter at a time
+    for k, name in enumerate(["alpha", "gain", "sigma_phi", "sigma_sa", "sigma_sm"]):
+        x0 = float(getattr(frames[0].spec, name))
+        h = 1e-6 * max(1.0, abs(x0))
+        fd = (_oracle_loss(frames, refl, gpol, gfan, **{name: x0 + h}) -
+              _oracle_loss(frames, refl, gpol, gfan, **{name: x0 - h})) / (2 * h)
+        if abs(fd) < 1e-9 and abs(g_par[0, k]) < 1e-9:
+            continue
+        assert abs(g_par[0, k] - fd) <= GRAD_RTOL_FD * max(abs(fd), 1e-6), (name, g_par[0, k], fd)
+
+
+def test_sonar_backward_many_materials_and_polar_only():
+    _say("sonar backward, per-return reflectivity (atomic path), polar-only loss")
+    frames, refl, gpol, gfan = _bwd_case(W.SPECKLE_GAMMA, None, n_frames=3, fan=False)
+    g_refl, g_par = gpu_backward(frames, refl, gpol, gfan)
+    o_refl, o_par = oracle_backward(frames, refl, gpol, gfan)
+    assert refl.shape[0] > 64
+    assert_grad_close(g_refl, o_refl, GRAD_RTOL_ORACLE, "refl vs oracle")
+    assert_grad_close(g_par[0, :5], o_par, GRAD_RTOL_ORACLE, "params vs oracle")
+
+
+def test_sonar_backward_fan_only_and_bitwise_repeat():
+    _say("sonar backward, fan-only loss, five repeats")
+    frames, refl, gpol, gfan = _bwd_case(W.SPECKLE_PAPER, 64, n_frames=2, polar=False)
+    runs = [gpu_backward(frames, refl, gpol, gfan) for _ in range(5)]
+    for a, b in runs[1:]:
+        np.testing.assert_array_equal(a, runs[0][0])
+        np.testing.assert_array_equal(b, runs[0][1])
+    o_refl, o_par = oracle_backward(frames, refl, gpol, gfan)
+    assert_grad_close(runs[0][0], o_refl, GRAD_RTOL_ORACLE, "refl vs oracle")
+    assert_grad_close(runs[0][1][0, :5], o_par, GRAD_RTOL_ORACLE, "params vs oracle")
+
+
+# --------------------------------------------------------------------------- #
+# camera                                                                      #
+# --------------------------------------------------------------------------- #
+def _gpu_uw(cams, waters):
+    import torch
+    osm = _osm()
+    Js = [torch.as_tensor(c.J).cuda() for c in cams]
+    ds = [torch.as_tensor(c.depth).cuda() for c in cams]
+    water = osm.water_params([(w.beta_d, w.beta_b, w.b_inf) for w in waters])
+    outs = osm.uw_form(Js, ds, water, [c.water_row for c in cams])
+    torch.cuda.synchronize()
+    return [o.cpu().numpy() for o in outs]
+
+
+def test_uw_forward_c2():
+    _say("uw_form 1920x1080")
+    cams, waters = W.camera_c2()
+    got = _gpu_uw(cams, waters)[0]
+    w = waters[0]
+    want = oracle.uw_forward(cams[0].J, cams[0].depth, w.beta_d, w.beta_b, w.b_inf)
+    assert_image_close(got, want, "uw 1080p")
+
+
+def test_uw_special_cases_and_ragged_batch():
+    _say("uw_form special cases, ragged batch")
+    st = W.Stream(12, 12)
+    shapes = [(7, 13), (32, 32), (1, 1), (5, 3), (64, 33)]
+    cams = [W.make_camera(st, h, w, water_row=k % 2) for k, (h, w) in enumerate(shapes)]
+    cams[2].depth[:] = np.inf
+    cams[3].depth[:] = 0.0
+    waters = [W.make_water(st), W.WaterSpec(beta_d=np.zeros(3, np.float32), beta_b=np.zeros(3, np.float32),
+                                            b_inf=np.array([0.1, 0.2, 0.3], np.float32))]
+    got = _gpu_uw(cams, waters)
+    for c, g in zip(cams, got):
+        w = waters[c.water_row]
+        want = oracle.uw_forward(c.J, c.depth, w.beta_d, w.beta_b, w.b_inf)
+        assert_image_close(g, want, "uw %s" % (c.depth.shape,))
+        if c.water_row == 1:
+            np.testing.assert_array_equal(g, c.J)   # no water: the clear image, bit for bit
+
+
+def test_uw_backward():
+    _say("uw_form backward")
+    import torch
+    osm = _osm()
+    st = W.Stream(13, 13)
+    cams = [W.make_camera(st, 96, 64), W.make_camera(st, 540, 960), W.make_camera(st, 3, 5)]
+    water = W.make_water(st)
+    gos = [W.loss_weights((13, k), c.J.shape) for k, c in enumerate(cams)]
+    Js = [torch.as_tensor(c.J).cuda() for c in cams]
+    ds = [torch.as_tensor(c.depth).cuda() for c in cams]
+    wt = osm.water_params([(water.beta_d, water.beta_b, water.b_inf)])
+    g_w, gJ, gd = osm.uw_form_backward(Js, ds, wt, [torch.as_tensor(g).cuda() for g in gos])
+    torch.cuda.synchronize()
+    o_par = np.zeros(9)
+    bd, bb, bi = (x.astype(np.float64) for x in (water.beta_d, water.beta_b, water.b_inf))
+    for k, c in enumerate(cams):
+        p, oj, od = oracle.uw_backward(c.J, c.depth, bd, bb, bi, gos[k])
+        o_par += p
+        assert_image_close(gJ[k].cpu().numpy(), oj, "grad J %d" % k)
+        # dL/dd sums terms of both signs over the channels: bound its error by
+        # 1e-5 of the sum of the magnitudes of those terms (its condition)
+        d = c.depth.astype(np.float64)[None]
+        J = c.J.astype(np.float64)
+        T = np.exp(-bd[:, None, None] * d)
+        S = np.exp(-bb[:, None, None] * d)
+        cond = (np.abs(gos[k]) * (bd[:, None, None] * np.abs(J) * T + bi[:, None, None] * bb[:, None, None] * S)).sum(0)
+        err = np.abs(gd[k].cpu().numpy().astype(np.float64) - od)
+        assert np.all(err <= 1e-5 * cond + 1e-30), "grad depth %d: worst %.3e" % (k, (err / np.maximum(cond, 1e-300)).max())
+    assert_grad_close(g_w.cpu().numpy()[0], o_par, GRAD_RTOL_ORACLE, "water params vs oracle")
+    params = np.concatenate([bd, bb, bi])
+    for k in range(9):
+        h = 1e-6 * max(1.0, abs(params[k]))
+        p1, p2 = params.copy(), params.copy()
+        p1[k] += h
+        p2[k] -= h
+        L = lambda p: sum(float((g * oracle.uw_forward(c.J, c.depth, p[:3], p[3:6], p[6:])).sum())
+                          for c, g in zip(cams, gos))
+        fd = (L(p1) - L(p2)) / (2 * h)
+        assert abs(g_w.cpu().numpy()[0, k] - fd) <= GRAD_RTOL_FD * abs(fd), (k, fd)
