@@ -1,0 +1,363 @@
+"""Throughput of the OceanSim sonar + underwater-camera image-formation path on
+one MI355X.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-batched] [--no-cpu]
+
+A step is one forward + backward pass of the whole path over the real-time
+workload: one sonar frame of 1024 beams x 128 rays = 131072 returns binned on a
+1024 x 1024 polar grid with gamma speckle and a 1024 x 2048 fan, plus Eq. (1)
+on one 1920 x 1080 RGB frame, and the adjoints of both with respect to the
+reflectivities, the sonar parameters and the water parameters.  Inputs are
+seeded synthetic data already resident in device memory.
+
+Prints one JSON line.  ``value`` is sonar returns per second through the full
+step; the line also carries forward-only and batched throughputs, the roofline
+of the dominant kernel (timed with HIP events on the stream it runs on) and
+the FP64 oracle timed on the host's cores on a bounded sample.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def log(msg):
+    print("[bench] " + msg, file=sys.stderr, flush=True)
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    return ap.parse_args()
+
+
+class RealTimeStep:
+    """Device buffers and prebuilt descriptors of the real-time workload."""
+
+    def __init__(self, dev):
+        import torch
+        import numpy as np
+        import paper_2503_01074_amd as osm
+        from paper_2503_01074_amd import _lib
+        from paper_2503_01074_amd.api import _sonar_struct, _uw_struct
+        import workloads as W
+
+        self.torch, self.lib = torch, _lib
+        frame = W.sonar_c2()[0]
+        cams, waters = W.camera_c2()
+        self.frame, self.cam, self.water_host = frame, cams[0], waters[0]
+        spec, hits = frame.spec, frame.hits
+        self.n_returns = hits.n
+        self.geom = osm.SonarGeometry.from_spec(spec)
+        self.hits = osm.DeviceHits.from_host(hits, dev)
+        self.params = osm.sonar_params([osm.sonar_params_from_spec(spec)], dev)
+        self.refl = torch.as_tensor(hits.refl, device=dev)
+        self.n_mat = int(self.refl.numel())
+        self.polar = torch.empty(spec.n_range, spec.n_azimuth, device=dev)
+        self.fan = torch.empty(spec.fan_h, spec.fan_w, device=dev)
+        self.gpol = torch.as_tensor(W.loss_weights((101, 1), (spec.n_range, spec.n_azimuth)), device=dev)
+        self.gfan = torch.as_tensor(W.loss_weights((101, 2), (spec.fan_h, spec.fan_w)), device=dev)
+        self.fwd = _sonar_struct(self.geom, self.hits, self.polar, self.fan)
+        self.bwd = _sonar_struct(self.geom, self.hits, grad_polar=self.gpol, grad_fan=self.gfan)
+        self.ws_f = torch.empty(_lib.oceansim_sonar_workspace_size(self.fwd, self.n_mat, False),
+                                dtype=torch.uint8, device=dev)
+        self.ws_b = torch.empty(_lib.oceansim_sonar_workspace_size(self.bwd, self.n_mat, True),
+                                dtype=torch.uint8, device=dev)
+        self.g_refl = torch.empty(self.n_mat, device=dev)
+        self.g_par = torch.empty(1, _lib.SONAR_GRAD_WIDTH, device=dev)
+
+        H, Wd = self.cam.depth.shape
+        self.npix = H * Wd
+        self.J = torch.as_tensor(self.cam.J, device=dev)
+        self.d = torch.as_tensor(self.cam.depth, device=dev)
+        self.img = torch.empty_like(self.J)
+        w = self.water_host
+        self.water = osm.water_params([(w.beta_d, w.beta_b, w.b_inf)], dev)
+        self.gimg = torch.as_tensor(W.loss_weights((101, 3), self.cam.J.shape), device=dev)
+        self.gJ = torch.empty_like(self.J)
+        self.gd = torch.empty_like(self.d)
+        self.uwf = _uw_struct(self.J, self.d, self.img)
+        self.uwb = _uw_struct(self.J, self.d, None, 0, self.gimg, self.gJ, self.gd)
+        self.ws_u = torch.empty(max(256, _lib.oceansim_uw_workspace_size(self.uwb, True)),
+                                dtype=torch.uint8, device=dev)
+        self.g_w = torch.empty(1, _lib.WATER_GRAD_WIDTH, device=dev)
+        self.stream = torch.cuda.current_stream(dev).cuda_stream
+        self.P = lambda t: t.data_ptr()
+
+    def sonar_forward(self):
+        L, P = self.lib, self.P
+        L.oceansim_sonar_render(self.fwd, P(self.params), 1, P(self.refl), self.n_mat, P(self.ws_f),
+                                self.ws_f.numel(), self.stream)
+
+    def sonar_backward(self):
+        L, P = self.lib, self.P
+        L.oceansim_sonar_render_backward(self.bwd, P(self.params), 1, P(self.refl), self.n_mat,
+                                         P(self.g_refl), P(self.g_par), P(self.ws_b), self.ws_b.numel(),
+                                         self.stream)
+
+    def uw_forward(self):
+        L, P = self.lib, self.P
+        L.oceansim_uw_form(self.uwf, P(self.water), 1, 0, 0, self.stream)
+
+    def uw_backward(self):
+        L, P = self.lib, self.P
+        L.oceansim_uw_form_backward(self.uwb, P(self.water), 1, P(self.g_w), P(self.ws_u), self.ws_u.numel(),
+                                    self.stream)
+
+    def forward(self):
+        self.sonar_forward()
+        self.uw_forward()
+
+    def step(self):
+        self.sonar_forward()
+        self.uw_forward()
+        self.sonar_backward()
+        self.uw_backward()
+
+
+def timed(torch, fn, steps, warmup):
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        fn()
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) / steps
+
+
+def event_time(torch, fn, reps):
+    """Average duration of fn's GPU work, from HIP events on the current stream."""
+    s = torch.cuda.current_stream()
+    fn()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record(s)
+    for _ in range(reps):
+        fn()
+    b.record(s)
+    b.synchronize()
+    return a.elapsed_time(b) / 1e3 / reps
+
+
+def batched_legs(torch, dev, steps):
+    """Ragged batch of 256 sonar frames (forward, one call) and a differentiable
+    batch of 32 sonar + 32 camera frames (forward + backward, one call per
+    entry point), with descriptors and buffers prepared before timing."""
+    import numpy as np
+    import paper_2503_01074_amd as osm
+    from paper_2503_01074_amd import _lib
+    from paper_2503_01074_amd.api import _sonar_struct, _uw_struct
+    import workloads as W
+
+    stream = torch.cuda.current_stream(dev).cuda_stream
+    P = lambda t: t.data_ptr()
+    out = {}
+
+    frames = W.sonar_c3()
+    tables, base, hits = [], 0, []
+    for f in frames:
+        mat = np.where(f.hits.mat >= 0, f.hits.mat + base, f.hits.mat).astype(np.int32)
+        tables.append(f.hits.refl)
+        base += f.hits.refl.shape[0]
+        h = osm.DeviceHits.from_host(f.hits, dev)
+        h.mat = torch.as_tensor(mat, device=dev)
+        hits.append(h)
+    refl = torch.as_tensor(np.concatenate(tables), device=dev)
+    geoms = [osm.SonarGeometry.from_spec(f.spec, param_row=i) for i, f in enumerate(frames)]
+    params = osm.sonar_params([osm.sonar_params_from_spec(f.spec) for f in frames], dev)
+    polars = [torch.empty(g.n_range, g.n_azimuth, device=dev) for g in geoms]
+    fans = [torch.empty(g.fan_h, g.fan_w, device=dev) for g in geoms]
+    arr = (_lib.SonarFrame * len(frames))(*[_sonar_struct(g, h, p, q) for g, h, p, q in
+                                            zip(geoms, hits, polars, fans)])
+    need = _lib.oceansim_sonar_workspace_size(arr, int(refl.numel()), False)
+    ws = torch.empty(need, dtype=torch.uint8, device=dev)
+    n_ret = sum(f.hits.n for f in frames)
+
+    def c3():
+        _lib.oceansim_sonar_render(arr, P(params), len(frames), P(refl), int(refl.numel()), P(ws), need, stream)
+    t = timed(torch, c3, max(5, steps // 10), 3)
+    out["batched_c3_fwd"] = {"frames": len(frames), "returns": n_ret, "ms": t * 1e3,
+                             "frames_per_s": len(frames) / t, "returns_per_s": n_ret / t}
+    log("C3 batched forward: %.3f ms for %d frames" % (t * 1e3, len(frames)))
+    del hits, polars, fans, ws, arr
+    torch.cuda.empty_cache()
+
+    frames = W.sonar_c4()
+    cams, waters = W.camera_c4()
+    refl = torch.as_tensor(frames[0].hits.refl, device=dev)
+    n_mat = int(refl.numel())
+    hits = [osm.DeviceHits.from_host(f.hits, dev) for f in frames]
+    geoms = [osm.SonarGeometry.from_spec(f.spec, param_row=0) for f in frames]
+    params = osm.sonar_params([osm.sonar_params_from_spec(frames[0].spec)], dev)
+    polars = [torch.empty(g.n_range, g.n_azimuth, device=dev) for g in geoms]
+    fans = [torch.empty(g.fan_h, g.fan_w, device=dev) for g in geoms]
+    gp = [torch.as_tensor(W.loss_weights((202, k), (g.n_range, g.n_azimuth)), device=dev)
+          for k, g in enumerate(geoms)]
+    gf = [torch.as_tensor(W.loss_weights((203, k), (g.fan_h, g.fan_w)), device=dev) for k, g in enumerate(geoms)]
+    sf = (_lib.SonarFrame * len(frames))(*[_sonar_struct(g, h, p, q) for g, h, p, q in
+                                           zip(geoms, hits, polars, fans)])
+    sb = (_lib.SonarFrame * len(frames))(*[_sonar_struct(g, h, grad_polar=a, grad_fan=b) for g, h, a, b in
+                                           zip(geoms, hits, gp, gf)])
+    ws_f = torch.empty(_lib.oceansim_sonar_workspace_size(sf, n_mat, False), dtype=torch.uint8, device=dev)
+    ws_b = torch.empty(_lib.oceansim_sonar_workspace_size(sb, n_mat, True), dtype=torch.uint8, device=dev)
+    g_refl = torch.empty(n_mat, device=dev)
+    g_par = torch.empty(1, _lib.SONAR_GRAD_WIDTH, device=dev)
+    Js = [torch.as_tensor(c.J, device=dev) for c in cams]
+    ds = [torch.as_tensor(c.depth, device=dev) for c in cams]
+    imgs = [torch.empty_like(J) for J in Js]
+    gi = [torch.as_tensor(W.loss_weights((204, k), c.J.shape), device=dev) for k, c in enumerate(cams)]
+    gJ = [torch.empty_like(J) for J in Js]
+    gd = [torch.empty_like(d) for d in ds]
+    w = waters[0]
+    water = osm.water_params([(w.beta_d, w.beta_b, w.b_inf)], dev)
+    uf = (_lib.UwFrame * len(cams))(*[_uw_struct(J, d, o) for J, d, o in zip(Js, ds, imgs)])
+    ub = (_lib.UwFrame * len(cams))(*[_uw_struct(J, d, None, 0, g, a, b) for J, d, g, a, b in
+                                      zip(Js, ds, gi, gJ, gd)])
+    ws_uf = torch.empty(max(256, _lib.oceansim_uw_workspace_size(uf, False)), dtype=torch.uint8, device=dev)
+    ws_ub = torch.empty(max(256, _lib.oceansim_uw_workspace_size(ub, True)), dtype=torch.uint8, device=dev)
+    g_w = torch.empty(1, _lib.WATER_GRAD_WIDTH, device=dev)
+    n_ret = sum(f.hits.n for f in frames)
+
+    def c4_fwd():
+        _lib.oceansim_sonar_render(sf, P(params), 1, P(refl), n_mat, P(ws_f), ws_f.numel(), stream)
+        _lib.oceansim_uw_form(uf, P(water), 1, P(ws_uf), ws_uf.numel(), stream)
+
+    def c4_step():
+        c4_fwd()
+        _lib.oceansim_sonar_render_backward(sb, P(params), 1, P(refl), n_mat, P(g_refl), P(g_par), P(ws_b),
+                                            ws_b.numel(), stream)
+        _lib.oceansim_uw_form_backward(ub, P(water), 1, P(g_w), P(ws_ub), ws_ub.numel(), stream)
+
+    tf = timed(torch, c4_fwd, max(5, steps // 5), 3)
+    ts = timed(torch, c4_step, max(5, steps // 5), 3)
+    out["batched_c4"] = {"sonar_frames": len(frames), "camera_frames": len(cams), "returns": n_ret,
+                         "fwd_ms": tf * 1e3, "fwd_bwd_ms": ts * 1e3,
+                         "fwd_bwd_frames_per_s": (len(frames) + len(cams)) / ts,
+                         "fwd_bwd_returns_per_s": n_ret / ts}
+    log("C4 batched: fwd %.3f ms, fwd+bwd %.3f ms" % (tf * 1e3, ts * 1e3))
+    return out
+
+
+def cpu_baseline(rt, budget_s):
+    """The FP64 oracle on this host's cores over a bounded sample of the same
+    workload: whole sonar frames (forward + backward) and the camera frame."""
+    import numpy as np
+    import oracle
+    import workloads as W
+
+    spec = rt.frame.spec
+    cfg = oracle.SonarConfig.from_spec(spec)
+    hits = rt.frame.hits
+    gp = W.loss_weights((101, 1), (spec.n_range, spec.n_azimuth))
+    gf = W.loss_weights((101, 2), (spec.fan_h, spec.fan_w))
+    w = rt.water_host
+    gi = W.loss_weights((101, 3), rt.cam.J.shape)
+    t0 = time.perf_counter()
+    n = 0
+    while True:
+        oracle.sonar_forward(cfg, hits, hits.refl)
+        oracle.uw_forward(rt.cam.J, rt.cam.depth, w.beta_d, w.beta_b, w.b_inf)
+        oracle.sonar_backward(cfg, hits, hits.refl, gp, gf)
+        oracle.uw_backward(rt.cam.J, rt.cam.depth, w.beta_d, w.beta_b, w.b_inf, gi, True)
+        n += 1
+        el = time.perf_counter() - t0
+        if el >= budget_s or n >= 50:
+            break
+    return {"value": n * hits.n / el, "unit": "returns/s", "cores": oracle.num_threads(), "kind": "oracle",
+            "sample": "%d full step(s) of the real-time workload (sonar fwd+bwd, camera fwd+bwd) in %.1f s"
+                      % (n, el)}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print("bench.py: this build measures one GPU; --gpus %d is not supported (the path shards by frame "
+              "across GPUs, see the design notes)" % args.gpus, file=sys.stderr)
+        sys.exit(2)
+    import torch
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    log("building workload")
+    rt = RealTimeStep(dev)
+
+    log("timing %d full steps after %d warm-up" % (args.steps, args.warmup))
+    t_step = timed(torch, rt.step, args.steps, args.warmup)
+    t_fwd = timed(torch, rt.forward, args.steps, args.warmup)
+    t_sonar_fwd = timed(torch, rt.sonar_forward, args.steps, args.warmup)
+    log("step %.3f ms, forward %.3f ms, sonar forward %.3f ms" % (t_step * 1e3, t_fwd * 1e3, t_sonar_fwd * 1e3))
+
+    # per-entry-point GPU durations from events on the launch stream
+    reps = max(20, args.steps)
+    parts = {
+        "sonar_forward": event_time(torch, rt.sonar_forward, reps),
+        "sonar_backward": event_time(torch, rt.sonar_backward, reps),
+        "uw_forward": event_time(torch, rt.uw_forward, reps),
+        "uw_backward": event_time(torch, rt.uw_backward, reps),
+    }
+    # dominant kernel by algorithmic bytes: the camera model, 28 B/px forward
+    # (J 12 + depth 4 in, I 12 out) and 44 B/px backward (grad_out 12, J 12,
+    # depth 4 in; grad_J 12, grad_depth 4 out)
+    uw_fwd_bytes = 28 * rt.npix
+    uw_bwd_bytes = 44 * rt.npix
+    dom = "uw_backward" if parts["uw_backward"] >= parts["uw_forward"] else "uw_forward"
+    dom_bytes = uw_bwd_bytes if dom == "uw_backward" else uw_fwd_bytes
+    achieved = dom_bytes / parts[dom] / 1e9
+    roofline = {"bound": "hbm", "kernel": "k_uw_bwd" if dom == "uw_backward" else "k_uw",
+                "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                "bytes_per_launch": dom_bytes, "launch_us": round(parts[dom] * 1e6, 2)}
+
+    extra = {}
+    if not args.no_batched:
+        extra = batched_legs(torch, dev, args.steps)
+    cpu = None
+    if not args.no_cpu:
+        log("timing the FP64 oracle on the host")
+        cpu = cpu_baseline(rt, args.cpu_seconds)
+
+    line = {
+        "metric": "sonar returns/s + frames/s (fwd, fwd+bwd, batched vs plain) at <=1e-5 rel err",
+        "value": rt.n_returns / t_step,
+        "unit": "returns/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": t_step * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "real-time frame: 131072 sonar returns (1024 beams x 128 rays, r in [1,50) m), "
+                               "1024x1024 polar bins, gamma speckle k=4, 1024x2048 fan, plus Eq. 1 on one "
+                               "1920x1080 RGB frame; forward + backward",
+                   "global_batch": 1, "parallelism": "none (1 GPU)"},
+        "frames_per_s": 1.0 / t_step,
+        "fwd_returns_per_s": rt.n_returns / t_fwd,
+        "fwd_frames_per_s": 1.0 / t_fwd,
+        "sonar_fwd_only_frames_per_s": 1.0 / t_sonar_fwd,
+        "camera_mpx_per_s_fwd_bwd": rt.npix / t_step / 1e6,
+        "entry_point_us": {k: round(v * 1e6, 2) for k, v in parts.items()},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+    }
+    line.update(extra)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -78,11 +78,11 @@ def _declare(lib):
     lib.orc_fan_adjoint.restype = None
     lib.orc_sonar_forward.argtypes = [C.POINTER(_Cfg), C.c_int64] + [_P] * 7 + [_P, C.c_int32] + [_P] * 6
     lib.orc_sonar_forward.restype = C.c_int
-    lib.orc_sonar_backward.argtypes = [C.POINTER(_Cfg), C.c_int64] + [_P] * 7 + [_P, C.c_int32] + [_P] * 5
+    lib.orc_sonar_backward.argtypes = [C.POINTER(_Cfg), C.c_int64] + [_P] * 7 + [_P, C.c_int32] + [_P] * 7
     lib.orc_sonar_backward.restype = C.c_int
     lib.orc_uw_forward.argtypes = [C.c_int64] + [_P] * 6
     lib.orc_uw_forward.restype = None
-    lib.orc_uw_backward.argtypes = [C.c_int64] + [_P] * 9
+    lib.orc_uw_backward.argtypes = [C.c_int64] + [_P] * 10
     lib.orc_uw_backward.restype = None
     lib.orc_num_threads.argtypes = []
     lib.orc_num_threads.restype = C.c_int
@@ -219,11 +219,13 @@ def sonar_forward(cfg: SonarConfig, hits, refl, with_fan: bool | None = None):
 SONAR_GRAD_NAMES = ("alpha", "gain", "sigma_phi", "sigma_sa", "sigma_sm")
 
 
-def sonar_backward(cfg: SonarConfig, hits, refl, g_polar=None, g_fan=None):
+def sonar_backward(cfg: SonarConfig, hits, refl, g_polar=None, g_fan=None, with_abs: bool = False):
     """Gradients of <g_polar, out> + <g_fan, fan>.
 
     Returns (g_refl [n_mat], g_par [5] in SONAR_GRAD_NAMES order,
-    g_out [n_range, n_azimuth] = gradient with respect to the polar output).
+    g_out [n_range, n_azimuth] = gradient with respect to the polar output),
+    followed, with ``with_abs``, by the sums of term magnitudes of g_refl and
+    g_par (the condition of each gradient sum).
     """
     arrs = _hits(hits)
     refl = _f32(refl)
@@ -231,10 +233,14 @@ def sonar_backward(cfg: SonarConfig, hits, refl, g_polar=None, g_fan=None):
     g_refl = np.zeros(refl.shape[0], np.float64)
     g_par = np.zeros(5, np.float64)
     g_out = np.empty((cfg.n_range, cfg.n_azimuth), np.float64)
+    a_refl = np.zeros(refl.shape[0], np.float64) if with_abs else None
+    a_par = np.zeros(5, np.float64) if with_abs else None
     c = cfg._c()
     _load().orc_sonar_backward(C.byref(c), n, *[_ptr(a) for a in arrs], _ptr(refl), refl.shape[0],
                                _ptr(_f64(g_polar)), _ptr(_f64(g_fan)), _ptr(g_refl), _ptr(g_par),
-                               _ptr(g_out))
+                               _ptr(g_out), _ptr(a_refl), _ptr(a_par))
+    if with_abs:
+        return g_refl, g_par, g_out, a_refl, a_par
     return g_refl, g_par, g_out
 
 
@@ -256,16 +262,21 @@ def uw_forward(J, depth, beta_d, beta_b, b_inf):
 UW_GRAD_NAMES = ("beta_d", "beta_b", "b_inf")
 
 
-def uw_backward(J, depth, beta_d, beta_b, b_inf, g_out, want_image_grads: bool = True):
-    """Gradients of <g_out, I>: (g_par [9] = beta_d[3], beta_b[3], b_inf[3], g_J, g_depth)."""
+def uw_backward(J, depth, beta_d, beta_b, b_inf, g_out, want_image_grads: bool = True,
+                with_abs: bool = False):
+    """Gradients of <g_out, I>: (g_par [9] = beta_d[3], beta_b[3], b_inf[3], g_J, g_depth),
+    followed, with ``with_abs``, by the sums of term magnitudes of g_par."""
     J = _f32(J)
     depth = _f32(depth)
     npix = depth.size
     bd, bb, bi = _water(beta_d, beta_b, b_inf)
     g_out = _f64(g_out)
     g_par = np.zeros(9, np.float64)
+    a_par = np.zeros(9, np.float64) if with_abs else None
     g_J = np.empty(J.shape, np.float64) if want_image_grads else None
     g_d = np.empty(depth.shape, np.float64) if want_image_grads else None
     _load().orc_uw_backward(npix, _ptr(J), _ptr(depth), _ptr(bd), _ptr(bb), _ptr(bi), _ptr(g_out),
-                            _ptr(g_par), _ptr(g_J), _ptr(g_d))
+                            _ptr(g_par), _ptr(g_J), _ptr(g_d), _ptr(a_par))
+    if with_abs:
+        return g_par, g_J, g_d, a_par
     return g_par, g_J, g_d

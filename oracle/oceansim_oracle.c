@@ -421,13 +421,17 @@ int orc_sonar_forward(const orc_sonar_cfg *c, int64_t n,
 /* (accumulated).  The forward is recomputed; nothing is saved between calls.*/
 /* Either gradient input may be NULL (zero).  g_out (optional) receives the  */
 /* gradient of L with respect to the polar output, [n_range][n_azimuth].     */
+/* g_refl_abs / g_par_abs (optional) accumulate the sums of the magnitudes   */
+/* of the terms each gradient component adds up: the condition of that sum, */
+/* against which a float32 evaluation's rounding error is measured.          */
 /* ------------------------------------------------------------------------- */
 int orc_sonar_backward(const orc_sonar_cfg *c, int64_t n,
                        const float *x, const float *y, const float *z,
                        const float *nx, const float *ny, const float *nz,
                        const int32_t *mat, const float *refl, int32_t n_mat,
                        const double *g_polar, const double *g_fan,
-                       double *g_refl, double *g_par, double *g_out)
+                       double *g_refl, double *g_par, double *g_out,
+                       double *g_refl_abs, double *g_par_abs)
 {
     int64_t nb = (int64_t)c->n_range * c->n_azimuth;
     double *P = (double *)malloc(sizeof(double) * nb);
@@ -445,6 +449,7 @@ int orc_sonar_backward(const orc_sonar_cfg *c, int64_t n,
 
     /* adjoint of steps 3-4 */
     double gG = 0.0, gsphi = 0.0, gssa = 0.0, gssm = 0.0;
+    double aG = 0.0, asphi = 0.0, assa = 0.0, assm = 0.0, aalpha = 0.0;
     for (int64_t b = 0; b < nb; ++b) {
         int i = (int)(b / c->n_azimuth), j = (int)(b % c->n_azimuth);
         double Q = c->gain * P[b];
@@ -459,12 +464,20 @@ int orc_sonar_backward(const orc_sonar_cfg *c, int64_t n,
             double R = ri * ri / (c->r_max * c->r_max);
             double E = exp(-(pj * pj) / c->sigma_phi);
             /* d add / d sigma_sa and d add / d sigma_phi, from Eq. (3)-(4) */
-            gssa += gO[b] * R * 0.5 * E * rayleigh;
-            gsphi += gO[b] * R * 0.5 * c->sigma_sa * rayleigh * E * (pj * pj) /
-                     (c->sigma_phi * c->sigma_phi);
-            if (c->speckle_mode == ORC_SPECKLE_PAPER) gssm += gO[b] * Q * gauss;
+            double tsa = gO[b] * R * 0.5 * E * rayleigh;
+            double tphi = gO[b] * R * 0.5 * c->sigma_sa * rayleigh * E * (pj * pj) /
+                          (c->sigma_phi * c->sigma_phi);
+            gssa += tsa;
+            gsphi += tphi;
+            assa += fabs(tsa);
+            asphi += fabs(tphi);
+            if (c->speckle_mode == ORC_SPECKLE_PAPER) {
+                gssm += gO[b] * Q * gauss;
+                assm += fabs(gO[b] * Q * gauss);
+            }
         }
         gG += gQ * P[b];
+        aG += fabs(gQ * P[b]);
         gP[b] = c->gain * gQ;
     }
 
@@ -481,12 +494,21 @@ int orc_sonar_backward(const orc_sonar_cfg *c, int64_t n,
         double gI = gP[b];
         g_refl[m] += gI * cosg * att;
         galpha += gI * I * (-c->kappa * r);
+        if (g_refl_abs) g_refl_abs[m] += fabs(gI * cosg * att);
+        aalpha += fabs(gI * I * c->kappa * r);
     }
     g_par[0] += galpha;
     g_par[1] += gG;
     g_par[2] += gsphi;
     g_par[3] += gssa;
     g_par[4] += gssm;
+    if (g_par_abs) {
+        g_par_abs[0] += aalpha;
+        g_par_abs[1] += aG;
+        g_par_abs[2] += asphi;
+        g_par_abs[3] += assa;
+        g_par_abs[4] += assm;
+    }
     free(P);
     free(gO);
     free(gP);
@@ -528,12 +550,13 @@ void orc_uw_forward(int64_t npix, const float *J, const float *depth, const doub
  *   dI/dJ = T,            dI/dd = -beta_D J T + B_inf beta_B S.              */
 void orc_uw_backward(int64_t npix, const float *J, const float *depth, const double *beta_d,
                      const double *beta_b, const double *b_inf, const double *g_out,
-                     double *g_par, double *g_J, double *g_d)
+                     double *g_par, double *g_J, double *g_d, double *g_par_abs)
 {
     if (g_d)
         for (int64_t p = 0; p < npix; ++p) g_d[p] = 0.0;
     for (int ch = 0; ch < 3; ++ch) {
         double s_bd = 0.0, s_bb = 0.0, s_binf = 0.0;
+        double a_bd = 0.0, a_bb = 0.0, a_binf = 0.0;
         for (int64_t p = 0; p < npix; ++p) {
             double d = depth[p];
             double T = exp(-orc_beta_d(beta_d[ch], d));
@@ -542,15 +565,27 @@ void orc_uw_backward(int64_t npix, const float *J, const float *depth, const dou
             double g = g_out[ch * npix + p];
             double Jv = J[ch * npix + p];
             /* the d-weighted terms vanish where T or S does (0 * inf := 0) */
-            if (T != 0.0) s_bd += g * (-Jv * T * d);
-            if (S != 0.0) s_bb += g * (b_inf[ch] * S * d);
+            if (T != 0.0) {
+                s_bd += g * (-Jv * T * d);
+                a_bd += fabs(g * Jv * T * d);
+            }
+            if (S != 0.0) {
+                s_bb += g * (b_inf[ch] * S * d);
+                a_bb += fabs(g * b_inf[ch] * S * d);
+            }
             s_binf += g * one_minus_S;
+            a_binf += fabs(g * one_minus_S);
             if (g_J) g_J[ch * npix + p] = g * T;
             if (g_d) g_d[p] += g * (-beta_d[ch] * Jv * T + b_inf[ch] * beta_b[ch] * S);
         }
         g_par[ch] += s_bd;
         g_par[3 + ch] += s_bb;
         g_par[6 + ch] += s_binf;
+        if (g_par_abs) {
+            g_par_abs[ch] += a_bd;
+            g_par_abs[3 + ch] += a_bb;
+            g_par_abs[6 + ch] += a_binf;
+        }
     }
 }
 

@@ -2,9 +2,12 @@
 
 Images (polar, fan, camera): per element |gpu - oracle| <= 1e-5 * max(|oracle|,
 1e-3 * max|oracle|), i.e. 1e-5 relative with a floor at 1e-3 of the image's
-peak for elements near zero.  Parameter gradients: 1e-5 relative to the FP64
-oracle's analytic gradient (floor 1e-3 of the largest component) and 1e-3
-relative to FP64 central differences.  Bin indices: bit-exact.
+peak for elements near zero.  Bin indices: bit-exact.
+
+Parameter gradients are sums of many float32 terms of both signs.  Against
+the FP64 oracle's analytic gradient each component must agree to 1e-5 of the
+sum of the magnitudes of its terms (the condition of the sum, reported by the
+oracle); against FP64 central differences to 1e-3 relative.
 """
 import numpy as np
 
@@ -44,3 +47,14 @@ def assert_grad_close(got, want, rtol, what=""):
     err = np.abs(got - want)
     ok = err <= rtol * scale + 1e-30
     assert ok.all(), "%s: got %s want %s (rel %s)" % (what, got[~ok], want[~ok], (err / np.maximum(scale, 1e-300))[~ok])
+
+
+def assert_grad_cond(got, want, cond, rtol=GRAD_RTOL_ORACLE, what=""):
+    """|got - want| <= rtol * cond per component, cond = sum of |terms|."""
+    got = np.asarray(got, np.float64).ravel()
+    want = np.asarray(want, np.float64).ravel()
+    cond = np.asarray(cond, np.float64).ravel()
+    err = np.abs(got - want)
+    ok = err <= rtol * cond + 1e-30
+    assert ok.all(), "%s: got %s want %s err/cond %s" % (what, got[~ok], want[~ok],
+                                                        (err / np.maximum(cond, 1e-300))[~ok])

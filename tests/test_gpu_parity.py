@@ -15,7 +15,7 @@ import oracle
 from oracle import SonarConfig
 import workloads as W
 from _cases import build_hits, hit_at, tiny_golden
-from _tol import (GRAD_RTOL_FD, GRAD_RTOL_ORACLE, assert_grad_close, assert_image_close)
+from _tol import (GRAD_RTOL_FD, GRAD_RTOL_ORACLE, assert_grad_cond, assert_image_close)
 
 pytestmark = pytest.mark.gpu
 
@@ -201,13 +201,19 @@ def gpu_backward(frames, refl, gpol, gfan):
 
 
 def oracle_backward(frames, refl, gpol, gfan):
+    """Summed oracle gradients and their conditions (sums of term magnitudes)."""
     g_refl = np.zeros(refl.shape[0])
     g_par = np.zeros(5)
+    a_refl = np.zeros(refl.shape[0])
+    a_par = np.zeros(5)
     for f, gp, gf in zip(frames, gpol, gfan):
-        a, b, _ = oracle.sonar_backward(SonarConfig.from_spec(f.spec), f.hits, refl, gp, gf)
+        a, b, _, ca, cb = oracle.sonar_backward(SonarConfig.from_spec(f.spec), f.hits, refl, gp, gf,
+                                                with_abs=True)
         g_refl += a
         g_par += b
-    return g_refl, g_par
+        a_refl += ca
+        a_par += cb
+    return g_refl, g_par, a_refl, a_par
 
 
 def _bwd_case(mode, n_mat, n_frames=1, fan=True, polar=True, seed=0):
@@ -247,9 +253,9 @@ def test_sonar_backward_vs_oracle_and_fd(mode, n_mat):
     _say("sonar backward mode %d n_mat %d" % (mode, n_mat))
     frames, refl, gpol, gfan = _bwd_case(mode, n_mat, n_frames=2)
     g_refl, g_par = gpu_backward(frames, refl, gpol, gfan)
-    o_refl, o_par = oracle_backward(frames, refl, gpol, gfan)
-    assert_grad_close(g_refl, o_refl, GRAD_RTOL_ORACLE, "refl vs oracle")
-    assert_grad_close(g_par[0, :5], o_par, GRAD_RTOL_ORACLE, "params vs oracle")
+    o_refl, o_par, c_refl, c_par = oracle_backward(frames, refl, gpol, gfan)
+    assert_grad_cond(g_refl, o_refl, c_refl, what="refl vs oracle")
+    assert_grad_cond(g_par[0, :5], o_par, c_par, what="params vs oracle")
     assert np.all(g_par[0, 5:] == 0)
     # FP64 central differences of the oracle's forward pass, one parameter at a time
     for k, name in enumerate(["alpha", "gain", "sigma_phi", "sigma_sa", "sigma_sm"]):
@@ -266,10 +272,10 @@ def test_sonar_backward_many_materials_and_polar_only():
     _say("sonar backward, per-return reflectivity (atomic path), polar-only loss")
     frames, refl, gpol, gfan = _bwd_case(W.SPECKLE_GAMMA, None, n_frames=3, fan=False)
     g_refl, g_par = gpu_backward(frames, refl, gpol, gfan)
-    o_refl, o_par = oracle_backward(frames, refl, gpol, gfan)
+    o_refl, o_par, c_refl, c_par = oracle_backward(frames, refl, gpol, gfan)
     assert refl.shape[0] > 64
-    assert_grad_close(g_refl, o_refl, GRAD_RTOL_ORACLE, "refl vs oracle")
-    assert_grad_close(g_par[0, :5], o_par, GRAD_RTOL_ORACLE, "params vs oracle")
+    assert_grad_cond(g_refl, o_refl, c_refl, what="refl vs oracle")
+    assert_grad_cond(g_par[0, :5], o_par, c_par, what="params vs oracle")
 
 
 def test_sonar_backward_fan_only_and_bitwise_repeat():
@@ -279,9 +285,9 @@ def test_sonar_backward_fan_only_and_bitwise_repeat():
     for a, b in runs[1:]:
         np.testing.assert_array_equal(a, runs[0][0])
         np.testing.assert_array_equal(b, runs[0][1])
-    o_refl, o_par = oracle_backward(frames, refl, gpol, gfan)
-    assert_grad_close(runs[0][0], o_refl, GRAD_RTOL_ORACLE, "refl vs oracle")
-    assert_grad_close(runs[0][1][0, :5], o_par, GRAD_RTOL_ORACLE, "params vs oracle")
+    o_refl, o_par, c_refl, c_par = oracle_backward(frames, refl, gpol, gfan)
+    assert_grad_cond(runs[0][0], o_refl, c_refl, what="refl vs oracle")
+    assert_grad_cond(runs[0][1][0, :5], o_par, c_par, what="params vs oracle")
 
 
 # --------------------------------------------------------------------------- #
@@ -339,10 +345,12 @@ def test_uw_backward():
     g_w, gJ, gd = osm.uw_form_backward(Js, ds, wt, [torch.as_tensor(g).cuda() for g in gos])
     torch.cuda.synchronize()
     o_par = np.zeros(9)
+    c_par = np.zeros(9)
     bd, bb, bi = (x.astype(np.float64) for x in (water.beta_d, water.beta_b, water.b_inf))
     for k, c in enumerate(cams):
-        p, oj, od = oracle.uw_backward(c.J, c.depth, bd, bb, bi, gos[k])
+        p, oj, od, cp = oracle.uw_backward(c.J, c.depth, bd, bb, bi, gos[k], with_abs=True)
         o_par += p
+        c_par += cp
         assert_image_close(gJ[k].cpu().numpy(), oj, "grad J %d" % k)
         # dL/dd sums terms of both signs over the channels: bound its error by
         # 1e-5 of the sum of the magnitudes of those terms (its condition)
@@ -353,7 +361,7 @@ def test_uw_backward():
         cond = (np.abs(gos[k]) * (bd[:, None, None] * np.abs(J) * T + bi[:, None, None] * bb[:, None, None] * S)).sum(0)
         err = np.abs(gd[k].cpu().numpy().astype(np.float64) - od)
         assert np.all(err <= 1e-5 * cond + 1e-30), "grad depth %d: worst %.3e" % (k, (err / np.maximum(cond, 1e-300)).max())
-    assert_grad_close(g_w.cpu().numpy()[0], o_par, GRAD_RTOL_ORACLE, "water params vs oracle")
+    assert_grad_cond(g_w.cpu().numpy()[0], o_par, c_par, what="water params vs oracle")
     params = np.concatenate([bd, bb, bi])
     for k in range(9):
         h = 1e-6 * max(1.0, abs(params[k]))
