@@ -56,7 +56,7 @@ struct SonarPlan {
     // workspace offsets
     size_t off_table = 0;
     std::vector<size_t> off_pairs, off_chunk_off, off_polar, off_grad_img;
-    size_t off_part = 0, off_part_row = 0, off_refl_part = 0;
+    size_t off_part = 0, off_refl_part = 0;
     int n_slots = 0;
 };
 
@@ -128,28 +128,54 @@ int plan_sonar(const oceansim_sonar_frame *frames, int n_frames, int n_param_row
     if (n_mat < 1) return fail(OCEANSIM_E_INVALID_ARG, "n_materials must be >= 1");
     if (n_param_rows < 1) return fail(OCEANSIM_E_INVALID_ARG, "n_param_rows must be >= 1");
     P.dev.assign(n_frames, SonarDev{});
-    int max_tiles = 1, max_tile_bins = 1;
-    // first pass: validation and tiling
+    int max_tiles = 1, max_tile_bins = 1, max_tile_bins_b = 1;
+    long long total_nb = 0, total_n = 0;
+    for (int i = 0; i < n_frames; ++i) {
+        int rc = check_frame(frames[i], i, n_param_rows, backward);
+        if (rc) return rc;
+        total_nb += (long long)frames[i].n_range * frames[i].n_azimuth;
+        total_n += frames[i].n_returns;
+    }
+    // Forward tiles: aim at ~512 tile workgroups per call or more, with
+    // 1024..4096 bins each; a tile holds whole range rows.  Backward tiles:
+    // up to 2048 bins (their pixel work grows with the tile's radial extent).
+    const long long tb_target = std::min<long long>(kMaxTileBins, std::max<long long>(1024, total_nb / 512));
     for (int i = 0; i < n_frames; ++i) {
         const oceansim_sonar_frame &fr = frames[i];
-        int rc = check_frame(fr, i, n_param_rows, backward);
-        if (rc) return rc;
         SonarDev &d = P.dev[i];
-        int rpt = std::max(1, std::min(fr.n_range, kMaxTileBins / fr.n_azimuth));
+        int rpt = std::max(1, std::min(fr.n_range, (int)(tb_target / fr.n_azimuth)));
         int n_tiles = (fr.n_range + rpt - 1) / rpt;
+        while (n_tiles > kMaxTiles && (rpt + 1) * fr.n_azimuth <= kMaxTileBins) {
+            ++rpt;
+            n_tiles = (fr.n_range + rpt - 1) / rpt;
+        }
         if (n_tiles > kMaxTiles) return fail(OCEANSIM_E_UNSUPPORTED, "frame %d: too many polar rows", i);
         d.rows_per_tile = rpt;
         d.tile_bins = rpt * fr.n_azimuth;
         d.n_tiles = n_tiles;
+        const int rpt_b = std::max(1, std::min(fr.n_range, 2048 / fr.n_azimuth));
+        d.rows_per_tile_b = rpt_b;
+        d.tile_bins_b = rpt_b * fr.n_azimuth;
+        d.n_tiles_b = (fr.n_range + rpt_b - 1) / rpt_b;
         max_tiles = std::max(max_tiles, n_tiles);
         max_tile_bins = std::max(max_tile_bins, d.tile_bins);
+        max_tile_bins_b = std::max(max_tile_bins_b, d.tile_bins_b);
     }
-    // one chunk size per call: >= 4 pairs per (chunk, tile) cell on average
-    int chunk = std::min(4096, std::max(1024, pow2_at_least(4LL * max_tiles)));
+    // Returns per binning workgroup: enough workgroups to fill the chip, while
+    // the per-(chunk, tile) offset table stays below ~2 entries per return.
+    int chunk = std::min(4096, std::max(512, pow2_at_least(total_n / 1024)));
+    auto table_entries = [&](int ch) {
+        long long e = 0;
+        for (int i = 0; i < n_frames; ++i)
+            e += (frames[i].n_returns + ch - 1) / ch * (long long)(P.dev[i].n_tiles + 1);
+        return e;
+    };
+    while (chunk < 4096 && table_entries(chunk) > 2 * total_n + (1 << 20)) chunk *= 2;
     P.grid.chunk = chunk;
     P.grid.ret_chunk = chunk;
     P.grid.max_tiles = max_tiles;
     P.grid.max_tile_bins = max_tile_bins;
+    P.grid.max_tile_bins_b = max_tile_bins_b;
 
     size_t off = 0;
     auto take = [&](size_t bytes) {
@@ -162,7 +188,7 @@ int plan_sonar(const oceansim_sonar_frame *frames, int n_frames, int n_param_row
     P.off_chunk_off.assign(n_frames, 0);
     P.off_polar.assign(n_frames, (size_t)-1);
     P.off_grad_img.assign(n_frames, 0);
-    int bin_blocks = 0, tile_blocks = 0, fan_blocks = 0, ret_blocks = 0;
+    int bin_blocks = 0, tile_blocks = 0, tile_b_blocks = 0, fan_blocks = 0, ret_blocks = 0;
     for (int i = 0; i < n_frames; ++i) {
         const oceansim_sonar_frame &fr = frames[i];
         SonarDev &d = P.dev[i];
@@ -189,8 +215,10 @@ int plan_sonar(const oceansim_sonar_frame *frames, int n_frames, int n_param_row
         d.blk[KTILE] = tile_blocks;
         d.blk[KFAN] = fan_blocks;
         d.blk[KRET] = ret_blocks;
+        d.blk[KTILEB] = tile_b_blocks;
         bin_blocks += d.n_chunks;
         tile_blocks += d.n_tiles;
+        tile_b_blocks += d.n_tiles_b;
         fan_blocks += d.fan_blocks;
         ret_blocks += d.n_ret_chunks;
         // geometry in double
@@ -203,6 +231,7 @@ int plan_sonar(const oceansim_sonar_frame *frames, int n_frames, int n_param_row
         d.scale_r = (double)fr.n_range / ((double)fr.r_max - (double)fr.r_min);
         d.scale_phi = (double)fr.n_azimuth / (double)fr.fov_az;
         d.dr = ((double)fr.r_max - (double)fr.r_min) / fr.n_range;
+        d.inv_r_max = 1.0 / (double)fr.r_max;
         d.dphi = (double)fr.fov_az / fr.n_azimuth;
         if (fr.fan_h > 0 && fr.fan_w > 0) {
             const double s1 = (double)fr.r_max / fr.fan_h;
@@ -235,10 +264,10 @@ int plan_sonar(const oceansim_sonar_frame *frames, int n_frames, int n_param_row
     P.grid.tile_blocks = tile_blocks;
     P.grid.fan_blocks = fan_blocks;
     P.grid.ret_blocks = ret_blocks;
+    P.grid.tile_b_blocks = tile_b_blocks;
     if (backward) {
-        P.n_slots = tile_blocks + ret_blocks;
+        P.n_slots = tile_b_blocks + ret_blocks;
         P.off_part = take(sizeof(double) * 5 * (size_t)std::max(1, P.n_slots));
-        P.off_part_row = take(sizeof(int) * (size_t)std::max(1, P.n_slots));
         if (n_mat <= kLaneHistMats)
             P.off_refl_part = take(sizeof(double) * (size_t)std::max(1, ret_blocks) * n_mat);
     }
@@ -397,27 +426,21 @@ int oceansim_sonar_render_backward(const oceansim_sonar_frame *frames, int32_t n
     carve_sonar(P, ws, true);
     hipStream_t st = static_cast<hipStream_t>(stream);
     double *part = reinterpret_cast<double *>(ws + P.off_part);
-    int *part_row = reinterpret_cast<int *>(ws + P.off_part_row);
     const bool lane_hist = n_materials <= kLaneHistMats;
     double *refl_part = lane_hist ? reinterpret_cast<double *>(ws + P.off_refl_part) : nullptr;
     hipError_t e = hipSuccess;
-    if (n_frames == 1) {
-        e = sonar_backward_one(P.dev[0], P.grid, params_dev, refl_dev, n_materials, part, part_row, refl_part,
-                               grad_refl_dev, st);
-    } else if (n_frames > 1) {
+    if (n_frames <= 1) {
+        SonarDev empty{};
+        e = sonar_backward_one(n_frames == 1 ? P.dev[0] : empty, P.grid, params_dev, n_param_rows, refl_dev,
+                               n_materials, part, refl_part, grad_params_dev, grad_refl_dev, st);
+    } else {
         e = upload_table(P.dev, ws, P.off_table, st);
         if (e != hipSuccess) return hip_fail(e, "frame table upload");
         e = sonar_backward_table(reinterpret_cast<const SonarDev *>(ws + P.off_table), n_frames, P.grid,
-                                 params_dev, refl_dev, n_materials, part, part_row, refl_part, grad_refl_dev,
-                                 st);
+                                 params_dev, n_param_rows, refl_dev, n_materials, part, refl_part,
+                                 grad_params_dev, grad_refl_dev, st);
     }
     if (e != hipSuccess) return hip_fail(e, "sonar backward launch");
-    e = reduce_rows(part, part_row, P.n_slots, 5, n_param_rows, grad_params_dev, OCEANSIM_SONAR_GRAD_WIDTH, st);
-    if (e != hipSuccess) return hip_fail(e, "sonar gradient reduction");
-    if (lane_hist) {
-        e = reduce_cols(refl_part, P.grid.ret_blocks, n_materials, grad_refl_dev, st);
-        if (e != hipSuccess) return hip_fail(e, "reflectivity gradient reduction");
-    }
     return ok();
 }
 

@@ -15,7 +15,7 @@ constexpr int kMaxTileBins = 4096;   // polar bins owned by one tile workgroup (
 constexpr int kMaxTiles = 4096;      // tiles per frame (LDS histogram in the binning pass)
 constexpr int kLaneHistMats = 64;    // materials reduced with lane-private LDS histograms
 
-enum Kind { KBIN = 0, KTILE = 1, KFAN = 2, KRET = 3, KIND_COUNT = 4 };
+enum Kind { KBIN = 0, KTILE = 1, KFAN = 2, KRET = 3, KTILEB = 4, KIND_COUNT = 5 };
 enum Speckle { SPECKLE_OFF = 0, SPECKLE_PAPER = 1, SPECKLE_GAMMA = 2 };
 
 // --------------------------------------------------------------------------
@@ -35,14 +35,14 @@ struct SonarDev {
     float *grad_img;            // backward: dL/d(polar image) [nb]
     long long n;                // returns
     int n_range, n_az, fan_h, fan_w;
-    int rows_per_tile, tile_bins, n_tiles;
+    int rows_per_tile, tile_bins, n_tiles;          // forward polar tiles
+    int rows_per_tile_b, tile_bins_b, n_tiles_b;    // backward polar tiles
     int chunk, n_chunks;        // returns per binning workgroup, workgroups
     int ret_chunk, n_ret_chunks;// returns per backward-gather workgroup, workgroups
     int fan_bpr, fan_blocks;    // fan: workgroups per pixel row, total
     int speckle, gamma_k, param_row;
     unsigned seed_lo, seed_hi, frame_id;
     int blk[KIND_COUNT];        // first global workgroup of this frame, per kernel kind
-    int part_base[2];           // first partial-sum slot: [0] tile pass, [1] return pass
     double r_min, r_max;        // polar grid [r_min, r_max)
     double fov_az, half_az;     // full and half azimuth field of view
     double sin_half_el;         // sin(fov_el / 2)
@@ -52,6 +52,7 @@ struct SonarDev {
     double dr, dphi;            // bin sizes
     double fan_s;               // fan pixel size
     double tan_half_az;         // tan(fov_az / 2) (fans need fov_az <= pi)
+    double inv_r_max;           // 1 / r_max
     float scale_phi_f, half_az_f;
     int az_fast;                // FP32 azimuth is accurate to < 1e-3 cell on this grid
 };
@@ -142,16 +143,16 @@ __device__ __forceinline__ float unit_uniform(uint32_t w) {
     return (float)((w >> 8) + 1u) * 5.9604644775390625e-8f;
 }
 
-// -ln(u) for a uniform u in (0, 1] (a multiple of 2^-24).  Near 1 the value
-// is taken as -log1p(u - 1), where u - 1 is exact, to keep full relative
-// accuracy when -ln(u) is tiny.
+// -ln(u) for a uniform u in (0, 1] (a multiple of 2^-24) from the hardware
+// log2.  Over all 2^24 such u its relative error is below 1.7e-7, also where
+// -ln(u) is tiny (u near 1); measured on gfx950 against FP64.
 __device__ __forceinline__ float neg_ln(float u) {
-    return u >= 0.5f ? -log1pf(u - 1.0f) : -logf(u);
+    return -__builtin_amdgcn_logf(u) * 0.69314718055994531f;
 }
 
 // Unit Rayleigh variate of bin b (additive stream, Eq. 4 with sigma = 1).
 __device__ __forceinline__ float rayleigh_of_word(uint32_t w) {
-    return __builtin_sqrtf(2.0f * neg_ln(unit_uniform(w)));
+    return __builtin_amdgcn_sqrtf(2.0f * neg_ln(unit_uniform(w)));
 }
 
 // Multiplicative speckle factor of bin b and, in PAPER mode, its standard
@@ -163,7 +164,7 @@ __device__ __forceinline__ float speckle_factor(const SonarDev &f, uint32_t b, f
         uint32_t h = (b & 1u) * 2u;
         float u0 = unit_uniform(pick(w, h));
         float u1 = unit_uniform(pick(w, h + 1u));
-        float g = __builtin_sqrtf(2.0f * neg_ln(u0)) * cospif(2.0f * u1);
+        float g = __builtin_amdgcn_sqrtf(2.0f * neg_ln(u0)) * cospif(2.0f * u1);
         *gauss_out = g;
         return 0.5f + sigma_sm * g;
     }
@@ -246,7 +247,7 @@ __device__ __forceinline__ float return_intensity(const SonarDev &f, float xf, f
 // bin-centre azimuth phi_j (Eq. 3).
 __device__ __forceinline__ float range_ramp(const SonarDev &f, int i) {
     double ri = f.r_min + ((double)i + 0.5) * f.dr;
-    double q = ri / f.r_max;
+    double q = ri * f.inv_r_max;
     return (float)(q * q);
 }
 __device__ __forceinline__ float bin_azimuth(const SonarDev &f, int j) {
@@ -271,15 +272,12 @@ __device__ __forceinline__ void fan_position(const SonarDev &f, int v, int u, do
     phi = atan2(-xc, yc);
 }
 
-__device__ __forceinline__ bool fan_stencil(const SonarDev &f, double rho, double phi,
-                                            Stencil &st) {
-    if (!(rho >= f.r_min && rho <= f.r_max && phi >= -f.half_az && phi <= f.half_az))
-        return false;
-    double fr = (rho - f.r_min) / f.dr - 0.5;
-    double fp = (phi + f.half_az) / f.dphi - 0.5;
-    double nr1 = (double)(f.n_range - 1), np1 = (double)(f.n_az - 1);
+// Radial half of the stencil: rows and weight of rho (inside test on rho).
+__device__ __forceinline__ bool fan_radial(const SonarDev &f, double rho, Stencil &st) {
+    if (!(rho >= f.r_min && rho <= f.r_max)) return false;
+    double fr = (rho - f.r_min) * f.scale_r - 0.5;
+    const double nr1 = (double)(f.n_range - 1);
     fr = fr < 0.0 ? 0.0 : (fr > nr1 ? nr1 : fr);
-    fp = fp < 0.0 ? 0.0 : (fp > np1 ? np1 : fp);
     if (f.n_range == 1) {
         st.i0 = st.i1 = 0;
         st.t = 0.0;
@@ -290,6 +288,15 @@ __device__ __forceinline__ bool fan_stencil(const SonarDev &f, double rho, doubl
         st.i1 = i0 + 1;
         st.t = fr - (double)i0;
     }
+    return true;
+}
+
+// Angular half: columns and weight of phi (inside test on phi).
+__device__ __forceinline__ bool fan_angular(const SonarDev &f, double phi, Stencil &st) {
+    if (!(phi >= -f.half_az && phi <= f.half_az)) return false;
+    double fp = (phi + f.half_az) * f.scale_phi - 0.5;
+    const double np1 = (double)(f.n_az - 1);
+    fp = fp < 0.0 ? 0.0 : (fp > np1 ? np1 : fp);
     if (f.n_az == 1) {
         st.j0 = st.j1 = 0;
         st.s = 0.0;
@@ -303,6 +310,11 @@ __device__ __forceinline__ bool fan_stencil(const SonarDev &f, double rho, doubl
     return true;
 }
 
+__device__ __forceinline__ bool fan_stencil(const SonarDev &f, double rho, double phi,
+                                            Stencil &st) {
+    return fan_radial(f, rho, st) && fan_angular(f, phi, st);
+}
+
 // --------------------------------------------------------------------------
 // Wave / workgroup reductions in a fixed order (bit-reproducible).
 // --------------------------------------------------------------------------
@@ -312,8 +324,9 @@ __device__ __forceinline__ double wave_sum(double v) {
     return v;   // lane 0 holds the sum
 }
 
-// Sums `v` over the workgroup; thread 0 receives the result.  `sh` needs
-// kBlock / kWave doubles.  Contains barriers: call from every thread.
+// Sums `v` over a workgroup of NT threads; thread 0 receives the result.
+// `sh` needs NT / kWave doubles.  Contains barriers: call from every thread.
+template <int NT = kBlock>
 __device__ __forceinline__ double block_sum(double v, double *sh) {
     v = wave_sum(v);
     int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
@@ -322,8 +335,36 @@ __device__ __forceinline__ double block_sum(double v, double *sh) {
     __syncthreads();
     double s = 0.0;
     if (threadIdx.x == 0)
-        for (int k = 0; k < kBlock / kWave; ++k) s += sh[k];
+        for (int k = 0; k < NT / kWave; ++k) s += sh[k];
     return s;
+}
+
+// Exclusive scan of a[0..n) in LDS by a workgroup of NT threads; a[n]
+// receives the total.  `tmp` holds NT ints.  Every thread must call it.
+template <int NT = kBlock>
+__device__ void block_exclusive_scan(int *a, int n, int *tmp) {
+    const int tid = threadIdx.x;
+    const int per = (n + NT - 1) / NT;
+    const int lo = tid * per;
+    const int hi = min(lo + per, n);
+    int s = 0;
+    for (int k = lo; k < hi; ++k) s += a[k];
+    tmp[tid] = s;
+    __syncthreads();
+    for (int off = 1; off < NT; off <<= 1) {
+        int v = tid >= off ? tmp[tid - off] : 0;
+        __syncthreads();
+        tmp[tid] += v;
+        __syncthreads();
+    }
+    int run = tmp[tid] - s;
+    for (int k = lo; k < hi; ++k) {
+        int c = a[k];
+        a[k] = run;
+        run += c;
+    }
+    if (tid == NT - 1) a[n] = tmp[NT - 1];
+    __syncthreads();
 }
 
 }  // namespace osim

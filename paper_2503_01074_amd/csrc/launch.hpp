@@ -11,13 +11,15 @@ namespace osim {
 // Launch geometry of one sonar call (all frames).
 struct SonarGrid {
     int bin_blocks;      // binning workgroups over all frames
-    int tile_blocks;     // polar-tile workgroups over all frames
+    int tile_blocks;     // forward polar-tile workgroups over all frames
+    int tile_b_blocks;   // backward polar-tile workgroups over all frames
     int fan_blocks;      // fan workgroups over all frames
     int ret_blocks;      // backward return-gather workgroups over all frames
     int chunk;           // returns per binning workgroup (256 * R)
     int ret_chunk;       // returns per return-gather workgroup (256 * R)
-    int max_tiles;       // largest tile count of a frame
-    int max_tile_bins;   // largest tile of a frame, in bins
+    int max_tiles;       // largest forward tile count of a frame
+    int max_tile_bins;   // largest forward tile of a frame, in bins
+    int max_tile_bins_b; // largest backward tile of a frame, in bins
 };
 
 hipError_t sonar_forward_one(const SonarDev &f, const SonarGrid &g, const oceansim_sonar_params *params,
@@ -25,13 +27,16 @@ hipError_t sonar_forward_one(const SonarDev &f, const SonarGrid &g, const oceans
 hipError_t sonar_forward_table(const SonarDev *t, int n, const SonarGrid &g,
                                const oceansim_sonar_params *params, const float *refl, int n_mat,
                                hipStream_t st);
+// Backward: partial sums into part (5 doubles per tile and return workgroup)
+// and refl_part (n_mat doubles per return workgroup, small tables), reduced
+// in a fixed order into grad_params [n_rows][8] and grad_refl [n_mat].
 hipError_t sonar_backward_one(const SonarDev &f, const SonarGrid &g, const oceansim_sonar_params *params,
-                              const float *refl, int n_mat, double *part, int *part_row,
-                              double *refl_part, float *grad_refl, hipStream_t st);
+                              int n_rows, const float *refl, int n_mat, double *part, double *refl_part,
+                              float *grad_params, float *grad_refl, hipStream_t st);
 hipError_t sonar_backward_table(const SonarDev *t, int n, const SonarGrid &g,
-                                const oceansim_sonar_params *params, const float *refl, int n_mat,
-                                double *part, int *part_row, double *refl_part, float *grad_refl,
-                                hipStream_t st);
+                                const oceansim_sonar_params *params, int n_rows, const float *refl,
+                                int n_mat, double *part, double *refl_part, float *grad_params,
+                                float *grad_refl, hipStream_t st);
 
 constexpr int kUwPixelsPerBlock = kBlock * 16;
 

@@ -28,36 +28,6 @@
 namespace osim {
 
 // ---------------------------------------------------------------------------
-// Exclusive scan of a[0..n) in LDS by one workgroup; a[n] receives the total.
-// `tmp` holds kBlock ints.  Every thread must call it.
-// ---------------------------------------------------------------------------
-__device__ void block_exclusive_scan(int *a, int n, int *tmp) {
-    const int tid = threadIdx.x;
-    const int per = (n + kBlock - 1) / kBlock;
-    const int lo = tid * per;
-    const int hi = min(lo + per, n);
-    int s = 0;
-    for (int k = lo; k < hi; ++k) s += a[k];
-    tmp[tid] = s;
-    __syncthreads();
-    // Hillis-Steele inclusive scan of the kBlock partial sums
-    for (int off = 1; off < kBlock; off <<= 1) {
-        int v = tid >= off ? tmp[tid - off] : 0;
-        __syncthreads();
-        tmp[tid] += v;
-        __syncthreads();
-    }
-    int run = tmp[tid] - s;   // exclusive prefix of this thread's segment
-    for (int k = lo; k < hi; ++k) {
-        int c = a[k];
-        a[k] = run;
-        run += c;
-    }
-    if (tid == kBlock - 1) a[n] = tmp[kBlock - 1];
-    __syncthreads();
-}
-
-// ---------------------------------------------------------------------------
 // k_bin
 // ---------------------------------------------------------------------------
 template <class Src, int R>
@@ -122,23 +92,49 @@ __global__ __launch_bounds__(kBlock) void k_bin(Src src, const oceansim_sonar_pa
 // ---------------------------------------------------------------------------
 // k_tile
 // ---------------------------------------------------------------------------
+// Additive term of Eq. (3)-(4) for the four bins b0..b0+3 (b0 % 4 == 0), which
+// share one Philox call; rows/columns advance with the linear index.
+struct AddCtx {
+    float sigma_sa, inv_sigma_phi;
+};
+
+__device__ __forceinline__ float additive_term(const SonarDev &f, const AddCtx &c, int i, int j, uint32_t word,
+                                               float &E_out, float &rho_out, float &R_out, float &phi_out) {
+    const float R = range_ramp(f, i);
+    const float phi = bin_azimuth(f, j);
+    const float E = expf(-(phi * phi) * c.inv_sigma_phi);
+    const float rho = rayleigh_of_word(word);
+    E_out = E;
+    rho_out = rho;
+    R_out = R;
+    phi_out = phi;
+    return R * (1.0f + 0.5f * E * (c.sigma_sa * rho));
+}
+
 template <class Src>
 __global__ __launch_bounds__(kBlock) void k_tile(Src src, const oceansim_sonar_params *params) {
     extern __shared__ int4 lds_raw[];
-    float *acc = reinterpret_cast<float *>(lds_raw);
+    __shared__ unsigned listed[kMaxTileBins / 32];
+    __shared__ int n_listed;
     int tile;
     const int fi = src.locate(blockIdx.x, KTILE, tile);
     const SonarDev &f = src.frame(fi);
     const int tid = threadIdx.x;
-    const long long nb = (long long)f.n_range * f.n_az;
-    const long long b_lo = (long long)tile * f.tile_bins;
-    const long long b_hi = min(b_lo + (long long)f.tile_bins, nb);
-    const int nbins = (int)(b_hi - b_lo);
+    const int nb = f.n_range * f.n_az;
+    const int b_lo = tile * f.tile_bins;
+    const int b_hi = min(b_lo + f.tile_bins, nb);
+    const int nbins = b_hi - b_lo;
+    float *acc = reinterpret_cast<float *>(lds_raw);           // [tile_bins]
+    int *list = reinterpret_cast<int *>(acc + f.tile_bins);    // [tile_bins]
+    const bool speckle = f.speckle != SPECKLE_OFF;
 
     for (int k = tid; k < nbins; k += kBlock) acc[k] = 0.0f;
+    for (int k = tid; k < (nbins + 31) / 32; k += kBlock) listed[k] = 0u;
+    if (tid == 0) n_listed = 0;
     __syncthreads();
 
-    // binning by summation: every chunk's segment for this tile
+    // binning by summation: every chunk's segment for this tile; bins that
+    // receive a nonzero intensity are listed once for the multiplicative draw
     const int stride = f.n_tiles + 1;
     for (int c = tid; c < f.n_chunks; c += kBlock) {
         const int *off = f.chunk_off + (long long)c * stride + tile;
@@ -146,42 +142,52 @@ __global__ __launch_bounds__(kBlock) void k_tile(Src src, const oceansim_sonar_p
         const uint2 *p = f.pairs + (long long)c * f.chunk;
         for (int k = s; k < e; ++k) {
             const uint2 q = p[k];
-            if (q.x < (uint32_t)nbins) atomicAdd(&acc[q.x], __uint_as_float(q.y));
+            if (q.x >= (uint32_t)nbins) continue;
+            const float I = __uint_as_float(q.y);
+            atomicAdd(&acc[q.x], I);
+            if (speckle && I != 0.0f) {
+                const unsigned bit = 1u << (q.x & 31);
+                if (!(atomicOr(&listed[q.x >> 5], bit) & bit)) list[atomicAdd(&n_listed, 1)] = (int)q.x;
+            }
         }
     }
     __syncthreads();
 
     const oceansim_sonar_params pr = params[f.param_row];
     const float G = pr.gain;
+    if (speckle) {
+        // Q m for the listed (nonempty) bins only: the other bins have Q = 0
+        const int nl = n_listed;
+        for (int e = tid; e < nl; e += kBlock) {
+            const int x = list[e];
+            float gz;
+            const float m = speckle_factor(f, (uint32_t)(b_lo + x), pr.sigma_sm, &gz);
+            acc[x] = (G * acc[x]) * m;
+        }
+        __syncthreads();
+    }
+
+    AddCtx ctx{pr.sigma_sa, 1.0f / pr.sigma_phi};
     // groups of four consecutive frame-linear bins share one additive Philox call
-    const long long q_first = b_lo >> 2, q_last = (b_hi - 1) >> 2;
-    for (long long q = q_first + tid; q <= q_last; q += kBlock) {
-        const long long b0 = q << 2;
-        float P[4], out[4];
+    const int q_first = b_lo >> 2, q_last = (b_hi - 1) >> 2;
+    for (int q = q_first + tid; q <= q_last; q += kBlock) {
+        const int b0 = q << 2;
+        float out[4];
         bool in[4];
 #pragma unroll
-        for (int w = 0; w < 4; ++w) {
-            const long long b = b0 + w;
-            in[w] = b >= b_lo && b < b_hi;
-            P[w] = in[w] ? acc[b - b_lo] : 0.0f;
-        }
-        if (f.speckle == SPECKLE_OFF) {
+        for (int w = 0; w < 4; ++w) in[w] = b0 + w >= b_lo && b0 + w < b_hi;
+        if (!speckle) {
 #pragma unroll
-            for (int w = 0; w < 4; ++w) out[w] = G * P[w];
+            for (int w = 0; w < 4; ++w) out[w] = in[w] ? G * acc[b0 + w - b_lo] : 0.0f;
         } else {
             const Words wd = philox((uint32_t)q, f.frame_id, 0u, 0u, f.seed_lo, f.seed_hi);
-            int i = (int)(b0 / f.n_az);
-            int j = (int)(b0 - (long long)i * f.n_az);
+            int i = b0 / f.n_az;
+            int j = b0 - i * f.n_az;
 #pragma unroll
             for (int w = 0; w < 4; ++w) {
-                const float R = range_ramp(f, i);
-                const float phi = bin_azimuth(f, j);
-                const float E = expf(-(phi * phi) / pr.sigma_phi);
-                const float rho = rayleigh_of_word(pick(wd, (uint32_t)w));
-                const float add = R * (1.0f + 0.5f * E * (pr.sigma_sa * rho));
-                float m = 0.0f, gz;
-                if (P[w] != 0.0f) m = speckle_factor(f, (uint32_t)(b0 + w), pr.sigma_sm, &gz);
-                out[w] = (G * P[w]) * m + add;
+                float E, rho, R, phi;
+                const float add = additive_term(f, ctx, i, j, pick(wd, (uint32_t)w), E, rho, R, phi);
+                out[w] = (in[w] ? acc[b0 + w - b_lo] : 0.0f) + add;
                 if (++j == f.n_az) { j = 0; ++i; }
             }
         }
@@ -238,6 +244,7 @@ __global__ __launch_bounds__(kBlock) void k_fan(Src src) {
 // ---------------------------------------------------------------------------
 // k_tile_bwd
 // ---------------------------------------------------------------------------
+constexpr int kBwdThreads = 512;
 constexpr int kRowBatch = 1024;
 
 // Left-half pixel interval [ua, ub] of fan row v whose centres may lie within
@@ -259,8 +266,8 @@ __device__ __forceinline__ void row_interval(const SonarDev &f, int v, double rl
     if (xi > xo) return;
     // left half: x in [-xo, -xi]  ->  u = x / s + W/2 - 1/2
     const double c = 0.5 * (double)f.fan_w - 0.5;
-    double a = -xo / s + c, b = -xi / s + c;
-    int half_w = (f.fan_w + 1) >> 1;
+    const double a = -xo / s + c, b = -xi / s + c;
+    const int half_w = (f.fan_w + 1) >> 1;
     int lo = (int)__builtin_floor(a) - 1, hi = (int)__builtin_ceil(b) + 1;
     lo = lo < 0 ? 0 : lo;
     hi = hi > half_w - 1 ? half_w - 1 : hi;
@@ -268,125 +275,192 @@ __device__ __forceinline__ void row_interval(const SonarDev &f, int v, double rl
     ub = hi;
 }
 
+// Candidate pixels of a tile, one batch of fan rows at a time: per-row
+// intervals and their exclusive prefix in LDS.  Returns the batch total.
+template <int NT>
+__device__ __forceinline__ int load_row_batch(const SonarDev &f, int vb, int nrows, double rlo, double rhi,
+                                              int *row_u0, int *row_pre, int *scan_tmp) {
+    __syncthreads();
+    for (int rr = threadIdx.x; rr < nrows; rr += NT) {
+        int ua, ub;
+        row_interval(f, vb + rr, rlo, rhi, ua, ub);
+        row_u0[rr] = ua;
+        row_pre[rr] = ub >= ua ? ub - ua + 1 : 0;
+    }
+    __syncthreads();
+    block_exclusive_scan<NT>(row_pre, nrows, scan_tmp);
+    return row_pre[nrows];
+}
+
+constexpr int kCandBatch = 8192;     // candidates per sub-batch (uint16 row index each)
+
+// Round x (|x| < 2^51) to the nearest integer, as an int64, by adding
+// 1.5 * 2^52: the sum's mantissa then holds the integer offset by 2^51.
+__device__ __forceinline__ long long round_to_ll(double x) {
+    const double t = x + 6755399441055744.0;
+    return (long long)__double_as_longlong(t) - 0x4338000000000000LL;
+}
+
 template <class Src>
-__global__ __launch_bounds__(kBlock) void k_tile_bwd(Src src, const oceansim_sonar_params *params,
-                                                     double *part, int *part_row,
-                                                     float *grad_refl_zero, int n_mat_zero) {
+__global__ __launch_bounds__(kBwdThreads, 4) void k_tile_bwd(Src src, const oceansim_sonar_params *params,
+                                                          double *part, float *grad_refl_zero,
+                                                          int n_mat_zero) {
+    constexpr int NT = kBwdThreads;
     extern __shared__ int4 lds_raw[];
     long long *acc = reinterpret_cast<long long *>(lds_raw);
     __shared__ int row_u0[kRowBatch];
     __shared__ int row_pre[kRowBatch + 1];
+    __shared__ unsigned short cand_row[kCandBatch];
+    __shared__ int scan_tmp[NT];
     __shared__ unsigned poison[kMaxTileBins / 32];
-    __shared__ double red[kBlock / kWave];
-    __shared__ int scan_tmp[kBlock];
-    __shared__ double sh_scale;
+    __shared__ double red[NT / kWave];
+    __shared__ int sh_exp;        // fixed-point exponent: values are stored times 2^(50 - sh_exp)
+    __shared__ int sh_shift;
 
-    int tile;
-    const int fi = src.locate(blockIdx.x, KTILE, tile);
+    int local;
+    const int fi = src.locate(blockIdx.x, KTILEB, local);
     const SonarDev &f = src.frame(fi);
+    const int tile = f.n_tiles_b - 1 - local;   // outer tiles (most pixels) first
     const int tid = threadIdx.x;
+    const int lane = tid & (kWave - 1), wave = tid / kWave;
 
     // the atomic reflectivity path (many materials) accumulates into a zeroed table
     if (grad_refl_zero)
-        for (int k = blockIdx.x * kBlock + tid; k < n_mat_zero; k += gridDim.x * kBlock)
-            grad_refl_zero[k] = 0.0f;
+        for (int k = blockIdx.x * NT + tid; k < n_mat_zero; k += gridDim.x * NT) grad_refl_zero[k] = 0.0f;
 
-    const long long nb = (long long)f.n_range * f.n_az;
-    const long long b_lo = (long long)tile * f.tile_bins;
-    const long long b_hi = min(b_lo + (long long)f.tile_bins, nb);
-    const int nbins = (int)(b_hi - b_lo);
-    const int ia = tile * f.rows_per_tile;
-    const int ib = min(ia + f.rows_per_tile, f.n_range);
+    const int nb = f.n_range * f.n_az;
+    const int b_lo = tile * f.tile_bins_b;
+    const int b_hi = min(b_lo + f.tile_bins_b, nb);
+    const int nbins = b_hi - b_lo;
+    const int ia = tile * f.rows_per_tile_b;
+    const int ib = min(ia + f.rows_per_tile_b, f.n_range);
 
-    for (int k = tid; k < nbins; k += kBlock) acc[k] = 0;
-    for (int k = tid; k < (nbins + 31) / 32; k += kBlock) poison[k] = 0u;
-    if (tid == 0) sh_scale = 0.0;
+    for (int k = tid; k < nbins; k += NT) acc[k] = 0;
+    for (int k = tid; k < (nbins + 31) / 32; k += NT) poison[k] = 0u;
+    if (tid == 0) sh_exp = -100000;
     __syncthreads();
 
     const bool have_fan = f.grad_fan != nullptr && f.fan_h > 0 && f.fan_w > 0;
     if (have_fan) {
         const double s = f.fan_s;
+        // pixels whose stencil may touch rows [ia, ib) lie at radial distance
+        // [r_min + (ia - 1/2) dr, r_min + (ib + 1/2) dr]; one pixel of margin
         double rlo = f.r_min + ((double)ia - 0.5) * f.dr - s;
         double rhi = f.r_min + ((double)ib + 0.5) * f.dr + s;
         rlo = rlo < 0.0 ? 0.0 : rlo;
-        const double rmax_s = f.r_max + s;
-        rhi = rhi > rmax_s ? rmax_s : rhi;
-        const double ymin = rlo * cos(f.half_az < 1.5707963267948966 ? f.half_az : 1.5707963267948966) - s;
-        const double ymax = rhi + s;
+        rhi = rhi > f.r_max + s ? f.r_max + s : rhi;
+        const double rlo2 = rlo * rlo, rhi2 = rhi * rhi;
+        const double cmin = cos(f.half_az < 1.5707963267948966 ? f.half_az : 1.5707963267948966);
+        const double ymin = rlo * cmin - s, ymax = rhi + s;
         const double H = (double)f.fan_h;
         int v_lo = (int)__builtin_floor(H - 0.5 - ymax / s);
         int v_hi = (int)__builtin_ceil(H - 0.5 - (ymin > 0.0 ? ymin : 0.0) / s);
         v_lo = v_lo < 0 ? 0 : v_lo;
         v_hi = v_hi > f.fan_h - 1 ? f.fan_h - 1 : v_hi;
         const int W = f.fan_w;
+        // Pixels that can add to one bin lie in its 2 x 2-cell neighbourhood:
+        // radial extent <= 2 dr, angular <= 2 dphi at radius <= rhi.  Their
+        // count bounds |bin sum| / max|g|; with a safety factor of 2 it keeps
+        // every scaled sum below 2^50.
+        const double wr = 2.0 * f.dr, wa = 2.0 * f.dphi * rhi;
+        const double pix_bound = 2.0 * ((wr * wa + 1.5 * s * 2.0 * (wr + wa)) / (s * s) + 8.0) + 16.0;
 
-        // two passes over the candidate pixels: the largest |gradient| fixes
-        // the fixed-point scale, then the stencil contributions are added
-        for (int pass = 0; pass < 2; ++pass) {
-            double local_max = 0.0, local_cnt = 0.0;
-            for (int vb = v_lo; vb <= v_hi; vb += kRowBatch) {
-                const int nrows = min(kRowBatch, v_hi - vb + 1);
-                __syncthreads();
-                for (int rr = tid; rr < nrows; rr += kBlock) {
-                    int ua, ub;
-                    row_interval(f, vb + rr, rlo, rhi, ua, ub);
-                    row_u0[rr] = ua;
-                    row_pre[rr] = ub >= ua ? ub - ua + 1 : 0;
+        for (int vb = v_lo; vb <= v_hi; vb += kRowBatch) {
+            const int nrows = min(kRowBatch, v_hi - vb + 1);
+            const int total = load_row_batch<NT>(f, vb, nrows, rlo, rhi, row_u0, row_pre, scan_tmp);
+            for (int cb = 0; cb < total; cb += kCandBatch) {
+                const int ncand = min(kCandBatch, total - cb);
+                // candidate -> row table for [cb, cb + ncand)
+                for (int r = tid; r < nrows; r += NT) {
+                    const int lo = max(row_pre[r], cb), hi = min(row_pre[r + 1], cb + ncand);
+                    for (int k = lo; k < hi; ++k) cand_row[k - cb] = (unsigned short)r;
                 }
                 __syncthreads();
-                block_exclusive_scan(row_pre, nrows, scan_tmp);
-                const int total = row_pre[nrows];
-                for (int idx = tid; idx < total; idx += kBlock) {
-                    int lo = 0, hi = nrows - 1;
-                    while (lo < hi) {
-                        const int mid = (lo + hi + 1) >> 1;
-                        if (row_pre[mid] <= idx) lo = mid; else hi = mid - 1;
+                // largest finite |gradient| of this sub-batch
+                double mx = 0.0;
+                for (int k = tid; k < ncand; k += NT) {
+                    const int r = cand_row[k];
+                    const int v = vb + r;
+                    const int u = row_u0[r] + (cb + k - row_pre[r]);
+                    const float *grow = f.grad_fan + (long long)v * W;
+                    const double a0 = __builtin_fabs((double)grow[u]);
+                    const double a1 = __builtin_fabs((double)grow[W - 1 - u]);
+                    if (a0 <= 1.7976931348623157e308 && a0 > mx) mx = a0;
+                    if (a1 <= 1.7976931348623157e308 && a1 > mx) mx = a1;
+                }
+                for (int off = 32; off > 0; off >>= 1) {
+                    const double o = __shfl_down(mx, off, kWave);
+                    mx = o > mx ? o : mx;
+                }
+                if (lane == 0) red[wave] = mx;
+                __syncthreads();
+                if (tid == 0) {
+                    double m = 0.0;
+                    for (int k = 0; k < NT / kWave; ++k) m = red[k] > m ? red[k] : m;
+                    int e = sh_exp;
+                    int shift = 0;
+                    if (m > 0.0) {
+                        int en;
+                        frexp(m * pix_bound, &en);   // m * bound < 2^en
+                        if (en > e) {
+                            shift = e == -100000 ? 0 : en - e;
+                            e = en;
+                        }
                     }
-                    const int v = vb + lo;
-                    const int u = row_u0[lo] + (idx - row_pre[lo]);
+                    sh_shift = shift > 63 ? 63 : shift;   // 63: all accumulated so far rounds away
+                    sh_exp = e;
+                }
+                __syncthreads();
+                if (sh_shift > 0) {
+                    // rescale what is accumulated to the larger exponent (an
+                    // arithmetic shift: deterministic)
+                    const int sh = sh_shift;
+                    for (int k = tid; k < nbins; k += NT) acc[k] = sh >= 63 ? 0 : (acc[k] >> sh);
+                    __syncthreads();
+                }
+                // no nonzero finite value yet: only non-finite ones (poison) can act
+                const double scale = sh_exp == -100000 ? 0.0 : ldexp(1.0, 50 - sh_exp);
+                for (int k = tid; k < ncand; k += NT) {
+                    const int r = cand_row[k];
+                    const int v = vb + r;
+                    const int u = row_u0[r] + (cb + k - row_pre[r]);
                     const int um = W - 1 - u;
                     const float *grow = f.grad_fan + (long long)v * W;
                     const float g0 = grow[u];
                     const float g1 = um != u ? grow[um] : 0.0f;
-                    if (pass == 0) {
-                        const double a0 = __builtin_fabs((double)g0), a1 = __builtin_fabs((double)g1);
-                        // a non-finite gradient poisons only its own stencil
-                        // (handled in pass 1), so leave it out of the scale
-                        if (a0 == a0 && a0 <= 1.7976931348623157e308 && a0 > local_max) local_max = a0;
-                        if (a1 == a1 && a1 <= 1.7976931348623157e308 && a1 > local_max) local_max = a1;
-                        local_cnt += 2.0;
-                        continue;
-                    }
-                    const double scale = sh_scale;
-                    double rho, phi;
-                    fan_left(f, v, u, rho, phi);
+                    if (g0 == 0.0f && g1 == 0.0f) continue;
+                    const double ax = (0.5 * (double)W - (double)u - 0.5) * s;
+                    const double yc = (H - (double)v - 0.5) * s;
+                    const double rho2 = ax * ax + yc * yc;
+                    if (rho2 < rlo2 || rho2 > rhi2) continue;
+                    Stencil st;
+                    if (!fan_radial(f, __builtin_sqrt(rho2), st)) continue;
+                    if (st.i1 < ia || st.i0 >= ib) continue;
+                    const double phi = atan2(ax, yc);
                     for (int side = 0; side < 2; ++side) {
                         if (side == 1 && um == u) break;
                         const float g = side == 0 ? g0 : g1;
                         if (g == 0.0f) continue;
-                        Stencil st;
-                        if (!fan_stencil(f, rho, side == 0 ? phi : -phi, st)) continue;
-                        if (st.i1 < ia || st.i0 >= ib) continue;
+                        if (!fan_angular(f, side == 0 ? phi : -phi, st)) continue;
                         const bool finite = __builtin_isfinite(g);
-                        const double gd = (double)g;
-                        const int ii[2] = {st.i0, st.i1};
-                        const int jj[2] = {st.j0, st.j1};
-                        const double wr[2] = {1.0 - st.t, st.t};
-                        const double wc[2] = {1.0 - st.s, st.s};
+                        const double gd = (double)g * scale;
+                        const double wr0 = (1.0 - st.t) * gd, wr1 = st.t * gd;
+                        const double wc0 = 1.0 - st.s, wc1 = st.s;
+                        const bool two_rows = st.i1 != st.i0, two_cols = st.j1 != st.j0;
 #pragma unroll
                         for (int a = 0; a < 2; ++a) {
-                            if (ii[a] < ia || ii[a] >= ib) continue;
-                            if (a == 1 && ii[1] == ii[0]) continue;
+                            const int ii = a == 0 ? st.i0 : st.i1;
+                            if (ii < ia || ii >= ib || (a == 1 && !two_rows)) continue;
+                            const double wa_ = a == 0 ? wr0 : wr1;
 #pragma unroll
                             for (int c = 0; c < 2; ++c) {
-                                if (c == 1 && jj[1] == jj[0]) continue;
-                                const int lb = (ii[a] - ia) * f.n_az + jj[c];
-                                const double w = wr[a] * wc[c];
+                                if (c == 1 && !two_cols) continue;
+                                const int lb = (ii - ia) * f.n_az + (c == 0 ? st.j0 : st.j1);
                                 if (!finite) {
                                     atomicOr(&poison[lb >> 5], 1u << (lb & 31));
                                     continue;
                                 }
-                                const long long qv = __double2ll_rn(w * gd * scale);
+                                const long long qv = round_to_ll(wa_ * (c == 0 ? wc0 : wc1));
                                 if (qv != 0)
                                     atomicAdd(reinterpret_cast<unsigned long long *>(&acc[lb]),
                                               (unsigned long long)qv);
@@ -394,81 +468,54 @@ __global__ __launch_bounds__(kBlock) void k_tile_bwd(Src src, const oceansim_son
                         }
                     }
                 }
-            }
-            if (pass == 0) {
-                // workgroup max of |g| and of the candidate count
-                double mx = local_max;
-                for (int off = 32; off > 0; off >>= 1) {
-                    const double o = __shfl_down(mx, off, kWave);
-                    mx = o > mx ? o : mx;
-                }
-                const double cnt = block_sum(local_cnt, red);   // thread 0
-                __syncthreads();
-                if ((tid & (kWave - 1)) == 0) red[tid / kWave] = mx;
-                __syncthreads();
-                if (tid == 0) {
-                    double m = 0.0;
-                    for (int k = 0; k < kBlock / kWave; ++k) m = red[k] > m ? red[k] : m;
-                    // |sum| <= cnt * max < 2^62 after scaling
-                    double sc = 0.0;
-                    if (m > 0.0) {
-                        int e;
-                        frexp(m * (cnt > 1.0 ? cnt : 1.0), &e);
-                        sc = ldexp(1.0, 61 - e);
-                    }
-                    sh_scale = sc;
-                }
                 __syncthreads();
             }
         }
-        __syncthreads();
     }
 
     // epilogue: fixed point -> float, plus the polar gradient; adjoint of Eq. (3)-(4)
     const oceansim_sonar_params pr = params[f.param_row];
-    const double inv_scale = (have_fan && sh_scale > 0.0) ? 1.0 / sh_scale : 0.0;
+    const double inv_scale = (have_fan && sh_exp != -100000) ? ldexp(1.0, sh_exp - 50) : 0.0;
+    const AddCtx ctx{pr.sigma_sa, 1.0f / pr.sigma_phi};
+    const double dsphi = 0.5 * (double)pr.sigma_sa / ((double)pr.sigma_phi * (double)pr.sigma_phi);
     double g_sphi = 0.0, g_ssa = 0.0;
-    const long long q_first = b_lo >> 2, q_last = (b_hi - 1) >> 2;
-    for (long long q = q_first + tid; q <= q_last; q += kBlock) {
-        const long long b0 = q << 2;
+    const int q_first = b_lo >> 2, q_last = (b_hi - 1) >> 2;
+    for (int q = q_first + tid; q <= q_last; q += NT) {
+        const int b0 = q << 2;
         Words wd{0u, 0u, 0u, 0u};
         if (f.speckle != SPECKLE_OFF) wd = philox((uint32_t)q, f.frame_id, 0u, 0u, f.seed_lo, f.seed_hi);
-        int i = (int)(b0 / f.n_az);
-        int j = (int)(b0 - (long long)i * f.n_az);
+        int i = b0 / f.n_az;
+        int j = b0 - i * f.n_az;
 #pragma unroll
         for (int w = 0; w < 4; ++w) {
-            const long long b = b0 + w;
+            const int b = b0 + w;
             if (b >= b_lo && b < b_hi) {
-                const int lb = (int)(b - b_lo);
+                const int lb = b - b_lo;
                 double g = (double)acc[lb] * inv_scale;
                 if (poison[lb >> 5] & (1u << (lb & 31))) g = __builtin_nan("");
                 if (f.grad_polar) g += (double)f.grad_polar[b];
                 f.grad_img[b] = (float)g;
                 if (f.speckle != SPECKLE_OFF) {
-                    const double R = (double)range_ramp(f, i);
-                    const double phi = (double)bin_azimuth(f, j);
-                    const double E = (double)expf(-((float)phi * (float)phi) / pr.sigma_phi);
-                    const double rho = (double)rayleigh_of_word(pick(wd, (uint32_t)w));
+                    float E, rho, R, phi;
+                    additive_term(f, ctx, i, j, pick(wd, (uint32_t)w), E, rho, R, phi);
                     // d add / d sigma_sa and d add / d sigma_phi of Eq. (3)-(4)
-                    g_ssa += g * R * 0.5 * E * rho;
-                    g_sphi += g * R * 0.5 * (double)pr.sigma_sa * rho * E * (phi * phi) /
-                              ((double)pr.sigma_phi * (double)pr.sigma_phi);
+                    const double t = g * (double)R * (double)E * (double)rho;
+                    g_ssa += 0.5 * t;
+                    g_sphi += t * dsphi * ((double)phi * (double)phi);
                 }
             }
             if (++j == f.n_az) { j = 0; ++i; }
         }
     }
-    const double s_phi = block_sum(g_sphi, red);
-    const double s_sa = block_sum(g_ssa, red);
+    const double s_phi = block_sum<NT>(g_sphi, red);
+    const double s_sa = block_sum<NT>(g_ssa, red);
     if (tid == 0) {
-        const int slot = blockIdx.x;
-        double *p = part + (long long)slot * 5;
+        double *p = part + (long long)blockIdx.x * 5;
         p[0] = 0.0;
         p[1] = 0.0;
         p[2] = s_phi;
         p[3] = s_sa;
         p[4] = 0.0;
-        part_row[slot] = f.param_row;
     }
 }
 
@@ -477,8 +524,7 @@ __global__ __launch_bounds__(kBlock) void k_tile_bwd(Src src, const oceansim_son
 // ---------------------------------------------------------------------------
 template <class Src, int R>
 __global__ __launch_bounds__(kBlock) void k_ret_bwd(Src src, const oceansim_sonar_params *params,
-                                                    const float *refl, int n_mat, double *part,
-                                                    int *part_row, int slot_base,
+                                                    const float *refl, int n_mat, double *part, int slot_base,
                                                     double *refl_part, float *grad_refl_atomic) {
     extern __shared__ int4 lds_raw[];
     // thread-private reflectivity columns [n_mat][kBlock] (small tables); the
@@ -499,7 +545,7 @@ __global__ __launch_bounds__(kBlock) void k_ret_bwd(Src src, const oceansim_sona
     const float G = pr.gain;
     double g_alpha = 0.0, g_gain = 0.0, g_ssm = 0.0;
     const long long base = (long long)local * (R * kBlock);
-#pragma unroll 4
+#pragma unroll
     for (int q = 0; q < R; ++q) {
         const long long k = base + (long long)q * kBlock + tid;
         if (k >= f.n) break;
@@ -518,7 +564,7 @@ __global__ __launch_bounds__(kBlock) void k_ret_bwd(Src src, const oceansim_sona
         const double gI = (double)G * (double)mult * gIt;   // dL / dI_k
         g_alpha += gI * (double)I * (-f.kappa * r);
         g_gain += gIt * (double)mult * (double)I;
-        g_ssm += gIt * (double)G * (double)I * (double)z;
+        if (f.speckle == SPECKLE_PAPER) g_ssm += gIt * (double)G * (double)I * (double)z;
         const float gr = (float)(gI * (double)cosg * (double)att);
         if (lane_hist)
             hist[m * kBlock + tid] += gr;
@@ -539,36 +585,76 @@ __global__ __launch_bounds__(kBlock) void k_ret_bwd(Src src, const oceansim_sona
     const double sa = block_sum(g_alpha, red);
     const double sg = block_sum(g_gain, red);
     const double sm = block_sum(g_ssm, red);
-    const int slot = slot_base + blockIdx.x;
     if (tid == 0) {
-        double *p = part + (long long)slot * 5;
+        double *p = part + (long long)(slot_base + blockIdx.x) * 5;
         p[0] = sa;
         p[1] = sg;
         p[2] = 0.0;
         p[3] = 0.0;
         p[4] = sm;
-        part_row[slot] = f.param_row;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// k_reduce_sonar: fixed-order sums of the partials.  Blocks [0, n_rows * 8)
+// produce grad_params[row][col] from the slots of the frames using that row;
+// the following n_mat blocks (small tables) produce grad_refl.
+// ---------------------------------------------------------------------------
+template <class Src>
+__global__ __launch_bounds__(kBlock) void k_reduce_sonar(Src src, int n_frames, const double *part,
+                                                         int tile_slots, int n_rows, float *grad_params,
+                                                         const double *refl_part, int ret_slots, int n_mat,
+                                                         float *grad_refl) {
+    __shared__ double red[kBlock / kWave];
+    const int b = blockIdx.x;
+    double s = 0.0;
+    if (b < n_rows * OCEANSIM_SONAR_GRAD_WIDTH) {
+        const int r = b / OCEANSIM_SONAR_GRAD_WIDTH, c = b % OCEANSIM_SONAR_GRAD_WIDTH;
+        if (c < 5) {
+            for (int fi = 0; fi < n_frames; ++fi) {
+                const SonarDev &f = src.frame(fi);
+                if (f.param_row != r) continue;
+                for (int k = threadIdx.x; k < f.n_tiles_b; k += kBlock)
+                    s += part[(long long)(f.blk[KTILEB] + k) * 5 + c];
+                for (int k = threadIdx.x; k < f.n_ret_chunks; k += kBlock)
+                    s += part[(long long)(tile_slots + f.blk[KRET] + k) * 5 + c];
+            }
+        }
+        const double tot = block_sum(s, red);
+        if (threadIdx.x == 0) grad_params[b] = (float)tot;
+    } else {
+        const int m = b - n_rows * OCEANSIM_SONAR_GRAD_WIDTH;
+        if (refl_part)
+            for (int k = threadIdx.x; k < ret_slots; k += kBlock) s += refl_part[(long long)k * n_mat + m];
+        const double tot = block_sum(s, red);
+        if (threadIdx.x == 0) grad_refl[m] = (float)tot;
     }
 }
 
 // ---------------------------------------------------------------------------
 // Launchers
 // ---------------------------------------------------------------------------
+#define OSIM_DISPATCH_R(R_, ...)                       \
+    switch (R_) {                                      \
+        case 2: { constexpr int RR = 2; __VA_ARGS__; } break;   \
+        case 4: { constexpr int RR = 4; __VA_ARGS__; } break;   \
+        case 8: { constexpr int RR = 8; __VA_ARGS__; } break;   \
+        case 16: { constexpr int RR = 16; __VA_ARGS__; } break; \
+        default: return hipErrorInvalidValue;          \
+    }
+
 template <class Src>
 static hipError_t launch_fwd(const Src &src, const SonarGrid &g, const oceansim_sonar_params *params,
                              const float *refl, int n_mat, hipStream_t st) {
     if (g.bin_blocks > 0) {
         const size_t lds = (size_t)((g.max_tiles + 1 + 3) & ~3) * 4 + (size_t)g.chunk * 8;
-        switch (g.chunk / kBlock) {
-            case 4: hipLaunchKernelGGL((k_bin<Src, 4>), dim3(g.bin_blocks), dim3(kBlock), lds, st, src, params, refl, n_mat); break;
-            case 8: hipLaunchKernelGGL((k_bin<Src, 8>), dim3(g.bin_blocks), dim3(kBlock), lds, st, src, params, refl, n_mat); break;
-            case 16: hipLaunchKernelGGL((k_bin<Src, 16>), dim3(g.bin_blocks), dim3(kBlock), lds, st, src, params, refl, n_mat); break;
-            default: return hipErrorInvalidValue;
-        }
+        OSIM_DISPATCH_R(g.chunk / kBlock,
+                        hipLaunchKernelGGL((k_bin<Src, RR>), dim3(g.bin_blocks), dim3(kBlock), lds, st, src,
+                                           params, refl, n_mat));
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
-    hipLaunchKernelGGL((k_tile<Src>), dim3(g.tile_blocks), dim3(kBlock), (size_t)g.max_tile_bins * 4, st,
+    hipLaunchKernelGGL((k_tile<Src>), dim3(g.tile_blocks), dim3(kBlock), (size_t)g.max_tile_bins * 8, st,
                        src, params);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
@@ -580,28 +666,38 @@ static hipError_t launch_fwd(const Src &src, const SonarGrid &g, const oceansim_
 }
 
 template <class Src>
-static hipError_t launch_bwd(const Src &src, const SonarGrid &g, const oceansim_sonar_params *params,
-                             const float *refl, int n_mat, double *part, int *part_row,
-                             double *refl_part, float *grad_refl, hipStream_t st) {
+static hipError_t launch_bwd(const Src &src, int n_frames, const SonarGrid &g,
+                             const oceansim_sonar_params *params, int n_rows, const float *refl, int n_mat,
+                             double *part, double *refl_part, float *grad_params, float *grad_refl,
+                             hipStream_t st) {
     const bool lane_hist = n_mat <= kLaneHistMats;
-    hipLaunchKernelGGL((k_tile_bwd<Src>), dim3(g.tile_blocks), dim3(kBlock), (size_t)g.max_tile_bins * 8, st,
-                       src, params, part, part_row, lane_hist ? (float *)nullptr : grad_refl, n_mat);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
+    hipError_t e = hipSuccess;
+    if (g.tile_b_blocks > 0) {
+        hipLaunchKernelGGL((k_tile_bwd<Src>), dim3(g.tile_b_blocks), dim3(kBwdThreads),
+                           (size_t)g.max_tile_bins_b * 8, st, src, params, part,
+                           lane_hist ? (float *)nullptr : grad_refl, n_mat);
+        e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
     if (g.ret_blocks > 0) {
         size_t lds = lane_hist ? (size_t)n_mat * kBlock * 4 : 0;
         if (lds < (size_t)(kBlock / kWave) * 8) lds = (size_t)(kBlock / kWave) * 8;
         double *rp = lane_hist ? refl_part : nullptr;
         float *ga = lane_hist ? nullptr : grad_refl;
-        switch (g.ret_chunk / kBlock) {
-            case 4: hipLaunchKernelGGL((k_ret_bwd<Src, 4>), dim3(g.ret_blocks), dim3(kBlock), lds, st, src, params, refl, n_mat, part, part_row, g.tile_blocks, rp, ga); break;
-            case 8: hipLaunchKernelGGL((k_ret_bwd<Src, 8>), dim3(g.ret_blocks), dim3(kBlock), lds, st, src, params, refl, n_mat, part, part_row, g.tile_blocks, rp, ga); break;
-            case 16: hipLaunchKernelGGL((k_ret_bwd<Src, 16>), dim3(g.ret_blocks), dim3(kBlock), lds, st, src, params, refl, n_mat, part, part_row, g.tile_blocks, rp, ga); break;
-            default: return hipErrorInvalidValue;
-        }
+        OSIM_DISPATCH_R(g.ret_chunk / kBlock,
+                        hipLaunchKernelGGL((k_ret_bwd<Src, RR>), dim3(g.ret_blocks), dim3(kBlock), lds, st, src,
+                                           params, refl, n_mat, part, g.tile_b_blocks, rp, ga));
         e = hipGetLastError();
+        if (e != hipSuccess) return e;
     }
-    return e;
+    // small tables are reduced here; the atomic path was zeroed by k_tile_bwd,
+    // unless there was no tile at all (then the reduction writes zeros)
+    const bool refl_blocks = lane_hist || g.tile_b_blocks == 0;
+    const int blocks = n_rows * OCEANSIM_SONAR_GRAD_WIDTH + (refl_blocks ? n_mat : 0);
+    hipLaunchKernelGGL((k_reduce_sonar<Src>), dim3(blocks), dim3(kBlock), 0, st, src, n_frames, part,
+                       g.tile_b_blocks, n_rows, grad_params, lane_hist ? refl_part : nullptr, g.ret_blocks,
+                       n_mat, grad_refl);
+    return hipGetLastError();
 }
 
 hipError_t sonar_forward_one(const SonarDev &f, const SonarGrid &g, const oceansim_sonar_params *params,
@@ -614,15 +710,17 @@ hipError_t sonar_forward_table(const SonarDev *t, int n, const SonarGrid &g,
     return launch_fwd(Table<SonarDev>{t, n}, g, params, refl, n_mat, st);
 }
 hipError_t sonar_backward_one(const SonarDev &f, const SonarGrid &g, const oceansim_sonar_params *params,
-                              const float *refl, int n_mat, double *part, int *part_row,
-                              double *refl_part, float *grad_refl, hipStream_t st) {
-    return launch_bwd(One<SonarDev>{f}, g, params, refl, n_mat, part, part_row, refl_part, grad_refl, st);
+                              int n_rows, const float *refl, int n_mat, double *part, double *refl_part,
+                              float *grad_params, float *grad_refl, hipStream_t st) {
+    return launch_bwd(One<SonarDev>{f}, 1, g, params, n_rows, refl, n_mat, part, refl_part, grad_params,
+                      grad_refl, st);
 }
 hipError_t sonar_backward_table(const SonarDev *t, int n, const SonarGrid &g,
-                                const oceansim_sonar_params *params, const float *refl, int n_mat,
-                                double *part, int *part_row, double *refl_part, float *grad_refl,
-                                hipStream_t st) {
-    return launch_bwd(Table<SonarDev>{t, n}, g, params, refl, n_mat, part, part_row, refl_part, grad_refl, st);
+                                const oceansim_sonar_params *params, int n_rows, const float *refl,
+                                int n_mat, double *part, double *refl_part, float *grad_params,
+                                float *grad_refl, hipStream_t st) {
+    return launch_bwd(Table<SonarDev>{t, n}, n, g, params, n_rows, refl, n_mat, part, refl_part, grad_params,
+                      grad_refl, st);
 }
 
 }  // namespace osim

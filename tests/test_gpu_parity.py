@@ -372,3 +372,65 @@ def test_uw_backward():
                           for c, g in zip(cams, gos))
         fd = (L(p1) - L(p2)) / (2 * h)
         assert abs(g_w.cpu().numpy()[0, k] - fd) <= GRAD_RTOL_FD * abs(fd), (k, fd)
+
+
+def test_sonar_backward_tall_fan_rescale():
+    """A fan taller than one row batch with many candidates per tile and a
+    gradient whose magnitude grows down the image (the fixed-point scale of a
+    tile grows between batches)."""
+    _say("sonar backward, 1400 x 2800 fan, growing gradient magnitude")
+    st = W.Stream(77, 1)
+    spec = W.SonarSpec(r_min=0.5, r_max=30.0, n_range=300, n_azimuth=200, fan_h=1400, fan_w=2800,
+                       alpha=0.08, gain=1.1, sigma_phi=0.3, sigma_sa=0.15, speckle_mode=W.SPECKLE_GAMMA,
+                       seed_lo=5, frame_id=1)
+    frames = [W.SonarFrame(spec, W.make_hits(st, spec, 20000, n_materials=16))]
+    refl = frames[0].hits.refl
+    ramp = np.logspace(-6, 3, spec.fan_h)[:, None]
+    gfan = [(W.loss_weights((77, 2), (spec.fan_h, spec.fan_w)) * ramp).astype(np.float32)]
+    gpol = [W.loss_weights((77, 3), (spec.n_range, spec.n_azimuth))]
+    g_refl, g_par = gpu_backward(frames, refl, gpol, gfan)
+    o_refl, o_par, c_refl, c_par = oracle_backward(frames, refl, gpol, gfan)
+    assert_grad_cond(g_refl, o_refl, c_refl, what="refl vs oracle")
+    assert_grad_cond(g_par[0, :5], o_par, c_par, what="params vs oracle")
+
+
+def test_sonar_backward_nonfinite_gradient():
+    _say("sonar backward, a NaN in the fan gradient")
+    frames, refl, gpol, gfan = _bwd_case(W.SPECKLE_GAMMA, 6, n_frames=1)
+    gfan = [g.copy() for g in gfan]
+    gfan[0][20, 30] = np.nan
+    g_refl, g_par = gpu_backward(frames, refl, gpol, gfan)
+    o_refl, o_par, _, _ = oracle_backward(frames, refl, gpol, gfan)
+    np.testing.assert_array_equal(np.isnan(g_refl), np.isnan(o_refl))
+    np.testing.assert_array_equal(np.isnan(g_par[0, :5]), np.isnan(o_par))
+    assert np.isnan(o_par).any()
+
+
+def test_negative_reflectivities():
+    """Sums that cancel to zero inside a bin (only possible with signed
+    reflectivities) still get the multiplicative speckle exactly once."""
+    _say("signed reflectivities")
+    st = W.Stream(78, 1)
+    spec = W.SonarSpec(r_min=0.5, r_max=10.0, n_range=64, n_azimuth=48, fan_h=32, fan_w=64,
+                       speckle_mode=W.SPECKLE_GAMMA, seed_lo=8)
+    hits = W.make_hits(st, spec, 30000, n_materials=3)
+    hits.refl = np.array([0.5, -0.5, 0.25], np.float32)
+    # put pairs of opposite returns on the same point so that some bins cancel exactly
+    hits.x[1::2], hits.y[1::2], hits.z[1::2] = hits.x[0::2], hits.y[0::2], hits.z[0::2]
+    hits.nx[1::2], hits.ny[1::2], hits.nz[1::2] = hits.nx[0::2], hits.ny[0::2], hits.nz[0::2]
+    hits.mat[0::4] = 0
+    hits.mat[1::4] = 1
+    f = W.SonarFrame(spec, hits)
+    want = oracle_forward(f, hits.refl)
+    got = gpu_forward([f], hits.refl)[0]
+    np.testing.assert_array_equal(got["bins"], want["bins"])
+    # bin sums of signed terms: float32 rounding is relative to the sum of the
+    # magnitudes of the terms (cond), not to the cancelled result
+    ok = want["bins"] >= 0
+    cond = np.bincount(want["bins"][ok], weights=np.abs(want["intensity"][ok]),
+                       minlength=spec.n_range * spec.n_azimuth).reshape(spec.n_range, spec.n_azimuth)
+    _, mul = oracle.speckle_fields(SonarConfig.from_spec(spec))
+    o = want["out"]
+    bound = 1e-5 * np.maximum(np.abs(o), 1e-3 * np.abs(o).max()) + 1e-6 * float(spec.gain) * mul * cond
+    assert (np.abs(got["polar"] - o) <= bound).all()
+    assert ((want["P"] == 0) & (cond > 0)).sum() > 0       # some bins cancel exactly
