@@ -41,7 +41,21 @@ def parse():
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a plain 64 MiB device-to-device copy (counter calibration)")
     return ap.parse_args()
+
+
+def copy_calibration(torch, dev):
+    """A plain copy of known size: 64 MiB read, 64 MiB written per launch,
+    used to scale the HBM byte counters of a profiler run."""
+    n = 64 << 20
+    a = torch.ones(n // 4, dtype=torch.float32, device=dev)
+    b = torch.empty_like(a)
+    for _ in range(5):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    log("copy calibration: 5 launches of a %d-byte device copy" % n)
 
 
 class RealTimeStep:
@@ -70,8 +84,12 @@ class RealTimeStep:
         self.fan = torch.empty(spec.fan_h, spec.fan_w, device=dev)
         self.gpol = torch.as_tensor(W.loss_weights((101, 1), (spec.n_range, spec.n_azimuth)), device=dev)
         self.gfan = torch.as_tensor(W.loss_weights((101, 2), (spec.fan_h, spec.fan_w)), device=dev)
+        # training steps save the fan stencils in the forward pass for the backward pass
+        self.stencil = osm.api.fan_stencil_buffer(self.geom, dev)
         self.fwd = _sonar_struct(self.geom, self.hits, self.polar, self.fan)
-        self.bwd = _sonar_struct(self.geom, self.hits, grad_polar=self.gpol, grad_fan=self.gfan)
+        self.fwd_train = _sonar_struct(self.geom, self.hits, self.polar, self.fan, stencil=self.stencil)
+        self.bwd = _sonar_struct(self.geom, self.hits, grad_polar=self.gpol, grad_fan=self.gfan,
+                                 stencil=self.stencil)
         self.ws_f = torch.empty(_lib.oceansim_sonar_workspace_size(self.fwd, self.n_mat, False),
                                 dtype=torch.uint8, device=dev)
         self.ws_b = torch.empty(_lib.oceansim_sonar_workspace_size(self.bwd, self.n_mat, True),
@@ -97,10 +115,10 @@ class RealTimeStep:
         self.stream = torch.cuda.current_stream(dev).cuda_stream
         self.P = lambda t: t.data_ptr()
 
-    def sonar_forward(self):
+    def sonar_forward(self, train=False):
         L, P = self.lib, self.P
-        L.oceansim_sonar_render(self.fwd, P(self.params), 1, P(self.refl), self.n_mat, P(self.ws_f),
-                                self.ws_f.numel(), self.stream)
+        L.oceansim_sonar_render(self.fwd_train if train else self.fwd, P(self.params), 1, P(self.refl),
+                                self.n_mat, P(self.ws_f), self.ws_f.numel(), self.stream)
 
     def sonar_backward(self):
         L, P = self.lib, self.P
@@ -122,10 +140,21 @@ class RealTimeStep:
         self.uw_forward()
 
     def step(self):
-        self.sonar_forward()
+        self.sonar_forward(train=True)
         self.uw_forward()
         self.sonar_backward()
         self.uw_backward()
+
+    def algorithmic_bytes(self):
+        """Bytes each kernel must move per launch by the per-unit figures of
+        the method (inputs read once, outputs written once): returns 28 B,
+        polar bins 4 B, fan pixels 4 B, camera pixels 28 B forward and 44 B
+        backward (with the image gradients)."""
+        nb = self.geom.n_range * self.geom.n_azimuth
+        npx_fan = self.geom.fan_h * self.geom.fan_w
+        return {"k_bin": 28 * self.n_returns, "k_tile": 4 * nb, "k_fan": 4 * npx_fan,
+                "k_tile_bwd": 4 * npx_fan + 4 * nb, "k_ret_bwd": 28 * self.n_returns,
+                "k_uw": 28 * self.npix, "k_uw_bwd": 44 * self.npix}
 
 
 def timed(torch, fn, steps, warmup):
@@ -291,6 +320,9 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
+    if args.copy_calibration:
+        copy_calibration(torch, dev)
+        return
     log("building workload")
     rt = RealTimeStep(dev)
 
@@ -308,18 +340,27 @@ def main():
         "uw_forward": event_time(torch, rt.uw_forward, reps),
         "uw_backward": event_time(torch, rt.uw_backward, reps),
     }
-    # dominant kernel by algorithmic bytes: the camera model, 28 B/px forward
-    # (J 12 + depth 4 in, I 12 out) and 44 B/px backward (grad_out 12, J 12,
-    # depth 4 in; grad_J 12, grad_depth 4 out)
-    uw_fwd_bytes = 28 * rt.npix
-    uw_bwd_bytes = 44 * rt.npix
-    dom = "uw_backward" if parts["uw_backward"] >= parts["uw_forward"] else "uw_forward"
-    dom_bytes = uw_bwd_bytes if dom == "uw_backward" else uw_fwd_bytes
-    achieved = dom_bytes / parts[dom] / 1e9
-    roofline = {"bound": "hbm", "kernel": "k_uw_bwd" if dom == "uw_backward" else "k_uw",
-                "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-                "bytes_per_launch": dom_bytes, "launch_us": round(parts[dom] * 1e6, 2)}
+    # per-kernel durations: the library brackets each launch with HIP events
+    # on its stream while tracing is on
+    rt.lib.oceansim_trace_enable(True)
+    for _ in range(reps):
+        rt.step()
+    torch.cuda.synchronize()
+    trace = rt.lib.oceansim_trace_summary()
+    rt.lib.oceansim_trace_enable(False)
+    kern_us = {k: us / calls for k, (calls, us) in trace.items()}
+    dom = max(kern_us, key=lambda k: kern_us[k] * trace[k][0])
+    abytes = rt.algorithmic_bytes()
+    dom_bytes = abytes.get(dom)
+    achieved = dom_bytes / (kern_us[dom] * 1e-6) / 1e9 if dom_bytes else None
+    roofline = {"bound": "hbm", "kernel": dom,
+                "achieved": None if achieved is None else round(achieved, 1), "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": None if achieved is None else round(achieved / HBM_PEAK_GBS, 4),
+                "traffic": None, "bytes_per_launch": dom_bytes, "launch_us": round(kern_us[dom], 2)}
+    kernel_table = {k: {"us": round(kern_us[k], 2), "alg_bytes": abytes.get(k),
+                        "alg_GBps": round(abytes[k] / (kern_us[k] * 1e-6) / 1e9, 1) if k in abytes else None}
+                    for k in sorted(kern_us, key=lambda k: -kern_us[k])}
+    log("kernels (us): " + ", ".join("%s %.2f" % (k, v["us"]) for k, v in kernel_table.items()))
 
     extra = {}
     if not args.no_batched:
@@ -352,6 +393,7 @@ def main():
         "sonar_fwd_only_frames_per_s": 1.0 / t_sonar_fwd,
         "camera_mpx_per_s_fwd_bwd": rt.npix / t_step / 1e6,
         "entry_point_us": {k: round(v * 1e6, 2) for k, v in parts.items()},
+        "kernels": kernel_table,
         "roofline": roofline,
         "cpu_baseline": cpu,
     }

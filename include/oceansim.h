@@ -153,7 +153,17 @@ typedef struct {
     int32_t *bin_of_return;          /* out [n_returns] bin or -1, or NULL   */
     const float *grad_polar;         /* backward in [N_r][N_phi] or NULL (0) */
     const float *grad_fan;           /* backward in [fan_h][fan_w] or NULL   */
+    void *fan_stencil;               /* optional saved fan stencils, see
+                                        oceansim_fan_stencil_size: written by
+                                        the forward when non-NULL (and a fan
+                                        is rendered), read by the backward
+                                        instead of recomputing the fan
+                                        geometry.  Same geometry in both. */
 } oceansim_sonar_frame;
+
+/* Bytes of the fan_stencil buffer of a fan_h x fan_w fan (16 per pair of
+ * mirror-image pixels: the bilinear rows, columns and weights of the pair). */
+size_t oceansim_fan_stencil_size(int32_t fan_h, int32_t fan_w);
 
 /* Workspace bytes for oceansim_sonar_render (with_backward = 0) or for
  * oceansim_sonar_render_backward (with_backward = 1) on these frames. */
@@ -230,6 +240,20 @@ int oceansim_uw_form_backward(const oceansim_uw_frame *frames, int32_t n_frames,
                               const oceansim_water_params *params_dev, int32_t n_param_rows,
                               float *grad_params_dev, void *workspace, size_t workspace_bytes,
                               void *stream);
+
+/* ======================================================================== */
+/* Tracing                                                                  */
+/* ======================================================================== */
+
+/* enable = 1 starts a new trace: from then on every kernel the library
+ * launches is bracketed by HIP events recorded on its launch stream.
+ * enable = 0 stops recording (the collected records are kept).            */
+int oceansim_trace_enable(int32_t enable);
+
+/* Waits for the recorded events and writes one line per kernel name,
+ * "name calls total_us\n", into buf (truncated to len bytes, NUL-ended).
+ * *needed receives the full length (may be NULL).                         */
+int oceansim_trace_summary(char *buf, size_t len, size_t *needed);
 
 #ifdef __cplusplus
 }

@@ -43,7 +43,7 @@ class SonarFrame(C.Structure):
                 ("speckle_mode", C.c_int32), ("gamma_k", C.c_int32), ("param_row", C.c_int32),
                 ("seed_lo", C.c_uint32), ("seed_hi", C.c_uint32), ("frame_id", C.c_uint32),
                 ("polar", _P), ("fan", _P), ("bin_of_return", _P),
-                ("grad_polar", _P), ("grad_fan", _P)]
+                ("grad_polar", _P), ("grad_fan", _P), ("fan_stencil", _P)]
 
 
 class WaterParams(C.Structure):
@@ -85,6 +85,12 @@ def _load() -> C.CDLL:
         fn = getattr(lib, name)
         fn.argtypes = args
         fn.restype = C.c_int
+    lib.oceansim_fan_stencil_size.argtypes = [C.c_int32, C.c_int32]
+    lib.oceansim_fan_stencil_size.restype = C.c_size_t
+    lib.oceansim_trace_enable.argtypes = [C.c_int32]
+    lib.oceansim_trace_enable.restype = C.c_int
+    lib.oceansim_trace_summary.argtypes = [C.c_char_p, C.c_size_t, C.POINTER(C.c_size_t)]
+    lib.oceansim_trace_summary.restype = C.c_int
     return lib
 
 
@@ -92,7 +98,8 @@ lib = _load()
 
 EXPORTED = ("oceansim_last_error", "oceansim_abi_version", "oceansim_sonar_workspace_size",
             "oceansim_sonar_render", "oceansim_sonar_render_backward", "oceansim_uw_workspace_size",
-            "oceansim_uw_form", "oceansim_uw_form_backward")
+            "oceansim_uw_form", "oceansim_uw_form_backward", "oceansim_fan_stencil_size",
+            "oceansim_trace_enable", "oceansim_trace_summary")
 
 
 def last_error() -> str:
@@ -161,3 +168,24 @@ def oceansim_uw_form_backward(frames, params_dev: int, n_param_rows: int, grad_p
     ptr, n, _keep = _frames(frames, UwFrame)
     check(lib.oceansim_uw_form_backward(ptr, n, params_dev, n_param_rows, grad_params_dev, workspace,
                                         workspace_bytes, stream), "oceansim_uw_form_backward")
+
+
+def oceansim_fan_stencil_size(fan_h: int, fan_w: int) -> int:
+    return int(lib.oceansim_fan_stencil_size(fan_h, fan_w))
+
+
+def oceansim_trace_enable(enable: bool) -> None:
+    check(lib.oceansim_trace_enable(int(enable)), "oceansim_trace_enable")
+
+
+def oceansim_trace_summary() -> dict:
+    """{kernel name: (calls, total microseconds)} of the traced launches."""
+    need = C.c_size_t(0)
+    check(lib.oceansim_trace_summary(None, 0, C.byref(need)), "oceansim_trace_summary")
+    buf = C.create_string_buffer(max(1, need.value))
+    check(lib.oceansim_trace_summary(buf, need.value, None), "oceansim_trace_summary")
+    out = {}
+    for line in buf.value.decode().splitlines():
+        name, calls, us = line.split()
+        out[name] = (int(calls), float(us))
+    return out

@@ -107,7 +107,7 @@ def water_params(rows: Sequence, device="cuda") -> torch.Tensor:
 
 
 def _sonar_struct(g: SonarGeometry, h: DeviceHits, polar=None, fan=None, bins=None, grad_polar=None,
-                  grad_fan=None) -> SonarFrame:
+                  grad_fan=None, stencil=None) -> SonarFrame:
     s = SonarFrame()
     s.x, s.y, s.z = _ptr(h.x), _ptr(h.y), _ptr(h.z)
     s.nx, s.ny, s.nz = _ptr(h.nx), _ptr(h.ny), _ptr(h.nz)
@@ -123,13 +123,23 @@ def _sonar_struct(g: SonarGeometry, h: DeviceHits, polar=None, fan=None, bins=No
     s.seed_lo, s.seed_hi, s.frame_id = g.seed_lo & 0xFFFFFFFF, g.seed_hi & 0xFFFFFFFF, g.frame_id & 0xFFFFFFFF
     s.polar, s.fan, s.bin_of_return = _ptr(polar), _ptr(fan), _ptr(bins)
     s.grad_polar, s.grad_fan = _ptr(grad_polar), _ptr(grad_fan)
+    s.fan_stencil = _ptr(stencil)
     return s
+
+
+def fan_stencil_buffer(g: SonarGeometry, device) -> Optional[torch.Tensor]:
+    """Device buffer for the saved fan stencils of a frame (None without a fan)."""
+    n = _lib.oceansim_fan_stencil_size(g.fan_h, g.fan_w)
+    return torch.empty(n, dtype=torch.uint8, device=device) if n else None
 
 
 def render_sonar(geoms: Sequence[SonarGeometry], hits: Sequence[DeviceHits], params: torch.Tensor,
                  refl: torch.Tensor, *, polar: bool = True, fan: bool = True, bins: bool = False,
-                 workspace: Optional[torch.Tensor] = None) -> List[dict]:
-    """Forward sonar image formation of one or many frames in one call."""
+                 save_stencil: bool = False, workspace: Optional[torch.Tensor] = None) -> List[dict]:
+    """Forward sonar image formation of one or many frames in one call.
+
+    With ``save_stencil`` each frame with a fan also returns "stencil": the
+    fan stencils, to hand to render_sonar_backward."""
     device = params.device
     outs, structs = [], []
     for g, h in zip(geoms, hits):
@@ -138,10 +148,13 @@ def render_sonar(geoms: Sequence[SonarGeometry], hits: Sequence[DeviceHits], par
             o["polar"] = torch.empty(g.n_range, g.n_azimuth, dtype=torch.float32, device=device)
         if fan and g.fan_h > 0 and g.fan_w > 0:
             o["fan"] = torch.empty(g.fan_h, g.fan_w, dtype=torch.float32, device=device)
+            if save_stencil:
+                o["stencil"] = fan_stencil_buffer(g, device)
         if bins:
             o["bins"] = torch.empty(h.n, dtype=torch.int32, device=device)
         outs.append(o)
-        structs.append(_sonar_struct(g, h, o.get("polar"), o.get("fan"), o.get("bins")))
+        structs.append(_sonar_struct(g, h, o.get("polar"), o.get("fan"), o.get("bins"),
+                                     stencil=o.get("stencil")))
     n_mat = int(refl.numel())
     need = _lib.oceansim_sonar_workspace_size(structs, n_mat, False)
     ws = workspace if workspace is not None and workspace.numel() >= need else _workspace(need, device)
@@ -153,11 +166,16 @@ def render_sonar(geoms: Sequence[SonarGeometry], hits: Sequence[DeviceHits], par
 def render_sonar_backward(geoms: Sequence[SonarGeometry], hits: Sequence[DeviceHits], params: torch.Tensor,
                           refl: torch.Tensor, grad_polar: Sequence[Optional[torch.Tensor]],
                           grad_fan: Sequence[Optional[torch.Tensor]],
+                          stencils: Optional[Sequence[Optional[torch.Tensor]]] = None,
                           workspace: Optional[torch.Tensor] = None):
-    """Gradients (refl [M], params [rows, 8]) of sum <grad_polar, polar> + <grad_fan, fan>."""
+    """Gradients (refl [M], params [rows, 8]) of sum <grad_polar, polar> + <grad_fan, fan>.
+
+    ``stencils``: the fan stencils saved by the forward call (optional; without
+    them the fan geometry is recomputed)."""
     device = params.device
-    structs = [_sonar_struct(g, h, grad_polar=gp, grad_fan=gf)
-               for g, h, gp, gf in zip(geoms, hits, grad_polar, grad_fan)]
+    stencils = stencils or [None] * len(geoms)
+    structs = [_sonar_struct(g, h, grad_polar=gp, grad_fan=gf, stencil=sv)
+               for g, h, gp, gf, sv in zip(geoms, hits, grad_polar, grad_fan, stencils)]
     n_mat = int(refl.numel())
     need = _lib.oceansim_sonar_workspace_size(structs, n_mat, True)
     ws = workspace if workspace is not None and workspace.numel() >= need else _workspace(need, device)
@@ -216,8 +234,9 @@ class SonarRender(torch.autograd.Function):
 
     @staticmethod
     def forward(ctx, refl, params, geoms, hits):
-        outs = render_sonar(geoms, hits, params, refl, polar=True, fan=True)
+        outs = render_sonar(geoms, hits, params, refl, polar=True, fan=True, save_stencil=True)
         ctx.geoms, ctx.hits = geoms, hits
+        ctx.stencils = [o.get("stencil") for o in outs]
         ctx.save_for_backward(refl, params)
         flat = []
         for g, o in zip(geoms, outs):
@@ -240,7 +259,7 @@ class SonarRender(torch.autograd.Function):
                 gf.append(None if gfan is None else gfan.contiguous())
             else:
                 gf.append(None)
-        g_refl, g_par = render_sonar_backward(ctx.geoms, ctx.hits, params, refl, gp, gf)
+        g_refl, g_par = render_sonar_backward(ctx.geoms, ctx.hits, params, refl, gp, gf, ctx.stencils)
         return g_refl, g_par, None, None
 
 

@@ -1,6 +1,9 @@
 """Builds liboceansim.so (gfx950) in-tree with hipcc.
 
-    python -m paper_2503_01074_amd.build [--force]
+    python paper_2503_01074_amd/build.py [--force]
+
+Run it as a script (or load it by path): importing the package first would
+load the library this script rebuilds.
 """
 from __future__ import annotations
 

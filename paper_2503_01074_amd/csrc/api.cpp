@@ -9,6 +9,8 @@
 #include <cstring>
 #include <string>
 #include <vector>
+#include <atomic>
+#include <mutex>
 
 #include "../../include/oceansim.h"
 #include "device.hpp"
@@ -106,12 +108,18 @@ int check_frame(const oceansim_sonar_frame &fr, int idx, int n_param_rows, bool 
             return fail(OCEANSIM_E_INVALID_ARG, "frame %d: polar/fan must be 16-byte aligned", idx);
         if (!aligned(fr.bin_of_return, 4))
             return fail(OCEANSIM_E_INVALID_ARG, "frame %d: misaligned bin_of_return", idx);
+        if (fr.fan_stencil && !fr.fan)
+            return fail(OCEANSIM_E_INVALID_ARG, "frame %d: fan_stencil is written with the fan output only", idx);
     } else {
         if (fr.grad_fan && !has_fan)
             return fail(OCEANSIM_E_SHAPE, "frame %d: grad_fan given but fan is 0x0", idx);
         if (!aligned(fr.grad_polar, 16) || !aligned(fr.grad_fan, 16))
             return fail(OCEANSIM_E_INVALID_ARG, "frame %d: grad_polar/grad_fan must be 16-byte aligned", idx);
     }
+    if (fr.fan_stencil && !has_fan)
+        return fail(OCEANSIM_E_SHAPE, "frame %d: fan_stencil given but fan is 0x0", idx);
+    if (!aligned(fr.fan_stencil, 16))
+        return fail(OCEANSIM_E_INVALID_ARG, "frame %d: fan_stencil must be 16-byte aligned", idx);
     return OCEANSIM_OK;
 }
 
@@ -202,7 +210,9 @@ int plan_sonar(const oceansim_sonar_frame *frames, int n_frames, int n_param_row
         d.n_chunks = (int)((fr.n_returns + chunk - 1) / chunk);
         d.ret_chunk = chunk;
         d.n_ret_chunks = d.n_chunks;
-        d.fan_bpr = (((fr.fan_w + 1) / 2) + kBlock - 1) / kBlock;
+        d.half_w = (fr.fan_w + 1) / 2;
+        d.fan_bpr = (d.half_w + kBlock - 1) / kBlock;
+        d.stencil = static_cast<int4 *>(fr.fan_stencil);
         const bool fan_out = fr.fan_h > 0 && fr.fan_w > 0 && (backward ? true : fr.fan != nullptr);
         d.fan_blocks = (!backward && fan_out) ? fr.fan_h * d.fan_bpr : 0;
         d.speckle = fr.speckle_mode;
@@ -265,6 +275,9 @@ int plan_sonar(const oceansim_sonar_frame *frames, int n_frames, int n_param_row
     P.grid.fan_blocks = fan_blocks;
     P.grid.ret_blocks = ret_blocks;
     P.grid.tile_b_blocks = tile_b_blocks;
+    P.grid.all_saved = 1;
+    for (int i = 0; i < n_frames; ++i)
+        if (frames[i].grad_fan && !frames[i].fan_stencil) P.grid.all_saved = 0;
     if (backward) {
         P.n_slots = tile_b_blocks + ret_blocks;
         P.off_part = take(sizeof(double) * 5 * (size_t)std::max(1, P.n_slots));
@@ -361,9 +374,81 @@ hipError_t upload_table(const std::vector<T> &v, char *ws, size_t off, hipStream
     return hipMemcpyAsync(ws + off, v.data(), sizeof(T) * v.size(), hipMemcpyHostToDevice, st);
 }
 
+// --------------------------------------------------------------------------
+// Kernel-launch tracing
+// --------------------------------------------------------------------------
+struct TraceRec {
+    std::string name;
+    hipEvent_t a, b;
+};
+std::mutex g_trace_mu;
+std::atomic<bool> g_trace_on{false};
+std::vector<TraceRec> g_trace;
+
 }  // namespace
 
+namespace osim {
+bool trace_active() { return g_trace_on.load(std::memory_order_relaxed); }
+void trace_record(const char *, hipStream_t st, hipEvent_t *a, hipEvent_t *b) {
+    if (hipEventCreate(a) != hipSuccess) { *a = *b = nullptr; return; }
+    if (hipEventCreate(b) != hipSuccess) { (void)hipEventDestroy(*a); *a = *b = nullptr; return; }
+    (void)hipEventRecord(*a, st);
+}
+void trace_commit(const char *name, hipStream_t st, hipEvent_t a, hipEvent_t b) {
+    if (!a) return;
+    (void)hipEventRecord(b, st);
+    std::lock_guard<std::mutex> lk(g_trace_mu);
+    g_trace.push_back(TraceRec{name, a, b});
+}
+}  // namespace osim
+
 extern "C" {
+
+int oceansim_trace_enable(int32_t enable) {
+    std::lock_guard<std::mutex> lk(g_trace_mu);
+    if (enable) {
+        for (auto &r : g_trace) {
+            (void)hipEventDestroy(r.a);
+            (void)hipEventDestroy(r.b);
+        }
+        g_trace.clear();
+    }
+    g_trace_on.store(enable != 0);
+    return ok();
+}
+
+int oceansim_trace_summary(char *buf, size_t len, size_t *needed) {
+    std::lock_guard<std::mutex> lk(g_trace_mu);
+    std::vector<std::pair<std::string, std::pair<long, double>>> agg;
+    for (auto &r : g_trace) {
+        hipError_t e = hipEventSynchronize(r.b);
+        if (e != hipSuccess) return hip_fail(e, "trace event");
+        float ms = 0.0f;
+        e = hipEventElapsedTime(&ms, r.a, r.b);
+        if (e != hipSuccess) return hip_fail(e, "trace event");
+        auto it = std::find_if(agg.begin(), agg.end(), [&](auto &p) { return p.first == r.name; });
+        if (it == agg.end()) agg.push_back({r.name, {1, ms * 1e3}});
+        else { it->second.first += 1; it->second.second += ms * 1e3; }
+    }
+    std::string out;
+    char line[256];
+    for (auto &p : agg) {
+        snprintf(line, sizeof line, "%s %ld %.3f\n", p.first.c_str(), p.second.first, p.second.second);
+        out += line;
+    }
+    if (needed) *needed = out.size() + 1;
+    if (buf && len > 0) {
+        size_t n = std::min(len - 1, out.size());
+        memcpy(buf, out.data(), n);
+        buf[n] = 0;
+    }
+    return ok();
+}
+
+size_t oceansim_fan_stencil_size(int32_t fan_h, int32_t fan_w) {
+    if (fan_h <= 0 || fan_w <= 0) return 0;
+    return (size_t)fan_h * (size_t)((fan_w + 1) / 2) * 16;
+}
 
 const char *oceansim_last_error(void) { return g_err.c_str(); }
 

@@ -55,6 +55,8 @@ struct SonarDev {
     double inv_r_max;           // 1 / r_max
     float scale_phi_f, half_az_f;
     int az_fast;                // FP32 azimuth is accurate to < 1e-3 cell on this grid
+    int half_w;                 // fan pixel pairs per row: ceil(fan_w / 2)
+    int4 *stencil;              // saved fan stencils [fan_h][half_w] or nullptr
 };
 
 struct UwDev {
@@ -313,6 +315,25 @@ __device__ __forceinline__ bool fan_angular(const SonarDev &f, double phi, Stenc
 __device__ __forceinline__ bool fan_stencil(const SonarDev &f, double rho, double phi,
                                             Stencil &st) {
     return fan_radial(f, rho, st) && fan_angular(f, phi, st);
+}
+
+// Saved stencil of a pair of mirror-image fan pixels (left pixel u, right
+// pixel W-1-u): {first row (-1 = outside the sector), left pixel's first
+// column, row weight, left column weight}.  A weight w in [0, 1] is stored as
+// the smaller of w and 1 - w, its sign bit telling which, so that both w and
+// 1 - w keep full float relative precision.  The right pixel's columns are
+// the mirror image: first column N_phi - 2 - j0, weight code negated.
+__device__ __forceinline__ float encode_weight(double w) {
+    return w <= 0.5 ? (float)w : -(float)(1.0 - w);
+}
+__device__ __forceinline__ void decode_weight(float e, float &w, float &one_minus_w) {
+    if (__builtin_signbit(e)) {
+        w = 1.0f + e;
+        one_minus_w = -e;
+    } else {
+        w = e;
+        one_minus_w = 1.0f - e;
+    }
 }
 
 // --------------------------------------------------------------------------

@@ -8,6 +8,31 @@
 
 namespace osim {
 
+// Event tracing of kernel launches (see oceansim_trace_enable): while tracing
+// is on, a TraceScope brackets one launch with events on its stream.
+bool trace_active();
+void trace_record(const char *name, hipStream_t st, hipEvent_t *a, hipEvent_t *b);
+void trace_commit(const char *name, hipStream_t st, hipEvent_t a, hipEvent_t b);
+
+struct TraceScope {
+    const char *name;
+    hipStream_t st;
+    hipEvent_t a = nullptr, b = nullptr;
+    bool on;
+    TraceScope(const char *n, hipStream_t s) : name(n), st(s), on(trace_active()) {
+        if (on) trace_record(name, st, &a, &b);
+    }
+    ~TraceScope() {
+        if (on) trace_commit(name, st, a, b);
+    }
+};
+
+#define OSIM_LAUNCH(NAME, ...)                   \
+    do {                                         \
+        ::osim::TraceScope osim_ts_(NAME, st);   \
+        hipLaunchKernelGGL(__VA_ARGS__);         \
+    } while (0)
+
 // Launch geometry of one sonar call (all frames).
 struct SonarGrid {
     int bin_blocks;      // binning workgroups over all frames
@@ -20,6 +45,7 @@ struct SonarGrid {
     int max_tiles;       // largest forward tile count of a frame
     int max_tile_bins;   // largest forward tile of a frame, in bins
     int max_tile_bins_b; // largest backward tile of a frame, in bins
+    int all_saved;       // every frame with a fan gradient has saved fan stencils
 };
 
 hipError_t sonar_forward_one(const SonarDev &f, const SonarGrid &g, const oceansim_sonar_params *params,

@@ -204,17 +204,6 @@ __global__ __launch_bounds__(kBlock) void k_tile(Src src, const oceansim_sonar_p
 // ---------------------------------------------------------------------------
 // k_fan: pixel u (left half, x <= 0) and its mirror W-1-u share rho and |phi|.
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ float fan_sample(const SonarDev &f, const float *img, double rho,
-                                            double phi) {
-    Stencil st;
-    if (!fan_stencil(f, rho, phi, st)) return 0.0f;
-    const long long r0 = (long long)st.i0 * f.n_az, r1 = (long long)st.i1 * f.n_az;
-    const double a = img[r0 + st.j0], b = img[r0 + st.j1];
-    const double c = img[r1 + st.j0], d = img[r1 + st.j1];
-    const double t = st.t, s = st.s;
-    return (float)((1.0 - t) * (1.0 - s) * a + (1.0 - t) * s * b + t * (1.0 - s) * c + t * s * d);
-}
-
 // Polar position of left-half pixel (v, u): rho and the azimuth |phi| >= 0.
 __device__ __forceinline__ void fan_left(const SonarDev &f, int v, int u, double &rho,
                                          double &phi_pos) {
@@ -231,14 +220,35 @@ __global__ __launch_bounds__(kBlock) void k_fan(Src src) {
     const SonarDev &f = src.frame(fi);
     const int v = local / f.fan_bpr;
     const int u = (local - v * f.fan_bpr) * kBlock + threadIdx.x;
-    const int half_w = (f.fan_w + 1) >> 1;
-    if (u >= half_w) return;
+    if (u >= f.half_w) return;
     double rho, phi;
     fan_left(f, v, u, rho, phi);
     float *row = f.fan + (long long)v * f.fan_w;
-    row[u] = fan_sample(f, f.polar, rho, phi);
     const int um = f.fan_w - 1 - u;
-    if (um != u) row[um] = fan_sample(f, f.polar, rho, -phi);
+    Stencil st;
+    const bool inside = fan_stencil(f, rho, phi, st);
+    float left = 0.0f, right = 0.0f;
+    if (inside) {
+        const float *img = f.polar;
+        const long long r0 = (long long)st.i0 * f.n_az, r1 = (long long)st.i1 * f.n_az;
+        auto blend = [&](int j0, int j1, double s) {
+            const double a = img[r0 + j0], b = img[r0 + j1], c = img[r1 + j0], d = img[r1 + j1];
+            const double t = st.t;
+            return (float)((1.0 - t) * (1.0 - s) * a + (1.0 - t) * s * b + t * (1.0 - s) * c + t * s * d);
+        };
+        left = blend(st.j0, st.j1, st.s);
+        if (um != u) {
+            Stencil sr = st;
+            fan_angular(f, -phi, sr);
+            right = blend(sr.j0, sr.j1, sr.s);
+        }
+    }
+    row[u] = left;
+    if (um != u) row[um] = right;
+    if (f.stencil)
+        f.stencil[(long long)v * f.half_w + u] =
+            inside ? make_int4(st.i0, st.j0, __float_as_int(encode_weight(st.t)), __float_as_int(encode_weight(st.s)))
+                   : make_int4(-1, 0, 0, 0);
 }
 
 // ---------------------------------------------------------------------------
@@ -247,9 +257,14 @@ __global__ __launch_bounds__(kBlock) void k_fan(Src src) {
 constexpr int kBwdThreads = 512;
 constexpr int kRowBatch = 1024;
 
-// Left-half pixel interval [ua, ub] of fan row v whose centres may lie within
-// radial distance [rlo, rhi] of the apex and inside the sector (with a
-// one-pixel margin; the exact stencil test decides membership).
+// Relative margin of the candidate bounds: far above FP64 rounding (1e-16)
+// and far below a pixel, so every pixel whose computed stencil can touch
+// the tile is enumerated and almost no other.
+constexpr double kCandEps = 1e-7;
+
+// Left-half pixel interval [ua, ub] of fan row v whose centres lie within
+// radial distance [rlo, rhi] of the apex and inside the sector; the exact
+// stencil test decides membership.
 __device__ __forceinline__ void row_interval(const SonarDev &f, int v, double rlo, double rhi,
                                              int &ua, int &ub) {
     const double s = f.fan_s;
@@ -259,7 +274,7 @@ __device__ __forceinline__ void row_interval(const SonarDev &f, int v, double rl
     if (y > rhi) return;
     double xo = __builtin_sqrt(rhi * rhi - y * y);
     if (f.half_az < 1.5707963267948966) {
-        const double xs = y * f.tan_half_az + s;
+        const double xs = y * f.tan_half_az * (1.0 + kCandEps) + kCandEps * s;
         xo = xo < xs ? xo : xs;
     }
     const double xi = rlo > y ? __builtin_sqrt(rlo * rlo - y * y) : 0.0;
@@ -267,10 +282,9 @@ __device__ __forceinline__ void row_interval(const SonarDev &f, int v, double rl
     // left half: x in [-xo, -xi]  ->  u = x / s + W/2 - 1/2
     const double c = 0.5 * (double)f.fan_w - 0.5;
     const double a = -xo / s + c, b = -xi / s + c;
-    const int half_w = (f.fan_w + 1) >> 1;
-    int lo = (int)__builtin_floor(a) - 1, hi = (int)__builtin_ceil(b) + 1;
+    int lo = (int)__builtin_ceil(a - 1e-6), hi = (int)__builtin_floor(b + 1e-6);
     lo = lo < 0 ? 0 : lo;
-    hi = hi > half_w - 1 ? half_w - 1 : hi;
+    hi = hi > f.half_w - 1 ? f.half_w - 1 : hi;
     ua = lo;
     ub = hi;
 }
@@ -301,7 +315,9 @@ __device__ __forceinline__ long long round_to_ll(double x) {
     return (long long)__double_as_longlong(t) - 0x4338000000000000LL;
 }
 
-template <class Src>
+// SAVED: every frame of the launch carries the stencils saved by its forward
+// pass (the geometry is not recomputed); otherwise frames may mix both kinds.
+template <class Src, bool SAVED>
 __global__ __launch_bounds__(kBwdThreads, 4) void k_tile_bwd(Src src, const oceansim_sonar_params *params,
                                                           double *part, float *grad_refl_zero,
                                                           int n_mat_zero) {
@@ -343,12 +359,12 @@ __global__ __launch_bounds__(kBwdThreads, 4) void k_tile_bwd(Src src, const ocea
     const bool have_fan = f.grad_fan != nullptr && f.fan_h > 0 && f.fan_w > 0;
     if (have_fan) {
         const double s = f.fan_s;
-        // pixels whose stencil may touch rows [ia, ib) lie at radial distance
-        // [r_min + (ia - 1/2) dr, r_min + (ib + 1/2) dr]; one pixel of margin
-        double rlo = f.r_min + ((double)ia - 0.5) * f.dr - s;
-        double rhi = f.r_min + ((double)ib + 0.5) * f.dr + s;
-        rlo = rlo < 0.0 ? 0.0 : rlo;
-        rhi = rhi > f.r_max + s ? f.r_max + s : rhi;
+        // pixels whose stencil touches rows [ia, ib) lie at radial distance
+        // [r_min + (ia - 1/2) dr, r_min + (ib + 1/2) dr) within [r_min, r_max]
+        double rlo = f.r_min + ((double)ia - 0.5) * f.dr;
+        double rhi = f.r_min + ((double)ib + 0.5) * f.dr;
+        rlo = (rlo < f.r_min ? f.r_min : rlo) * (1.0 - kCandEps);
+        rhi = (rhi > f.r_max ? f.r_max : rhi) * (1.0 + kCandEps);
         const double rlo2 = rlo * rlo, rhi2 = rhi * rhi;
         const double cmin = cos(f.half_az < 1.5707963267948966 ? f.half_az : 1.5707963267948966);
         const double ymin = rlo * cmin - s, ymax = rhi + s;
@@ -376,18 +392,31 @@ __global__ __launch_bounds__(kBwdThreads, 4) void k_tile_bwd(Src src, const ocea
                     for (int k = lo; k < hi; ++k) cand_row[k - cb] = (unsigned short)r;
                 }
                 __syncthreads();
-                // largest finite |gradient| of this sub-batch
-                double mx = 0.0;
-                for (int k = tid; k < ncand; k += NT) {
-                    const int r = cand_row[k];
-                    const int v = vb + r;
-                    const int u = row_u0[r] + (cb + k - row_pre[r]);
-                    const float *grow = f.grad_fan + (long long)v * W;
-                    const double a0 = __builtin_fabs((double)grow[u]);
-                    const double a1 = __builtin_fabs((double)grow[W - 1 - u]);
-                    if (a0 <= 1.7976931348623157e308 && a0 > mx) mx = a0;
-                    if (a1 <= 1.7976931348623157e308 && a1 > mx) mx = a1;
+                // largest finite |gradient| of this sub-batch (eight candidates
+                // per thread in flight)
+                float mxf = 0.0f;
+                for (int k0 = tid; k0 < ncand; k0 += 8 * NT) {
+                    float ga[8], gb[8];
+#pragma unroll
+                    for (int q = 0; q < 8; ++q) {
+                        const int k = k0 + q * NT;
+                        ga[q] = gb[q] = 0.0f;
+                        if (k < ncand) {
+                            const int r = cand_row[k];
+                            const int u = row_u0[r] + (cb + k - row_pre[r]);
+                            const float *grow = f.grad_fan + (long long)(vb + r) * W;
+                            ga[q] = grow[u];
+                            gb[q] = grow[W - 1 - u];
+                        }
+                    }
+#pragma unroll
+                    for (int q = 0; q < 8; ++q) {
+                        const float a0 = __builtin_fabsf(ga[q]), a1 = __builtin_fabsf(gb[q]);
+                        if (a0 <= 3.4028235e38f && a0 > mxf) mxf = a0;
+                        if (a1 <= 3.4028235e38f && a1 > mxf) mxf = a1;
+                    }
                 }
+                double mx = (double)mxf;
                 for (int off = 32; off > 0; off >>= 1) {
                     const double o = __shfl_down(mx, off, kWave);
                     mx = o > mx ? o : mx;
@@ -420,6 +449,83 @@ __global__ __launch_bounds__(kBwdThreads, 4) void k_tile_bwd(Src src, const ocea
                 }
                 // no nonzero finite value yet: only non-finite ones (poison) can act
                 const double scale = sh_exp == -100000 ? 0.0 : ldexp(1.0, 50 - sh_exp);
+                if (SAVED || f.stencil) {
+                    // stencils saved by the forward pass; four candidates per
+                    // thread with their loads issued before any is used
+                    constexpr int U = SAVED ? 4 : 1;
+                    for (int k0 = tid; k0 < ncand; k0 += U * NT) {
+                    float G0[U], G1[U];
+                    int4 REC[U];
+                    int UU[U];
+#pragma unroll
+                    for (int q = 0; q < U; ++q) {
+                        const int k = k0 + q * NT;
+                        G0[q] = G1[q] = 0.0f;
+                        REC[q] = make_int4(-1, 0, 0, 0);
+                        UU[q] = -1;
+                        if (k < ncand) {
+                            const int r = cand_row[k];
+                            const int v = vb + r;
+                            const int u = row_u0[r] + (cb + k - row_pre[r]);
+                            const float *grow = f.grad_fan + (long long)v * W;
+                            UU[q] = u;
+                            G0[q] = grow[u];
+                            G1[q] = (W - 1 - u) != u ? grow[W - 1 - u] : 0.0f;
+                            REC[q] = f.stencil[(long long)v * f.half_w + u];
+                        }
+                    }
+#pragma unroll
+                    for (int q = 0; q < U; ++q) {
+                        const int u = UU[q];
+                        const int um = W - 1 - u;
+                        const float g0 = G0[q], g1 = G1[q];
+                        if (u < 0 || (g0 == 0.0f && g1 == 0.0f)) continue;
+                        const int4 rec = REC[q];
+                        const int i0 = rec.x;
+                        if (i0 < 0) continue;
+                        const int i1 = f.n_range == 1 ? i0 : i0 + 1;
+                        if (i1 < ia || i0 >= ib) continue;
+                        float t, omt;
+                        decode_weight(__int_as_float(rec.z), t, omt);
+                        const float es = __int_as_float(rec.w);
+                        for (int side = 0; side < 2; ++side) {
+                            if (side == 1 && um == u) break;
+                            const float g = side == 0 ? g0 : g1;
+                            if (g == 0.0f) continue;
+                            const bool one_col = f.n_az == 1;
+                            const int j0 = side == 0 || one_col ? rec.y : f.n_az - 2 - rec.y;
+                            const int j1 = one_col ? j0 : j0 + 1;
+                            float sw, omsw;
+                            decode_weight(side == 0 || one_col ? es : -es, sw, omsw);
+                            const bool finite = __builtin_isfinite(g);
+                            const double gd = (double)g * scale;
+                            const double wr0 = (double)omt * gd, wr1 = (double)t * gd;
+#pragma unroll
+                            for (int a = 0; a < 2; ++a) {
+                                const int ii = a == 0 ? i0 : i1;
+                                if (ii < ia || ii >= ib || (a == 1 && i1 == i0)) continue;
+                                const double wa_ = a == 0 ? wr0 : wr1;
+#pragma unroll
+                                for (int c = 0; c < 2; ++c) {
+                                    if (c == 1 && one_col) continue;
+                                    const int lb = (ii - ia) * f.n_az + (c == 0 ? j0 : j1);
+                                    if (!finite) {
+                                        atomicOr(&poison[lb >> 5], 1u << (lb & 31));
+                                        continue;
+                                    }
+                                    const long long qv = round_to_ll(wa_ * (double)(c == 0 ? omsw : sw));
+                                    if (qv != 0)
+                                        atomicAdd(reinterpret_cast<unsigned long long *>(&acc[lb]),
+                                                  (unsigned long long)qv);
+                                }
+                            }
+                        }
+                    }
+                    }
+                    __syncthreads();
+                    continue;
+                }
+                if (SAVED) continue;   // not reached: every frame has saved stencils
                 for (int k = tid; k < ncand; k += NT) {
                     const int r = cand_row[k];
                     const int v = vb + r;
@@ -649,17 +755,17 @@ static hipError_t launch_fwd(const Src &src, const SonarGrid &g, const oceansim_
     if (g.bin_blocks > 0) {
         const size_t lds = (size_t)((g.max_tiles + 1 + 3) & ~3) * 4 + (size_t)g.chunk * 8;
         OSIM_DISPATCH_R(g.chunk / kBlock,
-                        hipLaunchKernelGGL((k_bin<Src, RR>), dim3(g.bin_blocks), dim3(kBlock), lds, st, src,
+                        OSIM_LAUNCH("k_bin", (k_bin<Src, RR>), dim3(g.bin_blocks), dim3(kBlock), lds, st, src,
                                            params, refl, n_mat));
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
-    hipLaunchKernelGGL((k_tile<Src>), dim3(g.tile_blocks), dim3(kBlock), (size_t)g.max_tile_bins * 8, st,
+    OSIM_LAUNCH("k_tile", (k_tile<Src>), dim3(g.tile_blocks), dim3(kBlock), (size_t)g.max_tile_bins * 8, st,
                        src, params);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     if (g.fan_blocks > 0) {
-        hipLaunchKernelGGL((k_fan<Src>), dim3(g.fan_blocks), dim3(kBlock), 0, st, src);
+        OSIM_LAUNCH("k_fan", (k_fan<Src>), dim3(g.fan_blocks), dim3(kBlock), 0, st, src);
         e = hipGetLastError();
     }
     return e;
@@ -673,9 +779,14 @@ static hipError_t launch_bwd(const Src &src, int n_frames, const SonarGrid &g,
     const bool lane_hist = n_mat <= kLaneHistMats;
     hipError_t e = hipSuccess;
     if (g.tile_b_blocks > 0) {
-        hipLaunchKernelGGL((k_tile_bwd<Src>), dim3(g.tile_b_blocks), dim3(kBwdThreads),
-                           (size_t)g.max_tile_bins_b * 8, st, src, params, part,
-                           lane_hist ? (float *)nullptr : grad_refl, n_mat);
+        if (g.all_saved)
+            OSIM_LAUNCH("k_tile_bwd", (k_tile_bwd<Src, true>), dim3(g.tile_b_blocks), dim3(kBwdThreads),
+                        (size_t)g.max_tile_bins_b * 8, st, src, params, part,
+                        lane_hist ? (float *)nullptr : grad_refl, n_mat);
+        else
+            OSIM_LAUNCH("k_tile_bwd", (k_tile_bwd<Src, false>), dim3(g.tile_b_blocks), dim3(kBwdThreads),
+                        (size_t)g.max_tile_bins_b * 8, st, src, params, part,
+                        lane_hist ? (float *)nullptr : grad_refl, n_mat);
         e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
@@ -685,7 +796,7 @@ static hipError_t launch_bwd(const Src &src, int n_frames, const SonarGrid &g,
         double *rp = lane_hist ? refl_part : nullptr;
         float *ga = lane_hist ? nullptr : grad_refl;
         OSIM_DISPATCH_R(g.ret_chunk / kBlock,
-                        hipLaunchKernelGGL((k_ret_bwd<Src, RR>), dim3(g.ret_blocks), dim3(kBlock), lds, st, src,
+                        OSIM_LAUNCH("k_ret_bwd", (k_ret_bwd<Src, RR>), dim3(g.ret_blocks), dim3(kBlock), lds, st, src,
                                            params, refl, n_mat, part, g.tile_b_blocks, rp, ga));
         e = hipGetLastError();
         if (e != hipSuccess) return e;
@@ -694,7 +805,7 @@ static hipError_t launch_bwd(const Src &src, int n_frames, const SonarGrid &g,
     // unless there was no tile at all (then the reduction writes zeros)
     const bool refl_blocks = lane_hist || g.tile_b_blocks == 0;
     const int blocks = n_rows * OCEANSIM_SONAR_GRAD_WIDTH + (refl_blocks ? n_mat : 0);
-    hipLaunchKernelGGL((k_reduce_sonar<Src>), dim3(blocks), dim3(kBlock), 0, st, src, n_frames, part,
+    OSIM_LAUNCH("k_reduce_sonar", (k_reduce_sonar<Src>), dim3(blocks), dim3(kBlock), 0, st, src, n_frames, part,
                        g.tile_b_blocks, n_rows, grad_params, lane_hist ? refl_part : nullptr, g.ret_blocks,
                        n_mat, grad_refl);
     return hipGetLastError();

@@ -145,23 +145,23 @@ __global__ __launch_bounds__(kBlock) void k_uw_bwd(Src src, const oceansim_water
 }
 
 hipError_t uw_forward_one(const UwDev &f, int blocks, const oceansim_water_params *params, hipStream_t st) {
-    hipLaunchKernelGGL((k_uw<One<UwDev>>), dim3(blocks), dim3(kBlock), 0, st, One<UwDev>{f}, params);
+    OSIM_LAUNCH("k_uw", (k_uw<One<UwDev>>), dim3(blocks), dim3(kBlock), 0, st, One<UwDev>{f}, params);
     return hipGetLastError();
 }
 hipError_t uw_forward_table(const UwDev *t, int n, int blocks, const oceansim_water_params *params,
                             hipStream_t st) {
-    hipLaunchKernelGGL((k_uw<Table<UwDev>>), dim3(blocks), dim3(kBlock), 0, st, Table<UwDev>{t, n}, params);
+    OSIM_LAUNCH("k_uw", (k_uw<Table<UwDev>>), dim3(blocks), dim3(kBlock), 0, st, Table<UwDev>{t, n}, params);
     return hipGetLastError();
 }
 hipError_t uw_backward_one(const UwDev &f, int blocks, const oceansim_water_params *params, double *part,
                            int *part_row, hipStream_t st) {
-    hipLaunchKernelGGL((k_uw_bwd<One<UwDev>>), dim3(blocks), dim3(kBlock), 0, st, One<UwDev>{f}, params,
+    OSIM_LAUNCH("k_uw_bwd", (k_uw_bwd<One<UwDev>>), dim3(blocks), dim3(kBlock), 0, st, One<UwDev>{f}, params,
                        part, part_row);
     return hipGetLastError();
 }
 hipError_t uw_backward_table(const UwDev *t, int n, int blocks, const oceansim_water_params *params,
                              double *part, int *part_row, hipStream_t st) {
-    hipLaunchKernelGGL((k_uw_bwd<Table<UwDev>>), dim3(blocks), dim3(kBlock), 0, st, Table<UwDev>{t, n},
+    OSIM_LAUNCH("k_uw_bwd", (k_uw_bwd<Table<UwDev>>), dim3(blocks), dim3(kBlock), 0, st, Table<UwDev>{t, n},
                        params, part, part_row);
     return hipGetLastError();
 }
@@ -193,13 +193,13 @@ __global__ __launch_bounds__(kBlock) void k_reduce_cols(const double *part, int 
 
 hipError_t reduce_rows(const double *part, const int *row, int n_slots, int width, int n_rows, float *out,
                        int out_stride, hipStream_t st) {
-    hipLaunchKernelGGL(k_reduce_rows, dim3(n_rows * out_stride), dim3(kBlock), 0, st, part, row, n_slots,
+    OSIM_LAUNCH("k_reduce_rows", k_reduce_rows, dim3(n_rows * out_stride), dim3(kBlock), 0, st, part, row, n_slots,
                        width, out, out_stride);
     return hipGetLastError();
 }
 
 hipError_t reduce_cols(const double *part, int n_slots, int width, float *out, hipStream_t st) {
-    hipLaunchKernelGGL(k_reduce_cols, dim3(width), dim3(kBlock), 0, st, part, n_slots, width, out);
+    OSIM_LAUNCH("k_reduce_cols", k_reduce_cols, dim3(width), dim3(kBlock), 0, st, part, n_slots, width, out);
     return hipGetLastError();
 }
 

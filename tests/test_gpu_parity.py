@@ -186,7 +186,9 @@ def test_batched_equals_plain_and_oracle():
 # --------------------------------------------------------------------------- #
 # backward                                                                    #
 # --------------------------------------------------------------------------- #
-def gpu_backward(frames, refl, gpol, gfan):
+def gpu_backward(frames, refl, gpol, gfan, saved=False):
+    """GPU gradients; with ``saved`` the forward pass runs first and saves the
+    fan stencils that the backward pass then reads."""
     import torch
     osm = _osm()
     geoms = [osm.SonarGeometry.from_spec(f.spec, param_row=0) for f in frames]
@@ -195,7 +197,11 @@ def gpu_backward(frames, refl, gpol, gfan):
     refl_d = torch.as_tensor(refl).cuda()
     gp = [None if g is None else torch.as_tensor(g, dtype=torch.float32).cuda() for g in gpol]
     gf = [None if g is None else torch.as_tensor(g, dtype=torch.float32).cuda() for g in gfan]
-    g_refl, g_par = osm.render_sonar_backward(geoms, hits, params, refl_d, gp, gf)
+    stencils = None
+    if saved:
+        outs = osm.render_sonar(geoms, hits, params, refl_d, save_stencil=True)
+        stencils = [o.get("stencil") for o in outs]
+    g_refl, g_par = osm.render_sonar_backward(geoms, hits, params, refl_d, gp, gf, stencils)
     torch.cuda.synchronize()
     return g_refl.cpu().numpy().astype(np.float64), g_par.cpu().numpy().astype(np.float64)
 
@@ -247,12 +253,13 @@ def _oracle_loss(frames, refl, gpol, gfan, **over):
     return L
 
 
+@pytest.mark.parametrize("saved", [False, True])
 @pytest.mark.parametrize("mode", [W.SPECKLE_OFF, W.SPECKLE_PAPER, W.SPECKLE_GAMMA])
 @pytest.mark.parametrize("n_mat", [6, 64])
-def test_sonar_backward_vs_oracle_and_fd(mode, n_mat):
-    _say("sonar backward mode %d n_mat %d" % (mode, n_mat))
+def test_sonar_backward_vs_oracle_and_fd(mode, n_mat, saved):
+    _say("sonar backward mode %d n_mat %d saved stencils %s" % (mode, n_mat, saved))
     frames, refl, gpol, gfan = _bwd_case(mode, n_mat, n_frames=2)
-    g_refl, g_par = gpu_backward(frames, refl, gpol, gfan)
+    g_refl, g_par = gpu_backward(frames, refl, gpol, gfan, saved)
     o_refl, o_par, c_refl, c_par = oracle_backward(frames, refl, gpol, gfan)
     assert_grad_cond(g_refl, o_refl, c_refl, what="refl vs oracle")
     assert_grad_cond(g_par[0, :5], o_par, c_par, what="params vs oracle")
@@ -374,11 +381,12 @@ def test_uw_backward():
         assert abs(g_w.cpu().numpy()[0, k] - fd) <= GRAD_RTOL_FD * abs(fd), (k, fd)
 
 
-def test_sonar_backward_tall_fan_rescale():
+@pytest.mark.parametrize("saved", [False, True])
+def test_sonar_backward_tall_fan_rescale(saved):
     """A fan taller than one row batch with many candidates per tile and a
     gradient whose magnitude grows down the image (the fixed-point scale of a
     tile grows between batches)."""
-    _say("sonar backward, 1400 x 2800 fan, growing gradient magnitude")
+    _say("sonar backward, 1400 x 2800 fan, growing gradient magnitude, saved %s" % saved)
     st = W.Stream(77, 1)
     spec = W.SonarSpec(r_min=0.5, r_max=30.0, n_range=300, n_azimuth=200, fan_h=1400, fan_w=2800,
                        alpha=0.08, gain=1.1, sigma_phi=0.3, sigma_sa=0.15, speckle_mode=W.SPECKLE_GAMMA,
@@ -388,18 +396,19 @@ def test_sonar_backward_tall_fan_rescale():
     ramp = np.logspace(-6, 3, spec.fan_h)[:, None]
     gfan = [(W.loss_weights((77, 2), (spec.fan_h, spec.fan_w)) * ramp).astype(np.float32)]
     gpol = [W.loss_weights((77, 3), (spec.n_range, spec.n_azimuth))]
-    g_refl, g_par = gpu_backward(frames, refl, gpol, gfan)
+    g_refl, g_par = gpu_backward(frames, refl, gpol, gfan, saved)
     o_refl, o_par, c_refl, c_par = oracle_backward(frames, refl, gpol, gfan)
     assert_grad_cond(g_refl, o_refl, c_refl, what="refl vs oracle")
     assert_grad_cond(g_par[0, :5], o_par, c_par, what="params vs oracle")
 
 
-def test_sonar_backward_nonfinite_gradient():
-    _say("sonar backward, a NaN in the fan gradient")
+@pytest.mark.parametrize("saved", [False, True])
+def test_sonar_backward_nonfinite_gradient(saved):
+    _say("sonar backward, a NaN in the fan gradient, saved %s" % saved)
     frames, refl, gpol, gfan = _bwd_case(W.SPECKLE_GAMMA, 6, n_frames=1)
     gfan = [g.copy() for g in gfan]
     gfan[0][20, 30] = np.nan
-    g_refl, g_par = gpu_backward(frames, refl, gpol, gfan)
+    g_refl, g_par = gpu_backward(frames, refl, gpol, gfan, saved)
     o_refl, o_par, _, _ = oracle_backward(frames, refl, gpol, gfan)
     np.testing.assert_array_equal(np.isnan(g_refl), np.isnan(o_refl))
     np.testing.assert_array_equal(np.isnan(g_par[0, :5]), np.isnan(o_par))
@@ -434,3 +443,24 @@ def test_negative_reflectivities():
     bound = 1e-5 * np.maximum(np.abs(o), 1e-3 * np.abs(o).max()) + 1e-6 * float(spec.gain) * mul * cond
     assert (np.abs(got["polar"] - o) <= bound).all()
     assert ((want["P"] == 0) & (cond > 0)).sum() > 0       # some bins cancel exactly
+
+
+@pytest.mark.parametrize("shape", [(37, 29, 41, 83), (1, 17, 8, 16), (23, 1, 9, 9), (60, 40, 33, 64)])
+def test_sonar_backward_saved_matches_recomputed(shape):
+    """Saved-stencil and recomputed-geometry backward passes agree, on odd and
+    degenerate grids (one range row, one azimuth column, odd fan width)."""
+    Nr, Np, H, Wd = shape
+    _say("saved vs recomputed stencils %s" % (shape,))
+    st = W.Stream(79, Nr + Np)
+    spec = W.SonarSpec(r_min=0.7, r_max=13.0, n_range=Nr, n_azimuth=Np, fan_h=H, fan_w=Wd,
+                       speckle_mode=W.SPECKLE_PAPER, seed_lo=3, frame_id=2)
+    frames = [W.SonarFrame(spec, W.make_hits(st, spec, 3000, n_materials=5))]
+    refl = frames[0].hits.refl
+    gpol = [W.loss_weights((79, 1), (Nr, Np))]
+    gfan = [W.loss_weights((79, 2), (H, Wd))]
+    a = gpu_backward(frames, refl, gpol, gfan, False)
+    b = gpu_backward(frames, refl, gpol, gfan, True)
+    o_refl, o_par, c_refl, c_par = oracle_backward(frames, refl, gpol, gfan)
+    for g_refl, g_par in (a, b):
+        assert_grad_cond(g_refl, o_refl, c_refl, what="refl vs oracle")
+        assert_grad_cond(g_par[0, :5], o_par, c_par, what="params vs oracle")
