@@ -242,6 +242,68 @@ int oceansim_uw_form_backward(const oceansim_uw_frame *frames, int32_t n_frames,
                               void *stream);
 
 /* ======================================================================== */
+/* Plans: a batch of sonar and camera frames prepared once and launched     */
+/* many times, optionally replayed from HIP graphs.                         */
+/* ======================================================================== */
+
+typedef struct oceansim_plan oceansim_plan;
+
+enum {
+    OCEANSIM_PLAN_BACKWARD = 1,   /* also prepare the adjoint launch           */
+    OCEANSIM_PLAN_GRAPH = 2,      /* capture each launch sequence in a graph   */
+    OCEANSIM_PLAN_AUTOTUNE = 4    /* time launch-shape candidates at creation  */
+};
+
+/* Validates every frame, chooses launch shapes, allocates the plan's own
+ * device memory (workspaces, frame tables, saved fan stencils), uploads the
+ * frame tables and, with OCEANSIM_PLAN_GRAPH, captures the forward (and
+ * backward) launch sequences into HIP graphs.  The plan keeps every pointer
+ * of the descriptors, parameter tables and gradient outputs until
+ * oceansim_plan_destroy: the caller keeps them alive, and may change their
+ * CONTENTS (new returns, images, parameters) between launches, not the
+ * shapes.  Sonar frames are rendered (forward) into their polar/fan outputs;
+ * with OCEANSIM_PLAN_BACKWARD their grad_polar/grad_fan inputs and the
+ * camera frames' grad_out are read by oceansim_plan_backward, which writes
+ * grad_refl_dev [n_materials], grad_sonar_params_dev [n_sonar_rows][8] and
+ * grad_water_params_dev [n_water_rows][9] (each may be NULL when there are no
+ * frames of that kind).  For frames with a fan and a fan gradient the plan
+ * saves the fan stencils in the forward pass for the backward pass.  The
+ * forward is the image formation of oceansim_sonar_render (Sec. III-A.2,
+ * Eq. 2-6, and the fan) and oceansim_uw_form (Sec. III-A.1, Eq. 1); the
+ * backward is their adjoint and reads what the plan's latest forward left
+ * (bins, saved stencils), so order the two on one stream.
+ *
+ * OCEANSIM_PLAN_AUTOTUNE times the forward (and backward) launch for a small
+ * set of tile and chunk sizes and keeps the fastest whose outputs agree with
+ * the default shape's (1e-5 relative); results are cached per process and,
+ * when the environment variable OCEANSIM_TUNE_CACHE names a file, in that
+ * JSON file, keyed by GPU architecture, CU count and a size class of the
+ * batch.  Tuning runs the launches, so it reads the inputs (which must hold
+ * representative returns) and writes the outputs and gradients.  All work of
+ * creation is done on `stream`, which is synchronised.  Errors: the status
+ * codes above; on error *plan is NULL and nothing stays allocated.        */
+int oceansim_plan_create(const oceansim_sonar_frame *sonar, int32_t n_sonar,
+                         const oceansim_uw_frame *camera, int32_t n_camera,
+                         const oceansim_sonar_params *sonar_params_dev, int32_t n_sonar_rows,
+                         const float *refl_dev, int32_t n_materials,
+                         const oceansim_water_params *water_params_dev, int32_t n_water_rows,
+                         float *grad_refl_dev, float *grad_sonar_params_dev,
+                         float *grad_water_params_dev, int32_t flags, void *stream,
+                         oceansim_plan **plan);
+
+/* Enqueue the plan's forward / backward launches on `stream`. */
+int oceansim_plan_forward(oceansim_plan *plan, void *stream);
+int oceansim_plan_backward(oceansim_plan *plan, void *stream);
+
+/* Launch shapes in use: {forward tile bins, returns per chunk, backward tile
+ * bins, graphs in use (0/1)}. */
+int oceansim_plan_shape(const oceansim_plan *plan, int32_t shape[4]);
+
+/* Frees the plan's device memory and graphs (after synchronising the
+ * device).  NULL is accepted. */
+int oceansim_plan_destroy(oceansim_plan *plan);
+
+/* ======================================================================== */
 /* Tracing                                                                  */
 /* ======================================================================== */
 

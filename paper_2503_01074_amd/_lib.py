@@ -91,6 +91,16 @@ def _load() -> C.CDLL:
     lib.oceansim_trace_enable.restype = C.c_int
     lib.oceansim_trace_summary.argtypes = [C.c_char_p, C.c_size_t, C.POINTER(C.c_size_t)]
     lib.oceansim_trace_summary.restype = C.c_int
+    lib.oceansim_plan_create.argtypes = [SF, C.c_int32, UF, C.c_int32, _P, C.c_int32, _P, C.c_int32, _P,
+                                         C.c_int32, _P, _P, _P, C.c_int32, _P, C.POINTER(_P)]
+    lib.oceansim_plan_create.restype = C.c_int
+    for name in ("oceansim_plan_forward", "oceansim_plan_backward"):
+        getattr(lib, name).argtypes = [_P, _P]
+        getattr(lib, name).restype = C.c_int
+    lib.oceansim_plan_shape.argtypes = [_P, C.POINTER(C.c_int32)]
+    lib.oceansim_plan_shape.restype = C.c_int
+    lib.oceansim_plan_destroy.argtypes = [_P]
+    lib.oceansim_plan_destroy.restype = C.c_int
     return lib
 
 
@@ -99,7 +109,11 @@ lib = _load()
 EXPORTED = ("oceansim_last_error", "oceansim_abi_version", "oceansim_sonar_workspace_size",
             "oceansim_sonar_render", "oceansim_sonar_render_backward", "oceansim_uw_workspace_size",
             "oceansim_uw_form", "oceansim_uw_form_backward", "oceansim_fan_stencil_size",
-            "oceansim_trace_enable", "oceansim_trace_summary")
+            "oceansim_trace_enable", "oceansim_trace_summary", "oceansim_plan_create",
+            "oceansim_plan_forward", "oceansim_plan_backward", "oceansim_plan_shape",
+            "oceansim_plan_destroy")
+
+PLAN_BACKWARD, PLAN_GRAPH, PLAN_AUTOTUNE = 1, 2, 4
 
 
 def last_error() -> str:
@@ -189,3 +203,35 @@ def oceansim_trace_summary() -> dict:
         name, calls, us = line.split()
         out[name] = (int(calls), float(us))
     return out
+
+
+def oceansim_plan_create(sonar_frames, camera_frames, sonar_params_dev: int, n_sonar_rows: int,
+                         refl_dev: int, n_materials: int, water_params_dev: int, n_water_rows: int,
+                         grad_refl_dev: int, grad_sonar_params_dev: int, grad_water_params_dev: int,
+                         flags: int, stream: int) -> int:
+    """Returns the plan handle (an opaque pointer value)."""
+    sp, ns, _k1 = _frames(sonar_frames, SonarFrame) if sonar_frames else (None, 0, None)
+    cp, nc, _k2 = _frames(camera_frames, UwFrame) if camera_frames else (None, 0, None)
+    out = _P(None)
+    check(lib.oceansim_plan_create(sp, ns, cp, nc, sonar_params_dev, n_sonar_rows, refl_dev, n_materials,
+                                   water_params_dev, n_water_rows, grad_refl_dev, grad_sonar_params_dev,
+                                   grad_water_params_dev, flags, stream, C.byref(out)), "oceansim_plan_create")
+    return out.value
+
+
+def oceansim_plan_forward(plan: int, stream: int) -> None:
+    check(lib.oceansim_plan_forward(plan, stream), "oceansim_plan_forward")
+
+
+def oceansim_plan_backward(plan: int, stream: int) -> None:
+    check(lib.oceansim_plan_backward(plan, stream), "oceansim_plan_backward")
+
+
+def oceansim_plan_shape(plan: int) -> tuple:
+    shape = (C.c_int32 * 4)()
+    check(lib.oceansim_plan_shape(plan, shape), "oceansim_plan_shape")
+    return tuple(shape)
+
+
+def oceansim_plan_destroy(plan: int) -> None:
+    check(lib.oceansim_plan_destroy(plan), "oceansim_plan_destroy")

@@ -224,6 +224,102 @@ def uw_form_backward(Js, depths, water: torch.Tensor, grad_outs, rows=None, want
 
 
 # --------------------------------------------------------------------------- #
+# plans                                                                       #
+# --------------------------------------------------------------------------- #
+class Plan:
+    """Sonar and camera frames prepared once and launched many times
+    (oceansim_plan_*): frame tables are uploaded once and, with ``graph``,
+    each direction replays a captured HIP graph.
+
+    ``sonar``: (SonarGeometry, DeviceHits) pairs; ``camera``: (J [3, H, W],
+    depth [H, W], water_row) triples.  The plan allocates the outputs
+    (``sonar_out[i]["polar" / "fan" / "bins"]``, ``camera_out[i]["out"]``) and,
+    with ``backward``, the gradient inputs (``"grad_polar"``, ``"grad_fan"``,
+    ``"grad_out"``, zero-filled) and outputs (``grad_refl``,
+    ``grad_sonar_params``, ``grad_water``, and ``"grad_J"``/``"grad_depth"``
+    with ``image_grads``).  Between launches the caller refills any of these
+    tensors, the hits, the parameter tables and the images in place; shapes
+    and buffers stay fixed."""
+
+    def __init__(self, sonar=(), camera=(), *, sonar_params: Optional[torch.Tensor] = None,
+                 refl: Optional[torch.Tensor] = None, water: Optional[torch.Tensor] = None,
+                 backward: bool = False, graph: bool = False, autotune: bool = False,
+                 polar: bool = True, fan: bool = True, bins: bool = False, image_grads: bool = False):
+        self.handle = None
+        anchor = sonar_params if sonar_params is not None else water
+        self.device = anchor.device
+        dev = self.device
+        self.sonar_out, self.camera_out = [], []
+        s_structs, c_structs = [], []
+        for g, h in sonar:
+            o = {}
+            has_fan = fan and g.fan_h > 0 and g.fan_w > 0
+            if polar or not has_fan:
+                o["polar"] = torch.empty(g.n_range, g.n_azimuth, dtype=torch.float32, device=dev)
+            if has_fan:
+                o["fan"] = torch.empty(g.fan_h, g.fan_w, dtype=torch.float32, device=dev)
+            if bins:
+                o["bins"] = torch.empty(h.n, dtype=torch.int32, device=dev)
+            if backward:
+                if "polar" in o:
+                    o["grad_polar"] = torch.zeros_like(o["polar"])
+                if has_fan:
+                    o["grad_fan"] = torch.zeros_like(o["fan"])
+            self.sonar_out.append(o)
+            s_structs.append(_sonar_struct(g, h, o.get("polar"), o.get("fan"), o.get("bins"),
+                                           o.get("grad_polar"), o.get("grad_fan")))
+        for J, d, row in camera:
+            o = {"out": torch.empty_like(J)}
+            if backward:
+                o["grad_out"] = torch.zeros_like(J)
+                if image_grads:
+                    o["grad_J"] = torch.empty_like(J)
+                    o["grad_depth"] = torch.empty_like(d)
+            self.camera_out.append(o)
+            c_structs.append(_uw_struct(J, d, o["out"], row, o.get("grad_out"), o.get("grad_J"),
+                                        o.get("grad_depth")))
+        n_mat = int(refl.numel()) if refl is not None else 0
+        self.grad_refl = self.grad_sonar_params = self.grad_water = None
+        if backward and sonar:
+            self.grad_refl = torch.zeros(n_mat, dtype=torch.float32, device=dev)
+            self.grad_sonar_params = torch.zeros(sonar_params.shape[0], SONAR_GRAD_WIDTH, dtype=torch.float32,
+                                                 device=dev)
+        if backward and camera:
+            self.grad_water = torch.zeros(water.shape[0], WATER_GRAD_WIDTH, dtype=torch.float32, device=dev)
+        flags = ((_lib.PLAN_BACKWARD if backward else 0) | (_lib.PLAN_GRAPH if graph else 0) |
+                 (_lib.PLAN_AUTOTUNE if autotune else 0))
+        # the plan keeps raw pointers: hold the tensors for its lifetime
+        self._keep = (list(sonar), list(camera), sonar_params, refl, water)
+        self.handle = _lib.oceansim_plan_create(
+            s_structs, c_structs, _ptr(sonar_params), 0 if sonar_params is None else int(sonar_params.shape[0]),
+            _ptr(refl), n_mat, _ptr(water), 0 if water is None else int(water.shape[0]),
+            _ptr(self.grad_refl), _ptr(self.grad_sonar_params), _ptr(self.grad_water), flags, _stream(dev))
+
+    def forward(self) -> None:
+        """Enqueue the forward launches on the current stream."""
+        _lib.oceansim_plan_forward(self.handle, _stream(self.device))
+
+    def backward(self) -> None:
+        """Enqueue the adjoint launches (after a forward) on the current stream."""
+        _lib.oceansim_plan_backward(self.handle, _stream(self.device))
+
+    def shape(self) -> dict:
+        a = _lib.oceansim_plan_shape(self.handle)
+        return {"fwd_tile_bins": a[0], "chunk": a[1], "bwd_tile_bins": a[2], "graph": bool(a[3])}
+
+    def close(self) -> None:
+        if self.handle:
+            _lib.oceansim_plan_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+# --------------------------------------------------------------------------- #
 # autograd                                                                    #
 # --------------------------------------------------------------------------- #
 class SonarRender(torch.autograd.Function):

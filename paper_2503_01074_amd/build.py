@@ -17,8 +17,8 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "liboceansim.so")
-SOURCES = ["api.cpp", "sonar.hip", "uw.hip"]
-HEADERS = ["device.hpp", "launch.hpp"]
+SOURCES = ["api.cpp", "plan.cpp", "sonar.hip", "uw.hip"]
+HEADERS = ["device.hpp", "launch.hpp", "host.hpp"]
 ARCH = os.environ.get("OCEANSIM_ARCH", "gfx950")
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

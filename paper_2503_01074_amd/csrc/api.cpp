@@ -15,10 +15,12 @@
 #include "../../include/oceansim.h"
 #include "device.hpp"
 #include "launch.hpp"
+#include "host.hpp"
 
 using namespace osim;
 
-namespace {
+namespace osim {
+namespace host {
 
 thread_local std::string g_err;
 
@@ -41,26 +43,16 @@ int hip_fail(hipError_t e, const char *what) {
     return fail(OCEANSIM_E_HIP, "%s: %s", what, hipGetErrorString(e));
 }
 
+namespace {
 bool aligned(const void *p, size_t a) { return ((uintptr_t)p % a) == 0; }
 size_t round_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
-
-constexpr size_t kWsAlign = 256;
 constexpr long long kMaxReturns = (1LL << 31) - 1;
 constexpr int kMaxFanSide = 32768;
+}  // namespace
 
 // --------------------------------------------------------------------------
 // Sonar planning
 // --------------------------------------------------------------------------
-struct SonarPlan {
-    std::vector<SonarDev> dev;
-    SonarGrid grid{};
-    size_t bytes = 0;
-    // workspace offsets
-    size_t off_table = 0;
-    std::vector<size_t> off_pairs, off_chunk_off, off_polar, off_grad_img;
-    size_t off_part = 0, off_refl_part = 0;
-    int n_slots = 0;
-};
 
 int check_frame(const oceansim_sonar_frame &fr, int idx, int n_param_rows, bool backward) {
     if (fr.n_returns < 0) return fail(OCEANSIM_E_SHAPE, "frame %d: n_returns < 0", idx);
@@ -130,7 +122,7 @@ int pow2_at_least(long long v) {
 }
 
 int plan_sonar(const oceansim_sonar_frame *frames, int n_frames, int n_param_rows, int n_mat, bool backward,
-               SonarPlan &P) {
+               SonarPlan &P, const Tuning *tune, bool force_table) {
     if (n_frames < 0) return fail(OCEANSIM_E_INVALID_ARG, "n_frames < 0");
     if (n_frames > 0 && !frames) return fail(OCEANSIM_E_INVALID_ARG, "frames is NULL");
     if (n_mat < 1) return fail(OCEANSIM_E_INVALID_ARG, "n_materials must be >= 1");
@@ -147,7 +139,9 @@ int plan_sonar(const oceansim_sonar_frame *frames, int n_frames, int n_param_row
     // Forward tiles: aim at ~512 tile workgroups per call or more, with
     // 1024..4096 bins each; a tile holds whole range rows.  Backward tiles:
     // up to 2048 bins (their pixel work grows with the tile's radial extent).
-    const long long tb_target = std::min<long long>(kMaxTileBins, std::max<long long>(1024, total_nb / 512));
+    long long tb_target = std::min<long long>(kMaxTileBins, std::max<long long>(1024, total_nb / 512));
+    if (tune && tune->fwd_tile_bins > 0) tb_target = std::min(tune->fwd_tile_bins, kMaxTileBins);
+    const int tb_b = (tune && tune->bwd_tile_bins > 0) ? std::min(tune->bwd_tile_bins, kMaxTileBins) : 2048;
     for (int i = 0; i < n_frames; ++i) {
         const oceansim_sonar_frame &fr = frames[i];
         SonarDev &d = P.dev[i];
@@ -161,7 +155,7 @@ int plan_sonar(const oceansim_sonar_frame *frames, int n_frames, int n_param_row
         d.rows_per_tile = rpt;
         d.tile_bins = rpt * fr.n_azimuth;
         d.n_tiles = n_tiles;
-        const int rpt_b = std::max(1, std::min(fr.n_range, 2048 / fr.n_azimuth));
+        const int rpt_b = std::max(1, std::min(fr.n_range, tb_b / fr.n_azimuth));
         d.rows_per_tile_b = rpt_b;
         d.tile_bins_b = rpt_b * fr.n_azimuth;
         d.n_tiles_b = (fr.n_range + rpt_b - 1) / rpt_b;
@@ -179,6 +173,7 @@ int plan_sonar(const oceansim_sonar_frame *frames, int n_frames, int n_param_row
         return e;
     };
     while (chunk < 4096 && table_entries(chunk) > 2 * total_n + (1 << 20)) chunk *= 2;
+    if (tune && tune->chunk > 0) chunk = tune->chunk;
     P.grid.chunk = chunk;
     P.grid.ret_chunk = chunk;
     P.grid.max_tiles = max_tiles;
@@ -191,7 +186,7 @@ int plan_sonar(const oceansim_sonar_frame *frames, int n_frames, int n_param_row
         off = round_up(off + bytes, kWsAlign);
         return o;
     };
-    P.off_table = n_frames > 1 ? take(sizeof(SonarDev) * n_frames) : 0;
+    P.off_table = (n_frames > 1 || force_table) ? take(sizeof(SonarDev) * std::max(1, n_frames)) : 0;
     P.off_pairs.assign(n_frames, 0);
     P.off_chunk_off.assign(n_frames, 0);
     P.off_polar.assign(n_frames, (size_t)-1);
@@ -312,13 +307,9 @@ int check_ws(void *ws, size_t have, size_t need) {
 // --------------------------------------------------------------------------
 // Camera planning
 // --------------------------------------------------------------------------
-struct UwPlan {
-    std::vector<UwDev> dev;
-    int blocks = 0;
-    size_t bytes = 0, off_table = 0, off_part = 0, off_part_row = 0;
-};
 
-int plan_uw(const oceansim_uw_frame *frames, int n_frames, int n_param_rows, bool backward, UwPlan &P) {
+int plan_uw(const oceansim_uw_frame *frames, int n_frames, int n_param_rows, bool backward, UwPlan &P,
+            bool force_table) {
     if (n_frames < 0) return fail(OCEANSIM_E_INVALID_ARG, "n_frames < 0");
     if (n_frames > 0 && !frames) return fail(OCEANSIM_E_INVALID_ARG, "frames is NULL");
     if (n_param_rows < 1) return fail(OCEANSIM_E_INVALID_ARG, "n_param_rows must be >= 1");
@@ -360,7 +351,7 @@ int plan_uw(const oceansim_uw_frame *frames, int n_frames, int n_param_rows, boo
         off = round_up(off + bytes, kWsAlign);
         return o;
     };
-    P.off_table = n_frames > 1 ? take(sizeof(UwDev) * n_frames) : 0;
+    P.off_table = (n_frames > 1 || force_table) ? take(sizeof(UwDev) * std::max(1, n_frames)) : 0;
     if (backward) {
         P.off_part = take(sizeof(double) * 9 * (size_t)std::max(1, blocks));
         P.off_part_row = take(sizeof(int) * (size_t)std::max(1, blocks));
@@ -369,11 +360,10 @@ int plan_uw(const oceansim_uw_frame *frames, int n_frames, int n_param_rows, boo
     return OCEANSIM_OK;
 }
 
-template <class T>
-hipError_t upload_table(const std::vector<T> &v, char *ws, size_t off, hipStream_t st) {
-    return hipMemcpyAsync(ws + off, v.data(), sizeof(T) * v.size(), hipMemcpyHostToDevice, st);
-}
+}  // namespace host
+}  // namespace osim
 
+namespace {
 // --------------------------------------------------------------------------
 // Kernel-launch tracing
 // --------------------------------------------------------------------------
@@ -388,7 +378,12 @@ std::vector<TraceRec> g_trace;
 }  // namespace
 
 namespace osim {
-bool trace_active() { return g_trace_on.load(std::memory_order_relaxed); }
+namespace {
+thread_local bool t_capturing = false;   // launches being captured into a graph are not traced
+}  // namespace
+
+void set_capturing(bool on) { t_capturing = on; }
+bool trace_active() { return g_trace_on.load(std::memory_order_relaxed) && !t_capturing; }
 void trace_record(const char *, hipStream_t st, hipEvent_t *a, hipEvent_t *b) {
     if (hipEventCreate(a) != hipSuccess) { *a = *b = nullptr; return; }
     if (hipEventCreate(b) != hipSuccess) { (void)hipEventDestroy(*a); *a = *b = nullptr; return; }
@@ -401,6 +396,8 @@ void trace_commit(const char *name, hipStream_t st, hipEvent_t a, hipEvent_t b) 
     g_trace.push_back(TraceRec{name, a, b});
 }
 }  // namespace osim
+
+using namespace osim::host;
 
 extern "C" {
 
@@ -459,7 +456,7 @@ int oceansim_sonar_workspace_size(const oceansim_sonar_frame *frames, int32_t n_
     if (!bytes) return fail(OCEANSIM_E_INVALID_ARG, "bytes is NULL");
     SonarPlan P;
     // the row count is not known here: accept any row index for sizing
-    int rc = plan_sonar(frames, n_frames, 0x7fffffff, n_materials, with_backward != 0, P);
+    int rc = plan_sonar(frames, n_frames, 0x7fffffff, n_materials, with_backward != 0, P, nullptr);
     if (rc) return rc;
     *bytes = P.bytes;
     return ok();
@@ -471,7 +468,7 @@ int oceansim_sonar_render(const oceansim_sonar_frame *frames, int32_t n_frames,
     if (!params_dev) return fail(OCEANSIM_E_INVALID_ARG, "params_dev is NULL");
     if (!refl_dev) return fail(OCEANSIM_E_INVALID_ARG, "refl_dev is NULL");
     SonarPlan P;
-    int rc = plan_sonar(frames, n_frames, n_param_rows, n_materials, false, P);
+    int rc = plan_sonar(frames, n_frames, n_param_rows, n_materials, false, P, nullptr);
     if (rc) return rc;
     if (n_frames == 0) return ok();
     rc = check_ws(workspace, workspace_bytes, P.bytes);
@@ -503,7 +500,7 @@ int oceansim_sonar_render_backward(const oceansim_sonar_frame *frames, int32_t n
     if (!aligned(grad_refl_dev, 4) || !aligned(grad_params_dev, 4))
         return fail(OCEANSIM_E_INVALID_ARG, "misaligned gradient output");
     SonarPlan P;
-    int rc = plan_sonar(frames, n_frames, n_param_rows, n_materials, true, P);
+    int rc = plan_sonar(frames, n_frames, n_param_rows, n_materials, true, P, nullptr);
     if (rc) return rc;
     rc = check_ws(workspace, workspace_bytes, P.bytes);
     if (rc) return rc;

@@ -1,0 +1,61 @@
+// Host-side planning shared by the plain entry points and plans (internal).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <string>
+#include <vector>
+
+#include "../../include/oceansim.h"
+#include "device.hpp"
+#include "launch.hpp"
+
+namespace osim {
+namespace host {
+
+constexpr size_t kWsAlign = 256;
+
+// Launch-shape knobs; 0 = the built-in heuristic.
+struct Tuning {
+    int fwd_tile_bins = 0;   // forward polar tile size target (bins, whole rows)
+    int chunk = 0;           // returns per binning / return-gather workgroup (512..4096)
+    int bwd_tile_bins = 0;   // backward polar tile size target (bins, whole rows)
+};
+
+struct SonarPlan {
+    std::vector<SonarDev> dev;
+    SonarGrid grid{};
+    size_t bytes = 0;
+    // workspace offsets
+    size_t off_table = 0;
+    std::vector<size_t> off_pairs, off_chunk_off, off_polar, off_grad_img;
+    size_t off_part = 0, off_refl_part = 0;
+    int n_slots = 0;
+};
+
+struct UwPlan {
+    std::vector<UwDev> dev;
+    int blocks = 0;
+    size_t bytes = 0, off_table = 0, off_part = 0, off_part_row = 0;
+};
+
+int fail(int code, const char *fmt, ...);
+int ok();
+int hip_fail(hipError_t e, const char *what);
+
+// force_table: reserve a device frame table even for a single frame (plans
+// always launch from tables; the plain entry points pass one frame by value).
+int plan_sonar(const oceansim_sonar_frame *frames, int n_frames, int n_param_rows, int n_mat, bool backward,
+               SonarPlan &P, const Tuning *tune, bool force_table = false);
+void carve_sonar(SonarPlan &P, char *ws, bool backward);
+int check_ws(void *ws, size_t have, size_t need);
+int plan_uw(const oceansim_uw_frame *frames, int n_frames, int n_param_rows, bool backward, UwPlan &P,
+            bool force_table = false);
+
+template <class T>
+hipError_t upload_table(const std::vector<T> &v, char *ws, size_t off, hipStream_t st) {
+    return hipMemcpyAsync(ws + off, v.data(), sizeof(T) * v.size(), hipMemcpyHostToDevice, st);
+}
+
+}  // namespace host
+}  // namespace osim

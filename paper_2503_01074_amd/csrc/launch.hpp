@@ -13,6 +13,8 @@ namespace osim {
 bool trace_active();
 void trace_record(const char *name, hipStream_t st, hipEvent_t *a, hipEvent_t *b);
 void trace_commit(const char *name, hipStream_t st, hipEvent_t a, hipEvent_t b);
+// While set (per thread), launches are being captured into a graph and are not traced.
+void set_capturing(bool on);
 
 struct TraceScope {
     const char *name;

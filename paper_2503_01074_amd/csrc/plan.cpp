@@ -1,0 +1,585 @@
+// Plans: batches of sonar and camera frames prepared once and launched many
+// times (frame tables uploaded once, launch sequences optionally captured in
+// HIP graphs), and the launch-shape autotuner.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "../../include/oceansim.h"
+#include "device.hpp"
+#include "host.hpp"
+#include "launch.hpp"
+
+using namespace osim;
+using namespace osim::host;
+
+struct oceansim_plan {
+    std::vector<oceansim_sonar_frame> sonar;
+    std::vector<oceansim_uw_frame> camera;
+    const oceansim_sonar_params *sp = nullptr;
+    int n_srows = 0;
+    const float *refl = nullptr;
+    int n_mat = 1;
+    const oceansim_water_params *wp = nullptr;
+    int n_wrows = 0;
+    float *g_refl = nullptr, *g_sp = nullptr, *g_wp = nullptr;
+    int flags = 0;
+    Tuning tune;
+    SonarPlan sf, sb;
+    UwPlan uf, ub;
+    char *mem = nullptr;        // workspaces and frame tables
+    char *stencil_mem = nullptr;
+    char *ws_sf = nullptr, *ws_sb = nullptr, *ws_uf = nullptr, *ws_ub = nullptr;
+    hipStream_t cap = nullptr;
+    hipGraphExec_t g_fwd = nullptr, g_bwd = nullptr;
+};
+
+namespace {
+
+// ---------------------------------------------------------------------------
+// Agreement check of a tuning candidate against the reference outputs:
+// counts elements with |a - b| > rtol * max(|a|, |b|) (NaN counts).
+// ---------------------------------------------------------------------------
+__global__ void k_count_disagree(const float *a, const float *b, long long n, float rtol, unsigned *bad) {
+    unsigned local = 0;
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (long long)gridDim.x * blockDim.x) {
+        const float x = a[i], y = b[i];
+        const float m = fmaxf(fabsf(x), fabsf(y));
+        if (!(fabsf(x - y) <= rtol * m)) ++local;
+    }
+    if (local) atomicAdd(bad, local);
+}
+
+hipError_t launch_forward(oceansim_plan *p, hipStream_t st) {
+    hipError_t e = hipSuccess;
+    if (!p->sonar.empty()) {
+        e = sonar_forward_table(reinterpret_cast<const SonarDev *>(p->ws_sf + p->sf.off_table),
+                                (int)p->sonar.size(), p->sf.grid, p->sp, p->refl, p->n_mat, st);
+        if (e != hipSuccess) return e;
+    }
+    if (!p->camera.empty() && p->uf.blocks > 0)
+        e = uw_forward_table(reinterpret_cast<const UwDev *>(p->ws_uf + p->uf.off_table), (int)p->camera.size(),
+                             p->uf.blocks, p->wp, st);
+    return e;
+}
+
+hipError_t launch_backward(oceansim_plan *p, hipStream_t st) {
+    hipError_t e = hipSuccess;
+    if (!p->sonar.empty()) {
+        const bool lane_hist = p->n_mat <= kLaneHistMats;
+        e = sonar_backward_table(reinterpret_cast<const SonarDev *>(p->ws_sb + p->sb.off_table),
+                                 (int)p->sonar.size(), p->sb.grid, p->sp, p->n_srows, p->refl, p->n_mat,
+                                 reinterpret_cast<double *>(p->ws_sb + p->sb.off_part),
+                                 lane_hist ? reinterpret_cast<double *>(p->ws_sb + p->sb.off_refl_part) : nullptr,
+                                 p->g_sp, p->g_refl, st);
+        if (e != hipSuccess) return e;
+    }
+    if (!p->camera.empty()) {
+        double *part = reinterpret_cast<double *>(p->ws_ub + p->ub.off_part);
+        int *row = reinterpret_cast<int *>(p->ws_ub + p->ub.off_part_row);
+        if (p->ub.blocks > 0) {
+            e = uw_backward_table(reinterpret_cast<const UwDev *>(p->ws_ub + p->ub.off_table), (int)p->camera.size(),
+                                  p->ub.blocks, p->wp, part, row, st);
+            if (e != hipSuccess) return e;
+        }
+        e = reduce_rows(part, row, p->ub.blocks, 9, p->n_wrows, p->g_wp, OCEANSIM_WATER_GRAD_WIDTH, st);
+    }
+    return e;
+}
+
+// ---------------------------------------------------------------------------
+// Tuning cache: per process, optionally persisted as JSON
+// ({"key": [fwd_tile_bins, chunk, bwd_tile_bins], ...}).
+// ---------------------------------------------------------------------------
+std::mutex g_tune_mu;
+std::map<std::string, Tuning> g_tune;
+bool g_tune_loaded = false;
+
+const char *tune_file() {
+    const char *p = getenv("OCEANSIM_TUNE_CACHE");
+    return (p && *p) ? p : nullptr;
+}
+
+void tune_load_locked() {
+    if (g_tune_loaded) return;
+    g_tune_loaded = true;
+    const char *path = tune_file();
+    if (!path) return;
+    FILE *fh = fopen(path, "r");
+    if (!fh) return;
+    std::string text;
+    char buf[4096];
+    size_t n;
+    while ((n = fread(buf, 1, sizeof buf, fh)) > 0) text.append(buf, n);
+    fclose(fh);
+    size_t pos = 0;
+    while ((pos = text.find('"', pos)) != std::string::npos) {
+        size_t end = text.find('"', pos + 1);
+        if (end == std::string::npos) break;
+        std::string key = text.substr(pos + 1, end - pos - 1);
+        Tuning t;
+        if (sscanf(text.c_str() + end + 1, " : [ %d , %d , %d ]", &t.fwd_tile_bins, &t.chunk, &t.bwd_tile_bins) == 3)
+            g_tune[key] = t;
+        pos = end + 1;
+    }
+}
+
+void tune_save_locked() {
+    const char *path = tune_file();
+    if (!path) return;
+    std::string tmp = std::string(path) + ".tmp";
+    FILE *fh = fopen(tmp.c_str(), "w");
+    if (!fh) return;
+    fprintf(fh, "{\n");
+    size_t k = 0;
+    for (auto &kv : g_tune)
+        fprintf(fh, "  \"%s\": [%d, %d, %d]%s\n", kv.first.c_str(), kv.second.fwd_tile_bins, kv.second.chunk,
+                kv.second.bwd_tile_bins, ++k < g_tune.size() ? "," : "");
+    fprintf(fh, "}\n");
+    fclose(fh);
+    rename(tmp.c_str(), path);
+}
+
+int ilog2(long long v) {
+    int e = 0;
+    while (v > 1) {
+        v >>= 1;
+        ++e;
+    }
+    return e;
+}
+
+std::string tune_key(const oceansim_plan *p) {
+    int dev = 0, cus = 0;
+    (void)hipGetDevice(&dev);
+    (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    hipDeviceProp_t prop;
+    std::string arch = "gfx";
+    if (hipGetDeviceProperties(&prop, dev) == hipSuccess) arch = prop.gcnArchName;
+    arch = arch.substr(0, arch.find(':'));
+    long long n = 0, nb = 0, px = 0;
+    for (auto &f : p->sonar) {
+        n += f.n_returns;
+        nb += (long long)f.n_range * f.n_azimuth;
+        px += (long long)f.fan_h * f.fan_w;
+    }
+    char buf[256];
+    snprintf(buf, sizeof buf, "%s/%dcu/s%d-r%d-b%d-f%d-m%d-bw%d", arch.c_str(), cus, ilog2(p->sonar.size()),
+             ilog2(n), ilog2(nb), ilog2(px), p->n_mat <= kLaneHistMats ? 0 : 1,
+             (p->flags & OCEANSIM_PLAN_BACKWARD) ? 1 : 0);
+    return buf;
+}
+
+struct Candidate {
+    Tuning t;
+    SonarPlan f, b;
+    double us = 1e30;
+    bool ok = false;
+};
+
+// Times `fn` (3 launches after one warm-up) on stream st, in microseconds.
+template <class F>
+double time_us(F fn, hipStream_t st) {
+    hipEvent_t a, b;
+    if (hipEventCreate(&a) != hipSuccess) return 1e30;
+    if (hipEventCreate(&b) != hipSuccess) {
+        (void)hipEventDestroy(a);
+        return 1e30;
+    }
+    fn();
+    (void)hipEventRecord(a, st);
+    for (int k = 0; k < 3; ++k) fn();
+    (void)hipEventRecord(b, st);
+    float ms = 1e30f;
+    if (hipEventSynchronize(b) == hipSuccess) (void)hipEventElapsedTime(&ms, a, b);
+    (void)hipEventDestroy(a);
+    (void)hipEventDestroy(b);
+    return ms * 1e3 / 3.0;
+}
+
+// Chooses p->tune by timing candidates; the plan's stencil memory is set.
+int autotune(oceansim_plan *p, hipStream_t st) {
+    const std::string key = tune_key(p);
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        tune_load_locked();
+        auto it = g_tune.find(key);
+        if (it != g_tune.end()) {
+            p->tune = it->second;
+            return OCEANSIM_OK;
+        }
+    }
+    const bool bwd = (p->flags & OCEANSIM_PLAN_BACKWARD) != 0;
+    const int n = (int)p->sonar.size();
+    std::vector<Candidate> cands;
+    cands.push_back(Candidate{});   // the default shape is the reference
+    for (int ft : {1024, 2048, 4096})
+        for (int ch : {512, 1024, 2048, 4096}) {
+            Candidate c;
+            c.t.fwd_tile_bins = ft;
+            c.t.chunk = ch;
+            cands.push_back(c);
+        }
+    size_t ws = 0;
+    for (auto &c : cands) {
+        int rc = plan_sonar(p->sonar.data(), n, p->n_srows, p->n_mat, false, c.f, &c.t, true);
+        if (rc) return rc;
+        ws = std::max(ws, c.f.bytes);
+    }
+    // reference outputs
+    size_t out_elems = 0;
+    for (auto &f : p->sonar) {
+        if (f.polar) out_elems += (size_t)f.n_range * f.n_azimuth;
+        if (f.fan) out_elems += (size_t)f.fan_h * f.fan_w;
+    }
+    char *tmp = nullptr;
+    float *ref = nullptr;
+    unsigned *bad = nullptr;
+    hipError_t e = hipMalloc(&tmp, ws + 256);
+    if (e != hipSuccess) return hip_fail(e, "autotune workspace");
+    e = hipMalloc(&ref, std::max<size_t>(out_elems, 1) * sizeof(float) + 256);
+    if (e == hipSuccess) e = hipMalloc(&bad, sizeof(unsigned));
+    if (e != hipSuccess) {
+        (void)hipFree(tmp);
+        if (ref) (void)hipFree(ref);
+        return hip_fail(e, "autotune buffers");
+    }
+    auto copy_outputs = [&](bool to_ref) -> hipError_t {
+        size_t off = 0;
+        for (auto &f : p->sonar) {
+            const size_t a = f.polar ? (size_t)f.n_range * f.n_azimuth : 0;
+            const size_t b = f.fan ? (size_t)f.fan_h * f.fan_w : 0;
+            hipError_t r = hipSuccess;
+            if (a) {
+                if (to_ref) r = hipMemcpyAsync(ref + off, f.polar, a * 4, hipMemcpyDeviceToDevice, st);
+                else hipLaunchKernelGGL(k_count_disagree, dim3(256), dim3(256), 0, st, f.polar, ref + off,
+                                        (long long)a, 1e-5f, bad);
+                off += a;
+            }
+            if (r == hipSuccess && b) {
+                if (to_ref) r = hipMemcpyAsync(ref + off, f.fan, b * 4, hipMemcpyDeviceToDevice, st);
+                else hipLaunchKernelGGL(k_count_disagree, dim3(256), dim3(256), 0, st, f.fan, ref + off,
+                                        (long long)b, 1e-5f, bad);
+                off += b;
+            }
+            if (r != hipSuccess) return r;
+        }
+        return hipGetLastError();
+    };
+    int rc = OCEANSIM_OK;
+    for (size_t k = 0; k < cands.size() && rc == OCEANSIM_OK; ++k) {
+        Candidate &c = cands[k];
+        carve_sonar(c.f, tmp, false);
+        e = upload_table(c.f.dev, tmp, c.f.off_table, st);
+        const SonarDev *table = reinterpret_cast<const SonarDev *>(tmp + c.f.off_table);
+        auto run = [&]() { return sonar_forward_table(table, n, c.f.grid, p->sp, p->refl, p->n_mat, st); };
+        if (e == hipSuccess) e = run();
+        if (e == hipSuccess && k == 0) e = copy_outputs(true);
+        unsigned nbad = 0;
+        if (e == hipSuccess && k > 0) {
+            e = hipMemsetAsync(bad, 0, sizeof(unsigned), st);
+            if (e == hipSuccess) e = copy_outputs(false);
+            if (e == hipSuccess) e = hipMemcpyAsync(&nbad, bad, sizeof(unsigned), hipMemcpyDeviceToHost, st);
+            if (e == hipSuccess) e = hipStreamSynchronize(st);
+        }
+        if (e != hipSuccess) {
+            rc = hip_fail(e, "autotune forward");
+            break;
+        }
+        c.ok = nbad == 0;
+        if (c.ok) c.us = time_us(run, st);
+    }
+    size_t best = 0;
+    for (size_t k = 1; k < cands.size(); ++k)
+        if (cands[k].ok && cands[k].us < cands[best].us) best = k;
+    Tuning chosen = cands[best].t;   // zeros: the built-in heuristic won
+
+    if (rc == OCEANSIM_OK && bwd) {
+        // restore the forward's saved stencils under the chosen shape, then
+        // time the backward tile sizes
+        SonarPlan fp;
+        rc = plan_sonar(p->sonar.data(), n, p->n_srows, p->n_mat, false, fp, &chosen, true);
+        std::vector<Candidate> bc;
+        for (int bt : {2048, 1024, 4096}) {
+            Candidate c;
+            c.t = chosen;
+            c.t.bwd_tile_bins = bt;
+            bc.push_back(c);
+        }
+        if (rc == OCEANSIM_OK && fp.bytes > ws) rc = fail(OCEANSIM_E_WORKSPACE, "autotune: forward workspace");
+        size_t wsb = 0;
+        for (auto &c : bc) {
+            if (rc) break;
+            rc = plan_sonar(p->sonar.data(), n, p->n_srows, p->n_mat, true, c.b, &c.t, true);
+            wsb = std::max(wsb, c.b.bytes);
+        }
+        char *tb = nullptr;
+        if (rc == OCEANSIM_OK) {
+            e = hipMalloc(&tb, wsb + 256);
+            if (e != hipSuccess) rc = hip_fail(e, "autotune workspace");
+        }
+        if (rc == OCEANSIM_OK) {
+            carve_sonar(fp, tmp, false);
+            e = upload_table(fp.dev, tmp, fp.off_table, st);
+            if (e == hipSuccess)
+                e = sonar_forward_table(reinterpret_cast<const SonarDev *>(tmp + fp.off_table), n, fp.grid, p->sp,
+                                        p->refl, p->n_mat, st);
+            std::vector<float> ref_g, got_g;
+            const size_t ng = (size_t)p->n_mat + (size_t)p->n_srows * OCEANSIM_SONAR_GRAD_WIDTH;
+            for (size_t k = 0; k < bc.size() && e == hipSuccess; ++k) {
+                Candidate &c = bc[k];
+                carve_sonar(c.b, tb, true);
+                e = upload_table(c.b.dev, tb, c.b.off_table, st);
+                const SonarDev *table = reinterpret_cast<const SonarDev *>(tb + c.b.off_table);
+                const bool lane_hist = p->n_mat <= kLaneHistMats;
+                auto run = [&]() {
+                    return sonar_backward_table(table, n, c.b.grid, p->sp, p->n_srows, p->refl, p->n_mat,
+                                                reinterpret_cast<double *>(tb + c.b.off_part),
+                                                lane_hist ? reinterpret_cast<double *>(tb + c.b.off_refl_part)
+                                                          : nullptr,
+                                                p->g_sp, p->g_refl, st);
+                };
+                if (e == hipSuccess) e = run();
+                std::vector<float> g(ng);
+                if (e == hipSuccess)
+                    e = hipMemcpyAsync(g.data(), p->g_refl, sizeof(float) * p->n_mat, hipMemcpyDeviceToHost, st);
+                if (e == hipSuccess)
+                    e = hipMemcpyAsync(g.data() + p->n_mat, p->g_sp,
+                                       sizeof(float) * p->n_srows * OCEANSIM_SONAR_GRAD_WIDTH,
+                                       hipMemcpyDeviceToHost, st);
+                if (e == hipSuccess) e = hipStreamSynchronize(st);
+                if (e != hipSuccess) break;
+                if (k == 0) ref_g = g;
+                float peak = 0.0f;
+                for (float v : ref_g) peak = std::max(peak, std::fabs(v));
+                c.ok = true;
+                for (size_t i = 0; i < ng; ++i)
+                    if (!(std::fabs(g[i] - ref_g[i]) <= 1e-5f * std::max(std::fabs(ref_g[i]), 1e-3f * peak)))
+                        c.ok = false;
+                if (c.ok) c.us = time_us(run, st);
+            }
+            if (e != hipSuccess) rc = hip_fail(e, "autotune backward");
+            size_t bbest = 0;
+            for (size_t k = 1; k < bc.size(); ++k)
+                if (bc[k].ok && bc[k].us < bc[bbest].us) bbest = k;
+            chosen.bwd_tile_bins = bc[bbest].t.bwd_tile_bins;
+        }
+        if (tb) (void)hipFree(tb);
+    }
+    (void)hipStreamSynchronize(st);
+    (void)hipFree(tmp);
+    (void)hipFree(ref);
+    (void)hipFree(bad);
+    if (rc) return rc;
+    p->tune = chosen;
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tune[key] = chosen;
+    tune_save_locked();
+    return OCEANSIM_OK;
+}
+
+void free_plan(oceansim_plan *p) {
+    if (!p) return;
+    (void)hipDeviceSynchronize();
+    if (p->g_fwd) (void)hipGraphExecDestroy(p->g_fwd);
+    if (p->g_bwd) (void)hipGraphExecDestroy(p->g_bwd);
+    if (p->cap) (void)hipStreamDestroy(p->cap);
+    if (p->mem) (void)hipFree(p->mem);
+    if (p->stencil_mem) (void)hipFree(p->stencil_mem);
+    delete p;
+}
+
+int capture(oceansim_plan *p, bool backward, hipGraphExec_t *out) {
+    set_capturing(true);
+    hipError_t e = hipStreamBeginCapture(p->cap, hipStreamCaptureModeThreadLocal);
+    if (e == hipSuccess) {
+        hipError_t le = backward ? launch_backward(p, p->cap) : launch_forward(p, p->cap);
+        hipGraph_t g = nullptr;
+        e = hipStreamEndCapture(p->cap, &g);
+        if (e == hipSuccess) e = le;
+        if (e == hipSuccess) e = hipGraphInstantiate(out, g, nullptr, nullptr, 0);
+        if (g) (void)hipGraphDestroy(g);
+    }
+    set_capturing(false);
+    return e == hipSuccess ? OCEANSIM_OK : hip_fail(e, "graph capture");
+}
+
+}  // namespace
+
+extern "C" {
+
+int oceansim_plan_create(const oceansim_sonar_frame *sonar, int32_t n_sonar, const oceansim_uw_frame *camera,
+                         int32_t n_camera, const oceansim_sonar_params *sonar_params_dev, int32_t n_sonar_rows,
+                         const float *refl_dev, int32_t n_materials,
+                         const oceansim_water_params *water_params_dev, int32_t n_water_rows,
+                         float *grad_refl_dev, float *grad_sonar_params_dev, float *grad_water_params_dev,
+                         int32_t flags, void *stream, oceansim_plan **plan) {
+    if (!plan) return fail(OCEANSIM_E_INVALID_ARG, "plan is NULL");
+    *plan = nullptr;
+    if (n_sonar < 0 || n_camera < 0) return fail(OCEANSIM_E_INVALID_ARG, "negative frame count");
+    if ((n_sonar > 0 && !sonar) || (n_camera > 0 && !camera))
+        return fail(OCEANSIM_E_INVALID_ARG, "frames is NULL");
+    if (n_sonar + n_camera == 0) return fail(OCEANSIM_E_INVALID_ARG, "a plan needs at least one frame");
+    if (flags & ~(OCEANSIM_PLAN_BACKWARD | OCEANSIM_PLAN_GRAPH | OCEANSIM_PLAN_AUTOTUNE))
+        return fail(OCEANSIM_E_INVALID_ARG, "unknown plan flags 0x%x", flags);
+    const bool bwd = (flags & OCEANSIM_PLAN_BACKWARD) != 0;
+    if (n_sonar > 0 && (!sonar_params_dev || !refl_dev))
+        return fail(OCEANSIM_E_INVALID_ARG, "sonar parameters or reflectivities are NULL");
+    if (n_camera > 0 && !water_params_dev) return fail(OCEANSIM_E_INVALID_ARG, "water parameters are NULL");
+    if (bwd && n_sonar > 0 && (!grad_refl_dev || !grad_sonar_params_dev))
+        return fail(OCEANSIM_E_INVALID_ARG, "sonar gradient outputs are NULL");
+    if (bwd && n_camera > 0 && !grad_water_params_dev)
+        return fail(OCEANSIM_E_INVALID_ARG, "water gradient output is NULL");
+    hipStream_t st = static_cast<hipStream_t>(stream);
+
+    oceansim_plan *p = new oceansim_plan;
+    p->sonar.assign(sonar, sonar + n_sonar);
+    p->camera.assign(camera, camera + n_camera);
+    p->sp = sonar_params_dev;
+    p->n_srows = std::max(1, n_sonar_rows);
+    p->refl = refl_dev;
+    p->n_mat = n_materials;
+    p->wp = water_params_dev;
+    p->n_wrows = std::max(1, n_water_rows);
+    p->g_refl = grad_refl_dev;
+    p->g_sp = grad_sonar_params_dev;
+    p->g_wp = grad_water_params_dev;
+    p->flags = flags;
+
+    // validation of both directions before anything is allocated
+    int rc = OCEANSIM_OK;
+    if (n_sonar > 0) {
+        rc = plan_sonar(p->sonar.data(), n_sonar, n_sonar_rows, n_materials, false, p->sf, nullptr);
+        if (!rc && bwd) rc = plan_sonar(p->sonar.data(), n_sonar, n_sonar_rows, n_materials, true, p->sb, nullptr);
+    }
+    if (!rc && n_camera > 0) {
+        rc = plan_uw(p->camera.data(), n_camera, n_water_rows, false, p->uf, true);
+        if (!rc && bwd) rc = plan_uw(p->camera.data(), n_camera, n_water_rows, true, p->ub, true);
+    }
+    if (rc) {
+        delete p;
+        return rc;
+    }
+    // saved fan stencils for frames rendered with a fan whose gradient is read
+    size_t st_bytes = 0;
+    std::vector<size_t> st_off(n_sonar, (size_t)-1);
+    if (bwd)
+        for (int i = 0; i < n_sonar; ++i) {
+            auto &f = p->sonar[i];
+            if (f.fan && f.grad_fan && !f.fan_stencil) {
+                st_off[i] = st_bytes;
+                st_bytes += (oceansim_fan_stencil_size(f.fan_h, f.fan_w) + kWsAlign - 1) / kWsAlign * kWsAlign;
+            }
+        }
+    hipError_t e = hipSuccess;
+    if (st_bytes) {
+        e = hipMalloc(&p->stencil_mem, st_bytes);
+        if (e != hipSuccess) {
+            free_plan(p);
+            return hip_fail(e, "plan stencil memory");
+        }
+        for (int i = 0; i < n_sonar; ++i)
+            if (st_off[i] != (size_t)-1) p->sonar[i].fan_stencil = p->stencil_mem + st_off[i];
+    }
+    if ((flags & OCEANSIM_PLAN_AUTOTUNE) && n_sonar > 0) {
+        rc = autotune(p, st);
+        if (rc) {
+            free_plan(p);
+            return rc;
+        }
+    }
+    // final shapes
+    if (n_sonar > 0) {
+        rc = plan_sonar(p->sonar.data(), n_sonar, n_sonar_rows, n_materials, false, p->sf, &p->tune, true);
+        if (!rc && bwd) rc = plan_sonar(p->sonar.data(), n_sonar, n_sonar_rows, n_materials, true, p->sb, &p->tune, true);
+        if (rc) {
+            free_plan(p);
+            return rc;
+        }
+    }
+    auto up = [](size_t v) { return (v + kWsAlign - 1) / kWsAlign * kWsAlign; };
+    const size_t b_sf = n_sonar ? up(p->sf.bytes) : 0, b_sb = (n_sonar && bwd) ? up(p->sb.bytes) : 0;
+    const size_t b_uf = n_camera ? up(p->uf.bytes) : 0, b_ub = (n_camera && bwd) ? up(p->ub.bytes) : 0;
+    e = hipMalloc(&p->mem, std::max<size_t>(b_sf + b_sb + b_uf + b_ub, kWsAlign));
+    if (e != hipSuccess) {
+        free_plan(p);
+        return hip_fail(e, "plan memory");
+    }
+    p->ws_sf = p->mem;
+    p->ws_sb = p->ws_sf + b_sf;
+    p->ws_uf = p->ws_sb + b_sb;
+    p->ws_ub = p->ws_uf + b_uf;
+    if (n_sonar > 0) {
+        carve_sonar(p->sf, p->ws_sf, false);
+        e = upload_table(p->sf.dev, p->ws_sf, p->sf.off_table, st);
+        if (e == hipSuccess && bwd) {
+            carve_sonar(p->sb, p->ws_sb, true);
+            e = upload_table(p->sb.dev, p->ws_sb, p->sb.off_table, st);
+        }
+    }
+    if (e == hipSuccess && n_camera > 0) {
+        e = upload_table(p->uf.dev, p->ws_uf, p->uf.off_table, st);
+        if (e == hipSuccess && bwd) e = upload_table(p->ub.dev, p->ws_ub, p->ub.off_table, st);
+    }
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) {
+        free_plan(p);
+        return hip_fail(e, "plan tables");
+    }
+    if (flags & OCEANSIM_PLAN_GRAPH) {
+        e = hipStreamCreateWithFlags(&p->cap, hipStreamNonBlocking);
+        if (e != hipSuccess) {
+            free_plan(p);
+            return hip_fail(e, "capture stream");
+        }
+        rc = capture(p, false, &p->g_fwd);
+        if (!rc && bwd) rc = capture(p, true, &p->g_bwd);
+        if (rc) {
+            free_plan(p);
+            return rc;
+        }
+    }
+    *plan = p;
+    return ok();
+}
+
+int oceansim_plan_forward(oceansim_plan *p, void *stream) {
+    if (!p) return fail(OCEANSIM_E_INVALID_ARG, "plan is NULL");
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    hipError_t e = p->g_fwd ? hipGraphLaunch(p->g_fwd, st) : launch_forward(p, st);
+    return e == hipSuccess ? ok() : hip_fail(e, "plan forward");
+}
+
+int oceansim_plan_backward(oceansim_plan *p, void *stream) {
+    if (!p) return fail(OCEANSIM_E_INVALID_ARG, "plan is NULL");
+    if (!(p->flags & OCEANSIM_PLAN_BACKWARD))
+        return fail(OCEANSIM_E_INVALID_ARG, "plan was created without OCEANSIM_PLAN_BACKWARD");
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    hipError_t e = p->g_bwd ? hipGraphLaunch(p->g_bwd, st) : launch_backward(p, st);
+    return e == hipSuccess ? ok() : hip_fail(e, "plan backward");
+}
+
+int oceansim_plan_shape(const oceansim_plan *p, int32_t shape[4]) {
+    if (!p || !shape) return fail(OCEANSIM_E_INVALID_ARG, "NULL argument");
+    shape[0] = p->sf.grid.max_tile_bins;
+    shape[1] = p->sf.grid.chunk;
+    shape[2] = p->sb.grid.max_tile_bins_b;
+    shape[3] = p->g_fwd ? 1 : 0;
+    return ok();
+}
+
+int oceansim_plan_destroy(oceansim_plan *p) {
+    free_plan(p);
+    return ok();
+}
+
+}  // extern "C"

@@ -195,3 +195,37 @@ def test_uw_backward_rejects():
     f = _uw(lib, grad_out=FAKE)
     assert so.oceansim_uw_form_backward(C.pointer(f), 1, FAKE, 1, None, FAKE, 1 << 30, None) == -1
     assert so.oceansim_uw_form_backward(C.pointer(f), 1, FAKE, 1, FAKE, FAKE, 8, None) == -3
+
+
+def test_plan_rejections():
+    lib = _lib()
+    so = lib.lib
+    out = C.c_void_p(FAKE)
+    good = _frame(lib, grad_fan=FAKE)
+    cam = _uw(lib, grad_out=FAKE)
+
+    def create(sonar=(good,), camera=(), sp=FAKE, rows=1, refl=FAKE, n_mat=8, wp=FAKE, wrows=1,
+               g_refl=FAKE, g_sp=FAKE, g_wp=FAKE, flags=1, plan=True):
+        s = (lib.SonarFrame * max(1, len(sonar)))(*sonar)
+        c = (lib.UwFrame * max(1, len(camera)))(*camera)
+        return so.oceansim_plan_create(s if sonar else None, len(sonar), c if camera else None, len(camera),
+                                       sp, rows, refl, n_mat, wp, wrows, g_refl, g_sp, g_wp, flags, None,
+                                       C.byref(out) if plan else None)
+
+    assert create(plan=False) == -1
+    assert create(sonar=(), camera=()) == -1                          # nothing to plan
+    assert create(flags=8) == -1                                      # unknown flag
+    assert create(sp=None) == -1 and create(refl=None) == -1
+    assert create(g_refl=None) == -1 and create(g_sp=None) == -1      # backward without outputs
+    assert create(sonar=(), camera=(cam,), wp=None) == -1
+    assert create(sonar=(), camera=(cam,), g_wp=None) == -1
+    assert out.value is None                                          # cleared on error
+    assert create(sonar=(good, _frame(lib, n_range=0))) == -2
+    assert "frame 1" in lib.last_error()
+    assert create(sonar=(_frame(lib, param_row=3),)) == -1
+    assert create(sonar=(), camera=(_uw(lib, H=0, grad_out=FAKE),)) == -2
+    assert create(sonar=(), camera=(_uw(lib),)) == -1                 # backward needs grad_out
+    assert so.oceansim_plan_forward(None, None) == -1
+    assert so.oceansim_plan_backward(None, None) == -1
+    assert so.oceansim_plan_shape(None, (C.c_int32 * 4)()) == -1
+    assert so.oceansim_plan_destroy(None) == 0

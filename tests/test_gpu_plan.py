@@ -1,0 +1,287 @@
+"""GPU parity of plans (frames prepared once, launched many times, replayed
+from HIP graphs) and of the launch-shape autotuner, through the C ABI.
+
+Every replay is checked against the FP64 oracle on that replay's inputs (bins
+bit-exact, images and gradients to the tolerances of the plain entry points)
+and against the plain entry points run eagerly on the same device buffers.
+"""
+import json
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle import SonarConfig
+import workloads as W
+from _tol import assert_grad_cond, assert_image_close
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(msg):
+    print("[case] " + msg, flush=True)
+    sys.stdout.flush()
+
+
+def _specs(it):
+    """Two sonar frames of fixed geometry whose parameters change with `it`."""
+    common = dict(r_min=0.5, r_max=10.0, sigma_phi=0.3 + 0.05 * it, sigma_sa=0.15, sigma_sm=0.1 + 0.02 * it,
+                  seed_lo=17, gamma_k=4)
+    return [
+        W.SonarSpec(n_range=48, n_azimuth=40, fan_h=40, fan_w=72, alpha=0.1 + 0.02 * it, gain=1.1 + 0.1 * it,
+                    speckle_mode=W.SPECKLE_GAMMA, frame_id=3, **common),
+        W.SonarSpec(n_range=61, n_azimuth=53, fan_h=51, fan_w=91, alpha=0.07 + 0.01 * it, gain=0.9 + 0.05 * it,
+                    speckle_mode=W.SPECKLE_PAPER, frame_id=4, **common),
+    ]
+
+
+N_RETURNS = (3000, 4100)
+
+
+def _inputs(it):
+    st = W.Stream(900 + it, 1)
+    specs = _specs(it)
+    frames = [W.SonarFrame(s, W.make_hits(st, s, n, n_materials=6, outside_frac=0.05))
+              for s, n in zip(specs, N_RETURNS)]
+    refl = frames[0].hits.refl
+    for f in frames:
+        f.hits.refl = refl
+    gpol = [W.loss_weights((901, 10 * it + k), (s.n_range, s.n_azimuth)) for k, s in enumerate(specs)]
+    gfan = [W.loss_weights((902, 10 * it + k), (s.fan_h, s.fan_w)) for k, s in enumerate(specs)]
+    cams = [W.make_camera(st, 45, 77, water_row=0), W.make_camera(st, 16, 9, water_row=1)]
+    waters = [W.make_water(st), W.make_water(st)]
+    gout = [W.loss_weights((903, 10 * it + k), c.J.shape) for k, c in enumerate(cams)]
+    return frames, refl, gpol, gfan, cams, waters, gout
+
+
+class _Bufs:
+    """Device buffers that a plan keeps; refilled in place for every replay."""
+
+    def __init__(self, osm, torch, it0):
+        frames, refl, _, _, cams, waters, _ = _inputs(it0)
+        self.geoms = [osm.SonarGeometry.from_spec(f.spec, param_row=k) for k, f in enumerate(frames)]
+        self.hits = [osm.DeviceHits.from_host(f.hits) for f in frames]
+        self.params = osm.sonar_params([osm.sonar_params_from_spec(f.spec) for f in frames])
+        self.refl = torch.as_tensor(refl).cuda()
+        self.Js = [torch.as_tensor(c.J).cuda() for c in cams]
+        self.ds = [torch.as_tensor(c.depth).cuda() for c in cams]
+        self.water = osm.water_params([(w.beta_d, w.beta_b, w.b_inf) for w in waters])
+        self.rows = [c.water_row for c in cams]
+
+    def fill(self, osm, torch, it):
+        frames, refl, gpol, gfan, cams, waters, gout = _inputs(it)
+        for h, f in zip(self.hits, frames):
+            src = osm.DeviceHits.from_host(f.hits)
+            for name in ("x", "y", "z", "nx", "ny", "nz", "mat"):
+                getattr(h, name).copy_(getattr(src, name))
+        self.params.copy_(osm.sonar_params([osm.sonar_params_from_spec(f.spec) for f in frames]))
+        self.refl.copy_(torch.as_tensor(refl))
+        for J, d, c in zip(self.Js, self.ds, cams):
+            J.copy_(torch.as_tensor(c.J))
+            d.copy_(torch.as_tensor(c.depth))
+        self.water.copy_(osm.water_params([(w.beta_d, w.beta_b, w.b_inf) for w in waters]))
+        return frames, refl, gpol, gfan, cams, waters, gout
+
+
+def _check_against_oracle(plan, frames, refl, gpol, gfan, cams, waters, gout, what):
+    # forward
+    for k, (f, o) in enumerate(zip(frames, plan.sonar_out)):
+        want = oracle.sonar_forward(SonarConfig.from_spec(f.spec), f.hits, refl)
+        np.testing.assert_array_equal(o["bins"].cpu().numpy(), want["bins"], err_msg="%s bins %d" % (what, k))
+        assert_image_close(o["polar"].cpu().numpy(), want["out"], "%s polar %d" % (what, k))
+        assert_image_close(o["fan"].cpu().numpy(), want["fan"], "%s fan %d" % (what, k), mask=~want["ambiguous"])
+    for k, (c, o) in enumerate(zip(cams, plan.camera_out)):
+        w = waters[c.water_row]
+        want = oracle.uw_forward(c.J, c.depth, w.beta_d, w.beta_b, w.b_inf)
+        assert_image_close(o["out"].cpu().numpy(), want, "%s camera %d" % (what, k))
+    # backward
+    g_refl = plan.grad_refl.cpu().numpy().astype(np.float64)
+    g_par = plan.grad_sonar_params.cpu().numpy().astype(np.float64)
+    o_refl = np.zeros(refl.shape[0])
+    c_refl = np.zeros(refl.shape[0])
+    for k, f in enumerate(frames):
+        a, b, _, ca, cb = oracle.sonar_backward(SonarConfig.from_spec(f.spec), f.hits, refl, gpol[k], gfan[k],
+                                                with_abs=True)
+        o_refl += a
+        c_refl += ca
+        assert_grad_cond(g_par[k, :5], b, cb, what="%s sonar params row %d" % (what, k))
+        assert np.all(g_par[k, 5:] == 0)
+    assert_grad_cond(g_refl, o_refl, c_refl, what="%s refl" % what)
+    g_w = plan.grad_water.cpu().numpy().astype(np.float64)
+    for r, w in enumerate(waters):
+        o_par, c_par = np.zeros(9), np.zeros(9)
+        bd, bb, bi = (x.astype(np.float64) for x in (w.beta_d, w.beta_b, w.b_inf))
+        for k, c in enumerate(cams):
+            if c.water_row != r:
+                continue
+            p, _, _, cp = oracle.uw_backward(c.J, c.depth, bd, bb, bi, gout[k], with_abs=True)
+            o_par += p
+            c_par += cp
+        assert_grad_cond(g_w[r], o_par, c_par, what="%s water row %d" % (what, r))
+
+
+@pytest.mark.parametrize("graph", [False, True])
+def test_plan_replays_track_new_inputs(graph):
+    """One plan, several launches; between launches the hits, reflectivities,
+    parameters, images and loss gradients change in place and eager work of
+    the program (plain entry-point calls, torch kernels, synchronisations) runs
+    on the same stream."""
+    import torch
+    import paper_2503_01074_amd as osm
+    _say("plan replays, graph %s" % graph)
+    B = _Bufs(osm, torch, 0)
+    plan = osm.Plan(list(zip(B.geoms, B.hits)), list(zip(B.Js, B.ds, B.rows)), sonar_params=B.params,
+                    refl=B.refl, water=B.water, backward=True, graph=graph, bins=True)
+    assert plan.shape()["graph"] == graph
+    for it in range(4):
+        _say("plan replay %d (graph %s)" % (it, graph))
+        frames, refl, gpol, gfan, cams, waters, gout = B.fill(osm, torch, it)
+        for o, gp, gf in zip(plan.sonar_out, gpol, gfan):
+            o["grad_polar"].copy_(torch.as_tensor(gp))
+            o["grad_fan"].copy_(torch.as_tensor(gf))
+        for o, g in zip(plan.camera_out, gout):
+            o["grad_out"].copy_(torch.as_tensor(g))
+        # unrelated eager work queued before the replay
+        junk = torch.randn(1 << 16, device="cuda").cumsum(0)
+        plan.forward()
+        plan.backward()
+        torch.cuda.synchronize()
+        # the plain entry points, eagerly, on the same buffers
+        eager = osm.render_sonar(B.geoms, B.hits, B.params, B.refl, bins=True, save_stencil=True)
+        e_refl, e_par = osm.render_sonar_backward(
+            B.geoms, B.hits, B.params, B.refl, [o["grad_polar"] for o in plan.sonar_out],
+            [o["grad_fan"] for o in plan.sonar_out], [o.get("stencil") for o in eager])
+        e_cam = osm.uw_form(B.Js, B.ds, B.water, B.rows)
+        e_w, _, _ = osm.uw_form_backward(B.Js, B.ds, B.water, [o["grad_out"] for o in plan.camera_out], B.rows,
+                                         want_image_grads=False)
+        torch.cuda.synchronize()
+        assert torch.isfinite(junk).all()
+        for k, (o, e) in enumerate(zip(plan.sonar_out, eager)):
+            assert torch.equal(o["bins"], e["bins"])
+            assert_image_close(o["polar"].cpu().numpy(), e["polar"].cpu().numpy(), "eager polar %d" % k, rtol=1e-6)
+            assert_image_close(o["fan"].cpu().numpy(), e["fan"].cpu().numpy(), "eager fan %d" % k, rtol=1e-6)
+        for k, (o, e) in enumerate(zip(plan.camera_out, e_cam)):
+            assert torch.equal(o["out"], e)
+        # the backward pass reduces in a fixed order: plan and plain agree bit for bit
+        assert torch.equal(plan.grad_refl, e_refl)
+        assert torch.equal(plan.grad_sonar_params, e_par)
+        assert torch.equal(plan.grad_water, e_w)
+        _check_against_oracle(plan, frames, refl, gpol, gfan, cams, waters, gout, "replay %d" % it)
+    plan.close()
+
+
+def test_plan_single_frames_and_camera_only():
+    """Plans over one sonar frame (polar only, no backward) and over camera
+    frames alone."""
+    import torch
+    import paper_2503_01074_amd as osm
+    _say("plan: one polar-only sonar frame; camera-only plan")
+    frames, refl, _, _, cams, waters, _ = _inputs(7)
+    f = frames[0]
+    g = osm.SonarGeometry.from_spec(f.spec)
+    h = osm.DeviceHits.from_host(f.hits)
+    params = osm.sonar_params([osm.sonar_params_from_spec(f.spec)])
+    plan = osm.Plan([(g, h)], sonar_params=params, refl=torch.as_tensor(refl).cuda(), fan=False, graph=True)
+    for _ in range(3):
+        plan.forward()
+        torch.cuda.synchronize()
+        want = oracle.sonar_forward(SonarConfig.from_spec(f.spec), f.hits, refl)
+        assert "fan" not in plan.sonar_out[0]
+        assert_image_close(plan.sonar_out[0]["polar"].cpu().numpy(), want["out"], "single polar")
+    plan.close()
+    Js = [torch.as_tensor(c.J).cuda() for c in cams]
+    ds = [torch.as_tensor(c.depth).cuda() for c in cams]
+    water = osm.water_params([(w.beta_d, w.beta_b, w.b_inf) for w in waters])
+    plan = osm.Plan(camera=list(zip(Js, ds, [c.water_row for c in cams])), water=water, graph=True,
+                    backward=True, image_grads=True)
+    gos = [W.loss_weights((55, k), c.J.shape) for k, c in enumerate(cams)]
+    for o, gg in zip(plan.camera_out, gos):
+        o["grad_out"].copy_(torch.as_tensor(gg))
+    for _ in range(3):
+        plan.forward()
+        plan.backward()
+        torch.cuda.synchronize()
+        for k, c in enumerate(cams):
+            w = waters[c.water_row]
+            bd, bb, bi = (x.astype(np.float64) for x in (w.beta_d, w.beta_b, w.b_inf))
+            assert_image_close(plan.camera_out[k]["out"].cpu().numpy(),
+                               oracle.uw_forward(c.J, c.depth, w.beta_d, w.beta_b, w.b_inf), "camera %d" % k)
+            _, oj, _, _ = oracle.uw_backward(c.J, c.depth, bd, bb, bi, gos[k], with_abs=True)
+            assert_image_close(plan.camera_out[k]["grad_J"].cpu().numpy(), oj, "grad J %d" % k)
+    plan.close()
+
+
+def test_plan_backward_requires_flag():
+    import torch
+    import paper_2503_01074_amd as osm
+    _say("plan without backward rejects a backward launch")
+    frames, refl, _, _, _, _, _ = _inputs(8)
+    f = frames[0]
+    plan = osm.Plan([(osm.SonarGeometry.from_spec(f.spec), osm.DeviceHits.from_host(f.hits))],
+                    sonar_params=osm.sonar_params([osm.sonar_params_from_spec(f.spec)]),
+                    refl=torch.as_tensor(refl).cuda())
+    with pytest.raises(osm.OceansimError):
+        plan.backward()
+    plan.close()
+
+
+def test_autotune_agrees_and_caches(tmp_path, monkeypatch):
+    """The autotuner picks a shape from its candidate set whose outputs agree
+    with the oracle, records it in the cache file, and a second plan of the same
+    size class reuses it."""
+    import torch
+    import paper_2503_01074_amd as osm
+    cache = tmp_path / "tune.json"
+    monkeypatch.setenv("OCEANSIM_TUNE_CACHE", str(cache))
+    _say("autotune: two 60k-return frames, 256x128 bins, 256x512 fans")
+    st = W.Stream(910, 1)
+    specs = [W.SonarSpec(r_min=0.5, r_max=30.0, n_range=256, n_azimuth=128, fan_h=256, fan_w=512,
+                         speckle_mode=W.SPECKLE_GAMMA, seed_lo=9, frame_id=k) for k in range(2)]
+    frames = [W.SonarFrame(s, W.make_hits(st, s, 60000, n_materials=8)) for s in specs]
+    refl = frames[0].hits.refl
+    gpol = [W.loss_weights((911, k), (s.n_range, s.n_azimuth)) for k, s in enumerate(specs)]
+    gfan = [W.loss_weights((912, k), (s.fan_h, s.fan_w)) for k, s in enumerate(specs)]
+    geoms = [osm.SonarGeometry.from_spec(s, param_row=0) for s in specs]
+    hits = [osm.DeviceHits.from_host(f.hits) for f in frames]
+    params = osm.sonar_params([osm.sonar_params_from_spec(specs[0])])
+    refl_d = torch.as_tensor(refl).cuda()
+
+    def make():
+        p = osm.Plan(list(zip(geoms, hits)), sonar_params=params, refl=refl_d, backward=True, graph=True,
+                     autotune=True, bins=True)
+        for o, gp, gf in zip(p.sonar_out, gpol, gfan):
+            o["grad_polar"].copy_(torch.as_tensor(gp))
+            o["grad_fan"].copy_(torch.as_tensor(gf))
+        return p
+
+    plan = make()
+    shape = plan.shape()
+    assert shape["fwd_tile_bins"] <= 4096 and shape["chunk"] in (512, 1024, 2048, 4096)
+    assert shape["bwd_tile_bins"] <= 4096
+    plan.forward()
+    plan.backward()
+    torch.cuda.synchronize()
+    o_refl, c_refl = np.zeros(refl.shape[0]), np.zeros(refl.shape[0])
+    o_par, c_par = np.zeros(5), np.zeros(5)
+    for k, f in enumerate(frames):
+        want = oracle.sonar_forward(SonarConfig.from_spec(f.spec), f.hits, refl)
+        o = plan.sonar_out[k]
+        np.testing.assert_array_equal(o["bins"].cpu().numpy(), want["bins"])
+        assert_image_close(o["polar"].cpu().numpy(), want["out"], "tuned polar %d" % k)
+        assert_image_close(o["fan"].cpu().numpy(), want["fan"], "tuned fan %d" % k, mask=~want["ambiguous"])
+        a, b, _, ca, cb = oracle.sonar_backward(SonarConfig.from_spec(f.spec), f.hits, refl, gpol[k], gfan[k],
+                                                with_abs=True)
+        o_refl += a
+        c_refl += ca
+        o_par += b
+        c_par += cb
+    assert_grad_cond(plan.grad_refl.cpu().numpy(), o_refl, c_refl, what="tuned refl")
+    assert_grad_cond(plan.grad_sonar_params.cpu().numpy()[0, :5], o_par, c_par, what="tuned params")
+    entries = json.loads(cache.read_text())
+    assert len(entries) >= 1 and all(len(v) == 3 for v in entries.values())
+    assert any(k.startswith("gfx") for k in entries)
+    again = make()
+    assert again.shape() == shape
+    plan.close()
+    again.close()
