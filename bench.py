@@ -114,6 +114,17 @@ class RealTimeStep:
         self.g_w = torch.empty(1, _lib.WATER_GRAD_WIDTH, device=dev)
         self.stream = torch.cuda.current_stream(dev).cuda_stream
         self.P = lambda t: t.data_ptr()
+        # the same step as a plan: frame tables uploaded once, forward and
+        # backward each replayed from a captured HIP graph
+        self.plans = {}
+        for name, graph in (("plan", False), ("graph", True)):
+            pl = osm.Plan([(self.geom, self.hits)], [(self.J, self.d, 0)], sonar_params=self.params,
+                          refl=self.refl, water=self.water, backward=True, graph=graph, autotune=True,
+                          image_grads=True)
+            pl.sonar_out[0]["grad_polar"].copy_(self.gpol)
+            pl.sonar_out[0]["grad_fan"].copy_(self.gfan)
+            pl.camera_out[0]["grad_out"].copy_(self.gimg)
+            self.plans[name] = pl
 
     def sonar_forward(self, train=False):
         L, P = self.lib, self.P
@@ -144,6 +155,14 @@ class RealTimeStep:
         self.uw_forward()
         self.sonar_backward()
         self.uw_backward()
+
+    def plan_forward(self, name):
+        self.lib.oceansim_plan_forward(self.plans[name].handle, self.stream)
+
+    def plan_step(self, name):
+        h = self.plans[name].handle
+        self.lib.oceansim_plan_forward(h, self.stream)
+        self.lib.oceansim_plan_backward(h, self.stream)
 
     def algorithmic_bytes(self):
         """Bytes each kernel must move per launch by the per-unit figures of
@@ -181,10 +200,18 @@ def event_time(torch, fn, reps):
     return a.elapsed_time(b) / 1e3 / reps
 
 
+def median_time(torch, fn, steps, warmup, repeats=5):
+    """Median over `repeats` of the mean wall-clock time of `steps` calls."""
+    ts = sorted(timed(torch, fn, steps, warmup if k == 0 else 1) for k in range(repeats))
+    return ts[len(ts) // 2]
+
+
 def batched_legs(torch, dev, steps):
-    """Ragged batch of 256 sonar frames (forward, one call) and a differentiable
-    batch of 32 sonar + 32 camera frames (forward + backward, one call per
-    entry point), with descriptors and buffers prepared before timing."""
+    """Ragged batch of 256 sonar frames (forward) and a differentiable batch of
+    32 sonar + 32 camera frames (forward + backward): one ABI call per frame
+    (plain), one call per entry point for the whole batch (batched), and a
+    plan replayed from HIP graphs, with descriptors and buffers prepared
+    before timing."""
     import numpy as np
     import paper_2503_01074_amd as osm
     from paper_2503_01074_amd import _lib
@@ -194,6 +221,7 @@ def batched_legs(torch, dev, steps):
     stream = torch.cuda.current_stream(dev).cuda_stream
     P = lambda t: t.data_ptr()
     out = {}
+    reps = max(5, steps // 10)
 
     frames = W.sonar_c3()
     tables, base, hits = [], 0, []
@@ -205,23 +233,46 @@ def batched_legs(torch, dev, steps):
         h.mat = torch.as_tensor(mat, device=dev)
         hits.append(h)
     refl = torch.as_tensor(np.concatenate(tables), device=dev)
+    n_mat = int(refl.numel())
     geoms = [osm.SonarGeometry.from_spec(f.spec, param_row=i) for i, f in enumerate(frames)]
     params = osm.sonar_params([osm.sonar_params_from_spec(f.spec) for f in frames], dev)
     polars = [torch.empty(g.n_range, g.n_azimuth, device=dev) for g in geoms]
     fans = [torch.empty(g.fan_h, g.fan_w, device=dev) for g in geoms]
-    arr = (_lib.SonarFrame * len(frames))(*[_sonar_struct(g, h, p, q) for g, h, p, q in
-                                            zip(geoms, hits, polars, fans)])
-    need = _lib.oceansim_sonar_workspace_size(arr, int(refl.numel()), False)
+    structs = [_sonar_struct(g, h, p, q) for g, h, p, q in zip(geoms, hits, polars, fans)]
+    arr = (_lib.SonarFrame * len(frames))(*structs)
+    need = _lib.oceansim_sonar_workspace_size(arr, n_mat, False)
     ws = torch.empty(need, dtype=torch.uint8, device=dev)
     n_ret = sum(f.hits.n for f in frames)
+    n_fr = len(frames)
 
     def c3():
-        _lib.oceansim_sonar_render(arr, P(params), len(frames), P(refl), int(refl.numel()), P(ws), need, stream)
-    t = timed(torch, c3, max(5, steps // 10), 3)
-    out["batched_c3_fwd"] = {"frames": len(frames), "returns": n_ret, "ms": t * 1e3,
-                             "frames_per_s": len(frames) / t, "returns_per_s": n_ret / t}
-    log("C3 batched forward: %.3f ms for %d frames" % (t * 1e3, len(frames)))
-    del hits, polars, fans, ws, arr
+        _lib.oceansim_sonar_render(arr, P(params), n_fr, P(refl), n_mat, P(ws), need, stream)
+
+    def c3_plain():
+        for sf in structs:
+            _lib.oceansim_sonar_render(sf, P(params), n_fr, P(refl), n_mat, P(ws), need, stream)
+
+    t = median_time(torch, c3, reps, 3)
+    t_plain = median_time(torch, c3_plain, max(3, reps // 4), 1)
+    _lib.oceansim_trace_enable(True)
+    for _ in range(3):
+        c3()
+    torch.cuda.synchronize()
+    tr = _lib.oceansim_trace_summary()
+    _lib.oceansim_trace_enable(False)
+    plan = osm.Plan(list(zip(geoms, hits)), sonar_params=params, refl=refl, graph=True, autotune=True)
+    t_graph = median_time(torch, plan.forward, reps, 3)
+    shape = plan.shape()
+    plan.close()
+    out["batched_c3_fwd"] = {"frames": n_fr, "returns": n_ret, "ms": t * 1e3,
+                             "frames_per_s": n_fr / t, "returns_per_s": n_ret / t,
+                             "plain_ms": t_plain * 1e3, "plain_frames_per_s": n_fr / t_plain,
+                             "graph_autotuned_ms": t_graph * 1e3, "graph_frames_per_s": n_fr / t_graph,
+                             "graph_returns_per_s": n_ret / t_graph, "autotuned_shape": shape,
+                             "kernels_us": {k: round(us / calls, 1) for k, (calls, us) in tr.items()}}
+    log("C3 forward, 256 frames: batched call %.3f ms, one call per frame %.3f ms, autotuned graph plan %.3f ms %s"
+        % (t * 1e3, t_plain * 1e3, t_graph * 1e3, shape))
+    del hits, polars, fans, ws, arr, structs
     torch.cuda.empty_cache()
 
     frames = W.sonar_c4()
@@ -233,13 +284,14 @@ def batched_legs(torch, dev, steps):
     params = osm.sonar_params([osm.sonar_params_from_spec(frames[0].spec)], dev)
     polars = [torch.empty(g.n_range, g.n_azimuth, device=dev) for g in geoms]
     fans = [torch.empty(g.fan_h, g.fan_w, device=dev) for g in geoms]
+    stencils = [osm.api.fan_stencil_buffer(g, dev) for g in geoms]
     gp = [torch.as_tensor(W.loss_weights((202, k), (g.n_range, g.n_azimuth)), device=dev)
           for k, g in enumerate(geoms)]
     gf = [torch.as_tensor(W.loss_weights((203, k), (g.fan_h, g.fan_w)), device=dev) for k, g in enumerate(geoms)]
-    sf = (_lib.SonarFrame * len(frames))(*[_sonar_struct(g, h, p, q) for g, h, p, q in
-                                           zip(geoms, hits, polars, fans)])
-    sb = (_lib.SonarFrame * len(frames))(*[_sonar_struct(g, h, grad_polar=a, grad_fan=b) for g, h, a, b in
-                                           zip(geoms, hits, gp, gf)])
+    sf = (_lib.SonarFrame * len(frames))(*[_sonar_struct(g, h, p, q, stencil=sv) for g, h, p, q, sv in
+                                           zip(geoms, hits, polars, fans, stencils)])
+    sb = (_lib.SonarFrame * len(frames))(*[_sonar_struct(g, h, grad_polar=a, grad_fan=b, stencil=sv)
+                                           for g, h, a, b, sv in zip(geoms, hits, gp, gf, stencils)])
     ws_f = torch.empty(_lib.oceansim_sonar_workspace_size(sf, n_mat, False), dtype=torch.uint8, device=dev)
     ws_b = torch.empty(_lib.oceansim_sonar_workspace_size(sb, n_mat, True), dtype=torch.uint8, device=dev)
     g_refl = torch.empty(n_mat, device=dev)
@@ -259,6 +311,7 @@ def batched_legs(torch, dev, steps):
     ws_ub = torch.empty(max(256, _lib.oceansim_uw_workspace_size(ub, True)), dtype=torch.uint8, device=dev)
     g_w = torch.empty(1, _lib.WATER_GRAD_WIDTH, device=dev)
     n_ret = sum(f.hits.n for f in frames)
+    n_fr = len(frames) + len(cams)
 
     def c4_fwd():
         _lib.oceansim_sonar_render(sf, P(params), 1, P(refl), n_mat, P(ws_f), ws_f.numel(), stream)
@@ -270,13 +323,29 @@ def batched_legs(torch, dev, steps):
                                             ws_b.numel(), stream)
         _lib.oceansim_uw_form_backward(ub, P(water), 1, P(g_w), P(ws_ub), ws_ub.numel(), stream)
 
-    tf = timed(torch, c4_fwd, max(5, steps // 5), 3)
-    ts = timed(torch, c4_step, max(5, steps // 5), 3)
+    tf = median_time(torch, c4_fwd, max(5, steps // 5), 3)
+    ts = median_time(torch, c4_step, max(5, steps // 5), 3)
+    plan = osm.Plan(list(zip(geoms, hits)), list(zip(Js, ds, [0] * len(cams))), sonar_params=params, refl=refl,
+                    water=water, backward=True, graph=True, image_grads=True)
+    for o, a, b in zip(plan.sonar_out, gp, gf):
+        o["grad_polar"].copy_(a)
+        o["grad_fan"].copy_(b)
+    for o, g in zip(plan.camera_out, gi):
+        o["grad_out"].copy_(g)
+
+    def c4_graph_step():
+        plan.forward()
+        plan.backward()
+    tgf = median_time(torch, plan.forward, max(5, steps // 5), 3)
+    tgs = median_time(torch, c4_graph_step, max(5, steps // 5), 3)
+    plan.close()
     out["batched_c4"] = {"sonar_frames": len(frames), "camera_frames": len(cams), "returns": n_ret,
                          "fwd_ms": tf * 1e3, "fwd_bwd_ms": ts * 1e3,
-                         "fwd_bwd_frames_per_s": (len(frames) + len(cams)) / ts,
-                         "fwd_bwd_returns_per_s": n_ret / ts}
-    log("C4 batched: fwd %.3f ms, fwd+bwd %.3f ms" % (tf * 1e3, ts * 1e3))
+                         "fwd_bwd_frames_per_s": n_fr / ts, "fwd_bwd_returns_per_s": n_ret / ts,
+                         "graph_fwd_ms": tgf * 1e3, "graph_fwd_bwd_ms": tgs * 1e3,
+                         "graph_fwd_bwd_frames_per_s": n_fr / tgs}
+    log("C4 batched: fwd %.3f ms, fwd+bwd %.3f ms; graph plan fwd %.3f ms, fwd+bwd %.3f ms"
+        % (tf * 1e3, ts * 1e3, tgf * 1e3, tgs * 1e3))
     return out
 
 
@@ -330,7 +399,15 @@ def main():
     t_step = timed(torch, rt.step, args.steps, args.warmup)
     t_fwd = timed(torch, rt.forward, args.steps, args.warmup)
     t_sonar_fwd = timed(torch, rt.sonar_forward, args.steps, args.warmup)
-    log("step %.3f ms, forward %.3f ms, sonar forward %.3f ms" % (t_step * 1e3, t_fwd * 1e3, t_sonar_fwd * 1e3))
+    log("plain entry points: step %.3f ms, forward %.3f ms, sonar forward %.3f ms"
+        % (t_step * 1e3, t_fwd * 1e3, t_sonar_fwd * 1e3))
+    plan_t = {}
+    for name in rt.plans:
+        ts = timed(torch, lambda: rt.plan_step(name), args.steps, args.warmup)
+        tf = timed(torch, lambda: rt.plan_forward(name), args.steps, args.warmup)
+        plan_t[name] = {"step_ms": ts * 1e3, "returns_per_s": rt.n_returns / ts, "fwd_ms": tf * 1e3,
+                        "fwd_returns_per_s": rt.n_returns / tf, "shape": rt.plans[name].shape()}
+        log("%s: step %.3f ms, forward %.3f ms, shape %s" % (name, ts * 1e3, tf * 1e3, rt.plans[name].shape()))
 
     # per-entry-point GPU durations from events on the launch stream
     reps = max(20, args.steps)
@@ -392,6 +469,7 @@ def main():
         "fwd_frames_per_s": 1.0 / t_fwd,
         "sonar_fwd_only_frames_per_s": 1.0 / t_sonar_fwd,
         "camera_mpx_per_s_fwd_bwd": rt.npix / t_step / 1e6,
+        "plans": plan_t,
         "entry_point_us": {k: round(v * 1e6, 2) for k, v in parts.items()},
         "kernels": kernel_table,
         "roofline": roofline,

@@ -190,6 +190,7 @@ int plan_sonar(const oceansim_sonar_frame *frames, int n_frames, int n_param_row
     P.off_pairs.assign(n_frames, 0);
     P.off_chunk_off.assign(n_frames, 0);
     P.off_polar.assign(n_frames, (size_t)-1);
+    P.off_cols.assign(n_frames, (size_t)-1);
     P.off_grad_img.assign(n_frames, 0);
     int bin_blocks = 0, tile_blocks = 0, tile_b_blocks = 0, fan_blocks = 0, ret_blocks = 0;
     for (int i = 0; i < n_frames; ++i) {
@@ -206,10 +207,10 @@ int plan_sonar(const oceansim_sonar_frame *frames, int n_frames, int n_param_row
         d.ret_chunk = chunk;
         d.n_ret_chunks = d.n_chunks;
         d.half_w = (fr.fan_w + 1) / 2;
-        d.fan_bpr = (d.half_w + kBlock - 1) / kBlock;
-        d.stencil = static_cast<int4 *>(fr.fan_stencil);
+        d.fan_bpr = (d.half_w + kFanTileU - 1) / kFanTileU;
+        d.stencil = gcast(static_cast<int4 *>(fr.fan_stencil));
         const bool fan_out = fr.fan_h > 0 && fr.fan_w > 0 && (backward ? true : fr.fan != nullptr);
-        d.fan_blocks = (!backward && fan_out) ? fr.fan_h * d.fan_bpr : 0;
+        d.fan_blocks = (!backward && fan_out) ? (fr.fan_h + kFanTileV - 1) / kFanTileV * d.fan_bpr : 0;
         d.speckle = fr.speckle_mode;
         d.gamma_k = fr.gamma_k;
         d.param_row = fr.param_row;
@@ -244,23 +245,32 @@ int plan_sonar(const oceansim_sonar_frame *frames, int n_frames, int n_param_row
             d.fan_s = s1 > s2 ? s1 : s2;
             d.tan_half_az = std::tan(std::min(d.half_az, 1.5707963267948966));
         }
+        d.sin_half_az = std::sin(d.half_az);
+        d.cos_half_az = std::cos(d.half_az);
+        d.r_min_f = fr.r_min;
+        d.scale_r_f = (float)d.scale_r;
+        d.cols = nullptr;
+        // offsets from a column centre reach half a column plus the error of
+        // the approximate azimuth; the short arctangent series needs |q| < 0.05
+        d.wide_cols = d.dphi > 0.09 ? 1 : 0;
         d.scale_phi_f = (float)d.scale_phi;
         d.half_az_f = (float)d.half_az;
         // FP32 azimuth error, in cells, is below ~3.3e-7 N_phi (see return_bin)
         d.az_fast = (3.5e-7 * fr.n_azimuth < 1e-3) ? 1 : 0;
         // pointers
-        d.x = fr.x; d.y = fr.y; d.z = fr.z;
-        d.nx = fr.nx; d.ny = fr.ny; d.nz = fr.nz;
-        d.mat = fr.mat;
-        d.polar = fr.polar;
-        d.fan = fr.fan;
-        d.bin_of_return = fr.bin_of_return;
-        d.grad_polar = fr.grad_polar;
-        d.grad_fan = fr.grad_fan;
+        d.x = gcast(fr.x); d.y = gcast(fr.y); d.z = gcast(fr.z);
+        d.nx = gcast(fr.nx); d.ny = gcast(fr.ny); d.nz = gcast(fr.nz);
+        d.mat = gcast(fr.mat);
+        d.polar = gcast(fr.polar);
+        d.fan = gcast(fr.fan);
+        d.bin_of_return = gcast(fr.bin_of_return);
+        d.grad_polar = gcast(fr.grad_polar);
+        d.grad_fan = gcast(fr.grad_fan);
         if (!backward) {
             P.off_pairs[i] = take(sizeof(uint2) * (size_t)d.n_chunks * chunk);
             P.off_chunk_off[i] = take(sizeof(int) * (size_t)d.n_chunks * (d.n_tiles + 1));
             if (!fr.polar) P.off_polar[i] = take(sizeof(float) * (size_t)nb);
+            if (d.fan_blocks > 0 && fr.n_azimuth > 1) P.off_cols[i] = take(sizeof(double) * 2 * (size_t)fr.n_azimuth);
         } else {
             P.off_grad_img[i] = take(sizeof(float) * (size_t)nb);
         }
@@ -287,11 +297,12 @@ void carve_sonar(SonarPlan &P, char *ws, bool backward) {
     for (size_t i = 0; i < P.dev.size(); ++i) {
         SonarDev &d = P.dev[i];
         if (!backward) {
-            d.pairs = reinterpret_cast<uint2 *>(ws + P.off_pairs[i]);
-            d.chunk_off = reinterpret_cast<int *>(ws + P.off_chunk_off[i]);
-            if (P.off_polar[i] != (size_t)-1) d.polar = reinterpret_cast<float *>(ws + P.off_polar[i]);
+            d.pairs = gcast(reinterpret_cast<uint2 *>(ws + P.off_pairs[i]));
+            d.chunk_off = gcast(reinterpret_cast<int *>(ws + P.off_chunk_off[i]));
+            if (P.off_polar[i] != (size_t)-1) d.polar = gcast(reinterpret_cast<float *>(ws + P.off_polar[i]));
+            if (P.off_cols[i] != (size_t)-1) d.cols = gcast(reinterpret_cast<double2 *>(ws + P.off_cols[i]));
         } else {
-            d.grad_img = reinterpret_cast<float *>(ws + P.off_grad_img[i]);
+            d.grad_img = gcast(reinterpret_cast<float *>(ws + P.off_grad_img[i]));
         }
     }
 }
@@ -309,7 +320,7 @@ int check_ws(void *ws, size_t have, size_t need) {
 // --------------------------------------------------------------------------
 
 int plan_uw(const oceansim_uw_frame *frames, int n_frames, int n_param_rows, bool backward, UwPlan &P,
-            bool force_table) {
+            bool force_table, int threads) {
     if (n_frames < 0) return fail(OCEANSIM_E_INVALID_ARG, "n_frames < 0");
     if (n_frames > 0 && !frames) return fail(OCEANSIM_E_INVALID_ARG, "frames is NULL");
     if (n_param_rows < 1) return fail(OCEANSIM_E_INVALID_ARG, "n_param_rows must be >= 1");
@@ -332,15 +343,16 @@ int plan_uw(const oceansim_uw_frame *frames, int n_frames, int n_param_rows, boo
             if (!aligned(p, 16))
                 return fail(OCEANSIM_E_INVALID_ARG, "camera frame %d: image buffers must be 16-byte aligned", i);
         UwDev &d = P.dev[i];
-        d.J = fr.J;
-        d.depth = fr.depth;
-        d.out = fr.out;
-        d.grad_out = fr.grad_out;
-        d.grad_J = fr.grad_J;
-        d.grad_depth = fr.grad_depth;
+        d.J = gcast(fr.J);
+        d.depth = gcast(fr.depth);
+        d.out = gcast(fr.out);
+        d.grad_out = gcast(fr.grad_out);
+        d.grad_J = gcast(fr.grad_J);
+        d.grad_depth = gcast(fr.grad_depth);
         d.npix = npix;
         d.param_row = fr.param_row;
-        d.n_blocks = (int)((npix + kUwPixelsPerBlock - 1) / kUwPixelsPerBlock);
+        const long long ppb = (long long)threads * (backward ? kUwBwdPixelsPerThread : kUwFwdPixelsPerThread);
+        d.n_blocks = (int)((npix + ppb - 1) / ppb);
         d.blk = blocks;
         blocks += d.n_blocks;
     }

@@ -13,10 +13,46 @@ constexpr int kBlock = 256;          // threads per workgroup (4 wave64)
 constexpr int kWave = 64;
 constexpr int kMaxTileBins = 4096;   // polar bins owned by one tile workgroup (one row at least)
 constexpr int kMaxTiles = 4096;      // tiles per frame (LDS histogram in the binning pass)
+constexpr int kXcds = 8;            // accelerator complex dies (each with its own L2)
+constexpr int kFanRows = 4;        // fan rows per thread (one pixel pair each, 8 rows apart)
+constexpr int kFanTileU = 32;      // pixel pairs per fan workgroup along a row
+constexpr int kFanTileV = 32;      // fan rows per fan workgroup (8 x kFanRows)
 constexpr int kLaneHistMats = 64;    // materials reduced with lane-private LDS histograms
 
 enum Kind { KBIN = 0, KTILE = 1, KFAN = 2, KRET = 3, KTILEB = 4, KIND_COUNT = 5 };
 enum Speckle { SPECKLE_OFF = 0, SPECKLE_PAPER = 1, SPECKLE_GAMMA = 2 };
+
+// Pointers into device global memory.  Descriptor pointers carry the global
+// address space in their type: read from a device frame table they would
+// otherwise be generic pointers, and every access would compile to a flat
+// (not global) memory instruction.
+template <class T>
+using gptr = __attribute__((address_space(1))) T *;
+template <class T>
+__host__ __device__ __forceinline__ gptr<T> gcast(T *p) {
+    return (gptr<T>)p;
+}
+
+// Vector loads and stores through global pointers (HIP's vector classes
+// take generic references, so they go through clang's native vectors).
+typedef unsigned u32x2_t __attribute__((ext_vector_type(2)));
+typedef int i32x4_t __attribute__((ext_vector_type(4)));
+typedef float f32x4_t __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ uint2 gload(gptr<const uint2> p) {
+    const u32x2_t v = *(gptr<const u32x2_t>)p;
+    return make_uint2(v.x, v.y);
+}
+__device__ __forceinline__ void gstore(gptr<uint2> p, uint2 v) { *(gptr<u32x2_t>)p = u32x2_t{v.x, v.y}; }
+__device__ __forceinline__ int4 gload(gptr<const int4> p) {
+    const i32x4_t v = *(gptr<const i32x4_t>)p;
+    return make_int4(v.x, v.y, v.z, v.w);
+}
+__device__ __forceinline__ void gstore(gptr<int4> p, int4 v) { *(gptr<i32x4_t>)p = i32x4_t{v.x, v.y, v.z, v.w}; }
+__device__ __forceinline__ float4 gload(gptr<const float4> p) {
+    const f32x4_t v = *(gptr<const f32x4_t>)p;
+    return make_float4(v.x, v.y, v.z, v.w);
+}
+__device__ __forceinline__ void gstore(gptr<float4> p, float4 v) { *(gptr<f32x4_t>)p = f32x4_t{v.x, v.y, v.z, v.w}; }
 
 // --------------------------------------------------------------------------
 // One sonar frame as the kernels see it.  Built on the host from the public
@@ -24,22 +60,22 @@ enum Speckle { SPECKLE_OFF = 0, SPECKLE_PAPER = 1, SPECKLE_GAMMA = 2 };
 // computed once in double.
 // --------------------------------------------------------------------------
 struct SonarDev {
-    const float *x, *y, *z, *nx, *ny, *nz;
-    const int *mat;
-    float *polar;               // speckled polar image (caller buffer or workspace)
-    float *fan;
-    int *bin_of_return;
-    const float *grad_polar, *grad_fan;
-    uint2 *pairs;               // binning pass output: (tile-local bin, intensity)
-    int *chunk_off;             // [n_chunks][n_tiles + 1] exclusive offsets per chunk
-    float *grad_img;            // backward: dL/d(polar image) [nb]
+    gptr<const float> x, y, z, nx, ny, nz;
+    gptr<const int> mat;
+    gptr<float> polar;          // speckled polar image (caller buffer or workspace)
+    gptr<float> fan;
+    gptr<int> bin_of_return;
+    gptr<const float> grad_polar, grad_fan;
+    gptr<uint2> pairs;          // binning pass output: (tile-local bin, intensity)
+    gptr<int> chunk_off;        // [n_chunks][n_tiles + 1] exclusive offsets per chunk
+    gptr<float> grad_img;       // backward: dL/d(polar image) [nb]
     long long n;                // returns
     int n_range, n_az, fan_h, fan_w;
     int rows_per_tile, tile_bins, n_tiles;          // forward polar tiles
     int rows_per_tile_b, tile_bins_b, n_tiles_b;    // backward polar tiles
     int chunk, n_chunks;        // returns per binning workgroup, workgroups
     int ret_chunk, n_ret_chunks;// returns per backward-gather workgroup, workgroups
-    int fan_bpr, fan_blocks;    // fan: workgroups per pixel row, total
+    int fan_bpr, fan_blocks;    // fan: workgroup columns (kFanTileU pairs each), workgroups
     int speckle, gamma_k, param_row;
     unsigned seed_lo, seed_hi, frame_id;
     int blk[KIND_COUNT];        // first global workgroup of this frame, per kernel kind
@@ -56,19 +92,37 @@ struct SonarDev {
     float scale_phi_f, half_az_f;
     int az_fast;                // FP32 azimuth is accurate to < 1e-3 cell on this grid
     int half_w;                 // fan pixel pairs per row: ceil(fan_w / 2)
-    int4 *stencil;              // saved fan stencils [fan_h][half_w] or nullptr
+    gptr<int4> stencil;         // saved fan stencils [fan_h][half_w] or nullptr
+    gptr<double2> cols;         // forward fan: {sin, cos} of each column-centre azimuth [n_az]
+    double sin_half_az, cos_half_az;
+    int wide_cols;              // columns wider than 0.09 rad: offsets need the full arctangent
+    float r_min_f, scale_r_f;
 };
 
 struct UwDev {
-    const float *J, *depth;
-    float *out;
-    const float *grad_out;
-    float *grad_J, *grad_depth;
+    gptr<const float> J, depth;
+    gptr<float> out;
+    gptr<const float> grad_out;
+    gptr<float> grad_J, grad_depth;
     long long npix;
     int param_row;
     int blk;                    // first global workgroup
     int n_blocks;
 };
+
+// Workgroups are dispatched to the XCDs round-robin (workgroup b to XCD
+// b % kXcds).  Kernels whose neighbouring workgroups share data (polar rows
+// gathered by nearby fan tiles, fan pixels near adjacent polar tiles) use
+// this logical id instead: each XCD receives runs of G consecutive logical
+// workgroups (so the shared lines are fetched into one L2), and the runs are
+// dealt round-robin (so work that varies smoothly with the id stays balanced
+// across XCDs).  A bijection on [0, n); the last partial round keeps b.
+template <int G>
+__device__ __forceinline__ int xcd_grouped_id(int b, int n) {
+    constexpr int round = kXcds * G;
+    if (b >= n / round * round) return b;
+    return b / round * round + (b % kXcds) * G + (b / kXcds) % G;
+}
 
 // Frame sources: a single frame passed by value in the kernel arguments, or a
 // device-resident table (batched calls and plans).  Workgroups find their
@@ -317,6 +371,105 @@ __device__ __forceinline__ bool fan_stencil(const SonarDev &f, double rho, doubl
     return fan_radial(f, rho, st) && fan_angular(f, phi, st);
 }
 
+// --------------------------------------------------------------------------
+// Fan geometry from the nearest bin centres.  The bilinear weight along an
+// axis is the pixel's offset from a bin centre in units of the bin size; it
+// is computed here from differences that are formed exactly in FP64 (squared
+// radii; the cross and dot products of the pixel position with the centre
+// direction), so each weight and its complement keep ~1e-7 RELATIVE accuracy
+// without an FP64 square root or arctangent per pixel.  Approximate FP32
+// positions only choose the nearest centre, to well within half a bin.
+// --------------------------------------------------------------------------
+
+// atan(z) for z in [0, 1]: odd least-squares polynomial fitted for this
+// kernel, |error| < 1.2e-5 rad (used only to pick the nearest column).
+__device__ __forceinline__ float atan01_approx(float z) {
+    const float z2 = z * z;
+    float p = 0.02084507f;
+    p = __builtin_fmaf(p, z2, -0.08515627f);
+    p = __builtin_fmaf(p, z2, 0.18015924f);
+    p = __builtin_fmaf(p, z2, -0.33030477f);
+    p = __builtin_fmaf(p, z2, 0.9998663f);
+    return p * z;
+}
+
+// atan2(a, b) for a, b >= 0, |error| < 1.2e-5 rad.
+__device__ __forceinline__ float atan2_pos_approx(float a, float b) {
+    const float lo = fminf(a, b), hi = fmaxf(a, b);
+    const float t = atan01_approx(lo * __builtin_amdgcn_rcpf(fmaxf(hi, 1e-30f)));
+    return a > b ? 1.5707963f - t : t;
+}
+
+// Offset e in (-1, 1) of a coordinate from centre k of an axis of n bins,
+// in bins -> first bin of the stencil and the stored weight code of the
+// second bin (see encode_weight), with the clamping of the plain definition
+// at the two outer half-bins.
+__device__ __forceinline__ void axis_from_offset(int k, float e, int n, int &k0, float &code) {
+    e = e + 0.0f;   // no negative zero: its sign would read as "weight 1"
+    if (n == 1) {
+        k0 = 0;
+        code = 0.0f;
+        return;
+    }
+    k0 = e < 0.0f ? k - 1 : k;
+    code = e > 0.5f ? e - 1.0f : (e < -0.5f ? e + 1.0f : e);
+    if (k0 < 0) {               // before the first centre: weight 0 on bin 1
+        k0 = 0;
+        code = 0.0f;
+    }
+    if (k0 > n - 2) {           // past the last centre: weight 1 on bin n-1
+        k0 = n - 2;
+        code = -0.0f;
+    }
+}
+
+// Radial half of a fan pixel at squared distance rho2 from the apex: inside
+// test and (first row, weight code).  rho2 in FP64 from exact pixel offsets.
+// The stencil is computed whatever the inside test says (and is valid).
+__device__ __forceinline__ bool fan_radial_fast(const SonarDev &f, double rho2, int &i0, float &code) {
+    const float rho_f = __builtin_amdgcn_sqrtf((float)rho2);   // hardware sqrt: only picks the nearest row
+    int in = (int)__builtin_rintf((rho_f - f.r_min_f) * f.scale_r_f - 0.5f);
+    in = in < 0 ? 0 : (in > f.n_range - 1 ? f.n_range - 1 : in);
+    const double rc = __builtin_fma((double)in + 0.5, f.dr, f.r_min);
+    // rho - rc = (rho^2 - rc^2) / (rho + rc): numerator exact to FP64 rounding
+    const float num = (float)__builtin_fma(-rc, rc, rho2);
+    const float e = num * __builtin_amdgcn_rcpf(rho_f + (float)rc) * f.scale_r_f;
+    axis_from_offset(in, e, f.n_range, i0, code);
+    return rho2 >= f.r_min * f.r_min && rho2 <= f.r_max * f.r_max;
+}
+
+// Angular half of a LEFT-half fan pixel (offset ax = -x_c >= 0 from the axis,
+// y_c > 0 along it): inside test and, for this pixel, the nearest column jn
+// and the offset e from its centre in columns; the mirror pixel has
+// N_phi - 1 - jn and -e.  Computed whatever the inside test says.
+__device__ __forceinline__ bool fan_angular_fast(const SonarDev &f, double ax, double yc, int &jn, float &e) {
+    jn = 0;
+    e = 0.0f;
+    if (f.n_az > 1) {
+        const float phi = atan2_pos_approx((float)ax, (float)yc);
+        int j = (int)__builtin_rintf((phi + f.half_az_f) * f.scale_phi_f - 0.5f);
+        j = j < 0 ? 0 : (j > f.n_az - 1 ? f.n_az - 1 : j);
+        const gptr<const double> cs = (gptr<const double>)f.cols;   // {sin, cos} of the centre azimuth
+        const double sn = cs[2 * j], cn = cs[2 * j + 1];
+        // angle from the centre direction: atan of the cross over the dot product
+        const double cr = __builtin_fma(ax, cn, -yc * sn);
+        const double dt = __builtin_fma(ax, sn, yc * cn);
+        const float q = (float)cr * __builtin_amdgcn_rcpf((float)dt);
+        float d;
+        if (f.wide_cols) {
+            d = atanf(q);
+        } else {
+            // |q| < 0.05: the series to q^5 is exact to float precision
+            const float q2 = q * q;
+            d = q * __builtin_fmaf(q2, __builtin_fmaf(q2, 0.2f, -0.33333334f), 1.0f);
+        }
+        jn = j;
+        e = d * f.scale_phi_f;
+    }
+    // |phi| <= fov/2  <=>  ax cos(fov/2) <= yc sin(fov/2)   (fov <= pi, yc > 0)
+    return ax * f.cos_half_az <= yc * f.sin_half_az;
+}
+
 // Saved stencil of a pair of mirror-image fan pixels (left pixel u, right
 // pixel W-1-u): {first row (-1 = outside the sector), left pixel's first
 // column, row weight, left column weight}.  A weight w in [0, 1] is stored as
@@ -358,6 +511,48 @@ __device__ __forceinline__ double block_sum(double v, double *sh) {
     if (threadIdx.x == 0)
         for (int k = 0; k < NT / kWave; ++k) s += sh[k];
     return s;
+}
+
+// N sums over a workgroup with one barrier pair: the same fixed order per
+// sum as block_sum.  `sh` holds N * NT / 64 doubles; thread k < N returns sum k.
+template <int N, int NT = kBlock>
+__device__ __forceinline__ double block_sum_n(const double (&v)[N], double *sh) {
+    const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < N; ++k) {
+        const double w = wave_sum(v[k]);
+        if (lane == 0) sh[k * (NT / kWave) + wid] = w;
+    }
+    __syncthreads();
+    double s = 0.0;
+    if (threadIdx.x < N)
+        for (int k = 0; k < NT / kWave; ++k) s += sh[threadIdx.x * (NT / kWave) + k];
+    return s;
+}
+
+// Inclusive scan of one value per thread across a workgroup of NT threads
+// (wave shuffles, then the wave totals); `wtot` holds NT / 64 ints in LDS and
+// may be reused only after a barrier.  Every thread must call it.
+template <int NT = kBlock>
+__device__ __forceinline__ int block_inclusive_scan1(int v, int *wtot, int &total) {
+    const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
+#pragma unroll
+    for (int o = 1; o < kWave; o <<= 1) {
+        const int t = __shfl_up(v, o, kWave);
+        if (lane >= o) v += t;
+    }
+    if (lane == kWave - 1) wtot[w] = v;
+    __syncthreads();
+    int base = 0, tot = 0;
+#pragma unroll
+    for (int k = 0; k < NT / kWave; ++k) {
+        const int t = wtot[k];
+        base += k < w ? t : 0;
+        tot += t;
+    }
+    total = tot;
+    return v + base;
 }
 
 // Exclusive scan of a[0..n) in LDS by a workgroup of NT threads; a[n]

@@ -28,7 +28,7 @@ struct SonarPlan {
     size_t bytes = 0;
     // workspace offsets
     size_t off_table = 0;
-    std::vector<size_t> off_pairs, off_chunk_off, off_polar, off_grad_img;
+    std::vector<size_t> off_pairs, off_chunk_off, off_polar, off_grad_img, off_cols;
     size_t off_part = 0, off_refl_part = 0;
     int n_slots = 0;
 };
@@ -49,8 +49,10 @@ int plan_sonar(const oceansim_sonar_frame *frames, int n_frames, int n_param_row
                SonarPlan &P, const Tuning *tune, bool force_table = false);
 void carve_sonar(SonarPlan &P, char *ws, bool backward);
 int check_ws(void *ws, size_t have, size_t need);
+// threads: workgroup size of the kernel that runs the camera frames (the
+// camera kernels' own, or that of a sonar kernel carrying them along).
 int plan_uw(const oceansim_uw_frame *frames, int n_frames, int n_param_rows, bool backward, UwPlan &P,
-            bool force_table = false);
+            bool force_table = false, int threads = kBlock);
 
 template <class T>
 hipError_t upload_table(const std::vector<T> &v, char *ws, size_t off, hipStream_t st) {

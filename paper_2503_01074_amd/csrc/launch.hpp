@@ -50,11 +50,25 @@ struct SonarGrid {
     int all_saved;       // every frame with a fan gradient has saved fan stencils
 };
 
+constexpr int kBwdThreads = 512;   // threads of a backward polar-tile workgroup
+
+// Camera frames carried along in the launch of a sonar kernel (plans with both
+// kinds of frames): device frame table, workgroups (planned for the thread
+// count of that sonar kernel), parameters and, backward, the partial sums.
+struct UwCompanion {
+    const UwDev *table = nullptr;
+    int n = 0;
+    int blocks = 0;
+    const oceansim_water_params *params = nullptr;
+    double *part = nullptr;
+    int *part_row = nullptr;
+};
+
 hipError_t sonar_forward_one(const SonarDev &f, const SonarGrid &g, const oceansim_sonar_params *params,
                              const float *refl, int n_mat, hipStream_t st);
 hipError_t sonar_forward_table(const SonarDev *t, int n, const SonarGrid &g,
                                const oceansim_sonar_params *params, const float *refl, int n_mat,
-                               hipStream_t st);
+                               hipStream_t st, const UwCompanion *uw = nullptr);
 // Backward: partial sums into part (5 doubles per tile and return workgroup)
 // and refl_part (n_mat doubles per return workgroup, small tables), reduced
 // in a fixed order into grad_params [n_rows][8] and grad_refl [n_mat].
@@ -64,9 +78,14 @@ hipError_t sonar_backward_one(const SonarDev &f, const SonarGrid &g, const ocean
 hipError_t sonar_backward_table(const SonarDev *t, int n, const SonarGrid &g,
                                 const oceansim_sonar_params *params, int n_rows, const float *refl,
                                 int n_mat, double *part, double *refl_part, float *grad_params,
-                                float *grad_refl, hipStream_t st);
+                                float *grad_refl, hipStream_t st, const UwCompanion *uw = nullptr);
 
-constexpr int kUwPixelsPerBlock = kBlock * 16;
+// Camera pixels per thread: one float4 group forward, two backward (the
+// per-workgroup parameter partial sums amortised over 8 pixels).
+constexpr int kUwFwdPixelsPerThread = 4;
+constexpr int kUwBwdPixelsPerThread = 8;
+constexpr int kUwFwdPixelsPerBlock = kBlock * kUwFwdPixelsPerThread;
+constexpr int kUwBwdPixelsPerBlock = kBlock * kUwBwdPixelsPerThread;
 
 hipError_t uw_forward_one(const UwDev &f, int blocks, const oceansim_water_params *params, hipStream_t st);
 hipError_t uw_forward_table(const UwDev *t, int n, int blocks, const oceansim_water_params *params,

@@ -38,7 +38,10 @@ struct oceansim_plan {
     char *mem = nullptr;        // workspaces and frame tables
     char *stencil_mem = nullptr;
     char *ws_sf = nullptr, *ws_sb = nullptr, *ws_uf = nullptr, *ws_ub = nullptr;
-    hipStream_t cap = nullptr;
+    hipStream_t cap = nullptr;   // capture stream (default priority)
+    // with both kinds of frames the camera frames ride along in the launches
+    // of the sonar tile kernels (one dispatch each way)
+    bool fused = false;
     hipGraphExec_t g_fwd = nullptr, g_bwd = nullptr;
 };
 
@@ -59,41 +62,67 @@ __global__ void k_count_disagree(const float *a, const float *b, long long n, fl
     if (local) atomicAdd(bad, local);
 }
 
-hipError_t launch_forward(oceansim_plan *p, hipStream_t st) {
-    hipError_t e = hipSuccess;
-    if (!p->sonar.empty()) {
-        e = sonar_forward_table(reinterpret_cast<const SonarDev *>(p->ws_sf + p->sf.off_table),
-                                (int)p->sonar.size(), p->sf.grid, p->sp, p->refl, p->n_mat, st);
+UwCompanion companion(oceansim_plan *p, bool backward) {
+    UwCompanion c;
+    const UwPlan &u = backward ? p->ub : p->uf;
+    char *ws = backward ? p->ws_ub : p->ws_uf;
+    c.table = reinterpret_cast<const UwDev *>(ws + u.off_table);
+    c.n = (int)p->camera.size();
+    c.blocks = u.blocks;
+    c.params = p->wp;
+    if (backward) {
+        c.part = reinterpret_cast<double *>(ws + u.off_part);
+        c.part_row = reinterpret_cast<int *>(ws + u.off_part_row);
+    }
+    return c;
+}
+
+hipError_t camera_forward(oceansim_plan *p, hipStream_t st) {
+    if (p->camera.empty() || p->uf.blocks == 0) return hipSuccess;
+    return uw_forward_table(reinterpret_cast<const UwDev *>(p->ws_uf + p->uf.off_table), (int)p->camera.size(),
+                            p->uf.blocks, p->wp, st);
+}
+
+hipError_t camera_reduce(oceansim_plan *p, hipStream_t st) {
+    double *part = reinterpret_cast<double *>(p->ws_ub + p->ub.off_part);
+    int *row = reinterpret_cast<int *>(p->ws_ub + p->ub.off_part_row);
+    return reduce_rows(part, row, p->ub.blocks, 9, p->n_wrows, p->g_wp, OCEANSIM_WATER_GRAD_WIDTH, st);
+}
+
+hipError_t camera_backward(oceansim_plan *p, hipStream_t st) {
+    if (p->camera.empty()) return hipSuccess;
+    if (p->ub.blocks > 0) {
+        hipError_t e = uw_backward_table(reinterpret_cast<const UwDev *>(p->ws_ub + p->ub.off_table),
+                                         (int)p->camera.size(), p->ub.blocks, p->wp,
+                                         reinterpret_cast<double *>(p->ws_ub + p->ub.off_part),
+                                         reinterpret_cast<int *>(p->ws_ub + p->ub.off_part_row), st);
         if (e != hipSuccess) return e;
     }
-    if (!p->camera.empty() && p->uf.blocks > 0)
-        e = uw_forward_table(reinterpret_cast<const UwDev *>(p->ws_uf + p->uf.off_table), (int)p->camera.size(),
-                             p->uf.blocks, p->wp, st);
-    return e;
+    return camera_reduce(p, st);
+}
+
+hipError_t launch_forward(oceansim_plan *p, hipStream_t st) {
+    if (p->sonar.empty()) return camera_forward(p, st);
+    const UwCompanion c = p->fused ? companion(p, false) : UwCompanion{};
+    hipError_t e = sonar_forward_table(reinterpret_cast<const SonarDev *>(p->ws_sf + p->sf.off_table),
+                                       (int)p->sonar.size(), p->sf.grid, p->sp, p->refl, p->n_mat, st,
+                                       p->fused ? &c : nullptr);
+    if (e != hipSuccess || p->fused) return e;
+    return camera_forward(p, st);
 }
 
 hipError_t launch_backward(oceansim_plan *p, hipStream_t st) {
-    hipError_t e = hipSuccess;
-    if (!p->sonar.empty()) {
-        const bool lane_hist = p->n_mat <= kLaneHistMats;
-        e = sonar_backward_table(reinterpret_cast<const SonarDev *>(p->ws_sb + p->sb.off_table),
-                                 (int)p->sonar.size(), p->sb.grid, p->sp, p->n_srows, p->refl, p->n_mat,
-                                 reinterpret_cast<double *>(p->ws_sb + p->sb.off_part),
-                                 lane_hist ? reinterpret_cast<double *>(p->ws_sb + p->sb.off_refl_part) : nullptr,
-                                 p->g_sp, p->g_refl, st);
-        if (e != hipSuccess) return e;
-    }
-    if (!p->camera.empty()) {
-        double *part = reinterpret_cast<double *>(p->ws_ub + p->ub.off_part);
-        int *row = reinterpret_cast<int *>(p->ws_ub + p->ub.off_part_row);
-        if (p->ub.blocks > 0) {
-            e = uw_backward_table(reinterpret_cast<const UwDev *>(p->ws_ub + p->ub.off_table), (int)p->camera.size(),
-                                  p->ub.blocks, p->wp, part, row, st);
-            if (e != hipSuccess) return e;
-        }
-        e = reduce_rows(part, row, p->ub.blocks, 9, p->n_wrows, p->g_wp, OCEANSIM_WATER_GRAD_WIDTH, st);
-    }
-    return e;
+    if (p->sonar.empty()) return camera_backward(p, st);
+    const bool lane_hist = p->n_mat <= kLaneHistMats;
+    const UwCompanion c = p->fused ? companion(p, true) : UwCompanion{};
+    hipError_t e = sonar_backward_table(reinterpret_cast<const SonarDev *>(p->ws_sb + p->sb.off_table),
+                                        (int)p->sonar.size(), p->sb.grid, p->sp, p->n_srows, p->refl, p->n_mat,
+                                        reinterpret_cast<double *>(p->ws_sb + p->sb.off_part),
+                                        lane_hist ? reinterpret_cast<double *>(p->ws_sb + p->sb.off_refl_part)
+                                                  : nullptr,
+                                        p->g_sp, p->g_refl, st, p->fused ? &c : nullptr);
+    if (e != hipSuccess) return e;
+    return p->fused ? camera_reduce(p, st) : camera_backward(p, st);
 }
 
 // ---------------------------------------------------------------------------
@@ -402,7 +431,7 @@ int capture(oceansim_plan *p, bool backward, hipGraphExec_t *out) {
     set_capturing(true);
     hipError_t e = hipStreamBeginCapture(p->cap, hipStreamCaptureModeThreadLocal);
     if (e == hipSuccess) {
-        hipError_t le = backward ? launch_backward(p, p->cap) : launch_forward(p, p->cap);
+        const hipError_t le = backward ? launch_backward(p, p->cap) : launch_forward(p, p->cap);
         hipGraph_t g = nullptr;
         e = hipStreamEndCapture(p->cap, &g);
         if (e == hipSuccess) e = le;
@@ -461,9 +490,12 @@ int oceansim_plan_create(const oceansim_sonar_frame *sonar, int32_t n_sonar, con
         rc = plan_sonar(p->sonar.data(), n_sonar, n_sonar_rows, n_materials, false, p->sf, nullptr);
         if (!rc && bwd) rc = plan_sonar(p->sonar.data(), n_sonar, n_sonar_rows, n_materials, true, p->sb, nullptr);
     }
+    p->fused = n_sonar > 0 && n_camera > 0;
     if (!rc && n_camera > 0) {
         rc = plan_uw(p->camera.data(), n_camera, n_water_rows, false, p->uf, true);
-        if (!rc && bwd) rc = plan_uw(p->camera.data(), n_camera, n_water_rows, true, p->ub, true);
+        if (!rc && bwd)
+            rc = plan_uw(p->camera.data(), n_camera, n_water_rows, true, p->ub, true,
+                         p->fused ? kBwdThreads : kBlock);
     }
     if (rc) {
         delete p;

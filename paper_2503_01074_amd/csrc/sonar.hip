@@ -24,6 +24,7 @@
 //               reflectivity partial sums).
 #include "device.hpp"
 #include "launch.hpp"
+#include "uw_body.hpp"
 
 namespace osim {
 
@@ -36,7 +37,7 @@ __global__ __launch_bounds__(kBlock) void k_bin(Src src, const oceansim_sonar_pa
     extern __shared__ int4 lds_raw[];
     int local;
     const int fi = src.locate(blockIdx.x, KBIN, local);
-    const SonarDev &f = src.frame(fi);
+    const SonarDev f = src.frame(fi);
     const int tid = threadIdx.x;
     const int n_tiles = f.n_tiles;
     int *hist = reinterpret_cast<int *>(lds_raw);                    // n_tiles + 1
@@ -49,6 +50,17 @@ __global__ __launch_bounds__(kBlock) void k_bin(Src src, const oceansim_sonar_pa
     for (int t = tid; t <= n_tiles; t += kBlock) hist[t] = 0;
     __syncthreads();
 
+    // restrict-qualified views: the optional bin output never aliases the
+    // returns, so the loads of all R returns can be in flight together
+    const gptr<const float> __restrict__ X = f.x;
+    const gptr<const float> __restrict__ Y = f.y;
+    const gptr<const float> __restrict__ Z = f.z;
+    const gptr<const float> __restrict__ NX = f.nx;
+    const gptr<const float> __restrict__ NY = f.ny;
+    const gptr<const float> __restrict__ NZ = f.nz;
+    const gptr<const int> __restrict__ MAT = f.mat;
+    const float *__restrict__ RF = refl;
+    const gptr<int> __restrict__ BO = f.bin_of_return;
     int tile[R], rank[R];
     uint32_t lbin[R];
     float inten[R];
@@ -57,15 +69,14 @@ __global__ __launch_bounds__(kBlock) void k_bin(Src src, const oceansim_sonar_pa
         const long long k = base + (long long)q * kBlock + tid;
         tile[q] = -1;
         if (k < f.n) {
-            const float xf = f.x[k], yf = f.y[k], zf = f.z[k];
-            const int m = f.mat[k];
+            const float xf = X[k], yf = Y[k], zf = Z[k];
+            const int m = MAT[k];
             double r;
             const int b = return_bin(f, xf, yf, zf, m, n_mat, r);
-            if (f.bin_of_return) f.bin_of_return[k] = b;
+            if (BO) BO[k] = b;
             if (b >= 0) {
                 float cosg, att;
-                inten[q] = return_intensity(f, xf, yf, zf, f.nx[k], f.ny[k], f.nz[k], r, refl[m],
-                                            alpha, cosg, att);
+                inten[q] = return_intensity(f, xf, yf, zf, NX[k], NY[k], NZ[k], r, RF[m], alpha, cosg, att);
                 const int i = b / f.n_az;
                 const int t = i / f.rows_per_tile;
                 tile[q] = t;
@@ -77,7 +88,7 @@ __global__ __launch_bounds__(kBlock) void k_bin(Src src, const oceansim_sonar_pa
     __syncthreads();
     block_exclusive_scan(hist, n_tiles, scan_tmp);
 
-    int *off = f.chunk_off + (long long)local * (n_tiles + 1);
+    const gptr<int> off = f.chunk_off + (long long)local * (n_tiles + 1);
     for (int t = tid; t <= n_tiles; t += kBlock) off[t] = hist[t];
 #pragma unroll
     for (int q = 0; q < R; ++q)
@@ -85,8 +96,8 @@ __global__ __launch_bounds__(kBlock) void k_bin(Src src, const oceansim_sonar_pa
             stage[hist[tile[q]] + rank[q]] = make_uint2(lbin[q], __float_as_uint(inten[q]));
     __syncthreads();
     const int total = hist[n_tiles];
-    uint2 *dst = f.pairs + base;
-    for (int k = tid; k < total; k += kBlock) dst[k] = stage[k];
+    const gptr<uint2> dst = f.pairs + base;
+    for (int k = tid; k < total; k += kBlock) gstore(dst + k, stage[k]);
 }
 
 // ---------------------------------------------------------------------------
@@ -111,14 +122,15 @@ __device__ __forceinline__ float additive_term(const SonarDev &f, const AddCtx &
     return R * (1.0f + 0.5f * E * (c.sigma_sa * rho));
 }
 
+// Forward polar tile `bid` of the launch (kBlock threads).
 template <class Src>
-__global__ __launch_bounds__(kBlock) void k_tile(Src src, const oceansim_sonar_params *params) {
+__device__ __forceinline__ void tile_fwd_block(const Src &src, const oceansim_sonar_params *params, int bid) {
     extern __shared__ int4 lds_raw[];
     __shared__ unsigned listed[kMaxTileBins / 32];
     __shared__ int n_listed;
     int tile;
-    const int fi = src.locate(blockIdx.x, KTILE, tile);
-    const SonarDev &f = src.frame(fi);
+    const int fi = src.locate(bid, KTILE, tile);
+    const SonarDev f = src.frame(fi);
     const int tid = threadIdx.x;
     const int nb = f.n_range * f.n_az;
     const int b_lo = tile * f.tile_bins;
@@ -128,20 +140,47 @@ __global__ __launch_bounds__(kBlock) void k_tile(Src src, const oceansim_sonar_p
     int *list = reinterpret_cast<int *>(acc + f.tile_bins);    // [tile_bins]
     const bool speckle = f.speckle != SPECKLE_OFF;
 
+    // side job for the fan launch that follows: {sin, cos} of the column-centre azimuths
+    if (f.cols)
+        for (int j = tile * kBlock + tid; j < f.n_az; j += f.n_tiles * kBlock) {
+            double sn, cs;
+            sincos(((double)j + 0.5) * f.dphi - f.half_az, &sn, &cs);
+            const gptr<double> cd = (gptr<double>)f.cols;
+            cd[2 * j] = sn;
+            cd[2 * j + 1] = cs;
+        }
     for (int k = tid; k < nbins; k += kBlock) acc[k] = 0.0f;
     for (int k = tid; k < (nbins + 31) / 32; k += kBlock) listed[k] = 0u;
     if (tid == 0) n_listed = 0;
     __syncthreads();
 
-    // binning by summation: every chunk's segment for this tile; bins that
-    // receive a nonzero intensity are listed once for the multiplicative draw
+    // binning by summation: the segments of this tile in every chunk, for
+    // kBlock chunks at a time, flattened so that every thread takes pairs
+    // (independent loads) whatever the segment lengths.  Bins that receive a
+    // nonzero intensity are listed once for the multiplicative draw.
     const int stride = f.n_tiles + 1;
-    for (int c = tid; c < f.n_chunks; c += kBlock) {
-        const int *off = f.chunk_off + (long long)c * stride + tile;
-        const int s = off[0], e = off[1];
-        const uint2 *p = f.pairs + (long long)c * f.chunk;
-        for (int k = s; k < e; ++k) {
-            const uint2 q = p[k];
+    __shared__ int seg_end[kBlock], seg_start[kBlock], wtot[kBlock / kWave];
+    for (int c0 = 0; c0 < f.n_chunks; c0 += kBlock) {
+        const int c = c0 + tid;
+        int s0 = 0, len = 0;
+        if (c < f.n_chunks) {
+            const gptr<const int> off = f.chunk_off + (long long)c * stride + tile;
+            s0 = off[0];
+            len = off[1] - s0;
+        }
+        int total;
+        const int incl = block_inclusive_scan1<kBlock>(len, wtot, total);
+        seg_end[tid] = incl;
+        seg_start[tid] = s0 - (incl - len);   // pair index = seg_start[c] + flat index
+        __syncthreads();
+        for (int k = tid; k < total; k += kBlock) {
+            // the segment holding flat index k: first c with seg_end[c] > k
+            int lo = 0, hi = kBlock - 1;
+            while (lo < hi) {
+                const int mid = (lo + hi) >> 1;
+                if (seg_end[mid] > k) hi = mid; else lo = mid + 1;
+            }
+            const uint2 q = gload(f.pairs + ((long long)(c0 + lo) * f.chunk + seg_start[lo] + k));
             if (q.x >= (uint32_t)nbins) continue;
             const float I = __uint_as_float(q.y);
             atomicAdd(&acc[q.x], I);
@@ -150,8 +189,8 @@ __global__ __launch_bounds__(kBlock) void k_tile(Src src, const oceansim_sonar_p
                 if (!(atomicOr(&listed[q.x >> 5], bit) & bit)) list[atomicAdd(&n_listed, 1)] = (int)q.x;
             }
         }
+        __syncthreads();
     }
-    __syncthreads();
 
     const oceansim_sonar_params pr = params[f.param_row];
     const float G = pr.gain;
@@ -192,7 +231,7 @@ __global__ __launch_bounds__(kBlock) void k_tile(Src src, const oceansim_sonar_p
             }
         }
         if (in[0] && in[3]) {
-            *reinterpret_cast<float4 *>(f.polar + b0) = make_float4(out[0], out[1], out[2], out[3]);
+            gstore((gptr<float4>)(f.polar + b0), make_float4(out[0], out[1], out[2], out[3]));
         } else {
 #pragma unroll
             for (int w = 0; w < 4; ++w)
@@ -201,60 +240,117 @@ __global__ __launch_bounds__(kBlock) void k_tile(Src src, const oceansim_sonar_p
     }
 }
 
+template <class Src>
+__global__ __launch_bounds__(kBlock) void k_tile(Src src, const oceansim_sonar_params *params) {
+    tile_fwd_block(src, params, blockIdx.x);
+}
+
+// The forward tiles of the sonar frames and, in the same launch, the camera
+// frames of a plan (workgroups n_tile_blocks and up): the camera stream of
+// HBM traffic runs beside the VALU-heavy tiles instead of after them.
+template <class Src>
+__global__ __launch_bounds__(kBlock) void k_tile_uw(Src src, const oceansim_sonar_params *params,
+                                                    int n_tile_blocks, Table<UwDev> usrc,
+                                                    const oceansim_water_params *wparams) {
+    if ((int)blockIdx.x < n_tile_blocks)
+        tile_fwd_block(src, params, blockIdx.x);
+    else
+        uw_fwd_block<Table<UwDev>, kBlock>(usrc, wparams, blockIdx.x - n_tile_blocks);
+}
+
 // ---------------------------------------------------------------------------
 // k_fan: pixel u (left half, x <= 0) and its mirror W-1-u share rho and |phi|.
 // ---------------------------------------------------------------------------
-// Polar position of left-half pixel (v, u): rho and the azimuth |phi| >= 0.
-__device__ __forceinline__ void fan_left(const SonarDev &f, int v, int u, double &rho,
-                                         double &phi_pos) {
-    const double ax = (0.5 * (double)f.fan_w - (double)u - 0.5) * f.fan_s;   // = -x_c >= 0
-    const double yc = ((double)f.fan_h - (double)v - 0.5) * f.fan_s;
-    rho = __builtin_sqrt(ax * ax + yc * yc);
-    phi_pos = atan2(ax, yc);
+// Load of polar-image element `idx` through a 32-bit byte offset from the
+// uniform image base (a polar image has at most 2^24 bins).
+__device__ __forceinline__ float polar_at(gptr<const float> base, int idx) {
+    return *(gptr<const float>)((gptr<const char>)base + (uint32_t)idx * 4u);
 }
 
 template <class Src>
 __global__ __launch_bounds__(kBlock) void k_fan(Src src) {
     int local;
-    const int fi = src.locate(blockIdx.x, KFAN, local);
-    const SonarDev &f = src.frame(fi);
-    const int v = local / f.fan_bpr;
-    const int u = (local - v * f.fan_bpr) * kBlock + threadIdx.x;
+    const int fi = src.locate(xcd_grouped_id<16>(blockIdx.x, gridDim.x), KFAN, local);
+    const SonarDev f = src.frame(fi);
+    // a workgroup covers 32 pixel pairs x 32 rows; each wave an 8 x 8 patch
+    // of pairs per load instruction (rows 8 apart across a thread's kFanRows),
+    // so the gathers of one instruction stay within a few polar rows
+    const int n_groups = (f.fan_h + kFanTileV - 1) / kFanTileV;
+    const int col = local / n_groups;            // vertically adjacent tiles are consecutive
+    const int g = local - col * n_groups;
+    const int lane = threadIdx.x & (kWave - 1);
+    const int u = col * kFanTileU + (threadIdx.x / kWave) * 8 + (lane & 7);
     if (u >= f.half_w) return;
-    double rho, phi;
-    fan_left(f, v, u, rho, phi);
-    float *row = f.fan + (long long)v * f.fan_w;
+    const int v0 = g * kFanTileV + (lane >> 3);
+    const gptr<const float> __restrict__ polar = f.polar;
+    const gptr<float> __restrict__ fan = f.fan;
     const int um = f.fan_w - 1 - u;
-    Stencil st;
-    const bool inside = fan_stencil(f, rho, phi, st);
-    float left = 0.0f, right = 0.0f;
-    if (inside) {
-        const float *img = f.polar;
-        const long long r0 = (long long)st.i0 * f.n_az, r1 = (long long)st.i1 * f.n_az;
-        auto blend = [&](int j0, int j1, double s) {
-            const double a = img[r0 + j0], b = img[r0 + j1], c = img[r1 + j0], d = img[r1 + j1];
-            const double t = st.t;
-            return (float)((1.0 - t) * (1.0 - s) * a + (1.0 - t) * s * b + t * (1.0 - s) * c + t * s * d);
-        };
-        left = blend(st.j0, st.j1, st.s);
-        if (um != u) {
-            Stencil sr = st;
-            fan_angular(f, -phi, sr);
-            right = blend(sr.j0, sr.j1, sr.s);
-        }
+    // left-half pixel (v, u) and its mirror W-1-u: exact offsets from the apex
+    const double ax = (0.5 * (double)f.fan_w - (double)u - 0.5) * f.fan_s;   // = -x_c >= 0
+    const double ax2 = ax * ax;
+    const int row1 = f.n_range > 1 ? f.n_az : 0;
+    const int col1 = f.n_az > 1 ? 1 : 0;
+    const int mirror = f.n_az > 1 ? f.n_az - 2 : 0;
+    // geometry of every row first, then all gathers, then the blends: the
+    // loads of the rows are in flight together.  The mirror pixel's stencil
+    // is the left one's reflected: first column N_phi - 2 - j0, weights swapped.
+    int i0[kFanRows], jL[kFanRows];
+    float ct[kFanRows], cL[kFanRows];
+    bool in[kFanRows];
+#pragma unroll
+    for (int r = 0; r < kFanRows; ++r) {
+        const double yc = ((double)f.fan_h - (double)(v0 + 8 * r) - 0.5) * f.fan_s;
+        int jn;
+        float e;
+        const bool rin = fan_radial_fast(f, __builtin_fma(yc, yc, ax2), i0[r], ct[r]);
+        const bool ain = fan_angular_fast(f, ax, yc, jn, e);
+        in[r] = rin && ain;
+        axis_from_offset(jn, e, f.n_az, jL[r], cL[r]);
     }
-    row[u] = left;
-    if (um != u) row[um] = right;
-    if (f.stencil)
-        f.stencil[(long long)v * f.half_w + u] =
-            inside ? make_int4(st.i0, st.j0, __float_as_int(encode_weight(st.t)), __float_as_int(encode_weight(st.s)))
-                   : make_int4(-1, 0, 0, 0);
+    float a[kFanRows][8];
+#pragma unroll
+    for (int r = 0; r < kFanRows; ++r) {
+        const int b0 = (int)__umul24((unsigned)i0[r], (unsigned)f.n_az), b1 = b0 + row1;   // < 2^24 bins
+        const int jr = mirror - jL[r];
+        if (!in[r]) {
+#pragma unroll
+            for (int k = 0; k < 8; ++k) a[r][k] = 0.0f;
+            continue;
+        }
+        a[r][0] = polar_at(polar, b0 + jL[r]);
+        a[r][1] = polar_at(polar, b0 + jL[r] + col1);
+        a[r][2] = polar_at(polar, b1 + jL[r]);
+        a[r][3] = polar_at(polar, b1 + jL[r] + col1);
+        a[r][4] = polar_at(polar, b0 + jr);
+        a[r][5] = polar_at(polar, b0 + jr + col1);
+        a[r][6] = polar_at(polar, b1 + jr);
+        a[r][7] = polar_at(polar, b1 + jr + col1);
+    }
+    gptr<float> row = fan + (long long)v0 * f.fan_w;
+    gptr<int4> rec = f.stencil ? f.stencil + (long long)v0 * f.half_w + u : nullptr;
+    const long long row_step = 8LL * f.fan_w, rec_step = 8LL * f.half_w;
+#pragma unroll
+    for (int r = 0; r < kFanRows; ++r) {
+        if (v0 + 8 * r < f.fan_h) {
+            float t, t1, s, s1;
+            decode_weight(ct[r], t, t1);
+            decode_weight(cL[r], s, s1);
+            const float left = t1 * (s1 * a[r][0] + s * a[r][1]) + t * (s1 * a[r][2] + s * a[r][3]);
+            const float right = t1 * (s * a[r][4] + s1 * a[r][5]) + t * (s * a[r][6] + s1 * a[r][7]);
+            row[u] = in[r] ? left : 0.0f;
+            if (um != u) row[um] = in[r] ? right : 0.0f;
+            if (rec)
+                gstore(rec, in[r] ? make_int4(i0[r], jL[r], __float_as_int(ct[r]), __float_as_int(cL[r]))
+                                  : make_int4(-1, 0, 0, 0));
+        }
+        row += row_step;
+        if (rec) rec += rec_step;
+    }
 }
 
 // ---------------------------------------------------------------------------
 // k_tile_bwd
 // ---------------------------------------------------------------------------
-constexpr int kBwdThreads = 512;
 constexpr int kRowBatch = 1024;
 
 // Relative margin of the candidate bounds: far above FP64 rounding (1e-16)
@@ -317,10 +413,11 @@ __device__ __forceinline__ long long round_to_ll(double x) {
 
 // SAVED: every frame of the launch carries the stencils saved by its forward
 // pass (the geometry is not recomputed); otherwise frames may mix both kinds.
+// Backward polar tile `bid` of the n_blocks tiles of the launch (kBwdThreads
+// threads).
 template <class Src, bool SAVED>
-__global__ __launch_bounds__(kBwdThreads, 4) void k_tile_bwd(Src src, const oceansim_sonar_params *params,
-                                                          double *part, float *grad_refl_zero,
-                                                          int n_mat_zero) {
+__device__ __forceinline__ void tile_bwd_block(const Src &src, const oceansim_sonar_params *params, double *part,
+                                               float *grad_refl_zero, int n_mat_zero, int bid, int n_blocks) {
     constexpr int NT = kBwdThreads;
     extern __shared__ int4 lds_raw[];
     long long *acc = reinterpret_cast<long long *>(lds_raw);
@@ -334,15 +431,16 @@ __global__ __launch_bounds__(kBwdThreads, 4) void k_tile_bwd(Src src, const ocea
     __shared__ int sh_shift;
 
     int local;
-    const int fi = src.locate(blockIdx.x, KTILEB, local);
-    const SonarDev &f = src.frame(fi);
+    const int lid = xcd_grouped_id<8>(bid, n_blocks);   // also this tile's partial-sum slot
+    const int fi = src.locate(lid, KTILEB, local);
+    const SonarDev f = src.frame(fi);
     const int tile = f.n_tiles_b - 1 - local;   // outer tiles (most pixels) first
     const int tid = threadIdx.x;
     const int lane = tid & (kWave - 1), wave = tid / kWave;
 
     // the atomic reflectivity path (many materials) accumulates into a zeroed table
     if (grad_refl_zero)
-        for (int k = blockIdx.x * NT + tid; k < n_mat_zero; k += gridDim.x * NT) grad_refl_zero[k] = 0.0f;
+        for (int k = bid * NT + tid; k < n_mat_zero; k += n_blocks * NT) grad_refl_zero[k] = 0.0f;
 
     const int nb = f.n_range * f.n_az;
     const int b_lo = tile * f.tile_bins_b;
@@ -404,7 +502,7 @@ __global__ __launch_bounds__(kBwdThreads, 4) void k_tile_bwd(Src src, const ocea
                         if (k < ncand) {
                             const int r = cand_row[k];
                             const int u = row_u0[r] + (cb + k - row_pre[r]);
-                            const float *grow = f.grad_fan + (long long)(vb + r) * W;
+                            const gptr<const float> grow = f.grad_fan + (long long)(vb + r) * W;
                             ga[q] = grow[u];
                             gb[q] = grow[W - 1 - u];
                         }
@@ -467,11 +565,11 @@ __global__ __launch_bounds__(kBwdThreads, 4) void k_tile_bwd(Src src, const ocea
                             const int r = cand_row[k];
                             const int v = vb + r;
                             const int u = row_u0[r] + (cb + k - row_pre[r]);
-                            const float *grow = f.grad_fan + (long long)v * W;
+                            const gptr<const float> grow = f.grad_fan + (long long)v * W;
                             UU[q] = u;
                             G0[q] = grow[u];
                             G1[q] = (W - 1 - u) != u ? grow[W - 1 - u] : 0.0f;
-                            REC[q] = f.stencil[(long long)v * f.half_w + u];
+                            REC[q] = gload(f.stencil + ((long long)v * f.half_w + u));
                         }
                     }
 #pragma unroll
@@ -531,7 +629,7 @@ __global__ __launch_bounds__(kBwdThreads, 4) void k_tile_bwd(Src src, const ocea
                     const int v = vb + r;
                     const int u = row_u0[r] + (cb + k - row_pre[r]);
                     const int um = W - 1 - u;
-                    const float *grow = f.grad_fan + (long long)v * W;
+                    const gptr<const float> grow = f.grad_fan + (long long)v * W;
                     const float g0 = grow[u];
                     const float g1 = um != u ? grow[um] : 0.0f;
                     if (g0 == 0.0f && g1 == 0.0f) continue;
@@ -616,13 +714,38 @@ __global__ __launch_bounds__(kBwdThreads, 4) void k_tile_bwd(Src src, const ocea
     const double s_phi = block_sum<NT>(g_sphi, red);
     const double s_sa = block_sum<NT>(g_ssa, red);
     if (tid == 0) {
-        double *p = part + (long long)blockIdx.x * 5;
+        double *p = part + (long long)lid * 5;
         p[0] = 0.0;
         p[1] = 0.0;
         p[2] = s_phi;
         p[3] = s_sa;
         p[4] = 0.0;
     }
+}
+
+template <class Src, bool SAVED>
+__global__ __launch_bounds__(kBwdThreads, 4) void k_tile_bwd(Src src, const oceansim_sonar_params *params,
+                                                          double *part, float *grad_refl_zero,
+                                                          int n_mat_zero) {
+    tile_bwd_block<Src, SAVED>(src, params, part, grad_refl_zero, n_mat_zero, blockIdx.x, gridDim.x);
+}
+
+// The backward tiles and, in the same launch, the camera frames of a plan
+// (workgroups n_tile_blocks and up, kBwdThreads threads each): the
+// latency-bound tiles leave most of the machine idle, and the HBM-bound
+// camera adjoint fills it.
+template <class Src, bool SAVED>
+__global__ __launch_bounds__(kBwdThreads, 4) void k_tile_bwd_uw(Src src, const oceansim_sonar_params *params,
+                                                             double *part, float *grad_refl_zero,
+                                                             int n_mat_zero, int n_tile_blocks,
+                                                             Table<UwDev> usrc,
+                                                             const oceansim_water_params *wparams,
+                                                             double *upart, int *urow) {
+    __shared__ double red9[9 * (kBwdThreads / kWave)];
+    if ((int)blockIdx.x < n_tile_blocks)
+        tile_bwd_block<Src, SAVED>(src, params, part, grad_refl_zero, n_mat_zero, blockIdx.x, n_tile_blocks);
+    else
+        uw_bwd_block<Table<UwDev>, kBwdThreads>(usrc, wparams, upart, urow, blockIdx.x - n_tile_blocks, red9);
 }
 
 // ---------------------------------------------------------------------------
@@ -639,7 +762,7 @@ __global__ __launch_bounds__(kBlock) void k_ret_bwd(Src src, const oceansim_sona
     double *red = reinterpret_cast<double *>(lds_raw);
     int local;
     const int fi = src.locate(blockIdx.x, KRET, local);
-    const SonarDev &f = src.frame(fi);
+    const SonarDev f = src.frame(fi);
     const int tid = threadIdx.x;
     const bool lane_hist = refl_part != nullptr;
 
@@ -718,7 +841,7 @@ __global__ __launch_bounds__(kBlock) void k_reduce_sonar(Src src, int n_frames, 
         const int r = b / OCEANSIM_SONAR_GRAD_WIDTH, c = b % OCEANSIM_SONAR_GRAD_WIDTH;
         if (c < 5) {
             for (int fi = 0; fi < n_frames; ++fi) {
-                const SonarDev &f = src.frame(fi);
+                const SonarDev f = src.frame(fi);
                 if (f.param_row != r) continue;
                 for (int k = threadIdx.x; k < f.n_tiles_b; k += kBlock)
                     s += part[(long long)(f.blk[KTILEB] + k) * 5 + c];
@@ -751,7 +874,7 @@ __global__ __launch_bounds__(kBlock) void k_reduce_sonar(Src src, int n_frames, 
 
 template <class Src>
 static hipError_t launch_fwd(const Src &src, const SonarGrid &g, const oceansim_sonar_params *params,
-                             const float *refl, int n_mat, hipStream_t st) {
+                             const float *refl, int n_mat, hipStream_t st, const UwCompanion *uw) {
     if (g.bin_blocks > 0) {
         const size_t lds = (size_t)((g.max_tiles + 1 + 3) & ~3) * 4 + (size_t)g.chunk * 8;
         OSIM_DISPATCH_R(g.chunk / kBlock,
@@ -760,8 +883,13 @@ static hipError_t launch_fwd(const Src &src, const SonarGrid &g, const oceansim_
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
-    OSIM_LAUNCH("k_tile", (k_tile<Src>), dim3(g.tile_blocks), dim3(kBlock), (size_t)g.max_tile_bins * 8, st,
-                       src, params);
+    if (uw && uw->blocks > 0)
+        OSIM_LAUNCH("k_tile_uw", (k_tile_uw<Src>), dim3(g.tile_blocks + uw->blocks), dim3(kBlock),
+                    (size_t)g.max_tile_bins * 8, st, src, params, g.tile_blocks, Table<UwDev>{uw->table, uw->n},
+                    uw->params);
+    else
+        OSIM_LAUNCH("k_tile", (k_tile<Src>), dim3(g.tile_blocks), dim3(kBlock), (size_t)g.max_tile_bins * 8, st,
+                    src, params);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     if (g.fan_blocks > 0) {
@@ -775,10 +903,24 @@ template <class Src>
 static hipError_t launch_bwd(const Src &src, int n_frames, const SonarGrid &g,
                              const oceansim_sonar_params *params, int n_rows, const float *refl, int n_mat,
                              double *part, double *refl_part, float *grad_params, float *grad_refl,
-                             hipStream_t st) {
+                             hipStream_t st, const UwCompanion *uw) {
     const bool lane_hist = n_mat <= kLaneHistMats;
     hipError_t e = hipSuccess;
-    if (g.tile_b_blocks > 0) {
+    if (uw && uw->blocks > 0) {
+        const Table<UwDev> us{uw->table, uw->n};
+        if (g.all_saved)
+            OSIM_LAUNCH("k_tile_bwd_uw", (k_tile_bwd_uw<Src, true>), dim3(g.tile_b_blocks + uw->blocks),
+                        dim3(kBwdThreads), (size_t)g.max_tile_bins_b * 8, st, src, params, part,
+                        lane_hist ? (float *)nullptr : grad_refl, n_mat, g.tile_b_blocks, us, uw->params, uw->part,
+                        uw->part_row);
+        else
+            OSIM_LAUNCH("k_tile_bwd_uw", (k_tile_bwd_uw<Src, false>), dim3(g.tile_b_blocks + uw->blocks),
+                        dim3(kBwdThreads), (size_t)g.max_tile_bins_b * 8, st, src, params, part,
+                        lane_hist ? (float *)nullptr : grad_refl, n_mat, g.tile_b_blocks, us, uw->params, uw->part,
+                        uw->part_row);
+        e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    } else if (g.tile_b_blocks > 0) {
         if (g.all_saved)
             OSIM_LAUNCH("k_tile_bwd", (k_tile_bwd<Src, true>), dim3(g.tile_b_blocks), dim3(kBwdThreads),
                         (size_t)g.max_tile_bins_b * 8, st, src, params, part,
@@ -813,25 +955,25 @@ static hipError_t launch_bwd(const Src &src, int n_frames, const SonarGrid &g,
 
 hipError_t sonar_forward_one(const SonarDev &f, const SonarGrid &g, const oceansim_sonar_params *params,
                              const float *refl, int n_mat, hipStream_t st) {
-    return launch_fwd(One<SonarDev>{f}, g, params, refl, n_mat, st);
+    return launch_fwd(One<SonarDev>{f}, g, params, refl, n_mat, st, nullptr);
 }
 hipError_t sonar_forward_table(const SonarDev *t, int n, const SonarGrid &g,
                                const oceansim_sonar_params *params, const float *refl, int n_mat,
-                               hipStream_t st) {
-    return launch_fwd(Table<SonarDev>{t, n}, g, params, refl, n_mat, st);
+                               hipStream_t st, const UwCompanion *uw) {
+    return launch_fwd(Table<SonarDev>{t, n}, g, params, refl, n_mat, st, uw);
 }
 hipError_t sonar_backward_one(const SonarDev &f, const SonarGrid &g, const oceansim_sonar_params *params,
                               int n_rows, const float *refl, int n_mat, double *part, double *refl_part,
                               float *grad_params, float *grad_refl, hipStream_t st) {
     return launch_bwd(One<SonarDev>{f}, 1, g, params, n_rows, refl, n_mat, part, refl_part, grad_params,
-                      grad_refl, st);
+                      grad_refl, st, nullptr);
 }
 hipError_t sonar_backward_table(const SonarDev *t, int n, const SonarGrid &g,
                                 const oceansim_sonar_params *params, int n_rows, const float *refl,
                                 int n_mat, double *part, double *refl_part, float *grad_params,
-                                float *grad_refl, hipStream_t st) {
+                                float *grad_refl, hipStream_t st, const UwCompanion *uw) {
     return launch_bwd(Table<SonarDev>{t, n}, n, g, params, n_rows, refl, n_mat, part, refl_part, grad_params,
-                      grad_refl, st);
+                      grad_refl, st, uw);
 }
 
 }  // namespace osim

@@ -1,0 +1,214 @@
+// Underwater colour image formation, Eq. (1) of arXiv 2503.01074 (Sec. III-A.1),
+// and its adjoint: per-pixel formulas and the work of one workgroup, shared
+// by the camera kernels and by the sonar kernels that carry camera frames
+// along in the same launch (internal).
+//
+//   I_c = J_c exp(-beta_D,c d) + B_inf,c (1 - exp(-beta_B,c d))
+#pragma once
+
+#include "device.hpp"
+#include "launch.hpp"
+
+namespace osim {
+
+struct Water {
+    float bd[3], bb[3], bi[3];
+};
+
+__device__ __forceinline__ Water load_water(const oceansim_water_params *p, int row) {
+    Water w;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        w.bd[c] = p[row].beta_d[c];
+        w.bb[c] = p[row].beta_b[c];
+        w.bi[c] = p[row].b_inf[c];
+    }
+    return w;
+}
+
+// beta * d, taken as 0 when beta = 0 (so an infinite depth leaves the term alone)
+__device__ __forceinline__ float bdprod(float beta, float d) { return beta == 0.0f ? 0.0f : beta * d; }
+
+// e^x for x <= 0 (also -inf and NaN): the hardware 2^y, with the product
+// x log2(e) carried to ~2^-48 relative in y + lo so that its rounding does
+// not reach the result (a few ulp over the whole range, against the plain
+// 2^(x log2 e), whose error grows with |x|).  Below 2^-150 the result is 0.
+__device__ __forceinline__ float exp_nonpos(float x) {
+    const float kLog2eHi = 1.44269502f;          // log2(e) rounded to float
+    const float kLog2eLo = 1.92596299e-8f;       // log2(e) - kLog2eHi
+    const float y = x * kLog2eHi;
+    if (y < -150.0f) return 0.0f;
+    const float lo = __builtin_fmaf(x, kLog2eHi, -y) + x * kLog2eLo;
+    return __builtin_amdgcn_exp2f(y) * __builtin_fmaf(lo, 0.693147182f, 1.0f);
+}
+
+// 1 - e^-x for x >= 0, given e = e^-x: the difference where it loses at most
+// two bits (x > 1/4), else the Taylor series of -expm1(-x) to x^7 (its
+// remainder is below 2e-9 relative there).
+__device__ __forceinline__ float one_minus_exp_neg(float x, float e) {
+    if (x > 0.25f) return 1.0f - e;
+    float p = 1.0f / 5040.0f;
+    p = __builtin_fmaf(p, x, -1.0f / 720.0f);
+    p = __builtin_fmaf(p, x, 1.0f / 120.0f);
+    p = __builtin_fmaf(p, x, -1.0f / 24.0f);
+    p = __builtin_fmaf(p, x, 1.0f / 6.0f);
+    p = __builtin_fmaf(p, x, -0.5f);
+    p = __builtin_fmaf(p, x, 1.0f);
+    return p * x;
+}
+
+__device__ __forceinline__ float uw_pixel(float J, float d, float bd, float bb, float bi) {
+    const float T = exp_nonpos(-bdprod(bd, d));
+    const float xb = bdprod(bb, d);
+    const float S1 = one_minus_exp_neg(xb, exp_nonpos(-xb));
+    return J * T + bi * S1;
+}
+
+// Workgroup `bid` (of NT threads) of a forward launch over the frames of src:
+// kUwFwdPixelsPerThread pixels per thread, as float4 groups.
+template <class Src, int NT>
+__device__ __forceinline__ void uw_fwd_block(const Src &src, const oceansim_water_params *params, int bid) {
+    int local;
+    const int fi = src.locate(bid, 0, local);
+    const UwDev f = src.frame(fi);
+    const Water w = load_water(params, f.param_row);
+    const long long npix = f.npix;
+    const long long p0 = (long long)local * (NT * kUwFwdPixelsPerThread);
+    // restrict-qualified views (the output never aliases the inputs), so the
+    // loads of every iteration can be in flight before the first store
+    const gptr<const float> __restrict__ Jp = f.J;
+    const gptr<const float> __restrict__ Dp = f.depth;
+    const gptr<float> __restrict__ Op = f.out;
+    constexpr int kIt = (NT * kUwFwdPixelsPerThread) / (NT * 4);
+    if ((npix & 3) == 0 && p0 + (NT * kUwFwdPixelsPerThread) <= npix) {
+        float4 d[kIt], J[kIt][3];
+#pragma unroll
+        for (int it = 0; it < kIt; ++it) {
+            const long long p = p0 + ((long long)it * NT + threadIdx.x) * 4;
+            d[it] = gload((gptr<const float4>)(Dp + p));
+#pragma unroll
+            for (int c = 0; c < 3; ++c) J[it][c] = gload((gptr<const float4>)(Jp + c * npix + p));
+        }
+#pragma unroll
+        for (int it = 0; it < kIt; ++it) {
+            const long long p = p0 + ((long long)it * NT + threadIdx.x) * 4;
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                float4 o;
+                o.x = uw_pixel(J[it][c].x, d[it].x, w.bd[c], w.bb[c], w.bi[c]);
+                o.y = uw_pixel(J[it][c].y, d[it].y, w.bd[c], w.bb[c], w.bi[c]);
+                o.z = uw_pixel(J[it][c].z, d[it].z, w.bd[c], w.bb[c], w.bi[c]);
+                o.w = uw_pixel(J[it][c].w, d[it].w, w.bd[c], w.bb[c], w.bi[c]);
+                gstore((gptr<float4>)(Op + c * npix + p), o);
+            }
+        }
+        return;
+    }
+    // ragged tail (or an image whose size is not a multiple of 4): per pixel
+    for (int it = 0; it < kIt; ++it) {
+        const long long p = p0 + ((long long)it * NT + threadIdx.x) * 4;
+        for (long long q = p; q < p + 4 && q < npix; ++q) {
+            const float d = Dp[q];
+#pragma unroll
+            for (int c = 0; c < 3; ++c) Op[c * npix + q] = uw_pixel(Jp[c * npix + q], d, w.bd[c], w.bb[c], w.bi[c]);
+        }
+    }
+}
+
+// Adjoint of Eq. (1) at one pixel and channel; accumulates the parameter
+// gradients and returns dL/dJ, adding this channel's share of dL/dd.
+__device__ __forceinline__ float uw_pixel_bwd(float g, float J, float d, float bd, float bb, float bi,
+                                              float acc[9], int c, float &gd) {
+    const float T = exp_nonpos(-bdprod(bd, d));
+    const float xb = bdprod(bb, d);
+    const float S = exp_nonpos(-xb);
+    const float S1 = one_minus_exp_neg(xb, S);
+    // the d-weighted terms vanish where T or S does (0 * inf := 0)
+    if (T != 0.0f) acc[c] += g * (-J * T * d);
+    if (S != 0.0f) acc[3 + c] += g * (bi * S * d);
+    acc[6 + c] += g * S1;
+    gd += g * (-bd * J * T + bi * bb * S);
+    return g * T;
+}
+
+// Workgroup `bid` (of NT threads) of a backward launch: kUwBwdPixelsPerThread
+// pixels per thread; the nine parameter partial sums of the workgroup go to
+// part[bid] (FP64, fixed order) and its parameter row to part_row[bid].
+// `red9` is LDS of 9 * NT / 64 doubles.
+template <class Src, int NT>
+__device__ __forceinline__ void uw_bwd_block(const Src &src, const oceansim_water_params *params, double *part,
+                                             int *part_row, int bid, double *red9) {
+    int local;
+    const int fi = src.locate(bid, 0, local);
+    const UwDev f = src.frame(fi);
+    const Water w = load_water(params, f.param_row);
+    const long long npix = f.npix;
+    const long long p0 = (long long)local * (NT * kUwBwdPixelsPerThread);
+    const gptr<const float> __restrict__ Jp = f.J;
+    const gptr<const float> __restrict__ Dp = f.depth;
+    const gptr<const float> __restrict__ Gp = f.grad_out;
+    const gptr<float> __restrict__ GJ = f.grad_J;
+    const gptr<float> __restrict__ GD = f.grad_depth;
+    constexpr int kIt = (NT * kUwBwdPixelsPerThread) / (NT * 4);
+    // per-thread partial sums of 8 pixels in FP32 (|error| <= ~5e-7 of the sum
+    // of the magnitudes), then FP64 across threads and workgroups
+    float acc[9];
+#pragma unroll
+    for (int k = 0; k < 9; ++k) acc[k] = 0.0f;
+    if ((npix & 3) == 0 && p0 + (NT * kUwBwdPixelsPerThread) <= npix) {
+#pragma unroll
+        for (int it = 0; it < kIt; it += 2) {
+            // two iterations' loads in flight together
+            float4 d[2], J[2][3], g[2][3];
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                const long long p = p0 + ((long long)(it + h) * NT + threadIdx.x) * 4;
+                d[h] = gload((gptr<const float4>)(Dp + p));
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    J[h][c] = gload((gptr<const float4>)(Jp + c * npix + p));
+                    g[h][c] = gload((gptr<const float4>)(Gp + c * npix + p));
+                }
+            }
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                const long long p = p0 + ((long long)(it + h) * NT + threadIdx.x) * 4;
+                float4 gdv = make_float4(0.f, 0.f, 0.f, 0.f);
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    float4 gj;
+                    gj.x = uw_pixel_bwd(g[h][c].x, J[h][c].x, d[h].x, w.bd[c], w.bb[c], w.bi[c], acc, c, gdv.x);
+                    gj.y = uw_pixel_bwd(g[h][c].y, J[h][c].y, d[h].y, w.bd[c], w.bb[c], w.bi[c], acc, c, gdv.y);
+                    gj.z = uw_pixel_bwd(g[h][c].z, J[h][c].z, d[h].z, w.bd[c], w.bb[c], w.bi[c], acc, c, gdv.z);
+                    gj.w = uw_pixel_bwd(g[h][c].w, J[h][c].w, d[h].w, w.bd[c], w.bb[c], w.bi[c], acc, c, gdv.w);
+                    if (GJ) gstore((gptr<float4>)(GJ + c * npix + p), gj);
+                }
+                if (GD) gstore((gptr<float4>)(GD + p), gdv);
+            }
+        }
+    } else {
+        // ragged tail (or an image whose size is not a multiple of 4): per pixel
+        for (int it = 0; it < kIt; ++it) {
+            const long long p = p0 + ((long long)it * NT + threadIdx.x) * 4;
+            for (long long q = p; q < p + 4 && q < npix; ++q) {
+                const float d = Dp[q];
+                float gd = 0.0f;
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    const float gj = uw_pixel_bwd(Gp[c * npix + q], Jp[c * npix + q], d, w.bd[c], w.bb[c],
+                                                  w.bi[c], acc, c, gd);
+                    if (GJ) GJ[c * npix + q] = gj;
+                }
+                if (GD) GD[q] = gd;
+            }
+        }
+    }
+    double accd[9];
+#pragma unroll
+    for (int k = 0; k < 9; ++k) accd[k] = (double)acc[k];
+    const double tot = block_sum_n<9, NT>(accd, red9);
+    if (threadIdx.x < 9) part[(long long)bid * 9 + threadIdx.x] = tot;
+    if (threadIdx.x == 0) part_row[bid] = f.param_row;
+}
+
+}  // namespace osim
