@@ -52,16 +52,14 @@ struct SonarGrid {
 
 constexpr int kBwdThreads = 512;   // threads of a backward polar-tile workgroup
 
-// Camera frames carried along in the launch of a sonar kernel (plans with both
-// kinds of frames): device frame table, workgroups (planned for the thread
-// count of that sonar kernel), parameters and, backward, the partial sums.
+// Camera frames carried along in the forward polar-tile launch of a plan
+// with both kinds of frames: device frame table, workgroups (kBlock threads
+// each) and the water parameters.
 struct UwCompanion {
     const UwDev *table = nullptr;
     int n = 0;
     int blocks = 0;
     const oceansim_water_params *params = nullptr;
-    double *part = nullptr;
-    int *part_row = nullptr;
 };
 
 hipError_t sonar_forward_one(const SonarDev &f, const SonarGrid &g, const oceansim_sonar_params *params,
@@ -78,7 +76,7 @@ hipError_t sonar_backward_one(const SonarDev &f, const SonarGrid &g, const ocean
 hipError_t sonar_backward_table(const SonarDev *t, int n, const SonarGrid &g,
                                 const oceansim_sonar_params *params, int n_rows, const float *refl,
                                 int n_mat, double *part, double *refl_part, float *grad_params,
-                                float *grad_refl, hipStream_t st, const UwCompanion *uw = nullptr);
+                                float *grad_refl, hipStream_t st);
 
 // Camera pixels per thread: one float4 group forward, two backward (the
 // per-workgroup parameter partial sums amortised over 8 pixels).

@@ -39,8 +39,8 @@ struct oceansim_plan {
     char *stencil_mem = nullptr;
     char *ws_sf = nullptr, *ws_sb = nullptr, *ws_uf = nullptr, *ws_ub = nullptr;
     hipStream_t cap = nullptr;   // capture stream (default priority)
-    // with both kinds of frames the camera frames ride along in the launches
-    // of the sonar tile kernels (one dispatch each way)
+    // with both kinds of frames the camera frames ride along in the forward
+    // polar-tile launch of the sonar frames
     bool fused = false;
     hipGraphExec_t g_fwd = nullptr, g_bwd = nullptr;
 };
@@ -62,18 +62,12 @@ __global__ void k_count_disagree(const float *a, const float *b, long long n, fl
     if (local) atomicAdd(bad, local);
 }
 
-UwCompanion companion(oceansim_plan *p, bool backward) {
+UwCompanion companion(oceansim_plan *p) {
     UwCompanion c;
-    const UwPlan &u = backward ? p->ub : p->uf;
-    char *ws = backward ? p->ws_ub : p->ws_uf;
-    c.table = reinterpret_cast<const UwDev *>(ws + u.off_table);
+    c.table = reinterpret_cast<const UwDev *>(p->ws_uf + p->uf.off_table);
     c.n = (int)p->camera.size();
-    c.blocks = u.blocks;
+    c.blocks = p->uf.blocks;
     c.params = p->wp;
-    if (backward) {
-        c.part = reinterpret_cast<double *>(ws + u.off_part);
-        c.part_row = reinterpret_cast<int *>(ws + u.off_part_row);
-    }
     return c;
 }
 
@@ -103,7 +97,7 @@ hipError_t camera_backward(oceansim_plan *p, hipStream_t st) {
 
 hipError_t launch_forward(oceansim_plan *p, hipStream_t st) {
     if (p->sonar.empty()) return camera_forward(p, st);
-    const UwCompanion c = p->fused ? companion(p, false) : UwCompanion{};
+    const UwCompanion c = p->fused ? companion(p) : UwCompanion{};
     hipError_t e = sonar_forward_table(reinterpret_cast<const SonarDev *>(p->ws_sf + p->sf.off_table),
                                        (int)p->sonar.size(), p->sf.grid, p->sp, p->refl, p->n_mat, st,
                                        p->fused ? &c : nullptr);
@@ -114,15 +108,14 @@ hipError_t launch_forward(oceansim_plan *p, hipStream_t st) {
 hipError_t launch_backward(oceansim_plan *p, hipStream_t st) {
     if (p->sonar.empty()) return camera_backward(p, st);
     const bool lane_hist = p->n_mat <= kLaneHistMats;
-    const UwCompanion c = p->fused ? companion(p, true) : UwCompanion{};
     hipError_t e = sonar_backward_table(reinterpret_cast<const SonarDev *>(p->ws_sb + p->sb.off_table),
                                         (int)p->sonar.size(), p->sb.grid, p->sp, p->n_srows, p->refl, p->n_mat,
                                         reinterpret_cast<double *>(p->ws_sb + p->sb.off_part),
                                         lane_hist ? reinterpret_cast<double *>(p->ws_sb + p->sb.off_refl_part)
                                                   : nullptr,
-                                        p->g_sp, p->g_refl, st, p->fused ? &c : nullptr);
+                                        p->g_sp, p->g_refl, st);
     if (e != hipSuccess) return e;
-    return p->fused ? camera_reduce(p, st) : camera_backward(p, st);
+    return camera_backward(p, st);
 }
 
 // ---------------------------------------------------------------------------
@@ -493,9 +486,7 @@ int oceansim_plan_create(const oceansim_sonar_frame *sonar, int32_t n_sonar, con
     p->fused = n_sonar > 0 && n_camera > 0;
     if (!rc && n_camera > 0) {
         rc = plan_uw(p->camera.data(), n_camera, n_water_rows, false, p->uf, true);
-        if (!rc && bwd)
-            rc = plan_uw(p->camera.data(), n_camera, n_water_rows, true, p->ub, true,
-                         p->fused ? kBwdThreads : kBlock);
+        if (!rc && bwd) rc = plan_uw(p->camera.data(), n_camera, n_water_rows, true, p->ub, true);
     }
     if (rc) {
         delete p;

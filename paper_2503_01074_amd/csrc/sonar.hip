@@ -361,7 +361,7 @@ constexpr double kCandEps = 1e-7;
 // Left-half pixel interval [ua, ub] of fan row v whose centres lie within
 // radial distance [rlo, rhi] of the apex and inside the sector; the exact
 // stencil test decides membership.
-__device__ __forceinline__ void row_interval(const SonarDev &f, int v, double rlo, double rhi,
+__device__ __forceinline__ void row_interval(const SonarDev &f, int v, double rlo, double rhi, double inv_s,
                                              int &ua, int &ub) {
     const double s = f.fan_s;
     const double y = ((double)f.fan_h - (double)v - 0.5) * s;
@@ -377,7 +377,7 @@ __device__ __forceinline__ void row_interval(const SonarDev &f, int v, double rl
     if (xi > xo) return;
     // left half: x in [-xo, -xi]  ->  u = x / s + W/2 - 1/2
     const double c = 0.5 * (double)f.fan_w - 0.5;
-    const double a = -xo / s + c, b = -xi / s + c;
+    const double a = -xo * inv_s + c, b = -xi * inv_s + c;
     int lo = (int)__builtin_ceil(a - 1e-6), hi = (int)__builtin_floor(b + 1e-6);
     lo = lo < 0 ? 0 : lo;
     hi = hi > f.half_w - 1 ? f.half_w - 1 : hi;
@@ -386,23 +386,50 @@ __device__ __forceinline__ void row_interval(const SonarDev &f, int v, double rl
 }
 
 // Candidate pixels of a tile, one batch of fan rows at a time: per-row
-// intervals and their exclusive prefix in LDS.  Returns the batch total.
+// intervals and their exclusive prefix in LDS (kRowBatch / NT rows per
+// thread, one workgroup scan).  Returns the batch total.
 template <int NT>
 __device__ __forceinline__ int load_row_batch(const SonarDev &f, int vb, int nrows, double rlo, double rhi,
-                                              int *row_u0, int *row_pre, int *scan_tmp) {
+                                              double inv_s, int *row_u0, int *row_pre, int *wtot) {
+    constexpr int RPT = kRowBatch / NT;
     __syncthreads();
-    for (int rr = threadIdx.x; rr < nrows; rr += NT) {
-        int ua, ub;
-        row_interval(f, vb + rr, rlo, rhi, ua, ub);
-        row_u0[rr] = ua;
-        row_pre[rr] = ub >= ua ? ub - ua + 1 : 0;
+    int cnt[RPT];
+    int sum = 0;
+#pragma unroll
+    for (int q = 0; q < RPT; ++q) {
+        const int rr = threadIdx.x * RPT + q;
+        cnt[q] = 0;
+        if (rr < nrows) {
+            int ua, ub;
+            row_interval(f, vb + rr, rlo, rhi, inv_s, ua, ub);
+            row_u0[rr] = ua;
+            cnt[q] = ub >= ua ? ub - ua + 1 : 0;
+        }
+        sum += cnt[q];
     }
+    int total;
+    int run = block_inclusive_scan1<NT>(sum, wtot, total) - sum;
+#pragma unroll
+    for (int q = 0; q < RPT; ++q) {
+        const int rr = threadIdx.x * RPT + q;
+        if (rr < nrows) row_pre[rr] = run;
+        run += cnt[q];
+    }
+    if (threadIdx.x == 0) row_pre[nrows] = total;
     __syncthreads();
-    block_exclusive_scan<NT>(row_pre, nrows, scan_tmp);
-    return row_pre[nrows];
+    return total;
 }
 
-constexpr int kCandBatch = 8192;     // candidates per sub-batch (uint16 row index each)
+// Row of candidate k within a batch: the last r with row_pre[r] <= k.
+__device__ __forceinline__ int row_of(const int *row_pre, int nrows, int k) {
+    int lo = 0, hi = nrows - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (row_pre[mid] <= k) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+
 
 // Round x (|x| < 2^51) to the nearest integer, as an int64, by adding
 // 1.5 * 2^52: the sum's mantissa then holds the integer offset by 2^51.
@@ -423,8 +450,7 @@ __device__ __forceinline__ void tile_bwd_block(const Src &src, const oceansim_so
     long long *acc = reinterpret_cast<long long *>(lds_raw);
     __shared__ int row_u0[kRowBatch];
     __shared__ int row_pre[kRowBatch + 1];
-    __shared__ unsigned short cand_row[kCandBatch];
-    __shared__ int scan_tmp[NT];
+    __shared__ int wtot[NT / kWave];
     __shared__ unsigned poison[kMaxTileBins / 32];
     __shared__ double red[NT / kWave];
     __shared__ int sh_exp;        // fixed-point exponent: values are stored times 2^(50 - sh_exp)
@@ -479,40 +505,45 @@ __device__ __forceinline__ void tile_bwd_block(const Src &src, const oceansim_so
         const double wr = 2.0 * f.dr, wa = 2.0 * f.dphi * rhi;
         const double pix_bound = 2.0 * ((wr * wa + 1.5 * s * 2.0 * (wr + wa)) / (s * s) + 8.0) + 16.0;
 
+        const double inv_s = 1.0 / s;
         for (int vb = v_lo; vb <= v_hi; vb += kRowBatch) {
             const int nrows = min(kRowBatch, v_hi - vb + 1);
-            const int total = load_row_batch<NT>(f, vb, nrows, rlo, rhi, row_u0, row_pre, scan_tmp);
-            for (int cb = 0; cb < total; cb += kCandBatch) {
-                const int ncand = min(kCandBatch, total - cb);
-                // candidate -> row table for [cb, cb + ncand)
-                for (int r = tid; r < nrows; r += NT) {
-                    const int lo = max(row_pre[r], cb), hi = min(row_pre[r + 1], cb + ncand);
-                    for (int k = lo; k < hi; ++k) cand_row[k - cb] = (unsigned short)r;
-                }
-                __syncthreads();
-                // largest finite |gradient| of this sub-batch (eight candidates
-                // per thread in flight)
+            const int total = load_row_batch<NT>(f, vb, nrows, rlo, rhi, inv_s, row_u0, row_pre, wtot);
+            // Rounds of U candidates per thread: the gradient pair (and the saved
+            // stencil) of every candidate is loaded once, into registers; the
+            // round's largest finite |gradient| sets the fixed-point scale
+            // (what is accumulated is rescaled by an arithmetic shift when it
+            // grows); then the contributions go to LDS from the registers.
+            constexpr int U = SAVED ? 4 : 1;
+            for (int k0 = 0; k0 < total; k0 += U * NT) {
+                float G0[U], G1[U];
+                int4 REC[U];
+                int UU[U], VV[U];
                 float mxf = 0.0f;
-                for (int k0 = tid; k0 < ncand; k0 += 8 * NT) {
-                    float ga[8], gb[8];
 #pragma unroll
-                    for (int q = 0; q < 8; ++q) {
-                        const int k = k0 + q * NT;
-                        ga[q] = gb[q] = 0.0f;
-                        if (k < ncand) {
-                            const int r = cand_row[k];
-                            const int u = row_u0[r] + (cb + k - row_pre[r]);
-                            const gptr<const float> grow = f.grad_fan + (long long)(vb + r) * W;
-                            ga[q] = grow[u];
-                            gb[q] = grow[W - 1 - u];
-                        }
+                for (int q = 0; q < U; ++q) {
+                    const int k = k0 + q * NT + tid;
+                    G0[q] = G1[q] = 0.0f;
+                    REC[q] = make_int4(-1, 0, 0, 0);
+                    UU[q] = -1;
+                    VV[q] = 0;
+                    if (k < total) {
+                        const int r = row_of(row_pre, nrows, k);
+                        const int v = vb + r;
+                        const int u = row_u0[r] + (k - row_pre[r]);
+                        const gptr<const float> grow = f.grad_fan + (long long)v * W;
+                        UU[q] = u;
+                        VV[q] = v;
+                        G0[q] = grow[u];
+                        G1[q] = (W - 1 - u) != u ? grow[W - 1 - u] : 0.0f;
+                        if (SAVED || f.stencil) REC[q] = gload(f.stencil + ((long long)v * f.half_w + u));
                     }
+                }
 #pragma unroll
-                    for (int q = 0; q < 8; ++q) {
-                        const float a0 = __builtin_fabsf(ga[q]), a1 = __builtin_fabsf(gb[q]);
-                        if (a0 <= 3.4028235e38f && a0 > mxf) mxf = a0;
-                        if (a1 <= 3.4028235e38f && a1 > mxf) mxf = a1;
-                    }
+                for (int q = 0; q < U; ++q) {
+                    const float a0 = __builtin_fabsf(G0[q]), a1 = __builtin_fabsf(G1[q]);
+                    if (a0 <= 3.4028235e38f && a0 > mxf) mxf = a0;
+                    if (a1 <= 3.4028235e38f && a1 > mxf) mxf = a1;
                 }
                 double mx = (double)mxf;
                 for (int off = 32; off > 0; off >>= 1) {
@@ -547,37 +578,14 @@ __device__ __forceinline__ void tile_bwd_block(const Src &src, const oceansim_so
                 }
                 // no nonzero finite value yet: only non-finite ones (poison) can act
                 const double scale = sh_exp == -100000 ? 0.0 : ldexp(1.0, 50 - sh_exp);
-                if (SAVED || f.stencil) {
-                    // stencils saved by the forward pass; four candidates per
-                    // thread with their loads issued before any is used
-                    constexpr int U = SAVED ? 4 : 1;
-                    for (int k0 = tid; k0 < ncand; k0 += U * NT) {
-                    float G0[U], G1[U];
-                    int4 REC[U];
-                    int UU[U];
 #pragma unroll
-                    for (int q = 0; q < U; ++q) {
-                        const int k = k0 + q * NT;
-                        G0[q] = G1[q] = 0.0f;
-                        REC[q] = make_int4(-1, 0, 0, 0);
-                        UU[q] = -1;
-                        if (k < ncand) {
-                            const int r = cand_row[k];
-                            const int v = vb + r;
-                            const int u = row_u0[r] + (cb + k - row_pre[r]);
-                            const gptr<const float> grow = f.grad_fan + (long long)v * W;
-                            UU[q] = u;
-                            G0[q] = grow[u];
-                            G1[q] = (W - 1 - u) != u ? grow[W - 1 - u] : 0.0f;
-                            REC[q] = gload(f.stencil + ((long long)v * f.half_w + u));
-                        }
-                    }
-#pragma unroll
-                    for (int q = 0; q < U; ++q) {
-                        const int u = UU[q];
-                        const int um = W - 1 - u;
-                        const float g0 = G0[q], g1 = G1[q];
-                        if (u < 0 || (g0 == 0.0f && g1 == 0.0f)) continue;
+                for (int q = 0; q < U; ++q) {
+                    const int u = UU[q];
+                    const int um = W - 1 - u;
+                    const float g0 = G0[q], g1 = G1[q];
+                    if (u < 0 || (g0 == 0.0f && g1 == 0.0f)) continue;
+                    if (SAVED || f.stencil) {
+                        // stencil saved by the forward pass
                         const int4 rec = REC[q];
                         const int i0 = rec.x;
                         if (i0 < 0) continue;
@@ -618,63 +626,52 @@ __device__ __forceinline__ void tile_bwd_block(const Src &src, const oceansim_so
                                 }
                             }
                         }
-                    }
-                    }
-                    __syncthreads();
-                    continue;
-                }
-                if (SAVED) continue;   // not reached: every frame has saved stencils
-                for (int k = tid; k < ncand; k += NT) {
-                    const int r = cand_row[k];
-                    const int v = vb + r;
-                    const int u = row_u0[r] + (cb + k - row_pre[r]);
-                    const int um = W - 1 - u;
-                    const gptr<const float> grow = f.grad_fan + (long long)v * W;
-                    const float g0 = grow[u];
-                    const float g1 = um != u ? grow[um] : 0.0f;
-                    if (g0 == 0.0f && g1 == 0.0f) continue;
-                    const double ax = (0.5 * (double)W - (double)u - 0.5) * s;
-                    const double yc = (H - (double)v - 0.5) * s;
-                    const double rho2 = ax * ax + yc * yc;
-                    if (rho2 < rlo2 || rho2 > rhi2) continue;
-                    Stencil st;
-                    if (!fan_radial(f, __builtin_sqrt(rho2), st)) continue;
-                    if (st.i1 < ia || st.i0 >= ib) continue;
-                    const double phi = atan2(ax, yc);
-                    for (int side = 0; side < 2; ++side) {
-                        if (side == 1 && um == u) break;
-                        const float g = side == 0 ? g0 : g1;
-                        if (g == 0.0f) continue;
-                        if (!fan_angular(f, side == 0 ? phi : -phi, st)) continue;
-                        const bool finite = __builtin_isfinite(g);
-                        const double gd = (double)g * scale;
-                        const double wr0 = (1.0 - st.t) * gd, wr1 = st.t * gd;
-                        const double wc0 = 1.0 - st.s, wc1 = st.s;
-                        const bool two_rows = st.i1 != st.i0, two_cols = st.j1 != st.j0;
+                    } else if (!SAVED) {
+                        // geometry recomputed in FP64
+                        const int v = VV[q];
+                        const double ax = (0.5 * (double)W - (double)u - 0.5) * s;
+                        const double yc = (H - (double)v - 0.5) * s;
+                        const double rho2 = ax * ax + yc * yc;
+                        if (rho2 < rlo2 || rho2 > rhi2) continue;
+                        Stencil st;
+                        if (!fan_radial(f, __builtin_sqrt(rho2), st)) continue;
+                        if (st.i1 < ia || st.i0 >= ib) continue;
+                        const double phi = atan2(ax, yc);
+                        for (int side = 0; side < 2; ++side) {
+                            if (side == 1 && um == u) break;
+                            const float g = side == 0 ? g0 : g1;
+                            if (g == 0.0f) continue;
+                            if (!fan_angular(f, side == 0 ? phi : -phi, st)) continue;
+                            const bool finite = __builtin_isfinite(g);
+                            const double gd = (double)g * scale;
+                            const double wr0 = (1.0 - st.t) * gd, wr1 = st.t * gd;
+                            const double wc0 = 1.0 - st.s, wc1 = st.s;
+                            const bool two_rows = st.i1 != st.i0, two_cols = st.j1 != st.j0;
 #pragma unroll
-                        for (int a = 0; a < 2; ++a) {
-                            const int ii = a == 0 ? st.i0 : st.i1;
-                            if (ii < ia || ii >= ib || (a == 1 && !two_rows)) continue;
-                            const double wa_ = a == 0 ? wr0 : wr1;
+                            for (int a = 0; a < 2; ++a) {
+                                const int ii = a == 0 ? st.i0 : st.i1;
+                                if (ii < ia || ii >= ib || (a == 1 && !two_rows)) continue;
+                                const double wa_ = a == 0 ? wr0 : wr1;
 #pragma unroll
-                            for (int c = 0; c < 2; ++c) {
-                                if (c == 1 && !two_cols) continue;
-                                const int lb = (ii - ia) * f.n_az + (c == 0 ? st.j0 : st.j1);
-                                if (!finite) {
-                                    atomicOr(&poison[lb >> 5], 1u << (lb & 31));
-                                    continue;
+                                for (int c = 0; c < 2; ++c) {
+                                    if (c == 1 && !two_cols) continue;
+                                    const int lb = (ii - ia) * f.n_az + (c == 0 ? st.j0 : st.j1);
+                                    if (!finite) {
+                                        atomicOr(&poison[lb >> 5], 1u << (lb & 31));
+                                        continue;
+                                    }
+                                    const long long qv = round_to_ll(wa_ * (c == 0 ? wc0 : wc1));
+                                    if (qv != 0)
+                                        atomicAdd(reinterpret_cast<unsigned long long *>(&acc[lb]),
+                                                  (unsigned long long)qv);
                                 }
-                                const long long qv = round_to_ll(wa_ * (c == 0 ? wc0 : wc1));
-                                if (qv != 0)
-                                    atomicAdd(reinterpret_cast<unsigned long long *>(&acc[lb]),
-                                              (unsigned long long)qv);
                             }
                         }
                     }
                 }
-                __syncthreads();
             }
         }
+        __syncthreads();
     }
 
     // epilogue: fixed point -> float, plus the polar gradient; adjoint of Eq. (3)-(4)
@@ -711,16 +708,17 @@ __device__ __forceinline__ void tile_bwd_block(const Src &src, const oceansim_so
             if (++j == f.n_az) { j = 0; ++i; }
         }
     }
-    const double s_phi = block_sum<NT>(g_sphi, red);
-    const double s_sa = block_sum<NT>(g_ssa, red);
+    __shared__ double red2[2 * (NT / kWave)];
+    const double sums[2] = {g_sphi, g_ssa};
+    const double tot = block_sum_n<2, NT>(sums, red2);   // thread 0: sigma_phi, thread 1: sigma_sa
+    double *p = part + (long long)lid * 5;
     if (tid == 0) {
-        double *p = part + (long long)lid * 5;
         p[0] = 0.0;
         p[1] = 0.0;
-        p[2] = s_phi;
-        p[3] = s_sa;
+        p[2] = tot;
         p[4] = 0.0;
     }
+    if (tid == 1) p[3] = tot;
 }
 
 template <class Src, bool SAVED>
@@ -728,24 +726,6 @@ __global__ __launch_bounds__(kBwdThreads, 4) void k_tile_bwd(Src src, const ocea
                                                           double *part, float *grad_refl_zero,
                                                           int n_mat_zero) {
     tile_bwd_block<Src, SAVED>(src, params, part, grad_refl_zero, n_mat_zero, blockIdx.x, gridDim.x);
-}
-
-// The backward tiles and, in the same launch, the camera frames of a plan
-// (workgroups n_tile_blocks and up, kBwdThreads threads each): the
-// latency-bound tiles leave most of the machine idle, and the HBM-bound
-// camera adjoint fills it.
-template <class Src, bool SAVED>
-__global__ __launch_bounds__(kBwdThreads, 4) void k_tile_bwd_uw(Src src, const oceansim_sonar_params *params,
-                                                             double *part, float *grad_refl_zero,
-                                                             int n_mat_zero, int n_tile_blocks,
-                                                             Table<UwDev> usrc,
-                                                             const oceansim_water_params *wparams,
-                                                             double *upart, int *urow) {
-    __shared__ double red9[9 * (kBwdThreads / kWave)];
-    if ((int)blockIdx.x < n_tile_blocks)
-        tile_bwd_block<Src, SAVED>(src, params, part, grad_refl_zero, n_mat_zero, blockIdx.x, n_tile_blocks);
-    else
-        uw_bwd_block<Table<UwDev>, kBwdThreads>(usrc, wparams, upart, urow, blockIdx.x - n_tile_blocks, red9);
 }
 
 // ---------------------------------------------------------------------------
@@ -903,24 +883,10 @@ template <class Src>
 static hipError_t launch_bwd(const Src &src, int n_frames, const SonarGrid &g,
                              const oceansim_sonar_params *params, int n_rows, const float *refl, int n_mat,
                              double *part, double *refl_part, float *grad_params, float *grad_refl,
-                             hipStream_t st, const UwCompanion *uw) {
+                             hipStream_t st) {
     const bool lane_hist = n_mat <= kLaneHistMats;
     hipError_t e = hipSuccess;
-    if (uw && uw->blocks > 0) {
-        const Table<UwDev> us{uw->table, uw->n};
-        if (g.all_saved)
-            OSIM_LAUNCH("k_tile_bwd_uw", (k_tile_bwd_uw<Src, true>), dim3(g.tile_b_blocks + uw->blocks),
-                        dim3(kBwdThreads), (size_t)g.max_tile_bins_b * 8, st, src, params, part,
-                        lane_hist ? (float *)nullptr : grad_refl, n_mat, g.tile_b_blocks, us, uw->params, uw->part,
-                        uw->part_row);
-        else
-            OSIM_LAUNCH("k_tile_bwd_uw", (k_tile_bwd_uw<Src, false>), dim3(g.tile_b_blocks + uw->blocks),
-                        dim3(kBwdThreads), (size_t)g.max_tile_bins_b * 8, st, src, params, part,
-                        lane_hist ? (float *)nullptr : grad_refl, n_mat, g.tile_b_blocks, us, uw->params, uw->part,
-                        uw->part_row);
-        e = hipGetLastError();
-        if (e != hipSuccess) return e;
-    } else if (g.tile_b_blocks > 0) {
+    if (g.tile_b_blocks > 0) {
         if (g.all_saved)
             OSIM_LAUNCH("k_tile_bwd", (k_tile_bwd<Src, true>), dim3(g.tile_b_blocks), dim3(kBwdThreads),
                         (size_t)g.max_tile_bins_b * 8, st, src, params, part,
@@ -966,14 +932,14 @@ hipError_t sonar_backward_one(const SonarDev &f, const SonarGrid &g, const ocean
                               int n_rows, const float *refl, int n_mat, double *part, double *refl_part,
                               float *grad_params, float *grad_refl, hipStream_t st) {
     return launch_bwd(One<SonarDev>{f}, 1, g, params, n_rows, refl, n_mat, part, refl_part, grad_params,
-                      grad_refl, st, nullptr);
+                      grad_refl, st);
 }
 hipError_t sonar_backward_table(const SonarDev *t, int n, const SonarGrid &g,
                                 const oceansim_sonar_params *params, int n_rows, const float *refl,
                                 int n_mat, double *part, double *refl_part, float *grad_params,
-                                float *grad_refl, hipStream_t st, const UwCompanion *uw) {
+                                float *grad_refl, hipStream_t st) {
     return launch_bwd(Table<SonarDev>{t, n}, n, g, params, n_rows, refl, n_mat, part, refl_part, grad_params,
-                      grad_refl, st, uw);
+                      grad_refl, st);
 }
 
 }  // namespace osim
