@@ -43,6 +43,8 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 64 MiB device-to-device copy (counter calibration)")
+    ap.add_argument("--only", choices=["c3", "c4"], default=None,
+                    help="only build and run one batched leg (for profiler runs); prints no JSON line")
     return ap.parse_args()
 
 
@@ -56,6 +58,53 @@ def copy_calibration(torch, dev):
         b.copy_(a)
     torch.cuda.synchronize()
     log("copy calibration: 5 launches of a %d-byte device copy" % n)
+
+
+def source_digest():
+    """SHA-256 over the library sources: HBM traffic measured by a profiler
+    run is used only while the kernels are those that were profiled."""
+    import hashlib
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_2503_01074_amd", "csrc")
+    for name in sorted(os.listdir(csrc)):
+        if name.endswith((".hip", ".hpp", ".cpp")):
+            with open(os.path.join(csrc, name), "rb") as fh:
+                h.update(name.encode() + b"\0" + fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(kernel):
+    """HBM bytes per launch of `kernel` (read + written) from the rocprofv3
+    counter summary in profiles/, if it was taken on the current sources."""
+    path = os.path.join(ROOT, "profiles", "c2_step_hbm_traffic.json")
+    try:
+        with open(path) as fh:
+            rec = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    if rec.get("source_sha256") != source_digest():
+        return None
+    k = rec.get("kernels", {}).get(kernel)
+    return None if k is None else int(k["fetch_bytes"] + k["write_bytes"])
+
+
+def copy_rate(torch, dev):
+    """Bandwidth of a plain 64 MiB device-to-device copy (read + written
+    bytes over the event-timed duration): what the memory system delivers to
+    a trivial streaming kernel, for context beside the 8 TB/s peak."""
+    a = torch.ones((64 << 20) // 4, dtype=torch.float32, device=dev)
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    s = torch.cuda.current_stream(dev)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(s)
+    for _ in range(20):
+        b.copy_(a)
+    e1.record(s)
+    e1.synchronize()
+    t = e0.elapsed_time(e1) / 1e3 / 20
+    return round(2 * a.numel() * 4 / t / 1e9, 1)
 
 
 class RealTimeStep:
@@ -173,7 +222,9 @@ class RealTimeStep:
         npx_fan = self.geom.fan_h * self.geom.fan_w
         return {"k_bin": 28 * self.n_returns, "k_tile": 4 * nb, "k_fan": 4 * npx_fan,
                 "k_tile_bwd": 4 * npx_fan + 4 * nb, "k_ret_bwd": 28 * self.n_returns,
-                "k_uw": 28 * self.npix, "k_uw_bwd": 44 * self.npix}
+                "k_uw": 28 * self.npix, "k_uw_bwd": 44 * self.npix,
+                # the plan's forward polar-tile launch also carries the camera frame
+                "k_tile_uw": 4 * nb + 28 * self.npix}
 
 
 def timed(torch, fn, steps, warmup):
@@ -206,7 +257,7 @@ def median_time(torch, fn, steps, warmup, repeats=5):
     return ts[len(ts) // 2]
 
 
-def batched_legs(torch, dev, steps):
+def batched_legs(torch, dev, steps, only=None):
     """Ragged batch of 256 sonar frames (forward) and a differentiable batch of
     32 sonar + 32 camera frames (forward + backward): one ABI call per frame
     (plain), one call per entry point for the whole batch (batched), and a
@@ -223,6 +274,8 @@ def batched_legs(torch, dev, steps):
     out = {}
     reps = max(5, steps // 10)
 
+    if only == "c4":
+        return c4_leg(torch, dev, steps, out)
     frames = W.sonar_c3()
     tables, base, hits = [], 0, []
     for f in frames:
@@ -260,21 +313,35 @@ def batched_legs(torch, dev, steps):
     torch.cuda.synchronize()
     tr = _lib.oceansim_trace_summary()
     _lib.oceansim_trace_enable(False)
-    plan = osm.Plan(list(zip(geoms, hits)), sonar_params=params, refl=refl, graph=True, autotune=True)
-    t_graph = median_time(torch, plan.forward, reps, 3)
+    plan = osm.Plan(list(zip(geoms, hits)), sonar_params=params, refl=refl, autotune=True)
+    t_plan = median_time(torch, plan.forward, reps, 3)
     shape = plan.shape()
     plan.close()
     out["batched_c3_fwd"] = {"frames": n_fr, "returns": n_ret, "ms": t * 1e3,
                              "frames_per_s": n_fr / t, "returns_per_s": n_ret / t,
                              "plain_ms": t_plain * 1e3, "plain_frames_per_s": n_fr / t_plain,
-                             "graph_autotuned_ms": t_graph * 1e3, "graph_frames_per_s": n_fr / t_graph,
-                             "graph_returns_per_s": n_ret / t_graph, "autotuned_shape": shape,
+                             "plan_ms": t_plan * 1e3, "plan_frames_per_s": n_fr / t_plan,
+                             "plan_returns_per_s": n_ret / t_plan, "autotuned_shape": shape,
                              "kernels_us": {k: round(us / calls, 1) for k, (calls, us) in tr.items()}}
-    log("C3 forward, 256 frames: batched call %.3f ms, one call per frame %.3f ms, autotuned graph plan %.3f ms %s"
-        % (t * 1e3, t_plain * 1e3, t_graph * 1e3, shape))
+    log("C3 forward, 256 frames: batched call %.3f ms, one call per frame %.3f ms, autotuned plan %.3f ms %s"
+        % (t * 1e3, t_plain * 1e3, t_plan * 1e3, shape))
     del hits, polars, fans, ws, arr, structs
     torch.cuda.empty_cache()
+    if only == "c3":
+        return out
+    return c4_leg(torch, dev, steps, out)
 
+
+def c4_leg(torch, dev, steps, out):
+    """32 sonar + 32 camera frames, forward and forward + backward: one call
+    per entry point for the whole batch, and a plan."""
+    import paper_2503_01074_amd as osm
+    from paper_2503_01074_amd import _lib
+    from paper_2503_01074_amd.api import _sonar_struct, _uw_struct
+    import workloads as W
+
+    stream = torch.cuda.current_stream(dev).cuda_stream
+    P = lambda t: t.data_ptr()
     frames = W.sonar_c4()
     cams, waters = W.camera_c4()
     refl = torch.as_tensor(frames[0].hits.refl, device=dev)
@@ -326,26 +393,28 @@ def batched_legs(torch, dev, steps):
     tf = median_time(torch, c4_fwd, max(5, steps // 5), 3)
     ts = median_time(torch, c4_step, max(5, steps // 5), 3)
     plan = osm.Plan(list(zip(geoms, hits)), list(zip(Js, ds, [0] * len(cams))), sonar_params=params, refl=refl,
-                    water=water, backward=True, graph=True, image_grads=True)
+                    water=water, backward=True, autotune=True, image_grads=True)
     for o, a, b in zip(plan.sonar_out, gp, gf):
         o["grad_polar"].copy_(a)
         o["grad_fan"].copy_(b)
     for o, g in zip(plan.camera_out, gi):
         o["grad_out"].copy_(g)
 
-    def c4_graph_step():
+    def c4_plan_step():
         plan.forward()
         plan.backward()
     tgf = median_time(torch, plan.forward, max(5, steps // 5), 3)
-    tgs = median_time(torch, c4_graph_step, max(5, steps // 5), 3)
+    tgs = median_time(torch, c4_plan_step, max(5, steps // 5), 3)
+    shape = plan.shape()
     plan.close()
     out["batched_c4"] = {"sonar_frames": len(frames), "camera_frames": len(cams), "returns": n_ret,
                          "fwd_ms": tf * 1e3, "fwd_bwd_ms": ts * 1e3,
                          "fwd_bwd_frames_per_s": n_fr / ts, "fwd_bwd_returns_per_s": n_ret / ts,
-                         "graph_fwd_ms": tgf * 1e3, "graph_fwd_bwd_ms": tgs * 1e3,
-                         "graph_fwd_bwd_frames_per_s": n_fr / tgs}
-    log("C4 batched: fwd %.3f ms, fwd+bwd %.3f ms; graph plan fwd %.3f ms, fwd+bwd %.3f ms"
-        % (tf * 1e3, ts * 1e3, tgf * 1e3, tgs * 1e3))
+                         "plan_fwd_ms": tgf * 1e3, "plan_fwd_bwd_ms": tgs * 1e3,
+                         "plan_fwd_bwd_frames_per_s": n_fr / tgs, "plan_fwd_bwd_returns_per_s": n_ret / tgs,
+                         "autotuned_shape": shape}
+    log("C4 batched: fwd %.3f ms, fwd+bwd %.3f ms; autotuned plan fwd %.3f ms, fwd+bwd %.3f ms %s"
+        % (tf * 1e3, ts * 1e3, tgf * 1e3, tgs * 1e3, shape))
     return out
 
 
@@ -392,22 +461,30 @@ def main():
     if args.copy_calibration:
         copy_calibration(torch, dev)
         return
+    if args.only:
+        legs = batched_legs(torch, dev, args.steps, only=args.only)
+        log("done: %s" % ", ".join(sorted(legs)))
+        return
     log("building workload")
     rt = RealTimeStep(dev)
 
+    # The step: the plan (frames prepared once, launch shapes autotuned),
+    # forward + backward, K times after W warm-up steps, timed by the host
+    # clock between two device synchronisations.
     log("timing %d full steps after %d warm-up" % (args.steps, args.warmup))
-    t_step = timed(torch, rt.step, args.steps, args.warmup)
-    t_fwd = timed(torch, rt.forward, args.steps, args.warmup)
+    headline = lambda: rt.plan_step("plan")
+    t_step = timed(torch, headline, args.steps, args.warmup)
+    t_fwd = timed(torch, lambda: rt.plan_forward("plan"), args.steps, args.warmup)
+    log("plan: step %.3f ms, forward %.3f ms, shape %s" % (t_step * 1e3, t_fwd * 1e3, rt.plans["plan"].shape()))
+    # the same step through the plain entry points (one call per entry point)
+    # and through the plan's HIP graphs
+    t_pstep = timed(torch, rt.step, args.steps, args.warmup)
+    t_pfwd = timed(torch, rt.forward, args.steps, args.warmup)
     t_sonar_fwd = timed(torch, rt.sonar_forward, args.steps, args.warmup)
-    log("plain entry points: step %.3f ms, forward %.3f ms, sonar forward %.3f ms"
-        % (t_step * 1e3, t_fwd * 1e3, t_sonar_fwd * 1e3))
-    plan_t = {}
-    for name in rt.plans:
-        ts = timed(torch, lambda: rt.plan_step(name), args.steps, args.warmup)
-        tf = timed(torch, lambda: rt.plan_forward(name), args.steps, args.warmup)
-        plan_t[name] = {"step_ms": ts * 1e3, "returns_per_s": rt.n_returns / ts, "fwd_ms": tf * 1e3,
-                        "fwd_returns_per_s": rt.n_returns / tf, "shape": rt.plans[name].shape()}
-        log("%s: step %.3f ms, forward %.3f ms, shape %s" % (name, ts * 1e3, tf * 1e3, rt.plans[name].shape()))
+    t_gstep = timed(torch, lambda: rt.plan_step("graph"), args.steps, args.warmup)
+    t_gfwd = timed(torch, lambda: rt.plan_forward("graph"), args.steps, args.warmup)
+    log("plain entry points: step %.3f ms, forward %.3f ms, sonar forward %.3f ms; graph plan: step %.3f ms, "
+        "forward %.3f ms" % (t_pstep * 1e3, t_pfwd * 1e3, t_sonar_fwd * 1e3, t_gstep * 1e3, t_gfwd * 1e3))
 
     # per-entry-point GPU durations from events on the launch stream
     reps = max(20, args.steps)
@@ -421,7 +498,7 @@ def main():
     # on its stream while tracing is on
     rt.lib.oceansim_trace_enable(True)
     for _ in range(reps):
-        rt.step()
+        headline()
     torch.cuda.synchronize()
     trace = rt.lib.oceansim_trace_summary()
     rt.lib.oceansim_trace_enable(False)
@@ -433,7 +510,7 @@ def main():
     roofline = {"bound": "hbm", "kernel": dom,
                 "achieved": None if achieved is None else round(achieved, 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": None if achieved is None else round(achieved / HBM_PEAK_GBS, 4),
-                "traffic": None, "bytes_per_launch": dom_bytes, "launch_us": round(kern_us[dom], 2)}
+                "traffic": measured_traffic(dom), "bytes_per_launch": dom_bytes, "launch_us": round(kern_us[dom], 2)}
     kernel_table = {k: {"us": round(kern_us[k], 2), "alg_bytes": abytes.get(k),
                         "alg_GBps": round(abytes[k] / (kern_us[k] * 1e-6) / 1e9, 1) if k in abytes else None}
                     for k in sorted(kern_us, key=lambda k: -kern_us[k])}
@@ -464,12 +541,15 @@ def main():
                                "1024x1024 polar bins, gamma speckle k=4, 1024x2048 fan, plus Eq. 1 on one "
                                "1920x1080 RGB frame; forward + backward",
                    "global_batch": 1, "parallelism": "none (1 GPU)"},
+        "path": "plan (frames prepared once, autotuned launch shapes, camera forward in the polar-tile launch)",
         "frames_per_s": 1.0 / t_step,
         "fwd_returns_per_s": rt.n_returns / t_fwd,
         "fwd_frames_per_s": 1.0 / t_fwd,
-        "sonar_fwd_only_frames_per_s": 1.0 / t_sonar_fwd,
+        "plain": {"step_ms": t_pstep * 1e3, "returns_per_s": rt.n_returns / t_pstep, "fwd_ms": t_pfwd * 1e3,
+                  "sonar_fwd_only_frames_per_s": 1.0 / t_sonar_fwd},
+        "graph": {"step_ms": t_gstep * 1e3, "returns_per_s": rt.n_returns / t_gstep, "fwd_ms": t_gfwd * 1e3},
+        "copy_GBps": copy_rate(torch, dev),
         "camera_mpx_per_s_fwd_bwd": rt.npix / t_step / 1e6,
-        "plans": plan_t,
         "entry_point_us": {k: round(v * 1e6, 2) for k, v in parts.items()},
         "kernels": kernel_table,
         "roofline": roofline,
