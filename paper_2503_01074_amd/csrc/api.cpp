@@ -285,7 +285,8 @@ int plan_sonar(const oceansim_sonar_frame *frames, int n_frames, int n_param_row
         if (frames[i].grad_fan && !frames[i].fan_stencil) P.grid.all_saved = 0;
     if (backward) {
         P.n_slots = tile_b_blocks + ret_blocks;
-        P.off_part = take(sizeof(double) * 5 * (size_t)std::max(1, P.n_slots));
+        // five FP64 partial sums per slot (column-major), then the slot's parameter row
+        P.off_part = take((sizeof(double) * 5 + sizeof(int)) * (size_t)std::max(1, P.n_slots));
         if (n_mat <= kLaneHistMats)
             P.off_refl_part = take(sizeof(double) * (size_t)std::max(1, ret_blocks) * n_mat);
     }

@@ -531,6 +531,31 @@ __device__ __forceinline__ double block_sum_n(const double (&v)[N], double *sh) 
     return s;
 }
 
+// This thread's share of sum_{k < n} get(k) over a workgroup of NT threads
+// (thread t takes k = t, t + NT, ...), with sixteen loads in flight per
+// iteration and four accumulators; the assignment of elements to threads and
+// accumulators is fixed, so the result is reproducible.  Combine the threads
+// with block_sum.
+template <int NT = kBlock, class Get>
+__device__ __forceinline__ double thread_share_sum(int n, Get get) {
+    double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+    int k = threadIdx.x;
+    for (; k + 15 * NT < n; k += 16 * NT) {
+        double v[16];
+#pragma unroll
+        for (int q = 0; q < 16; ++q) v[q] = get(k + q * NT);
+#pragma unroll
+        for (int q = 0; q < 16; q += 4) {
+            s0 += v[q];
+            s1 += v[q + 1];
+            s2 += v[q + 2];
+            s3 += v[q + 3];
+        }
+    }
+    for (; k < n; k += NT) s0 += get(k);
+    return ((s0 + s1) + s2) + s3;
+}
+
 // Inclusive scan of one value per thread across a workgroup of NT threads
 // (wave shuffles, then the wave totals); `wtot` holds NT / 64 ints in LDS and
 // may be reused only after a barrier.  Every thread must call it.

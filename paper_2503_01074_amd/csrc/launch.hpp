@@ -67,9 +67,10 @@ hipError_t sonar_forward_one(const SonarDev &f, const SonarGrid &g, const oceans
 hipError_t sonar_forward_table(const SonarDev *t, int n, const SonarGrid &g,
                                const oceansim_sonar_params *params, const float *refl, int n_mat,
                                hipStream_t st, const UwCompanion *uw = nullptr);
-// Backward: partial sums into part (5 doubles per tile and return workgroup)
-// and refl_part (n_mat doubles per return workgroup, small tables), reduced
-// in a fixed order into grad_params [n_rows][8] and grad_refl [n_mat].
+// Backward: partial sums into part (column-major [5][tile and return
+// workgroups]) and refl_part (column-major [n_mat][return workgroups], small
+// tables), reduced in a fixed order into grad_params [n_rows][8] and
+// grad_refl [n_mat].
 hipError_t sonar_backward_one(const SonarDev &f, const SonarGrid &g, const oceansim_sonar_params *params,
                               int n_rows, const float *refl, int n_mat, double *part, double *refl_part,
                               float *grad_params, float *grad_refl, hipStream_t st);
@@ -93,11 +94,11 @@ hipError_t uw_backward_one(const UwDev &f, int blocks, const oceansim_water_para
 hipError_t uw_backward_table(const UwDev *t, int n, int blocks, const oceansim_water_params *params,
                              double *part, int *part_row, hipStream_t st);
 
-// out[r * out_stride + c] = sum over slots s with row[s] == r of part[s * width + c]
+// out[r * out_stride + c] = sum over slots s with row[s] == r of part[c * n_slots + s]
 // (c < width; columns width..out_stride-1 are written 0), in a fixed order.
 hipError_t reduce_rows(const double *part, const int *row, int n_slots, int width, int n_rows,
                        float *out, int out_stride, hipStream_t st);
-// out[c] = sum over s of part[s * width + c], fixed order.
+// out[c] = sum over s of part[c * n_slots + s], fixed order.
 hipError_t reduce_cols(const double *part, int n_slots, int width, float *out, hipStream_t st);
 
 }  // namespace osim

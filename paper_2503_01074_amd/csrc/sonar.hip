@@ -444,7 +444,8 @@ __device__ __forceinline__ long long round_to_ll(double x) {
 // threads).
 template <class Src, bool SAVED>
 __device__ __forceinline__ void tile_bwd_block(const Src &src, const oceansim_sonar_params *params, double *part,
-                                               float *grad_refl_zero, int n_mat_zero, int bid, int n_blocks) {
+                                               int n_slots, float *grad_refl_zero, int n_mat_zero, int bid,
+                                               int n_blocks) {
     constexpr int NT = kBwdThreads;
     extern __shared__ int4 lds_raw[];
     long long *acc = reinterpret_cast<long long *>(lds_raw);
@@ -711,21 +712,22 @@ __device__ __forceinline__ void tile_bwd_block(const Src &src, const oceansim_so
     __shared__ double red2[2 * (NT / kWave)];
     const double sums[2] = {g_sphi, g_ssa};
     const double tot = block_sum_n<2, NT>(sums, red2);   // thread 0: sigma_phi, thread 1: sigma_sa
-    double *p = part + (long long)lid * 5;
+    // partial sums column-major: part[c * n_slots + slot], then the slots' rows
     if (tid == 0) {
-        p[0] = 0.0;
-        p[1] = 0.0;
-        p[2] = tot;
-        p[4] = 0.0;
+        reinterpret_cast<int *>(part + 5LL * n_slots)[lid] = f.param_row;
+        part[0LL * n_slots + lid] = 0.0;
+        part[1LL * n_slots + lid] = 0.0;
+        part[2LL * n_slots + lid] = tot;
+        part[4LL * n_slots + lid] = 0.0;
     }
-    if (tid == 1) p[3] = tot;
+    if (tid == 1) part[3LL * n_slots + lid] = tot;
 }
 
 template <class Src, bool SAVED>
 __global__ __launch_bounds__(kBwdThreads, 4) void k_tile_bwd(Src src, const oceansim_sonar_params *params,
-                                                          double *part, float *grad_refl_zero,
+                                                          double *part, int n_slots, float *grad_refl_zero,
                                                           int n_mat_zero) {
-    tile_bwd_block<Src, SAVED>(src, params, part, grad_refl_zero, n_mat_zero, blockIdx.x, gridDim.x);
+    tile_bwd_block<Src, SAVED>(src, params, part, n_slots, grad_refl_zero, n_mat_zero, blockIdx.x, gridDim.x);
 }
 
 // ---------------------------------------------------------------------------
@@ -734,12 +736,12 @@ __global__ __launch_bounds__(kBwdThreads, 4) void k_tile_bwd(Src src, const ocea
 template <class Src, int R>
 __global__ __launch_bounds__(kBlock) void k_ret_bwd(Src src, const oceansim_sonar_params *params,
                                                     const float *refl, int n_mat, double *part, int slot_base,
-                                                    double *refl_part, float *grad_refl_atomic) {
+                                                    int n_slots, double *refl_part, float *grad_refl_atomic) {
     extern __shared__ int4 lds_raw[];
     // thread-private reflectivity columns [n_mat][kBlock] (small tables); the
     // same memory later serves the workgroup reductions
     float *hist = reinterpret_cast<float *>(lds_raw);
-    double *red = reinterpret_cast<double *>(lds_raw);
+    double *red3 = reinterpret_cast<double *>(lds_raw);
     int local;
     const int fi = src.locate(blockIdx.x, KRET, local);
     const SonarDev f = src.frame(fi);
@@ -782,26 +784,32 @@ __global__ __launch_bounds__(kBlock) void k_ret_bwd(Src src, const oceansim_sona
     }
     if (lane_hist) {
         __syncthreads();
-        // fixed order: threads 0..255 of each material column
-        for (int mm = tid; mm < n_mat; mm += kBlock) {
-            double s = 0.0;
+        // per material, the 256 thread columns summed by one wave in a fixed
+        // tree order (four per lane, then the wave's shuffle tree); partial
+        // sums column-major: refl_part[m * n_ret_slots + slot]
+        const int lane = tid & (kWave - 1), wave = tid / kWave;
+        for (int mm = wave; mm < n_mat; mm += kBlock / kWave) {
             const float *h = hist + mm * kBlock;
-            for (int l = 0; l < kBlock; ++l) s += (double)h[l];
-            refl_part[(long long)blockIdx.x * n_mat + mm] = s;
+            double s = (double)h[lane];
+#pragma unroll
+            for (int q = 1; q < kBlock / kWave; ++q) s += (double)h[lane + q * kWave];
+            s = wave_sum(s);
+            if (lane == 0) refl_part[(long long)mm * gridDim.x + blockIdx.x] = s;
         }
     }
     __syncthreads();
-    const double sa = block_sum(g_alpha, red);
-    const double sg = block_sum(g_gain, red);
-    const double sm = block_sum(g_ssm, red);
+    const double sums[3] = {g_alpha, g_gain, g_ssm};
+    const double tot = block_sum_n<3>(sums, red3);   // thread 0: alpha, 1: gain, 2: sigma_sm
+    // partial sums column-major: part[c * n_slots + slot]
+    const long long slot = slot_base + blockIdx.x;
     if (tid == 0) {
-        double *p = part + (long long)(slot_base + blockIdx.x) * 5;
-        p[0] = sa;
-        p[1] = sg;
-        p[2] = 0.0;
-        p[3] = 0.0;
-        p[4] = sm;
+        reinterpret_cast<int *>(part + 5LL * n_slots)[slot] = f.param_row;
+        part[0LL * n_slots + slot] = tot;
+        part[2LL * n_slots + slot] = 0.0;
+        part[3LL * n_slots + slot] = 0.0;
     }
+    if (tid == 1) part[1LL * n_slots + slot] = tot;
+    if (tid == 2) part[4LL * n_slots + slot] = tot;
 }
 
 // ---------------------------------------------------------------------------
@@ -809,32 +817,29 @@ __global__ __launch_bounds__(kBlock) void k_ret_bwd(Src src, const oceansim_sona
 // produce grad_params[row][col] from the slots of the frames using that row;
 // the following n_mat blocks (small tables) produce grad_refl.
 // ---------------------------------------------------------------------------
-template <class Src>
-__global__ __launch_bounds__(kBlock) void k_reduce_sonar(Src src, int n_frames, const double *part,
-                                                         int tile_slots, int n_rows, float *grad_params,
-                                                         const double *refl_part, int ret_slots, int n_mat,
-                                                         float *grad_refl) {
+__global__ __launch_bounds__(kBlock) void k_reduce_sonar(const double *part, int n_slots, int n_rows,
+                                                         float *grad_params, const double *refl_part,
+                                                         int ret_slots, int n_mat, float *grad_refl) {
     __shared__ double red[kBlock / kWave];
     const int b = blockIdx.x;
-    double s = 0.0;
     if (b < n_rows * OCEANSIM_SONAR_GRAD_WIDTH) {
         const int r = b / OCEANSIM_SONAR_GRAD_WIDTH, c = b % OCEANSIM_SONAR_GRAD_WIDTH;
+        double s = 0.0;
         if (c < 5) {
-            for (int fi = 0; fi < n_frames; ++fi) {
-                const SonarDev f = src.frame(fi);
-                if (f.param_row != r) continue;
-                for (int k = threadIdx.x; k < f.n_tiles_b; k += kBlock)
-                    s += part[(long long)(f.blk[KTILEB] + k) * 5 + c];
-                for (int k = threadIdx.x; k < f.n_ret_chunks; k += kBlock)
-                    s += part[(long long)(tile_slots + f.blk[KRET] + k) * 5 + c];
-            }
+            // every slot (tiles, then return chunks) whose frame uses row r
+            const double *a = part + (long long)c * n_slots;
+            const int *row = reinterpret_cast<const int *>(part + 5LL * n_slots);
+            s = thread_share_sum(n_slots, [&](int k) {
+                const double v = a[k];
+                return row[k] == r ? v : 0.0;
+            });
         }
         const double tot = block_sum(s, red);
         if (threadIdx.x == 0) grad_params[b] = (float)tot;
     } else {
         const int m = b - n_rows * OCEANSIM_SONAR_GRAD_WIDTH;
-        if (refl_part)
-            for (int k = threadIdx.x; k < ret_slots; k += kBlock) s += refl_part[(long long)k * n_mat + m];
+        const double *a = refl_part ? refl_part + (long long)m * ret_slots : nullptr;
+        const double s = a ? thread_share_sum(ret_slots, [&](int k) { return a[k]; }) : 0.0;
         const double tot = block_sum(s, red);
         if (threadIdx.x == 0) grad_refl[m] = (float)tot;
     }
@@ -885,27 +890,28 @@ static hipError_t launch_bwd(const Src &src, int n_frames, const SonarGrid &g,
                              double *part, double *refl_part, float *grad_params, float *grad_refl,
                              hipStream_t st) {
     const bool lane_hist = n_mat <= kLaneHistMats;
+    const int n_slots = g.tile_b_blocks + g.ret_blocks;   // partial-sum slots: tiles, then return chunks
     hipError_t e = hipSuccess;
     if (g.tile_b_blocks > 0) {
         if (g.all_saved)
             OSIM_LAUNCH("k_tile_bwd", (k_tile_bwd<Src, true>), dim3(g.tile_b_blocks), dim3(kBwdThreads),
-                        (size_t)g.max_tile_bins_b * 8, st, src, params, part,
+                        (size_t)g.max_tile_bins_b * 8, st, src, params, part, n_slots,
                         lane_hist ? (float *)nullptr : grad_refl, n_mat);
         else
             OSIM_LAUNCH("k_tile_bwd", (k_tile_bwd<Src, false>), dim3(g.tile_b_blocks), dim3(kBwdThreads),
-                        (size_t)g.max_tile_bins_b * 8, st, src, params, part,
+                        (size_t)g.max_tile_bins_b * 8, st, src, params, part, n_slots,
                         lane_hist ? (float *)nullptr : grad_refl, n_mat);
         e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
     if (g.ret_blocks > 0) {
         size_t lds = lane_hist ? (size_t)n_mat * kBlock * 4 : 0;
-        if (lds < (size_t)(kBlock / kWave) * 8) lds = (size_t)(kBlock / kWave) * 8;
+        if (lds < (size_t)3 * (kBlock / kWave) * 8) lds = (size_t)3 * (kBlock / kWave) * 8;
         double *rp = lane_hist ? refl_part : nullptr;
         float *ga = lane_hist ? nullptr : grad_refl;
         OSIM_DISPATCH_R(g.ret_chunk / kBlock,
                         OSIM_LAUNCH("k_ret_bwd", (k_ret_bwd<Src, RR>), dim3(g.ret_blocks), dim3(kBlock), lds, st, src,
-                                           params, refl, n_mat, part, g.tile_b_blocks, rp, ga));
+                                           params, refl, n_mat, part, g.tile_b_blocks, n_slots, rp, ga));
         e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
@@ -913,9 +919,8 @@ static hipError_t launch_bwd(const Src &src, int n_frames, const SonarGrid &g,
     // unless there was no tile at all (then the reduction writes zeros)
     const bool refl_blocks = lane_hist || g.tile_b_blocks == 0;
     const int blocks = n_rows * OCEANSIM_SONAR_GRAD_WIDTH + (refl_blocks ? n_mat : 0);
-    OSIM_LAUNCH("k_reduce_sonar", (k_reduce_sonar<Src>), dim3(blocks), dim3(kBlock), 0, st, src, n_frames, part,
-                       g.tile_b_blocks, n_rows, grad_params, lane_hist ? refl_part : nullptr, g.ret_blocks,
-                       n_mat, grad_refl);
+    OSIM_LAUNCH("k_reduce_sonar", k_reduce_sonar, dim3(blocks), dim3(kBlock), 0, st, part, n_slots, n_rows,
+                grad_params, lane_hist ? refl_part : nullptr, g.ret_blocks, n_mat, grad_refl);
     return hipGetLastError();
 }
 

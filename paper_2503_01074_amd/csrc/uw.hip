@@ -19,7 +19,7 @@ template <class Src>
 __global__ __launch_bounds__(kBlock) void k_uw_bwd(Src src, const oceansim_water_params *params,
                                                    double *part, int *part_row) {
     __shared__ double red9[9 * (kBlock / kWave)];
-    uw_bwd_block<Src, kBlock>(src, params, part, part_row, blockIdx.x, red9);
+    uw_bwd_block<Src, kBlock>(src, params, part, part_row, blockIdx.x, gridDim.x, red9);
 }
 
 hipError_t uw_forward_one(const UwDev &f, int blocks, const oceansim_water_params *params, hipStream_t st) {
@@ -52,9 +52,14 @@ __global__ __launch_bounds__(kBlock) void k_reduce_rows(const double *part, cons
     __shared__ double red[kBlock / kWave];
     const int r = blockIdx.x / out_stride, c = blockIdx.x % out_stride;
     double s = 0.0;
-    if (c < width)
-        for (int k = threadIdx.x; k < n_slots; k += kBlock)
-            if (row[k] == r) s += part[(long long)k * width + c];
+    if (c < width) {
+        // column c of the column-major partials, slots of row r
+        const double *a = part + (long long)c * n_slots;
+        s = thread_share_sum(n_slots, [&](int k) {
+            const double v = a[k];   // both loads issued; the row decides
+            return row[k] == r ? v : 0.0;
+        });
+    }
     const double tot = block_sum(s, red);
     if (threadIdx.x == 0) out[(long long)r * out_stride + c] = c < width ? (float)tot : 0.0f;
 }
@@ -64,7 +69,7 @@ __global__ __launch_bounds__(kBlock) void k_reduce_cols(const double *part, int 
     __shared__ double red[kBlock / kWave];
     const int c = blockIdx.x;
     double s = 0.0;
-    for (int k = threadIdx.x; k < n_slots; k += kBlock) s += part[(long long)k * width + c];
+    for (int k = threadIdx.x; k < n_slots; k += kBlock) s += part[(long long)c * n_slots + k];
     const double tot = block_sum(s, red);
     if (threadIdx.x == 0) out[c] = (float)tot;
 }

@@ -133,11 +133,12 @@ __device__ __forceinline__ float uw_pixel_bwd(float g, float J, float d, float b
 
 // Workgroup `bid` (of NT threads) of a backward launch: kUwBwdPixelsPerThread
 // pixels per thread; the nine parameter partial sums of the workgroup go to
-// part[bid] (FP64, fixed order) and its parameter row to part_row[bid].
+// part[c * n_slots + bid] (FP64, fixed order) and its parameter row to
+// part_row[bid].
 // `red9` is LDS of 9 * NT / 64 doubles.
 template <class Src, int NT>
 __device__ __forceinline__ void uw_bwd_block(const Src &src, const oceansim_water_params *params, double *part,
-                                             int *part_row, int bid, double *red9) {
+                                             int *part_row, int bid, int n_slots, double *red9) {
     int local;
     const int fi = src.locate(bid, 0, local);
     const UwDev f = src.frame(fi);
@@ -207,7 +208,7 @@ __device__ __forceinline__ void uw_bwd_block(const Src &src, const oceansim_wate
 #pragma unroll
     for (int k = 0; k < 9; ++k) accd[k] = (double)acc[k];
     const double tot = block_sum_n<9, NT>(accd, red9);
-    if (threadIdx.x < 9) part[(long long)bid * 9 + threadIdx.x] = tot;
+    if (threadIdx.x < 9) part[(long long)threadIdx.x * n_slots + bid] = tot;   // column-major partials
     if (threadIdx.x == 0) part_row[bid] = f.param_row;
 }
 
