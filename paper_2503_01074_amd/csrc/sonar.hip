@@ -723,8 +723,10 @@ __device__ __forceinline__ void tile_bwd_block(const Src &src, const oceansim_so
     if (tid == 1) part[3LL * n_slots + lid] = tot;
 }
 
+// Saved stencils need fewer registers: three workgroups per CU (six waves per
+// SIMD); the recomputing variant keeps four waves per SIMD.
 template <class Src, bool SAVED>
-__global__ __launch_bounds__(kBwdThreads, 4) void k_tile_bwd(Src src, const oceansim_sonar_params *params,
+__global__ __launch_bounds__(kBwdThreads, SAVED ? 6 : 4) void k_tile_bwd(Src src, const oceansim_sonar_params *params,
                                                           double *part, int n_slots, float *grad_refl_zero,
                                                           int n_mat_zero) {
     tile_bwd_block<Src, SAVED>(src, params, part, n_slots, grad_refl_zero, n_mat_zero, blockIdx.x, gridDim.x);
