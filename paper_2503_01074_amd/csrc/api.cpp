@@ -270,7 +270,7 @@ int plan_sonar(const oceansim_sonar_frame *frames, int n_frames, int n_param_row
             P.off_pairs[i] = take(sizeof(uint2) * (size_t)d.n_chunks * chunk);
             P.off_chunk_off[i] = take(sizeof(int) * (size_t)d.n_chunks * (d.n_tiles + 1));
             if (!fr.polar) P.off_polar[i] = take(sizeof(float) * (size_t)nb);
-            if (d.fan_blocks > 0 && fr.n_azimuth > 1) P.off_cols[i] = take(sizeof(double) * 2 * (size_t)fr.n_azimuth);
+            if (d.fan_blocks > 0) P.off_cols[i] = take(sizeof(double) * 2 * (size_t)fr.n_azimuth);
         } else {
             P.off_grad_img[i] = take(sizeof(float) * (size_t)nb);
         }

@@ -423,10 +423,17 @@ __device__ __forceinline__ void axis_from_offset(int k, float e, int n, int &k0,
     }
 }
 
-// Radial half of a fan pixel at squared distance rho2 from the apex: inside
-// test and (first row, weight code).  rho2 in FP64 from exact pixel offsets.
-// The stencil is computed whatever the inside test says (and is valid).
-__device__ __forceinline__ bool fan_radial_fast(const SonarDev &f, double rho2, int &i0, float &code) {
+// Whether a LEFT-half fan pixel (offset ax = -x_c >= 0 from the axis, y_c > 0
+// along it, squared distance rho2 from the apex, all FP64 from exact pixel
+// offsets) lies in the sector: r_min <= rho <= r_max and |phi| <= fov/2,
+// the latter as ax cos(fov/2) <= yc sin(fov/2) (fov <= pi, yc > 0).
+__device__ __forceinline__ bool fan_inside(const SonarDev &f, double ax, double yc, double rho2) {
+    return rho2 >= f.r_min * f.r_min && rho2 <= f.r_max * f.r_max && ax * f.cos_half_az <= yc * f.sin_half_az;
+}
+
+// Radial half of a fan pixel at squared distance rho2 from the apex: (first
+// row, weight code); valid indices for any rho2.
+__device__ __forceinline__ void fan_radial_fast(const SonarDev &f, double rho2, int &i0, float &code) {
     const float rho_f = __builtin_amdgcn_sqrtf((float)rho2);   // hardware sqrt: only picks the nearest row
     int in = (int)__builtin_rintf((rho_f - f.r_min_f) * f.scale_r_f - 0.5f);
     in = in < 0 ? 0 : (in > f.n_range - 1 ? f.n_range - 1 : in);
@@ -435,39 +442,33 @@ __device__ __forceinline__ bool fan_radial_fast(const SonarDev &f, double rho2, 
     const float num = (float)__builtin_fma(-rc, rc, rho2);
     const float e = num * __builtin_amdgcn_rcpf(rho_f + (float)rc) * f.scale_r_f;
     axis_from_offset(in, e, f.n_range, i0, code);
-    return rho2 >= f.r_min * f.r_min && rho2 <= f.r_max * f.r_max;
 }
 
-// Angular half of a LEFT-half fan pixel (offset ax = -x_c >= 0 from the axis,
-// y_c > 0 along it): inside test and, for this pixel, the nearest column jn
-// and the offset e from its centre in columns; the mirror pixel has
-// N_phi - 1 - jn and -e.  Computed whatever the inside test says.
-__device__ __forceinline__ bool fan_angular_fast(const SonarDev &f, double ax, double yc, int &jn, float &e) {
-    jn = 0;
-    e = 0.0f;
-    if (f.n_az > 1) {
-        const float phi = atan2_pos_approx((float)ax, (float)yc);
-        int j = (int)__builtin_rintf((phi + f.half_az_f) * f.scale_phi_f - 0.5f);
-        j = j < 0 ? 0 : (j > f.n_az - 1 ? f.n_az - 1 : j);
-        const gptr<const double> cs = (gptr<const double>)f.cols;   // {sin, cos} of the centre azimuth
-        const double sn = cs[2 * j], cn = cs[2 * j + 1];
-        // angle from the centre direction: atan of the cross over the dot product
-        const double cr = __builtin_fma(ax, cn, -yc * sn);
-        const double dt = __builtin_fma(ax, sn, yc * cn);
-        const float q = (float)cr * __builtin_amdgcn_rcpf((float)dt);
-        float d;
-        if (f.wide_cols) {
-            d = atanf(q);
-        } else {
-            // |q| < 0.05: the series to q^5 is exact to float precision
-            const float q2 = q * q;
-            d = q * __builtin_fmaf(q2, __builtin_fmaf(q2, 0.2f, -0.33333334f), 1.0f);
-        }
-        jn = j;
-        e = d * f.scale_phi_f;
+// Angular half of a LEFT-half fan pixel, in two steps so that the column
+// table loads of several pixels can be in flight together: the nearest column
+// from the approximate azimuth (clamped, valid for any position), then the
+// offset e from that column's centre in columns, from its {sin, cos}: the
+// mirror pixel has column N_phi - 1 - jn and offset -e.
+__device__ __forceinline__ int fan_column_guess(const SonarDev &f, double ax, double yc) {
+    const float phi = atan2_pos_approx((float)ax, (float)yc);
+    const int j = (int)__builtin_rintf((phi + f.half_az_f) * f.scale_phi_f - 0.5f);
+    return j < 0 ? 0 : (j > f.n_az - 1 ? f.n_az - 1 : j);
+}
+
+__device__ __forceinline__ float fan_column_offset(const SonarDev &f, double ax, double yc, double sn, double cn) {
+    // angle from the centre direction: atan of the cross over the dot product
+    const double cr = __builtin_fma(ax, cn, -yc * sn);
+    const double dt = __builtin_fma(ax, sn, yc * cn);
+    const float q = (float)cr * __builtin_amdgcn_rcpf((float)dt);
+    float d;
+    if (f.wide_cols) {
+        d = atanf(q);
+    } else {
+        // |q| < 0.05: the series to q^5 is exact to float precision
+        const float q2 = q * q;
+        d = q * __builtin_fmaf(q2, __builtin_fmaf(q2, 0.2f, -0.33333334f), 1.0f);
     }
-    // |phi| <= fov/2  <=>  ax cos(fov/2) <= yc sin(fov/2)   (fov <= pi, yc > 0)
-    return ax * f.cos_half_az <= yc * f.sin_half_az;
+    return d * f.scale_phi_f;
 }
 
 // Saved stencil of a pair of mirror-image fan pixels (left pixel u, right

@@ -294,18 +294,31 @@ __global__ __launch_bounds__(kBlock) void k_fan(Src src) {
     // geometry of every row first, then all gathers, then the blends: the
     // loads of the rows are in flight together.  The mirror pixel's stencil
     // is the left one's reflected: first column N_phi - 2 - j0, weights swapped.
-    int i0[kFanRows], jL[kFanRows];
+    int i0[kFanRows], jL[kFanRows], jn[kFanRows];
     float ct[kFanRows], cL[kFanRows];
+    double yc[kFanRows], rho2[kFanRows], sn[kFanRows], cn[kFanRows];
     bool in[kFanRows];
+    const gptr<const double> cols = (gptr<const double>)f.cols;   // {sin, cos} per column
 #pragma unroll
     for (int r = 0; r < kFanRows; ++r) {
-        const double yc = ((double)f.fan_h - (double)(v0 + 8 * r) - 0.5) * f.fan_s;
-        int jn;
-        float e;
-        const bool rin = fan_radial_fast(f, __builtin_fma(yc, yc, ax2), i0[r], ct[r]);
-        const bool ain = fan_angular_fast(f, ax, yc, jn, e);
-        in[r] = rin && ain;
-        axis_from_offset(jn, e, f.n_az, jL[r], cL[r]);
+        yc[r] = ((double)f.fan_h - (double)(v0 + 8 * r) - 0.5) * f.fan_s;
+        rho2[r] = __builtin_fma(yc[r], yc[r], ax2);
+        in[r] = v0 + 8 * r < f.fan_h && fan_inside(f, ax, yc[r], rho2[r]);
+        // the column-table loads of all rows in flight together (the index is
+        // clamped to the table, so they need no guard)
+        jn[r] = f.n_az > 1 ? fan_column_guess(f, ax, yc[r]) : 0;
+        sn[r] = cols[2 * jn[r]];
+        cn[r] = cols[2 * jn[r] + 1];
+    }
+#pragma unroll
+    for (int r = 0; r < kFanRows; ++r) {
+        i0[r] = jL[r] = 0;
+        ct[r] = cL[r] = 0.0f;
+        if (in[r]) {   // waves wholly outside the sector skip the stencil
+            fan_radial_fast(f, rho2[r], i0[r], ct[r]);
+            const float e = f.n_az > 1 ? fan_column_offset(f, ax, yc[r], sn[r], cn[r]) : 0.0f;
+            axis_from_offset(jn[r], e, f.n_az, jL[r], cL[r]);
+        }
     }
     float a[kFanRows][8];
 #pragma unroll
