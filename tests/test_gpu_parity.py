@@ -464,3 +464,58 @@ def test_sonar_backward_saved_matches_recomputed(shape):
     for g_refl, g_par in (a, b):
         assert_grad_cond(g_refl, o_refl, c_refl, what="refl vs oracle")
         assert_grad_cond(g_par[0, :5], o_par, c_par, what="params vs oracle")
+
+
+@pytest.mark.parametrize("per_return_refl", [False, True])
+def test_sonar_backward_many_frames_and_rows(per_return_refl):
+    """Seven uneven frames in one backward call, sharing four parameter rows
+    (frames 0, 3 on row 0; 1, 4 on row 1; 2, 5 on row 2; 6 on row 3), every
+    speckle mode, a shared 20-material table or per-return reflectivity:
+    each row's gradient is the sum over its frames, the reflectivity gradient
+    the sum over all."""
+    import torch
+    osm = _osm()
+    _say("sonar backward, 7 frames on 4 parameter rows, per-return reflectivity %s" % per_return_refl)
+    st = W.Stream(4400, 7 + per_return_refl)
+    rows = [0, 1, 2, 0, 1, 2, 3]
+    modes = [W.SPECKLE_GAMMA, W.SPECKLE_PAPER, W.SPECKLE_OFF, W.SPECKLE_GAMMA, W.SPECKLE_PAPER, W.SPECKLE_OFF,
+             W.SPECKLE_GAMMA]
+    frames = []
+    for k, (r, mode) in enumerate(zip(rows, modes)):
+        spec = W.SonarSpec(r_min=0.5, r_max=8.0 + k, n_range=30 + 7 * k, n_azimuth=24 + 5 * k, fan_h=20 + 3 * k,
+                           fan_w=41 + 6 * k, alpha=0.05 + 0.02 * r, gain=0.8 + 0.2 * r, sigma_phi=0.2 + 0.05 * r,
+                           sigma_sa=0.1 + 0.02 * r, sigma_sm=0.1 + 0.03 * r, speckle_mode=mode, gamma_k=3,
+                           seed_lo=5, frame_id=k)
+        frames.append(W.SonarFrame(spec, W.make_hits(st, spec, 900 + 300 * k, n_materials=20)))
+    if per_return_refl:
+        frames, refl = merged(frames)            # one reflectivity per return (ids offset per frame)
+    else:
+        refl = frames[0].hits.refl
+        for f in frames:
+            f.hits.refl = refl
+    gpol = [W.loss_weights((4401, k), (f.spec.n_range, f.spec.n_azimuth)) for k, f in enumerate(frames)]
+    gfan = [W.loss_weights((4402, k), (f.spec.fan_h, f.spec.fan_w)) for k, f in enumerate(frames)]
+    geoms = [osm.SonarGeometry.from_spec(f.spec, param_row=r) for f, r in zip(frames, rows)]
+    hits = [osm.DeviceHits.from_host(f.hits) for f in frames]
+    row_spec = {r: f.spec for f, r in zip(frames, rows)}
+    params = osm.sonar_params([osm.sonar_params_from_spec(row_spec[r]) for r in range(4)])
+    refl_d = torch.as_tensor(refl).cuda()
+    outs = osm.render_sonar(geoms, hits, params, refl_d, save_stencil=True)
+    g_refl, g_par = osm.render_sonar_backward(
+        geoms, hits, params, refl_d, [torch.as_tensor(g).cuda() for g in gpol],
+        [torch.as_tensor(g).cuda() for g in gfan], [o.get("stencil") for o in outs])
+    torch.cuda.synchronize()
+    g_refl = g_refl.cpu().numpy().astype(np.float64)
+    g_par = g_par.cpu().numpy().astype(np.float64)
+    o_refl, c_refl = np.zeros(refl.shape[0]), np.zeros(refl.shape[0])
+    o_par, c_par = np.zeros((4, 5)), np.zeros((4, 5))
+    for f, r, gp, gf in zip(frames, rows, gpol, gfan):
+        a, b, _, ca, cb = oracle.sonar_backward(SonarConfig.from_spec(f.spec), f.hits, refl, gp, gf, with_abs=True)
+        o_refl += a
+        c_refl += ca
+        o_par[r] += b
+        c_par[r] += cb
+    assert_grad_cond(g_refl, o_refl, c_refl, what="refl")
+    for r in range(4):
+        assert_grad_cond(g_par[r, :5], o_par[r], c_par[r], what="row %d" % r)
+    assert np.all(g_par[:, 5:] == 0)
