@@ -48,6 +48,7 @@ struct SonarGrid {
     int max_tile_bins;   // largest forward tile of a frame, in bins
     int max_tile_bins_b; // largest backward tile of a frame, in bins
     int all_saved;       // every frame with a fan gradient has saved fan stencils
+    int max_n_az;        // widest polar grid of a frame (azimuth cells)
 };
 
 constexpr int kBwdThreads = 512;   // threads of a backward polar-tile workgroup

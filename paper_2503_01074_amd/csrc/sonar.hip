@@ -138,7 +138,16 @@ __device__ __forceinline__ void tile_fwd_block(const Src &src, const oceansim_so
     const int nbins = b_hi - b_lo;
     float *acc = reinterpret_cast<float *>(lds_raw);           // [tile_bins]
     int *list = reinterpret_cast<int *>(acc + f.tile_bins);    // [tile_bins]
+    float *etab = reinterpret_cast<float *>(list + f.tile_bins);   // [n_az]: beam pattern of Eq. 3 per column
     const bool speckle = f.speckle != SPECKLE_OFF;
+    const oceansim_sonar_params pr = params[f.param_row];
+    const AddCtx ctx{pr.sigma_sa, 1.0f / pr.sigma_phi};
+    // the column factor exp(-phi_j^2 / sigma_phi) once per column of the tile's rows
+    if (speckle)
+        for (int j = tid; j < f.n_az; j += kBlock) {
+            const float phi = bin_azimuth(f, j);
+            etab[j] = expf(-(phi * phi) * ctx.inv_sigma_phi);
+        }
 
     // side job for the fan launch that follows: {sin, cos} of the column-centre azimuths
     if (f.cols)
@@ -192,7 +201,6 @@ __device__ __forceinline__ void tile_fwd_block(const Src &src, const oceansim_so
         __syncthreads();
     }
 
-    const oceansim_sonar_params pr = params[f.param_row];
     const float G = pr.gain;
     if (speckle) {
         // Q m for the listed (nonempty) bins only: the other bins have Q = 0
@@ -206,7 +214,6 @@ __device__ __forceinline__ void tile_fwd_block(const Src &src, const oceansim_so
         __syncthreads();
     }
 
-    AddCtx ctx{pr.sigma_sa, 1.0f / pr.sigma_phi};
     // groups of four consecutive frame-linear bins share one additive Philox call
     const int q_first = b_lo >> 2, q_last = (b_hi - 1) >> 2;
     for (int q = q_first + tid; q <= q_last; q += kBlock) {
@@ -222,12 +229,17 @@ __device__ __forceinline__ void tile_fwd_block(const Src &src, const oceansim_so
             const Words wd = philox((uint32_t)q, f.frame_id, 0u, 0u, f.seed_lo, f.seed_hi);
             int i = b0 / f.n_az;
             int j = b0 - i * f.n_az;
+            float R = range_ramp(f, i);
 #pragma unroll
             for (int w = 0; w < 4; ++w) {
-                float E, rho, R, phi;
-                const float add = additive_term(f, ctx, i, j, pick(wd, (uint32_t)w), E, rho, R, phi);
+                // additive term of Eq. (3)-(4): R_i (1 + 0.5 E_j sigma_sa rho)
+                const float rho = rayleigh_of_word(pick(wd, (uint32_t)w));
+                const float add = R * (1.0f + 0.5f * etab[j] * (ctx.sigma_sa * rho));
                 out[w] = (in[w] ? acc[b0 + w - b_lo] : 0.0f) + add;
-                if (++j == f.n_az) { j = 0; ++i; }
+                if (++j == f.n_az) {
+                    j = 0;
+                    R = range_ramp(f, ++i);
+                }
             }
         }
         if (in[0] && in[3]) {
@@ -885,11 +897,11 @@ static hipError_t launch_fwd(const Src &src, const SonarGrid &g, const oceansim_
     }
     if (uw && uw->blocks > 0)
         OSIM_LAUNCH("k_tile_uw", (k_tile_uw<Src>), dim3(g.tile_blocks + uw->blocks), dim3(kBlock),
-                    (size_t)g.max_tile_bins * 8, st, src, params, g.tile_blocks, Table<UwDev>{uw->table, uw->n},
-                    uw->params);
+                    (size_t)g.max_tile_bins * 8 + (size_t)g.max_n_az * 4, st, src, params, g.tile_blocks,
+                    Table<UwDev>{uw->table, uw->n}, uw->params);
     else
-        OSIM_LAUNCH("k_tile", (k_tile<Src>), dim3(g.tile_blocks), dim3(kBlock), (size_t)g.max_tile_bins * 8, st,
-                    src, params);
+        OSIM_LAUNCH("k_tile", (k_tile<Src>), dim3(g.tile_blocks), dim3(kBlock),
+                    (size_t)g.max_tile_bins * 8 + (size_t)g.max_n_az * 4, st, src, params);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     if (g.fan_blocks > 0) {
