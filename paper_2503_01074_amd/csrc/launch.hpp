@@ -84,6 +84,7 @@ hipError_t sonar_backward_table(const SonarDev *t, int n, const SonarGrid &g,
 // per-workgroup parameter partial sums amortised over 8 pixels).
 constexpr int kUwFwdPixelsPerThread = 4;
 constexpr int kUwBwdPixelsPerThread = 8;
+constexpr int kUwBwdLoadsInFlight = 1;
 constexpr int kUwFwdPixelsPerBlock = kBlock * kUwFwdPixelsPerThread;
 constexpr int kUwBwdPixelsPerBlock = kBlock * kUwBwdPixelsPerThread;
 

@@ -44,9 +44,10 @@ __device__ __forceinline__ float exp_nonpos(float x) {
 
 // 1 - e^-x for x >= 0, given e = e^-x: the difference where it loses at most
 // two bits (x > 1/4), else the Taylor series of -expm1(-x) to x^7 (its
-// remainder is below 2e-9 relative there).
+// remainder is below 2e-9 relative there).  Both are evaluated and one is
+// selected: a branch here splits the unrolled pixel loop into divergent
+// blocks and keeps every pixel's intermediates live across them.
 __device__ __forceinline__ float one_minus_exp_neg(float x, float e) {
-    if (x > 0.25f) return 1.0f - e;
     float p = 1.0f / 5040.0f;
     p = __builtin_fmaf(p, x, -1.0f / 720.0f);
     p = __builtin_fmaf(p, x, 1.0f / 120.0f);
@@ -54,7 +55,9 @@ __device__ __forceinline__ float one_minus_exp_neg(float x, float e) {
     p = __builtin_fmaf(p, x, 1.0f / 6.0f);
     p = __builtin_fmaf(p, x, -0.5f);
     p = __builtin_fmaf(p, x, 1.0f);
-    return p * x;
+    const float near = p * x;
+    const float far = 1.0f - e;
+    return x > 0.25f ? far : near;
 }
 
 __device__ __forceinline__ float uw_pixel(float J, float d, float bd, float bb, float bi) {
@@ -99,7 +102,7 @@ __device__ __forceinline__ void uw_fwd_block(const Src &src, const oceansim_wate
                 o.y = uw_pixel(J[it][c].y, d[it].y, w.bd[c], w.bb[c], w.bi[c]);
                 o.z = uw_pixel(J[it][c].z, d[it].z, w.bd[c], w.bb[c], w.bi[c]);
                 o.w = uw_pixel(J[it][c].w, d[it].w, w.bd[c], w.bb[c], w.bi[c]);
-                gstore((gptr<float4>)(Op + c * npix + p), o);
+                gstore_stream((gptr<float4>)(Op + c * npix + p), o);
             }
         }
         return;
@@ -110,7 +113,8 @@ __device__ __forceinline__ void uw_fwd_block(const Src &src, const oceansim_wate
         for (long long q = p; q < p + 4 && q < npix; ++q) {
             const float d = Dp[q];
 #pragma unroll
-            for (int c = 0; c < 3; ++c) Op[c * npix + q] = uw_pixel(Jp[c * npix + q], d, w.bd[c], w.bb[c], w.bi[c]);
+            for (int c = 0; c < 3; ++c)
+                gstore_stream(Op + c * npix + q, uw_pixel(Jp[c * npix + q], d, w.bd[c], w.bb[c], w.bi[c]));
         }
     }
 }
@@ -151,6 +155,11 @@ __device__ __forceinline__ void uw_bwd_block(const Src &src, const oceansim_wate
     const gptr<float> __restrict__ GJ = f.grad_J;
     const gptr<float> __restrict__ GD = f.grad_depth;
     constexpr int kIt = (NT * kUwBwdPixelsPerThread) / (NT * 4);
+    // float4 iterations whose loads are in flight together: one keeps the
+    // kernel near 64 VGPRs (more waves per SIMD hide the HBM latency better
+    // than more loads per wave)
+    constexpr int kH = kUwBwdLoadsInFlight;
+    static_assert(kIt % kH == 0, "iterations must split into groups of kH");
     // per-thread partial sums of 8 pixels in FP32 (|error| <= ~5e-7 of the sum
     // of the magnitudes), then FP64 across threads and workgroups
     float acc[9];
@@ -158,11 +167,10 @@ __device__ __forceinline__ void uw_bwd_block(const Src &src, const oceansim_wate
     for (int k = 0; k < 9; ++k) acc[k] = 0.0f;
     if ((npix & 3) == 0 && p0 + (NT * kUwBwdPixelsPerThread) <= npix) {
 #pragma unroll
-        for (int it = 0; it < kIt; it += 2) {
-            // two iterations' loads in flight together
-            float4 d[2], J[2][3], g[2][3];
+        for (int it = 0; it < kIt; it += kH) {
+            float4 d[kH], J[kH][3], g[kH][3];
 #pragma unroll
-            for (int h = 0; h < 2; ++h) {
+            for (int h = 0; h < kH; ++h) {
                 const long long p = p0 + ((long long)(it + h) * NT + threadIdx.x) * 4;
                 d[h] = gload((gptr<const float4>)(Dp + p));
 #pragma unroll
@@ -172,7 +180,7 @@ __device__ __forceinline__ void uw_bwd_block(const Src &src, const oceansim_wate
                 }
             }
 #pragma unroll
-            for (int h = 0; h < 2; ++h) {
+            for (int h = 0; h < kH; ++h) {
                 const long long p = p0 + ((long long)(it + h) * NT + threadIdx.x) * 4;
                 float4 gdv = make_float4(0.f, 0.f, 0.f, 0.f);
 #pragma unroll
@@ -182,9 +190,9 @@ __device__ __forceinline__ void uw_bwd_block(const Src &src, const oceansim_wate
                     gj.y = uw_pixel_bwd(g[h][c].y, J[h][c].y, d[h].y, w.bd[c], w.bb[c], w.bi[c], acc, c, gdv.y);
                     gj.z = uw_pixel_bwd(g[h][c].z, J[h][c].z, d[h].z, w.bd[c], w.bb[c], w.bi[c], acc, c, gdv.z);
                     gj.w = uw_pixel_bwd(g[h][c].w, J[h][c].w, d[h].w, w.bd[c], w.bb[c], w.bi[c], acc, c, gdv.w);
-                    if (GJ) gstore((gptr<float4>)(GJ + c * npix + p), gj);
+                    if (GJ) gstore_stream((gptr<float4>)(GJ + c * npix + p), gj);
                 }
-                if (GD) gstore((gptr<float4>)(GD + p), gdv);
+                if (GD) gstore_stream((gptr<float4>)(GD + p), gdv);
             }
         }
     } else {
@@ -198,9 +206,9 @@ __device__ __forceinline__ void uw_bwd_block(const Src &src, const oceansim_wate
                 for (int c = 0; c < 3; ++c) {
                     const float gj = uw_pixel_bwd(Gp[c * npix + q], Jp[c * npix + q], d, w.bd[c], w.bb[c],
                                                   w.bi[c], acc, c, gd);
-                    if (GJ) GJ[c * npix + q] = gj;
+                    if (GJ) gstore_stream(GJ + c * npix + q, gj);
                 }
-                if (GD) GD[q] = gd;
+                if (GD) gstore_stream(GD + q, gd);
             }
         }
     }
