@@ -18,7 +18,7 @@ CSRC = os.path.join(PKG, "csrc")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "liboceansim.so")
 SOURCES = ["api.cpp", "plan.cpp", "sonar.hip", "uw.hip"]
-HEADERS = ["device.hpp", "launch.hpp", "host.hpp", "uw_body.hpp"]
+HEADERS = ["device.hpp", "launch.hpp", "host.hpp", "uw_body.hpp", "reduce_body.hpp"]
 ARCH = os.environ.get("OCEANSIM_ARCH", "gfx950")
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

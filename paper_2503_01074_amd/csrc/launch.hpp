@@ -68,23 +68,46 @@ hipError_t sonar_forward_one(const SonarDev &f, const SonarGrid &g, const oceans
 hipError_t sonar_forward_table(const SonarDev *t, int n, const SonarGrid &g,
                                const oceansim_sonar_params *params, const float *refl, int n_mat,
                                hipStream_t st, const UwCompanion *uw = nullptr);
+// Arguments of the fixed-order reduction that ends a sonar backward launch
+// (`blocks` workgroups: n_rows * 8 parameter sums, then n_mat reflectivity
+// sums when the small-table path is used).
+struct SonarReduce {
+    const double *part = nullptr;
+    int n_slots = 0, n_rows = 0;
+    float *grad_params = nullptr;
+    const double *refl_part = nullptr;
+    int ret_slots = 0, n_mat = 0;
+    float *grad_refl = nullptr;
+    int blocks = 0;
+};
+// Arguments of a row-keyed reduction (n_rows * out_stride workgroups).
+struct RowsReduce {
+    const double *part = nullptr;
+    const int *row = nullptr;
+    int n_slots = 0, width = 0;
+    float *out = nullptr;
+    int out_stride = 0;
+    int blocks = 0;
+};
+
 // Backward: partial sums into part (column-major [5][tile and return
 // workgroups]) and refl_part (column-major [n_mat][return workgroups], small
 // tables), reduced in a fixed order into grad_params [n_rows][8] and
-// grad_refl [n_mat].
+// grad_refl [n_mat].  With `defer`, the reduction is not launched: its
+// arguments are returned there for a later reduce_pair.
 hipError_t sonar_backward_one(const SonarDev &f, const SonarGrid &g, const oceansim_sonar_params *params,
                               int n_rows, const float *refl, int n_mat, double *part, double *refl_part,
                               float *grad_params, float *grad_refl, hipStream_t st);
 hipError_t sonar_backward_table(const SonarDev *t, int n, const SonarGrid &g,
                                 const oceansim_sonar_params *params, int n_rows, const float *refl,
                                 int n_mat, double *part, double *refl_part, float *grad_params,
-                                float *grad_refl, hipStream_t st);
+                                float *grad_refl, hipStream_t st, SonarReduce *defer = nullptr);
 
 // Camera pixels per thread: one float4 group forward, two backward (the
 // per-workgroup parameter partial sums amortised over 8 pixels).
 constexpr int kUwFwdPixelsPerThread = 4;
 constexpr int kUwBwdPixelsPerThread = 8;
-constexpr int kUwBwdLoadsInFlight = 1;
+constexpr int kUwBwdLoadsInFlight = 2;
 constexpr int kUwFwdPixelsPerBlock = kBlock * kUwFwdPixelsPerThread;
 constexpr int kUwBwdPixelsPerBlock = kBlock * kUwBwdPixelsPerThread;
 
@@ -100,7 +123,8 @@ hipError_t uw_backward_table(const UwDev *t, int n, int blocks, const oceansim_w
 // (c < width; columns width..out_stride-1 are written 0), in a fixed order.
 hipError_t reduce_rows(const double *part, const int *row, int n_slots, int width, int n_rows,
                        float *out, int out_stride, hipStream_t st);
-// out[c] = sum over s of part[c * n_slots + s], fixed order.
-hipError_t reduce_cols(const double *part, int n_slots, int width, float *out, hipStream_t st);
+// A deferred sonar reduction and a row-keyed reduction in one launch (the
+// same per-output order as launching them apart, so the same bits).
+hipError_t reduce_pair(const SonarReduce &s, const RowsReduce &r, hipStream_t st);
 
 }  // namespace osim

@@ -105,17 +105,35 @@ hipError_t launch_forward(oceansim_plan *p, hipStream_t st) {
     return camera_forward(p, st);
 }
 
+// Sonar backward, then camera backward; with both, their two fixed-order
+// reductions run as one launch after the camera kernel.
 hipError_t launch_backward(oceansim_plan *p, hipStream_t st) {
     if (p->sonar.empty()) return camera_backward(p, st);
     const bool lane_hist = p->n_mat <= kLaneHistMats;
+    const bool pair = !p->camera.empty() && p->ub.blocks > 0;
+    SonarReduce sr;
     hipError_t e = sonar_backward_table(reinterpret_cast<const SonarDev *>(p->ws_sb + p->sb.off_table),
                                         (int)p->sonar.size(), p->sb.grid, p->sp, p->n_srows, p->refl, p->n_mat,
                                         reinterpret_cast<double *>(p->ws_sb + p->sb.off_part),
                                         lane_hist ? reinterpret_cast<double *>(p->ws_sb + p->sb.off_refl_part)
                                                   : nullptr,
-                                        p->g_sp, p->g_refl, st);
+                                        p->g_sp, p->g_refl, st, pair ? &sr : nullptr);
     if (e != hipSuccess) return e;
-    return camera_backward(p, st);
+    if (!pair) return camera_backward(p, st);
+    double *part = reinterpret_cast<double *>(p->ws_ub + p->ub.off_part);
+    int *row = reinterpret_cast<int *>(p->ws_ub + p->ub.off_part_row);
+    e = uw_backward_table(reinterpret_cast<const UwDev *>(p->ws_ub + p->ub.off_table), (int)p->camera.size(),
+                          p->ub.blocks, p->wp, part, row, st);
+    if (e != hipSuccess) return e;
+    RowsReduce rr;
+    rr.part = part;
+    rr.row = row;
+    rr.n_slots = p->ub.blocks;
+    rr.width = 9;
+    rr.out = p->g_wp;
+    rr.out_stride = OCEANSIM_WATER_GRAD_WIDTH;
+    rr.blocks = p->n_wrows * OCEANSIM_WATER_GRAD_WIDTH;
+    return reduce_pair(sr, rr, st);
 }
 
 // ---------------------------------------------------------------------------

@@ -24,6 +24,7 @@
 //               reflectivity partial sums).
 #include "device.hpp"
 #include "launch.hpp"
+#include "reduce_body.hpp"
 #include "uw_body.hpp"
 
 namespace osim {
@@ -844,32 +845,9 @@ __global__ __launch_bounds__(kBlock) void k_ret_bwd(Src src, const oceansim_sona
 // produce grad_params[row][col] from the slots of the frames using that row;
 // the following n_mat blocks (small tables) produce grad_refl.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(kBlock) void k_reduce_sonar(const double *part, int n_slots, int n_rows,
-                                                         float *grad_params, const double *refl_part,
-                                                         int ret_slots, int n_mat, float *grad_refl) {
+__global__ __launch_bounds__(kBlock) void k_reduce_sonar(SonarReduce a) {
     __shared__ double red[kBlock / kWave];
-    const int b = blockIdx.x;
-    if (b < n_rows * OCEANSIM_SONAR_GRAD_WIDTH) {
-        const int r = b / OCEANSIM_SONAR_GRAD_WIDTH, c = b % OCEANSIM_SONAR_GRAD_WIDTH;
-        double s = 0.0;
-        if (c < 5) {
-            // every slot (tiles, then return chunks) whose frame uses row r
-            const double *a = part + (long long)c * n_slots;
-            const int *row = reinterpret_cast<const int *>(part + 5LL * n_slots);
-            s = thread_share_sum(n_slots, [&](int k) {
-                const double v = a[k];
-                return row[k] == r ? v : 0.0;
-            });
-        }
-        const double tot = block_sum(s, red);
-        if (threadIdx.x == 0) grad_params[b] = (float)tot;
-    } else {
-        const int m = b - n_rows * OCEANSIM_SONAR_GRAD_WIDTH;
-        const double *a = refl_part ? refl_part + (long long)m * ret_slots : nullptr;
-        const double s = a ? thread_share_sum(ret_slots, [&](int k) { return a[k]; }) : 0.0;
-        const double tot = block_sum(s, red);
-        if (threadIdx.x == 0) grad_refl[m] = (float)tot;
-    }
+    sonar_reduce_block(a, blockIdx.x, red);
 }
 
 // ---------------------------------------------------------------------------
@@ -915,7 +893,7 @@ template <class Src>
 static hipError_t launch_bwd(const Src &src, int n_frames, const SonarGrid &g,
                              const oceansim_sonar_params *params, int n_rows, const float *refl, int n_mat,
                              double *part, double *refl_part, float *grad_params, float *grad_refl,
-                             hipStream_t st) {
+                             hipStream_t st, SonarReduce *defer) {
     const bool lane_hist = n_mat <= kLaneHistMats;
     const int n_slots = g.tile_b_blocks + g.ret_blocks;   // partial-sum slots: tiles, then return chunks
     hipError_t e = hipSuccess;
@@ -945,9 +923,21 @@ static hipError_t launch_bwd(const Src &src, int n_frames, const SonarGrid &g,
     // small tables are reduced here; the atomic path was zeroed by k_tile_bwd,
     // unless there was no tile at all (then the reduction writes zeros)
     const bool refl_blocks = lane_hist || g.tile_b_blocks == 0;
-    const int blocks = n_rows * OCEANSIM_SONAR_GRAD_WIDTH + (refl_blocks ? n_mat : 0);
-    OSIM_LAUNCH("k_reduce_sonar", k_reduce_sonar, dim3(blocks), dim3(kBlock), 0, st, part, n_slots, n_rows,
-                grad_params, lane_hist ? refl_part : nullptr, g.ret_blocks, n_mat, grad_refl);
+    SonarReduce a;
+    a.part = part;
+    a.n_slots = n_slots;
+    a.n_rows = n_rows;
+    a.grad_params = grad_params;
+    a.refl_part = lane_hist ? refl_part : nullptr;
+    a.ret_slots = g.ret_blocks;
+    a.n_mat = n_mat;
+    a.grad_refl = grad_refl;
+    a.blocks = n_rows * OCEANSIM_SONAR_GRAD_WIDTH + (refl_blocks ? n_mat : 0);
+    if (defer) {
+        *defer = a;
+        return hipSuccess;
+    }
+    OSIM_LAUNCH("k_reduce_sonar", k_reduce_sonar, dim3(a.blocks), dim3(kBlock), 0, st, a);
     return hipGetLastError();
 }
 
@@ -964,14 +954,14 @@ hipError_t sonar_backward_one(const SonarDev &f, const SonarGrid &g, const ocean
                               int n_rows, const float *refl, int n_mat, double *part, double *refl_part,
                               float *grad_params, float *grad_refl, hipStream_t st) {
     return launch_bwd(One<SonarDev>{f}, 1, g, params, n_rows, refl, n_mat, part, refl_part, grad_params,
-                      grad_refl, st);
+                      grad_refl, st, nullptr);
 }
 hipError_t sonar_backward_table(const SonarDev *t, int n, const SonarGrid &g,
                                 const oceansim_sonar_params *params, int n_rows, const float *refl,
                                 int n_mat, double *part, double *refl_part, float *grad_params,
-                                float *grad_refl, hipStream_t st) {
+                                float *grad_refl, hipStream_t st, SonarReduce *defer) {
     return launch_bwd(Table<SonarDev>{t, n}, n, g, params, n_rows, refl, n_mat, part, refl_part, grad_params,
-                      grad_refl, st);
+                      grad_refl, st, defer);
 }
 
 }  // namespace osim

@@ -6,6 +6,7 @@
 // and written as float4 on planar [3][H][W] images.  The backward kernel
 // reduces the nine parameter gradients per workgroup in FP64 and a fixed
 // order; the final per-row sum is reduce_rows.
+#include "reduce_body.hpp"
 #include "uw_body.hpp"
 
 namespace osim {
@@ -47,43 +48,44 @@ hipError_t uw_backward_table(const UwDev *t, int n, int blocks, const oceansim_w
 // ---------------------------------------------------------------------------
 // Fixed-order reductions of per-workgroup partial sums.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(kBlock) void k_reduce_rows(const double *part, const int *row, int n_slots,
-                                                        int width, float *out, int out_stride) {
+__global__ __launch_bounds__(kBlock) void k_reduce_rows(RowsReduce a) {
     __shared__ double red[kBlock / kWave];
-    const int r = blockIdx.x / out_stride, c = blockIdx.x % out_stride;
-    double s = 0.0;
-    if (c < width) {
-        // column c of the column-major partials, slots of row r
-        const double *a = part + (long long)c * n_slots;
-        s = thread_share_sum(n_slots, [&](int k) {
-            const double v = a[k];   // both loads issued; the row decides
-            return row[k] == r ? v : 0.0;
-        });
-    }
-    const double tot = block_sum(s, red);
-    if (threadIdx.x == 0) out[(long long)r * out_stride + c] = c < width ? (float)tot : 0.0f;
+    rows_reduce_block(a, blockIdx.x, red);
 }
 
-__global__ __launch_bounds__(kBlock) void k_reduce_cols(const double *part, int n_slots, int width,
-                                                        float *out) {
+// The sonar reduction's workgroups, then the row-keyed reduction's.
+__global__ __launch_bounds__(kBlock) void k_reduce_pair(SonarReduce s, RowsReduce r) {
     __shared__ double red[kBlock / kWave];
-    const int c = blockIdx.x;
-    double s = 0.0;
-    for (int k = threadIdx.x; k < n_slots; k += kBlock) s += part[(long long)c * n_slots + k];
-    const double tot = block_sum(s, red);
-    if (threadIdx.x == 0) out[c] = (float)tot;
+    if ((int)blockIdx.x < s.blocks)
+        sonar_reduce_block(s, blockIdx.x, red);
+    else
+        rows_reduce_block(r, blockIdx.x - s.blocks, red);
+}
+
+static RowsReduce rows_args(const double *part, const int *row, int n_slots, int width, int n_rows, float *out,
+                            int out_stride) {
+    RowsReduce a;
+    a.part = part;
+    a.row = row;
+    a.n_slots = n_slots;
+    a.width = width;
+    a.out = out;
+    a.out_stride = out_stride;
+    a.blocks = n_rows * out_stride;
+    return a;
 }
 
 hipError_t reduce_rows(const double *part, const int *row, int n_slots, int width, int n_rows, float *out,
                        int out_stride, hipStream_t st) {
-    OSIM_LAUNCH("k_reduce_rows", k_reduce_rows, dim3(n_rows * out_stride), dim3(kBlock), 0, st, part, row, n_slots,
-                       width, out, out_stride);
+    const RowsReduce a = rows_args(part, row, n_slots, width, n_rows, out, out_stride);
+    OSIM_LAUNCH("k_reduce_rows", k_reduce_rows, dim3(a.blocks), dim3(kBlock), 0, st, a);
     return hipGetLastError();
 }
 
-hipError_t reduce_cols(const double *part, int n_slots, int width, float *out, hipStream_t st) {
-    OSIM_LAUNCH("k_reduce_cols", k_reduce_cols, dim3(width), dim3(kBlock), 0, st, part, n_slots, width, out);
+hipError_t reduce_pair(const SonarReduce &s, const RowsReduce &r, hipStream_t st) {
+    OSIM_LAUNCH("k_reduce_pair", k_reduce_pair, dim3(s.blocks + r.blocks), dim3(kBlock), 0, st, s, r);
     return hipGetLastError();
 }
+
 
 }  // namespace osim
