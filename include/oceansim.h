@@ -255,7 +255,7 @@ enum {
 };
 
 /* Validates every frame, chooses launch shapes, allocates the plan's own
- * device memory (workspaces, frame tables, saved fan stencils), uploads the
+ * device memory (workspaces, frame tables, transposed fan operators), uploads the
  * frame tables and, with OCEANSIM_PLAN_GRAPH, captures the forward (and
  * backward) launch sequences into HIP graphs.  A plan holding both sonar and
  * camera frames runs the camera forward inside the launch of the sonar
@@ -269,14 +269,20 @@ enum {
  * camera frames' grad_out are read by oceansim_plan_backward, which writes
  * grad_refl_dev [n_materials], grad_sonar_params_dev [n_sonar_rows][8] and
  * grad_water_params_dev [n_water_rows][9] (each may be NULL when there are no
- * frames of that kind).  For frames with a fan and a fan gradient the plan
- * saves the fan stencils in the forward pass for the backward pass.  The
+ * frames of that kind).  The fan of a frame is a fixed linear map of its
+ * polar image; for frames with a fan and a fan gradient a backward plan
+ * builds the transpose of that map once, at creation (for each polar bin,
+ * the fan pixels that read it and their bilinear weights, from the same
+ * stencils the fan kernel computes: one int per bin plus 8 bytes per
+ * pixel-bin pair, on the order of 40 bytes per fan pixel), and its backward
+ * gathers each bin's fan gradient through it.  The plan's forward saves no
+ * stencils (a caller's own fan_stencil buffer is still written).  The
  * forward is the image formation of oceansim_sonar_render (Sec. III-A.2,
  * Eq. 2-6, and the fan) and oceansim_uw_form (Sec. III-A.1, Eq. 1); the
  * backward is their adjoint and reads what the plan's latest forward left
- * (bins, saved stencils), so order the two on one stream.
+ * (bins), so order the two on one stream.
  *
- * OCEANSIM_PLAN_AUTOTUNE times the forward (and backward) launch for a small
+ * OCEANSIM_PLAN_AUTOTUNE times the forward launch for a small
  * set of tile and chunk sizes and keeps the fastest whose outputs agree with
  * the default shape's (1e-5 relative); results are cached per process and,
  * when the environment variable OCEANSIM_TUNE_CACHE names a file, in that
@@ -298,8 +304,8 @@ int oceansim_plan_create(const oceansim_sonar_frame *sonar, int32_t n_sonar,
 int oceansim_plan_forward(oceansim_plan *plan, void *stream);
 int oceansim_plan_backward(oceansim_plan *plan, void *stream);
 
-/* Launch shapes in use: {forward tile bins, returns per chunk, backward tile
- * bins, graphs in use (0/1)}. */
+/* Launch shapes in use: {forward tile bins, returns per chunk, polar bins
+ * per backward workgroup (0 without a sonar backward), graphs in use (0/1)}. */
 int oceansim_plan_shape(const oceansim_plan *plan, int32_t shape[4]);
 
 /* Frees the plan's device memory and graphs (after synchronising the

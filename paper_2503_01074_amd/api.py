@@ -305,7 +305,7 @@ class Plan:
 
     def shape(self) -> dict:
         a = _lib.oceansim_plan_shape(self.handle)
-        return {"fwd_tile_bins": a[0], "chunk": a[1], "bwd_tile_bins": a[2], "graph": bool(a[3])}
+        return {"fwd_tile_bins": a[0], "chunk": a[1], "bwd_block_bins": a[2], "graph": bool(a[3])}
 
     def close(self) -> None:
         if self.handle:

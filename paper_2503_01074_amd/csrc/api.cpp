@@ -194,7 +194,7 @@ int plan_sonar(const oceansim_sonar_frame *frames, int n_frames, int n_param_row
     P.off_polar.assign(n_frames, (size_t)-1);
     P.off_cols.assign(n_frames, (size_t)-1);
     P.off_grad_img.assign(n_frames, 0);
-    int bin_blocks = 0, tile_blocks = 0, tile_b_blocks = 0, fan_blocks = 0, ret_blocks = 0;
+    int bin_blocks = 0, tile_blocks = 0, tile_b_blocks = 0, fan_blocks = 0, ret_blocks = 0, fant_blocks = 0;
     for (int i = 0; i < n_frames; ++i) {
         const oceansim_sonar_frame &fr = frames[i];
         SonarDev &d = P.dev[i];
@@ -224,6 +224,9 @@ int plan_sonar(const oceansim_sonar_frame *frames, int n_frames, int n_param_row
         d.blk[KFAN] = fan_blocks;
         d.blk[KRET] = ret_blocks;
         d.blk[KTILEB] = tile_b_blocks;
+        d.blk[KFANT] = fant_blocks;
+        d.n_fant_blocks = backward ? (int)((nb + kBlock - 1) / kBlock) : 0;
+        fant_blocks += d.n_fant_blocks;
         bin_blocks += d.n_chunks;
         tile_blocks += d.n_tiles;
         tile_b_blocks += d.n_tiles_b;
@@ -282,11 +285,14 @@ int plan_sonar(const oceansim_sonar_frame *frames, int n_frames, int n_param_row
     P.grid.fan_blocks = fan_blocks;
     P.grid.ret_blocks = ret_blocks;
     P.grid.tile_b_blocks = tile_b_blocks;
+    P.grid.fant_blocks = fant_blocks;
+    P.grid.use_fant = 0;
     P.grid.all_saved = 1;
     for (int i = 0; i < n_frames; ++i)
         if (frames[i].grad_fan && !frames[i].fan_stencil) P.grid.all_saved = 0;
     if (backward) {
-        P.n_slots = tile_b_blocks + ret_blocks;
+        // slots for either backward decomposition of the polar gradient
+        P.n_slots = std::max(tile_b_blocks, fant_blocks) + ret_blocks;
         // five FP64 partial sums per slot (column-major), then the slot's parameter row
         P.off_part = take((sizeof(double) * 5 + sizeof(int)) * (size_t)std::max(1, P.n_slots));
         if (n_mat <= kLaneHistMats)

@@ -19,7 +19,7 @@ constexpr int kFanTileU = 32;      // pixel pairs per fan workgroup along a row
 constexpr int kFanTileV = 32;      // fan rows per fan workgroup (8 x kFanRows)
 constexpr int kLaneHistMats = 64;    // materials reduced with lane-private LDS histograms
 
-enum Kind { KBIN = 0, KTILE = 1, KFAN = 2, KRET = 3, KTILEB = 4, KIND_COUNT = 5 };
+enum Kind { KBIN = 0, KTILE = 1, KFAN = 2, KRET = 3, KTILEB = 4, KFANT = 5, KIND_COUNT = 6 };
 enum Speckle { SPECKLE_OFF = 0, SPECKLE_PAPER = 1, SPECKLE_GAMMA = 2 };
 
 // Pointers into device global memory.  Descriptor pointers carry the global
@@ -104,6 +104,12 @@ struct SonarDev {
     double sin_half_az, cos_half_az;
     int wide_cols;              // columns wider than 0.09 rad: offsets need the full arctangent
     float r_min_f, scale_r_f;
+    // Transposed fan operator (plans): the entries of bin b are
+    // ft_ent[ft_ptr[b] .. ft_ptr[b + 1]), each {fan pixel v * fan_w + u,
+    // bilinear weight as float bits}, in a fixed order.  nullptr: none.
+    gptr<const int> ft_ptr;
+    gptr<const uint2> ft_ent;
+    int n_fant_blocks;          // backward workgroups of kBlock bins through the transposed operator
 };
 
 struct UwDev {

@@ -49,6 +49,8 @@ struct SonarGrid {
     int max_tile_bins_b; // largest backward tile of a frame, in bins
     int all_saved;       // every frame with a fan gradient has saved fan stencils
     int max_n_az;        // widest polar grid of a frame (azimuth cells)
+    int fant_blocks;     // backward workgroups of kBlock bins over all frames (transposed fan operator)
+    int use_fant;        // backward through the frames' transposed fan operators instead of polar tiles
 };
 
 constexpr int kBwdThreads = 512;   // threads of a backward polar-tile workgroup
@@ -68,6 +70,10 @@ hipError_t sonar_forward_one(const SonarDev &f, const SonarGrid &g, const oceans
 hipError_t sonar_forward_table(const SonarDev *t, int n, const SonarGrid &g,
                                const oceansim_sonar_params *params, const float *refl, int n_mat,
                                hipStream_t st, const UwCompanion *uw = nullptr);
+// The saved fan stencils of the frames of a forward table (column tables,
+// then the fan kernel's geometry alone: no image is read or written).
+hipError_t sonar_fan_stencils_table(const SonarDev *t, int n, const SonarGrid &g, hipStream_t st);
+
 // Arguments of the fixed-order reduction that ends a sonar backward launch
 // (`blocks` workgroups: n_rows * 8 parameter sums, then n_mat reflectivity
 // sums when the small-table path is used).

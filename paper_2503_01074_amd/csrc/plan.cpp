@@ -7,6 +7,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
+#include <cstdint>
 #include <cstring>
 #include <map>
 #include <mutex>
@@ -37,6 +38,11 @@ struct oceansim_plan {
     UwPlan uf, ub;
     char *mem = nullptr;        // workspaces and frame tables
     char *stencil_mem = nullptr;
+    // transposed fan operators of the sonar frames (backward plans), per frame
+    // (nullptr where a frame has none)
+    char *fant_mem = nullptr;
+    std::vector<const int *> fant_ptr;
+    std::vector<const uint2 *> fant_ent;
     char *ws_sf = nullptr, *ws_sb = nullptr, *ws_uf = nullptr, *ws_ub = nullptr;
     hipStream_t cap = nullptr;   // capture stream (default priority)
     // with both kinds of frames the camera frames ride along in the forward
@@ -246,7 +252,8 @@ double time_us(F fn, hipStream_t st) {
     return ms * 1e3 / 3.0;
 }
 
-// Chooses p->tune by timing candidates; the plan's stencil memory is set.
+// Chooses p->tune by timing forward candidates (the backward of a plan goes
+// through the transposed fan operators, whose shape is fixed).
 int autotune(oceansim_plan *p, hipStream_t st) {
     const std::string key = tune_key(p);
     {
@@ -258,7 +265,6 @@ int autotune(oceansim_plan *p, hipStream_t st) {
             return OCEANSIM_OK;
         }
     }
-    const bool bwd = (p->flags & OCEANSIM_PLAN_BACKWARD) != 0;
     const int n = (int)p->sonar.size();
     std::vector<Candidate> cands;
     cands.push_back(Candidate{});   // the default shape is the reference
@@ -343,78 +349,6 @@ int autotune(oceansim_plan *p, hipStream_t st) {
         if (cands[k].ok && cands[k].us < cands[best].us) best = k;
     Tuning chosen = cands[best].t;   // zeros: the built-in heuristic won
 
-    if (rc == OCEANSIM_OK && bwd) {
-        // restore the forward's saved stencils under the chosen shape, then
-        // time the backward tile sizes
-        SonarPlan fp;
-        rc = plan_sonar(p->sonar.data(), n, p->n_srows, p->n_mat, false, fp, &chosen, true);
-        std::vector<Candidate> bc;
-        for (int bt : {2048, 1024, 4096}) {
-            Candidate c;
-            c.t = chosen;
-            c.t.bwd_tile_bins = bt;
-            bc.push_back(c);
-        }
-        if (rc == OCEANSIM_OK && fp.bytes > ws) rc = fail(OCEANSIM_E_WORKSPACE, "autotune: forward workspace");
-        size_t wsb = 0;
-        for (auto &c : bc) {
-            if (rc) break;
-            rc = plan_sonar(p->sonar.data(), n, p->n_srows, p->n_mat, true, c.b, &c.t, true);
-            wsb = std::max(wsb, c.b.bytes);
-        }
-        char *tb = nullptr;
-        if (rc == OCEANSIM_OK) {
-            e = hipMalloc(&tb, wsb + 256);
-            if (e != hipSuccess) rc = hip_fail(e, "autotune workspace");
-        }
-        if (rc == OCEANSIM_OK) {
-            carve_sonar(fp, tmp, false);
-            e = upload_table(fp.dev, tmp, fp.off_table, st);
-            if (e == hipSuccess)
-                e = sonar_forward_table(reinterpret_cast<const SonarDev *>(tmp + fp.off_table), n, fp.grid, p->sp,
-                                        p->refl, p->n_mat, st);
-            std::vector<float> ref_g, got_g;
-            const size_t ng = (size_t)p->n_mat + (size_t)p->n_srows * OCEANSIM_SONAR_GRAD_WIDTH;
-            for (size_t k = 0; k < bc.size() && e == hipSuccess; ++k) {
-                Candidate &c = bc[k];
-                carve_sonar(c.b, tb, true);
-                e = upload_table(c.b.dev, tb, c.b.off_table, st);
-                const SonarDev *table = reinterpret_cast<const SonarDev *>(tb + c.b.off_table);
-                const bool lane_hist = p->n_mat <= kLaneHistMats;
-                auto run = [&]() {
-                    return sonar_backward_table(table, n, c.b.grid, p->sp, p->n_srows, p->refl, p->n_mat,
-                                                reinterpret_cast<double *>(tb + c.b.off_part),
-                                                lane_hist ? reinterpret_cast<double *>(tb + c.b.off_refl_part)
-                                                          : nullptr,
-                                                p->g_sp, p->g_refl, st);
-                };
-                if (e == hipSuccess) e = run();
-                std::vector<float> g(ng);
-                if (e == hipSuccess)
-                    e = hipMemcpyAsync(g.data(), p->g_refl, sizeof(float) * p->n_mat, hipMemcpyDeviceToHost, st);
-                if (e == hipSuccess)
-                    e = hipMemcpyAsync(g.data() + p->n_mat, p->g_sp,
-                                       sizeof(float) * p->n_srows * OCEANSIM_SONAR_GRAD_WIDTH,
-                                       hipMemcpyDeviceToHost, st);
-                if (e == hipSuccess) e = hipStreamSynchronize(st);
-                if (e != hipSuccess) break;
-                if (k == 0) ref_g = g;
-                float peak = 0.0f;
-                for (float v : ref_g) peak = std::max(peak, std::fabs(v));
-                c.ok = true;
-                for (size_t i = 0; i < ng; ++i)
-                    if (!(std::fabs(g[i] - ref_g[i]) <= 1e-5f * std::max(std::fabs(ref_g[i]), 1e-3f * peak)))
-                        c.ok = false;
-                if (c.ok) c.us = time_us(run, st);
-            }
-            if (e != hipSuccess) rc = hip_fail(e, "autotune backward");
-            size_t bbest = 0;
-            for (size_t k = 1; k < bc.size(); ++k)
-                if (bc[k].ok && bc[k].us < bc[bbest].us) bbest = k;
-            chosen.bwd_tile_bins = bc[bbest].t.bwd_tile_bins;
-        }
-        if (tb) (void)hipFree(tb);
-    }
     (void)hipStreamSynchronize(st);
     (void)hipFree(tmp);
     (void)hipFree(ref);
@@ -435,7 +369,152 @@ void free_plan(oceansim_plan *p) {
     if (p->cap) (void)hipStreamDestroy(p->cap);
     if (p->mem) (void)hipFree(p->mem);
     if (p->stencil_mem) (void)hipFree(p->stencil_mem);
+    if (p->fant_mem) (void)hipFree(p->fant_mem);
     delete p;
+}
+
+// ---------------------------------------------------------------------------
+// Transposed fan operators.  The fan of a frame is a fixed linear map of its
+// polar image (bilinear weights that depend on the geometry alone), so its
+// adjoint is a fixed sparse matrix: for each polar bin, the fan pixels that
+// read it and their weights.  It is built once per plan, on the host, from
+// the stencil records the fan kernel writes (the same bins and weights the
+// forward pass uses), in bin-major order with each bin's entries in pixel
+// order; the backward pass then gathers instead of scattering.
+// ---------------------------------------------------------------------------
+
+// Weight w and 1 - w of a stencil code (the device decoding, in FP32).
+void decode_code(float e, float &w, float &omw) {
+    if (std::signbit(e)) {
+        w = 1.0f + e;
+        omw = -e;
+    } else {
+        w = e;
+        omw = 1.0f - e;
+    }
+}
+
+struct HostRec {
+    int i0, j0, ct, cl;
+};
+
+// Visits the entries of one frame's transposed operator in pixel order:
+// fn(bin, pixel, weight).  The corners and the mirror pixel follow the
+// backward tile kernel's reading of a saved stencil.
+template <class Fn>
+void for_each_entry(const oceansim_sonar_frame &f, const std::vector<HostRec> &recs, Fn fn) {
+    const int W = f.fan_w, half_w = (f.fan_w + 1) / 2, n_az = f.n_azimuth;
+    const bool one_row = f.n_range == 1, one_col = n_az == 1;
+    for (int v = 0; v < f.fan_h; ++v)
+        for (int u = 0; u < half_w; ++u) {
+            const HostRec &r = recs[(size_t)v * half_w + u];
+            if (r.i0 < 0) continue;
+            float ct, cl, t, omt;
+            std::memcpy(&ct, &r.ct, 4);
+            std::memcpy(&cl, &r.cl, 4);
+            decode_code(ct, t, omt);
+            const int um = W - 1 - u;
+            for (int side = 0; side < 2; ++side) {
+                if (side == 1 && um == u) break;
+                const int j0 = side == 0 || one_col ? r.j0 : n_az - 2 - r.j0;
+                float sw, omsw;
+                decode_code(side == 0 || one_col ? cl : -cl, sw, omsw);
+                const long long pix = (long long)v * W + (side == 0 ? u : um);
+                for (int a = 0; a < (one_row ? 1 : 2); ++a) {
+                    const double wa = a == 0 ? omt : t;
+                    for (int c = 0; c < (one_col ? 1 : 2); ++c) {
+                        const double wc = c == 0 ? omsw : sw;
+                        fn((long long)(r.i0 + a) * n_az + j0 + c, pix, (float)(wa * wc));
+                    }
+                }
+            }
+        }
+}
+
+// Stencils of the frames that need an operator, then the operators; the
+// plan's own stencil memory is released afterwards (the forward pass then
+// saves none).
+int build_fan_transposes(oceansim_plan *p, hipStream_t st) {
+    const int n = (int)p->sonar.size();
+    p->fant_ptr.assign(n, nullptr);
+    p->fant_ent.assign(n, nullptr);
+    std::vector<int> need;
+    for (int i = 0; i < n; ++i)
+        if (p->sonar[i].fan && p->sonar[i].grad_fan && p->sonar[i].fan_stencil) need.push_back(i);
+    if (need.empty()) return OCEANSIM_OK;
+    SonarPlan fp;
+    int rc = plan_sonar(p->sonar.data(), n, p->n_srows, p->n_mat, false, fp, nullptr, true);
+    if (rc) return rc;
+    char *ws = nullptr;
+    hipError_t e = hipMalloc(&ws, fp.bytes + 256);
+    if (e != hipSuccess) return hip_fail(e, "fan operator workspace");
+    carve_sonar(fp, ws, false);
+    e = upload_table(fp.dev, ws, fp.off_table, st);
+    if (e == hipSuccess)
+        e = sonar_fan_stencils_table(reinterpret_cast<const SonarDev *>(ws + fp.off_table), n, fp.grid, st);
+    std::vector<std::vector<HostRec>> recs(need.size());
+    for (size_t k = 0; k < need.size() && e == hipSuccess; ++k) {
+        const oceansim_sonar_frame &f = p->sonar[need[k]];
+        recs[k].resize((size_t)f.fan_h * ((f.fan_w + 1) / 2));
+        e = hipMemcpyAsync(recs[k].data(), f.fan_stencil, recs[k].size() * sizeof(HostRec), hipMemcpyDeviceToHost,
+                           st);
+    }
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    (void)hipFree(ws);
+    if (e != hipSuccess) return hip_fail(e, "fan stencils");
+    // bin-major layout: counts, offsets, then the entries in pixel order
+    std::vector<std::vector<int>> ptr(need.size());
+    std::vector<std::vector<uint2>> ent(need.size());
+    size_t bytes = 0;
+    std::vector<size_t> off_ptr(need.size()), off_ent(need.size());
+    for (size_t k = 0; k < need.size(); ++k) {
+        const oceansim_sonar_frame &f = p->sonar[need[k]];
+        const long long nb = (long long)f.n_range * f.n_azimuth;
+        std::vector<int> &P = ptr[k];
+        P.assign(nb + 1, 0);
+        long long total = 0;
+        for_each_entry(f, recs[k], [&](long long b, long long, float) {
+            ++P[b + 1];
+            ++total;
+        });
+        if (total > INT32_MAX || (long long)f.fan_h * f.fan_w > INT32_MAX)
+            return fail(OCEANSIM_E_UNSUPPORTED, "frame %d: fan operator too large", need[k]);
+        for (long long b = 0; b < nb; ++b) P[b + 1] += P[b];
+        std::vector<int> cur(P.begin(), P.end() - 1);
+        ent[k].resize((size_t)total);
+        for_each_entry(f, recs[k], [&](long long b, long long pix, float w) {
+            uint32_t wb;
+            std::memcpy(&wb, &w, 4);
+            ent[k][cur[b]++] = make_uint2((unsigned)pix, wb);
+        });
+        off_ptr[k] = bytes;
+        bytes = (bytes + sizeof(int) * P.size() + kWsAlign - 1) / kWsAlign * kWsAlign;
+        off_ent[k] = bytes;
+        bytes = (bytes + sizeof(uint2) * std::max<size_t>(1, ent[k].size()) + kWsAlign - 1) / kWsAlign * kWsAlign;
+    }
+    e = hipMalloc(&p->fant_mem, bytes);
+    if (e != hipSuccess) return hip_fail(e, "fan operator memory");
+    for (size_t k = 0; k < need.size() && e == hipSuccess; ++k) {
+        e = hipMemcpyAsync(p->fant_mem + off_ptr[k], ptr[k].data(), sizeof(int) * ptr[k].size(),
+                           hipMemcpyHostToDevice, st);
+        if (e == hipSuccess && !ent[k].empty())
+            e = hipMemcpyAsync(p->fant_mem + off_ent[k], ent[k].data(), sizeof(uint2) * ent[k].size(),
+                               hipMemcpyHostToDevice, st);
+        p->fant_ptr[need[k]] = reinterpret_cast<const int *>(p->fant_mem + off_ptr[k]);
+        p->fant_ent[need[k]] = reinterpret_cast<const uint2 *>(p->fant_mem + off_ent[k]);
+    }
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return hip_fail(e, "fan operator upload");
+    return OCEANSIM_OK;
+}
+
+// Backward tables of a plan read the frames' transposed operators.
+void attach_fan_transposes(const oceansim_plan *p, SonarPlan &P) {
+    for (size_t i = 0; i < P.dev.size() && i < p->fant_ptr.size(); ++i) {
+        P.dev[i].ft_ptr = gcast(p->fant_ptr[i]);
+        P.dev[i].ft_ent = gcast(p->fant_ent[i]);
+    }
+    P.grid.use_fant = 1;
 }
 
 int capture(oceansim_plan *p, bool backward, hipGraphExec_t *out) {
@@ -531,6 +610,20 @@ int oceansim_plan_create(const oceansim_sonar_frame *sonar, int32_t n_sonar, con
         for (int i = 0; i < n_sonar; ++i)
             if (st_off[i] != (size_t)-1) p->sonar[i].fan_stencil = p->stencil_mem + st_off[i];
     }
+    if (bwd && n_sonar > 0) {
+        rc = build_fan_transposes(p, st);
+        // the stencils were needed for the operators only
+        for (int i = 0; i < n_sonar; ++i)
+            if (st_off[i] != (size_t)-1) p->sonar[i].fan_stencil = nullptr;
+        if (p->stencil_mem) {
+            (void)hipFree(p->stencil_mem);
+            p->stencil_mem = nullptr;
+        }
+        if (rc) {
+            free_plan(p);
+            return rc;
+        }
+    }
     if ((flags & OCEANSIM_PLAN_AUTOTUNE) && n_sonar > 0) {
         rc = autotune(p, st);
         if (rc) {
@@ -541,7 +634,10 @@ int oceansim_plan_create(const oceansim_sonar_frame *sonar, int32_t n_sonar, con
     // final shapes
     if (n_sonar > 0) {
         rc = plan_sonar(p->sonar.data(), n_sonar, n_sonar_rows, n_materials, false, p->sf, &p->tune, true);
-        if (!rc && bwd) rc = plan_sonar(p->sonar.data(), n_sonar, n_sonar_rows, n_materials, true, p->sb, &p->tune, true);
+        if (!rc && bwd) {
+            rc = plan_sonar(p->sonar.data(), n_sonar, n_sonar_rows, n_materials, true, p->sb, &p->tune, true);
+            attach_fan_transposes(p, p->sb);
+        }
         if (rc) {
             free_plan(p);
             return rc;
@@ -613,7 +709,7 @@ int oceansim_plan_shape(const oceansim_plan *p, int32_t shape[4]) {
     if (!p || !shape) return fail(OCEANSIM_E_INVALID_ARG, "NULL argument");
     shape[0] = p->sf.grid.max_tile_bins;
     shape[1] = p->sf.grid.chunk;
-    shape[2] = p->sb.grid.max_tile_bins_b;
+    shape[2] = (p->flags & OCEANSIM_PLAN_BACKWARD) && !p->sonar.empty() ? kBlock : 0;   // bins per backward workgroup
     shape[3] = p->g_fwd ? 1 : 0;
     return ok();
 }

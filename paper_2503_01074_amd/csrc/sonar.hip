@@ -123,6 +123,15 @@ __device__ __forceinline__ float additive_term(const SonarDev &f, const AddCtx &
     return R * (1.0f + 0.5f * E * (c.sigma_sa * rho));
 }
 
+// Entry j of the fan's column table: {sin, cos} of column j's centre azimuth.
+__device__ __forceinline__ void write_fan_column(const SonarDev &f, int j) {
+    double sn, cs;
+    sincos(((double)j + 0.5) * f.dphi - f.half_az, &sn, &cs);
+    const gptr<double> cd = (gptr<double>)f.cols;
+    cd[2 * j] = sn;
+    cd[2 * j + 1] = cs;
+}
+
 // Forward polar tile `bid` of the launch (kBlock threads).
 template <class Src>
 __device__ __forceinline__ void tile_fwd_block(const Src &src, const oceansim_sonar_params *params, int bid) {
@@ -152,13 +161,7 @@ __device__ __forceinline__ void tile_fwd_block(const Src &src, const oceansim_so
 
     // side job for the fan launch that follows: {sin, cos} of the column-centre azimuths
     if (f.cols)
-        for (int j = tile * kBlock + tid; j < f.n_az; j += f.n_tiles * kBlock) {
-            double sn, cs;
-            sincos(((double)j + 0.5) * f.dphi - f.half_az, &sn, &cs);
-            const gptr<double> cd = (gptr<double>)f.cols;
-            cd[2 * j] = sn;
-            cd[2 * j + 1] = cs;
-        }
+        for (int j = tile * kBlock + tid; j < f.n_az; j += f.n_tiles * kBlock) write_fan_column(f, j);
     for (int k = tid; k < nbins; k += kBlock) acc[k] = 0.0f;
     for (int k = tid; k < (nbins + 31) / 32; k += kBlock) listed[k] = 0u;
     if (tid == 0) n_listed = 0;
@@ -280,7 +283,9 @@ __device__ __forceinline__ float polar_at(gptr<const float> base, int idx) {
     return *(gptr<const float>)((gptr<const char>)base + (uint32_t)idx * 4u);
 }
 
-template <class Src>
+// IMAGE = false: the stencil records alone (geometry only; the polar image is
+// not read and the fan is not written).
+template <class Src, bool IMAGE = true>
 __global__ __launch_bounds__(kBlock) void k_fan(Src src) {
     int local;
     const int fi = src.locate(xcd_grouped_id<16>(blockIdx.x, gridDim.x), KFAN, local);
@@ -338,7 +343,7 @@ __global__ __launch_bounds__(kBlock) void k_fan(Src src) {
     for (int r = 0; r < kFanRows; ++r) {
         const int b0 = (int)__umul24((unsigned)i0[r], (unsigned)f.n_az), b1 = b0 + row1;   // < 2^24 bins
         const int jr = mirror - jL[r];
-        if (!in[r]) {
+        if (!IMAGE || !in[r]) {
 #pragma unroll
             for (int k = 0; k < 8; ++k) a[r][k] = 0.0f;
             continue;
@@ -363,8 +368,10 @@ __global__ __launch_bounds__(kBlock) void k_fan(Src src) {
             decode_weight(cL[r], s, s1);
             const float left = t1 * (s1 * a[r][0] + s * a[r][1]) + t * (s1 * a[r][2] + s * a[r][3]);
             const float right = t1 * (s * a[r][4] + s1 * a[r][5]) + t * (s * a[r][6] + s1 * a[r][7]);
-            row[u] = in[r] ? left : 0.0f;
-            if (um != u) row[um] = in[r] ? right : 0.0f;
+            if (IMAGE) {
+                row[u] = in[r] ? left : 0.0f;
+                if (um != u) row[um] = in[r] ? right : 0.0f;
+            }
             if (rec)
                 gstore(rec, in[r] ? make_int4(i0[r], jL[r], __float_as_int(ct[r]), __float_as_int(cL[r]))
                                   : make_int4(-1, 0, 0, 0));
@@ -841,6 +848,112 @@ __global__ __launch_bounds__(kBlock) void k_ret_bwd(Src src, const oceansim_sona
 }
 
 // ---------------------------------------------------------------------------
+// k_fant_bwd: the polar gradient through the frames' transposed fan operators
+// (plans), one bin per thread: dL/dI[b] is the sum of weight * dL/dF over the
+// bin's entries, in FP64 and in the entries' fixed order (each product of
+// two floats is exact in FP64), plus the direct polar gradient; then the
+// adjoint of Eq. (3)-(4) as in the tile epilogue.  No candidate search, no
+// fixed-point scale, no workgroup barrier before the partial sums.
+//
+// The entries of a wave's 64 consecutive bins are contiguous: the wave reads
+// them in coalesced 64-entry chunks (lane k takes entry k of the chunk), so
+// the loads of one instruction are one span of 512 bytes and its fan
+// gathers are the neighbouring pixels of neighbouring bins; the products go
+// to the wave's slice of LDS, and each lane then sums its own bin's run.
+// ---------------------------------------------------------------------------
+constexpr int kFantChunks = 8;   // 64-entry chunks staged per round (512 entries per wave)
+
+template <class Src>
+__global__ __launch_bounds__(kBlock) void k_fant_bwd(Src src, const oceansim_sonar_params *params, double *part,
+                                                     int n_slots, float *grad_refl_zero, int n_mat_zero) {
+    __shared__ double prod[kBlock / kWave][kFantChunks * kWave];
+    int local;
+    const int bid = blockIdx.x;
+    const int fi = src.locate(bid, KFANT, local);
+    const SonarDev f = src.frame(fi);
+    const int tid = threadIdx.x;
+    const int lane = tid & (kWave - 1), wave = tid / kWave;
+    // the atomic reflectivity path (many materials) accumulates into a zeroed table
+    if (grad_refl_zero)
+        for (int k = bid * kBlock + tid; k < n_mat_zero; k += (int)gridDim.x * kBlock) grad_refl_zero[k] = 0.0f;
+    const int nb = f.n_range * f.n_az;
+    const int b = local * kBlock + tid;
+    const oceansim_sonar_params pr = params[f.param_row];
+    double g = 0.0;
+    if (f.ft_ptr) {
+        // this lane's entries [p_lo, p_hi); the wave's [w_lo, w_hi)
+        const int p_lo = f.ft_ptr[b < nb ? b : nb];
+        const int p_hi = f.ft_ptr[b + 1 < nb ? b + 1 : nb];
+        const int w_lo = __shfl(p_lo, 0, kWave), w_hi = __shfl(p_hi, kWave - 1, kWave);
+        double *slice = prod[wave];
+        for (int r0 = w_lo; r0 < w_hi; r0 += kFantChunks * kWave) {
+            uint2 en[kFantChunks];
+            float gv[kFantChunks];
+#pragma unroll
+            for (int c = 0; c < kFantChunks; ++c) {
+                const int e = r0 + c * kWave + lane;
+                en[c] = e < w_hi ? gload(f.ft_ent + e) : make_uint2(0u, 0u);
+            }
+#pragma unroll
+            for (int c = 0; c < kFantChunks; ++c) {
+                const int e = r0 + c * kWave + lane;
+                gv[c] = e < w_hi ? f.grad_fan[(long long)en[c].x] : 0.0f;
+            }
+#pragma unroll
+            for (int c = 0; c < kFantChunks; ++c) slice[c * kWave + lane] = (double)__uint_as_float(en[c].y) * (double)gv[c];
+            // the wave's own LDS writes, then its reads (no other wave touches the slice)
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            const int a = p_lo > r0 ? p_lo : r0;
+            const int z = p_hi < r0 + kFantChunks * kWave ? p_hi : r0 + kFantChunks * kWave;
+            for (int e = a; e < z; ++e) g += slice[e - r0];
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        }
+    }
+    double g_sphi = 0.0, g_ssa = 0.0;
+    if (b < nb) {
+        if (f.grad_polar) g += (double)f.grad_polar[b];
+        f.grad_img[b] = (float)g;
+        if (f.speckle != SPECKLE_OFF) {
+            // d add / d sigma_sa and d add / d sigma_phi of Eq. (3)-(4); the
+            // bin's Philox word is the one its forward tile drew
+            const Words wd = philox((uint32_t)(b >> 2), f.frame_id, 0u, 0u, f.seed_lo, f.seed_hi);
+            const int i = b / f.n_az, j = b - i * f.n_az;
+            const AddCtx ctx{pr.sigma_sa, 1.0f / pr.sigma_phi};
+            const double dsphi = 0.5 * (double)pr.sigma_sa / ((double)pr.sigma_phi * (double)pr.sigma_phi);
+            float E, rho, R, phi;
+            additive_term(f, ctx, i, j, pick(wd, (uint32_t)(b & 3)), E, rho, R, phi);
+            const double t = g * (double)R * (double)E * (double)rho;
+            g_ssa = 0.5 * t;
+            g_sphi = t * dsphi * ((double)phi * (double)phi);
+        }
+    }
+    __shared__ double red2[2 * (kBlock / kWave)];
+    const double sums[2] = {g_sphi, g_ssa};
+    const double tot = block_sum_n<2, kBlock>(sums, red2);   // thread 0: sigma_phi, thread 1: sigma_sa
+    if (tid == 0) {
+        reinterpret_cast<int *>(part + 5LL * n_slots)[bid] = f.param_row;
+        part[0LL * n_slots + bid] = 0.0;
+        part[1LL * n_slots + bid] = 0.0;
+        part[2LL * n_slots + bid] = tot;
+        part[4LL * n_slots + bid] = 0.0;
+    }
+    if (tid == 1) part[3LL * n_slots + bid] = tot;
+}
+
+// Column table of the fan frames (workgroup = frame), the input the fan
+// kernel's stencils need besides the geometry.
+template <class Src>
+__global__ __launch_bounds__(kBlock) void k_fan_cols(Src src) {
+    const SonarDev f = src.frame((int)blockIdx.x);
+    if (f.cols)
+        for (int j = threadIdx.x; j < f.n_az; j += kBlock) write_fan_column(f, j);
+}
+
+// ---------------------------------------------------------------------------
 // k_reduce_sonar: fixed-order sums of the partials.  Blocks [0, n_rows * 8)
 // produce grad_params[row][col] from the slots of the frames using that row;
 // the following n_mat blocks (small tables) produce grad_refl.
@@ -895,9 +1008,17 @@ static hipError_t launch_bwd(const Src &src, int n_frames, const SonarGrid &g,
                              double *part, double *refl_part, float *grad_params, float *grad_refl,
                              hipStream_t st, SonarReduce *defer) {
     const bool lane_hist = n_mat <= kLaneHistMats;
-    const int n_slots = g.tile_b_blocks + g.ret_blocks;   // partial-sum slots: tiles, then return chunks
+    // partial-sum slots: polar workgroups (tiles, or bin blocks through the
+    // transposed fan operators), then return chunks
+    const int polar_blocks = g.use_fant ? g.fant_blocks : g.tile_b_blocks;
+    const int n_slots = polar_blocks + g.ret_blocks;
     hipError_t e = hipSuccess;
-    if (g.tile_b_blocks > 0) {
+    if (g.use_fant && g.fant_blocks > 0) {
+        OSIM_LAUNCH("k_fant_bwd", (k_fant_bwd<Src>), dim3(g.fant_blocks), dim3(kBlock), 0, st, src, params, part,
+                    n_slots, lane_hist ? (float *)nullptr : grad_refl, n_mat);
+        e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    } else if (!g.use_fant && g.tile_b_blocks > 0) {
         if (g.all_saved)
             OSIM_LAUNCH("k_tile_bwd", (k_tile_bwd<Src, true>), dim3(g.tile_b_blocks), dim3(kBwdThreads),
                         (size_t)g.max_tile_bins_b * 8, st, src, params, part, n_slots,
@@ -916,13 +1037,13 @@ static hipError_t launch_bwd(const Src &src, int n_frames, const SonarGrid &g,
         float *ga = lane_hist ? nullptr : grad_refl;
         OSIM_DISPATCH_R(g.ret_chunk / kBlock,
                         OSIM_LAUNCH("k_ret_bwd", (k_ret_bwd<Src, RR>), dim3(g.ret_blocks), dim3(kBlock), lds, st, src,
-                                           params, refl, n_mat, part, g.tile_b_blocks, n_slots, rp, ga));
+                                           params, refl, n_mat, part, polar_blocks, n_slots, rp, ga));
         e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
-    // small tables are reduced here; the atomic path was zeroed by k_tile_bwd,
-    // unless there was no tile at all (then the reduction writes zeros)
-    const bool refl_blocks = lane_hist || g.tile_b_blocks == 0;
+    // small tables are reduced here; the atomic path was zeroed by the polar
+    // kernel, unless there was none (then the reduction writes zeros)
+    const bool refl_blocks = lane_hist || polar_blocks == 0;
     SonarReduce a;
     a.part = part;
     a.n_slots = n_slots;
@@ -950,6 +1071,16 @@ hipError_t sonar_forward_table(const SonarDev *t, int n, const SonarGrid &g,
                                hipStream_t st, const UwCompanion *uw) {
     return launch_fwd(Table<SonarDev>{t, n}, g, params, refl, n_mat, st, uw);
 }
+hipError_t sonar_fan_stencils_table(const SonarDev *t, int n, const SonarGrid &g, hipStream_t st) {
+    if (n <= 0 || g.fan_blocks == 0) return hipSuccess;
+    const Table<SonarDev> src{t, n};
+    OSIM_LAUNCH("k_fan_cols", k_fan_cols<Table<SonarDev>>, dim3(n), dim3(kBlock), 0, st, src);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    OSIM_LAUNCH("k_fan", (k_fan<Table<SonarDev>, false>), dim3(g.fan_blocks), dim3(kBlock), 0, st, src);
+    return hipGetLastError();
+}
+
 hipError_t sonar_backward_one(const SonarDev &f, const SonarGrid &g, const oceansim_sonar_params *params,
                               int n_rows, const float *refl, int n_mat, double *part, double *refl_part,
                               float *grad_params, float *grad_refl, hipStream_t st) {

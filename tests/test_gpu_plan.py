@@ -163,11 +163,14 @@ def test_plan_replays_track_new_inputs(graph):
             assert_image_close(o["fan"].cpu().numpy(), e["fan"].cpu().numpy(), "eager fan %d" % k, rtol=1e-6)
         for k, (o, e) in enumerate(zip(plan.camera_out, e_cam)):
             assert torch.equal(o["out"], e)
-        # the backward passes reduce in a fixed order over the same workgroups:
-        # plan and plain agree bit for bit
-        assert torch.equal(plan.grad_refl, e_refl)
-        assert torch.equal(plan.grad_sonar_params, e_par)
+        # camera: the same kernels and reduction order, so the same bits; sonar:
+        # the plan gathers through its transposed fan operators (FP64 sums)
+        # where the plain call scatters in fixed point, so the two agree to
+        # rounding (both are checked against the oracle below)
         assert torch.equal(plan.grad_water, e_w)
+        for a, b in ((plan.grad_refl, e_refl), (plan.grad_sonar_params, e_par)):
+            a, b = a.cpu().numpy().astype(np.float64), b.cpu().numpy().astype(np.float64)
+            np.testing.assert_allclose(a, b, rtol=1e-5, atol=1e-6 * max(1.0, float(np.abs(b).max())))
         _check_against_oracle(plan, frames, refl, gpol, gfan, cams, waters, gout, "replay %d" % it)
     plan.close()
 
@@ -259,7 +262,7 @@ def test_autotune_agrees_and_caches(tmp_path, monkeypatch):
     plan = make()
     shape = plan.shape()
     assert shape["fwd_tile_bins"] <= 4096 and shape["chunk"] in (512, 1024, 2048, 4096)
-    assert shape["bwd_tile_bins"] <= 4096
+    assert shape["bwd_block_bins"] == 256
     plan.forward()
     plan.backward()
     torch.cuda.synchronize()
