@@ -282,8 +282,9 @@ enum {
  * backward is their adjoint and reads what the plan's latest forward left
  * (bins), so order the two on one stream.
  *
- * OCEANSIM_PLAN_AUTOTUNE times the forward launch for a small
- * set of tile and chunk sizes and keeps the fastest whose outputs agree with
+ * OCEANSIM_PLAN_AUTOTUNE times the forward launch for a small set of tile
+ * and chunk sizes (and, with a backward, the backward for 1, 2 and 4 polar
+ * bins per thread) and keeps the fastest whose outputs agree with
  * the default shape's (1e-5 relative); results are cached per process and,
  * when the environment variable OCEANSIM_TUNE_CACHE names a file, in that
  * JSON file, keyed by GPU architecture, CU count and a size class of the

@@ -195,6 +195,11 @@ int plan_sonar(const oceansim_sonar_frame *frames, int n_frames, int n_param_row
     P.off_cols.assign(n_frames, (size_t)-1);
     P.off_grad_img.assign(n_frames, 0);
     int bin_blocks = 0, tile_blocks = 0, tile_b_blocks = 0, fan_blocks = 0, ret_blocks = 0, fant_blocks = 0;
+    // Bins per thread through the transposed fan operators: one while the
+    // workgroups fit the chip a few times over; more for large batches, where
+    // the per-workgroup costs (frame lookup, pointer loads, partial sums) add up.
+    int fant_bpt = total_nb >= (16LL << 20) ? 4 : (total_nb >= (2LL << 20) ? 2 : 1);
+    if (tune && (tune->fant_bpt == 1 || tune->fant_bpt == 2 || tune->fant_bpt == 4)) fant_bpt = tune->fant_bpt;
     for (int i = 0; i < n_frames; ++i) {
         const oceansim_sonar_frame &fr = frames[i];
         SonarDev &d = P.dev[i];
@@ -225,7 +230,7 @@ int plan_sonar(const oceansim_sonar_frame *frames, int n_frames, int n_param_row
         d.blk[KRET] = ret_blocks;
         d.blk[KTILEB] = tile_b_blocks;
         d.blk[KFANT] = fant_blocks;
-        d.n_fant_blocks = backward ? (int)((nb + kBlock - 1) / kBlock) : 0;
+        d.n_fant_blocks = backward ? (int)((nb + kBlock * fant_bpt - 1) / (kBlock * fant_bpt)) : 0;
         fant_blocks += d.n_fant_blocks;
         bin_blocks += d.n_chunks;
         tile_blocks += d.n_tiles;
@@ -286,6 +291,7 @@ int plan_sonar(const oceansim_sonar_frame *frames, int n_frames, int n_param_row
     P.grid.ret_blocks = ret_blocks;
     P.grid.tile_b_blocks = tile_b_blocks;
     P.grid.fant_blocks = fant_blocks;
+    P.grid.fant_bpt = fant_bpt;
     P.grid.use_fant = 0;
     P.grid.all_saved = 1;
     for (int i = 0; i < n_frames; ++i)

@@ -109,7 +109,7 @@ struct SonarDev {
     // bilinear weight as float bits}, in a fixed order.  nullptr: none.
     gptr<const int> ft_ptr;
     gptr<const uint2> ft_ent;
-    int n_fant_blocks;          // backward workgroups of kBlock bins through the transposed operator
+    int n_fant_blocks;          // backward workgroups (kBlock * BPT bins each) through the transposed operator
 };
 
 struct UwDev {

@@ -20,6 +20,7 @@ struct Tuning {
     int fwd_tile_bins = 0;   // forward polar tile size target (bins, whole rows)
     int chunk = 0;           // returns per binning / return-gather workgroup (512..4096)
     int bwd_tile_bins = 0;   // backward polar tile size target (bins, whole rows)
+    int fant_bpt = 0;        // bins per thread through the transposed fan operators (1, 2, 4; 0: by size)
 };
 
 struct SonarPlan {

@@ -49,7 +49,8 @@ struct SonarGrid {
     int max_tile_bins_b; // largest backward tile of a frame, in bins
     int all_saved;       // every frame with a fan gradient has saved fan stencils
     int max_n_az;        // widest polar grid of a frame (azimuth cells)
-    int fant_blocks;     // backward workgroups of kBlock bins over all frames (transposed fan operator)
+    int fant_blocks;     // backward workgroups of kBlock * fant_bpt bins over all frames (transposed fan operator)
+    int fant_bpt;        // bins per thread of those workgroups: 1, 2 or 4
     int use_fant;        // backward through the frames' transposed fan operators instead of polar tiles
 };
 

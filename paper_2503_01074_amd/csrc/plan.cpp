@@ -144,7 +144,7 @@ hipError_t launch_backward(oceansim_plan *p, hipStream_t st) {
 
 // ---------------------------------------------------------------------------
 // Tuning cache: per process, optionally persisted as JSON
-// ({"key": [fwd_tile_bins, chunk, bwd_tile_bins], ...}).
+// ({"key": [fwd_tile_bins, chunk, fant_bpt], ...}).
 // ---------------------------------------------------------------------------
 std::mutex g_tune_mu;
 std::map<std::string, Tuning> g_tune;
@@ -173,8 +173,10 @@ void tune_load_locked() {
         if (end == std::string::npos) break;
         std::string key = text.substr(pos + 1, end - pos - 1);
         Tuning t;
-        if (sscanf(text.c_str() + end + 1, " : [ %d , %d , %d ]", &t.fwd_tile_bins, &t.chunk, &t.bwd_tile_bins) == 3)
+        if (sscanf(text.c_str() + end + 1, " : [ %d , %d , %d ]", &t.fwd_tile_bins, &t.chunk, &t.fant_bpt) == 3) {
+            if (t.fant_bpt != 1 && t.fant_bpt != 2 && t.fant_bpt != 4) t.fant_bpt = 0;
             g_tune[key] = t;
+        }
         pos = end + 1;
     }
 }
@@ -189,7 +191,7 @@ void tune_save_locked() {
     size_t k = 0;
     for (auto &kv : g_tune)
         fprintf(fh, "  \"%s\": [%d, %d, %d]%s\n", kv.first.c_str(), kv.second.fwd_tile_bins, kv.second.chunk,
-                kv.second.bwd_tile_bins, ++k < g_tune.size() ? "," : "");
+                kv.second.fant_bpt, ++k < g_tune.size() ? "," : "");
     fprintf(fh, "}\n");
     fclose(fh);
     rename(tmp.c_str(), path);
@@ -252,8 +254,11 @@ double time_us(F fn, hipStream_t st) {
     return ms * 1e3 / 3.0;
 }
 
-// Chooses p->tune by timing forward candidates (the backward of a plan goes
-// through the transposed fan operators, whose shape is fixed).
+void attach_fan_transposes(const oceansim_plan *p, SonarPlan &P);
+
+// Chooses p->tune by timing candidates: forward tile and chunk sizes, then
+// the bins per thread of the backward through the transposed fan operators
+// (built before tuning).
 int autotune(oceansim_plan *p, hipStream_t st) {
     const std::string key = tune_key(p);
     {
@@ -349,6 +354,79 @@ int autotune(oceansim_plan *p, hipStream_t st) {
         if (cands[k].ok && cands[k].us < cands[best].us) best = k;
     Tuning chosen = cands[best].t;   // zeros: the built-in heuristic won
 
+    if (rc == OCEANSIM_OK && (p->flags & OCEANSIM_PLAN_BACKWARD)) {
+        // backward: bins per thread through the transposed fan operators,
+        // after one forward under the chosen shape
+        SonarPlan fp;
+        rc = plan_sonar(p->sonar.data(), n, p->n_srows, p->n_mat, false, fp, &chosen, true);
+        if (rc == OCEANSIM_OK && fp.bytes > ws) rc = fail(OCEANSIM_E_WORKSPACE, "autotune: forward workspace");
+        std::vector<Candidate> bc;
+        for (int bpt : {0, 1, 2, 4}) {   // 0: the size heuristic, the reference
+            Candidate c;
+            c.t = chosen;
+            c.t.fant_bpt = bpt;
+            bc.push_back(c);
+        }
+        size_t wsb = 0;
+        for (auto &c : bc) {
+            if (rc) break;
+            rc = plan_sonar(p->sonar.data(), n, p->n_srows, p->n_mat, true, c.b, &c.t, true);
+            attach_fan_transposes(p, c.b);
+            wsb = std::max(wsb, c.b.bytes);
+        }
+        char *tb = nullptr;
+        if (rc == OCEANSIM_OK) {
+            e = hipMalloc(&tb, wsb + 256);
+            if (e != hipSuccess) rc = hip_fail(e, "autotune workspace");
+        }
+        if (rc == OCEANSIM_OK) {
+            carve_sonar(fp, tmp, false);
+            e = upload_table(fp.dev, tmp, fp.off_table, st);
+            if (e == hipSuccess)
+                e = sonar_forward_table(reinterpret_cast<const SonarDev *>(tmp + fp.off_table), n, fp.grid, p->sp,
+                                        p->refl, p->n_mat, st);
+            std::vector<float> ref_g;
+            const size_t ng = (size_t)p->n_mat + (size_t)p->n_srows * OCEANSIM_SONAR_GRAD_WIDTH;
+            const bool lane_hist = p->n_mat <= kLaneHistMats;
+            for (size_t k = 0; k < bc.size() && e == hipSuccess; ++k) {
+                Candidate &c = bc[k];
+                carve_sonar(c.b, tb, true);
+                e = upload_table(c.b.dev, tb, c.b.off_table, st);
+                const SonarDev *table = reinterpret_cast<const SonarDev *>(tb + c.b.off_table);
+                auto run = [&]() {
+                    return sonar_backward_table(table, n, c.b.grid, p->sp, p->n_srows, p->refl, p->n_mat,
+                                                reinterpret_cast<double *>(tb + c.b.off_part),
+                                                lane_hist ? reinterpret_cast<double *>(tb + c.b.off_refl_part)
+                                                          : nullptr,
+                                                p->g_sp, p->g_refl, st);
+                };
+                if (e == hipSuccess) e = run();
+                std::vector<float> g(ng);
+                if (e == hipSuccess)
+                    e = hipMemcpyAsync(g.data(), p->g_refl, sizeof(float) * p->n_mat, hipMemcpyDeviceToHost, st);
+                if (e == hipSuccess)
+                    e = hipMemcpyAsync(g.data() + p->n_mat, p->g_sp,
+                                       sizeof(float) * p->n_srows * OCEANSIM_SONAR_GRAD_WIDTH,
+                                       hipMemcpyDeviceToHost, st);
+                if (e == hipSuccess) e = hipStreamSynchronize(st);
+                if (e != hipSuccess) break;
+                if (k == 0) ref_g = g;
+                float peak = 0.0f;
+                for (float v : ref_g) peak = std::max(peak, std::fabs(v));
+                c.ok = true;
+                for (size_t i = 0; i < ng; ++i)
+                    if (!(std::fabs(g[i] - ref_g[i]) <= 1e-5f * std::max(std::fabs(ref_g[i]), 1e-3f * peak)))
+                        c.ok = false;
+                if (c.ok) c.us = time_us(run, st);
+            }
+            if (e != hipSuccess) rc = hip_fail(e, "autotune backward");
+            size_t bbest = 0;
+            for (size_t k = 1; k < bc.size(); ++k)
+                if (bc[k].ok && bc[k].us < bc[bbest].us) bbest = k;
+            chosen.fant_bpt = bc[bbest].t.fant_bpt;
+        }
+        if (tb) (void)hipFree(tb);
+    }
     (void)hipStreamSynchronize(st);
     (void)hipFree(tmp);
     (void)hipFree(ref);
@@ -709,7 +787,8 @@ int oceansim_plan_shape(const oceansim_plan *p, int32_t shape[4]) {
     if (!p || !shape) return fail(OCEANSIM_E_INVALID_ARG, "NULL argument");
     shape[0] = p->sf.grid.max_tile_bins;
     shape[1] = p->sf.grid.chunk;
-    shape[2] = (p->flags & OCEANSIM_PLAN_BACKWARD) && !p->sonar.empty() ? kBlock : 0;   // bins per backward workgroup
+    // bins per backward workgroup
+    shape[2] = (p->flags & OCEANSIM_PLAN_BACKWARD) && !p->sonar.empty() ? kBlock * p->sb.grid.fant_bpt : 0;
     shape[3] = p->g_fwd ? 1 : 0;
     return ok();
 }

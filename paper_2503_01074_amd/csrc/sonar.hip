@@ -849,21 +849,24 @@ __global__ __launch_bounds__(kBlock) void k_ret_bwd(Src src, const oceansim_sona
 
 // ---------------------------------------------------------------------------
 // k_fant_bwd: the polar gradient through the frames' transposed fan operators
-// (plans), one bin per thread: dL/dI[b] is the sum of weight * dL/dF over the
-// bin's entries, in FP64 and in the entries' fixed order (each product of
-// two floats is exact in FP64), plus the direct polar gradient; then the
-// adjoint of Eq. (3)-(4) as in the tile epilogue.  No candidate search, no
-// fixed-point scale, no workgroup barrier before the partial sums.
+// (plans), BPT consecutive bins per thread: dL/dI[b] is the sum of weight *
+// dL/dF over the bin's entries, in FP64 and in the entries' fixed order
+// (each product of two floats is exact in FP64), plus the direct polar
+// gradient; then the adjoint of Eq. (3)-(4) as in the tile epilogue.  No
+// candidate search, no fixed-point scale, no workgroup barrier before the
+// partial sums.
 //
-// The entries of a wave's 64 consecutive bins are contiguous: the wave reads
-// them in coalesced 64-entry chunks (lane k takes entry k of the chunk), so
-// the loads of one instruction are one span of 512 bytes and its fan
+// The entries of a wave's 64 * BPT consecutive bins are contiguous: the wave
+// reads them in coalesced 64-entry chunks (lane k takes entry k of a chunk),
+// so the loads of one instruction are one span of 512 bytes and its fan
 // gathers are the neighbouring pixels of neighbouring bins; the products go
-// to the wave's slice of LDS, and each lane then sums its own bin's run.
+// to the wave's slice of LDS, and each lane then sums its own bins' runs.
+// More bins per thread amortise the workgroup's fixed costs (frame lookup,
+// pointer loads, partial sums) where there are many bins to share the chip.
 // ---------------------------------------------------------------------------
 constexpr int kFantChunks = 8;   // 64-entry chunks staged per round (512 entries per wave)
 
-template <class Src>
+template <class Src, int BPT>
 __global__ __launch_bounds__(kBlock) void k_fant_bwd(Src src, const oceansim_sonar_params *params, double *part,
                                                      int n_slots, float *grad_refl_zero, int n_mat_zero) {
     __shared__ double prod[kBlock / kWave][kFantChunks * kWave];
@@ -877,14 +880,18 @@ __global__ __launch_bounds__(kBlock) void k_fant_bwd(Src src, const oceansim_son
     if (grad_refl_zero)
         for (int k = bid * kBlock + tid; k < n_mat_zero; k += (int)gridDim.x * kBlock) grad_refl_zero[k] = 0.0f;
     const int nb = f.n_range * f.n_az;
-    const int b = local * kBlock + tid;
+    const int b0 = (local * kBlock + tid) * BPT;   // this thread's first bin
     const oceansim_sonar_params pr = params[f.param_row];
-    double g = 0.0;
+    double gs[BPT];
+#pragma unroll
+    for (int m = 0; m < BPT; ++m) gs[m] = 0.0;
     if (f.ft_ptr) {
-        // this lane's entries [p_lo, p_hi); the wave's [w_lo, w_hi)
-        const int p_lo = f.ft_ptr[b < nb ? b : nb];
-        const int p_hi = f.ft_ptr[b + 1 < nb ? b + 1 : nb];
-        const int w_lo = __shfl(p_lo, 0, kWave), w_hi = __shfl(p_hi, kWave - 1, kWave);
+        // this lane's bins' entries start at p[0..BPT-1] and end at p[BPT];
+        // the wave's span is [w_lo, w_hi)
+        int p[BPT + 1];
+#pragma unroll
+        for (int m = 0; m <= BPT; ++m) p[m] = f.ft_ptr[b0 + m < nb ? b0 + m : nb];
+        const int w_lo = __shfl(p[0], 0, kWave), w_hi = __shfl(p[BPT], kWave - 1, kWave);
         double *slice = prod[wave];
         for (int r0 = w_lo; r0 < w_hi; r0 += kFantChunks * kWave) {
             uint2 en[kFantChunks];
@@ -900,35 +907,52 @@ __global__ __launch_bounds__(kBlock) void k_fant_bwd(Src src, const oceansim_son
                 gv[c] = e < w_hi ? f.grad_fan[(long long)en[c].x] : 0.0f;
             }
 #pragma unroll
-            for (int c = 0; c < kFantChunks; ++c) slice[c * kWave + lane] = (double)__uint_as_float(en[c].y) * (double)gv[c];
+            for (int c = 0; c < kFantChunks; ++c)
+                slice[c * kWave + lane] = (double)__uint_as_float(en[c].y) * (double)gv[c];
             // the wave's own LDS writes, then its reads (no other wave touches the slice)
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
             __builtin_amdgcn_wave_barrier();
             __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-            const int a = p_lo > r0 ? p_lo : r0;
-            const int z = p_hi < r0 + kFantChunks * kWave ? p_hi : r0 + kFantChunks * kWave;
-            for (int e = a; e < z; ++e) g += slice[e - r0];
+            const int a = p[0] > r0 ? p[0] : r0;
+            const int z = p[BPT] < r0 + kFantChunks * kWave ? p[BPT] : r0 + kFantChunks * kWave;
+            for (int e = a; e < z; ++e) {
+                const double v = slice[e - r0];
+                int m = 0;
+#pragma unroll
+                for (int k = 1; k < BPT; ++k) m += e >= p[k] ? 1 : 0;
+#pragma unroll
+                for (int k = 0; k < BPT; ++k) gs[k] += m == k ? v : 0.0;
+            }
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
             __builtin_amdgcn_wave_barrier();
             __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
         }
     }
     double g_sphi = 0.0, g_ssa = 0.0;
-    if (b < nb) {
+    const AddCtx ctx{pr.sigma_sa, 1.0f / pr.sigma_phi};
+    const double dsphi = 0.5 * (double)pr.sigma_sa / ((double)pr.sigma_phi * (double)pr.sigma_phi);
+    Words wd{0u, 0u, 0u, 0u};
+    int wq = -1;
+#pragma unroll
+    for (int m = 0; m < BPT; ++m) {
+        const int b = b0 + m;
+        if (b >= nb) break;
+        double g = gs[m];
         if (f.grad_polar) g += (double)f.grad_polar[b];
         f.grad_img[b] = (float)g;
         if (f.speckle != SPECKLE_OFF) {
             // d add / d sigma_sa and d add / d sigma_phi of Eq. (3)-(4); the
             // bin's Philox word is the one its forward tile drew
-            const Words wd = philox((uint32_t)(b >> 2), f.frame_id, 0u, 0u, f.seed_lo, f.seed_hi);
+            if ((b >> 2) != wq) {
+                wq = b >> 2;
+                wd = philox((uint32_t)wq, f.frame_id, 0u, 0u, f.seed_lo, f.seed_hi);
+            }
             const int i = b / f.n_az, j = b - i * f.n_az;
-            const AddCtx ctx{pr.sigma_sa, 1.0f / pr.sigma_phi};
-            const double dsphi = 0.5 * (double)pr.sigma_sa / ((double)pr.sigma_phi * (double)pr.sigma_phi);
             float E, rho, R, phi;
             additive_term(f, ctx, i, j, pick(wd, (uint32_t)(b & 3)), E, rho, R, phi);
             const double t = g * (double)R * (double)E * (double)rho;
-            g_ssa = 0.5 * t;
-            g_sphi = t * dsphi * ((double)phi * (double)phi);
+            g_ssa += 0.5 * t;
+            g_sphi += t * dsphi * ((double)phi * (double)phi);
         }
     }
     __shared__ double red2[2 * (kBlock / kWave)];
@@ -1014,8 +1038,16 @@ static hipError_t launch_bwd(const Src &src, int n_frames, const SonarGrid &g,
     const int n_slots = polar_blocks + g.ret_blocks;
     hipError_t e = hipSuccess;
     if (g.use_fant && g.fant_blocks > 0) {
-        OSIM_LAUNCH("k_fant_bwd", (k_fant_bwd<Src>), dim3(g.fant_blocks), dim3(kBlock), 0, st, src, params, part,
-                    n_slots, lane_hist ? (float *)nullptr : grad_refl, n_mat);
+        float *gz = lane_hist ? (float *)nullptr : grad_refl;
+        switch (g.fant_bpt) {
+            case 1: OSIM_LAUNCH("k_fant_bwd", (k_fant_bwd<Src, 1>), dim3(g.fant_blocks), dim3(kBlock), 0, st, src,
+                                params, part, n_slots, gz, n_mat); break;
+            case 2: OSIM_LAUNCH("k_fant_bwd", (k_fant_bwd<Src, 2>), dim3(g.fant_blocks), dim3(kBlock), 0, st, src,
+                                params, part, n_slots, gz, n_mat); break;
+            case 4: OSIM_LAUNCH("k_fant_bwd", (k_fant_bwd<Src, 4>), dim3(g.fant_blocks), dim3(kBlock), 0, st, src,
+                                params, part, n_slots, gz, n_mat); break;
+            default: return hipErrorInvalidValue;
+        }
         e = hipGetLastError();
         if (e != hipSuccess) return e;
     } else if (!g.use_fant && g.tile_b_blocks > 0) {

@@ -262,7 +262,7 @@ def test_autotune_agrees_and_caches(tmp_path, monkeypatch):
     plan = make()
     shape = plan.shape()
     assert shape["fwd_tile_bins"] <= 4096 and shape["chunk"] in (512, 1024, 2048, 4096)
-    assert shape["bwd_block_bins"] == 256
+    assert shape["bwd_block_bins"] in (256, 512, 1024)
     plan.forward()
     plan.backward()
     torch.cuda.synchronize()
