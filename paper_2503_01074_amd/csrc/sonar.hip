@@ -876,36 +876,75 @@ __global__ __launch_bounds__(kBlock) void k_fant_bwd(Src src, const oceansim_son
     const SonarDev f = src.frame(fi);
     const int tid = threadIdx.x;
     const int lane = tid & (kWave - 1), wave = tid / kWave;
+    const int nb = f.n_range * f.n_az;
+    const int b0 = (local * kBlock + tid) * BPT;   // this thread's first bin
+    // Loads first, without branches (indices clamped), so that they are in
+    // flight together while the speckle factors are computed: the parameter
+    // row (before any store, so it may come through the scalar cache), this
+    // lane's bins' operator pointers and the direct polar gradient.
+    const oceansim_sonar_params pr = params[f.param_row];
+    int p[BPT + 1];   // this lane's bins' entries start at p[0..BPT-1] and end at p[BPT]
+#pragma unroll
+    for (int m = 0; m <= BPT; ++m) p[m] = f.ft_ptr ? f.ft_ptr[b0 + m < nb ? b0 + m : nb] : 0;
+    // (without a polar gradient the load reads this frame's own gradient
+    // buffer, a valid address, and the value is discarded: a select, not a
+    // branch that would wait for the load)
+    float gpol[BPT];
+    {
+        const bool has = f.grad_polar != nullptr;
+        const gptr<const float> src_pol = has ? f.grad_polar : (gptr<const float>)f.grad_img;
+#pragma unroll
+        for (int m = 0; m < BPT; ++m) {
+            const float v = src_pol[b0 + m < nb ? b0 + m : nb - 1];
+            gpol[m] = has ? v : 0.0f;
+        }
+    }
     // the atomic reflectivity path (many materials) accumulates into a zeroed table
     if (grad_refl_zero)
         for (int k = bid * kBlock + tid; k < n_mat_zero; k += (int)gridDim.x * kBlock) grad_refl_zero[k] = 0.0f;
-    const int nb = f.n_range * f.n_az;
-    const int b0 = (local * kBlock + tid) * BPT;   // this thread's first bin
-    const oceansim_sonar_params pr = params[f.param_row];
+    // per bin, the factors of the adjoint of Eq. (3)-(4): R E rho and phi^2
+    float fac[BPT], phi2[BPT];
+    {
+        const AddCtx ctx{pr.sigma_sa, 1.0f / pr.sigma_phi};
+        Words wd{0u, 0u, 0u, 0u};
+        int wq = -1;
+#pragma unroll
+        for (int m = 0; m < BPT; ++m) {
+            const int b = b0 + m;
+            fac[m] = phi2[m] = 0.0f;
+            if (f.speckle != SPECKLE_OFF && b < nb) {
+                // the bin's Philox word is the one its forward tile drew
+                if ((b >> 2) != wq) {
+                    wq = b >> 2;
+                    wd = philox((uint32_t)wq, f.frame_id, 0u, 0u, f.seed_lo, f.seed_hi);
+                }
+                const int i = b / f.n_az, j = b - i * f.n_az;
+                float E, rho, R, phi;
+                additive_term(f, ctx, i, j, pick(wd, (uint32_t)(b & 3)), E, rho, R, phi);
+                fac[m] = R * E * rho;
+                phi2[m] = phi * phi;
+            }
+        }
+    }
     double gs[BPT];
 #pragma unroll
     for (int m = 0; m < BPT; ++m) gs[m] = 0.0;
     if (f.ft_ptr) {
-        // this lane's bins' entries start at p[0..BPT-1] and end at p[BPT];
-        // the wave's span is [w_lo, w_hi)
-        int p[BPT + 1];
-#pragma unroll
-        for (int m = 0; m <= BPT; ++m) p[m] = f.ft_ptr[b0 + m < nb ? b0 + m : nb];
         const int w_lo = __shfl(p[0], 0, kWave), w_hi = __shfl(p[BPT], kWave - 1, kWave);
         double *slice = prod[wave];
         for (int r0 = w_lo; r0 < w_hi; r0 += kFantChunks * kWave) {
+            // Every lane loads (past the end it re-reads the wave's last entry,
+            // whose product no bin sums): no branch in the unrolled loads, so
+            // all the chunk's loads, then all its gathers, are in flight together.
             uint2 en[kFantChunks];
             float gv[kFantChunks];
 #pragma unroll
             for (int c = 0; c < kFantChunks; ++c) {
                 const int e = r0 + c * kWave + lane;
-                en[c] = e < w_hi ? gload(f.ft_ent + e) : make_uint2(0u, 0u);
+                en[c] = gload(f.ft_ent + (e < w_hi ? e : w_hi - 1));
             }
 #pragma unroll
-            for (int c = 0; c < kFantChunks; ++c) {
-                const int e = r0 + c * kWave + lane;
-                gv[c] = e < w_hi ? f.grad_fan[(long long)en[c].x] : 0.0f;
-            }
+            for (int c = 0; c < kFantChunks; ++c) gv[c] = f.grad_fan[(long long)en[c].x];
 #pragma unroll
             for (int c = 0; c < kFantChunks; ++c)
                 slice[c * kWave + lane] = (double)__uint_as_float(en[c].y) * (double)gv[c];
@@ -929,31 +968,18 @@ __global__ __launch_bounds__(kBlock) void k_fant_bwd(Src src, const oceansim_son
         }
     }
     double g_sphi = 0.0, g_ssa = 0.0;
-    const AddCtx ctx{pr.sigma_sa, 1.0f / pr.sigma_phi};
     const double dsphi = 0.5 * (double)pr.sigma_sa / ((double)pr.sigma_phi * (double)pr.sigma_phi);
-    Words wd{0u, 0u, 0u, 0u};
-    int wq = -1;
 #pragma unroll
     for (int m = 0; m < BPT; ++m) {
         const int b = b0 + m;
         if (b >= nb) break;
-        double g = gs[m];
-        if (f.grad_polar) g += (double)f.grad_polar[b];
+        const double g = gs[m] + (double)gpol[m];
         f.grad_img[b] = (float)g;
-        if (f.speckle != SPECKLE_OFF) {
-            // d add / d sigma_sa and d add / d sigma_phi of Eq. (3)-(4); the
-            // bin's Philox word is the one its forward tile drew
-            if ((b >> 2) != wq) {
-                wq = b >> 2;
-                wd = philox((uint32_t)wq, f.frame_id, 0u, 0u, f.seed_lo, f.seed_hi);
-            }
-            const int i = b / f.n_az, j = b - i * f.n_az;
-            float E, rho, R, phi;
-            additive_term(f, ctx, i, j, pick(wd, (uint32_t)(b & 3)), E, rho, R, phi);
-            const double t = g * (double)R * (double)E * (double)rho;
-            g_ssa += 0.5 * t;
-            g_sphi += t * dsphi * ((double)phi * (double)phi);
-        }
+        // d add / d sigma_sa and d add / d sigma_phi of Eq. (3)-(4) (zero
+        // factors without speckle)
+        const double t = g * (double)fac[m];
+        g_ssa += 0.5 * t;
+        g_sphi += t * dsphi * (double)phi2[m];
     }
     __shared__ double red2[2 * (kBlock / kWave)];
     const double sums[2] = {g_sphi, g_ssa};
