@@ -223,6 +223,8 @@ class RealTimeStep:
         return {"k_bin": 28 * self.n_returns, "k_tile": 4 * nb, "k_fan": 4 * npx_fan,
                 "k_tile_bwd": 4 * npx_fan + 4 * nb, "k_fant_bwd": 4 * npx_fan + 4 * nb,
                 "k_ret_bwd": 28 * self.n_returns,
+                # the plan's return-gather launch also carries the camera backward
+                "k_ret_uw_bwd": 28 * self.n_returns + 44 * self.npix,
                 "k_uw": 28 * self.npix, "k_uw_bwd": 44 * self.npix,
                 # the plan's forward polar-tile launch also carries the camera frame
                 "k_tile_uw": 4 * nb + 28 * self.npix}

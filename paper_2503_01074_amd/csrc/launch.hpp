@@ -66,6 +66,18 @@ struct UwCompanion {
     const oceansim_water_params *params = nullptr;
 };
 
+// Camera frames whose backward rides along in the return-gather launch of a
+// plan's sonar backward: device frame table, workgroups (kBlock threads
+// each), water parameters and the partial-sum buffers of the camera backward.
+struct UwBwdCompanion {
+    const UwDev *table = nullptr;
+    int n = 0;
+    int blocks = 0;
+    const oceansim_water_params *params = nullptr;
+    double *part = nullptr;
+    int *part_row = nullptr;
+};
+
 hipError_t sonar_forward_one(const SonarDev &f, const SonarGrid &g, const oceansim_sonar_params *params,
                              const float *refl, int n_mat, hipStream_t st);
 hipError_t sonar_forward_table(const SonarDev *t, int n, const SonarGrid &g,
@@ -101,14 +113,17 @@ struct RowsReduce {
 // workgroups]) and refl_part (column-major [n_mat][return workgroups], small
 // tables), reduced in a fixed order into grad_params [n_rows][8] and
 // grad_refl [n_mat].  With `defer`, the reduction is not launched: its
-// arguments are returned there for a later reduce_pair.
+// arguments are returned there for a later reduce_pair.  With `uwb`, the
+// camera backward of those frames is launched too (in the return-gather
+// launch when its LDS allows, else right after it).
 hipError_t sonar_backward_one(const SonarDev &f, const SonarGrid &g, const oceansim_sonar_params *params,
                               int n_rows, const float *refl, int n_mat, double *part, double *refl_part,
                               float *grad_params, float *grad_refl, hipStream_t st);
 hipError_t sonar_backward_table(const SonarDev *t, int n, const SonarGrid &g,
                                 const oceansim_sonar_params *params, int n_rows, const float *refl,
                                 int n_mat, double *part, double *refl_part, float *grad_params,
-                                float *grad_refl, hipStream_t st, SonarReduce *defer = nullptr);
+                                float *grad_refl, hipStream_t st, SonarReduce *defer = nullptr,
+                                const UwBwdCompanion *uwb = nullptr);
 
 // Camera pixels per thread: one float4 group forward, two backward (the
 // per-workgroup parameter partial sums amortised over 8 pixels).

@@ -111,26 +111,34 @@ hipError_t launch_forward(oceansim_plan *p, hipStream_t st) {
     return camera_forward(p, st);
 }
 
-// Sonar backward, then camera backward; with both, their two fixed-order
-// reductions run as one launch after the camera kernel.
+// Sonar backward, then camera backward; with both, the camera workgroups run
+// in the sonar return-gather launch and the two fixed-order reductions are
+// one launch.
 hipError_t launch_backward(oceansim_plan *p, hipStream_t st) {
     if (p->sonar.empty()) return camera_backward(p, st);
     const bool lane_hist = p->n_mat <= kLaneHistMats;
     const bool pair = !p->camera.empty() && p->ub.blocks > 0;
     SonarReduce sr;
+    double *part = pair ? reinterpret_cast<double *>(p->ws_ub + p->ub.off_part) : nullptr;
+    int *row = pair ? reinterpret_cast<int *>(p->ws_ub + p->ub.off_part_row) : nullptr;
+    // the camera backward rides along in the sonar return-gather launch
+    UwBwdCompanion uwb;
+    if (pair) {
+        uwb.table = reinterpret_cast<const UwDev *>(p->ws_ub + p->ub.off_table);
+        uwb.n = (int)p->camera.size();
+        uwb.blocks = p->ub.blocks;
+        uwb.params = p->wp;
+        uwb.part = part;
+        uwb.part_row = row;
+    }
     hipError_t e = sonar_backward_table(reinterpret_cast<const SonarDev *>(p->ws_sb + p->sb.off_table),
                                         (int)p->sonar.size(), p->sb.grid, p->sp, p->n_srows, p->refl, p->n_mat,
                                         reinterpret_cast<double *>(p->ws_sb + p->sb.off_part),
                                         lane_hist ? reinterpret_cast<double *>(p->ws_sb + p->sb.off_refl_part)
                                                   : nullptr,
-                                        p->g_sp, p->g_refl, st, pair ? &sr : nullptr);
+                                        p->g_sp, p->g_refl, st, pair ? &sr : nullptr, pair ? &uwb : nullptr);
     if (e != hipSuccess) return e;
     if (!pair) return camera_backward(p, st);
-    double *part = reinterpret_cast<double *>(p->ws_ub + p->ub.off_part);
-    int *row = reinterpret_cast<int *>(p->ws_ub + p->ub.off_part_row);
-    e = uw_backward_table(reinterpret_cast<const UwDev *>(p->ws_ub + p->ub.off_table), (int)p->camera.size(),
-                          p->ub.blocks, p->wp, part, row, st);
-    if (e != hipSuccess) return e;
     RowsReduce rr;
     rr.part = part;
     rr.row = row;

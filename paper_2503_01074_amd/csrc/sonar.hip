@@ -768,17 +768,19 @@ __global__ __launch_bounds__(kBwdThreads, SAVED ? 6 : 4) void k_tile_bwd(Src src
 // ---------------------------------------------------------------------------
 // k_ret_bwd
 // ---------------------------------------------------------------------------
+// Return chunk `bid` of the n_blocks chunks of the launch.
 template <class Src, int R>
-__global__ __launch_bounds__(kBlock) void k_ret_bwd(Src src, const oceansim_sonar_params *params,
-                                                    const float *refl, int n_mat, double *part, int slot_base,
-                                                    int n_slots, double *refl_part, float *grad_refl_atomic) {
+__device__ __forceinline__ void ret_bwd_block(const Src &src, const oceansim_sonar_params *params,
+                                              const float *refl, int n_mat, double *part, int slot_base,
+                                              int n_slots, double *refl_part, float *grad_refl_atomic, int bid,
+                                              int n_blocks) {
     extern __shared__ int4 lds_raw[];
     // thread-private reflectivity columns [n_mat][kBlock] (small tables); the
     // same memory later serves the workgroup reductions
     float *hist = reinterpret_cast<float *>(lds_raw);
     double *red3 = reinterpret_cast<double *>(lds_raw);
     int local;
-    const int fi = src.locate(blockIdx.x, KRET, local);
+    const int fi = src.locate(bid, KRET, local);
     const SonarDev f = src.frame(fi);
     const int tid = threadIdx.x;
     const bool lane_hist = refl_part != nullptr;
@@ -829,14 +831,14 @@ __global__ __launch_bounds__(kBlock) void k_ret_bwd(Src src, const oceansim_sona
 #pragma unroll
             for (int q = 1; q < kBlock / kWave; ++q) s += (double)h[lane + q * kWave];
             s = wave_sum(s);
-            if (lane == 0) refl_part[(long long)mm * gridDim.x + blockIdx.x] = s;
+            if (lane == 0) refl_part[(long long)mm * n_blocks + bid] = s;
         }
     }
     __syncthreads();
     const double sums[3] = {g_alpha, g_gain, g_ssm};
     const double tot = block_sum_n<3>(sums, red3);   // thread 0: alpha, 1: gain, 2: sigma_sm
     // partial sums column-major: part[c * n_slots + slot]
-    const long long slot = slot_base + blockIdx.x;
+    const long long slot = slot_base + bid;
     if (tid == 0) {
         reinterpret_cast<int *>(part + 5LL * n_slots)[slot] = f.param_row;
         part[0LL * n_slots + slot] = tot;
@@ -845,6 +847,32 @@ __global__ __launch_bounds__(kBlock) void k_ret_bwd(Src src, const oceansim_sona
     }
     if (tid == 1) part[1LL * n_slots + slot] = tot;
     if (tid == 2) part[4LL * n_slots + slot] = tot;
+}
+
+template <class Src, int R>
+__global__ __launch_bounds__(kBlock) void k_ret_bwd(Src src, const oceansim_sonar_params *params,
+                                                    const float *refl, int n_mat, double *part, int slot_base,
+                                                    int n_slots, double *refl_part, float *grad_refl_atomic) {
+    ret_bwd_block<Src, R>(src, params, refl, n_mat, part, slot_base, n_slots, refl_part, grad_refl_atomic,
+                          blockIdx.x, gridDim.x);
+}
+
+// The return chunks of the sonar frames and, in the same launch, the camera
+// backward of a plan (workgroups n_ret_blocks and up): the camera's HBM
+// stream runs beside the latency-bound gathers of the returns.
+template <class Src, int R>
+__global__ __launch_bounds__(kBlock) void k_ret_uw_bwd(Src src, const oceansim_sonar_params *params,
+                                                       const float *refl, int n_mat, double *part, int slot_base,
+                                                       int n_slots, double *refl_part, float *grad_refl_atomic,
+                                                       int n_ret_blocks, UwBwdCompanion uw) {
+    if ((int)blockIdx.x < n_ret_blocks) {
+        ret_bwd_block<Src, R>(src, params, refl, n_mat, part, slot_base, n_slots, refl_part, grad_refl_atomic,
+                              blockIdx.x, n_ret_blocks);
+    } else {
+        __shared__ double red9[9 * (kBlock / kWave)];
+        uw_bwd_block<Table<UwDev>, kBlock>(Table<UwDev>{uw.table, uw.n}, uw.params, uw.part, uw.part_row,
+                                           blockIdx.x - n_ret_blocks, uw.blocks, red9);
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -864,7 +892,8 @@ __global__ __launch_bounds__(kBlock) void k_ret_bwd(Src src, const oceansim_sona
 // More bins per thread amortise the workgroup's fixed costs (frame lookup,
 // pointer loads, partial sums) where there are many bins to share the chip.
 // ---------------------------------------------------------------------------
-constexpr int kFantChunks = 8;   // 64-entry chunks staged per round (512 entries per wave)
+constexpr int kFantChunks = 8;
+constexpr size_t kFuseLdsBytes = 16384;   // LDS of a return-gather workgroup that camera workgroups may share   // 64-entry chunks staged per round (512 entries per wave)
 
 template <class Src, int BPT>
 __global__ __launch_bounds__(kBlock) void k_fant_bwd(Src src, const oceansim_sonar_params *params, double *part,
@@ -1056,7 +1085,7 @@ template <class Src>
 static hipError_t launch_bwd(const Src &src, int n_frames, const SonarGrid &g,
                              const oceansim_sonar_params *params, int n_rows, const float *refl, int n_mat,
                              double *part, double *refl_part, float *grad_params, float *grad_refl,
-                             hipStream_t st, SonarReduce *defer) {
+                             hipStream_t st, SonarReduce *defer, const UwBwdCompanion *uwb) {
     const bool lane_hist = n_mat <= kLaneHistMats;
     // partial-sum slots: polar workgroups (tiles, or bin blocks through the
     // transposed fan operators), then return chunks
@@ -1088,16 +1117,33 @@ static hipError_t launch_bwd(const Src &src, int n_frames, const SonarGrid &g,
         e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
-    if (g.ret_blocks > 0) {
-        size_t lds = lane_hist ? (size_t)n_mat * kBlock * 4 : 0;
-        if (lds < (size_t)3 * (kBlock / kWave) * 8) lds = (size_t)3 * (kBlock / kWave) * 8;
-        double *rp = lane_hist ? refl_part : nullptr;
-        float *ga = lane_hist ? nullptr : grad_refl;
+    const int uw_blocks = uwb ? uwb->blocks : 0;
+    size_t lds = lane_hist ? (size_t)n_mat * kBlock * 4 : 0;
+    if (lds < (size_t)3 * (kBlock / kWave) * 8) lds = (size_t)3 * (kBlock / kWave) * 8;
+    // the camera workgroups would reserve the same LDS: fused only while it
+    // still leaves room for eight of them per CU
+    const bool fuse = uw_blocks > 0 && lds <= kFuseLdsBytes;
+    double *rp = lane_hist ? refl_part : nullptr;
+    float *ga = lane_hist ? nullptr : grad_refl;
+    if (fuse) {
         OSIM_DISPATCH_R(g.ret_chunk / kBlock,
-                        OSIM_LAUNCH("k_ret_bwd", (k_ret_bwd<Src, RR>), dim3(g.ret_blocks), dim3(kBlock), lds, st, src,
-                                           params, refl, n_mat, part, polar_blocks, n_slots, rp, ga));
+                        OSIM_LAUNCH("k_ret_uw_bwd", (k_ret_uw_bwd<Src, RR>), dim3(g.ret_blocks + uw_blocks),
+                                    dim3(kBlock), lds, st, src, params, refl, n_mat, part, polar_blocks, n_slots, rp,
+                                    ga, g.ret_blocks, *uwb));
         e = hipGetLastError();
         if (e != hipSuccess) return e;
+    } else {
+        if (g.ret_blocks > 0) {
+            OSIM_DISPATCH_R(g.ret_chunk / kBlock,
+                            OSIM_LAUNCH("k_ret_bwd", (k_ret_bwd<Src, RR>), dim3(g.ret_blocks), dim3(kBlock), lds, st,
+                                        src, params, refl, n_mat, part, polar_blocks, n_slots, rp, ga));
+            e = hipGetLastError();
+            if (e != hipSuccess) return e;
+        }
+        if (uw_blocks > 0) {
+            e = uw_backward_table(uwb->table, uwb->n, uwb->blocks, uwb->params, uwb->part, uwb->part_row, st);
+            if (e != hipSuccess) return e;
+        }
     }
     // small tables are reduced here; the atomic path was zeroed by the polar
     // kernel, unless there was none (then the reduction writes zeros)
@@ -1143,14 +1189,15 @@ hipError_t sonar_backward_one(const SonarDev &f, const SonarGrid &g, const ocean
                               int n_rows, const float *refl, int n_mat, double *part, double *refl_part,
                               float *grad_params, float *grad_refl, hipStream_t st) {
     return launch_bwd(One<SonarDev>{f}, 1, g, params, n_rows, refl, n_mat, part, refl_part, grad_params,
-                      grad_refl, st, nullptr);
+                      grad_refl, st, nullptr, nullptr);
 }
 hipError_t sonar_backward_table(const SonarDev *t, int n, const SonarGrid &g,
                                 const oceansim_sonar_params *params, int n_rows, const float *refl,
                                 int n_mat, double *part, double *refl_part, float *grad_params,
-                                float *grad_refl, hipStream_t st, SonarReduce *defer) {
+                                float *grad_refl, hipStream_t st, SonarReduce *defer,
+                                const UwBwdCompanion *uwb) {
     return launch_bwd(Table<SonarDev>{t, n}, n, g, params, n_rows, refl, n_mat, part, refl_part, grad_params,
-                      grad_refl, st, defer);
+                      grad_refl, st, defer, uwb);
 }
 
 }  // namespace osim
