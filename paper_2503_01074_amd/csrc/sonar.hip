@@ -912,6 +912,14 @@ __global__ __launch_bounds__(kBlock) void k_fant_bwd(Src src, const oceansim_son
     // row (before any store, so it may come through the scalar cache), this
     // lane's bins' operator pointers and the direct polar gradient.
     const oceansim_sonar_params pr = params[f.param_row];
+    // the wave's span of entries [w_lo, w_hi): uniform addresses, so scalar
+    // loads, and the only ones the entry loads wait for
+    const int wb = (local * kBlock + __builtin_amdgcn_readfirstlane(wave) * kWave) * BPT;
+    int w_lo = 0, w_hi = 0;
+    if (f.ft_ptr) {
+        w_lo = f.ft_ptr[wb < nb ? wb : nb];
+        w_hi = f.ft_ptr[wb + kWave * BPT < nb ? wb + kWave * BPT : nb];
+    }
     int p[BPT + 1];   // this lane's bins' entries start at p[0..BPT-1] and end at p[BPT]
 #pragma unroll
     for (int m = 0; m <= BPT; ++m) p[m] = f.ft_ptr ? f.ft_ptr[b0 + m < nb ? b0 + m : nb] : 0;
@@ -931,9 +939,10 @@ __global__ __launch_bounds__(kBlock) void k_fant_bwd(Src src, const oceansim_son
     // the atomic reflectivity path (many materials) accumulates into a zeroed table
     if (grad_refl_zero)
         for (int k = bid * kBlock + tid; k < n_mat_zero; k += (int)gridDim.x * kBlock) grad_refl_zero[k] = 0.0f;
-    // per bin, the factors of the adjoint of Eq. (3)-(4): R E rho and phi^2
+    // per bin, the factors of the adjoint of Eq. (3)-(4): R E rho and phi^2;
+    // computed once, while the first round's gathers are in flight
     float fac[BPT], phi2[BPT];
-    {
+    auto speckle_factors = [&]() {
         const AddCtx ctx{pr.sigma_sa, 1.0f / pr.sigma_phi};
         Words wd{0u, 0u, 0u, 0u};
         int wq = -1;
@@ -954,12 +963,12 @@ __global__ __launch_bounds__(kBlock) void k_fant_bwd(Src src, const oceansim_son
                 phi2[m] = phi * phi;
             }
         }
-    }
+    };
+    bool have_factors = false;
     double gs[BPT];
 #pragma unroll
     for (int m = 0; m < BPT; ++m) gs[m] = 0.0;
     if (f.ft_ptr) {
-        const int w_lo = __shfl(p[0], 0, kWave), w_hi = __shfl(p[BPT], kWave - 1, kWave);
         double *slice = prod[wave];
         for (int r0 = w_lo; r0 < w_hi; r0 += kFantChunks * kWave) {
             // Every lane loads (past the end it re-reads the wave's last entry,
@@ -971,6 +980,10 @@ __global__ __launch_bounds__(kBlock) void k_fant_bwd(Src src, const oceansim_son
             for (int c = 0; c < kFantChunks; ++c) {
                 const int e = r0 + c * kWave + lane;
                 en[c] = gload(f.ft_ent + (e < w_hi ? e : w_hi - 1));
+            }
+            if (!have_factors) {   // uniform: under the first round's entry loads
+                speckle_factors();
+                have_factors = true;
             }
 #pragma unroll
             for (int c = 0; c < kFantChunks; ++c) gv[c] = f.grad_fan[(long long)en[c].x];
@@ -996,6 +1009,7 @@ __global__ __launch_bounds__(kBlock) void k_fant_bwd(Src src, const oceansim_son
             __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
         }
     }
+    if (!have_factors) speckle_factors();
     double g_sphi = 0.0, g_ssa = 0.0;
     const double dsphi = 0.5 * (double)pr.sigma_sa / ((double)pr.sigma_phi * (double)pr.sigma_phi);
 #pragma unroll
