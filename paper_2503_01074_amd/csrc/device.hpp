@@ -14,9 +14,9 @@ constexpr int kWave = 64;
 constexpr int kMaxTileBins = 4096;   // polar bins owned by one tile workgroup (one row at least)
 constexpr int kMaxTiles = 4096;      // tiles per frame (LDS histogram in the binning pass)
 constexpr int kXcds = 8;            // accelerator complex dies (each with its own L2)
-constexpr int kFanRows = 4;        // fan rows per thread (one pixel pair each, 8 rows apart)
+constexpr int kFanRows = 2;        // fan rows per thread (one pixel pair each, 8 rows apart)
 constexpr int kFanTileU = 32;      // pixel pairs per fan workgroup along a row
-constexpr int kFanTileV = 32;      // fan rows per fan workgroup (8 x kFanRows)
+constexpr int kFanTileV = 16;      // fan rows per fan workgroup (8 x kFanRows)
 constexpr int kLaneHistMats = 64;    // materials reduced with lane-private LDS histograms
 
 enum Kind { KBIN = 0, KTILE = 1, KFAN = 2, KRET = 3, KTILEB = 4, KFANT = 5, KIND_COUNT = 6 };

@@ -290,7 +290,7 @@ __global__ __launch_bounds__(kBlock) void k_fan(Src src) {
     int local;
     const int fi = src.locate(xcd_grouped_id<16>(blockIdx.x, gridDim.x), KFAN, local);
     const SonarDev f = src.frame(fi);
-    // a workgroup covers 32 pixel pairs x 32 rows; each wave an 8 x 8 patch
+    // a workgroup covers kFanTileU pixel pairs x kFanTileV rows; each wave an 8 x 8 patch
     // of pairs per load instruction (rows 8 apart across a thread's kFanRows),
     // so the gathers of one instruction stay within a few polar rows
     const int n_groups = (f.fan_h + kFanTileV - 1) / kFanTileV;
