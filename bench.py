@@ -226,8 +226,8 @@ class RealTimeStep:
                 # the plan's return-gather launch also carries the camera backward
                 "k_ret_uw_bwd": 28 * self.n_returns + 44 * self.npix,
                 "k_uw": 28 * self.npix, "k_uw_bwd": 44 * self.npix,
-                # the plan's forward polar-tile launch also carries the camera frame
-                "k_tile_uw": 4 * nb + 28 * self.npix}
+                # the plan's binning launch also carries the camera forward
+                "k_bin_uw": 28 * self.n_returns + 28 * self.npix}
 
 
 def timed(torch, fn, steps, warmup):
@@ -544,7 +544,7 @@ def main():
                                "1024x1024 polar bins, gamma speckle k=4, 1024x2048 fan, plus Eq. 1 on one "
                                "1920x1080 RGB frame; forward + backward",
                    "global_batch": 1, "parallelism": "none (1 GPU)"},
-        "path": "plan (frames prepared once, autotuned launch shapes, camera forward in the polar-tile launch)",
+        "path": "plan (frames prepared once, autotuned launch shapes, camera work inside the sonar binning and return-gather launches)",
         "frames_per_s": 1.0 / t_step,
         "fwd_returns_per_s": rt.n_returns / t_fwd,
         "fwd_frames_per_s": 1.0 / t_fwd,

@@ -258,9 +258,10 @@ enum {
  * device memory (workspaces, frame tables, transposed fan operators), uploads the
  * frame tables and, with OCEANSIM_PLAN_GRAPH, captures the forward (and
  * backward) launch sequences into HIP graphs.  A plan holding both sonar and
- * camera frames runs the camera forward inside the launch of the sonar
- * polar-tile kernel (one dispatch for both), so the camera's HBM traffic
- * overlaps the VALU-bound speckle work.  The plan keeps every pointer
+ * camera frames runs the camera forward inside the sonar binning launch and
+ * the camera backward inside the sonar return-gather launch (one dispatch
+ * for both, when the return gather's LDS leaves room), so the camera's HBM
+ * traffic overlaps latency-bound sonar work.  The plan keeps every pointer
  * of the descriptors, parameter tables and gradient outputs until
  * oceansim_plan_destroy: the caller keeps them alive, and may change their
  * CONTENTS (new returns, images, parameters) between launches, not the

@@ -56,7 +56,7 @@ struct SonarGrid {
 
 constexpr int kBwdThreads = 512;   // threads of a backward polar-tile workgroup
 
-// Camera frames carried along in the forward polar-tile launch of a plan
+// Camera frames carried along in the forward binning launch of a plan
 // with both kinds of frames: device frame table, workgroups (kBlock threads
 // each) and the water parameters.
 struct UwCompanion {

@@ -46,7 +46,7 @@ struct oceansim_plan {
     char *ws_sf = nullptr, *ws_sb = nullptr, *ws_uf = nullptr, *ws_ub = nullptr;
     hipStream_t cap = nullptr;   // capture stream (default priority)
     // with both kinds of frames the camera frames ride along in the forward
-    // polar-tile launch of the sonar frames
+    // binning launch of the sonar frames
     bool fused = false;
     hipGraphExec_t g_fwd = nullptr, g_bwd = nullptr;
 };

@@ -32,12 +32,13 @@ namespace osim {
 // ---------------------------------------------------------------------------
 // k_bin
 // ---------------------------------------------------------------------------
+// Binning chunk `bid` of the launch (kBlock threads, R returns each).
 template <class Src, int R>
-__global__ __launch_bounds__(kBlock) void k_bin(Src src, const oceansim_sonar_params *params,
-                                                const float *refl, int n_mat) {
+__device__ __forceinline__ void bin_block(const Src &src, const oceansim_sonar_params *params, const float *refl,
+                                          int n_mat, int bid) {
     extern __shared__ int4 lds_raw[];
     int local;
-    const int fi = src.locate(blockIdx.x, KBIN, local);
+    const int fi = src.locate(bid, KBIN, local);
     const SonarDev f = src.frame(fi);
     const int tid = threadIdx.x;
     const int n_tiles = f.n_tiles;
@@ -99,6 +100,25 @@ __global__ __launch_bounds__(kBlock) void k_bin(Src src, const oceansim_sonar_pa
     const int total = hist[n_tiles];
     const gptr<uint2> dst = f.pairs + base;
     for (int k = tid; k < total; k += kBlock) gstore(dst + k, stage[k]);
+}
+
+template <class Src, int R>
+__global__ __launch_bounds__(kBlock) void k_bin(Src src, const oceansim_sonar_params *params,
+                                                const float *refl, int n_mat) {
+    bin_block<Src, R>(src, params, refl, n_mat, blockIdx.x);
+}
+
+// The binning chunks of the sonar frames and, in the same launch, the camera
+// forward of a plan (workgroups n_bin_blocks and up): the chunks are few and
+// latency-bound, so the camera's HBM stream fills the rest of the chip.
+template <class Src, int R>
+__global__ __launch_bounds__(kBlock) void k_bin_uw(Src src, const oceansim_sonar_params *params,
+                                                   const float *refl, int n_mat, int n_bin_blocks,
+                                                   Table<UwDev> usrc, const oceansim_water_params *wparams) {
+    if ((int)blockIdx.x < n_bin_blocks)
+        bin_block<Src, R>(src, params, refl, n_mat, blockIdx.x);
+    else
+        uw_fwd_block<Table<UwDev>, kBlock>(usrc, wparams, blockIdx.x - n_bin_blocks);
 }
 
 // ---------------------------------------------------------------------------
@@ -259,19 +279,6 @@ __device__ __forceinline__ void tile_fwd_block(const Src &src, const oceansim_so
 template <class Src>
 __global__ __launch_bounds__(kBlock) void k_tile(Src src, const oceansim_sonar_params *params) {
     tile_fwd_block(src, params, blockIdx.x);
-}
-
-// The forward tiles of the sonar frames and, in the same launch, the camera
-// frames of a plan (workgroups n_tile_blocks and up): the camera stream of
-// HBM traffic runs beside the VALU-heavy tiles instead of after them.
-template <class Src>
-__global__ __launch_bounds__(kBlock) void k_tile_uw(Src src, const oceansim_sonar_params *params,
-                                                    int n_tile_blocks, Table<UwDev> usrc,
-                                                    const oceansim_water_params *wparams) {
-    if ((int)blockIdx.x < n_tile_blocks)
-        tile_fwd_block(src, params, blockIdx.x);
-    else
-        uw_fwd_block<Table<UwDev>, kBlock>(usrc, wparams, blockIdx.x - n_tile_blocks);
 }
 
 // ---------------------------------------------------------------------------
@@ -1071,21 +1078,26 @@ __global__ __launch_bounds__(kBlock) void k_reduce_sonar(SonarReduce a) {
 template <class Src>
 static hipError_t launch_fwd(const Src &src, const SonarGrid &g, const oceansim_sonar_params *params,
                              const float *refl, int n_mat, hipStream_t st, const UwCompanion *uw) {
-    if (g.bin_blocks > 0) {
+    // a plan's camera forward rides along in the binning launch (few,
+    // latency-bound workgroups with little LDS)
+    const bool with_uw = uw && uw->blocks > 0;
+    if (g.bin_blocks > 0 || with_uw) {
         const size_t lds = (size_t)((g.max_tiles + 1 + 3) & ~3) * 4 + (size_t)g.chunk * 8;
-        OSIM_DISPATCH_R(g.chunk / kBlock,
-                        OSIM_LAUNCH("k_bin", (k_bin<Src, RR>), dim3(g.bin_blocks), dim3(kBlock), lds, st, src,
-                                           params, refl, n_mat));
+        if (with_uw) {
+            OSIM_DISPATCH_R(g.chunk / kBlock,
+                            OSIM_LAUNCH("k_bin_uw", (k_bin_uw<Src, RR>), dim3(g.bin_blocks + uw->blocks),
+                                        dim3(kBlock), lds, st, src, params, refl, n_mat, g.bin_blocks,
+                                        Table<UwDev>{uw->table, uw->n}, uw->params));
+        } else {
+            OSIM_DISPATCH_R(g.chunk / kBlock,
+                            OSIM_LAUNCH("k_bin", (k_bin<Src, RR>), dim3(g.bin_blocks), dim3(kBlock), lds, st, src,
+                                        params, refl, n_mat));
+        }
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
-    if (uw && uw->blocks > 0)
-        OSIM_LAUNCH("k_tile_uw", (k_tile_uw<Src>), dim3(g.tile_blocks + uw->blocks), dim3(kBlock),
-                    (size_t)g.max_tile_bins * 8 + (size_t)g.max_n_az * 4, st, src, params, g.tile_blocks,
-                    Table<UwDev>{uw->table, uw->n}, uw->params);
-    else
-        OSIM_LAUNCH("k_tile", (k_tile<Src>), dim3(g.tile_blocks), dim3(kBlock),
-                    (size_t)g.max_tile_bins * 8 + (size_t)g.max_n_az * 4, st, src, params);
+    OSIM_LAUNCH("k_tile", (k_tile<Src>), dim3(g.tile_blocks), dim3(kBlock),
+                (size_t)g.max_tile_bins * 8 + (size_t)g.max_n_az * 4, st, src, params);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     if (g.fan_blocks > 0) {
