@@ -423,7 +423,11 @@ int orc_sonar_forward(const orc_sonar_cfg *c, int64_t n,
 /* gradient of L with respect to the polar output, [n_range][n_azimuth].     */
 /* g_refl_abs / g_par_abs (optional) accumulate the sums of the magnitudes   */
 /* of the terms each gradient component adds up: the condition of that sum, */
-/* against which a float32 evaluation's rounding error is measured.          */
+/* against which a float32 evaluation's rounding error is measured.  The    */
+/* terms are taken fully expanded: the polar-output gradient of a bin is    */
+/* itself a sum (the fan's pixels that read the bin, weighted, plus the     */
+/* direct polar gradient), so the magnitudes use that sum's own magnitude   */
+/* sum, the fan adjoint of |g_fan| plus |g_polar|, in its place.            */
 /* ------------------------------------------------------------------------- */
 int orc_sonar_backward(const orc_sonar_cfg *c, int64_t n,
                        const float *x, const float *y, const float *z,
@@ -446,39 +450,58 @@ int orc_sonar_backward(const orc_sonar_cfg *c, int64_t n,
     if (g_polar)
         for (int64_t b = 0; b < nb; ++b) gO[b] += g_polar[b];
     if (g_out) memcpy(g_out, gO, sizeof(double) * nb);
+    /* magnitude sum of each bin's output gradient (for the conditions) */
+    double *gOa = NULL;
+    if (g_refl_abs || g_par_abs) {
+        gOa = (double *)malloc(sizeof(double) * nb);
+        if (g_fan && c->fan_h > 0 && c->fan_w > 0) {
+            int64_t npx = (int64_t)c->fan_h * c->fan_w;
+            double *af = (double *)malloc(sizeof(double) * npx);
+            for (int64_t q = 0; q < npx; ++q) af[q] = fabs(g_fan[q]);
+            orc_fan_adjoint(c, af, gOa);
+            free(af);
+        } else {
+            memset(gOa, 0, sizeof(double) * nb);
+        }
+        if (g_polar)
+            for (int64_t b = 0; b < nb; ++b) gOa[b] += fabs(g_polar[b]);
+    }
 
-    /* adjoint of steps 3-4 */
+    /* adjoint of steps 3-4 (gPa: magnitude sum of each bin's gP) */
+    double *gPa = gOa ? (double *)malloc(sizeof(double) * nb) : NULL;
     double gG = 0.0, gsphi = 0.0, gssa = 0.0, gssm = 0.0;
     double aG = 0.0, asphi = 0.0, assa = 0.0, assm = 0.0, aalpha = 0.0;
     for (int64_t b = 0; b < nb; ++b) {
         int i = (int)(b / c->n_azimuth), j = (int)(b % c->n_azimuth);
         double Q = c->gain * P[b];
-        double gQ;
+        double ga = gOa ? gOa[b] : 0.0;   /* magnitude sum of gO[b] */
+        double gQ, mulv = 1.0;
         if (c->speckle_mode == ORC_SPECKLE_OFF) {
             gQ = gO[b];
         } else {
             double add, mul, rayleigh, gauss;
             orc_speckle_terms(c, i, j, &add, &mul, &rayleigh, &gauss);
             gQ = gO[b] * mul;
+            mulv = mul;
             double ri = orc_bin_range(c, i), pj = orc_bin_azimuth(c, j);
             double R = ri * ri / (c->r_max * c->r_max);
             double E = exp(-(pj * pj) / c->sigma_phi);
             /* d add / d sigma_sa and d add / d sigma_phi, from Eq. (3)-(4) */
-            double tsa = gO[b] * R * 0.5 * E * rayleigh;
-            double tphi = gO[b] * R * 0.5 * c->sigma_sa * rayleigh * E * (pj * pj) /
-                          (c->sigma_phi * c->sigma_phi);
-            gssa += tsa;
-            gsphi += tphi;
-            assa += fabs(tsa);
-            asphi += fabs(tphi);
+            double fsa = R * 0.5 * E * rayleigh;
+            double fphi = R * 0.5 * c->sigma_sa * rayleigh * E * (pj * pj) / (c->sigma_phi * c->sigma_phi);
+            gssa += gO[b] * fsa;
+            gsphi += gO[b] * fphi;
+            assa += ga * fabs(fsa);
+            asphi += ga * fabs(fphi);
             if (c->speckle_mode == ORC_SPECKLE_PAPER) {
                 gssm += gO[b] * Q * gauss;
-                assm += fabs(gO[b] * Q * gauss);
+                assm += ga * fabs(Q * gauss);
             }
         }
         gG += gQ * P[b];
-        aG += fabs(gQ * P[b]);
+        aG += ga * fabs(mulv * P[b]);
         gP[b] = c->gain * gQ;
+        if (gPa) gPa[b] = ga * fabs(c->gain * mulv);
     }
 
     /* adjoint of steps 1-2: each return reads the gradient of its bin */
@@ -492,10 +515,11 @@ int orc_sonar_backward(const orc_sonar_cfg *c, int64_t n,
         double I = orc_return_intensity(c, x[k], y[k], z[k], nx[k], ny[k], nz[k], r, refl[m],
                                         &cosg, &att);
         double gI = gP[b];
+        double gIa = gPa ? gPa[b] : 0.0;
         g_refl[m] += gI * cosg * att;
         galpha += gI * I * (-c->kappa * r);
-        if (g_refl_abs) g_refl_abs[m] += fabs(gI * cosg * att);
-        aalpha += fabs(gI * I * c->kappa * r);
+        if (g_refl_abs) g_refl_abs[m] += gIa * fabs(cosg * att);
+        aalpha += gIa * fabs(I * c->kappa * r);
     }
     g_par[0] += galpha;
     g_par[1] += gG;
@@ -512,6 +536,8 @@ int orc_sonar_backward(const orc_sonar_cfg *c, int64_t n,
     free(P);
     free(gO);
     free(gP);
+    free(gOa);
+    free(gPa);
     return 0;
 }
 

@@ -403,3 +403,32 @@ def test_uw_backward_matches_central_differences():
             return (g * oracle.uw_forward(cam.J, d, bd, bb, bi)).sum()
         d0 = float(cam.depth[v, u])
         assert g_d[v, u] == pytest.approx((L(d0 + h) - L(d0 - h)) / (2 * h), rel=1e-5)
+
+
+def test_sonar_backward_conditions_expand_the_fan():
+    """The conditions of the gradients (sums of term magnitudes, the scale of
+    float32 rounding) expand each bin's output gradient into its terms: the
+    sigma_sa condition equals sum_b (adjoint of |g_fan| + |g_polar|)_b times
+    the bin's factor R E rho / 2, which the additive field gives as
+    (add - R) / sigma_sa; with a gradient that cancels within bins it exceeds
+    the magnitude of the cancelled sums."""
+    st = Stream(22, 1)
+    spec = SonarSpec(r_min=0.5, r_max=8.0, n_range=24, n_azimuth=20, fan_h=40, fan_w=64,
+                     alpha=0.13, gain=1.4, sigma_phi=0.35, sigma_sa=0.15, sigma_sm=0.12,
+                     speckle_mode=SPECKLE_PAPER, seed_lo=9, frame_id=2)
+    hits = make_hits(st, spec, 600, n_materials=6)
+    cfg = _cfg(spec)
+    wp = st.normal((24, 20))
+    wf = st.normal((40, 64))
+    _, g_par, g_out, a_refl, a_par = oracle.sonar_backward(cfg, hits, hits.refl, wp, wf, with_abs=True)
+    add, _ = oracle.speckle_fields(cfg)
+    dr = (spec.r_max - spec.r_min) / spec.n_range
+    r = spec.r_min + (np.arange(spec.n_range) + 0.5) * dr
+    R = (r * r / (spec.r_max * spec.r_max))[:, None]
+    fsa = (add - R) / spec.sigma_sa                       # R E rho / 2 per bin
+    g_abs = oracle.fan_adjoint(cfg, np.abs(wf)) + np.abs(wp)
+    assert a_par[3] == pytest.approx(float((g_abs * np.abs(fsa)).sum()), rel=1e-12)
+    assert a_par[3] > float(np.abs(g_out * fsa).sum())    # cancellation inside bins
+    # without a fan gradient the expansion is the polar gradient itself
+    _, _, g_out2, _, a_par2 = oracle.sonar_backward(cfg, hits, hits.refl, wp, None, with_abs=True)
+    assert a_par2[3] == pytest.approx(float(np.abs(g_out2 * fsa).sum()), rel=1e-12)
