@@ -1,0 +1,216 @@
+"""GPU parity at the workloads' full sizes, in the launch configurations the
+benchmark times: the real-time frame (sonar + camera) through an autotuned
+backward plan, every frame checked; the 256-frame ragged batch through one
+batched call and through an autotuned plan, sampled frames checked; the
+differentiable batch (32 sonar + 32 camera frames) through an autotuned
+backward plan, every frame and gradient checked; and eight frames of the
+calibration shape (2048 x 1024 returns, 2048 x 2048 bins, no fan, plus
+1920 x 1080 camera frames) through a backward plan.
+
+Bins bit-exact, images to 1e-5 relative, gradients to 1e-5 of the sums of
+their terms' magnitudes (as in the small-size parity tests).
+"""
+import copy
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle import SonarConfig
+import workloads as W
+from _tol import assert_grad_cond, assert_image_close
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(msg):
+    print("[case] " + msg, flush=True)
+    sys.stdout.flush()
+
+
+def _plan(osm, torch, frames, refl, cams=(), water=None, *, backward=True, autotune=True, bins=True,
+          image_grads=True):
+    geoms = [osm.SonarGeometry.from_spec(f.spec, param_row=0) for f in frames]
+    hits = [osm.DeviceHits.from_host(f.hits) for f in frames]
+    params = osm.sonar_params([osm.sonar_params_from_spec(frames[0].spec)])
+    refl_d = torch.as_tensor(refl).cuda()
+    cam = []
+    wt = None
+    if cams:
+        w = water
+        wt = osm.water_params([(w.beta_d, w.beta_b, w.b_inf)])
+        cam = [(torch.as_tensor(c.J).cuda(), torch.as_tensor(c.depth).cuda(), 0) for c in cams]
+    plan = osm.Plan(list(zip(geoms, hits)), cam, sonar_params=params, refl=refl_d, water=wt, backward=backward,
+                    autotune=autotune, bins=bins, image_grads=image_grads and backward and bool(cams))
+    return plan, (geoms, hits, params, refl_d, cam, wt)
+
+
+def _check_sonar_forward(plan, frames, refl, which, what):
+    for k in which:
+        f, o = frames[k], plan.sonar_out[k]
+        want = oracle.sonar_forward(SonarConfig.from_spec(f.spec), f.hits, refl)
+        np.testing.assert_array_equal(o["bins"].cpu().numpy(), want["bins"], err_msg="%s bins %d" % (what, k))
+        if "polar" in o:
+            assert_image_close(o["polar"].cpu().numpy(), want["out"], "%s polar %d" % (what, k))
+        if "fan" in o:
+            assert_image_close(o["fan"].cpu().numpy(), want["fan"], "%s fan %d" % (what, k), mask=~want["ambiguous"])
+
+
+def _check_backward(plan, frames, refl, gpol, gfan, cams, water, gout, what):
+    o_refl, c_refl = np.zeros(refl.shape[0]), np.zeros(refl.shape[0])
+    o_par, c_par = np.zeros(5), np.zeros(5)
+    for k, f in enumerate(frames):
+        a, b, _, ca, cb = oracle.sonar_backward(SonarConfig.from_spec(f.spec), f.hits, refl, gpol[k], gfan[k],
+                                                with_abs=True)
+        o_refl += a
+        c_refl += ca
+        o_par += b
+        c_par += cb
+    assert_grad_cond(plan.grad_refl.cpu().numpy(), o_refl, c_refl, what="%s refl" % what)
+    assert_grad_cond(plan.grad_sonar_params.cpu().numpy()[0, :5], o_par, c_par, what="%s sonar params" % what)
+    if not cams:
+        return
+    bd, bb, bi = (x.astype(np.float64) for x in (water.beta_d, water.beta_b, water.b_inf))
+    o_w, c_w = np.zeros(9), np.zeros(9)
+    for k, c in enumerate(cams):
+        want = oracle.uw_forward(c.J, c.depth, bd, bb, bi)
+        o = plan.camera_out[k]
+        assert_image_close(o["out"].cpu().numpy(), want, "%s camera %d" % (what, k))
+        p, gj, gd, cp = oracle.uw_backward(c.J, c.depth, bd, bb, bi, gout[k], with_abs=True)
+        o_w += p
+        c_w += cp
+        if "grad_J" in o:
+            assert_image_close(o["grad_J"].cpu().numpy(), gj, "%s grad J %d" % (what, k))
+            # dL/dd sums terms of both signs over the channels: bounded by 1e-5
+            # of the sum of their magnitudes
+            d = c.depth.astype(np.float64)[None]
+            J = c.J.astype(np.float64)
+            cond = (np.abs(gout[k]) * (bd[:, None, None] * np.abs(J) * np.exp(-bd[:, None, None] * d) +
+                                       bi[:, None, None] * bb[:, None, None] * np.exp(-bb[:, None, None] * d))).sum(0)
+            err = np.abs(o["grad_depth"].cpu().numpy().astype(np.float64) - gd)
+            assert np.all(err <= 1e-5 * cond + 1e-30), "%s grad depth %d" % (what, k)
+    assert_grad_cond(plan.grad_water.cpu().numpy()[0], o_w, c_w, what="%s water" % what)
+
+
+def _fill_grads(torch, plan, gpol, gfan, gout):
+    for o, a, b in zip(plan.sonar_out, gpol, gfan):
+        if "grad_polar" in o:
+            o["grad_polar"].copy_(torch.as_tensor(a))
+        if "grad_fan" in o:
+            o["grad_fan"].copy_(torch.as_tensor(b))
+    for o, g in zip(plan.camera_out, gout):
+        o["grad_out"].copy_(torch.as_tensor(g))
+
+
+def test_real_time_frame_plan():
+    """The benchmark's step: one sonar frame (131072 returns, 1024 x 1024
+    bins, 1024 x 2048 fan) and one 1920 x 1080 camera frame through an
+    autotuned backward plan, forward then backward, twice."""
+    import torch
+    import paper_2503_01074_amd as osm
+    _say("real-time frame through an autotuned backward plan")
+    frames = W.sonar_c2()
+    cams, waters = W.camera_c2()
+    f = frames[0]
+    refl = f.hits.refl
+    gpol = [W.loss_weights((101, 1), (f.spec.n_range, f.spec.n_azimuth))]
+    gfan = [W.loss_weights((101, 2), (f.spec.fan_h, f.spec.fan_w))]
+    gout = [W.loss_weights((101, 3), cams[0].J.shape)]
+    plan, keep = _plan(osm, torch, frames, refl, cams, waters[0])
+    _fill_grads(torch, plan, gpol, gfan, gout)
+    for rep in range(2):
+        plan.forward()
+        plan.backward()
+        torch.cuda.synchronize()
+        _check_sonar_forward(plan, frames, refl, [0], "real-time %d" % rep)
+        _check_backward(plan, frames, refl, gpol, gfan, cams, waters[0], gout, "real-time %d" % rep)
+    plan.close()
+
+
+def test_ragged_batch_full_size_sampled():
+    """All 256 frames of the ragged batch in one batched call and in an
+    autotuned plan; twelve frames spread over the batch checked in full."""
+    import torch
+    import paper_2503_01074_amd as osm
+    _say("ragged batch: 256 frames, batched call and plan, 12 sampled frames")
+    frames = W.sonar_c3()
+    # one reflectivity table for the batch: per-frame tables concatenated,
+    # material ids offset (misses stay negative), as the benchmark does
+    refl = np.concatenate([f.hits.refl for f in frames]).astype(np.float32)
+    shifted, base = [], 0
+    for f in frames:
+        h = copy.copy(f.hits)
+        h.mat = np.where(f.hits.mat >= 0, f.hits.mat + base, f.hits.mat).astype(np.int32)
+        h.refl = refl
+        base += f.hits.refl.shape[0]
+        shifted.append(W.SonarFrame(f.spec, h))
+    which = sorted(set(np.linspace(0, len(frames) - 1, 12).astype(int).tolist()))
+    geoms = [osm.SonarGeometry.from_spec(f.spec, param_row=i) for i, f in enumerate(shifted)]
+    hits = [osm.DeviceHits.from_host(f.hits) for f in shifted]
+    params = osm.sonar_params([osm.sonar_params_from_spec(f.spec) for f in shifted])
+    refl_d = torch.as_tensor(refl).cuda()
+    outs = osm.render_sonar(geoms, hits, params, refl_d, polar=True, fan=True, bins=True)
+    torch.cuda.synchronize()
+    for k in which:
+        f, o = shifted[k], outs[k]
+        want = oracle.sonar_forward(SonarConfig.from_spec(f.spec), f.hits, refl)
+        np.testing.assert_array_equal(o["bins"].cpu().numpy(), want["bins"], err_msg="batched bins %d" % k)
+        assert_image_close(o["polar"].cpu().numpy(), want["out"], "batched polar %d" % k)
+        assert_image_close(o["fan"].cpu().numpy(), want["fan"], "batched fan %d" % k, mask=~want["ambiguous"])
+    del outs
+    plan = osm.Plan(list(zip(geoms, hits)), sonar_params=params, refl=refl_d, autotune=True, bins=True)
+    plan.forward()
+    torch.cuda.synchronize()
+    _check_sonar_forward(plan, shifted, refl, which, "ragged plan")
+    plan.close()
+
+
+def test_differentiable_batch_plan():
+    """32 sonar frames (512 x 64 returns, 64 materials, 512 x 512 bins, 512 x
+    1024 fan, paper speckle) and 32 camera frames (960 x 540) through an
+    autotuned backward plan: every image and every gradient."""
+    import torch
+    import paper_2503_01074_amd as osm
+    _say("differentiable batch: 32 + 32 frames through an autotuned backward plan")
+    frames = W.sonar_c4()
+    cams, waters = W.camera_c4()
+    refl = frames[0].hits.refl
+    gpol = [W.loss_weights((202, k), (f.spec.n_range, f.spec.n_azimuth)) for k, f in enumerate(frames)]
+    gfan = [W.loss_weights((203, k), (f.spec.fan_h, f.spec.fan_w)) for k, f in enumerate(frames)]
+    gout = [W.loss_weights((204, k), c.J.shape) for k, c in enumerate(cams)]
+    plan, keep = _plan(osm, torch, frames, refl, cams, waters[0])
+    _fill_grads(torch, plan, gpol, gfan, gout)
+    plan.forward()
+    plan.backward()
+    torch.cuda.synchronize()
+    _check_sonar_forward(plan, frames, refl, range(len(frames)), "differentiable")
+    _check_backward(plan, frames, refl, gpol, gfan, cams, waters[0], gout, "differentiable")
+    plan.close()
+
+
+def test_calibration_shape_plan():
+    """Eight frames of the calibration shape (2048 x 1024 returns, 2048 x 2048
+    bins, no fan, 64 materials, gamma speckle) and eight 1920 x 1080 camera
+    frames through a backward plan (polar loss): two frames' images and all
+    gradients checked."""
+    import torch
+    import paper_2503_01074_amd as osm
+    _say("calibration shape: 8 sonar frames of 2M returns, 2048^2 bins, + 8 camera frames 1080p")
+    frames = W.sonar_c5(n_frames=8)
+    st = W.Stream(W.BASE_SEED + 4, 1 << 21)
+    water = W.make_water(st)
+    cams = [W.make_camera(W.Stream(W.BASE_SEED + 4, (1 << 22) + k), 1080, 1920) for k in range(8)]
+    refl = frames[0].hits.refl
+    gpol = [W.loss_weights((205, k), (f.spec.n_range, f.spec.n_azimuth)) for k, f in enumerate(frames)]
+    gfan = [None] * len(frames)
+    gout = [W.loss_weights((206, k), c.J.shape) for k, c in enumerate(cams)]
+    plan, keep = _plan(osm, torch, frames, refl, cams, water, autotune=False, image_grads=False)
+    assert "fan" not in plan.sonar_out[0]
+    _fill_grads(torch, plan, gpol, gfan, gout)
+    plan.forward()
+    plan.backward()
+    torch.cuda.synchronize()
+    _check_sonar_forward(plan, frames, refl, [0, 7], "calibration shape")
+    _check_backward(plan, frames, refl, gpol, gfan, cams, water, gout, "calibration shape")
+    plan.close()
