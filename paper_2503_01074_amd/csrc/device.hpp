@@ -17,7 +17,7 @@ constexpr int kXcds = 8;            // accelerator complex dies (each with its o
 constexpr int kFanRows = 2;        // fan rows per thread (one pixel pair each, 8 rows apart)
 constexpr int kFanTileU = 32;      // pixel pairs per fan workgroup along a row
 constexpr int kFanTileV = 16;      // fan rows per fan workgroup (8 x kFanRows)
-constexpr int kLaneHistMats = 64;    // materials reduced with lane-private LDS histograms
+constexpr int kLaneHistMats = 64;    // materials reduced per workgroup in an LDS table (above: global atomics)
 
 enum Kind { KBIN = 0, KTILE = 1, KFAN = 2, KRET = 3, KTILEB = 4, KFANT = 5, KIND_COUNT = 6 };
 enum Speckle { SPECKLE_OFF = 0, SPECKLE_PAPER = 1, SPECKLE_GAMMA = 2 };

@@ -776,30 +776,52 @@ __global__ __launch_bounds__(kBwdThreads, SAVED ? 6 : 4) void k_tile_bwd(Src src
 // k_ret_bwd
 // ---------------------------------------------------------------------------
 // Return chunk `bid` of the n_blocks chunks of the launch.
+//
+// Small reflectivity tables (n_mat <= kLaneHistMats) are reduced per
+// workgroup in LDS without thread-private columns: each material's
+// contributions are added as 64-bit fixed point, scaled from that
+// material's own largest magnitude in the chunk (a first pass takes the
+// maxima), so the integer sums are exact, order-independent and therefore
+// reproducible, and each keeps ~2^-39 of its material's largest term; a
+// non-finite contribution makes its material's partial sum NaN.  The table
+// needs 12 bytes per material, so the launch keeps its occupancy (and room
+// for camera workgroups).
 template <class Src, int R>
 __device__ __forceinline__ void ret_bwd_block(const Src &src, const oceansim_sonar_params *params,
                                               const float *refl, int n_mat, double *part, int slot_base,
                                               int n_slots, double *refl_part, float *grad_refl_atomic, int bid,
                                               int n_blocks) {
     extern __shared__ int4 lds_raw[];
-    // thread-private reflectivity columns [n_mat][kBlock] (small tables); the
-    // same memory later serves the workgroup reductions
-    float *hist = reinterpret_cast<float *>(lds_raw);
+    // [n_mat] fixed-point sums, then [n_mat] magnitude maxima (float bits;
+    // 0x7f800001 and up: a non-finite contribution); the same memory later
+    // serves the workgroup reductions
+    long long *racc = reinterpret_cast<long long *>(lds_raw);
+    unsigned *rmax = reinterpret_cast<unsigned *>(racc + n_mat);
     double *red3 = reinterpret_cast<double *>(lds_raw);
     int local;
     const int fi = src.locate(bid, KRET, local);
     const SonarDev f = src.frame(fi);
     const int tid = threadIdx.x;
-    const bool lane_hist = refl_part != nullptr;
+    const bool table = refl_part != nullptr;
 
-    if (lane_hist)
-        for (int k = tid; k < n_mat * kBlock; k += kBlock) hist[k] = 0.0f;
+    if (table)
+        for (int k = tid; k < n_mat; k += kBlock) {
+            racc[k] = 0;
+            rmax[k] = 0u;
+        }
     __syncthreads();
 
     const oceansim_sonar_params pr = params[f.param_row];
     const float G = pr.gain;
     double g_alpha = 0.0, g_gain = 0.0, g_ssm = 0.0;
     const long long base = (long long)local * (R * kBlock);
+    float gr_q[R];
+    int m_q[R];   // -1: no contribution (past the frame's end, a miss, or the atomic path)
+#pragma unroll
+    for (int q = 0; q < R; ++q) {
+        m_q[q] = -1;
+        gr_q[q] = 0.0f;
+    }
 #pragma unroll
     for (int q = 0; q < R; ++q) {
         const long long k = base + (long long)q * kBlock + tid;
@@ -821,24 +843,41 @@ __device__ __forceinline__ void ret_bwd_block(const Src &src, const oceansim_son
         g_gain += gIt * (double)mult * (double)I;
         if (f.speckle == SPECKLE_PAPER) g_ssm += gIt * (double)G * (double)I * (double)z;
         const float gr = (float)(gI * (double)cosg * (double)att);
-        if (lane_hist)
-            hist[m * kBlock + tid] += gr;
-        else
+        if (table) {
+            m_q[q] = m;
+            gr_q[q] = gr;
+            atomicMax(&rmax[m], __float_as_uint(__builtin_fabsf(gr)));   // ordered as the magnitudes
+        } else {
             atomicAdd(&grad_refl_atomic[m], gr);
+        }
     }
-    if (lane_hist) {
+    if (table) {
         __syncthreads();
-        // per material, the 256 thread columns summed by one wave in a fixed
-        // tree order (four per lane, then the wave's shuffle tree); partial
-        // sums column-major: refl_part[m * n_ret_slots + slot]
-        const int lane = tid & (kWave - 1), wave = tid / kWave;
-        for (int mm = wave; mm < n_mat; mm += kBlock / kWave) {
-            const float *h = hist + mm * kBlock;
-            double s = (double)h[lane];
 #pragma unroll
-            for (int q = 1; q < kBlock / kWave; ++q) s += (double)h[lane + q * kWave];
-            s = wave_sum(s);
-            if (lane == 0) refl_part[(long long)mm * n_blocks + bid] = s;
+        for (int q = 0; q < R; ++q) {
+            const int m = m_q[q];
+            if (m < 0) continue;
+            const unsigned mb = rmax[m];
+            if (mb >= 0x7f800000u || mb == 0u) continue;   // non-finite (flagged) or all zero
+            int e;
+            frexpf(__uint_as_float(mb), &e);                // largest magnitude < 2^e
+            // |scaled| < 2^50, and at most 2^12 of them per workgroup: the sum fits
+            const long long v = round_to_ll((double)gr_q[q] * ldexp(1.0, 50 - e));
+            if (v != 0) atomicAdd(reinterpret_cast<unsigned long long *>(&racc[m]), (unsigned long long)v);
+        }
+        __syncthreads();
+        // partial sums column-major: refl_part[m * n_ret_slots + slot]
+        for (int m = tid; m < n_mat; m += kBlock) {
+            const unsigned mb = rmax[m];
+            double sum = 0.0;
+            if (mb >= 0x7f800000u) {
+                sum = __builtin_nan("");
+            } else if (mb != 0u) {
+                int e;
+                frexpf(__uint_as_float(mb), &e);
+                sum = (double)racc[m] * ldexp(1.0, e - 50);
+            }
+            refl_part[(long long)m * n_blocks + bid] = sum;
         }
     }
     __syncthreads();
@@ -1144,7 +1183,7 @@ static hipError_t launch_bwd(const Src &src, int n_frames, const SonarGrid &g,
         if (e != hipSuccess) return e;
     }
     const int uw_blocks = uwb ? uwb->blocks : 0;
-    size_t lds = lane_hist ? (size_t)n_mat * kBlock * 4 : 0;
+    size_t lds = lane_hist ? (size_t)n_mat * 12 : 0;
     if (lds < (size_t)3 * (kBlock / kWave) * 8) lds = (size_t)3 * (kBlock / kWave) * 8;
     // the camera workgroups would reserve the same LDS: fused only while it
     // still leaves room for eight of them per CU
