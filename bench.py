@@ -43,8 +43,10 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 64 MiB device-to-device copy (counter calibration)")
-    ap.add_argument("--only", choices=["c3", "c4"], default=None,
+    ap.add_argument("--only", choices=["c3", "c4", "c5"], default=None,
                     help="only build and run one batched leg (for profiler runs); prints no JSON line")
+    ap.add_argument("--c5-frames", type=int, default=64,
+                    help="sonar and camera frames of the calibration-scale leg (--only c5)")
     return ap.parse_args()
 
 
@@ -451,6 +453,61 @@ def cpu_baseline(rt, budget_s):
                       % (n, el)}
 
 
+def calibration_leg(torch, dev, steps, n_frames):
+    """Calibration scale: n_frames sonar frames of 2048 x 1024 returns (2048 x
+    2048 bins, no fan, 64 materials, gamma speckle) and n_frames 1920 x 1080
+    camera frames, forward and forward + backward through an autotuned plan
+    (polar and image losses).  Four distinct sonar and camera frames are
+    generated and uploaded n_frames / 4 times each (separate device buffers,
+    distinct frame ids, so distinct speckle), which keeps the host-side
+    generation to seconds."""
+    import paper_2503_01074_amd as osm
+    import workloads as W
+    t0 = time.perf_counter()
+    base = W.sonar_c5(n_frames=4)
+    st = W.Stream(W.BASE_SEED + 4, 1 << 21)
+    water_h = W.make_water(st)
+    cams = [W.make_camera(W.Stream(W.BASE_SEED + 4, (1 << 22) + k), 1080, 1920) for k in range(4)]
+    hits, geoms, Js, ds = [], [], [], []
+    for k in range(n_frames):
+        f, c = base[k % 4], cams[k % 4]
+        hits.append(osm.DeviceHits.from_host(f.hits, dev))
+        g = osm.SonarGeometry.from_spec(f.spec, param_row=0)
+        g.frame_id = k
+        geoms.append(g)
+        Js.append(torch.as_tensor(c.J, device=dev))
+        ds.append(torch.as_tensor(c.depth, device=dev))
+    refl = torch.as_tensor(base[0].hits.refl, device=dev)
+    params = osm.sonar_params([osm.sonar_params_from_spec(base[0].spec)], dev)
+    water = osm.water_params([(water_h.beta_d, water_h.beta_b, water_h.b_inf)], dev)
+    plan = osm.Plan(list(zip(geoms, hits)), [(J, d, 0) for J, d in zip(Js, ds)], sonar_params=params, refl=refl,
+                    water=water, backward=True, autotune=True)
+    gp = [torch.as_tensor(W.loss_weights((205, k), (2048, 2048)), device=dev) for k in range(4)]
+    go = [torch.as_tensor(W.loss_weights((206, k), (3, 1080, 1920)), device=dev) for k in range(4)]
+    for k, o in enumerate(plan.sonar_out):
+        o["grad_polar"].copy_(gp[k % 4])
+    for k, o in enumerate(plan.camera_out):
+        o["grad_out"].copy_(go[k % 4])
+    log("C5 leg: %d + %d frames prepared in %.1f s" % (n_frames, n_frames, time.perf_counter() - t0))
+
+    def step():
+        plan.forward()
+        plan.backward()
+    n = max(3, steps // 20)
+    tf = median_time(torch, plan.forward, n, 2, 3)
+    ts = median_time(torch, step, n, 2, 3)
+    n_ret = sum(h.n for h in hits)
+    nb = n_frames * 2048 * 2048
+    npx = n_frames * 1920 * 1080
+    alg_f = 28 * n_ret + 4 * nb + 28 * npx
+    alg_s = alg_f + 28 * n_ret + 4 * nb + 44 * npx
+    log("C5 calibration scale, %d + %d frames: fwd %.3f ms (%.2f TB/s algorithmic, %.2f of 8 TB/s), fwd+bwd "
+        "%.3f ms (%.2f TB/s, %.2f), %.2f G returns/s, shape %s"
+        % (n_frames, n_frames, tf * 1e3, alg_f / tf / 1e12, alg_f / tf / 8e12, ts * 1e3, alg_s / ts / 1e12,
+           alg_s / ts / 8e12, n_ret / ts / 1e9, plan.shape()))
+    plan.close()
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -463,6 +520,9 @@ def main():
     torch.cuda.set_device(dev)
     if args.copy_calibration:
         copy_calibration(torch, dev)
+        return
+    if args.only == "c5":
+        calibration_leg(torch, dev, args.steps, args.c5_frames)
         return
     if args.only:
         legs = batched_legs(torch, dev, args.steps, only=args.only)
