@@ -152,6 +152,8 @@ __device__ __forceinline__ void write_fan_column(const SonarDev &f, int j) {
     cd[2 * j + 1] = cs;
 }
 
+constexpr int kTileLoads = 4;   // pair gathers in flight per thread of a forward tile
+
 // Forward polar tile `bid` of the launch (kBlock threads).
 template <class Src>
 __device__ __forceinline__ void tile_fwd_block(const Src &src, const oceansim_sonar_params *params, int bid) {
@@ -206,20 +208,29 @@ __device__ __forceinline__ void tile_fwd_block(const Src &src, const oceansim_so
         seg_end[tid] = incl;
         seg_start[tid] = s0 - (incl - len);   // pair index = seg_start[c] + flat index
         __syncthreads();
-        for (int k = tid; k < total; k += kBlock) {
-            // the segment holding flat index k: first c with seg_end[c] > k
-            int lo = 0, hi = kBlock - 1;
-            while (lo < hi) {
-                const int mid = (lo + hi) >> 1;
-                if (seg_end[mid] > k) hi = mid; else lo = mid + 1;
+        // kTileLoads pairs in flight per thread: the searches and gathers of a
+        // round are independent; indices past the end re-read the last pair
+        // (no masked loads) and are dropped before the accumulation
+        for (int k0 = 0; k0 < total; k0 += kBlock * kTileLoads) {
+            uint2 q[kTileLoads];
+#pragma unroll
+            for (int u = 0; u < kTileLoads; ++u) {
+                const int k = min(k0 + u * kBlock + tid, total - 1);
+                // the segment holding flat index k: first c with seg_end[c] > k
+                int c = 0;
+#pragma unroll
+                for (int s = kBlock / 2; s > 0; s >>= 1) c += seg_end[c + s - 1] <= k ? s : 0;
+                q[u] = gload(f.pairs + ((long long)(c0 + c) * f.chunk + seg_start[c] + k));
             }
-            const uint2 q = gload(f.pairs + ((long long)(c0 + lo) * f.chunk + seg_start[lo] + k));
-            if (q.x >= (uint32_t)nbins) continue;
-            const float I = __uint_as_float(q.y);
-            atomicAdd(&acc[q.x], I);
-            if (speckle && I != 0.0f) {
-                const unsigned bit = 1u << (q.x & 31);
-                if (!(atomicOr(&listed[q.x >> 5], bit) & bit)) list[atomicAdd(&n_listed, 1)] = (int)q.x;
+#pragma unroll
+            for (int u = 0; u < kTileLoads; ++u) {
+                if (k0 + u * kBlock + tid >= total || q[u].x >= (uint32_t)nbins) continue;
+                const float I = __uint_as_float(q[u].y);
+                atomicAdd(&acc[q[u].x], I);
+                if (speckle && I != 0.0f) {
+                    const unsigned bit = 1u << (q[u].x & 31);
+                    if (!(atomicOr(&listed[q[u].x >> 5], bit) & bit)) list[atomicAdd(&n_listed, 1)] = (int)q[u].x;
+                }
             }
         }
         __syncthreads();
