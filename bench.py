@@ -46,7 +46,7 @@ def parse():
     ap.add_argument("--only", choices=["c3", "c4", "c5"], default=None,
                     help="only build and run one batched leg (for profiler runs); prints no JSON line")
     ap.add_argument("--c5-frames", type=int, default=64,
-                    help="sonar and camera frames of the calibration-scale leg (--only c5)")
+                    help="sonar and camera frames of the calibration-scale leg")
     return ap.parse_args()
 
 
@@ -501,11 +501,16 @@ def calibration_leg(torch, dev, steps, n_frames):
     npx = n_frames * 1920 * 1080
     alg_f = 28 * n_ret + 4 * nb + 28 * npx
     alg_s = alg_f + 28 * n_ret + 4 * nb + 44 * npx
+    shape = plan.shape()
     log("C5 calibration scale, %d + %d frames: fwd %.3f ms (%.2f TB/s algorithmic, %.2f of 8 TB/s), fwd+bwd "
         "%.3f ms (%.2f TB/s, %.2f), %.2f G returns/s, shape %s"
         % (n_frames, n_frames, tf * 1e3, alg_f / tf / 1e12, alg_f / tf / 8e12, ts * 1e3, alg_s / ts / 1e12,
-           alg_s / ts / 8e12, n_ret / ts / 1e9, plan.shape()))
+           alg_s / ts / 8e12, n_ret / ts / 1e9, shape))
     plan.close()
+    return {"sonar_frames": n_frames, "camera_frames": n_frames, "returns": n_ret, "distinct_frames": 4,
+            "fwd_ms": tf * 1e3, "fwd_bwd_ms": ts * 1e3, "fwd_bwd_returns_per_s": n_ret / ts,
+            "fwd_alg_TBps": alg_f / tf / 1e12, "fwd_bwd_alg_TBps": alg_s / ts / 1e12,
+            "fwd_bwd_hbm_frac": alg_s / ts / (HBM_PEAK_GBS * 1e9), "autotuned_shape": shape}
 
 
 def main():
@@ -582,6 +587,7 @@ def main():
     extra = {}
     if not args.no_batched:
         extra = batched_legs(torch, dev, args.steps)
+        extra["calibration_c5"] = calibration_leg(torch, dev, args.steps, args.c5_frames)
     cpu = None
     if not args.no_cpu:
         log("timing the FP64 oracle on the host")
