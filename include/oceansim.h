@@ -276,7 +276,11 @@ enum {
  * the fan pixels that read it and their bilinear weights, from the same
  * stencils the fan kernel computes: one int per bin plus 8 bytes per
  * pixel-bin pair, on the order of 40 bytes per fan pixel), and its backward
- * gathers each bin's fan gradient through it.  The plan's forward saves no
+ * gathers each bin's fan gradient through it.  With an even fan width (at
+ * most 65535 x 65535 pixels) the two halves of the fan are exact mirror
+ * images, and the operator holds the bins of the first ceil(n_azimuth / 2)
+ * columns only: each also yields its mirror bin from the mirrored pixels
+ * (about 20 bytes per fan pixel).  The plan's forward saves no
  * stencils (a caller's own fan_stencil buffer is still written).  The
  * forward is the image formation of oceansim_sonar_render (Sec. III-A.2,
  * Eq. 2-6, and the fan) and oceansim_uw_form (Sec. III-A.1, Eq. 1); the
@@ -284,8 +288,8 @@ enum {
  * (bins), so order the two on one stream.
  *
  * OCEANSIM_PLAN_AUTOTUNE times the forward launch for a small set of tile
- * and chunk sizes (and, with a backward, the backward for 1, 2 and 4 polar
- * bins per thread) and keeps the fastest whose outputs agree with
+ * and chunk sizes (and, with a backward, the backward for 1, 2 and 4
+ * operator rows per thread) and keeps the fastest whose outputs agree with
  * the default shape's (1e-5 relative); results are cached per process and,
  * when the environment variable OCEANSIM_TUNE_CACHE names a file, in that
  * JSON file, keyed by GPU architecture, CU count and a size class of the
@@ -306,8 +310,9 @@ int oceansim_plan_create(const oceansim_sonar_frame *sonar, int32_t n_sonar,
 int oceansim_plan_forward(oceansim_plan *plan, void *stream);
 int oceansim_plan_backward(oceansim_plan *plan, void *stream);
 
-/* Launch shapes in use: {forward tile bins, returns per chunk, polar bins
- * per backward workgroup (0 without a sonar backward), graphs in use (0/1)}. */
+/* Launch shapes in use: {forward tile bins, returns per chunk, operator rows
+ * per backward workgroup (a row is a polar bin, or a bin and its mirror bin;
+ * 0 without a sonar backward), graphs in use (0/1)}. */
 int oceansim_plan_shape(const oceansim_plan *plan, int32_t shape[4]);
 
 /* Frees the plan's device memory and graphs (after synchronising the

@@ -230,7 +230,9 @@ int plan_sonar(const oceansim_sonar_frame *frames, int n_frames, int n_param_row
         d.blk[KRET] = ret_blocks;
         d.blk[KTILEB] = tile_b_blocks;
         d.blk[KFANT] = fant_blocks;
-        d.n_fant_blocks = backward ? (int)((nb + kBlock * fant_bpt - 1) / (kBlock * fant_bpt)) : 0;
+        d.ft_mirror = backward && fan_operator_layout(fr) == 2 ? 1 : 0;
+        const long long op_rows = d.ft_mirror ? (long long)fr.n_range * ((fr.n_azimuth + 1) / 2) : nb;
+        d.n_fant_blocks = backward ? (int)((op_rows + kBlock * fant_bpt - 1) / (kBlock * fant_bpt)) : 0;
         fant_blocks += d.n_fant_blocks;
         bin_blocks += d.n_chunks;
         tile_blocks += d.n_tiles;

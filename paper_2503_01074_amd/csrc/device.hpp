@@ -104,12 +104,17 @@ struct SonarDev {
     double sin_half_az, cos_half_az;
     int wide_cols;              // columns wider than 0.09 rad: offsets need the full arctangent
     float r_min_f, scale_r_f;
-    // Transposed fan operator (plans): the entries of bin b are
-    // ft_ent[ft_ptr[b] .. ft_ptr[b + 1]), each {fan pixel v * fan_w + u,
-    // bilinear weight as float bits}, in a fixed order.  nullptr: none.
+    // Transposed fan operator (plans): the entries of operator row h are
+    // ft_ent[ft_ptr[h] .. ft_ptr[h + 1]), each {fan pixel, bilinear weight as
+    // float bits}, in a fixed order.  Plain layout: row h is bin h, pixel
+    // v * fan_w + u.  Mirrored layout (ft_mirror, even fan width): row
+    // i * ceil(N_phi / 2) + j is bin (i, j) and also stands for its mirror
+    // bin (i, N_phi-1-j), whose entries are the same weights at the mirrored
+    // pixels (v, fan_w-1-u); pixel packed as (v << 16) | u.  nullptr: none.
     gptr<const int> ft_ptr;
     gptr<const uint2> ft_ent;
-    int n_fant_blocks;          // backward workgroups (kBlock * BPT bins each) through the transposed operator
+    int ft_mirror;
+    int n_fant_blocks;          // backward workgroups (kBlock * BPT operator rows each) through the operator
 };
 
 struct UwDev {

@@ -40,6 +40,18 @@ struct UwPlan {
     size_t bytes = 0, off_table = 0, off_part = 0, off_part_row = 0;
 };
 
+// Layout of a frame's transposed fan operator in a backward plan: 0 none (no
+// fan gradient), 1 one row per polar bin, 2 mirrored: with an even fan width
+// the fan's left and right halves are exact mirror images (pixel (v, u) and
+// (v, W-1-u) take mirrored stencils with bit-identical weights), so the bins
+// of the first ceil(N_phi / 2) columns carry the entries and bin (i, N_phi-1-j)
+// reads those of (i, j) at the mirrored pixels: half the operator bytes.
+// Pixels are then packed as (v << 16) | u, hence the 16-bit limits.
+inline int fan_operator_layout(const oceansim_sonar_frame &f) {
+    if (!f.fan || !f.grad_fan || f.fan_h <= 0 || f.fan_w <= 0) return 0;
+    return (f.fan_w % 2 == 0 && f.fan_w <= 65535 && f.fan_h <= 65535) ? 2 : 1;
+}
+
 int fail(int code, const char *fmt, ...);
 int ok();
 int hip_fail(hipError_t e, const char *what);

@@ -485,8 +485,8 @@ struct HostRec {
 };
 
 // Visits the entries of one frame's transposed operator in pixel order:
-// fn(bin, pixel, weight).  The corners and the mirror pixel follow the
-// backward tile kernel's reading of a saved stencil.
+// fn(bin, pixel row v, pixel column u, weight).  The corners and the mirror
+// pixel follow the backward tile kernel's reading of a saved stencil.
 template <class Fn>
 void for_each_entry(const oceansim_sonar_frame &f, const std::vector<HostRec> &recs, Fn fn) {
     const int W = f.fan_w, half_w = (f.fan_w + 1) / 2, n_az = f.n_azimuth;
@@ -505,12 +505,12 @@ void for_each_entry(const oceansim_sonar_frame &f, const std::vector<HostRec> &r
                 const int j0 = side == 0 || one_col ? r.j0 : n_az - 2 - r.j0;
                 float sw, omsw;
                 decode_code(side == 0 || one_col ? cl : -cl, sw, omsw);
-                const long long pix = (long long)v * W + (side == 0 ? u : um);
+                const int pu = side == 0 ? u : um;
                 for (int a = 0; a < (one_row ? 1 : 2); ++a) {
                     const double wa = a == 0 ? omt : t;
                     for (int c = 0; c < (one_col ? 1 : 2); ++c) {
                         const double wc = c == 0 ? omsw : sw;
-                        fn((long long)(r.i0 + a) * n_az + j0 + c, pix, (float)(wa * wc));
+                        fn((long long)(r.i0 + a) * n_az + j0 + c, v, pu, (float)(wa * wc));
                     }
                 }
             }
@@ -526,7 +526,11 @@ int build_fan_transposes(oceansim_plan *p, hipStream_t st) {
     p->fant_ent.assign(n, nullptr);
     std::vector<int> need;
     for (int i = 0; i < n; ++i)
-        if (p->sonar[i].fan && p->sonar[i].grad_fan && p->sonar[i].fan_stencil) need.push_back(i);
+        if (fan_operator_layout(p->sonar[i]) != 0) {
+            // the backward launch shapes assume an operator for every such frame
+            if (!p->sonar[i].fan_stencil) return fail(OCEANSIM_E_INVALID_ARG, "frame %d: no fan stencil", i);
+            need.push_back(i);
+        }
     if (need.empty()) return OCEANSIM_OK;
     SonarPlan fp;
     int rc = plan_sonar(p->sonar.data(), n, p->n_srows, p->n_mat, false, fp, nullptr, true);
@@ -548,30 +552,43 @@ int build_fan_transposes(oceansim_plan *p, hipStream_t st) {
     if (e == hipSuccess) e = hipStreamSynchronize(st);
     (void)hipFree(ws);
     if (e != hipSuccess) return hip_fail(e, "fan stencils");
-    // bin-major layout: counts, offsets, then the entries in pixel order
+    // row-major layout: counts, offsets, then the entries in pixel order
     std::vector<std::vector<int>> ptr(need.size());
     std::vector<std::vector<uint2>> ent(need.size());
     size_t bytes = 0;
     std::vector<size_t> off_ptr(need.size()), off_ent(need.size());
     for (size_t k = 0; k < need.size(); ++k) {
         const oceansim_sonar_frame &f = p->sonar[need[k]];
-        const long long nb = (long long)f.n_range * f.n_azimuth;
+        const bool mirror = fan_operator_layout(f) == 2;
+        const int n_az = f.n_azimuth, ncol = mirror ? (n_az + 1) / 2 : n_az;
+        const long long nrow = (long long)f.n_range * ncol;
+        // operator row of bin b; -1: a mirror bin, read through its partner
+        auto row_of = [&](long long b) -> long long {
+            if (!mirror) return b;
+            const long long i = b / n_az, j = b - i * n_az;
+            return j < ncol ? i * ncol + j : -1;
+        };
         std::vector<int> &P = ptr[k];
-        P.assign(nb + 1, 0);
+        P.assign(nrow + 1, 0);
         long long total = 0;
-        for_each_entry(f, recs[k], [&](long long b, long long, float) {
-            ++P[b + 1];
+        for_each_entry(f, recs[k], [&](long long b, int, int, float) {
+            const long long h = row_of(b);
+            if (h < 0) return;
+            ++P[h + 1];
             ++total;
         });
         if (total > INT32_MAX || (long long)f.fan_h * f.fan_w > INT32_MAX)
             return fail(OCEANSIM_E_UNSUPPORTED, "frame %d: fan operator too large", need[k]);
-        for (long long b = 0; b < nb; ++b) P[b + 1] += P[b];
+        for (long long h = 0; h < nrow; ++h) P[h + 1] += P[h];
         std::vector<int> cur(P.begin(), P.end() - 1);
         ent[k].resize((size_t)total);
-        for_each_entry(f, recs[k], [&](long long b, long long pix, float w) {
+        for_each_entry(f, recs[k], [&](long long b, int v, int u, float w) {
+            const long long h = row_of(b);
+            if (h < 0) return;
             uint32_t wb;
             std::memcpy(&wb, &w, 4);
-            ent[k][cur[b]++] = make_uint2((unsigned)pix, wb);
+            const unsigned pix = mirror ? ((unsigned)v << 16) | (unsigned)u : (unsigned)((long long)v * f.fan_w + u);
+            ent[k][cur[h]++] = make_uint2(pix, wb);
         });
         off_ptr[k] = bytes;
         bytes = (bytes + sizeof(int) * P.size() + kWsAlign - 1) / kWsAlign * kWsAlign;

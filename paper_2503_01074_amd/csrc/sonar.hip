@@ -22,6 +22,8 @@
 //               gather of the bin gradient at each return, then of gain,
 //               multiplicative speckle and Eq. (2) (alpha, gain, sigma_sm and
 //               reflectivity partial sums).
+#include <type_traits>
+
 #include "device.hpp"
 #include "launch.hpp"
 #include "reduce_body.hpp"
@@ -948,9 +950,13 @@ __global__ __launch_bounds__(kBlock) void k_ret_uw_bwd(Src src, const oceansim_s
 // to the wave's slice of LDS, and each lane then sums its own bins' runs.
 // More bins per thread amortise the workgroup's fixed costs (frame lookup,
 // pointer loads, partial sums) where there are many bins to share the chip.
+// With a mirrored operator (even fan width) a thread's rows are bins of the
+// left half of the azimuth columns: each entry is gathered at its pixel and
+// at the mirrored pixel, giving the row's bin and its mirror bin at once from
+// half the operator bytes.
 // ---------------------------------------------------------------------------
-constexpr int kFantChunks = 8;
-constexpr size_t kFuseLdsBytes = 16384;   // LDS of a return-gather workgroup that camera workgroups may share   // 64-entry chunks staged per round (512 entries per wave)
+constexpr int kFantChunks = 8;   // 64-entry chunks staged per round (512 entries per wave; mirrored: 256)
+constexpr size_t kFuseLdsBytes = 16384;   // LDS of a return-gather workgroup that camera workgroups may share
 
 template <class Src, int BPT>
 __global__ __launch_bounds__(kBlock) void k_fant_bwd(Src src, const oceansim_sonar_params *params, double *part,
@@ -962,52 +968,74 @@ __global__ __launch_bounds__(kBlock) void k_fant_bwd(Src src, const oceansim_son
     const SonarDev f = src.frame(fi);
     const int tid = threadIdx.x;
     const int lane = tid & (kWave - 1), wave = tid / kWave;
-    const int nb = f.n_range * f.n_az;
-    const int b0 = (local * kBlock + tid) * BPT;   // this thread's first bin
+    // operator rows: the bins, or (mirrored layout) the bins of the first
+    // ceil(N_phi / 2) columns, each also standing for its mirror bin
+    const bool mir = f.ft_mirror != 0 && f.ft_ptr;
+    const int ncol = mir ? (f.n_az + 1) >> 1 : f.n_az;
+    const int nrow = f.n_range * ncol;
+    const int h0 = (local * kBlock + tid) * BPT;   // this thread's first row
     // Loads first, without branches (indices clamped), so that they are in
     // flight together while the speckle factors are computed: the parameter
     // row (before any store, so it may come through the scalar cache), this
-    // lane's bins' operator pointers and the direct polar gradient.
+    // lane's rows' operator pointers and the direct polar gradient.
     const oceansim_sonar_params pr = params[f.param_row];
     // the wave's span of entries [w_lo, w_hi): uniform addresses, so scalar
     // loads, and the only ones the entry loads wait for
     const int wb = (local * kBlock + __builtin_amdgcn_readfirstlane(wave) * kWave) * BPT;
     int w_lo = 0, w_hi = 0;
     if (f.ft_ptr) {
-        w_lo = f.ft_ptr[wb < nb ? wb : nb];
-        w_hi = f.ft_ptr[wb + kWave * BPT < nb ? wb + kWave * BPT : nb];
+        w_lo = f.ft_ptr[wb < nrow ? wb : nrow];
+        w_hi = f.ft_ptr[wb + kWave * BPT < nrow ? wb + kWave * BPT : nrow];
     }
-    int p[BPT + 1];   // this lane's bins' entries start at p[0..BPT-1] and end at p[BPT]
+    int p[BPT + 1];   // this lane's rows' entries start at p[0..BPT-1] and end at p[BPT]
 #pragma unroll
-    for (int m = 0; m <= BPT; ++m) p[m] = f.ft_ptr ? f.ft_ptr[b0 + m < nb ? b0 + m : nb] : 0;
+    for (int m = 0; m <= BPT; ++m) p[m] = f.ft_ptr ? f.ft_ptr[h0 + m < nrow ? h0 + m : nrow] : 0;
+    // output bins: ob[m] is row m's own bin, ob[BPT + m] its mirror bin (-1:
+    // none, plain layout or a middle column that is its own mirror); -1 past
+    // the end
+    int ob[2 * BPT];
+    {
+        int i = h0 / ncol, j = h0 - i * ncol;
+#pragma unroll
+        for (int m = 0; m < BPT; ++m) {
+            const bool in = h0 + m < nrow;
+            const int jm = f.n_az - 1 - j;
+            ob[m] = in ? i * f.n_az + j : -1;
+            ob[BPT + m] = in && mir && jm != j ? i * f.n_az + jm : -1;
+            if (++j == ncol) {
+                j = 0;
+                ++i;
+            }
+        }
+    }
     // (without a polar gradient the load reads this frame's own gradient
     // buffer, a valid address, and the value is discarded: a select, not a
     // branch that would wait for the load)
-    float gpol[BPT];
+    float gpol[2 * BPT];
     {
         const bool has = f.grad_polar != nullptr;
         const gptr<const float> src_pol = has ? f.grad_polar : (gptr<const float>)f.grad_img;
 #pragma unroll
-        for (int m = 0; m < BPT; ++m) {
-            const float v = src_pol[b0 + m < nb ? b0 + m : nb - 1];
-            gpol[m] = has ? v : 0.0f;
+        for (int k = 0; k < 2 * BPT; ++k) {
+            const float v = src_pol[ob[k] >= 0 ? ob[k] : 0];
+            gpol[k] = has ? v : 0.0f;
         }
     }
     // the atomic reflectivity path (many materials) accumulates into a zeroed table
     if (grad_refl_zero)
         for (int k = bid * kBlock + tid; k < n_mat_zero; k += (int)gridDim.x * kBlock) grad_refl_zero[k] = 0.0f;
-    // per bin, the factors of the adjoint of Eq. (3)-(4): R E rho and phi^2;
-    // computed once, while the first round's gathers are in flight
-    float fac[BPT], phi2[BPT];
+    // per output bin, the factors of the adjoint of Eq. (3)-(4): R E rho and
+    // phi^2; computed once, while the first round's gathers are in flight
+    float fac[2 * BPT], phi2[2 * BPT];
     auto speckle_factors = [&]() {
         const AddCtx ctx{pr.sigma_sa, 1.0f / pr.sigma_phi};
         Words wd{0u, 0u, 0u, 0u};
         int wq = -1;
 #pragma unroll
-        for (int m = 0; m < BPT; ++m) {
-            const int b = b0 + m;
-            fac[m] = phi2[m] = 0.0f;
-            if (f.speckle != SPECKLE_OFF && b < nb) {
+        for (int k = 0; k < 2 * BPT; ++k) {
+            const int b = ob[k];
+            fac[k] = phi2[k] = 0.0f;
+            if (f.speckle != SPECKLE_OFF && b >= 0) {
                 // the bin's Philox word is the one its forward tile drew
                 if ((b >> 2) != wq) {
                     wq = b >> 2;
@@ -1016,25 +1044,28 @@ __global__ __launch_bounds__(kBlock) void k_fant_bwd(Src src, const oceansim_son
                 const int i = b / f.n_az, j = b - i * f.n_az;
                 float E, rho, R, phi;
                 additive_term(f, ctx, i, j, pick(wd, (uint32_t)(b & 3)), E, rho, R, phi);
-                fac[m] = R * E * rho;
-                phi2[m] = phi * phi;
+                fac[k] = R * E * rho;
+                phi2[k] = phi * phi;
             }
         }
     };
     bool have_factors = false;
-    double gs[BPT];
+    double gs[2 * BPT];
 #pragma unroll
-    for (int m = 0; m < BPT; ++m) gs[m] = 0.0;
-    if (f.ft_ptr) {
+    for (int k = 0; k < 2 * BPT; ++k) gs[k] = 0.0;
+    // Rounds of NC coalesced 64-entry chunks; MIR: each entry also gathers
+    // the mirrored pixel, whose products fill the slice's second half.
+    auto rounds = [&](auto nc, auto mirror) {
+        constexpr int NC = decltype(nc)::value;
+        constexpr bool MIR = decltype(mirror)::value;
         double *slice = prod[wave];
-        for (int r0 = w_lo; r0 < w_hi; r0 += kFantChunks * kWave) {
+        for (int r0 = w_lo; r0 < w_hi; r0 += NC * kWave) {
             // Every lane loads (past the end it re-reads the wave's last entry,
-            // whose product no bin sums): no branch in the unrolled loads, so
+            // whose product no row sums): no branch in the unrolled loads, so
             // all the chunk's loads, then all its gathers, are in flight together.
-            uint2 en[kFantChunks];
-            float gv[kFantChunks];
+            uint2 en[NC];
 #pragma unroll
-            for (int c = 0; c < kFantChunks; ++c) {
+            for (int c = 0; c < NC; ++c) {
                 const int e = r0 + c * kWave + lane;
                 en[c] = gload(f.ft_ent + (e < w_hi ? e : w_hi - 1));
             }
@@ -1042,17 +1073,30 @@ __global__ __launch_bounds__(kBlock) void k_fant_bwd(Src src, const oceansim_son
                 speckle_factors();
                 have_factors = true;
             }
+            float gv[NC], gm[NC];
 #pragma unroll
-            for (int c = 0; c < kFantChunks; ++c) gv[c] = f.grad_fan[(long long)en[c].x];
+            for (int c = 0; c < NC; ++c) {
+                if constexpr (MIR) {
+                    const unsigned u = en[c].x & 0xffffu;
+                    const unsigned row = __umul24(en[c].x >> 16, (unsigned)f.fan_w);   // < 2^31
+                    gv[c] = f.grad_fan[row + u];
+                    gm[c] = f.grad_fan[row + ((unsigned)f.fan_w - 1u - u)];
+                } else {
+                    gv[c] = f.grad_fan[(long long)en[c].x];
+                }
+            }
 #pragma unroll
-            for (int c = 0; c < kFantChunks; ++c)
-                slice[c * kWave + lane] = (double)__uint_as_float(en[c].y) * (double)gv[c];
+            for (int c = 0; c < NC; ++c) {
+                const double w = (double)__uint_as_float(en[c].y);
+                slice[c * kWave + lane] = w * (double)gv[c];
+                if constexpr (MIR) slice[(NC + c) * kWave + lane] = w * (double)gm[c];
+            }
             // the wave's own LDS writes, then its reads (no other wave touches the slice)
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
             __builtin_amdgcn_wave_barrier();
             __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
             const int a = p[0] > r0 ? p[0] : r0;
-            const int z = p[BPT] < r0 + kFantChunks * kWave ? p[BPT] : r0 + kFantChunks * kWave;
+            const int z = p[BPT] < r0 + NC * kWave ? p[BPT] : r0 + NC * kWave;
             for (int e = a; e < z; ++e) {
                 const double v = slice[e - r0];
                 int m = 0;
@@ -1060,26 +1104,37 @@ __global__ __launch_bounds__(kBlock) void k_fant_bwd(Src src, const oceansim_son
                 for (int k = 1; k < BPT; ++k) m += e >= p[k] ? 1 : 0;
 #pragma unroll
                 for (int k = 0; k < BPT; ++k) gs[k] += m == k ? v : 0.0;
+                if constexpr (MIR) {
+                    const double vm = slice[NC * kWave + e - r0];
+#pragma unroll
+                    for (int k = 0; k < BPT; ++k) gs[BPT + k] += m == k ? vm : 0.0;
+                }
             }
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
             __builtin_amdgcn_wave_barrier();
             __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
         }
+    };
+    if (f.ft_ptr) {
+        if (mir)
+            rounds(std::integral_constant<int, kFantChunks / 2>{}, std::true_type{});
+        else
+            rounds(std::integral_constant<int, kFantChunks>{}, std::false_type{});
     }
     if (!have_factors) speckle_factors();
     double g_sphi = 0.0, g_ssa = 0.0;
     const double dsphi = 0.5 * (double)pr.sigma_sa / ((double)pr.sigma_phi * (double)pr.sigma_phi);
 #pragma unroll
-    for (int m = 0; m < BPT; ++m) {
-        const int b = b0 + m;
-        if (b >= nb) break;
-        const double g = gs[m] + (double)gpol[m];
+    for (int k = 0; k < 2 * BPT; ++k) {
+        const int b = ob[k];
+        if (b < 0) continue;
+        const double g = gs[k] + (double)gpol[k];
         f.grad_img[b] = (float)g;
         // d add / d sigma_sa and d add / d sigma_phi of Eq. (3)-(4) (zero
         // factors without speckle)
-        const double t = g * (double)fac[m];
+        const double t = g * (double)fac[k];
         g_ssa += 0.5 * t;
-        g_sphi += t * dsphi * (double)phi2[m];
+        g_sphi += t * dsphi * (double)phi2[k];
     }
     __shared__ double red2[2 * (kBlock / kWave)];
     const double sums[2] = {g_sphi, g_ssa};

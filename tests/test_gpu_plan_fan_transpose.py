@@ -69,11 +69,13 @@ def _frame(st, Nr, Np, H, Wd, n, mode=W.SPECKLE_PAPER, frame_id=0, r_max=13.0):
 
 
 @pytest.mark.parametrize("shape", [(37, 29, 41, 83), (1, 17, 8, 16), (23, 1, 9, 9), (60, 40, 33, 64),
-                                   (300, 700, 64, 128)])
+                                   (300, 700, 64, 128), (24, 1, 10, 20), (2, 2, 12, 30)])
 @pytest.mark.parametrize("graph", [False, True])
 def test_plan_fan_transpose_vs_oracle(shape, graph):
-    """Odd fan width (a centre column that is its own mirror), one range row,
-    one azimuth column, more bins than fan pixels."""
+    """Odd fan width (a centre column that is its own mirror: plain operator
+    rows), even widths (mirrored rows) with an odd azimuth count (a middle
+    column that is its own mirror), one range row, one or two azimuth columns,
+    more bins than fan pixels."""
     Nr, Np, H, Wd = shape
     _say("plan fan transpose %s graph %s" % (shape, graph))
     st = W.Stream(8100, Nr + Np)
@@ -152,14 +154,15 @@ def test_plan_fan_transpose_nan_gradient():
 @pytest.mark.parametrize("n_frames,n_bins,block_bins", [(3, 1024, 512), (4, 2048, 1024)])
 def test_plan_fan_transpose_large_batches(n_frames, n_bins, block_bins):
     """Batches of many polar bins take two or four bins per thread (the
-    workgroup's wave spans then cover 128 or 256 bins and several chunks)."""
+    workgroup's wave spans then cover 128 or 256 bins and several chunks);
+    even and odd fan widths alternate (mirrored and plain operator rows)."""
     import paper_2503_01074_amd as osm
     _say("plan fan transpose: %d frames of %d x %d bins" % (n_frames, n_bins, n_bins))
     st = W.Stream(8500 + n_bins, n_frames)
     frames = []
     for k in range(n_frames):
         spec = W.SonarSpec(r_min=0.5, r_max=12.0 + k, n_range=n_bins, n_azimuth=n_bins + 8 * k, fan_h=150 + 10 * k,
-                           fan_w=301 + 20 * k, alpha=0.09, gain=1.2, sigma_phi=0.3, sigma_sa=0.15, sigma_sm=0.12,
+                           fan_w=300 + 21 * k, alpha=0.09, gain=1.2, sigma_phi=0.3, sigma_sa=0.15, sigma_sm=0.12,
                            speckle_mode=(W.SPECKLE_GAMMA, W.SPECKLE_PAPER, W.SPECKLE_OFF)[k % 3], gamma_k=3,
                            seed_lo=3, frame_id=k)
         frames.append(W.SonarFrame(spec, W.make_hits(st, spec, 3000, n_materials=5)))
