@@ -295,6 +295,8 @@ int plan_sonar(const oceansim_sonar_frame *frames, int n_frames, int n_param_row
     P.grid.fant_blocks = fant_blocks;
     P.grid.fant_bpt = fant_bpt;
     P.grid.use_fant = 0;
+    P.grid.fant_mirror = 0;
+    for (const SonarDev &d : P.dev) P.grid.fant_mirror |= d.ft_mirror;
     P.grid.all_saved = 1;
     for (int i = 0; i < n_frames; ++i)
         if (frames[i].grad_fan && !frames[i].fan_stencil) P.grid.all_saved = 0;

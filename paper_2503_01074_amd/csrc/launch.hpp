@@ -52,6 +52,7 @@ struct SonarGrid {
     int fant_blocks;     // backward workgroups of kBlock * fant_bpt bins over all frames (transposed fan operator)
     int fant_bpt;        // bins per thread of those workgroups: 1, 2 or 4
     int use_fant;        // backward through the frames' transposed fan operators instead of polar tiles
+    int fant_mirror;     // some frame's operator has the mirrored layout
 };
 
 constexpr int kBwdThreads = 512;   // threads of a backward polar-tile workgroup

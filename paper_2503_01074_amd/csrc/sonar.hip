@@ -958,7 +958,9 @@ __global__ __launch_bounds__(kBlock) void k_ret_uw_bwd(Src src, const oceansim_s
 constexpr int kFantChunks = 8;   // 64-entry chunks staged per round (512 entries per wave; mirrored: 256)
 constexpr size_t kFuseLdsBytes = 16384;   // LDS of a return-gather workgroup that camera workgroups may share
 
-template <class Src, int BPT>
+// MIRROR: the batch has mirrored operators (their rows produce two bins;
+// without any, the kernel keeps one output per row and fewer registers).
+template <class Src, int BPT, bool MIRROR>
 __global__ __launch_bounds__(kBlock) void k_fant_bwd(Src src, const oceansim_sonar_params *params, double *part,
                                                      int n_slots, float *grad_refl_zero, int n_mat_zero) {
     __shared__ double prod[kBlock / kWave][kFantChunks * kWave];
@@ -970,7 +972,8 @@ __global__ __launch_bounds__(kBlock) void k_fant_bwd(Src src, const oceansim_son
     const int lane = tid & (kWave - 1), wave = tid / kWave;
     // operator rows: the bins, or (mirrored layout) the bins of the first
     // ceil(N_phi / 2) columns, each also standing for its mirror bin
-    const bool mir = f.ft_mirror != 0 && f.ft_ptr;
+    constexpr int NO = MIRROR ? 2 * BPT : BPT;   // outputs per thread
+    const bool mir = MIRROR && f.ft_mirror != 0 && f.ft_ptr;
     const int ncol = mir ? (f.n_az + 1) >> 1 : f.n_az;
     const int nrow = f.n_range * ncol;
     const int h0 = (local * kBlock + tid) * BPT;   // this thread's first row
@@ -990,11 +993,11 @@ __global__ __launch_bounds__(kBlock) void k_fant_bwd(Src src, const oceansim_son
     int p[BPT + 1];   // this lane's rows' entries start at p[0..BPT-1] and end at p[BPT]
 #pragma unroll
     for (int m = 0; m <= BPT; ++m) p[m] = f.ft_ptr ? f.ft_ptr[h0 + m < nrow ? h0 + m : nrow] : 0;
-    // output bins: ob[m] is row m's own bin, ob[BPT + m] its mirror bin (-1:
+    // output bins: ob[m] is row m's own bin, ob[BPT + m] (MIRROR) its mirror bin (-1:
     // none, plain layout or a middle column that is its own mirror); -1 past
     // the end
-    int ob[2 * BPT];
-    {
+    int ob[MIRROR ? NO : 1];
+    if constexpr (MIRROR) {
         int i = h0 / ncol, j = h0 - i * ncol;
 #pragma unroll
         for (int m = 0; m < BPT; ++m) {
@@ -1008,16 +1011,22 @@ __global__ __launch_bounds__(kBlock) void k_fant_bwd(Src src, const oceansim_son
             }
         }
     }
+    // output bin k (plain rows are the bins themselves)
+    auto out_bin = [&](int k) __attribute__((always_inline)) -> int {
+        if constexpr (MIRROR) return ob[k];
+        else return h0 + k < nrow ? h0 + k : -1;
+    };
     // (without a polar gradient the load reads this frame's own gradient
     // buffer, a valid address, and the value is discarded: a select, not a
     // branch that would wait for the load)
-    float gpol[2 * BPT];
+    float gpol[NO];
     {
         const bool has = f.grad_polar != nullptr;
         const gptr<const float> src_pol = has ? f.grad_polar : (gptr<const float>)f.grad_img;
 #pragma unroll
-        for (int k = 0; k < 2 * BPT; ++k) {
-            const float v = src_pol[ob[k] >= 0 ? ob[k] : 0];
+        for (int k = 0; k < NO; ++k) {
+            const int bk = out_bin(k);
+            const float v = src_pol[bk >= 0 ? bk : 0];
             gpol[k] = has ? v : 0.0f;
         }
     }
@@ -1026,14 +1035,14 @@ __global__ __launch_bounds__(kBlock) void k_fant_bwd(Src src, const oceansim_son
         for (int k = bid * kBlock + tid; k < n_mat_zero; k += (int)gridDim.x * kBlock) grad_refl_zero[k] = 0.0f;
     // per output bin, the factors of the adjoint of Eq. (3)-(4): R E rho and
     // phi^2; computed once, while the first round's gathers are in flight
-    float fac[2 * BPT], phi2[2 * BPT];
-    auto speckle_factors = [&]() {
+    float fac[NO], phi2[NO];
+    auto speckle_factors = [&]() __attribute__((always_inline)) {
         const AddCtx ctx{pr.sigma_sa, 1.0f / pr.sigma_phi};
         Words wd{0u, 0u, 0u, 0u};
         int wq = -1;
 #pragma unroll
-        for (int k = 0; k < 2 * BPT; ++k) {
-            const int b = ob[k];
+        for (int k = 0; k < NO; ++k) {
+            const int b = out_bin(k);
             fac[k] = phi2[k] = 0.0f;
             if (f.speckle != SPECKLE_OFF && b >= 0) {
                 // the bin's Philox word is the one its forward tile drew
@@ -1050,12 +1059,12 @@ __global__ __launch_bounds__(kBlock) void k_fant_bwd(Src src, const oceansim_son
         }
     };
     bool have_factors = false;
-    double gs[2 * BPT];
+    double gs[NO];
 #pragma unroll
-    for (int k = 0; k < 2 * BPT; ++k) gs[k] = 0.0;
+    for (int k = 0; k < NO; ++k) gs[k] = 0.0;
     // Rounds of NC coalesced 64-entry chunks; MIR: each entry also gathers
     // the mirrored pixel, whose products fill the slice's second half.
-    auto rounds = [&](auto nc, auto mirror) {
+    auto rounds = [&](auto nc, auto mirror) __attribute__((always_inline)) {
         constexpr int NC = decltype(nc)::value;
         constexpr bool MIR = decltype(mirror)::value;
         double *slice = prod[wave];
@@ -1104,7 +1113,7 @@ __global__ __launch_bounds__(kBlock) void k_fant_bwd(Src src, const oceansim_son
                 for (int k = 1; k < BPT; ++k) m += e >= p[k] ? 1 : 0;
 #pragma unroll
                 for (int k = 0; k < BPT; ++k) gs[k] += m == k ? v : 0.0;
-                if constexpr (MIR) {
+                if constexpr (MIR && MIRROR) {
                     const double vm = slice[NC * kWave + e - r0];
 #pragma unroll
                     for (int k = 0; k < BPT; ++k) gs[BPT + k] += m == k ? vm : 0.0;
@@ -1117,7 +1126,7 @@ __global__ __launch_bounds__(kBlock) void k_fant_bwd(Src src, const oceansim_son
     };
     if (f.ft_ptr) {
         if (mir)
-            rounds(std::integral_constant<int, kFantChunks / 2>{}, std::true_type{});
+            rounds(std::integral_constant<int, kFantChunks / 2>{}, std::integral_constant<bool, MIRROR>{});
         else
             rounds(std::integral_constant<int, kFantChunks>{}, std::false_type{});
     }
@@ -1125,9 +1134,12 @@ __global__ __launch_bounds__(kBlock) void k_fant_bwd(Src src, const oceansim_son
     double g_sphi = 0.0, g_ssa = 0.0;
     const double dsphi = 0.5 * (double)pr.sigma_sa / ((double)pr.sigma_phi * (double)pr.sigma_phi);
 #pragma unroll
-    for (int k = 0; k < 2 * BPT; ++k) {
-        const int b = ob[k];
-        if (b < 0) continue;
+    for (int k = 0; k < NO; ++k) {
+        const int b = out_bin(k);
+        if (b < 0) {
+            if constexpr (MIRROR) continue;   // a missing mirror bin; later rows may follow
+            else break;                       // past the end
+        }
         const double g = gs[k] + (double)gpol[k];
         f.grad_img[b] = (float)g;
         // d add / d sigma_sa and d add / d sigma_phi of Eq. (3)-(4) (zero
@@ -1225,15 +1237,19 @@ static hipError_t launch_bwd(const Src &src, int n_frames, const SonarGrid &g,
     hipError_t e = hipSuccess;
     if (g.use_fant && g.fant_blocks > 0) {
         float *gz = lane_hist ? (float *)nullptr : grad_refl;
-        switch (g.fant_bpt) {
-            case 1: OSIM_LAUNCH("k_fant_bwd", (k_fant_bwd<Src, 1>), dim3(g.fant_blocks), dim3(kBlock), 0, st, src,
-                                params, part, n_slots, gz, n_mat); break;
-            case 2: OSIM_LAUNCH("k_fant_bwd", (k_fant_bwd<Src, 2>), dim3(g.fant_blocks), dim3(kBlock), 0, st, src,
-                                params, part, n_slots, gz, n_mat); break;
-            case 4: OSIM_LAUNCH("k_fant_bwd", (k_fant_bwd<Src, 4>), dim3(g.fant_blocks), dim3(kBlock), 0, st, src,
-                                params, part, n_slots, gz, n_mat); break;
+#define OSIM_FANT(B, M)                                                                                     \
+    OSIM_LAUNCH("k_fant_bwd", (k_fant_bwd<Src, B, M>), dim3(g.fant_blocks), dim3(kBlock), 0, st, src, params, \
+                part, n_slots, gz, n_mat)
+        switch (g.fant_bpt * 2 + (g.fant_mirror ? 1 : 0)) {
+            case 2: OSIM_FANT(1, false); break;
+            case 3: OSIM_FANT(1, true); break;
+            case 4: OSIM_FANT(2, false); break;
+            case 5: OSIM_FANT(2, true); break;
+            case 8: OSIM_FANT(4, false); break;
+            case 9: OSIM_FANT(4, true); break;
             default: return hipErrorInvalidValue;
         }
+#undef OSIM_FANT
         e = hipGetLastError();
         if (e != hipSuccess) return e;
     } else if (!g.use_fant && g.tile_b_blocks > 0) {
