@@ -8,7 +8,9 @@ load the library this script rebuilds.
 from __future__ import annotations
 
 import concurrent.futures as cf
+import json
 import os
+import re
 import subprocess
 import sys
 
@@ -39,14 +41,40 @@ def _stale(obj: str, src: str) -> bool:
     return any(os.path.getmtime(d) > t for d in deps)
 
 
+RESOURCE_KEYS = {"VGPRs": "vgprs", "ScratchSize [bytes/lane]": "scratch_bytes_per_lane",
+                 "Occupancy [waves/SIMD]": "waves_per_simd", "LDS Size [bytes/block]": "lds_bytes",
+                 "VGPRs Spill": "vgpr_spills"}
+
+
+def kernel_resources(remarks: str) -> dict:
+    """Per-kernel register, stack, occupancy and LDS figures from the
+    compiler's kernel-resource-usage remarks (device code built here)."""
+    out, cur = {}, None
+    for line in remarks.splitlines():
+        m = re.search(r"remark:\s+(.+?):\s+(\S+)\s+\[-Rpass-analysis", line)
+        if not m:
+            continue
+        key, val = m.group(1).strip(), m.group(2)
+        if key == "Function Name":
+            cur = out.setdefault(val, {})
+        elif cur is not None and key in RESOURCE_KEYS:
+            cur[RESOURCE_KEYS[key]] = int(val)
+    return out
+
+
 def _compile(src: str, force: bool) -> str:
     path = os.path.join(CSRC, src)
     obj = os.path.join(BUILD, src + ".o")
     if force or _stale(obj, path):
         cmd = [HIPCC] + FLAGS + ["-c", path, "-o", obj]
+        if src.endswith(".hip"):
+            cmd.append("-Rpass-analysis=kernel-resource-usage")
         r = subprocess.run(cmd, capture_output=True, text=True)
         if r.returncode != 0:
             raise RuntimeError("hipcc failed for %s:\n%s\n%s" % (src, r.stdout, r.stderr))
+        if src.endswith(".hip"):
+            with open(os.path.join(BUILD, src + ".resources.json"), "w") as fh:
+                json.dump(kernel_resources(r.stderr), fh, indent=1, sort_keys=True)
     return obj
 
 
