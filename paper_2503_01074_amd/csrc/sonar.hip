@@ -835,19 +835,48 @@ __device__ __forceinline__ void ret_bwd_block(const Src &src, const oceansim_son
         m_q[q] = -1;
         gr_q[q] = 0.0f;
     }
+    // Groups of RG returns: all their loads, then all their gathers, are in
+    // flight together (clamped indices, no masked loads: a load under a branch
+    // in the unrolled loop would wait for itself before the next return's)
+    constexpr int RG = R < 4 ? R : 4;
 #pragma unroll
-    for (int q = 0; q < R; ++q) {
-        const long long k = base + (long long)q * kBlock + tid;
-        if (k >= f.n) break;
-        const float xf = f.x[k], yf = f.y[k], zf = f.z[k];
-        const int m = f.mat[k];
-        double r;
-        const int b = return_bin(f, xf, yf, zf, m, n_mat, r);
+    for (int q0 = 0; q0 < R; q0 += RG) {
+    float xs[RG], ys[RG], zs[RG], nxs[RG], nys[RG], nzs[RG], gis[RG], rfs[RG];
+    int ms[RG], bs[RG];
+    double rs[RG];
+#pragma unroll
+    for (int u = 0; u < RG; ++u) {
+        const long long k = base + (long long)(q0 + u) * kBlock + tid;
+        const long long kc = k < f.n ? k : f.n - 1;
+        xs[u] = f.x[kc];
+        ys[u] = f.y[kc];
+        zs[u] = f.z[kc];
+        nxs[u] = f.nx[kc];
+        nys[u] = f.ny[kc];
+        nzs[u] = f.nz[kc];
+        ms[u] = f.mat[kc];
+    }
+#pragma unroll
+    for (int u = 0; u < RG; ++u) {
+        const long long k = base + (long long)(q0 + u) * kBlock + tid;
+        const int b = return_bin(f, xs[u], ys[u], zs[u], ms[u], n_mat, rs[u]);
+        bs[u] = k < f.n ? b : -1;   // a valid bin implies a valid material
+    }
+#pragma unroll
+    for (int u = 0; u < RG; ++u) {
+        gis[u] = f.grad_img[bs[u] >= 0 ? bs[u] : 0];   // dL / d(polar image) at the return's bin
+        rfs[u] = refl[bs[u] >= 0 ? ms[u] : 0];
+    }
+#pragma unroll
+    for (int u = 0; u < RG; ++u) {
+        const int q = q0 + u;
+        const int b = bs[u], m = ms[u];
         if (b < 0) continue;
+        const float xf = xs[u], yf = ys[u], zf = zs[u];
+        const double r = rs[u];
         float cosg, att;
-        const float I = return_intensity(f, xf, yf, zf, f.nx[k], f.ny[k], f.nz[k], r, refl[m],
-                                         pr.alpha, cosg, att);
-        const float gI_t = f.grad_img[b];          // dL / d(polar image) at this return's bin
+        const float I = return_intensity(f, xf, yf, zf, nxs[u], nys[u], nzs[u], r, rfs[u], pr.alpha, cosg, att);
+        const float gI_t = gis[u];
         float z = 0.0f;
         const float mult = speckle_factor(f, (uint32_t)b, pr.sigma_sm, &z);
         const double gIt = (double)gI_t;
@@ -863,6 +892,9 @@ __device__ __forceinline__ void ret_bwd_block(const Src &src, const oceansim_son
         } else {
             atomicAdd(&grad_refl_atomic[m], gr);
         }
+    }
+    // keep the next group's loads below this one (registers for one group)
+    __builtin_amdgcn_sched_barrier(0);
     }
     if (table) {
         __syncthreads();
