@@ -68,19 +68,44 @@ __device__ __forceinline__ void bin_block(const Src &src, const oceansim_sonar_p
     int tile[R], rank[R];
     uint32_t lbin[R];
     float inten[R];
+    // Groups of RG returns: all their loads, then their reflectivity gathers,
+    // are in flight together (clamped indices: a load under the per-return
+    // branches would wait for itself before the next return's)
+    constexpr int RG = R < 4 ? R : 4;
 #pragma unroll
-    for (int q = 0; q < R; ++q) {
-        const long long k = base + (long long)q * kBlock + tid;
-        tile[q] = -1;
-        if (k < f.n) {
-            const float xf = X[k], yf = Y[k], zf = Z[k];
-            const int m = MAT[k];
-            double r;
-            const int b = return_bin(f, xf, yf, zf, m, n_mat, r);
-            if (BO) BO[k] = b;
+    for (int q0 = 0; q0 < R; q0 += RG) {
+        float xs[RG], ys[RG], zs[RG], nxs[RG], nys[RG], nzs[RG], rfs[RG];
+        int ms[RG], bs[RG];
+        double rs[RG];
+#pragma unroll
+        for (int u = 0; u < RG; ++u) {
+            const long long k = base + (long long)(q0 + u) * kBlock + tid;
+            const long long kc = k < f.n ? k : f.n - 1;
+            xs[u] = X[kc];
+            ys[u] = Y[kc];
+            zs[u] = Z[kc];
+            nxs[u] = NX[kc];
+            nys[u] = NY[kc];
+            nzs[u] = NZ[kc];
+            ms[u] = MAT[kc];
+        }
+#pragma unroll
+        for (int u = 0; u < RG; ++u) {
+            const long long k = base + (long long)(q0 + u) * kBlock + tid;
+            const int b = return_bin(f, xs[u], ys[u], zs[u], ms[u], n_mat, rs[u]);
+            if (BO && k < f.n) BO[k] = b;
+            bs[u] = k < f.n ? b : -1;   // a valid bin implies a valid material
+        }
+#pragma unroll
+        for (int u = 0; u < RG; ++u) rfs[u] = RF[bs[u] >= 0 ? ms[u] : 0];
+#pragma unroll
+        for (int u = 0; u < RG; ++u) {
+            const int q = q0 + u, b = bs[u];
+            tile[q] = -1;
             if (b >= 0) {
                 float cosg, att;
-                inten[q] = return_intensity(f, xf, yf, zf, NX[k], NY[k], NZ[k], r, RF[m], alpha, cosg, att);
+                inten[q] = return_intensity(f, xs[u], ys[u], zs[u], nxs[u], nys[u], nzs[u], rs[u], rfs[u], alpha,
+                                            cosg, att);
                 const int i = b / f.n_az;
                 const int t = i / f.rows_per_tile;
                 tile[q] = t;
