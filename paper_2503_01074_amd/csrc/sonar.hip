@@ -70,8 +70,9 @@ __device__ __forceinline__ void bin_block(const Src &src, const oceansim_sonar_p
     float inten[R];
     // Groups of RG returns: all their loads, then their reflectivity gathers,
     // are in flight together (clamped indices: a load under the per-return
-    // branches would wait for itself before the next return's)
-    constexpr int RG = R < 4 ? R : 4;
+    // branches would wait for itself before the next return's); pairs for
+    // small chunks, whose workgroups share the launch with camera workgroups
+    constexpr int RG = R <= 4 ? 2 : 4;
 #pragma unroll
     for (int q0 = 0; q0 < R; q0 += RG) {
         float xs[RG], ys[RG], zs[RG], nxs[RG], nys[RG], nzs[RG], rfs[RG];
