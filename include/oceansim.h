@@ -285,7 +285,8 @@ enum {
  * forward is the image formation of oceansim_sonar_render (Sec. III-A.2,
  * Eq. 2-6, and the fan) and oceansim_uw_form (Sec. III-A.1, Eq. 1); the
  * backward is their adjoint and reads what the plan's latest forward left
- * (bins), so order the two on one stream.
+ * (bins), so order the two on one stream.  In a backward plan a frame's
+ * grad_fan needs its fan output (OCEANSIM_E_INVALID_ARG otherwise).
  *
  * OCEANSIM_PLAN_AUTOTUNE times the forward launch for a small set of tile
  * and chunk sizes (and, with a backward, the backward for 1, 2 and 4

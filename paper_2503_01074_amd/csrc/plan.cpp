@@ -661,6 +661,13 @@ int oceansim_plan_create(const oceansim_sonar_frame *sonar, int32_t n_sonar, con
         return fail(OCEANSIM_E_INVALID_ARG, "sonar gradient outputs are NULL");
     if (bwd && n_camera > 0 && !grad_water_params_dev)
         return fail(OCEANSIM_E_INVALID_ARG, "water gradient output is NULL");
+    // a backward plan gathers the fan gradient through the operator it builds
+    // from the frame's rendered fan: a fan gradient needs the fan output
+    if (bwd)
+        for (int i = 0; i < n_sonar; ++i)
+            if (sonar[i].grad_fan && !sonar[i].fan)
+                return fail(OCEANSIM_E_INVALID_ARG, "frame %d: a backward plan reads grad_fan only with the fan output",
+                            i);
     hipStream_t st = static_cast<hipStream_t>(stream);
 
     oceansim_plan *p = new oceansim_plan;

@@ -223,6 +223,8 @@ def test_plan_rejections():
     assert create(sonar=(good, _frame(lib, n_range=0))) == -2
     assert "frame 1" in lib.last_error()
     assert create(sonar=(_frame(lib, param_row=3),)) == -1
+    assert create(sonar=(good, _frame(lib, grad_fan=FAKE, fan=0))) == -1   # fan gradient without the fan
+    assert "frame 1" in lib.last_error()
     assert create(sonar=(), camera=(_uw(lib, H=0, grad_out=FAKE),)) == -2
     assert create(sonar=(), camera=(_uw(lib),)) == -1                 # backward needs grad_out
     assert so.oceansim_plan_forward(None, None) == -1
