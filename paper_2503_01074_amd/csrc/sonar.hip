@@ -12,8 +12,14 @@
 //           streams the tile out row-major.
 //   k_fan   one thread per mirror pair of fan pixels: FP64 polar coordinates,
 //           bilinear interpolation of the polar image.
+//   k_bin_uw    (plans with camera frames) k_bin plus the camera forward.
 // Backward, per frame:
-//   k_tile_bwd  one workgroup per polar tile: transpose of the fan as a gather
+//   k_fant_bwd  (plans) rows of the transposed fan operator built at plan
+//               creation: each bin's fan gradient gathered through its
+//               entries in FP64 (a mirrored row yields a bin and its mirror
+//               bin), plus the polar gradient; adjoint of the additive
+//               speckle term (sigma_phi, sigma_sa partial sums).
+//   k_tile_bwd  (plain entry points) one workgroup per polar tile: transpose of the fan as a gather
 //               of the fan pixels whose stencil touches the tile, accumulated
 //               in LDS in 64-bit fixed point (order-independent, so the sums
 //               are bit-reproducible), plus the polar gradient; adjoint of the
@@ -22,6 +28,7 @@
 //               gather of the bin gradient at each return, then of gain,
 //               multiplicative speckle and Eq. (2) (alpha, gain, sigma_sm and
 //               reflectivity partial sums).
+//   k_ret_uw_bwd  (plans with camera frames) k_ret_bwd plus the camera backward.
 #include <type_traits>
 
 #include "device.hpp"
