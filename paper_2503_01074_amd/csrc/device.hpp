@@ -60,12 +60,6 @@ __device__ __forceinline__ void gstore_stream(gptr<float4> p, float4 v) {
     __builtin_nontemporal_store(f32x4_t{v.x, v.y, v.z, v.w}, (gptr<f32x4_t>)p);
 }
 __device__ __forceinline__ void gstore_stream(gptr<float> p, float v) { __builtin_nontemporal_store(v, p); }
-// Non-temporal load, for inputs read once that no later kernel reads (the
-// loss gradients): they do not displace lines the next kernels reuse.
-__device__ __forceinline__ float4 gload_stream(gptr<const float4> p) {
-    const f32x4_t v = __builtin_nontemporal_load((gptr<const f32x4_t>)p);
-    return make_float4(v.x, v.y, v.z, v.w);
-}
 
 // --------------------------------------------------------------------------
 // One sonar frame as the kernels see it.  Built on the host from the public

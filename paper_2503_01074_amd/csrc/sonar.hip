@@ -1091,7 +1091,7 @@ __global__ __launch_bounds__(kBlock) void k_fant_bwd(Src src, const oceansim_son
 #pragma unroll
         for (int k = 0; k < NO; ++k) {
             const int bk = out_bin(k);
-            const float v = __builtin_nontemporal_load(&src_pol[bk >= 0 ? bk : 0]);   // read once
+            const float v = src_pol[bk >= 0 ? bk : 0];
             gpol[k] = has ? v : 0.0f;
         }
     }

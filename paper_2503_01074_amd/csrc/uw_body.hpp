@@ -176,7 +176,7 @@ __device__ __forceinline__ void uw_bwd_block(const Src &src, const oceansim_wate
 #pragma unroll
                 for (int c = 0; c < 3; ++c) {
                     J[h][c] = gload((gptr<const float4>)(Jp + c * npix + p));
-                    g[h][c] = gload_stream((gptr<const float4>)(Gp + c * npix + p));   // read once
+                    g[h][c] = gload((gptr<const float4>)(Gp + c * npix + p));
                 }
             }
 #pragma unroll
