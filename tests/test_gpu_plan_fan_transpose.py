@@ -151,20 +151,27 @@ def test_plan_fan_transpose_nan_gradient():
     assert np.isnan(o_par).any()
 
 
-@pytest.mark.parametrize("n_frames,n_bins,block_bins,mixed", [(3, 1024, 512, True), (4, 2048, 1024, True),
-                                                               (3, 1024, 512, False), (4, 2048, 1024, False)])
-def test_plan_fan_transpose_large_batches(n_frames, n_bins, block_bins, mixed):
+@pytest.mark.parametrize("n_frames,n_bins,block_bins,mixed,odd_az", [(3, 1024, 512, True, False),
+                                                                      (4, 2048, 1024, True, False),
+                                                                      (3, 1024, 512, False, False),
+                                                                      (4, 2048, 1024, False, False),
+                                                                      (3, 1024, 512, True, True),
+                                                                      (4, 2048, 1024, True, True)])
+def test_plan_fan_transpose_large_batches(n_frames, n_bins, block_bins, mixed, odd_az):
     """Batches of many polar bins take two or four rows per thread (the
     workgroup's wave spans then cover 128 or 256 rows and several chunks);
     even and odd fan widths alternate (mirrored and plain operator rows in one
     launch), or all widths are odd (plain rows only: the kernel without
-    mirror outputs)."""
+    mirror outputs); with odd azimuth counts a thread's mirrored rows wrap
+    from one range row to the next around a middle column that is its own
+    mirror."""
     import paper_2503_01074_amd as osm
-    _say("plan fan transpose: %d frames of %d x %d bins, mixed layouts %s" % (n_frames, n_bins, n_bins, mixed))
+    _say("plan fan transpose: %d frames of %d x %d bins, mixed layouts %s, odd azimuth counts %s"
+         % (n_frames, n_bins, n_bins, mixed, odd_az))
     st = W.Stream(8500 + n_bins, n_frames)
     frames = []
     for k in range(n_frames):
-        spec = W.SonarSpec(r_min=0.5, r_max=12.0 + k, n_range=n_bins, n_azimuth=n_bins + 8 * k, fan_h=150 + 10 * k,
+        spec = W.SonarSpec(r_min=0.5, r_max=12.0 + k, n_range=n_bins, n_azimuth=n_bins + 8 * k + (1 if odd_az else 0), fan_h=150 + 10 * k,
                            fan_w=300 + 21 * k if mixed else 301 + 20 * k, alpha=0.09, gain=1.2, sigma_phi=0.3, sigma_sa=0.15, sigma_sm=0.12,
                            speckle_mode=(W.SPECKLE_GAMMA, W.SPECKLE_PAPER, W.SPECKLE_OFF)[k % 3], gamma_k=3,
                            seed_lo=3, frame_id=k)
