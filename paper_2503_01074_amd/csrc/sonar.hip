@@ -356,6 +356,40 @@ __global__ __launch_bounds__(kBlock) void k_fan(Src src) {
     const gptr<const float> __restrict__ polar = f.polar;
     const gptr<float> __restrict__ fan = f.fan;
     const int um = f.fan_w - 1 - u;
+    {
+        // A tile wholly outside the sector (nearest corner beyond r_max,
+        // farthest within r_min, or every pixel beyond the edge azimuth, with
+        // a relative margin far above rounding so that no pixel's own test
+        // could pass) only writes its zeros: the same outputs, without the
+        // geometry or the column-table loads.
+        const int u_lo = col * kFanTileU, u_hi = min(u_lo + kFanTileU, f.half_w) - 1;
+        const int v_lo = g * kFanTileV, v_hi = min(v_lo + kFanTileV, f.fan_h) - 1;
+        const double ax_min = (0.5 * (double)f.fan_w - (double)u_hi - 0.5) * f.fan_s;
+        const double ax_max = (0.5 * (double)f.fan_w - (double)u_lo - 0.5) * f.fan_s;
+        const double yc_min = ((double)f.fan_h - (double)v_hi - 0.5) * f.fan_s;
+        const double yc_max = ((double)f.fan_h - (double)v_lo - 0.5) * f.fan_s;
+        const double near2 = ax_min * ax_min + yc_min * yc_min, far2 = ax_max * ax_max + yc_max * yc_max;
+        const double edge_l = ax_min * f.cos_half_az, edge_r = yc_max * f.sin_half_az;
+        const bool outside = near2 > f.r_max * f.r_max * (1.0 + 1e-9) || far2 < f.r_min * f.r_min * (1.0 - 1e-9) ||
+                             edge_l - edge_r > 1e-9 * (edge_l + edge_r);
+        if (outside) {
+            gptr<float> row = fan + (long long)v0 * f.fan_w;
+            gptr<int4> rec = f.stencil ? f.stencil + (long long)v0 * f.half_w + u : nullptr;
+#pragma unroll
+            for (int r = 0; r < kFanRows; ++r) {
+                if (v0 + 8 * r < f.fan_h) {
+                    if (IMAGE) {
+                        row[u] = 0.0f;
+                        if (um != u) row[um] = 0.0f;
+                    }
+                    if (rec) gstore(rec, make_int4(-1, 0, 0, 0));
+                }
+                row += 8LL * f.fan_w;
+                if (rec) rec += 8LL * f.half_w;
+            }
+            return;
+        }
+    }
     // left-half pixel (v, u) and its mirror W-1-u: exact offsets from the apex
     const double ax = (0.5 * (double)f.fan_w - (double)u - 0.5) * f.fan_s;   // = -x_c >= 0
     const double ax2 = ax * ax;
