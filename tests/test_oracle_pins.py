@@ -303,6 +303,19 @@ def test_fan_adjoint_identity():
     assert (fan * y).sum() == pytest.approx((x * gx).sum(), rel=1e-12)
 
 
+def test_fan_adjoint_mirror_symmetry():
+    """The transpose of the fan commutes with the left-right mirror: the fan
+    gradient mirrored across the image gives the polar gradient mirrored in
+    azimuth (the property that lets one operator row serve a bin and its
+    mirror bin)."""
+    cfg = _cfg(FAN_SPEC)
+    y = Stream(4, 5).uniform(-1, 1, (96, 160))
+    gx = oracle.fan_adjoint(cfg, y)
+    gxm = oracle.fan_adjoint(cfg, y[:, ::-1].copy())
+    np.testing.assert_allclose(gx[:, ::-1], gxm, rtol=1e-12, atol=1e-14)
+    assert np.abs(gx).max() > 0
+
+
 # --------------------------------------------------------------------------- #
 # Camera, Eq. (1)                                                             #
 # --------------------------------------------------------------------------- #
