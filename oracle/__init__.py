@@ -61,6 +61,7 @@ class _Cfg(C.Structure):
         ("speckle_mode", C.c_int32), ("gamma_k", C.c_int32),
         ("seed_lo", C.c_uint32), ("seed_hi", C.c_uint32), ("frame_id", C.c_uint32),
         ("fan_band", C.c_double),
+        ("range_norm", C.c_int32),
     ]
 
 
@@ -127,6 +128,7 @@ class SonarConfig:
     seed_hi: int = 0
     frame_id: int = 0
     fan_band: float = 1e-6
+    range_norm: int = 0
 
     @classmethod
     def from_spec(cls, spec, **over) -> "SonarConfig":

@@ -19,13 +19,16 @@
  *   - Additive speckle: Eq. (3)-(4); multiplicative speckle: Eq. (5)-(6).
  *   - 130 deg / 20 deg field of view defaults: Sec. III-A.2, last paragraph.
  * Readings where the paper is silent (gain, two-way path factor, gamma
- * speckle, RNG counter layout, fan geometry) are listed in the design notes
+ * speckle, RNG counter layout, fan geometry, range-wise normalisation) are listed in the design notes
  * and restated at each function below.
  *
  * Parity status per function:
  *   orc_philox4x32_10   pinned (published known-answer vectors)
- *   orc_sonar_forward   pinned (closed forms, brute-force bins, moments)
- *   orc_sonar_backward  pinned (FP64 central differences of the forward)
+ *   orc_sonar_forward   pinned (closed forms, brute-force bins, moments;
+ *                       range-wise normalisation: row peaks, empty and
+ *                       negative rows, gain and scale invariance)
+ *   orc_sonar_backward  pinned (FP64 central differences of the forward,
+ *                       with and without the range-wise normalisation)
  *   orc_fan_forward     pinned (constant / linear fields, symmetry)
  *   orc_fan_adjoint     pinned (adjoint identity against orc_fan_forward)
  *   orc_uw_forward      pinned (Eq. 1 special cases)
@@ -107,6 +110,7 @@ typedef struct {
     int32_t gamma_k;       /* shape of the gamma speckle (integer 1..8)     */
     uint32_t seed_lo, seed_hi, frame_id;
     double fan_band;       /* ambiguity band, in units of the pixel size    */
+    int32_t range_norm;    /* 1: range-wise normalisation after the gain    */
 } orc_sonar_cfg;
 
 /* ------------------------------------------------------------------------- */
@@ -359,6 +363,28 @@ void orc_fan_adjoint(const orc_sonar_cfg *c, const double *g_fan, double *g_img)
 /* Any output pointer may be NULL.  refl has n_mat entries; a material id at */
 /* or beyond n_mat is treated as a miss.  Returns 0.                         */
 /* ------------------------------------------------------------------------- */
+/* ------------------------------------------------------------------------- */
+/* Range-wise normalisation (Sec. III-A.2 mentions normalising the binned    */
+/* image range by range and gives no formula).  Reading: after the gain and  */
+/* before the speckle, each range row i of Q = G P is divided by its maximum */
+/* over azimuth, m_i = max_j Q_ij, when m_i > 0; a row whose maximum is 0 or */
+/* negative (an empty row in particular) is left as it is.  NaN entries are  */
+/* skipped by the maximum.  j*_i is the first column attaining m_i: the      */
+/* subgradient of the maximum is taken there.                                */
+/* ------------------------------------------------------------------------- */
+static void orc_row_max(const double *Q, int n, double *m, int *jstar)
+{
+    double best = -INFINITY;
+    int at = -1;
+    for (int j = 0; j < n; ++j)
+        if (Q[j] > best) {
+            best = Q[j];
+            at = j;
+        }
+    *m = best;
+    *jstar = at;
+}
+
 int orc_sonar_forward(const orc_sonar_cfg *c, int64_t n,
                       const float *x, const float *y, const float *z,
                       const float *nx, const float *ny, const float *nz,
@@ -390,13 +416,25 @@ int orc_sonar_forward(const orc_sonar_cfg *c, int64_t n,
     for (int64_t b = 0; b < nb; ++b) Pw[b] = 0.0;
     for (int64_t k = 0; k < n; ++k)
         if (bk[k] >= 0) Pw[bk[k]] += Ik[k];
-    /* steps 3-4 */
+    /* step 3: gain, then (optionally) the range-wise normalisation; the
+       normalised image goes through Ow */
+    for (int64_t b = 0; b < nb; ++b) Ow[b] = c->gain * Pw[b];
+    if (c->range_norm)
+        for (int i = 0; i < c->n_range; ++i) {
+            double *row = Ow + (int64_t)i * c->n_azimuth;
+            double m;
+            int js;
+            orc_row_max(row, c->n_azimuth, &m, &js);
+            if (m > 0.0)
+                for (int j = 0; j < c->n_azimuth; ++j) row[j] /= m;
+        }
+    /* step 4 */
 #pragma omp parallel for schedule(static)
     for (int64_t b = 0; b < nb; ++b) {
         int i = (int)(b / c->n_azimuth), j = (int)(b % c->n_azimuth);
         double add, mul;
         orc_speckle_terms(c, i, j, &add, &mul, NULL, NULL);
-        double Q = c->gain * Pw[b];
+        double Q = Ow[b];
         Ow[b] = (c->speckle_mode == ORC_SPECKLE_OFF) ? Q : Q * mul + add;
     }
     /* step 5 */
@@ -467,13 +505,31 @@ int orc_sonar_backward(const orc_sonar_cfg *c, int64_t n,
             for (int64_t b = 0; b < nb; ++b) gOa[b] += fabs(g_polar[b]);
     }
 
-    /* adjoint of steps 3-4 (gPa: magnitude sum of each bin's gP) */
+    /* the normalisation of step 3: per row, the maximum and where it is
+       (scale[i] = 1 / m_i for a normalised row, else 1) */
+    double *scale = (double *)malloc(sizeof(double) * c->n_range);
+    int *jst = (int *)malloc(sizeof(int) * c->n_range);
+    {
+        double *row = (double *)malloc(sizeof(double) * c->n_azimuth);
+        for (int i = 0; i < c->n_range; ++i) {
+            for (int j = 0; j < c->n_azimuth; ++j) row[j] = c->gain * P[(int64_t)i * c->n_azimuth + j];
+            double m;
+            orc_row_max(row, c->n_azimuth, &m, &jst[i]);
+            scale[i] = (c->range_norm && m > 0.0) ? 1.0 / m : 1.0;
+            if (!(c->range_norm && m > 0.0)) jst[i] = -1;
+        }
+        free(row);
+    }
+
+    /* adjoint of step 4: gN[b] = dL/d(normalised image) (gNa: magnitude sums) */
+    double *gN = (double *)malloc(sizeof(double) * nb);
+    double *gNa = gOa ? (double *)malloc(sizeof(double) * nb) : NULL;
     double *gPa = gOa ? (double *)malloc(sizeof(double) * nb) : NULL;
     double gG = 0.0, gsphi = 0.0, gssa = 0.0, gssm = 0.0;
     double aG = 0.0, asphi = 0.0, assa = 0.0, assm = 0.0, aalpha = 0.0;
     for (int64_t b = 0; b < nb; ++b) {
         int i = (int)(b / c->n_azimuth), j = (int)(b % c->n_azimuth);
-        double Q = c->gain * P[b];
+        double Q = c->gain * P[b] * scale[i];   /* the (normalised) image the speckle acts on */
         double ga = gOa ? gOa[b] : 0.0;   /* magnitude sum of gO[b] */
         double gQ, mulv = 1.0;
         if (c->speckle_mode == ORC_SPECKLE_OFF) {
@@ -498,11 +554,36 @@ int orc_sonar_backward(const orc_sonar_cfg *c, int64_t n,
                 assm += ga * fabs(Q * gauss);
             }
         }
-        gG += gQ * P[b];
-        aG += ga * fabs(mulv * P[b]);
-        gP[b] = c->gain * gQ;
-        if (gPa) gPa[b] = ga * fabs(c->gain * mulv);
+        gN[b] = gQ;
+        if (gNa) gNa[b] = ga * fabs(mulv);
     }
+    /* adjoint of step 3: a normalised row N_j = Q_j / Q_j* gives
+       dL/dQ_k = gN_k / m - [k = j*] sum_j gN_j Q_j / m^2; then Q = G P */
+    for (int i = 0; i < c->n_range; ++i) {
+        const int64_t r0 = (int64_t)i * c->n_azimuth;
+        double S = 0.0, Sa = 0.0;
+        if (jst[i] >= 0)
+            for (int j = 0; j < c->n_azimuth; ++j) {
+                S += gN[r0 + j] * (c->gain * P[r0 + j]);
+                if (gNa) Sa += gNa[r0 + j] * fabs(c->gain * P[r0 + j]);
+            }
+        for (int j = 0; j < c->n_azimuth; ++j) {
+            const int64_t b = r0 + j;
+            double gQ = gN[b] * scale[i], gQa = gNa ? gNa[b] * fabs(scale[i]) : 0.0;
+            if (j == jst[i]) {
+                gQ -= S * scale[i] * scale[i];
+                gQa += Sa * scale[i] * scale[i];
+            }
+            gG += gQ * P[b];
+            aG += gQa * fabs(P[b]);
+            gP[b] = c->gain * gQ;
+            if (gPa) gPa[b] = gQa * fabs(c->gain);
+        }
+    }
+    free(gN);
+    free(gNa);
+    free(scale);
+    free(jst);
 
     /* adjoint of steps 1-2: each return reads the gradient of its bin */
     double galpha = 0.0;

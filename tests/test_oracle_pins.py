@@ -387,6 +387,90 @@ def test_sonar_backward_matches_central_differences(mode):
         assert g_refl[m] == pytest.approx(want, rel=1e-6, abs=1e-9)
 
 
+# --------------------------------------------------------------------------- #
+# Range-wise normalisation (Sec. III-A.2, no formula given; the reading:     #
+# after the gain, each range row over its maximum when that is positive)     #
+# --------------------------------------------------------------------------- #
+def _norm_frame(seed, n=900, mode=SPECKLE_OFF):
+    st = Stream(60 + seed, mode)
+    spec = SonarSpec(r_min=0.5, r_max=8.0, n_range=30, n_azimuth=24, fan_h=40, fan_w=64,
+                     alpha=0.13, gain=1.4, sigma_phi=0.35, sigma_sa=0.15, sigma_sm=0.12,
+                     speckle_mode=mode, gamma_k=4, seed_lo=9, frame_id=2, range_norm=1)
+    hits = make_hits(st, spec, n, n_materials=6)
+    return spec, hits
+
+
+def _rows_emptied_and_negated(spec, hits, empty=(3, 7), negative=(5, 11)):
+    """Per-return reflectivities; the returns of some rows made misses, those
+    of others given negative reflectivities."""
+    rows = oracle.sonar_forward(_cfg(spec, range_norm=0), hits, hits.refl)["bins"] // spec.n_azimuth
+    hits.mat = np.where(np.isin(rows, empty), -1, np.arange(len(rows))).astype(np.int32)
+    refl = np.abs(Stream(77, 1).uniform(0.2, 1.0, len(rows))).astype(np.float32)
+    hits.refl = np.where(np.isin(rows, negative), -refl, refl).astype(np.float32)
+    return hits
+
+
+def test_range_norm_rows_peak_at_one():
+    """Speckle off: every row with a positive maximum peaks at exactly 1 and
+    keeps its shape; empty rows stay 0; the gain and a common scale of the
+    reflectivities cancel."""
+    spec, hits = _norm_frame(1)
+    hits = _rows_emptied_and_negated(spec, hits, negative=())
+    out = oracle.sonar_forward(_cfg(spec), hits, hits.refl)["out"]
+    raw = oracle.sonar_forward(_cfg(spec, range_norm=0), hits, hits.refl)["out"]
+    pos = raw.max(axis=1) > 0
+    assert pos.sum() > 10 and (~pos).sum() > 0          # some rows are empty (returns cover part of the range)
+    np.testing.assert_array_equal(out[pos].max(axis=1), 1.0)
+    assert np.all(out[~pos] == 0.0)
+    # each normalised row is a positive multiple of the raw row
+    ratio = raw[pos].max(axis=1) / out[pos].max(axis=1)
+    np.testing.assert_allclose(out[pos] * ratio[:, None], raw[pos], rtol=1e-12, atol=1e-300)
+    out2 = oracle.sonar_forward(_cfg(spec, gain=3.7), hits, (hits.refl * 4.0).astype(np.float32))["out"]
+    np.testing.assert_allclose(out2, out, rtol=1e-12, atol=1e-15)
+
+
+def test_range_norm_leaves_negative_rows():
+    """Signed reflectivities: a row whose maximum is 0 or negative is left
+    as it is; the others peak at 1."""
+    spec, hits = _norm_frame(2)
+    hits = _rows_emptied_and_negated(spec, hits)
+    out = oracle.sonar_forward(_cfg(spec), hits, hits.refl)["out"]
+    raw = oracle.sonar_forward(_cfg(spec, range_norm=0), hits, hits.refl)["out"]
+    neg = (raw.max(axis=1) <= 0) & (raw.min(axis=1) < 0)
+    pos = raw.max(axis=1) > 0
+    assert neg.sum() > 0 and pos.sum() > 0
+    np.testing.assert_array_equal(out[neg], raw[neg])
+    np.testing.assert_array_equal(out[pos].max(axis=1), 1.0)
+
+
+@pytest.mark.parametrize("mode", [SPECKLE_OFF, SPECKLE_PAPER, SPECKLE_GAMMA])
+def test_range_norm_backward_matches_central_differences(mode):
+    """The subgradient at each row's maximum matches central differences
+    (the maxima are unique, and the steps are too small to move them)."""
+    spec, hits = _norm_frame(3, mode=mode)
+    st = Stream(70, mode)
+    wp = st.normal((30, 24))
+    wf = st.normal((40, 64))
+    refl = hits.refl.astype(np.float64)
+    g_refl, g_par, _ = oracle.sonar_backward(_cfg(spec), hits, hits.refl, wp, wf)
+    for k, name in enumerate(["alpha", "gain", "sigma_phi", "sigma_sa", "sigma_sm"]):
+        x0 = float(getattr(spec, name))
+        h = 1e-6 * max(1.0, abs(x0))
+        want = (_sonar_loss(spec, hits, hits.refl, wp, wf, **{name: x0 + h}) -
+                _sonar_loss(spec, hits, hits.refl, wp, wf, **{name: x0 - h})) / (2 * h)
+        assert g_par[k] == pytest.approx(want, rel=1e-6, abs=1e-8 * max(1.0, abs(want)))
+    # the gain cancels in every normalised row (all rows here have positive maxima or are empty)
+    assert abs(g_par[1]) <= 1e-9 * np.abs(g_par).max()
+    for m in range(6):
+        def L(v):
+            rf = refl.copy()
+            rf[m] = v
+            return _sonar_loss(spec, hits, rf.astype(np.float32), wp, wf)
+        h = 2.0 ** -16
+        want = (L(refl[m] + h) - L(refl[m] - h)) / (2 * h)
+        assert g_refl[m] == pytest.approx(want, rel=1e-5, abs=1e-8 * np.abs(g_refl).max())
+
+
 def test_uw_backward_matches_central_differences():
     st = Stream(31, 1)
     cam = make_camera(st, 12, 10)

@@ -65,6 +65,7 @@ class SonarSpec:
     seed_lo: int = 0
     seed_hi: int = 0
     frame_id: int = 0
+    range_norm: int = 0   # 1: each range row divided by its maximum after the gain
 
     def __post_init__(self):
         for f in ("r_min", "r_max", "fov_az", "fov_el", "kappa", "alpha", "gain", "sigma_phi",
