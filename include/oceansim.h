@@ -46,7 +46,7 @@
 extern "C" {
 #endif
 
-#define OCEANSIM_ABI_VERSION 1
+#define OCEANSIM_ABI_VERSION 2
 
 typedef enum {
     OCEANSIM_OK = 0,
@@ -159,6 +159,19 @@ typedef struct {
                                         is rendered), read by the backward
                                         instead of recomputing the fan
                                         geometry.  Same geometry in both. */
+    int32_t range_norm;              /* 1: range-wise normalisation: after the
+                                        gain each range row is divided by its
+                                        maximum over azimuth when that is
+                                        positive (rows with a maximum <= 0
+                                        are left as they are); 0: none.  The
+                                        paper (Sec. III-A.2) names the step
+                                        without a formula: this is a reading. */
+    float *saved_p;                  /* [N_r][N_phi] binned sums P (before the
+                                        gain): written by the forward when
+                                        non-NULL; the backward of a frame with
+                                        range_norm = 1 reads it (required
+                                        there: the adjoint of a row maximum
+                                        needs the row).  Plans keep their own. */
 } oceansim_sonar_frame;
 
 /* Bytes of the fan_stencil buffer of a fan_h x fan_w fan (16 per pair of

@@ -43,7 +43,8 @@ class SonarFrame(C.Structure):
                 ("speckle_mode", C.c_int32), ("gamma_k", C.c_int32), ("param_row", C.c_int32),
                 ("seed_lo", C.c_uint32), ("seed_hi", C.c_uint32), ("frame_id", C.c_uint32),
                 ("polar", _P), ("fan", _P), ("bin_of_return", _P),
-                ("grad_polar", _P), ("grad_fan", _P), ("fan_stencil", _P)]
+                ("grad_polar", _P), ("grad_fan", _P), ("fan_stencil", _P),
+                ("range_norm", C.c_int32), ("saved_p", _P)]
 
 
 class WaterParams(C.Structure):

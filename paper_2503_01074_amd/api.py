@@ -49,6 +49,7 @@ class SonarGeometry:
     seed_hi: int = 0
     frame_id: int = 0
     param_row: int = 0
+    range_norm: int = 0   # 1: each range row over its maximum after the gain (needs saved sums backward)
 
     @classmethod
     def from_spec(cls, spec, param_row: int = 0) -> "SonarGeometry":
@@ -56,7 +57,7 @@ class SonarGeometry:
                    fov_az=spec.fov_az, fov_el=spec.fov_el, path_factor=spec.kappa, fan_h=spec.fan_h,
                    fan_w=spec.fan_w, speckle_mode=spec.speckle_mode, gamma_k=spec.gamma_k,
                    seed_lo=spec.seed_lo, seed_hi=spec.seed_hi, frame_id=spec.frame_id,
-                   param_row=param_row)
+                   param_row=param_row, range_norm=int(getattr(spec, "range_norm", 0)))
 
 
 @dataclass
@@ -107,7 +108,7 @@ def water_params(rows: Sequence, device="cuda") -> torch.Tensor:
 
 
 def _sonar_struct(g: SonarGeometry, h: DeviceHits, polar=None, fan=None, bins=None, grad_polar=None,
-                  grad_fan=None, stencil=None) -> SonarFrame:
+                  grad_fan=None, stencil=None, saved_p=None) -> SonarFrame:
     s = SonarFrame()
     s.x, s.y, s.z = _ptr(h.x), _ptr(h.y), _ptr(h.z)
     s.nx, s.ny, s.nz = _ptr(h.nx), _ptr(h.ny), _ptr(h.nz)
@@ -124,6 +125,8 @@ def _sonar_struct(g: SonarGeometry, h: DeviceHits, polar=None, fan=None, bins=No
     s.polar, s.fan, s.bin_of_return = _ptr(polar), _ptr(fan), _ptr(bins)
     s.grad_polar, s.grad_fan = _ptr(grad_polar), _ptr(grad_fan)
     s.fan_stencil = _ptr(stencil)
+    s.range_norm = int(g.range_norm)
+    s.saved_p = _ptr(saved_p)
     return s
 
 
@@ -139,7 +142,8 @@ def render_sonar(geoms: Sequence[SonarGeometry], hits: Sequence[DeviceHits], par
     """Forward sonar image formation of one or many frames in one call.
 
     With ``save_stencil`` each frame with a fan also returns "stencil": the
-    fan stencils, to hand to render_sonar_backward."""
+    fan stencils, to hand to render_sonar_backward.  A range-normalised frame
+    also returns "saved_p", the binned sums its backward needs."""
     device = params.device
     outs, structs = [], []
     for g, h in zip(geoms, hits):
@@ -152,9 +156,11 @@ def render_sonar(geoms: Sequence[SonarGeometry], hits: Sequence[DeviceHits], par
                 o["stencil"] = fan_stencil_buffer(g, device)
         if bins:
             o["bins"] = torch.empty(h.n, dtype=torch.int32, device=device)
+        if g.range_norm:
+            o["saved_p"] = torch.empty(g.n_range, g.n_azimuth, dtype=torch.float32, device=device)
         outs.append(o)
         structs.append(_sonar_struct(g, h, o.get("polar"), o.get("fan"), o.get("bins"),
-                                     stencil=o.get("stencil")))
+                                     stencil=o.get("stencil"), saved_p=o.get("saved_p")))
     n_mat = int(refl.numel())
     need = _lib.oceansim_sonar_workspace_size(structs, n_mat, False)
     ws = workspace if workspace is not None and workspace.numel() >= need else _workspace(need, device)
@@ -167,15 +173,18 @@ def render_sonar_backward(geoms: Sequence[SonarGeometry], hits: Sequence[DeviceH
                           refl: torch.Tensor, grad_polar: Sequence[Optional[torch.Tensor]],
                           grad_fan: Sequence[Optional[torch.Tensor]],
                           stencils: Optional[Sequence[Optional[torch.Tensor]]] = None,
-                          workspace: Optional[torch.Tensor] = None):
+                          workspace: Optional[torch.Tensor] = None,
+                          saved_p: Optional[Sequence[Optional[torch.Tensor]]] = None):
     """Gradients (refl [M], params [rows, 8]) of sum <grad_polar, polar> + <grad_fan, fan>.
 
     ``stencils``: the fan stencils saved by the forward call (optional; without
-    them the fan geometry is recomputed)."""
+    them the fan geometry is recomputed).  ``saved_p``: the forward's binned
+    sums, required for range-normalised frames."""
     device = params.device
     stencils = stencils or [None] * len(geoms)
-    structs = [_sonar_struct(g, h, grad_polar=gp, grad_fan=gf, stencil=sv)
-               for g, h, gp, gf, sv in zip(geoms, hits, grad_polar, grad_fan, stencils)]
+    saved_p = saved_p or [None] * len(geoms)
+    structs = [_sonar_struct(g, h, grad_polar=gp, grad_fan=gf, stencil=sv, saved_p=sp)
+               for g, h, gp, gf, sv, sp in zip(geoms, hits, grad_polar, grad_fan, stencils, saved_p)]
     n_mat = int(refl.numel())
     need = _lib.oceansim_sonar_workspace_size(structs, n_mat, True)
     ws = workspace if workspace is not None and workspace.numel() >= need else _workspace(need, device)
@@ -333,6 +342,7 @@ class SonarRender(torch.autograd.Function):
         outs = render_sonar(geoms, hits, params, refl, polar=True, fan=True, save_stencil=True)
         ctx.geoms, ctx.hits = geoms, hits
         ctx.stencils = [o.get("stencil") for o in outs]
+        ctx.saved_p = [o.get("saved_p") for o in outs]
         ctx.save_for_backward(refl, params)
         flat = []
         for g, o in zip(geoms, outs):
@@ -355,7 +365,8 @@ class SonarRender(torch.autograd.Function):
                 gf.append(None if gfan is None else gfan.contiguous())
             else:
                 gf.append(None)
-        g_refl, g_par = render_sonar_backward(ctx.geoms, ctx.hits, params, refl, gp, gf, ctx.stencils)
+        g_refl, g_par = render_sonar_backward(ctx.geoms, ctx.hits, params, refl, gp, gf, ctx.stencils,
+                                              saved_p=ctx.saved_p)
         return g_refl, g_par, None, None
 
 

@@ -85,6 +85,9 @@ int check_frame(const oceansim_sonar_frame &fr, int idx, int n_param_rows, bool 
     if (fr.param_row < 0 || fr.param_row >= n_param_rows)
         return fail(OCEANSIM_E_INVALID_ARG, "frame %d: param_row %d outside [0, %d)", idx, fr.param_row,
                     n_param_rows);
+    if (fr.range_norm != 0 && fr.range_norm != 1)
+        return fail(OCEANSIM_E_INVALID_ARG, "frame %d: range_norm must be 0 or 1", idx);
+    if (!aligned(fr.saved_p, 16)) return fail(OCEANSIM_E_INVALID_ARG, "frame %d: saved_p must be 16-byte aligned", idx);
     const bool has_fan = fr.fan_h != 0 || fr.fan_w != 0;
     if (has_fan) {
         if (fr.fan_h < 1 || fr.fan_w < 1 || fr.fan_h > kMaxFanSide || fr.fan_w > kMaxFanSide)
@@ -195,6 +198,8 @@ int plan_sonar(const oceansim_sonar_frame *frames, int n_frames, int n_param_row
     P.off_cols.assign(n_frames, (size_t)-1);
     P.off_grad_img.assign(n_frames, 0);
     int bin_blocks = 0, tile_blocks = 0, tile_b_blocks = 0, fan_blocks = 0, ret_blocks = 0, fant_blocks = 0;
+    int row_blocks = 0, max_rows_per_tile = 0;   // range-wise normalisation
+    P.off_dldq.assign(n_frames, (size_t)-1);
     // Bins per thread through the transposed fan operators: one while the
     // workgroups fit the chip a few times over; more for large batches, where
     // the per-workgroup costs (frame lookup, pointer loads, partial sums) add up.
@@ -278,6 +283,11 @@ int plan_sonar(const oceansim_sonar_frame *frames, int n_frames, int n_param_row
         d.bin_of_return = gcast(fr.bin_of_return);
         d.grad_polar = gcast(fr.grad_polar);
         d.grad_fan = gcast(fr.grad_fan);
+        d.range_norm = fr.range_norm;
+        d.saved_p = gcast(fr.saved_p);
+        d.blk[KROW] = row_blocks;
+        if (backward && fr.range_norm) row_blocks += fr.n_range;
+        if (fr.range_norm) max_rows_per_tile = std::max(max_rows_per_tile, d.rows_per_tile);
         if (!backward) {
             P.off_pairs[i] = take(sizeof(uint2) * (size_t)d.n_chunks * chunk);
             P.off_chunk_off[i] = take(sizeof(int) * (size_t)d.n_chunks * (d.n_tiles + 1));
@@ -285,9 +295,12 @@ int plan_sonar(const oceansim_sonar_frame *frames, int n_frames, int n_param_row
             if (d.fan_blocks > 0) P.off_cols[i] = take(sizeof(double) * 2 * (size_t)fr.n_azimuth);
         } else {
             P.off_grad_img[i] = take(sizeof(float) * (size_t)nb);
+            if (fr.range_norm) P.off_dldq[i] = take(sizeof(float) * (size_t)nb);
         }
     }
     P.grid.bin_blocks = bin_blocks;
+    P.grid.row_blocks = row_blocks;
+    P.grid.max_rows_per_tile = max_rows_per_tile;
     P.grid.tile_blocks = tile_blocks;
     P.grid.fan_blocks = fan_blocks;
     P.grid.ret_blocks = ret_blocks;
@@ -302,7 +315,7 @@ int plan_sonar(const oceansim_sonar_frame *frames, int n_frames, int n_param_row
         if (frames[i].grad_fan && !frames[i].fan_stencil) P.grid.all_saved = 0;
     if (backward) {
         // slots for either backward decomposition of the polar gradient
-        P.n_slots = std::max(tile_b_blocks, fant_blocks) + ret_blocks;
+        P.n_slots = std::max(tile_b_blocks, fant_blocks) + ret_blocks + row_blocks;
         // five FP64 partial sums per slot (column-major), then the slot's parameter row
         P.off_part = take((sizeof(double) * 5 + sizeof(int)) * (size_t)std::max(1, P.n_slots));
         if (n_mat <= kLaneHistMats)
@@ -322,6 +335,7 @@ void carve_sonar(SonarPlan &P, char *ws, bool backward) {
             if (P.off_cols[i] != (size_t)-1) d.cols = gcast(reinterpret_cast<double2 *>(ws + P.off_cols[i]));
         } else {
             d.grad_img = gcast(reinterpret_cast<float *>(ws + P.off_grad_img[i]));
+            if (P.off_dldq[i] != (size_t)-1) d.dldq = gcast(reinterpret_cast<float *>(ws + P.off_dldq[i]));
         }
     }
 }
@@ -533,6 +547,9 @@ int oceansim_sonar_render_backward(const oceansim_sonar_frame *frames, int32_t n
     SonarPlan P;
     int rc = plan_sonar(frames, n_frames, n_param_rows, n_materials, true, P, nullptr);
     if (rc) return rc;
+    for (int i = 0; i < n_frames; ++i)
+        if (frames[i].range_norm && !frames[i].saved_p)
+            return fail(OCEANSIM_E_INVALID_ARG, "frame %d: range_norm needs the forward's saved_p", i);
     rc = check_ws(workspace, workspace_bytes, P.bytes);
     if (rc) return rc;
     char *ws = static_cast<char *>(workspace);

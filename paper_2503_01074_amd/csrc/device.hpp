@@ -19,7 +19,7 @@ constexpr int kFanTileU = 32;      // pixel pairs per fan workgroup along a row
 constexpr int kFanTileV = 16;      // fan rows per fan workgroup (8 x kFanRows)
 constexpr int kLaneHistMats = 64;    // materials reduced per workgroup in an LDS table (above: global atomics)
 
-enum Kind { KBIN = 0, KTILE = 1, KFAN = 2, KRET = 3, KTILEB = 4, KFANT = 5, KIND_COUNT = 6 };
+enum Kind { KBIN = 0, KTILE = 1, KFAN = 2, KRET = 3, KTILEB = 4, KFANT = 5, KROW = 6, KIND_COUNT = 7 };
 enum Speckle { SPECKLE_OFF = 0, SPECKLE_PAPER = 1, SPECKLE_GAMMA = 2 };
 
 // Pointers into device global memory.  Descriptor pointers carry the global
@@ -114,6 +114,12 @@ struct SonarDev {
     gptr<const int> ft_ptr;
     gptr<const uint2> ft_ent;
     int ft_mirror;
+    // Range-wise normalisation: each range row of Q = G P over its maximum
+    // (when positive).  saved_p: the forward's binned sums P [nb]; dldq: the
+    // backward's dL/dQ per bin [nb].
+    int range_norm;
+    gptr<float> saved_p;
+    gptr<float> dldq;
     int n_fant_blocks;          // backward workgroups (kBlock * BPT operator rows each) through the operator
 };
 

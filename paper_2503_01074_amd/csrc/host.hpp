@@ -30,6 +30,7 @@ struct SonarPlan {
     // workspace offsets
     size_t off_table = 0;
     std::vector<size_t> off_pairs, off_chunk_off, off_polar, off_grad_img, off_cols;
+    std::vector<size_t> off_dldq;   // range-normalised frames' dL/dQ (backward)
     size_t off_part = 0, off_refl_part = 0;
     int n_slots = 0;
 };

@@ -53,6 +53,8 @@ struct SonarGrid {
     int fant_bpt;        // bins per thread of those workgroups: 1, 2 or 4
     int use_fant;        // backward through the frames' transposed fan operators instead of polar tiles
     int fant_mirror;     // some frame's operator has the mirrored layout
+    int row_blocks;      // backward: one workgroup per range row of the range-normalised frames
+    int max_rows_per_tile;   // forward: widest tile (rows) of a range-normalised frame; 0: none
 };
 
 constexpr int kBwdThreads = 512;   // threads of a backward polar-tile workgroup

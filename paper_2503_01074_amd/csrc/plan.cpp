@@ -38,6 +38,7 @@ struct oceansim_plan {
     UwPlan uf, ub;
     char *mem = nullptr;        // workspaces and frame tables
     char *stencil_mem = nullptr;
+    char *savedp_mem = nullptr;   // binned sums of range-normalised frames (backward plans)
     // transposed fan operators of the sonar frames (backward plans), per frame
     // (nullptr where a frame has none)
     char *fant_mem = nullptr;
@@ -455,6 +456,7 @@ void free_plan(oceansim_plan *p) {
     if (p->cap) (void)hipStreamDestroy(p->cap);
     if (p->mem) (void)hipFree(p->mem);
     if (p->stencil_mem) (void)hipFree(p->stencil_mem);
+    if (p->savedp_mem) (void)hipFree(p->savedp_mem);
     if (p->fant_mem) (void)hipFree(p->fant_mem);
     delete p;
 }
@@ -698,6 +700,27 @@ int oceansim_plan_create(const oceansim_sonar_frame *sonar, int32_t n_sonar, con
     if (rc) {
         delete p;
         return rc;
+    }
+    // the binned sums a range-normalised frame's backward reads, where the
+    // caller keeps none
+    if (bwd) {
+        size_t sp_bytes = 0;
+        std::vector<size_t> sp_off(n_sonar, (size_t)-1);
+        for (int i = 0; i < n_sonar; ++i)
+            if (p->sonar[i].range_norm && !p->sonar[i].saved_p) {
+                sp_off[i] = sp_bytes;
+                sp_bytes += (sizeof(float) * (size_t)p->sonar[i].n_range * p->sonar[i].n_azimuth + kWsAlign - 1) /
+                            kWsAlign * kWsAlign;
+            }
+        if (sp_bytes) {
+            hipError_t se = hipMalloc(&p->savedp_mem, sp_bytes);
+            if (se != hipSuccess) {
+                free_plan(p);
+                return hip_fail(se, "plan binned-sum memory");
+            }
+            for (int i = 0; i < n_sonar; ++i)
+                if (sp_off[i] != (size_t)-1) p->sonar[i].saved_p = reinterpret_cast<float *>(p->savedp_mem + sp_off[i]);
+        }
     }
     // saved fan stencils for frames rendered with a fan whose gradient is read
     size_t st_bytes = 0;

@@ -271,7 +271,31 @@ __device__ __forceinline__ void tile_fwd_block(const Src &src, const oceansim_so
         __syncthreads();
     }
 
-    const float G = pr.gain;
+    float G = pr.gain;
+    if (f.saved_p)   // the binned sums P, for the backward of a range-normalised frame
+        for (int k = tid; k < nbins; k += kBlock) f.saved_p[b_lo + k] = acc[k];
+    if (f.range_norm) {
+        // range-wise normalisation: each row of Q = G P over its maximum when
+        // that is positive (the maximum over the positive entries: NaN and
+        // non-positive values do not count), else the row as it is; acc then
+        // holds the normalised Q, so the gain below is 1
+        unsigned *rmax = reinterpret_cast<unsigned *>(etab + f.n_az);   // [rows of the tile]
+        const int rows = nbins / f.n_az;
+        for (int r = tid; r < rows; r += kBlock) rmax[r] = 0u;
+        __syncthreads();
+        for (int k = tid; k < nbins; k += kBlock) {
+            const float q = G * acc[k];
+            if (q > 0.0f) atomicMax(&rmax[k / f.n_az], __float_as_uint(q));   // positive floats order as their bits
+        }
+        __syncthreads();
+        for (int k = tid; k < nbins; k += kBlock) {
+            const float m = __uint_as_float(rmax[k / f.n_az]);
+            const float q = G * acc[k];
+            acc[k] = m > 0.0f ? q / m : q;
+        }
+        __syncthreads();
+        G = 1.0f;
+    }
     if (speckle) {
         // Q m for the listed (nonempty) bins only: the other bins have Q = 0
         const int nl = n_listed;
@@ -947,10 +971,16 @@ __device__ __forceinline__ void ret_bwd_block(const Src &src, const oceansim_son
         float z = 0.0f;
         const float mult = speckle_factor(f, (uint32_t)b, pr.sigma_sm, &z);
         const double gIt = (double)gI_t;
-        const double gI = (double)G * (double)mult * gIt;   // dL / dI_k
+        // dL/dQ at the bin: through the multiplicative speckle, or (range-
+        // normalised frames, a uniform branch) as the row-normalisation
+        // adjoint left it, with the row's scale for the multiplicative draw
+        double gq = (double)mult * gIt;
+        if (f.range_norm) gq = (double)f.dldq[b];
+        const double gI = (double)G * gq;   // dL / dI_k
         g_alpha += gI * (double)I * (-f.kappa * r);
-        g_gain += gIt * (double)mult * (double)I;
-        if (f.speckle == SPECKLE_PAPER) g_ssm += gIt * (double)G * (double)I * (double)z;
+        g_gain += gq * (double)I;
+        // (for a range-normalised frame the row kernel adds the sigma_sm term)
+        if (f.speckle == SPECKLE_PAPER && !f.range_norm) g_ssm += gIt * (double)G * (double)I * (double)z;
         const float gr = (float)(gI * (double)cosg * (double)att);
         if (table) {
             m_q[q] = m;
@@ -1260,6 +1290,92 @@ __global__ __launch_bounds__(kBlock) void k_fant_bwd(Src src, const oceansim_son
     if (tid == 1) part[3LL * n_slots + bid] = tot;
 }
 
+// ---------------------------------------------------------------------------
+// k_rownorm_bwd: adjoint of the range-wise normalisation, one workgroup per
+// range row of each range-normalised frame.  With gN = dL/d(normalised Q)
+// (the polar gradient times the multiplicative speckle factor, or alone
+// without speckle), a row normalised by its maximum m = Q_j* gives
+// dL/dQ_j = gN_j / m - [j = j*] (sum_k gN_k Q_k) / m^2; other rows pass gN.
+// The maximum is the forward's (over the positive entries of G P, from the
+// saved sums), j* the first column attaining it; the sum is FP64 in a fixed
+// order.  Writes dL/dQ per bin, and the row's partial sum of dL/d sigma_sm
+// (the paper's multiplicative draw acts on the normalised row) to its slot.
+// ---------------------------------------------------------------------------
+template <class Src>
+__global__ __launch_bounds__(kBlock) void k_rownorm_bwd(Src src, const oceansim_sonar_params *params, double *part,
+                                                        int slot_base, int n_slots) {
+    __shared__ unsigned s_max;
+    __shared__ int s_arg;
+    __shared__ double s_sum;
+    int i;
+    const int fi = src.locate(blockIdx.x, KROW, i);
+    const SonarDev f = src.frame(fi);
+    const oceansim_sonar_params pr = params[f.param_row];
+    const float G = pr.gain;
+    const int tid = threadIdx.x;
+    const int r0 = i * f.n_az;
+    if (tid == 0) {
+        s_max = 0u;
+        s_arg = f.n_az;
+    }
+    __syncthreads();
+    for (int j = tid; j < f.n_az; j += kBlock) {
+        const float q = G * f.saved_p[r0 + j];
+        if (q > 0.0f) atomicMax(&s_max, __float_as_uint(q));   // positive floats order as their bits
+    }
+    __syncthreads();
+    const float m = __uint_as_float(s_max);
+    const bool norm = m > 0.0f;
+    const double scale = norm ? 1.0 / (double)m : 1.0;
+    auto g_norm = [&](int b, double &gssm) -> double {   // dL/d(normalised Q) at bin b
+        double g = (double)f.grad_img[b];
+        gssm = 0.0;
+        if (f.speckle != SPECKLE_OFF) {
+            float z = 0.0f;
+            const double gt = g;
+            g *= (double)speckle_factor(f, (uint32_t)b, pr.sigma_sm, &z);
+            if (f.speckle == SPECKLE_PAPER)   // d/d sigma_sm of (normalised Q) m
+                gssm = gt * ((double)(G * f.saved_p[b]) * scale) * (double)z;
+        }
+        return g;
+    };
+    double ps = 0.0, pssm = 0.0;
+    for (int j = tid; j < f.n_az; j += kBlock) {
+        const float q = G * f.saved_p[r0 + j];
+        if (norm && q == m) atomicMin(&s_arg, j);
+        double gs;
+        ps += g_norm(r0 + j, gs) * (double)q;
+        pssm += gs;
+    }
+    const double sums[2] = {ps, pssm};
+    __shared__ double red2[2 * (kBlock / kWave)];
+    const double tot = block_sum_n<2, kBlock>(sums, red2);   // thread 0: the row sum, 1: sigma_sm
+    if (tid == 0) s_sum = tot;
+    // the row's partial sums: column 4 (sigma_sm), zeros elsewhere
+    const long long slot = slot_base + blockIdx.x;
+    if (tid == 0) {
+        reinterpret_cast<int *>(part + 5LL * n_slots)[slot] = f.param_row;
+        part[0LL * n_slots + slot] = 0.0;
+        part[1LL * n_slots + slot] = 0.0;
+        part[2LL * n_slots + slot] = 0.0;
+        part[3LL * n_slots + slot] = 0.0;
+    }
+    if (tid == 1) part[4LL * n_slots + slot] = tot;
+    __syncthreads();
+    const int js = s_arg;
+    const double S = s_sum, md = (double)m;
+    for (int j = tid; j < f.n_az; j += kBlock) {
+        const int b = r0 + j;
+        double gs;
+        double d = g_norm(b, gs);
+        if (norm) {
+            d /= md;
+            if (j == js) d -= S / (md * md);
+        }
+        f.dldq[b] = (float)d;
+    }
+}
+
 // Column table of the fan frames (workgroup = frame), the input the fan
 // kernel's stencils need besides the geometry.
 template <class Src>
@@ -1313,7 +1429,8 @@ static hipError_t launch_fwd(const Src &src, const SonarGrid &g, const oceansim_
         if (e != hipSuccess) return e;
     }
     OSIM_LAUNCH("k_tile", (k_tile<Src>), dim3(g.tile_blocks), dim3(kBlock),
-                (size_t)g.max_tile_bins * 8 + (size_t)g.max_n_az * 4, st, src, params);
+                (size_t)g.max_tile_bins * 8 + (size_t)g.max_n_az * 4 + (size_t)g.max_rows_per_tile * 4, st, src,
+                params);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     if (g.fan_blocks > 0) {
@@ -1332,7 +1449,7 @@ static hipError_t launch_bwd(const Src &src, int n_frames, const SonarGrid &g,
     // partial-sum slots: polar workgroups (tiles, or bin blocks through the
     // transposed fan operators), then return chunks
     const int polar_blocks = g.use_fant ? g.fant_blocks : g.tile_b_blocks;
-    const int n_slots = polar_blocks + g.ret_blocks;
+    const int n_slots = polar_blocks + g.ret_blocks + g.row_blocks;
     hipError_t e = hipSuccess;
     if (g.use_fant && g.fant_blocks > 0) {
         float *gz = lane_hist ? (float *)nullptr : grad_refl;
@@ -1360,6 +1477,12 @@ static hipError_t launch_bwd(const Src &src, int n_frames, const SonarGrid &g,
             OSIM_LAUNCH("k_tile_bwd", (k_tile_bwd<Src, false>), dim3(g.tile_b_blocks), dim3(kBwdThreads),
                         (size_t)g.max_tile_bins_b * 8, st, src, params, part, n_slots,
                         lane_hist ? (float *)nullptr : grad_refl, n_mat);
+        e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    if (g.row_blocks > 0) {   // range-normalised frames: dL/dQ per bin before the return gather
+        OSIM_LAUNCH("k_rownorm_bwd", (k_rownorm_bwd<Src>), dim3(g.row_blocks), dim3(kBlock), 0, st, src, params,
+                    part, polar_blocks + g.ret_blocks, n_slots);
         e = hipGetLastError();
         if (e != hipSuccess) return e;
     }

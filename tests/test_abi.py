@@ -27,7 +27,7 @@ def test_exports_every_declared_function():
     for name in sorted(declared):
         assert hasattr(so, name), name
     assert set(lib.EXPORTED) == declared
-    assert lib.oceansim_abi_version() == 1
+    assert lib.oceansim_abi_version() == 2
 
 
 def test_struct_layout_matches_header():
@@ -195,6 +195,23 @@ def test_uw_backward_rejects():
     f = _uw(lib, grad_out=FAKE)
     assert so.oceansim_uw_form_backward(C.pointer(f), 1, FAKE, 1, None, FAKE, 1 << 30, None) == -1
     assert so.oceansim_uw_form_backward(C.pointer(f), 1, FAKE, 1, FAKE, FAKE, 8, None) == -3
+
+
+def test_range_norm_rejections():
+    """range_norm must be 0 or 1; the plain backward of a range-normalised
+    frame needs the forward's binned sums (checked before any device work)."""
+    lib = _lib()
+    so = lib.lib
+    f = _frame(lib, range_norm=2)
+    ws = C.c_size_t()
+    assert so.oceansim_sonar_workspace_size(C.pointer(f), 1, 8, 0, C.byref(ws)) == -1
+    assert "range_norm" in lib.last_error()
+    g = _frame(lib, range_norm=1, polar=0, fan=0, grad_polar=FAKE)
+    assert so.oceansim_sonar_render_backward(C.pointer(g), 1, FAKE, 1, FAKE, 8, FAKE, FAKE, FAKE, 1 << 30,
+                                             None) == -1
+    assert "saved_p" in lib.last_error()
+    h = _frame(lib, range_norm=1, saved_p=FAKE + 4)
+    assert so.oceansim_sonar_workspace_size(C.pointer(h), 1, 8, 0, C.byref(ws)) == -1   # misaligned
 
 
 def test_plan_rejections():
