@@ -176,6 +176,15 @@ class RealTimeStep:
             pl.sonar_out[0]["grad_fan"].copy_(self.gfan)
             pl.camera_out[0]["grad_out"].copy_(self.gimg)
             self.plans[name] = pl
+        # the same step with the range-wise normalisation after the gain
+        import dataclasses
+        pl = osm.Plan([(dataclasses.replace(self.geom, range_norm=1), self.hits)], [(self.J, self.d, 0)],
+                      sonar_params=self.params, refl=self.refl, water=self.water, backward=True, autotune=True,
+                      image_grads=True)
+        pl.sonar_out[0]["grad_polar"].copy_(self.gpol)
+        pl.sonar_out[0]["grad_fan"].copy_(self.gfan)
+        pl.camera_out[0]["grad_out"].copy_(self.gimg)
+        self.plans["norm"] = pl
 
     def sonar_forward(self, train=False):
         L, P = self.lib, self.P
@@ -553,6 +562,9 @@ def main():
     t_gfwd = timed(torch, lambda: rt.plan_forward("graph"), args.steps, args.warmup)
     log("plain entry points: step %.3f ms, forward %.3f ms, sonar forward %.3f ms; graph plan: step %.3f ms, "
         "forward %.3f ms" % (t_pstep * 1e3, t_pfwd * 1e3, t_sonar_fwd * 1e3, t_gstep * 1e3, t_gfwd * 1e3))
+    t_nstep = timed(torch, lambda: rt.plan_step("norm"), args.steps, args.warmup)
+    t_nfwd = timed(torch, lambda: rt.plan_forward("norm"), args.steps, args.warmup)
+    log("with range-wise normalisation: step %.3f ms, forward %.3f ms" % (t_nstep * 1e3, t_nfwd * 1e3))
 
     # per-entry-point GPU durations from events on the launch stream
     reps = max(20, args.steps)
@@ -617,6 +629,7 @@ def main():
         "plain": {"step_ms": t_pstep * 1e3, "returns_per_s": rt.n_returns / t_pstep, "fwd_ms": t_pfwd * 1e3,
                   "sonar_fwd_only_frames_per_s": 1.0 / t_sonar_fwd},
         "graph": {"step_ms": t_gstep * 1e3, "returns_per_s": rt.n_returns / t_gstep, "fwd_ms": t_gfwd * 1e3},
+        "range_norm": {"step_ms": t_nstep * 1e3, "returns_per_s": rt.n_returns / t_nstep, "fwd_ms": t_nfwd * 1e3},
         "copy_GBps": copy_rate(torch, dev),
         "camera_mpx_per_s_fwd_bwd": rt.npix / t_step / 1e6,
         "entry_point_us": {k: round(v * 1e6, 2) for k, v in parts.items()},

@@ -1339,12 +1339,16 @@ __global__ __launch_bounds__(kBlock) void k_rownorm_bwd(Src src, const oceansim_
         }
         return g;
     };
+    extern __shared__ int4 lds_raw[];
+    double *gnr = reinterpret_cast<double *>(lds_raw);   // [n_az]: dL/d(normalised Q) of the row
     double ps = 0.0, pssm = 0.0;
     for (int j = tid; j < f.n_az; j += kBlock) {
         const float q = G * f.saved_p[r0 + j];
         if (norm && q == m) atomicMin(&s_arg, j);
         double gs;
-        ps += g_norm(r0 + j, gs) * (double)q;
+        const double gn = g_norm(r0 + j, gs);
+        gnr[j] = gn;
+        ps += gn * (double)q;
         pssm += gs;
     }
     const double sums[2] = {ps, pssm};
@@ -1366,8 +1370,7 @@ __global__ __launch_bounds__(kBlock) void k_rownorm_bwd(Src src, const oceansim_
     const double S = s_sum, md = (double)m;
     for (int j = tid; j < f.n_az; j += kBlock) {
         const int b = r0 + j;
-        double gs;
-        double d = g_norm(b, gs);
+        double d = gnr[j];   // this thread's own entry
         if (norm) {
             d /= md;
             if (j == js) d -= S / (md * md);
@@ -1481,8 +1484,8 @@ static hipError_t launch_bwd(const Src &src, int n_frames, const SonarGrid &g,
         if (e != hipSuccess) return e;
     }
     if (g.row_blocks > 0) {   // range-normalised frames: dL/dQ per bin before the return gather
-        OSIM_LAUNCH("k_rownorm_bwd", (k_rownorm_bwd<Src>), dim3(g.row_blocks), dim3(kBlock), 0, st, src, params,
-                    part, polar_blocks + g.ret_blocks, n_slots);
+        OSIM_LAUNCH("k_rownorm_bwd", (k_rownorm_bwd<Src>), dim3(g.row_blocks), dim3(kBlock),
+                    (size_t)g.max_n_az * sizeof(double), st, src, params, part, polar_blocks + g.ret_blocks, n_slots);
         e = hipGetLastError();
         if (e != hipSuccess) return e;
     }

@@ -130,3 +130,32 @@ def test_plan_mixed_batch(graph):
         assert_grad_cond(plan.grad_refl.cpu().numpy(), o_refl, c_refl, what="refl %d" % rep)
         assert_grad_cond(plan.grad_sonar_params.cpu().numpy()[0, :5], o_par, c_par, what="params %d" % rep)
     plan.close()
+
+
+def test_real_time_frame_plan():
+    """The real-time frame (131072 returns, 1024 x 1024 bins, 1024 x 2048
+    fan, gamma speckle) with the normalisation, through an autotuned
+    backward plan: image and all gradients."""
+    import torch
+    import paper_2503_01074_amd as osm
+    _say("range norm, real-time frame through an autotuned backward plan")
+    f = W.sonar_c2()[0]
+    f.spec.range_norm = 1
+    refl = f.hits.refl
+    plan = osm.Plan([(osm.SonarGeometry.from_spec(f.spec), osm.DeviceHits.from_host(f.hits))],
+                    sonar_params=osm.sonar_params([osm.sonar_params_from_spec(f.spec)]),
+                    refl=torch.as_tensor(refl).cuda(), backward=True, autotune=True)
+    gp = W.loss_weights((9401, 1), (f.spec.n_range, f.spec.n_azimuth))
+    gf = W.loss_weights((9401, 2), (f.spec.fan_h, f.spec.fan_w))
+    plan.sonar_out[0]["grad_polar"].copy_(torch.as_tensor(gp))
+    plan.sonar_out[0]["grad_fan"].copy_(torch.as_tensor(gf))
+    plan.forward()
+    plan.backward()
+    torch.cuda.synchronize()
+    want = oracle.sonar_forward(SonarConfig.from_spec(f.spec), f.hits, refl)
+    assert_image_close(plan.sonar_out[0]["polar"].cpu().numpy(), want["out"], "polar")
+    assert_image_close(plan.sonar_out[0]["fan"].cpu().numpy(), want["fan"], "fan", mask=~want["ambiguous"])
+    o_refl, o_par, c_refl, c_par = _oracle_grads([f], refl, [gp], [gf])
+    assert_grad_cond(plan.grad_refl.cpu().numpy(), o_refl, c_refl, what="refl")
+    assert_grad_cond(plan.grad_sonar_params.cpu().numpy()[0, :5], o_par, c_par, what="params")
+    plan.close()
