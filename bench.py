@@ -40,6 +40,8 @@ def parse():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-range-norm", action="store_true",
+                    help="skip the real-time step with the range-wise normalisation (profiler runs)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 64 MiB device-to-device copy (counter calibration)")
@@ -112,7 +114,7 @@ def copy_rate(torch, dev):
 class RealTimeStep:
     """Device buffers and prebuilt descriptors of the real-time workload."""
 
-    def __init__(self, dev):
+    def __init__(self, dev, range_norm=True):
         import torch
         import numpy as np
         import paper_2503_01074_amd as osm
@@ -176,6 +178,8 @@ class RealTimeStep:
             pl.sonar_out[0]["grad_fan"].copy_(self.gfan)
             pl.camera_out[0]["grad_out"].copy_(self.gimg)
             self.plans[name] = pl
+        if not range_norm:
+            return
         # the same step with the range-wise normalisation after the gain
         import dataclasses
         pl = osm.Plan([(dataclasses.replace(self.geom, range_norm=1), self.hits)], [(self.J, self.d, 0)],
@@ -543,7 +547,7 @@ def main():
         log("done: %s" % ", ".join(sorted(legs)))
         return
     log("building workload")
-    rt = RealTimeStep(dev)
+    rt = RealTimeStep(dev, range_norm=not args.no_range_norm)
 
     # The step: the plan (frames prepared once, launch shapes autotuned),
     # forward + backward, K times after W warm-up steps, timed by the host
@@ -562,9 +566,12 @@ def main():
     t_gfwd = timed(torch, lambda: rt.plan_forward("graph"), args.steps, args.warmup)
     log("plain entry points: step %.3f ms, forward %.3f ms, sonar forward %.3f ms; graph plan: step %.3f ms, "
         "forward %.3f ms" % (t_pstep * 1e3, t_pfwd * 1e3, t_sonar_fwd * 1e3, t_gstep * 1e3, t_gfwd * 1e3))
-    t_nstep = timed(torch, lambda: rt.plan_step("norm"), args.steps, args.warmup)
-    t_nfwd = timed(torch, lambda: rt.plan_forward("norm"), args.steps, args.warmup)
-    log("with range-wise normalisation: step %.3f ms, forward %.3f ms" % (t_nstep * 1e3, t_nfwd * 1e3))
+    norm = None
+    if "norm" in rt.plans:
+        t_nstep = timed(torch, lambda: rt.plan_step("norm"), args.steps, args.warmup)
+        t_nfwd = timed(torch, lambda: rt.plan_forward("norm"), args.steps, args.warmup)
+        log("with range-wise normalisation: step %.3f ms, forward %.3f ms" % (t_nstep * 1e3, t_nfwd * 1e3))
+        norm = {"step_ms": t_nstep * 1e3, "returns_per_s": rt.n_returns / t_nstep, "fwd_ms": t_nfwd * 1e3}
 
     # per-entry-point GPU durations from events on the launch stream
     reps = max(20, args.steps)
@@ -629,7 +636,7 @@ def main():
         "plain": {"step_ms": t_pstep * 1e3, "returns_per_s": rt.n_returns / t_pstep, "fwd_ms": t_pfwd * 1e3,
                   "sonar_fwd_only_frames_per_s": 1.0 / t_sonar_fwd},
         "graph": {"step_ms": t_gstep * 1e3, "returns_per_s": rt.n_returns / t_gstep, "fwd_ms": t_gfwd * 1e3},
-        "range_norm": {"step_ms": t_nstep * 1e3, "returns_per_s": rt.n_returns / t_nstep, "fwd_ms": t_nfwd * 1e3},
+        "range_norm": norm,
         "copy_GBps": copy_rate(torch, dev),
         "camera_mpx_per_s_fwd_bwd": rt.npix / t_step / 1e6,
         "entry_point_us": {k: round(v * 1e6, 2) for k, v in parts.items()},
