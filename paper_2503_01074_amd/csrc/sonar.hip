@@ -8,8 +8,9 @@
 //           per-tile offsets.  No global atomics.
 //   k_tile  one workgroup per polar tile: gathers the tile's pairs from every
 //           chunk and sums them into an LDS histogram (binning by summation),
-//           then applies the gain and the speckle of Eq. (3)-(6) per bin and
-//           streams the tile out row-major.
+//           then applies the gain, the optional range-wise normalisation
+//           (each row over its maximum) and the speckle of Eq. (3)-(6) per
+//           bin and streams the tile out row-major.
 //   k_fan   one thread per mirror pair of fan pixels: FP64 polar coordinates,
 //           bilinear interpolation of the polar image.
 //   k_bin_uw    (plans with camera frames) k_bin plus the camera forward.
@@ -29,6 +30,8 @@
 //               multiplicative speckle and Eq. (2) (alpha, gain, sigma_sm and
 //               reflectivity partial sums).
 //   k_ret_uw_bwd  (plans with camera frames) k_ret_bwd plus the camera backward.
+//   k_rownorm_bwd (range-normalised frames) one workgroup per range row:
+//               adjoint of the row normalisation, before the return gather.
 #include <type_traits>
 
 #include "device.hpp"
