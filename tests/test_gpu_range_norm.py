@@ -159,3 +159,36 @@ def test_real_time_frame_plan():
     assert_grad_cond(plan.grad_refl.cpu().numpy(), o_refl, c_refl, what="refl")
     assert_grad_cond(plan.grad_sonar_params.cpu().numpy()[0, :5], o_par, c_par, what="params")
     plan.close()
+
+
+def test_plain_batched_call_mixed():
+    """One batched plain call (frame tables, backward polar tiles) over a
+    normalised and a plain frame; the backward reads the saved sums."""
+    import torch
+    import paper_2503_01074_amd as osm
+    _say("range norm, plain batched call over a mixed pair")
+    frames = [_frame(6, W.SPECKLE_GAMMA, degenerate=False, n_materials=8, frame_id=0),
+              _frame(7, W.SPECKLE_PAPER, degenerate=False, n_materials=8, frame_id=1, Nr=31, Np=53, Wd=90)]
+    frames[1].spec.range_norm = 0
+    refl = frames[0].hits.refl
+    for f in frames:
+        f.hits.refl = refl
+    g = [osm.SonarGeometry.from_spec(f.spec) for f in frames]
+    h = [osm.DeviceHits.from_host(f.hits) for f in frames]
+    params = osm.sonar_params([osm.sonar_params_from_spec(frames[0].spec)])
+    refl_d = torch.as_tensor(refl).cuda()
+    outs = osm.render_sonar(g, h, params, refl_d, polar=True, fan=True)
+    torch.cuda.synchronize()
+    assert "saved_p" in outs[0] and "saved_p" not in outs[1]
+    for f, o in zip(frames, outs):
+        want = oracle.sonar_forward(SonarConfig.from_spec(f.spec), f.hits, refl)
+        assert_image_close(o["polar"].cpu().numpy(), want["out"], "polar")
+    gpol = [W.loss_weights((9501, k), (f.spec.n_range, f.spec.n_azimuth)) for k, f in enumerate(frames)]
+    gfan = [W.loss_weights((9502, k), (f.spec.fan_h, f.spec.fan_w)) for k, f in enumerate(frames)]
+    g_refl, g_par = osm.render_sonar_backward(g, h, params, refl_d, [torch.as_tensor(a).cuda() for a in gpol],
+                                              [torch.as_tensor(a).cuda() for a in gfan],
+                                              saved_p=[o.get("saved_p") for o in outs])
+    torch.cuda.synchronize()
+    o_refl, o_par, c_refl, c_par = _oracle_grads(frames, refl, gpol, gfan)
+    assert_grad_cond(g_refl.cpu().numpy(), o_refl, c_refl, what="refl")
+    assert_grad_cond(g_par.cpu().numpy()[0, :5], o_par, c_par, what="params")
