@@ -192,3 +192,29 @@ def test_plain_batched_call_mixed():
     o_refl, o_par, c_refl, c_par = _oracle_grads(frames, refl, gpol, gfan)
     assert_grad_cond(g_refl.cpu().numpy(), o_refl, c_refl, what="refl")
     assert_grad_cond(g_par.cpu().numpy()[0, :5], o_par, c_par, what="params")
+
+
+@pytest.mark.parametrize("norm", [0, 1])
+def test_autograd_function(norm):
+    """torch.autograd through SonarRender (forward saves the stencils and,
+    for a normalised frame, the binned sums): reflectivity and parameter
+    gradients of a weighted sum of the images against the oracle."""
+    import torch
+    import paper_2503_01074_amd as osm
+    _say("autograd SonarRender, range_norm %d" % norm)
+    f = _frame(8 + norm, W.SPECKLE_PAPER, degenerate=False, n_materials=8)
+    f.spec.range_norm = norm
+    refl = f.hits.refl
+    g = [osm.SonarGeometry.from_spec(f.spec)]
+    h = [osm.DeviceHits.from_host(f.hits)]
+    params = osm.sonar_params([osm.sonar_params_from_spec(f.spec)]).requires_grad_(True)
+    refl_d = torch.as_tensor(refl).cuda().requires_grad_(True)
+    gp = W.loss_weights((9601, norm), (f.spec.n_range, f.spec.n_azimuth))
+    gf = W.loss_weights((9602, norm), (f.spec.fan_h, f.spec.fan_w))
+    polar, fan = osm.api.SonarRender.apply(refl_d, params, g, h)
+    loss = (polar * torch.as_tensor(gp).cuda()).sum() + (fan * torch.as_tensor(gf).cuda()).sum()
+    loss.backward()
+    torch.cuda.synchronize()
+    o_refl, o_par, c_refl, c_par = _oracle_grads([f], refl, [gp], [gf])
+    assert_grad_cond(refl_d.grad.cpu().numpy(), o_refl, c_refl, what="refl")
+    assert_grad_cond(params.grad.cpu().numpy()[0, :5], o_par, c_par, what="params")
