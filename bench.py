@@ -526,6 +526,52 @@ def calibration_leg(torch, dev, steps, n_frames):
             "fwd_bwd_hbm_frac": alg_s / ts / (HBM_PEAK_GBS * 1e9), "autotuned_shape": shape}
 
 
+def camera_io_leg(torch, dev, steps):
+    """8-bit sRGB and z-depth in, Eq. (1), 8-bit sRGB out on one 1920 x 1080
+    RGBA frame: each entry point timed alone over `steps` launches, with its
+    algorithmic bytes (conditioning 24 B/pixel: 4 B RGBA + 4 B depth in, 12 B
+    J + 4 B range out; encoding 16 B: 12 B in, 4 B out; the adjoint 8 B)."""
+    import paper_2503_01074_amd as osm
+    H, Wd = 1080, 1920
+    g = torch.Generator(device="cpu").manual_seed(7)
+    img = torch.randint(0, 256, (H, Wd, 4), generator=g, dtype=torch.uint8).to(dev)
+    z = (torch.rand(H, Wd, generator=g) * 20 + 0.5).to(dev)
+    intr = (1662.77, 1662.77, 960.0, 540.0)     # 60 degree horizontal field of view
+    water = osm.water_params([((0.35, 0.12, 0.08), (0.30, 0.15, 0.10), (0.05, 0.25, 0.35))], device=dev)
+    (J,), (r,) = osm.cam_condition([img], [z], [intr])
+    (I,) = osm.uw_form([J], [r], water)
+    n = max(20, steps)
+    s = torch.cuda.current_stream(dev)
+
+    def timed(fn):
+        fn()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(s)
+        for _ in range(n):
+            fn()
+        b.record(s)
+        b.synchronize()
+        return a.elapsed_time(b) / 1e3 / n
+
+    t_c = timed(lambda: osm.cam_condition([img], [z], [intr]))
+    t_u = timed(lambda: osm.uw_form([J], [r], water))
+    t_e = timed(lambda: osm.cam_encode([I], channels_out=4))
+    t_b = timed(lambda: osm.cam_condition_backward([r], [intr]))
+    def pipeline():
+        (j,), (rr,) = osm.cam_condition([img], [z], [intr])
+        (ii,) = osm.uw_form([j], [rr], water)
+        osm.cam_encode([ii], channels_out=4)
+
+    t_all = timed(pipeline)
+    px = H * Wd
+    rate = lambda b, t: round(b * px / t / 1e9, 1)
+    return {"frame": "1920x1080 RGBA8 + z-depth -> Eq. 1 -> RGBA8", "pipeline_us": round(t_all * 1e6, 2),
+            "frames_per_s": round(1.0 / t_all, 1),
+            "condition_us": round(t_c * 1e6, 2), "condition_GBps": rate(24, t_c),
+            "uw_form_us": round(t_u * 1e6, 2), "encode_us": round(t_e * 1e6, 2), "encode_GBps": rate(16, t_e),
+            "range_backward_us": round(t_b * 1e6, 2), "range_backward_GBps": rate(8, t_b)}
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -607,6 +653,8 @@ def main():
     if not args.no_batched:
         extra = batched_legs(torch, dev, args.steps)
         extra["calibration_c5"] = calibration_leg(torch, dev, args.steps, args.c5_frames)
+    extra["camera_io"] = camera_io_leg(torch, dev, args.steps)
+    log("camera io: %s" % extra["camera_io"])
     cpu = None
     if not args.no_cpu:
         log("timing the FP64 oracle on the host")

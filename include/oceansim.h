@@ -46,7 +46,7 @@
 extern "C" {
 #endif
 
-#define OCEANSIM_ABI_VERSION 2
+#define OCEANSIM_ABI_VERSION 3
 
 typedef enum {
     OCEANSIM_OK = 0,
@@ -253,6 +253,60 @@ int oceansim_uw_form_backward(const oceansim_uw_frame *frames, int32_t n_frames,
                               const oceansim_water_params *params_dev, int32_t n_param_rows,
                               float *grad_params_dev, void *workspace, size_t workspace_bytes,
                               void *stream);
+
+/* ======================================================================== */
+/* Camera input conditioning and output encoding (Sec. III-A.1)            */
+/*                                                                          */
+/* Eq. (1) attenuates with the distance d travelled along the line of      */
+/* sight, which the paper calls depth or range.  A renderer's depth buffer  */
+/* holds z-depth (distance along the optical axis); with pinhole            */
+/* intrinsics (fx, fy, cx, cy in pixels, pixel (u, v) centred at            */
+/* (u + 1/2, v + 1/2)) the range of pixel (u, v) is                         */
+/*   r = z * sqrt(1 + ((u + 1/2 - cx) / fx)^2 + ((v + 1/2 - cy) / fy)^2).   */
+/* Colour enters and leaves as 8-bit sRGB (IEC 61966-2-1 transfer function) */
+/* while Eq. (1) acts on linear intensities: decoding maps code c to        */
+/* srgb_to_linear(c / 255) rounded to the nearest float; encoding maps a    */
+/* linear value x to floor(255 * linear_to_srgb(min(max(x, 0), 1)) + 1/2),  */
+/* computed exactly (NaN encodes as 0).                                     */
+/* ======================================================================== */
+
+/* One camera frame to condition.  Either input may be NULL, which skips   */
+/* that half.  srgb_in is interleaved [H][W][channels_in] bytes (3: RGB,     */
+/* 4: RGBA, alpha ignored); J is planar [3][H][W]; zdepth, range,           */
+/* grad_range and grad_zdepth are [H][W].  Buffers 16-byte aligned.  An     */
+/* empty frame (H or W 0) is skipped and needs no buffers.                  */
+typedef struct {
+    const uint8_t *srgb_in;    /* forward input, or NULL                   */
+    const float *zdepth;       /* forward input (metres), or NULL          */
+    float *J;                  /* forward output, needed with srgb_in      */
+    float *range;              /* forward output, needed with zdepth       */
+    const float *grad_range;   /* backward input                           */
+    float *grad_zdepth;        /* backward output                          */
+    int32_t H, W;              /* 0 <= H, W <= 65535                        */
+    int32_t channels_in;       /* 3 or 4 (read only with srgb_in)          */
+    float fx, fy, cx, cy;      /* fx, fy finite and nonzero; cx, cy finite */
+} oceansim_cam_frame;
+
+/* Decode srgb_in into J and convert zdepth into range on n_frames frames   */
+/* (uneven sizes allowed; no workspace).  Non-finite or non-positive depths */
+/* pass through the scale unchanged in kind (0 -> 0, inf -> inf, NaN ->     */
+/* NaN).                                                                    */
+int oceansim_cam_condition(const oceansim_cam_frame *frames, int32_t n_frames, void *stream);
+
+/* Adjoint of the range conversion: grad_zdepth = grad_range * r / z, the   */
+/* per-pixel scale above.  Decoding has no adjoint (its input is integer).  */
+int oceansim_cam_condition_backward(const oceansim_cam_frame *frames, int32_t n_frames, void *stream);
+
+/* One image to encode: I planar [3][H][W] linear float in, srgb_out         */
+/* interleaved [H][W][channels_out] bytes out (4: alpha written as 255).    */
+typedef struct {
+    const float *I;
+    uint8_t *srgb_out;
+    int32_t H, W;              /* 0 <= H, W <= 65535                        */
+    int32_t channels_out;      /* 3 or 4                                   */
+} oceansim_cam_out_frame;
+
+int oceansim_cam_encode(const oceansim_cam_out_frame *frames, int32_t n_frames, void *stream);
 
 /* ======================================================================== */
 /* Plans: a batch of sonar and camera frames prepared once and launched     */

@@ -57,6 +57,16 @@ class UwFrame(C.Structure):
                 ("param_row", C.c_int32), ("grad_out", _P), ("grad_J", _P), ("grad_depth", _P)]
 
 
+class CamFrame(C.Structure):
+    _fields_ = [("srgb_in", _P), ("zdepth", _P), ("J", _P), ("range", _P), ("grad_range", _P),
+                ("grad_zdepth", _P), ("H", C.c_int32), ("W", C.c_int32), ("channels_in", C.c_int32),
+                ("fx", C.c_float), ("fy", C.c_float), ("cx", C.c_float), ("cy", C.c_float)]
+
+
+class CamOutFrame(C.Structure):
+    _fields_ = [("I", _P), ("srgb_out", _P), ("H", C.c_int32), ("W", C.c_int32), ("channels_out", C.c_int32)]
+
+
 class OceansimError(RuntimeError):
     def __init__(self, status: int, where: str, text: str):
         super().__init__("%s: %s (%s)" % (where, STATUS_NAMES.get(status, status), text))
@@ -81,6 +91,9 @@ def _load() -> C.CDLL:
         "oceansim_uw_workspace_size": [UF, C.c_int32, C.c_int32, C.POINTER(C.c_size_t)],
         "oceansim_uw_form": [UF, C.c_int32, _P, C.c_int32, _P, C.c_size_t, _P],
         "oceansim_uw_form_backward": [UF, C.c_int32, _P, C.c_int32, _P, _P, C.c_size_t, _P],
+        "oceansim_cam_condition": [C.POINTER(CamFrame), C.c_int32, _P],
+        "oceansim_cam_condition_backward": [C.POINTER(CamFrame), C.c_int32, _P],
+        "oceansim_cam_encode": [C.POINTER(CamOutFrame), C.c_int32, _P],
     }
     for name, args in sig.items():
         fn = getattr(lib, name)
@@ -112,7 +125,8 @@ EXPORTED = ("oceansim_last_error", "oceansim_abi_version", "oceansim_sonar_works
             "oceansim_uw_form", "oceansim_uw_form_backward", "oceansim_fan_stencil_size",
             "oceansim_trace_enable", "oceansim_trace_summary", "oceansim_plan_create",
             "oceansim_plan_forward", "oceansim_plan_backward", "oceansim_plan_shape",
-            "oceansim_plan_destroy")
+            "oceansim_plan_destroy", "oceansim_cam_condition", "oceansim_cam_condition_backward",
+            "oceansim_cam_encode")
 
 PLAN_BACKWARD, PLAN_GRAPH, PLAN_AUTOTUNE = 1, 2, 4
 
@@ -169,6 +183,21 @@ def oceansim_uw_workspace_size(frames, with_backward: bool) -> int:
     check(lib.oceansim_uw_workspace_size(ptr, n, int(with_backward), C.byref(out)),
           "oceansim_uw_workspace_size")
     return out.value
+
+
+def oceansim_cam_condition(frames, stream: int) -> None:
+    ptr, n, _keep = _frames(frames, CamFrame)
+    check(lib.oceansim_cam_condition(ptr, n, stream), "oceansim_cam_condition")
+
+
+def oceansim_cam_condition_backward(frames, stream: int) -> None:
+    ptr, n, _keep = _frames(frames, CamFrame)
+    check(lib.oceansim_cam_condition_backward(ptr, n, stream), "oceansim_cam_condition_backward")
+
+
+def oceansim_cam_encode(frames, stream: int) -> None:
+    ptr, n, _keep = _frames(frames, CamOutFrame)
+    check(lib.oceansim_cam_encode(ptr, n, stream), "oceansim_cam_encode")
 
 
 def oceansim_uw_form(frames, params_dev: int, n_param_rows: int, workspace: int, workspace_bytes: int,

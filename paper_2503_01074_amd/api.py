@@ -12,7 +12,7 @@ from typing import List, Optional, Sequence
 import torch
 
 from . import _lib
-from ._lib import (SONAR_GRAD_WIDTH, WATER_GRAD_WIDTH, SonarFrame, UwFrame)
+from ._lib import (SONAR_GRAD_WIDTH, WATER_GRAD_WIDTH, CamFrame, CamOutFrame, SonarFrame, UwFrame)
 
 SONAR_PARAM_WIDTH = 8     # alpha, gain, sigma_phi, sigma_sa, sigma_sm, 3 reserved
 WATER_PARAM_WIDTH = 12    # beta_d[3], beta_b[3], b_inf[3], 3 reserved
@@ -230,6 +230,69 @@ def uw_form_backward(Js, depths, water: torch.Tensor, grad_outs, rows=None, want
     _lib.oceansim_uw_form_backward(structs, _ptr(water), int(water.shape[0]), _ptr(g_w), _ptr(ws), ws.numel(),
                                    _stream(water.device))
     return g_w, gJ, gd
+
+
+# --------------------------------------------------------------------------- #
+# camera input conditioning and output encoding                                #
+# --------------------------------------------------------------------------- #
+
+def _cam_struct(H, W, intr, srgb=None, zdepth=None, J=None, rng=None, grad_range=None, grad_z=None) -> CamFrame:
+    s = CamFrame()
+    s.srgb_in, s.zdepth, s.J, s.range = _ptr(srgb), _ptr(zdepth), _ptr(J), _ptr(rng)
+    s.grad_range, s.grad_zdepth = _ptr(grad_range), _ptr(grad_z)
+    s.H, s.W = int(H), int(W)
+    s.channels_in = int(srgb.shape[-1]) if srgb is not None else 3
+    s.fx, s.fy, s.cx, s.cy = (float(v) for v in intr)
+    return s
+
+
+def cam_condition(srgbs: Sequence[Optional[torch.Tensor]], zdepths: Sequence[Optional[torch.Tensor]],
+                  intrinsics: Sequence[Sequence[float]]):
+    """Frames of uint8 sRGB [H, W, 3 or 4] and/or z-depth [H, W] (either may be
+    None) -> (list of linear planar J [3, H, W] or None, list of range [H, W] or
+    None), one launch per 16 frames.  intrinsics: (fx, fy, cx, cy) per frame."""
+    Js, rngs, structs = [], [], []
+    for srgb, z, intr in zip(srgbs, zdepths, intrinsics):
+        ref = srgb if srgb is not None else z
+        if ref is None:             # nothing to condition in this frame
+            Js.append(None)
+            rngs.append(None)
+            continue
+        H, W = int(ref.shape[0]), int(ref.shape[1])
+        J = torch.empty(3, H, W, dtype=torch.float32, device=ref.device) if srgb is not None else None
+        r = torch.empty_like(z) if z is not None else None
+        Js.append(J)
+        rngs.append(r)
+        structs.append(_cam_struct(H, W, intr, srgb, z, J, r))
+    if structs:
+        dev = next(t for t in list(srgbs) + list(zdepths) if t is not None).device   # noqa: E501
+        _lib.oceansim_cam_condition(structs, _stream(dev))
+    return Js, rngs
+
+
+def cam_condition_backward(grad_ranges: Sequence[torch.Tensor], intrinsics: Sequence[Sequence[float]]):
+    """dL/d(range) [H, W] per frame -> dL/d(z-depth) [H, W] per frame."""
+    gz = [torch.empty_like(g) for g in grad_ranges]
+    structs = [_cam_struct(g.shape[0], g.shape[1], intr, grad_range=g, grad_z=o)
+               for g, o, intr in zip(grad_ranges, gz, intrinsics)]
+    if structs:
+        _lib.oceansim_cam_condition_backward(structs, _stream(grad_ranges[0].device))
+    return gz
+
+
+def cam_encode(images: Sequence[torch.Tensor], channels_out: int = 3) -> List[torch.Tensor]:
+    """Planar linear [3, H, W] float images -> uint8 sRGB [H, W, channels_out]."""
+    outs, structs = [], []
+    for I in images:
+        H, W = int(I.shape[-2]), int(I.shape[-1])
+        o = torch.empty(H, W, channels_out, dtype=torch.uint8, device=I.device)
+        s = CamOutFrame()
+        s.I, s.srgb_out, s.H, s.W, s.channels_out = _ptr(I), _ptr(o), H, W, channels_out
+        outs.append(o)
+        structs.append(s)
+    if structs:
+        _lib.oceansim_cam_encode(structs, _stream(images[0].device))
+    return outs
 
 
 # --------------------------------------------------------------------------- #

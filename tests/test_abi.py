@@ -27,7 +27,7 @@ def test_exports_every_declared_function():
     for name in sorted(declared):
         assert hasattr(so, name), name
     assert set(lib.EXPORTED) == declared
-    assert lib.oceansim_abi_version() == 2
+    assert lib.oceansim_abi_version() == 3
 
 
 def test_struct_layout_matches_header():
@@ -37,6 +37,8 @@ def test_struct_layout_matches_header():
         "oceansim_sonar_frame": lib.SonarFrame,
         "oceansim_water_params": lib.WaterParams,
         "oceansim_uw_frame": lib.UwFrame,
+        "oceansim_cam_frame": lib.CamFrame,
+        "oceansim_cam_out_frame": lib.CamOutFrame,
     }
     lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "oceansim.h"', "int main(void){"]
     for cname, py in structs.items():
@@ -248,3 +250,46 @@ def test_plan_rejections():
     assert so.oceansim_plan_backward(None, None) == -1
     assert so.oceansim_plan_shape(None, (C.c_int32 * 4)()) == -1
     assert so.oceansim_plan_destroy(None) == 0
+
+
+def _cam(lib, **over):
+    f = lib.CamFrame()
+    f.srgb_in, f.zdepth, f.J, f.range = FAKE, FAKE, FAKE, FAKE
+    f.grad_range, f.grad_zdepth = FAKE, FAKE
+    f.H, f.W, f.channels_in = 480, 640, 3
+    f.fx, f.fy, f.cx, f.cy = 500.0, 500.0, 320.0, 240.0
+    for k, v in over.items():
+        setattr(f, k, v)
+    return f
+
+
+@pytest.mark.parametrize("over,fn,text", [
+    (dict(H=-1), "fwd", "H = -1"), (dict(W=65536), "fwd", "65536"),
+    (dict(channels_in=2), "fwd", "channels_in"), (dict(J=0), "fwd", "without J"),
+    (dict(range=0), "fwd", "without range"), (dict(srgb_in=FAKE + 4), "fwd", "aligned"),
+    (dict(fx=0.0), "fwd", "fx, fy"), (dict(cy=float("nan")), "fwd", "fx, fy"),
+    (dict(fy=float("inf")), "bwd", "fx, fy"), (dict(grad_zdepth=0), "bwd", "grad_range"),
+    (dict(grad_range=FAKE + 8), "bwd", "aligned"),
+])
+def test_cam_rejections(over, fn, text):
+    """Camera conditioning validates every frame before any launch."""
+    lib = _lib()
+    so = lib.lib
+    frames = (lib.CamFrame * 2)(_cam(lib), _cam(lib, **over))
+    call = so.oceansim_cam_condition if fn == "fwd" else so.oceansim_cam_condition_backward
+    assert call(frames, 2, None) in (-1, -2)
+    assert text in lib.last_error() and "frame 1" in lib.last_error()
+
+
+def test_cam_encode_rejections():
+    lib = _lib()
+    so = lib.lib
+    good = lib.CamOutFrame(FAKE, FAKE, 4, 4, 3)
+    for bad, text in [(lib.CamOutFrame(FAKE, FAKE, 4, 4, 5), "channels_out"),
+                      (lib.CamOutFrame(0, FAKE, 4, 4, 3), "required"),
+                      (lib.CamOutFrame(FAKE, FAKE + 3, 4, 4, 3), "aligned"),
+                      (lib.CamOutFrame(FAKE, FAKE, 70000, 4, 3), "outside")]:
+        assert so.oceansim_cam_encode((lib.CamOutFrame * 2)(good, bad), 2, None) in (-1, -2)
+        assert text in lib.last_error()
+    assert so.oceansim_cam_encode(None, 0, None) == 0
+    assert so.oceansim_cam_encode(None, -1, None) == -1

@@ -37,7 +37,7 @@ def test_no_kernel_keeps_arrays_on_the_stack():
 @pytest.mark.skipif(not REPORTS, reason="library not built in this tree")
 def test_plan_hot_kernels_have_no_spills():
     ks = _kernels()
-    hot = [k for k in ks if any(n in k for n in ("k_fant_bwd", "k_ret_uw_bwd", "k_bin_uw", "6k_tileI", "5k_fanI",
+    hot = [k for k in ks if any(n in k for n in ("k_fant_bwd", "k_ret_uw_bwd", "k_bin_uw", "k_cam_", "6k_tileI", "5k_fanI",
                                                   "k_uw_bwd", "4k_uwI"))]
     assert len(hot) >= 10
     for k in hot:
