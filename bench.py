@@ -653,8 +653,8 @@ def main():
     if not args.no_batched:
         extra = batched_legs(torch, dev, args.steps)
         extra["calibration_c5"] = calibration_leg(torch, dev, args.steps, args.c5_frames)
-    extra["camera_io"] = camera_io_leg(torch, dev, args.steps)
-    log("camera io: %s" % extra["camera_io"])
+        extra["camera_io"] = camera_io_leg(torch, dev, args.steps)
+        log("camera io: %s" % extra["camera_io"])
     cpu = None
     if not args.no_cpu:
         log("timing the FP64 oracle on the host")
