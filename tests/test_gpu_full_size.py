@@ -7,10 +7,17 @@ backward plan, every frame and gradient checked; and eight frames of the
 calibration shape (2048 x 1024 returns, 2048 x 2048 bins, no fan, plus
 1920 x 1080 camera frames) through a backward plan.
 
-Bins bit-exact, images to 1e-5 relative, gradients to 1e-5 of the sums of
-their terms' magnitudes (as in the small-size parity tests).
+Bins bit-exact, images to 1e-5 relative.  Gradients: every component to
+1e-3 relative of the FP64 oracle's analytic gradient (the reflectivity table
+with a floor at 1e-3 of its largest component; scalar parameters each to
+1e-3 of their own value), and to 1e-5 of the sum of its terms' magnitudes;
+on the differentiable batch also to 1e-3 of FP64 central differences of the
+oracle's forward pass (tests/golden/c4_central_differences.json, written by
+tests/golden/make_c4_fd.py).
 """
 import copy
+import json
+import os
 import sys
 
 import numpy as np
@@ -19,7 +26,7 @@ import pytest
 import oracle
 from oracle import SonarConfig
 import workloads as W
-from _tol import assert_grad_cond, assert_image_close
+from _tol import assert_grad_close, assert_grad_cond, assert_grad_scalars, assert_image_close
 
 pytestmark = pytest.mark.gpu
 
@@ -67,8 +74,12 @@ def _check_backward(plan, frames, refl, gpol, gfan, cams, water, gout, what):
         c_refl += ca
         o_par += b
         c_par += cb
-    assert_grad_cond(plan.grad_refl.cpu().numpy(), o_refl, c_refl, what="%s refl" % what)
-    assert_grad_cond(plan.grad_sonar_params.cpu().numpy()[0, :5], o_par, c_par, what="%s sonar params" % what)
+    g_refl = plan.grad_refl.cpu().numpy()
+    g_par = plan.grad_sonar_params.cpu().numpy()[0, :5]
+    assert_grad_cond(g_refl, o_refl, c_refl, what="%s refl" % what)
+    assert_grad_cond(g_par, o_par, c_par, what="%s sonar params" % what)
+    assert_grad_close(g_refl, o_refl, 1e-3, what="%s refl (1e-3 relative)" % what)
+    assert_grad_scalars(g_par, o_par, 1e-3, what="%s sonar params (1e-3 relative)" % what)
     if not cams:
         return
     bd, bb, bi = (x.astype(np.float64) for x in (water.beta_d, water.beta_b, water.b_inf))
@@ -90,7 +101,9 @@ def _check_backward(plan, frames, refl, gpol, gfan, cams, water, gout, what):
                                        bi[:, None, None] * bb[:, None, None] * np.exp(-bb[:, None, None] * d))).sum(0)
             err = np.abs(o["grad_depth"].cpu().numpy().astype(np.float64) - gd)
             assert np.all(err <= 1e-5 * cond + 1e-30), "%s grad depth %d" % (what, k)
-    assert_grad_cond(plan.grad_water.cpu().numpy()[0], o_w, c_w, what="%s water" % what)
+    g_w = plan.grad_water.cpu().numpy()[0]
+    assert_grad_cond(g_w, o_w, c_w, what="%s water" % what)
+    assert_grad_scalars(g_w, o_w, 1e-3, what="%s water (1e-3 relative)" % what)
 
 
 def _fill_grads(torch, plan, gpol, gfan, gout):
@@ -186,6 +199,18 @@ def test_differentiable_batch_plan():
     torch.cuda.synchronize()
     _check_sonar_forward(plan, frames, refl, range(len(frames)), "differentiable")
     _check_backward(plan, frames, refl, gpol, gfan, cams, waters[0], gout, "differentiable")
+    # against FP64 central differences of the oracle's forward pass
+    with open(os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden",
+                           "c4_central_differences.json")) as fh:
+        fd = json.load(fh)
+    g_par = plan.grad_sonar_params.cpu().numpy()[0, :5]
+    assert_grad_scalars(g_par, fd["sonar"], 1e-3, what="differentiable sonar params vs central differences")
+    g_refl = plan.grad_refl.cpu().numpy()
+    ms = sorted(int(m) for m in fd["refl"])
+    assert_grad_scalars(g_refl[ms], [fd["refl"][str(m)] for m in ms], 1e-3,
+                        what="differentiable reflectivities %s vs central differences" % ms)
+    assert_grad_scalars(plan.grad_water.cpu().numpy()[0], fd["water"], 1e-3,
+                        what="differentiable water vs central differences")
     plan.close()
 
 

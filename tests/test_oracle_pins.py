@@ -529,3 +529,21 @@ def test_sonar_backward_conditions_expand_the_fan():
     # without a fan gradient the expansion is the polar gradient itself
     _, _, g_out2, _, a_par2 = oracle.sonar_backward(cfg, hits, hits.refl, wp, None, with_abs=True)
     assert a_par2[3] == pytest.approx(float(np.abs(g_out2 * fsa).sum()), rel=1e-12)
+
+
+def test_differentiable_batch_gradients_match_stored_central_differences():
+    """The oracle's analytic gradients on the whole differentiable batch (32
+    sonar + 32 camera frames) against FP64 central differences of its own
+    forward pass, stored by tests/golden/make_c4_fd.py: 1e-7 relative."""
+    import json
+    import os
+
+    import _fd
+    with open(os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden",
+                           "c4_central_differences.json")) as fh:
+        fd = json.load(fh)
+    g_refl, g_par, g_w = _fd.c4_oracle_gradients()
+    np.testing.assert_allclose(g_par, fd["sonar"], rtol=1e-7, atol=0)
+    for m, v in fd["refl"].items():
+        assert g_refl[int(m)] == pytest.approx(v, rel=1e-7)
+    np.testing.assert_allclose(g_w, fd["water"], rtol=1e-7, atol=0)
