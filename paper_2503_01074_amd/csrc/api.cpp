@@ -125,7 +125,7 @@ int pow2_at_least(long long v) {
 }
 
 int plan_sonar(const oceansim_sonar_frame *frames, int n_frames, int n_param_rows, int n_mat, bool backward,
-               SonarPlan &P, const Tuning *tune, bool force_table) {
+               SonarPlan &P, const Tuning *tune, bool force_table, bool pair_mode) {
     if (n_frames < 0) return fail(OCEANSIM_E_INVALID_ARG, "n_frames < 0");
     if (n_frames > 0 && !frames) return fail(OCEANSIM_E_INVALID_ARG, "frames is NULL");
     if (n_mat < 1) return fail(OCEANSIM_E_INVALID_ARG, "n_materials must be >= 1");
@@ -143,14 +143,14 @@ int plan_sonar(const oceansim_sonar_frame *frames, int n_frames, int n_param_row
     // 1024..4096 bins each; a tile holds whole range rows.  Backward tiles:
     // up to 2048 bins (their pixel work grows with the tile's radial extent).
     long long tb_target = std::min<long long>(kMaxTileBins, std::max<long long>(1024, total_nb / 512));
-    if (tune && tune->fwd_tile_bins > 0) tb_target = std::min(tune->fwd_tile_bins, kMaxTileBins);
+    if (tune && tune->fwd_tile_bins > 0) tb_target = std::min(tune->fwd_tile_bins, kMaxFwdTileBins);
     const int tb_b = (tune && tune->bwd_tile_bins > 0) ? std::min(tune->bwd_tile_bins, kMaxTileBins) : 2048;
     for (int i = 0; i < n_frames; ++i) {
         const oceansim_sonar_frame &fr = frames[i];
         SonarDev &d = P.dev[i];
         int rpt = std::max(1, std::min(fr.n_range, (int)(tb_target / fr.n_azimuth)));
         int n_tiles = (fr.n_range + rpt - 1) / rpt;
-        while (n_tiles > kMaxTiles && (rpt + 1) * fr.n_azimuth <= kMaxTileBins) {
+        while (n_tiles > kMaxTiles && (rpt + 1) * fr.n_azimuth <= kMaxFwdTileBins) {
             ++rpt;
             n_tiles = (fr.n_range + rpt - 1) / rpt;
         }
@@ -177,8 +177,10 @@ int plan_sonar(const oceansim_sonar_frame *frames, int n_frames, int n_param_row
     };
     while (chunk < 4096 && table_entries(chunk) > 2 * total_n + (1 << 20)) chunk *= 2;
     if (tune && tune->chunk > 0) chunk = tune->chunk;
+    // the return-gather workgroups (256 threads) take at most 4096 returns
+    const int ret_chunk = std::min(chunk, 4096);
     P.grid.chunk = chunk;
-    P.grid.ret_chunk = chunk;
+    P.grid.ret_chunk = ret_chunk;
     P.grid.max_tiles = max_tiles;
     P.grid.max_tile_bins = max_tile_bins;
     P.grid.max_tile_bins_b = max_tile_bins_b;
@@ -196,7 +198,9 @@ int plan_sonar(const oceansim_sonar_frame *frames, int n_frames, int n_param_row
     P.off_chunk_off.assign(n_frames, 0);
     P.off_polar.assign(n_frames, (size_t)-1);
     P.off_cols.assign(n_frames, (size_t)-1);
-    P.off_grad_img.assign(n_frames, 0);
+    P.off_grad_img.assign(n_frames, (size_t)-1);
+    P.off_pair_r.assign(n_frames, (size_t)-1);
+    P.off_cemax.assign(n_frames, (size_t)-1);
     int bin_blocks = 0, tile_blocks = 0, tile_b_blocks = 0, fan_blocks = 0, ret_blocks = 0, fant_blocks = 0;
     int row_blocks = 0, max_rows_per_tile = 0;   // range-wise normalisation
     P.off_dldq.assign(n_frames, (size_t)-1);
@@ -216,8 +220,9 @@ int plan_sonar(const oceansim_sonar_frame *frames, int n_frames, int n_param_row
         d.fan_w = fr.fan_w;
         d.chunk = chunk;
         d.n_chunks = (int)((fr.n_returns + chunk - 1) / chunk);
-        d.ret_chunk = chunk;
-        d.n_ret_chunks = d.n_chunks;
+        d.ret_chunk = ret_chunk;
+        d.n_ret_chunks = (int)((fr.n_returns + ret_chunk - 1) / ret_chunk);
+        d.matp = n_mat <= kLaneHistMats ? 1 : 0;
         d.half_w = (fr.fan_w + 1) / 2;
         d.fan_bpr = (d.half_w + kFanTileU - 1) / kFanTileU;
         d.stencil = gcast(static_cast<int4 *>(fr.fan_stencil));
@@ -237,7 +242,10 @@ int plan_sonar(const oceansim_sonar_frame *frames, int n_frames, int n_param_row
         d.blk[KFANT] = fant_blocks;
         d.ft_mirror = backward && fan_operator_layout(fr) == 2 ? 1 : 0;
         const long long op_rows = d.ft_mirror ? (long long)fr.n_range * ((fr.n_azimuth + 1) / 2) : nb;
-        d.n_fant_blocks = backward ? (int)((op_rows + kBlock * fant_bpt - 1) / (kBlock * fant_bpt)) : 0;
+        // the pair backward reads the polar gradient of frames without a
+        // transposed fan operator directly: operator rows for the others only
+        const bool fant_rows = backward && (!pair_mode || fan_operator_layout(fr) != 0);
+        d.n_fant_blocks = fant_rows ? (int)((op_rows + kBlock * fant_bpt - 1) / (kBlock * fant_bpt)) : 0;
         fant_blocks += d.n_fant_blocks;
         bin_blocks += d.n_chunks;
         tile_blocks += d.n_tiles;
@@ -293,8 +301,12 @@ int plan_sonar(const oceansim_sonar_frame *frames, int n_frames, int n_param_row
             P.off_chunk_off[i] = take(sizeof(int) * (size_t)d.n_chunks * (d.n_tiles + 1));
             if (!fr.polar) P.off_polar[i] = take(sizeof(float) * (size_t)nb);
             if (d.fan_blocks > 0) P.off_cols[i] = take(sizeof(double) * 2 * (size_t)fr.n_azimuth);
+            if (pair_mode) {
+                P.off_pair_r[i] = take(sizeof(float) * (size_t)d.n_chunks * chunk);
+                P.off_cemax[i] = take(sizeof(float) * (size_t)d.n_tiles);
+            }
         } else {
-            P.off_grad_img[i] = take(sizeof(float) * (size_t)nb);
+            if (d.n_fant_blocks > 0 || !pair_mode) P.off_grad_img[i] = take(sizeof(float) * (size_t)nb);
             if (fr.range_norm) P.off_dldq[i] = take(sizeof(float) * (size_t)nb);
         }
     }
@@ -308,6 +320,7 @@ int plan_sonar(const oceansim_sonar_frame *frames, int n_frames, int n_param_row
     P.grid.fant_blocks = fant_blocks;
     P.grid.fant_bpt = fant_bpt;
     P.grid.use_fant = 0;
+    P.grid.pair_bwd = backward && pair_mode ? 1 : 0;
     P.grid.fant_mirror = 0;
     for (const SonarDev &d : P.dev) P.grid.fant_mirror |= d.ft_mirror;
     P.grid.all_saved = 1;
@@ -315,14 +328,31 @@ int plan_sonar(const oceansim_sonar_frame *frames, int n_frames, int n_param_row
         if (frames[i].grad_fan && !frames[i].fan_stencil) P.grid.all_saved = 0;
     if (backward) {
         // slots for either backward decomposition of the polar gradient
-        P.n_slots = std::max(tile_b_blocks, fant_blocks) + ret_blocks + row_blocks;
+        // (the pair backward: operator rows, then one slot per forward tile)
+        P.n_slots = pair_mode ? fant_blocks + tile_blocks : std::max(tile_b_blocks, fant_blocks) + ret_blocks + row_blocks;
         // five FP64 partial sums per slot (column-major), then the slot's parameter row
         P.off_part = take((sizeof(double) * 5 + sizeof(int)) * (size_t)std::max(1, P.n_slots));
         if (n_mat <= kLaneHistMats)
-            P.off_refl_part = take(sizeof(double) * (size_t)std::max(1, ret_blocks) * n_mat);
+            P.off_refl_part = take(sizeof(double) * (size_t)std::max(1, pair_mode ? tile_blocks : ret_blocks) * n_mat);
     }
     P.bytes = std::max<size_t>(off, kWsAlign);
     return OCEANSIM_OK;
+}
+
+bool pair_backward_ok(const oceansim_sonar_frame *frames, int n_frames, int n_mat) {
+    if (n_mat > kLaneHistMats) return false;
+    for (int i = 0; i < n_frames; ++i)
+        if (frames[i].range_norm) return false;
+    return true;
+}
+
+void link_pairs(SonarPlan &bwd, const SonarPlan &fwd) {
+    for (size_t i = 0; i < bwd.dev.size() && i < fwd.dev.size(); ++i) {
+        bwd.dev[i].pairs = fwd.dev[i].pairs;
+        bwd.dev[i].chunk_off = fwd.dev[i].chunk_off;
+        bwd.dev[i].pair_r = fwd.dev[i].pair_r;
+        bwd.dev[i].tile_cemax = fwd.dev[i].tile_cemax;
+    }
 }
 
 void carve_sonar(SonarPlan &P, char *ws, bool backward) {
@@ -333,8 +363,10 @@ void carve_sonar(SonarPlan &P, char *ws, bool backward) {
             d.chunk_off = gcast(reinterpret_cast<int *>(ws + P.off_chunk_off[i]));
             if (P.off_polar[i] != (size_t)-1) d.polar = gcast(reinterpret_cast<float *>(ws + P.off_polar[i]));
             if (P.off_cols[i] != (size_t)-1) d.cols = gcast(reinterpret_cast<double2 *>(ws + P.off_cols[i]));
+            if (P.off_pair_r[i] != (size_t)-1) d.pair_r = gcast(reinterpret_cast<float *>(ws + P.off_pair_r[i]));
+            if (P.off_cemax[i] != (size_t)-1) d.tile_cemax = gcast(reinterpret_cast<float *>(ws + P.off_cemax[i]));
         } else {
-            d.grad_img = gcast(reinterpret_cast<float *>(ws + P.off_grad_img[i]));
+            if (P.off_grad_img[i] != (size_t)-1) d.grad_img = gcast(reinterpret_cast<float *>(ws + P.off_grad_img[i]));
             if (P.off_dldq[i] != (size_t)-1) d.dldq = gcast(reinterpret_cast<float *>(ws + P.off_dldq[i]));
         }
     }

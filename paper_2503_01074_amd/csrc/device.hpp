@@ -11,7 +11,9 @@ namespace osim {
 
 constexpr int kBlock = 256;          // threads per workgroup (4 wave64)
 constexpr int kWave = 64;
-constexpr int kMaxTileBins = 4096;   // polar bins owned by one tile workgroup (one row at least)
+constexpr int kMaxTileBins = 4096;   // polar bins of a backward tile workgroup (one row at least)
+constexpr int kMaxFwdTileBins = 16384;   // polar bins owned by one forward tile workgroup
+constexpr int kWideThreads = 512;    // threads of the wide binning, forward-tile and pair-backward workgroups
 constexpr int kMaxTiles = 4096;      // tiles per frame (LDS histogram in the binning pass)
 constexpr int kXcds = 8;            // accelerator complex dies (each with its own L2)
 constexpr int kFanRows = 2;        // fan rows per thread (one pixel pair each, 8 rows apart)
@@ -73,7 +75,12 @@ struct SonarDev {
     gptr<float> fan;
     gptr<int> bin_of_return;
     gptr<const float> grad_polar, grad_fan;
-    gptr<uint2> pairs;          // binning pass output: (tile-local bin, intensity)
+    gptr<uint2> pairs;          // binning pass output: (tile-local bin, intensity), or with
+                                // matp (tile-local bin | material << 16, cos x attenuation)
+    gptr<float> pair_r;         // the pairs' ranges (same order), for the pair backward; or nullptr
+    gptr<float> tile_cemax;     // per forward tile, the largest |cos x attenuation| of its pairs
+                                // (written by the forward tile with pair_r; bounds the pair backward's sums)
+    int matp;                   // pairs carry the material id (tables of at most 64 materials)
     gptr<int> chunk_off;        // [n_chunks][n_tiles + 1] exclusive offsets per chunk
     gptr<float> grad_img;       // backward: dL/d(polar image) [nb]
     long long n;                // returns

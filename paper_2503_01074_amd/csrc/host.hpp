@@ -30,6 +30,8 @@ struct SonarPlan {
     // workspace offsets
     size_t off_table = 0;
     std::vector<size_t> off_pairs, off_chunk_off, off_polar, off_grad_img, off_cols;
+    std::vector<size_t> off_pair_r;   // ranges of the pairs (forward of a pair-backward plan)
+    std::vector<size_t> off_cemax;    // per-tile largest |cos x attenuation| (same)
     std::vector<size_t> off_dldq;   // range-normalised frames' dL/dQ (backward)
     size_t off_part = 0, off_refl_part = 0;
     int n_slots = 0;
@@ -59,8 +61,18 @@ int hip_fail(hipError_t e, const char *what);
 
 // force_table: reserve a device frame table even for a single frame (plans
 // always launch from tables; the plain entry points pass one frame by value).
+// pair_mode (plans): the backward runs from the forward's material pairs
+// (k_pair_bwd): the forward keeps the pairs' ranges, the backward takes one
+// workgroup per forward tile and operator rows only for frames with a fan
+// gradient; link_pairs then points the backward frames at the forward's pairs.
 int plan_sonar(const oceansim_sonar_frame *frames, int n_frames, int n_param_rows, int n_mat, bool backward,
-               SonarPlan &P, const Tuning *tune, bool force_table = false);
+               SonarPlan &P, const Tuning *tune, bool force_table = false, bool pair_mode = false);
+// Whether a plan over these frames can take the pair backward: material
+// tables of at most 64 entries and no range-wise normalisation.
+bool pair_backward_ok(const oceansim_sonar_frame *frames, int n_frames, int n_mat);
+// Backward frames of a pair-backward plan read the pairs, offsets and ranges
+// of the forward frames (after both are carved).
+void link_pairs(SonarPlan &bwd, const SonarPlan &fwd);
 void carve_sonar(SonarPlan &P, char *ws, bool backward);
 int check_ws(void *ws, size_t have, size_t need);
 // threads: workgroup size of the kernel that runs the camera frames (the

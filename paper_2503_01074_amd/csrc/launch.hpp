@@ -55,6 +55,7 @@ struct SonarGrid {
     int fant_mirror;     // some frame's operator has the mirrored layout
     int row_blocks;      // backward: one workgroup per range row of the range-normalised frames
     int max_rows_per_tile;   // forward: widest tile (rows) of a range-normalised frame; 0: none
+    int pair_bwd;        // backward from the forward's material pairs (k_pair_bwd, one workgroup per forward tile)
 };
 
 constexpr int kBwdThreads = 512;   // threads of a backward polar-tile workgroup

@@ -49,6 +49,8 @@ struct oceansim_plan {
     // with both kinds of frames the camera frames ride along in the forward
     // binning launch of the sonar frames
     bool fused = false;
+    // the backward runs from the forward's material pairs (k_pair_bwd)
+    bool pair = false;
     hipGraphExec_t g_fwd = nullptr, g_bwd = nullptr;
 };
 
@@ -282,8 +284,8 @@ int autotune(oceansim_plan *p, hipStream_t st) {
     const int n = (int)p->sonar.size();
     std::vector<Candidate> cands;
     cands.push_back(Candidate{});   // the default shape is the reference
-    for (int ft : {1024, 2048, 4096})
-        for (int ch : {512, 1024, 2048, 4096}) {
+    for (int ft : {1024, 2048, 4096, 8192, 16384})
+        for (int ch : {512, 1024, 2048, 4096, 8192}) {
             Candidate c;
             c.t.fwd_tile_bins = ft;
             c.t.chunk = ch;
@@ -291,7 +293,7 @@ int autotune(oceansim_plan *p, hipStream_t st) {
         }
     size_t ws = 0;
     for (auto &c : cands) {
-        int rc = plan_sonar(p->sonar.data(), n, p->n_srows, p->n_mat, false, c.f, &c.t, true);
+        int rc = plan_sonar(p->sonar.data(), n, p->n_srows, p->n_mat, false, c.f, &c.t, true, p->pair);
         if (rc) return rc;
         ws = std::max(ws, c.f.bytes);
     }
@@ -367,7 +369,7 @@ int autotune(oceansim_plan *p, hipStream_t st) {
         // backward: bins per thread through the transposed fan operators,
         // after one forward under the chosen shape
         SonarPlan fp;
-        rc = plan_sonar(p->sonar.data(), n, p->n_srows, p->n_mat, false, fp, &chosen, true);
+        rc = plan_sonar(p->sonar.data(), n, p->n_srows, p->n_mat, false, fp, &chosen, true, p->pair);
         if (rc == OCEANSIM_OK && fp.bytes > ws) rc = fail(OCEANSIM_E_WORKSPACE, "autotune: forward workspace");
         std::vector<Candidate> bc;
         for (int bpt : {0, 1, 2, 4}) {   // 0: the size heuristic, the reference
@@ -379,7 +381,7 @@ int autotune(oceansim_plan *p, hipStream_t st) {
         size_t wsb = 0;
         for (auto &c : bc) {
             if (rc) break;
-            rc = plan_sonar(p->sonar.data(), n, p->n_srows, p->n_mat, true, c.b, &c.t, true);
+            rc = plan_sonar(p->sonar.data(), n, p->n_srows, p->n_mat, true, c.b, &c.t, true, p->pair);
             attach_fan_transposes(p, c.b);
             wsb = std::max(wsb, c.b.bytes);
         }
@@ -400,6 +402,7 @@ int autotune(oceansim_plan *p, hipStream_t st) {
             for (size_t k = 0; k < bc.size() && e == hipSuccess; ++k) {
                 Candidate &c = bc[k];
                 carve_sonar(c.b, tb, true);
+                if (p->pair) link_pairs(c.b, fp);
                 e = upload_table(c.b.dev, tb, c.b.off_table, st);
                 const SonarDev *table = reinterpret_cast<const SonarDev *>(tb + c.b.off_table);
                 auto run = [&]() {
@@ -422,7 +425,9 @@ int autotune(oceansim_plan *p, hipStream_t st) {
                 if (k == 0) ref_g = g;
                 float peak = 0.0f;
                 for (float v : ref_g) peak = std::max(peak, std::fabs(v));
-                c.ok = true;
+                // an all-zero reference (zero loss gradients) checks nothing:
+                // then only the default shape is accepted
+                c.ok = k == 0 || peak > 0.0f;
                 for (size_t i = 0; i < ng; ++i)
                     if (!(std::fabs(g[i] - ref_g[i]) <= 1e-5f * std::max(std::fabs(ref_g[i]), 1e-3f * peak)))
                         c.ok = false;
@@ -693,6 +698,7 @@ int oceansim_plan_create(const oceansim_sonar_frame *sonar, int32_t n_sonar, con
         if (!rc && bwd) rc = plan_sonar(p->sonar.data(), n_sonar, n_sonar_rows, n_materials, true, p->sb, nullptr);
     }
     p->fused = n_sonar > 0 && n_camera > 0;
+    p->pair = bwd && n_sonar > 0 && pair_backward_ok(p->sonar.data(), n_sonar, n_materials);
     if (!rc && n_camera > 0) {
         rc = plan_uw(p->camera.data(), n_camera, n_water_rows, false, p->uf, true);
         if (!rc && bwd) rc = plan_uw(p->camera.data(), n_camera, n_water_rows, true, p->ub, true);
@@ -766,9 +772,10 @@ int oceansim_plan_create(const oceansim_sonar_frame *sonar, int32_t n_sonar, con
     }
     // final shapes
     if (n_sonar > 0) {
-        rc = plan_sonar(p->sonar.data(), n_sonar, n_sonar_rows, n_materials, false, p->sf, &p->tune, true);
+        rc = plan_sonar(p->sonar.data(), n_sonar, n_sonar_rows, n_materials, false, p->sf, &p->tune, true, p->pair);
         if (!rc && bwd) {
-            rc = plan_sonar(p->sonar.data(), n_sonar, n_sonar_rows, n_materials, true, p->sb, &p->tune, true);
+            rc = plan_sonar(p->sonar.data(), n_sonar, n_sonar_rows, n_materials, true, p->sb, &p->tune, true,
+                            p->pair);
             attach_fan_transposes(p, p->sb);
         }
         if (rc) {
@@ -793,6 +800,7 @@ int oceansim_plan_create(const oceansim_sonar_frame *sonar, int32_t n_sonar, con
         e = upload_table(p->sf.dev, p->ws_sf, p->sf.off_table, st);
         if (e == hipSuccess && bwd) {
             carve_sonar(p->sb, p->ws_sb, true);
+            if (p->pair) link_pairs(p->sb, p->sf);
             e = upload_table(p->sb.dev, p->ws_sb, p->sb.off_table, st);
         }
     }

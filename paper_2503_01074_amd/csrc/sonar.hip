@@ -44,8 +44,13 @@ namespace osim {
 // ---------------------------------------------------------------------------
 // k_bin
 // ---------------------------------------------------------------------------
-// Binning chunk `bid` of the launch (kBlock threads, R returns each).
-template <class Src, int R>
+// Binning chunk `bid` of the launch (NT threads, R returns each).  With matp
+// the pairs carry the material id and the reflectivity-free factor
+// cos(gamma) exp(-kappa alpha r) (the tile multiplies by the reflectivity),
+// and with pair_r the ranges of the pairs are written too, in the same order
+// (a second pass through the staging memory): what the pair backward reads
+// instead of the returns.
+template <class Src, int NT, int R>
 __device__ __forceinline__ void bin_block(const Src &src, const oceansim_sonar_params *params, const float *refl,
                                           int n_mat, int bid) {
     extern __shared__ int4 lds_raw[];
@@ -55,13 +60,14 @@ __device__ __forceinline__ void bin_block(const Src &src, const oceansim_sonar_p
     const int tid = threadIdx.x;
     const int n_tiles = f.n_tiles;
     int *hist = reinterpret_cast<int *>(lds_raw);                    // n_tiles + 1
-    __shared__ int scan_tmp[kBlock];
-    uint2 *stage = reinterpret_cast<uint2 *>(hist + ((n_tiles + 1 + 3) & ~3));  // R * kBlock
+    __shared__ int scan_tmp[NT];
+    uint2 *stage = reinterpret_cast<uint2 *>(hist + ((n_tiles + 1 + 3) & ~3));  // R * NT
+    const bool matp = f.matp != 0;
 
     const float alpha = params[f.param_row].alpha;
-    const long long base = (long long)local * (R * kBlock);
+    const long long base = (long long)local * (R * NT);
 
-    for (int t = tid; t <= n_tiles; t += kBlock) hist[t] = 0;
+    for (int t = tid; t <= n_tiles; t += NT) hist[t] = 0;
     __syncthreads();
 
     // restrict-qualified views: the optional bin output never aliases the
@@ -75,14 +81,16 @@ __device__ __forceinline__ void bin_block(const Src &src, const oceansim_sonar_p
     const gptr<const int> __restrict__ MAT = f.mat;
     const float *__restrict__ RF = refl;
     const gptr<int> __restrict__ BO = f.bin_of_return;
-    int tile[R], rank[R];
+    const bool want_r = f.pair_r != nullptr;
+    // trk: tile << 14 | rank within the tile (-1: no pair); chunks hold at most 2^14 returns
+    int trk[R];
     uint32_t lbin[R];
-    float inten[R];
+    float inten[R], rr[R];
     // Groups of RG returns: all their loads, then their reflectivity gathers,
     // are in flight together (clamped indices: a load under the per-return
     // branches would wait for itself before the next return's); pairs for
     // small chunks, whose workgroups share the launch with camera workgroups
-    constexpr int RG = R <= 4 ? 2 : 4;
+    constexpr int RG = (R <= 4 && NT == kBlock) ? 2 : 4;
 #pragma unroll
     for (int q0 = 0; q0 < R; q0 += RG) {
         float xs[RG], ys[RG], zs[RG], nxs[RG], nys[RG], nzs[RG], rfs[RG];
@@ -90,7 +98,7 @@ __device__ __forceinline__ void bin_block(const Src &src, const oceansim_sonar_p
         double rs[RG];
 #pragma unroll
         for (int u = 0; u < RG; ++u) {
-            const long long k = base + (long long)(q0 + u) * kBlock + tid;
+            const long long k = base + (long long)(q0 + u) * NT + tid;
             const long long kc = k < f.n ? k : f.n - 1;
             xs[u] = X[kc];
             ys[u] = Y[kc];
@@ -102,48 +110,61 @@ __device__ __forceinline__ void bin_block(const Src &src, const oceansim_sonar_p
         }
 #pragma unroll
         for (int u = 0; u < RG; ++u) {
-            const long long k = base + (long long)(q0 + u) * kBlock + tid;
+            const long long k = base + (long long)(q0 + u) * NT + tid;
             const int b = return_bin(f, xs[u], ys[u], zs[u], ms[u], n_mat, rs[u]);
             if (BO && k < f.n) BO[k] = b;
             bs[u] = k < f.n ? b : -1;   // a valid bin implies a valid material
         }
+        if (!matp) {
 #pragma unroll
-        for (int u = 0; u < RG; ++u) rfs[u] = RF[bs[u] >= 0 ? ms[u] : 0];
+            for (int u = 0; u < RG; ++u) rfs[u] = RF[bs[u] >= 0 ? ms[u] : 0];
+        }
 #pragma unroll
         for (int u = 0; u < RG; ++u) {
             const int q = q0 + u, b = bs[u];
-            tile[q] = -1;
+            trk[q] = -1;
             if (b >= 0) {
                 float cosg, att;
-                inten[q] = return_intensity(f, xs[u], ys[u], zs[u], nxs[u], nys[u], nzs[u], rs[u], rfs[u], alpha,
-                                            cosg, att);
+                inten[q] = return_intensity(f, xs[u], ys[u], zs[u], nxs[u], nys[u], nzs[u], rs[u],
+                                            matp ? 1.0f : rfs[u], alpha, cosg, att);
+                rr[q] = (float)rs[u];
                 const int i = b / f.n_az;
                 const int t = i / f.rows_per_tile;
-                tile[q] = t;
-                lbin[q] = (uint32_t)(b - t * f.tile_bins);
-                rank[q] = atomicAdd(&hist[t], 1);
+                lbin[q] = (uint32_t)(b - t * f.tile_bins) | (matp ? (uint32_t)ms[u] << 16 : 0u);
+                trk[q] = (t << 14) | atomicAdd(&hist[t], 1);
             }
         }
     }
     __syncthreads();
-    block_exclusive_scan(hist, n_tiles, scan_tmp);
+    block_exclusive_scan<NT>(hist, n_tiles, scan_tmp);
 
     const gptr<int> off = f.chunk_off + (long long)local * (n_tiles + 1);
-    for (int t = tid; t <= n_tiles; t += kBlock) off[t] = hist[t];
+    for (int t = tid; t <= n_tiles; t += NT) off[t] = hist[t];
 #pragma unroll
     for (int q = 0; q < R; ++q)
-        if (tile[q] >= 0)
-            stage[hist[tile[q]] + rank[q]] = make_uint2(lbin[q], __float_as_uint(inten[q]));
+        if (trk[q] >= 0)
+            stage[hist[trk[q] >> 14] + (trk[q] & 16383)] = make_uint2(lbin[q], __float_as_uint(inten[q]));
     __syncthreads();
     const int total = hist[n_tiles];
     const gptr<uint2> dst = f.pairs + base;
-    for (int k = tid; k < total; k += kBlock) gstore(dst + k, stage[k]);
+    for (int k = tid; k < total; k += NT) gstore(dst + k, stage[k]);
+    if (want_r) {
+        // the ranges, in the pairs' order, through the same staging memory
+        float *rstage = reinterpret_cast<float *>(stage);
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < R; ++q)
+            if (trk[q] >= 0) rstage[hist[trk[q] >> 14] + (trk[q] & 16383)] = rr[q];
+        __syncthreads();
+        const gptr<float> rdst = f.pair_r + base;
+        for (int k = tid; k < total; k += NT) rdst[k] = rstage[k];
+    }
 }
 
-template <class Src, int R>
-__global__ __launch_bounds__(kBlock) void k_bin(Src src, const oceansim_sonar_params *params,
-                                                const float *refl, int n_mat) {
-    bin_block<Src, R>(src, params, refl, n_mat, blockIdx.x);
+template <class Src, int NT, int R>
+__global__ __launch_bounds__(NT) void k_bin(Src src, const oceansim_sonar_params *params, const float *refl,
+                                            int n_mat) {
+    bin_block<Src, NT, R>(src, params, refl, n_mat, blockIdx.x);
 }
 
 // The binning chunks of the sonar frames and, in the same launch, the camera
@@ -154,7 +175,7 @@ __global__ __launch_bounds__(kBlock) void k_bin_uw(Src src, const oceansim_sonar
                                                    const float *refl, int n_mat, int n_bin_blocks,
                                                    Table<UwDev> usrc, const oceansim_water_params *wparams) {
     if ((int)blockIdx.x < n_bin_blocks)
-        bin_block<Src, R>(src, params, refl, n_mat, blockIdx.x);
+        bin_block<Src, kBlock, R>(src, params, refl, n_mat, blockIdx.x);
     else
         uw_fwd_block<Table<UwDev>, kBlock>(usrc, wparams, blockIdx.x - n_bin_blocks);
 }
@@ -190,14 +211,105 @@ __device__ __forceinline__ void write_fan_column(const SonarDev &f, int j) {
     cd[2 * j + 1] = cs;
 }
 
-constexpr int kTileLoads = 4;   // pair gathers in flight per thread of a forward tile
+constexpr int kTileLoads = 4;   // pair gathers in flight per thread of a tile
 
-// Forward polar tile `bid` of the launch (kBlock threads).
-template <class Src>
-__device__ __forceinline__ void tile_fwd_block(const Src &src, const oceansim_sonar_params *params, int bid) {
+// Visits the pairs of polar tile `tile` of frame f: its segment in every
+// binning chunk, for NT chunks at a time, flattened so that every thread
+// takes pairs (independent loads) whatever the segment lengths, kTileLoads
+// per thread per round (each pair's segment found by a branch-free binary
+// search of the LDS prefix; indices past the end re-read the last pair and
+// are not visited).  fn(pair, range):
+// WITH_R loads the pair's range from f.pair_r with the pair (else 0).  pre()
+// runs once, after the first offset loads are issued and before they are
+// used: independent arithmetic placed there overlaps their latency.
+// Contains barriers.
+template <int NT, bool WITH_R, class Fn, class Pre>
+__device__ __forceinline__ void for_tile_pairs(const SonarDev &f, int tile, int *seg_end, int *seg_start, int *wtot,
+                                               Fn fn, Pre pre) {
+    const int tid = threadIdx.x;
+    const int stride = f.n_tiles + 1;
+    for (int c0 = 0; c0 < f.n_chunks; c0 += NT) {
+        const int c = c0 + tid;
+        // the offsets of chunk c (clamped: a thread past the last chunk
+        // re-reads the last one and takes an empty segment)
+        const int cl = c < f.n_chunks ? c : f.n_chunks - 1;
+        const gptr<const int> off = f.chunk_off + (long long)cl * stride + tile;
+        const int o0 = off[0], o1 = off[1];
+        if (c0 == 0) pre();
+        const int s0 = o0, len = c < f.n_chunks ? o1 - o0 : 0;
+        int total;
+        const int incl = block_inclusive_scan1<NT>(len, wtot, total);
+        seg_end[tid] = incl;
+        seg_start[tid] = s0 - (incl - len);   // pair index = seg_start[c] + flat index
+        __syncthreads();
+        for (int k0 = 0; k0 < total; k0 += NT * kTileLoads) {
+            uint2 q[kTileLoads];
+            float rv[kTileLoads];
+#pragma unroll
+            for (int u = 0; u < kTileLoads; ++u) {
+                const int k = min(k0 + u * NT + tid, total - 1);
+                // the segment holding flat index k: first c with seg_end[c] > k
+                int cc = 0;
+#pragma unroll
+                for (int s = NT / 2; s > 0; s >>= 1) cc += seg_end[cc + s - 1] <= k ? s : 0;
+                const long long idx = (long long)(c0 + cc) * f.chunk + seg_start[cc] + k;
+                q[u] = gload(f.pairs + idx);
+                rv[u] = WITH_R ? f.pair_r[idx] : 0.0f;
+            }
+#pragma unroll
+            for (int u = 0; u < kTileLoads; ++u)
+                if (k0 + u * NT + tid < total) fn(q[u], rv[u]);
+        }
+        __syncthreads();
+    }
+    if (f.n_chunks <= 0) pre();
+}
+
+// Wave-level stream compaction: every wave walks its share of [0, n), queues
+// the indices x with pred(x) in its own LDS queue (2 x 64 entries) and runs
+// work(x) 64 at a time, so the costly work of the sparse set keeps all lanes
+// busy.  Call from every thread; no workgroup barrier inside.
+template <int NT, class Pred, class Work>
+__device__ __forceinline__ void wave_compact(int n, int *queues, Pred pred, Work work) {
+    const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
+    constexpr int NW = NT / kWave;
+    const int per = ((n + NW - 1) / NW + kWave - 1) / kWave * kWave;
+    const int lo = min(w * per, n), hi = min(lo + per, n);
+    int *qw = queues + w * 2 * kWave;
+    int qn = 0;
+    auto sync = [&]() __attribute__((always_inline)) {
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    };
+    for (int base = lo; base < hi; base += kWave) {
+        const int x = base + lane;
+        const bool p = x < hi && pred(x);
+        const unsigned long long mask = __ballot(p);
+        if (p) qw[qn + __popcll(mask & ((1ull << lane) - 1ull))] = x;   // qn < 64: within the queue
+        qn += __popcll(mask);
+        sync();
+        if (qn >= kWave) {
+            work(qw[lane]);
+            const int t = qw[lane + kWave];   // the tail beyond the first 64 (read before it moves)
+            sync();
+            if (lane + kWave < qn) qw[lane] = t;
+            qn -= kWave;
+            sync();
+        }
+    }
+    if (lane < qn) work(qw[lane]);
+}
+
+// Forward polar tile `bid` of the launch (NT threads).
+template <class Src, int NT>
+__device__ __forceinline__ void tile_fwd_block(const Src &src, const oceansim_sonar_params *params, const float *refl,
+                                               int n_mat, int bid) {
     extern __shared__ int4 lds_raw[];
-    __shared__ unsigned listed[kMaxTileBins / 32];
-    __shared__ int n_listed;
+    constexpr int NW = NT / kWave;
+    __shared__ int queues[NW * 2 * kWave];
+    __shared__ float refl_s[kLaneHistMats];
+    __shared__ int seg_end[NT], seg_start[NT], wtot[NW];
     int tile;
     const int fi = src.locate(bid, KTILE, tile);
     const SonarDev f = src.frame(fi);
@@ -206,77 +318,76 @@ __device__ __forceinline__ void tile_fwd_block(const Src &src, const oceansim_so
     const int b_lo = tile * f.tile_bins;
     const int b_hi = min(b_lo + f.tile_bins, nb);
     const int nbins = b_hi - b_lo;
-    float *acc = reinterpret_cast<float *>(lds_raw);           // [tile_bins]
-    int *list = reinterpret_cast<int *>(acc + f.tile_bins);    // [tile_bins]
-    float *etab = reinterpret_cast<float *>(list + f.tile_bins);   // [n_az]: beam pattern of Eq. 3 per column
+    float *acc = reinterpret_cast<float *>(lds_raw);               // [tile_bins]
+    float *etab = acc + f.tile_bins;                               // [n_az]: beam pattern of Eq. 3 per column
     const bool speckle = f.speckle != SPECKLE_OFF;
+    const bool matp = f.matp != 0;
     const oceansim_sonar_params pr = params[f.param_row];
     const AddCtx ctx{pr.sigma_sa, 1.0f / pr.sigma_phi};
     // the column factor exp(-phi_j^2 / sigma_phi) once per column of the tile's rows
     if (speckle)
-        for (int j = tid; j < f.n_az; j += kBlock) {
+        for (int j = tid; j < f.n_az; j += NT) {
             const float phi = bin_azimuth(f, j);
             etab[j] = expf(-(phi * phi) * ctx.inv_sigma_phi);
         }
+    // material pairs carry cos x attenuation: the reflectivity is applied here
+    if (matp)
+        for (int k = tid; k < n_mat; k += NT) refl_s[k] = refl[k];
 
     // side job for the fan launch that follows: {sin, cos} of the column-centre azimuths
     if (f.cols)
-        for (int j = tile * kBlock + tid; j < f.n_az; j += f.n_tiles * kBlock) write_fan_column(f, j);
-    for (int k = tid; k < nbins; k += kBlock) acc[k] = 0.0f;
-    for (int k = tid; k < (nbins + 31) / 32; k += kBlock) listed[k] = 0u;
-    if (tid == 0) n_listed = 0;
+        for (int j = tile * NT + tid; j < f.n_az; j += f.n_tiles * NT) write_fan_column(f, j);
+    for (int k = tid; k < nbins; k += NT) acc[k] = 0.0f;
     __syncthreads();
 
-    // binning by summation: the segments of this tile in every chunk, for
-    // kBlock chunks at a time, flattened so that every thread takes pairs
-    // (independent loads) whatever the segment lengths.  Bins that receive a
-    // nonzero intensity are listed once for the multiplicative draw.
-    const int stride = f.n_tiles + 1;
-    __shared__ int seg_end[kBlock], seg_start[kBlock], wtot[kBlock / kWave];
-    for (int c0 = 0; c0 < f.n_chunks; c0 += kBlock) {
-        const int c = c0 + tid;
-        int s0 = 0, len = 0;
-        if (c < f.n_chunks) {
-            const gptr<const int> off = f.chunk_off + (long long)c * stride + tile;
-            s0 = off[0];
-            len = off[1] - s0;
-        }
-        int total;
-        const int incl = block_inclusive_scan1<kBlock>(len, wtot, total);
-        seg_end[tid] = incl;
-        seg_start[tid] = s0 - (incl - len);   // pair index = seg_start[c] + flat index
-        __syncthreads();
-        // kTileLoads pairs in flight per thread: the searches and gathers of a
-        // round are independent; indices past the end re-read the last pair
-        // (no masked loads) and are dropped before the accumulation
-        for (int k0 = 0; k0 < total; k0 += kBlock * kTileLoads) {
-            uint2 q[kTileLoads];
+    const int q_first = b_lo >> 2, q_last = (b_hi - 1) >> 2;
+    // additive term of Eq. (3)-(4) for the group of four consecutive
+    // frame-linear bins starting at 4q (one Philox call)
+    auto additive_group = [&](int q, float (&add)[4]) __attribute__((always_inline)) {
+        const int b0 = q << 2;
+        const Words wd = philox((uint32_t)q, f.frame_id, 0u, 0u, f.seed_lo, f.seed_hi);
+        int i = b0 / f.n_az;
+        int j = b0 - i * f.n_az;
+        float R = range_ramp(f, i);
 #pragma unroll
-            for (int u = 0; u < kTileLoads; ++u) {
-                const int k = min(k0 + u * kBlock + tid, total - 1);
-                // the segment holding flat index k: first c with seg_end[c] > k
-                int c = 0;
-#pragma unroll
-                for (int s = kBlock / 2; s > 0; s >>= 1) c += seg_end[c + s - 1] <= k ? s : 0;
-                q[u] = gload(f.pairs + ((long long)(c0 + c) * f.chunk + seg_start[c] + k));
-            }
-#pragma unroll
-            for (int u = 0; u < kTileLoads; ++u) {
-                if (k0 + u * kBlock + tid >= total || q[u].x >= (uint32_t)nbins) continue;
-                const float I = __uint_as_float(q[u].y);
-                atomicAdd(&acc[q[u].x], I);
-                if (speckle && I != 0.0f) {
-                    const unsigned bit = 1u << (q[u].x & 31);
-                    if (!(atomicOr(&listed[q[u].x >> 5], bit) & bit)) list[atomicAdd(&n_listed, 1)] = (int)q[u].x;
-                }
+        for (int w = 0; w < 4; ++w) {
+            // R_i (1 + 0.5 E_j sigma_sa rho)
+            const float rho = rayleigh_of_word(pick(wd, (uint32_t)w));
+            add[w] = R * (1.0f + 0.5f * etab[j] * (ctx.sigma_sa * rho));
+            if (++j == f.n_az) {
+                j = 0;
+                R = range_ramp(f, ++i);
             }
         }
+    };
+
+    // binning by summation of the tile's pairs (and, for a pair backward, the
+    // largest |cos x attenuation| among them)
+    float cemax = 0.0f;
+    for_tile_pairs<NT, false>(
+        f, tile, seg_end, seg_start, wtot,
+        [&](uint2 q, float) __attribute__((always_inline)) {
+            const uint32_t lb = matp ? (q.x & 0xffffu) : q.x;
+            if (lb >= (uint32_t)nbins) return;
+            const float I = matp ? refl_s[q.x >> 16] * __uint_as_float(q.y) : __uint_as_float(q.y);
+            cemax = fmaxf(cemax, __builtin_fabsf(__uint_as_float(q.y)));
+            atomicAdd(&acc[lb], I);
+        },
+        []() {});
+    if (f.tile_cemax) {
+        __shared__ unsigned s_cemax;
+        if (tid == 0) s_cemax = 0u;
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) cemax = fmaxf(cemax, __shfl_down(cemax, off, kWave));
         __syncthreads();
+        if ((tid & (kWave - 1)) == 0) atomicMax(&s_cemax, __float_as_uint(cemax));   // non-negative: ordered as bits
+        __syncthreads();
+        if (tid == 0) f.tile_cemax[tile] = __uint_as_float(s_cemax);
     }
 
     float G = pr.gain;
     if (f.saved_p)   // the binned sums P, for the backward of a range-normalised frame
-        for (int k = tid; k < nbins; k += kBlock) f.saved_p[b_lo + k] = acc[k];
+        for (int k = tid; k < nbins; k += NT) f.saved_p[b_lo + k] = acc[k];
     if (f.range_norm) {
         // range-wise normalisation: each row of Q = G P over its maximum when
         // that is positive (the maximum over the positive entries: NaN and
@@ -284,14 +395,14 @@ __device__ __forceinline__ void tile_fwd_block(const Src &src, const oceansim_so
         // holds the normalised Q, so the gain below is 1
         unsigned *rmax = reinterpret_cast<unsigned *>(etab + f.n_az);   // [rows of the tile]
         const int rows = nbins / f.n_az;
-        for (int r = tid; r < rows; r += kBlock) rmax[r] = 0u;
+        for (int r = tid; r < rows; r += NT) rmax[r] = 0u;
         __syncthreads();
-        for (int k = tid; k < nbins; k += kBlock) {
+        for (int k = tid; k < nbins; k += NT) {
             const float q = G * acc[k];
             if (q > 0.0f) atomicMax(&rmax[k / f.n_az], __float_as_uint(q));   // positive floats order as their bits
         }
         __syncthreads();
-        for (int k = tid; k < nbins; k += kBlock) {
+        for (int k = tid; k < nbins; k += NT) {
             const float m = __uint_as_float(rmax[k / f.n_az]);
             const float q = G * acc[k];
             acc[k] = m > 0.0f ? q / m : q;
@@ -300,44 +411,28 @@ __device__ __forceinline__ void tile_fwd_block(const Src &src, const oceansim_so
         G = 1.0f;
     }
     if (speckle) {
-        // Q m for the listed (nonempty) bins only: the other bins have Q = 0
-        const int nl = n_listed;
-        for (int e = tid; e < nl; e += kBlock) {
-            const int x = list[e];
-            float gz;
-            const float m = speckle_factor(f, (uint32_t)(b_lo + x), pr.sigma_sm, &gz);
-            acc[x] = (G * acc[x]) * m;
-        }
+        // Q m for the nonzero bins only (the others have Q m = 0 whatever m),
+        // compacted per wave so that the draws keep the lanes busy
+        wave_compact<NT>(
+            nbins, queues, [&](int x) __attribute__((always_inline)) { return acc[x] != 0.0f; },
+            [&](int x) __attribute__((always_inline)) {
+                float gz;
+                const float m = speckle_factor(f, (uint32_t)(b_lo + x), pr.sigma_sm, &gz);
+                acc[x] = (G * acc[x]) * m;
+            });
         __syncthreads();
     }
 
-    // groups of four consecutive frame-linear bins share one additive Philox call
-    const int q_first = b_lo >> 2, q_last = (b_hi - 1) >> 2;
-    for (int q = q_first + tid; q <= q_last; q += kBlock) {
+    // out = Q m + additive term (speckle) or G P, groups of four bins, float4 stores
+    auto store_group = [&](int q, const float (&add)[4]) __attribute__((always_inline)) {
         const int b0 = q << 2;
         float out[4];
         bool in[4];
 #pragma unroll
-        for (int w = 0; w < 4; ++w) in[w] = b0 + w >= b_lo && b0 + w < b_hi;
-        if (!speckle) {
-#pragma unroll
-            for (int w = 0; w < 4; ++w) out[w] = in[w] ? G * acc[b0 + w - b_lo] : 0.0f;
-        } else {
-            const Words wd = philox((uint32_t)q, f.frame_id, 0u, 0u, f.seed_lo, f.seed_hi);
-            int i = b0 / f.n_az;
-            int j = b0 - i * f.n_az;
-            float R = range_ramp(f, i);
-#pragma unroll
-            for (int w = 0; w < 4; ++w) {
-                // additive term of Eq. (3)-(4): R_i (1 + 0.5 E_j sigma_sa rho)
-                const float rho = rayleigh_of_word(pick(wd, (uint32_t)w));
-                const float add = R * (1.0f + 0.5f * etab[j] * (ctx.sigma_sa * rho));
-                out[w] = (in[w] ? acc[b0 + w - b_lo] : 0.0f) + add;
-                if (++j == f.n_az) {
-                    j = 0;
-                    R = range_ramp(f, ++i);
-                }
-            }
+        for (int w = 0; w < 4; ++w) {
+            in[w] = b0 + w >= b_lo && b0 + w < b_hi;
+            const float a = in[w] ? acc[b0 + w - b_lo] : 0.0f;
+            out[w] = speckle ? a + add[w] : G * a;
         }
         if (in[0] && in[3]) {
             gstore((gptr<float4>)(f.polar + b0), make_float4(out[0], out[1], out[2], out[3]));
@@ -346,12 +441,18 @@ __device__ __forceinline__ void tile_fwd_block(const Src &src, const oceansim_so
             for (int w = 0; w < 4; ++w)
                 if (in[w]) f.polar[b0 + w] = out[w];
         }
+    };
+    for (int q = q_first + tid; q <= q_last; q += NT) {
+        float add[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+        if (speckle) additive_group(q, add);
+        store_group(q, add);
     }
 }
 
-template <class Src>
-__global__ __launch_bounds__(kBlock) void k_tile(Src src, const oceansim_sonar_params *params) {
-    tile_fwd_block(src, params, blockIdx.x);
+template <class Src, int NT>
+__global__ __launch_bounds__(NT) void k_tile(Src src, const oceansim_sonar_params *params, const float *refl,
+                                             int n_mat) {
+    tile_fwd_block<Src, NT>(src, params, refl, n_mat, blockIdx.x);
 }
 
 // ---------------------------------------------------------------------------
@@ -1067,6 +1168,253 @@ __global__ __launch_bounds__(kBlock) void k_ret_uw_bwd(Src src, const oceansim_s
 }
 
 // ---------------------------------------------------------------------------
+// k_pair_bwd (plans whose frames carry material pairs, tables of at most 64
+// materials): the adjoint of binning, gain, the multiplicative speckle and
+// Eq. (2), one workgroup per forward polar tile, from the pairs and ranges the
+// plan's forward pass left.  The tile's dL/d(polar image) is read once into
+// LDS (coalesced) and each return looks its bin up there, instead of
+// gathering it from global memory at the return's bin; the returns
+// themselves are not read again.  Frames without a transposed fan operator
+// also get the adjoint of the additive speckle term here (their
+// dL/d(polar image) is the polar gradient itself).
+//
+// The pairs' order within a chunk follows the forward's LDS atomics and may
+// change between runs, so the per-return sums are order-independent: each
+// contribution is scaled by a power of two chosen from an a priori bound on
+// its magnitude in this tile (the tile's largest finite |dL/dI~|, the largest
+// value of the multiplicative factor, the largest reflectivity, the largest
+// |cos x attenuation| of the tile's pairs, which the forward tile records,
+// and the tile's far range edge), rounded to a 64-bit integer and
+// summed in integers: the sums are exact and bit-reproducible, each term kept
+// to ~2^-40 of its bound (at 2^21 returns per frame; finer for fewer).  A
+// non-finite contribution makes its sum NaN.
+// ---------------------------------------------------------------------------
+// |m| and |z| of the multiplicative draw: -ln u <= 24 ln 2 for u >= 2^-24,
+// so a gamma factor is at most 24 ln 2 and |z| at most sqrt(48 ln 2).
+constexpr double kGammaMax = 16.635532333438686;
+constexpr double kGaussMax = 5.7678665758658466;
+
+__device__ __forceinline__ long long scale_round(double x, double scale) {
+    return round_to_ll(x * scale);
+}
+
+// 2^sc with |x| * 2^sc < 2^(50 - extra) for |x| <= bound, where 2^extra
+// covers the number of terms (n <= 2^(11 + extra)), so that a sum of up to n
+// scaled terms stays below 2^61.
+__device__ __forceinline__ int fixed_exponent(double bound, long long n) {
+    int e = 0;
+    if (bound > 0.0) frexp(bound, &e);   // bound < 2^e
+    int lg = 0;
+    while ((1LL << lg) < n && lg < 62) ++lg;
+    const int extra = lg > 11 ? lg - 11 : 0;
+    return 50 - e - extra;
+}
+
+template <class Src>
+__global__ __launch_bounds__(kWideThreads) void k_pair_bwd(Src src, const oceansim_sonar_params *params,
+                                                           const float *refl, int n_mat, double *part,
+                                                           int slot_base, int n_slots, double *refl_part,
+                                                           int n_refl_slots) {
+    constexpr int NT = kWideThreads;
+    constexpr int NW = NT / kWave;
+    extern __shared__ int4 lds_raw[];
+    __shared__ int seg_end[NT], seg_start[NT], wtot[NW];
+    __shared__ float refl_s[kLaneHistMats];
+    __shared__ unsigned long long racc[kLaneHistMats];
+    __shared__ unsigned long long rbad;
+    __shared__ float wmax[NW];
+    __shared__ long long lred[3 * NW];
+    __shared__ double dred[2 * NW];
+    __shared__ unsigned bad_any;
+    int tile;
+    const int bid = blockIdx.x;
+    const int fi = src.locate(bid, KTILE, tile);
+    const SonarDev f = src.frame(fi);
+    const int tid = threadIdx.x, lane = tid & (kWave - 1), wave = tid / kWave;
+    const int nb = f.n_range * f.n_az;
+    const int b_lo = tile * f.tile_bins;
+    const int b_hi = min(b_lo + f.tile_bins, nb);
+    float *gt = reinterpret_cast<float *>(lds_raw);   // [tile_bins]: dL/d(polar image) of the tile's bins
+    const oceansim_sonar_params pr = params[f.param_row];
+    const float G = pr.gain;
+    for (int k = tid; k < n_mat; k += NT) {
+        refl_s[k] = refl[k];
+        racc[k] = 0ull;
+    }
+    if (tid == 0) {
+        rbad = 0ull;
+        bad_any = 0u;
+    }
+
+    // 1. the tile's gradient into LDS; without an operator this kernel also
+    // owns the adjoint of the additive term of Eq. (3)-(4)
+    const bool own_add = f.ft_ptr == nullptr;
+    const gptr<const float> gsrc = own_add ? f.grad_polar : (gptr<const float>)f.grad_img;
+    const bool add_adj = own_add && f.speckle != SPECKLE_OFF;
+    const AddCtx ctx{pr.sigma_sa, 1.0f / pr.sigma_phi};
+    const double dsphi = 0.5 * (double)pr.sigma_sa / ((double)pr.sigma_phi * (double)pr.sigma_phi);
+    double g_sphi = 0.0, g_ssa = 0.0;
+    float gmax = 0.0f;
+    const int q_first = b_lo >> 2, q_last = (b_hi - 1) >> 2;
+    for (int q = q_first + tid; q <= q_last; q += NT) {
+        const int b0 = q << 2;
+        bool in[4];
+        float g[4];
+#pragma unroll
+        for (int w = 0; w < 4; ++w) in[w] = b0 + w >= b_lo && b0 + w < b_hi;
+        if (!gsrc) {
+#pragma unroll
+            for (int w = 0; w < 4; ++w) g[w] = 0.0f;
+        } else if (in[0] && in[3]) {
+            const float4 v = gload((gptr<const float4>)(gsrc + b0));
+            g[0] = v.x;
+            g[1] = v.y;
+            g[2] = v.z;
+            g[3] = v.w;
+        } else {
+#pragma unroll
+            for (int w = 0; w < 4; ++w) g[w] = in[w] ? gsrc[b0 + w] : 0.0f;
+        }
+#pragma unroll
+        for (int w = 0; w < 4; ++w) {
+            if (!in[w]) continue;
+            gt[b0 + w - b_lo] = g[w];
+            const float a = __builtin_fabsf(g[w]);
+            if (a <= 3.4028235e38f && a > gmax) gmax = a;
+        }
+        if (add_adj) {
+            const Words wd = philox((uint32_t)q, f.frame_id, 0u, 0u, f.seed_lo, f.seed_hi);
+            int i = b0 / f.n_az;
+            int j = b0 - i * f.n_az;
+#pragma unroll
+            for (int w = 0; w < 4; ++w) {
+                if (in[w]) {
+                    float E, rho, R, phi;
+                    additive_term(f, ctx, i, j, pick(wd, (uint32_t)w), E, rho, R, phi);
+                    // d add / d sigma_sa and d add / d sigma_phi of Eq. (3)-(4)
+                    const double t = (double)g[w] * (double)R * (double)E * (double)rho;
+                    g_ssa += 0.5 * t;
+                    g_sphi += t * dsphi * ((double)phi * (double)phi);
+                }
+                if (++j == f.n_az) {
+                    j = 0;
+                    ++i;
+                }
+            }
+        }
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) gmax = fmaxf(gmax, __shfl_down(gmax, off, kWave));
+    if (lane == 0) wmax[wave] = gmax;
+    __syncthreads();
+    float Mg = 0.0f;
+#pragma unroll
+    for (int k = 0; k < NW; ++k) Mg = fmaxf(Mg, wmax[k]);
+    float Rmax = 0.0f;
+    for (int k = 0; k < n_mat; ++k) {
+        const float a = __builtin_fabsf(refl_s[k]);
+        if (a <= 3.4028235e38f && a > Rmax) Rmax = a;
+    }
+
+    // 2. bounds of one return's contributions in this tile, and their scales
+    // (the largest |cos x attenuation| of the tile's pairs is the forward's)
+    const int ia = tile * f.rows_per_tile;
+    const int ib = min(ia + f.rows_per_tile, f.n_range);
+    const double r_hi = f.r_min + (double)ib * f.dr;
+    const double Emax = (double)f.tile_cemax[tile];
+    const double Mm = f.speckle == SPECKLE_GAMMA   ? kGammaMax
+                      : f.speckle == SPECKLE_PAPER ? 0.5 + __builtin_fabs((double)pr.sigma_sm) * kGaussMax
+                                                   : 1.0;
+    const double safety = 1.01;
+    const double absG = __builtin_fabs((double)G);
+    const double B_refl = safety * absG * Mm * (double)Mg * Emax;                  // |dL/dI cos att|
+    const double B_alpha = B_refl * (double)Rmax * f.kappa * r_hi * 1.001;        // |dL/dI I kappa r|
+    const double B_gain = safety * Mm * (double)Mg * (double)Rmax * Emax;          // |dL/dQ I|
+    const double B_ssm = safety * (double)Mg * absG * (double)Rmax * Emax * kGaussMax;   // |g G I z|
+    const long long n_terms = f.n > 0 ? f.n : 1;
+    const int e_refl = fixed_exponent(B_refl, n_terms), e_alpha = fixed_exponent(B_alpha, n_terms);
+    const int e_gain = fixed_exponent(B_gain, n_terms), e_ssm = fixed_exponent(B_ssm, n_terms);
+    const double s_refl = ldexp(1.0, min(e_refl, 1000)), s_alpha = ldexp(1.0, min(e_alpha, 1000));
+    const double s_gain = ldexp(1.0, min(e_gain, 1000)), s_ssm = ldexp(1.0, min(e_ssm, 1000));
+    const bool refl_ok = __builtin_isfinite(B_refl);
+    const bool paper = f.speckle == SPECKLE_PAPER;
+
+    // 3. the tile's returns: dL/dI = G m dL/dI~ at the return's bin
+    long long a_alpha = 0, a_gain = 0, a_ssm = 0;
+    // non-finite contributions per sum (alpha, gain, sigma_sm)
+    bool bad_a = !__builtin_isfinite(B_alpha), bad_g = !__builtin_isfinite(B_gain);
+    bool bad_s = paper && !__builtin_isfinite(B_ssm);
+    const double neg_kappa = -f.kappa;
+    for_tile_pairs<NT, true>(f, tile, seg_end, seg_start, wtot, [&](uint2 pq, float r) __attribute__((always_inline)) {
+        const uint32_t lb = pq.x & 0xffffu;
+        const int m = (int)(pq.x >> 16);
+        if (lb >= (uint32_t)(b_hi - b_lo) || m >= n_mat) return;
+        const float ce = __uint_as_float(pq.y);   // cos(gamma) exp(-kappa alpha r)
+        float z = 0.0f;
+        const float mult = speckle_factor(f, (uint32_t)(b_lo + (int)lb), pr.sigma_sm, &z);
+        const float g = gt[lb];
+        const double gq = (double)mult * (double)g;   // dL/dQ at the bin
+        const double gI = (double)G * gq;             // dL/dI_k
+        const float I = refl_s[m] * ce;
+        const double xr = gI * (double)ce;
+        const double xa = gI * (double)I * (neg_kappa * (double)r);
+        const double xg = gq * (double)I;
+        const double xs = paper ? (double)g * (double)G * (double)I * (double)z : 0.0;
+        if (__builtin_isfinite(xr)) {
+            const long long v = scale_round(xr, s_refl);
+            if (v != 0) atomicAdd(&racc[m], (unsigned long long)v);
+        } else {
+            atomicOr(&rbad, 1ull << m);
+        }
+        if (__builtin_isfinite(xa)) a_alpha += scale_round(xa, s_alpha); else bad_a = true;
+        if (__builtin_isfinite(xg)) a_gain += scale_round(xg, s_gain); else bad_g = true;
+        if (__builtin_isfinite(xs)) a_ssm += scale_round(xs, s_ssm); else bad_s = true;
+    }, []() {});
+
+    // 4. workgroup sums (integers: any order; doubles: a fixed order)
+    long long lv[3] = {a_alpha, a_gain, a_ssm};
+    double dv[2] = {g_sphi, g_ssa};
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+#pragma unroll
+        for (int k = 0; k < 3; ++k) lv[k] += __shfl_down(lv[k], off, kWave);
+#pragma unroll
+        for (int k = 0; k < 2; ++k) dv[k] += __shfl_down(dv[k], off, kWave);
+    }
+    const unsigned bad_bits = (bad_a ? 1u : 0u) | (bad_g ? 2u : 0u) | (bad_s ? 4u : 0u);
+    if (bad_bits) atomicOr(&bad_any, bad_bits);
+    if (lane == 0) {
+#pragma unroll
+        for (int k = 0; k < 3; ++k) lred[k * NW + wave] = lv[k];
+#pragma unroll
+        for (int k = 0; k < 2; ++k) dred[k * NW + wave] = dv[k];
+    }
+    __syncthreads();
+    const long long slot = slot_base + bid;
+    if (tid < 5) {
+        double v;
+        if (tid < 3) {
+            long long t = 0;
+            for (int k = 0; k < NW; ++k) t += lred[tid * NW + k];
+            const double sc = tid == 0 ? s_alpha : tid == 1 ? s_gain : s_ssm;
+            v = ((bad_any >> tid) & 1u) ? __builtin_nan("") : (double)t / sc;
+        } else {
+            double t = 0.0;
+            for (int k = 0; k < NW; ++k) t += dred[(tid - 3) * NW + k];
+            v = t;
+        }
+        // columns: 0 alpha, 1 gain, 2 sigma_phi, 3 sigma_sa, 4 sigma_sm
+        const int col = tid == 0 ? 0 : tid == 1 ? 1 : tid == 2 ? 4 : tid == 3 ? 2 : 3;
+        part[(long long)col * n_slots + slot] = v;
+        if (tid == 0) reinterpret_cast<int *>(part + 5LL * n_slots)[slot] = f.param_row;
+    }
+    for (int m = tid; m < n_mat; m += NT) {
+        const bool pm = !refl_ok || ((rbad >> m) & 1ull);
+        refl_part[(long long)m * n_refl_slots + bid] = pm ? __builtin_nan("") : (double)(long long)racc[m] / s_refl;
+    }
+}
+
+// ---------------------------------------------------------------------------
 // k_fant_bwd: the polar gradient through the frames' transposed fan operators
 // (plans), BPT consecutive bins per thread: dL/dI[b] is the sum of weight *
 // dL/dF over the bin's entries, in FP64 and in the entries' fixed order
@@ -1417,26 +1765,41 @@ template <class Src>
 static hipError_t launch_fwd(const Src &src, const SonarGrid &g, const oceansim_sonar_params *params,
                              const float *refl, int n_mat, hipStream_t st, const UwCompanion *uw) {
     // a plan's camera forward rides along in the binning launch (few,
-    // latency-bound workgroups with little LDS)
+    // latency-bound workgroups with little LDS); wide binning workgroups
+    // (chunks above 4096 returns) take 64 KB of LDS each, so the camera
+    // frames then run in a launch of their own
+    const bool wide = g.chunk > 4096;
     const bool with_uw = uw && uw->blocks > 0;
-    if (g.bin_blocks > 0 || with_uw) {
+    if (g.bin_blocks > 0 || (with_uw && !wide)) {
         const size_t lds = (size_t)((g.max_tiles + 1 + 3) & ~3) * 4 + (size_t)g.chunk * 8;
-        if (with_uw) {
+        if (wide) {
+            if (g.chunk != kWideThreads * 16) return hipErrorInvalidValue;
+            OSIM_LAUNCH("k_bin", (k_bin<Src, kWideThreads, 16>), dim3(g.bin_blocks), dim3(kWideThreads), lds, st,
+                        src, params, refl, n_mat);
+        } else if (with_uw) {
             OSIM_DISPATCH_R(g.chunk / kBlock,
                             OSIM_LAUNCH("k_bin_uw", (k_bin_uw<Src, RR>), dim3(g.bin_blocks + uw->blocks),
                                         dim3(kBlock), lds, st, src, params, refl, n_mat, g.bin_blocks,
                                         Table<UwDev>{uw->table, uw->n}, uw->params));
         } else {
             OSIM_DISPATCH_R(g.chunk / kBlock,
-                            OSIM_LAUNCH("k_bin", (k_bin<Src, RR>), dim3(g.bin_blocks), dim3(kBlock), lds, st, src,
-                                        params, refl, n_mat));
+                            OSIM_LAUNCH("k_bin", (k_bin<Src, kBlock, RR>), dim3(g.bin_blocks), dim3(kBlock), lds,
+                                        st, src, params, refl, n_mat));
         }
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
-    OSIM_LAUNCH("k_tile", (k_tile<Src>), dim3(g.tile_blocks), dim3(kBlock),
-                (size_t)g.max_tile_bins * 8 + (size_t)g.max_n_az * 4 + (size_t)g.max_rows_per_tile * 4, st, src,
-                params);
+    if (with_uw && wide) {
+        hipError_t e = uw_forward_table(uw->table, uw->n, uw->blocks, uw->params, st);
+        if (e != hipSuccess) return e;
+    }
+    const size_t tile_lds = (size_t)g.max_tile_bins * 4 + (size_t)g.max_n_az * 4 + (size_t)g.max_rows_per_tile * 4;
+    if (g.max_tile_bins > kMaxTileBins)
+        OSIM_LAUNCH("k_tile", (k_tile<Src, kWideThreads>), dim3(g.tile_blocks), dim3(kWideThreads), tile_lds, st, src,
+                    params, refl, n_mat);
+    else
+        OSIM_LAUNCH("k_tile", (k_tile<Src, kBlock>), dim3(g.tile_blocks), dim3(kBlock), tile_lds, st, src, params,
+                    refl, n_mat);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     if (g.fan_blocks > 0) {
@@ -1452,6 +1815,56 @@ static hipError_t launch_bwd(const Src &src, int n_frames, const SonarGrid &g,
                              double *part, double *refl_part, float *grad_params, float *grad_refl,
                              hipStream_t st, SonarReduce *defer, const UwBwdCompanion *uwb) {
     const bool lane_hist = n_mat <= kLaneHistMats;
+    if (g.pair_bwd) {
+        // operator rows of the frames with a fan gradient, then one pair
+        // workgroup per forward tile; the camera backward in its own launch
+        const int n_slots = g.fant_blocks + g.tile_blocks;
+        hipError_t e = hipSuccess;
+        if (g.fant_blocks > 0) {
+#define OSIM_FANT(B, M)                                                                                     \
+    OSIM_LAUNCH("k_fant_bwd", (k_fant_bwd<Src, B, M>), dim3(g.fant_blocks), dim3(kBlock), 0, st, src, params, \
+                part, n_slots, (float *)nullptr, n_mat)
+            switch (g.fant_bpt * 2 + (g.fant_mirror ? 1 : 0)) {
+                case 2: OSIM_FANT(1, false); break;
+                case 3: OSIM_FANT(1, true); break;
+                case 4: OSIM_FANT(2, false); break;
+                case 5: OSIM_FANT(2, true); break;
+                case 8: OSIM_FANT(4, false); break;
+                case 9: OSIM_FANT(4, true); break;
+                default: return hipErrorInvalidValue;
+            }
+#undef OSIM_FANT
+            e = hipGetLastError();
+            if (e != hipSuccess) return e;
+        }
+        if (g.tile_blocks > 0) {
+            OSIM_LAUNCH("k_pair_bwd", (k_pair_bwd<Src>), dim3(g.tile_blocks), dim3(kWideThreads),
+                        (size_t)g.max_tile_bins * 4, st, src, params, refl, n_mat, part, g.fant_blocks, n_slots,
+                        refl_part, g.tile_blocks);
+            e = hipGetLastError();
+            if (e != hipSuccess) return e;
+        }
+        if (uwb && uwb->blocks > 0) {
+            e = uw_backward_table(uwb->table, uwb->n, uwb->blocks, uwb->params, uwb->part, uwb->part_row, st);
+            if (e != hipSuccess) return e;
+        }
+        SonarReduce a;
+        a.part = part;
+        a.n_slots = n_slots;
+        a.n_rows = n_rows;
+        a.grad_params = grad_params;
+        a.refl_part = refl_part;
+        a.ret_slots = g.tile_blocks;
+        a.n_mat = n_mat;
+        a.grad_refl = grad_refl;
+        a.blocks = n_rows * OCEANSIM_SONAR_GRAD_WIDTH + n_mat;
+        if (defer) {
+            *defer = a;
+            return hipSuccess;
+        }
+        OSIM_LAUNCH("k_reduce_sonar", k_reduce_sonar, dim3(a.blocks), dim3(kBlock), 0, st, a);
+        return hipGetLastError();
+    }
     // partial-sum slots: polar workgroups (tiles, or bin blocks through the
     // transposed fan operators), then return chunks
     const int polar_blocks = g.use_fant ? g.fant_blocks : g.tile_b_blocks;
