@@ -3,17 +3,23 @@ one MI355X.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-batched] [--no-cpu]
 
-A step is one forward + backward pass of the whole path over the real-time
-workload: one sonar frame of 1024 beams x 128 rays = 131072 returns binned on a
-1024 x 1024 polar grid with gamma speckle and a 1024 x 2048 fan, plus Eq. (1)
-on one 1920 x 1080 RGB frame, and the adjoints of both with respect to the
-reflectivities, the sonar parameters and the water parameters.  Inputs are
-seeded synthetic data already resident in device memory.
+A step is one forward + backward pass of the whole path over the calibration-
+scale workload: 64 sonar frames of 2048 beams x 1024 rays = 2,097,152 returns
+each (range U[0.5, 50) m, 64 materials, 2048 x 2048 polar bins, gamma speckle,
+no fan) and 64 RGB frames of 1920 x 1080 through Eq. (1), with the adjoints
+with respect to the reflectivities, the sonar parameters and the water
+parameters (polar and image losses; no image gradients).  Inputs are seeded
+synthetic data already resident in device memory; the frames go through one
+autotuned plan.
 
 Prints one JSON line.  ``value`` is sonar returns per second through the full
-step; the line also carries forward-only and batched throughputs, the roofline
-of the dominant kernel (timed with HIP events on the stream it runs on) and
-the FP64 oracle timed on the host's cores on a bounded sample.
+step.  The line also carries the roofline of the dominant kernel (HIP events
+on the stream the kernel is launched on), the whole step's fraction of HBM
+peak, the 200-step Adam calibration at this scale, and the other workloads:
+one plain frame (forward), the real-time frame (sonar + 1080p camera), the
+256-frame ragged batch and the 32 + 32 differentiable batch (unbatched
+forward-only against batched forward + backward), and the FP64 oracle timed on
+the host's cores over a bounded sample.
 """
 from __future__ import annotations
 
@@ -27,6 +33,9 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+# non-packed vector lanes: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz
+VALU_PEAK_LANE_OPS = 256 * 64 * 2.4e9
+C5_TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "c5_step_hbm_traffic.json")
 
 
 def log(msg):
@@ -36,19 +45,18 @@ def log(msg):
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=200)
-    ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--no-batched", action="store_true", help="skip the other workloads and the calibration run")
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--no-range-norm", action="store_true",
-                    help="skip the real-time step with the range-wise normalisation (profiler runs)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 64 MiB device-to-device copy (counter calibration)")
-    ap.add_argument("--only", choices=["c3", "c4", "c5"], default=None,
-                    help="only build and run one batched leg (for profiler runs); prints no JSON line")
+    ap.add_argument("--only", choices=["c2", "c3", "c4", "c5"], default=None,
+                    help="only build and run one workload (for profiler runs); prints no JSON line")
     ap.add_argument("--c5-frames", type=int, default=64,
-                    help="sonar and camera frames of the calibration-scale leg")
+                    help="sonar and camera frames of the calibration-scale workload")
+    ap.add_argument("--calib-steps", type=int, default=200, help="Adam steps of the calibration run")
     return ap.parse_args()
 
 
@@ -77,19 +85,19 @@ def source_digest():
     return h.hexdigest()
 
 
-def measured_traffic(kernel):
-    """HBM bytes per launch of `kernel` (read + written) from the rocprofv3
-    counter summary in profiles/, if it was taken on the current sources."""
-    path = os.path.join(ROOT, "profiles", "c2_step_hbm_traffic.json")
+
+def measured_profile():
+    """Per-kernel HBM bytes and VALU instructions per launch of the
+    calibration-scale step, from the rocprofv3 counter summary in profiles/,
+    if it was taken on the current sources (else None)."""
     try:
-        with open(path) as fh:
+        with open(C5_TRAFFIC_PROFILE) as fh:
             rec = json.load(fh)
     except (OSError, ValueError):
         return None
     if rec.get("source_sha256") != source_digest():
         return None
-    k = rec.get("kernels", {}).get(kernel)
-    return None if k is None else int(k["fetch_bytes"] + k["write_bytes"])
+    return rec.get("kernels", {})
 
 
 def copy_rate(torch, dev):
@@ -275,25 +283,142 @@ def median_time(torch, fn, steps, warmup, repeats=5):
     return ts[len(ts) // 2]
 
 
-def batched_legs(torch, dev, steps, only=None):
-    """Ragged batch of 256 sonar frames (forward) and a differentiable batch of
-    32 sonar + 32 camera frames (forward + backward): one ABI call per frame
-    (plain), one call per entry point for the whole batch (batched), and a
-    plan replayed from HIP graphs, with descriptors and buffers prepared
-    before timing."""
+
+
+class CalibrationScale:
+    """The calibration-scale workload on the device: n_frames sonar frames of
+    2048 x 1024 returns (2048 x 2048 bins, no fan, 64 materials, gamma
+    speckle) and n_frames 1920 x 1080 camera frames in one autotuned backward
+    plan, with seeded N(0, 1) loss gradients (polar and image losses).  Four
+    distinct sonar and camera frames are generated and uploaded n_frames / 4
+    times each (separate device buffers, distinct frame ids, so distinct
+    speckle), which keeps the host-side generation to seconds."""
+
+    def __init__(self, torch, dev, n_frames, autotune=True, losses=True):
+        import paper_2503_01074_amd as osm
+        import workloads as W
+        t0 = time.perf_counter()
+        self.torch = torch
+        base = W.sonar_c5(n_frames=4)
+        st = W.Stream(W.BASE_SEED + 4, 1 << 21)
+        self.water_h = W.make_water(st)
+        cams = [W.make_camera(W.Stream(W.BASE_SEED + 4, (1 << 22) + k), 1080, 1920) for k in range(4)]
+        self.hits, self.geoms, self.Js, self.ds = [], [], [], []
+        for k in range(n_frames):
+            f, c = base[k % 4], cams[k % 4]
+            self.hits.append(osm.DeviceHits.from_host(f.hits, dev))
+            g = osm.SonarGeometry.from_spec(f.spec, param_row=0)
+            g.frame_id = k
+            self.geoms.append(g)
+            self.Js.append(torch.as_tensor(c.J, device=dev))
+            self.ds.append(torch.as_tensor(c.depth, device=dev))
+        self.base = base
+        self.refl = torch.as_tensor(base[0].hits.refl, device=dev)
+        self.params = osm.sonar_params([osm.sonar_params_from_spec(base[0].spec)], dev)
+        w = self.water_h
+        self.water = osm.water_params([(w.beta_d, w.beta_b, w.b_inf)], dev)
+        self.plan = osm.Plan(list(zip(self.geoms, self.hits)), [(J, d, 0) for J, d in zip(self.Js, self.ds)],
+                             sonar_params=self.params, refl=self.refl, water=self.water, backward=True,
+                             autotune=autotune)
+        if losses:
+            gp = [torch.as_tensor(W.loss_weights((205, k), (2048, 2048)), device=dev) for k in range(4)]
+            go = [torch.as_tensor(W.loss_weights((206, k), (3, 1080, 1920)), device=dev) for k in range(4)]
+            for k, o in enumerate(self.plan.sonar_out):
+                o["grad_polar"].copy_(gp[k % 4])
+            for k, o in enumerate(self.plan.camera_out):
+                o["grad_out"].copy_(go[k % 4])
+        self.n_frames = n_frames
+        self.n_returns = sum(h.n for h in self.hits)
+        self.n_bins = n_frames * 2048 * 2048
+        self.n_px = n_frames * 1920 * 1080
+        log("calibration-scale workload: %d + %d frames prepared in %.1f s, plan shape %s"
+            % (n_frames, n_frames, time.perf_counter() - t0, self.plan.shape()))
+
+    def forward(self):
+        self.plan.forward()
+
+    def step(self):
+        self.plan.forward()
+        self.plan.backward()
+
+    def algorithmic_bytes(self):
+        """Bytes the method must move, per launch of each kernel and per step:
+        returns 28 B, polar bins 4 B out, camera pixels 28 B forward (J, d in,
+        I out) and 28 B backward (dL/dI, J, d in; no image gradients); the
+        sonar backward reads dL/d(polar) 4 B per bin and the returns 28 B."""
+        n, nb, npx = self.n_returns, self.n_bins, self.n_px
+        per_kernel = {"k_bin": 28 * n, "k_bin_uw": 28 * n + 28 * npx, "k_tile": 4 * nb, "k_uw": 28 * npx,
+                      "k_pair_bwd": 4 * nb + 28 * n, "k_fant_bwd": 4 * nb, "k_ret_bwd": 28 * n,
+                      "k_ret_uw_bwd": 28 * n + 28 * npx, "k_uw_bwd": 28 * npx}
+        fwd = 28 * n + 4 * nb + 28 * npx
+        bwd = 4 * nb + 28 * n + 28 * npx
+        return per_kernel, fwd, bwd
+
+
+def c1_leg(torch, dev, steps):
+    """One plain frame (256 beams x 32 rays, 512 x 256 bins, 512 x 1024 fan):
+    the forward through the plain entry point, one call per frame."""
+    import paper_2503_01074_amd as osm
+    from paper_2503_01074_amd import _lib
+    from paper_2503_01074_amd.api import _sonar_struct
+    import workloads as W
+    f = W.sonar_c1()[0]
+    g = osm.SonarGeometry.from_spec(f.spec)
+    h = osm.DeviceHits.from_host(f.hits, dev)
+    params = osm.sonar_params([osm.sonar_params_from_spec(f.spec)], dev)
+    refl = torch.as_tensor(f.hits.refl, device=dev)
+    polar = torch.empty(g.n_range, g.n_azimuth, device=dev)
+    fan = torch.empty(g.fan_h, g.fan_w, device=dev)
+    sf = _sonar_struct(g, h, polar, fan)
+    n_mat = int(refl.numel())
+    ws = torch.empty(max(256, _lib.oceansim_sonar_workspace_size(sf, n_mat, False)), dtype=torch.uint8, device=dev)
+    stream = torch.cuda.current_stream(dev).cuda_stream
+    P = lambda t: t.data_ptr()
+
+    def fwd():
+        _lib.oceansim_sonar_render(sf, P(params), 1, P(refl), n_mat, P(ws), ws.numel(), stream)
+    t = median_time(torch, fwd, max(50, steps * 5), 10)
+    tg = event_time(torch, fwd, max(50, steps * 5))
+    log("C1 plain forward: %.1f us per frame (wall), %.1f us (GPU events)" % (t * 1e6, tg * 1e6))
+    return {"returns": h.n, "fwd_us": t * 1e6, "fwd_gpu_us": tg * 1e6, "frames_per_s": 1.0 / t,
+            "returns_per_s": h.n / t}
+
+
+def c2_leg(torch, dev, steps):
+    """The real-time frame (131072 returns, 1024 x 1024 bins, 1024 x 2048 fan,
+    plus one 1920 x 1080 camera frame): forward + backward through the plan,
+    the plain entry points and graphs, the forward alone, and the same step
+    with the range-wise normalisation."""
+    rt = RealTimeStep(dev, range_norm=True)
+    k = max(50, steps * 5)
+    t_step = timed(torch, lambda: rt.plan_step("plan"), k, 10)
+    t_fwd = timed(torch, lambda: rt.plan_forward("plan"), k, 10)
+    t_pstep = timed(torch, rt.step, k, 10)
+    t_pfwd = timed(torch, rt.forward, k, 10)
+    t_sfwd = timed(torch, rt.sonar_forward, k, 10)
+    t_gstep = timed(torch, lambda: rt.plan_step("graph"), k, 10)
+    t_nstep = timed(torch, lambda: rt.plan_step("norm"), k, 10)
+    log("C2 real-time frame: plan step %.3f ms, forward %.3f ms; plain step %.3f ms; graph step %.3f ms; "
+        "range-normalised step %.3f ms" % (t_step * 1e3, t_fwd * 1e3, t_pstep * 1e3, t_gstep * 1e3, t_nstep * 1e3))
+    return {"returns": rt.n_returns, "camera_px": rt.npix, "step_ms": t_step * 1e3,
+            "returns_per_s": rt.n_returns / t_step, "frames_per_s": 2.0 / t_step, "fwd_ms": t_fwd * 1e3,
+            "plain_step_ms": t_pstep * 1e3, "plain_fwd_ms": t_pfwd * 1e3,
+            "plain_sonar_fwd_frames_per_s": 1.0 / t_sfwd, "graph_step_ms": t_gstep * 1e3,
+            "range_norm_step_ms": t_nstep * 1e3, "plan_shape": rt.plans["plan"].shape()}
+
+
+def c3_leg(torch, dev, steps):
+    """256 ragged sonar frames: forward only with one call per frame
+    (unbatched), forward through one batched call and an autotuned plan, and
+    forward + backward through the batched entry points (saved fan stencils,
+    per-return reflectivities: the polar-tile backward)."""
     import numpy as np
     import paper_2503_01074_amd as osm
     from paper_2503_01074_amd import _lib
-    from paper_2503_01074_amd.api import _sonar_struct, _uw_struct
+    from paper_2503_01074_amd.api import _sonar_struct
     import workloads as W
-
     stream = torch.cuda.current_stream(dev).cuda_stream
     P = lambda t: t.data_ptr()
-    out = {}
-    reps = max(5, steps // 10)
-
-    if only == "c4":
-        return c4_leg(torch, dev, steps, out)
     frames = W.sonar_c3()
     tables, base, hits = [], 0, []
     for f in frames:
@@ -309,50 +434,58 @@ def batched_legs(torch, dev, steps, only=None):
     params = osm.sonar_params([osm.sonar_params_from_spec(f.spec) for f in frames], dev)
     polars = [torch.empty(g.n_range, g.n_azimuth, device=dev) for g in geoms]
     fans = [torch.empty(g.fan_h, g.fan_w, device=dev) for g in geoms]
+    stencils = [osm.api.fan_stencil_buffer(g, dev) for g in geoms]
+    gp = [torch.as_tensor(W.loss_weights((301, k), (g.n_range, g.n_azimuth)), device=dev)
+          for k, g in enumerate(geoms)]
+    gf = [torch.as_tensor(W.loss_weights((302, k), (g.fan_h, g.fan_w)), device=dev) for k, g in enumerate(geoms)]
     structs = [_sonar_struct(g, h, p, q) for g, h, p, q in zip(geoms, hits, polars, fans)]
+    sf = (_lib.SonarFrame * len(frames))(*[_sonar_struct(g, h, p, q, stencil=sv) for g, h, p, q, sv in
+                                           zip(geoms, hits, polars, fans, stencils)])
+    sb = (_lib.SonarFrame * len(frames))(*[_sonar_struct(g, h, grad_polar=a, grad_fan=b, stencil=sv)
+                                           for g, h, a, b, sv in zip(geoms, hits, gp, gf, stencils)])
     arr = (_lib.SonarFrame * len(frames))(*structs)
     need = _lib.oceansim_sonar_workspace_size(arr, n_mat, False)
     ws = torch.empty(need, dtype=torch.uint8, device=dev)
+    ws_f = torch.empty(_lib.oceansim_sonar_workspace_size(sf, n_mat, False), dtype=torch.uint8, device=dev)
+    ws_b = torch.empty(_lib.oceansim_sonar_workspace_size(sb, n_mat, True), dtype=torch.uint8, device=dev)
+    g_refl = torch.empty(n_mat, device=dev)
+    g_par = torch.empty(len(frames), _lib.SONAR_GRAD_WIDTH, device=dev)
     n_ret = sum(f.hits.n for f in frames)
     n_fr = len(frames)
 
-    def c3():
+    def fwd_batched():
         _lib.oceansim_sonar_render(arr, P(params), n_fr, P(refl), n_mat, P(ws), need, stream)
 
-    def c3_plain():
-        for sf in structs:
-            _lib.oceansim_sonar_render(sf, P(params), n_fr, P(refl), n_mat, P(ws), need, stream)
+    def fwd_unbatched():
+        for s1 in structs:
+            _lib.oceansim_sonar_render(s1, P(params), n_fr, P(refl), n_mat, P(ws), need, stream)
 
-    t = median_time(torch, c3, reps, 3)
-    t_plain = median_time(torch, c3_plain, max(3, reps // 4), 1)
-    _lib.oceansim_trace_enable(True)
-    for _ in range(3):
-        c3()
-    torch.cuda.synchronize()
-    tr = _lib.oceansim_trace_summary()
-    _lib.oceansim_trace_enable(False)
+    def step_batched():
+        _lib.oceansim_sonar_render(sf, P(params), n_fr, P(refl), n_mat, P(ws_f), ws_f.numel(), stream)
+        _lib.oceansim_sonar_render_backward(sb, P(params), n_fr, P(refl), n_mat, P(g_refl), P(g_par), P(ws_b),
+                                            ws_b.numel(), stream)
+
+    reps = max(5, steps // 2)
+    t_b = median_time(torch, fwd_batched, reps, 3)
+    t_u = median_time(torch, fwd_unbatched, max(3, reps // 4), 1)
+    t_s = median_time(torch, step_batched, reps, 3)
     plan = osm.Plan(list(zip(geoms, hits)), sonar_params=params, refl=refl, autotune=True)
-    t_plan = median_time(torch, plan.forward, reps, 3)
+    t_p = median_time(torch, plan.forward, reps, 3)
     shape = plan.shape()
     plan.close()
-    out["batched_c3_fwd"] = {"frames": n_fr, "returns": n_ret, "ms": t * 1e3,
-                             "frames_per_s": n_fr / t, "returns_per_s": n_ret / t,
-                             "plain_ms": t_plain * 1e3, "plain_frames_per_s": n_fr / t_plain,
-                             "plan_ms": t_plan * 1e3, "plan_frames_per_s": n_fr / t_plan,
-                             "plan_returns_per_s": n_ret / t_plan, "autotuned_shape": shape,
-                             "kernels_us": {k: round(us / calls, 1) for k, (calls, us) in tr.items()}}
-    log("C3 forward, 256 frames: batched call %.3f ms, one call per frame %.3f ms, autotuned plan %.3f ms %s"
-        % (t * 1e3, t_plain * 1e3, t_plan * 1e3, shape))
-    del hits, polars, fans, ws, arr, structs
-    torch.cuda.empty_cache()
-    if only == "c3":
-        return out
-    return c4_leg(torch, dev, steps, out)
+    log("C3 ragged batch, 256 frames: unbatched forward %.3f ms, batched forward %.3f ms, plan forward %.3f ms, "
+        "batched forward + backward %.3f ms" % (t_u * 1e3, t_b * 1e3, t_p * 1e3, t_s * 1e3))
+    return {"frames": n_fr, "returns": n_ret, "unbatched_fwd_ms": t_u * 1e3,
+            "unbatched_fwd_frames_per_s": n_fr / t_u, "batched_fwd_ms": t_b * 1e3,
+            "batched_fwd_frames_per_s": n_fr / t_b, "plan_fwd_ms": t_p * 1e3, "plan_fwd_frames_per_s": n_fr / t_p,
+            "plan_fwd_returns_per_s": n_ret / t_p, "batched_fwd_bwd_ms": t_s * 1e3,
+            "batched_fwd_bwd_frames_per_s": n_fr / t_s, "autotuned_shape": shape}
 
 
-def c4_leg(torch, dev, steps, out):
-    """32 sonar + 32 camera frames, forward and forward + backward: one call
-    per entry point for the whole batch, and a plan."""
+def c4_leg(torch, dev, steps):
+    """32 sonar + 32 camera frames: forward only with one call per frame
+    (unbatched), and forward + backward through the batched entry points and
+    through an autotuned plan."""
     import paper_2503_01074_amd as osm
     from paper_2503_01074_amd import _lib
     from paper_2503_01074_amd.api import _sonar_struct, _uw_struct
@@ -373,10 +506,12 @@ def c4_leg(torch, dev, steps, out):
     gp = [torch.as_tensor(W.loss_weights((202, k), (g.n_range, g.n_azimuth)), device=dev)
           for k, g in enumerate(geoms)]
     gf = [torch.as_tensor(W.loss_weights((203, k), (g.fan_h, g.fan_w)), device=dev) for k, g in enumerate(geoms)]
+    s1 = [_sonar_struct(g, h, p, q) for g, h, p, q in zip(geoms, hits, polars, fans)]
     sf = (_lib.SonarFrame * len(frames))(*[_sonar_struct(g, h, p, q, stencil=sv) for g, h, p, q, sv in
                                            zip(geoms, hits, polars, fans, stencils)])
     sb = (_lib.SonarFrame * len(frames))(*[_sonar_struct(g, h, grad_polar=a, grad_fan=b, stencil=sv)
                                            for g, h, a, b, sv in zip(geoms, hits, gp, gf, stencils)])
+    ws_1 = torch.empty(_lib.oceansim_sonar_workspace_size(s1[0], n_mat, False), dtype=torch.uint8, device=dev)
     ws_f = torch.empty(_lib.oceansim_sonar_workspace_size(sf, n_mat, False), dtype=torch.uint8, device=dev)
     ws_b = torch.empty(_lib.oceansim_sonar_workspace_size(sb, n_mat, True), dtype=torch.uint8, device=dev)
     g_refl = torch.empty(n_mat, device=dev)
@@ -385,145 +520,180 @@ def c4_leg(torch, dev, steps, out):
     ds = [torch.as_tensor(c.depth, device=dev) for c in cams]
     imgs = [torch.empty_like(J) for J in Js]
     gi = [torch.as_tensor(W.loss_weights((204, k), c.J.shape), device=dev) for k, c in enumerate(cams)]
-    gJ = [torch.empty_like(J) for J in Js]
-    gd = [torch.empty_like(d) for d in ds]
     w = waters[0]
     water = osm.water_params([(w.beta_d, w.beta_b, w.b_inf)], dev)
-    uf = (_lib.UwFrame * len(cams))(*[_uw_struct(J, d, o) for J, d, o in zip(Js, ds, imgs)])
-    ub = (_lib.UwFrame * len(cams))(*[_uw_struct(J, d, None, 0, g, a, b) for J, d, g, a, b in
-                                      zip(Js, ds, gi, gJ, gd)])
+    u1 = [_uw_struct(J, d, o) for J, d, o in zip(Js, ds, imgs)]
+    uf = (_lib.UwFrame * len(cams))(*u1)
+    ub = (_lib.UwFrame * len(cams))(*[_uw_struct(J, d, None, 0, g) for J, d, g in zip(Js, ds, gi)])
     ws_uf = torch.empty(max(256, _lib.oceansim_uw_workspace_size(uf, False)), dtype=torch.uint8, device=dev)
     ws_ub = torch.empty(max(256, _lib.oceansim_uw_workspace_size(ub, True)), dtype=torch.uint8, device=dev)
     g_w = torch.empty(1, _lib.WATER_GRAD_WIDTH, device=dev)
     n_ret = sum(f.hits.n for f in frames)
     n_fr = len(frames) + len(cams)
 
-    def c4_fwd():
+    def fwd_unbatched():
+        for s in s1:
+            _lib.oceansim_sonar_render(s, P(params), 1, P(refl), n_mat, P(ws_1), ws_1.numel(), stream)
+        for u in u1:
+            _lib.oceansim_uw_form(u, P(water), 1, P(ws_uf), ws_uf.numel(), stream)
+
+    def step_batched():
         _lib.oceansim_sonar_render(sf, P(params), 1, P(refl), n_mat, P(ws_f), ws_f.numel(), stream)
         _lib.oceansim_uw_form(uf, P(water), 1, P(ws_uf), ws_uf.numel(), stream)
-
-    def c4_step():
-        c4_fwd()
         _lib.oceansim_sonar_render_backward(sb, P(params), 1, P(refl), n_mat, P(g_refl), P(g_par), P(ws_b),
                                             ws_b.numel(), stream)
         _lib.oceansim_uw_form_backward(ub, P(water), 1, P(g_w), P(ws_ub), ws_ub.numel(), stream)
 
-    tf = median_time(torch, c4_fwd, max(5, steps // 5), 3)
-    ts = median_time(torch, c4_step, max(5, steps // 5), 3)
+    reps = max(5, steps // 2)
+    t_u = median_time(torch, fwd_unbatched, reps, 3)
+    t_s = median_time(torch, step_batched, reps, 3)
     plan = osm.Plan(list(zip(geoms, hits)), list(zip(Js, ds, [0] * len(cams))), sonar_params=params, refl=refl,
-                    water=water, backward=True, autotune=True, image_grads=True)
+                    water=water, backward=True, autotune=True)
     for o, a, b in zip(plan.sonar_out, gp, gf):
         o["grad_polar"].copy_(a)
         o["grad_fan"].copy_(b)
     for o, g in zip(plan.camera_out, gi):
         o["grad_out"].copy_(g)
 
-    def c4_plan_step():
+    def plan_step():
         plan.forward()
         plan.backward()
-    tgf = median_time(torch, plan.forward, max(5, steps // 5), 3)
-    tgs = median_time(torch, c4_plan_step, max(5, steps // 5), 3)
+    t_pf = median_time(torch, plan.forward, reps, 3)
+    t_ps = median_time(torch, plan_step, reps, 3)
     shape = plan.shape()
     plan.close()
-    out["batched_c4"] = {"sonar_frames": len(frames), "camera_frames": len(cams), "returns": n_ret,
-                         "fwd_ms": tf * 1e3, "fwd_bwd_ms": ts * 1e3,
-                         "fwd_bwd_frames_per_s": n_fr / ts, "fwd_bwd_returns_per_s": n_ret / ts,
-                         "plan_fwd_ms": tgf * 1e3, "plan_fwd_bwd_ms": tgs * 1e3,
-                         "plan_fwd_bwd_frames_per_s": n_fr / tgs, "plan_fwd_bwd_returns_per_s": n_ret / tgs,
-                         "autotuned_shape": shape}
-    log("C4 batched: fwd %.3f ms, fwd+bwd %.3f ms; autotuned plan fwd %.3f ms, fwd+bwd %.3f ms %s"
-        % (tf * 1e3, ts * 1e3, tgf * 1e3, tgs * 1e3, shape))
-    return out
+    log("C4 differentiable batch, 32 + 32 frames: unbatched forward %.3f ms; batched forward + backward %.3f ms; "
+        "plan forward %.3f ms, forward + backward %.3f ms %s"
+        % (t_u * 1e3, t_s * 1e3, t_pf * 1e3, t_ps * 1e3, shape))
+    return {"sonar_frames": len(frames), "camera_frames": len(cams), "returns": n_ret,
+            "unbatched_fwd_ms": t_u * 1e3, "unbatched_fwd_frames_per_s": n_fr / t_u,
+            "batched_fwd_bwd_ms": t_s * 1e3, "batched_fwd_bwd_frames_per_s": n_fr / t_s,
+            "plan_fwd_ms": t_pf * 1e3, "plan_fwd_bwd_ms": t_ps * 1e3, "plan_fwd_bwd_frames_per_s": n_fr / t_ps,
+            "plan_fwd_bwd_returns_per_s": n_ret / t_ps, "autotuned_shape": shape}
 
 
-def cpu_baseline(rt, budget_s):
-    """The FP64 oracle on this host's cores over a bounded sample of the same
-    workload: whole sonar frames (forward + backward) and the camera frame."""
+def calibration_run(torch, dev, n_frames, n_steps):
+    """Sim-to-real calibration at scale: the targets are rendered with hidden
+    parameters (sonar alpha, sigma_phi, sigma_sa, the 64 reflectivities; the
+    water row), then Adam (learning rate 1e-2, on the logarithms of the
+    parameters) starts from hidden x U[0.5, 1.5] and minimises the mean
+    squared error of all polar and camera images through the plan's adjoints.
+    G is held fixed (it trades off against the reflectivities); both sides use
+    the same speckle draws."""
     import numpy as np
+    cs = CalibrationScale(torch, dev, n_frames, autotune=True, losses=False)
+    plan = cs.plan
+    base = cs.base[0].spec
+    hidden_sonar = np.array([base.alpha, base.sigma_phi, base.sigma_sa], np.float64)
+    hidden_refl = cs.refl.double().cpu().numpy()
+    w = cs.water_h
+    hidden_water = np.concatenate([w.beta_d, w.beta_b, w.b_inf]).astype(np.float64)
+    t0 = time.perf_counter()
+    plan.forward()
+    tgt_s = [o["polar"].clone() for o in plan.sonar_out]
+    tgt_c = [o["out"].clone() for o in plan.camera_out]
+    rng = np.random.default_rng(250301074)
+    hidden = (hidden_sonar, hidden_refl, hidden_water)
+    starts = [np.asarray(v, np.float64) * rng.uniform(0.5, 1.5, np.shape(v)) for v in hidden]
+    start_err = max(float(np.max(np.abs(a - b) / np.abs(b))) for a, b in zip(starts, hidden))
+    theta = [torch.tensor(np.log(v), device=dev, requires_grad=True) for v in starts]
+    opt = torch.optim.Adam(theta, lr=1e-2)
+    scale_s = 1.0 / float(sum((t.double() ** 2).sum() for t in tgt_s))
+    scale_c = 1.0 / float(sum((t.double() ** 2).sum() for t in tgt_c))
+    loss_dev = torch.zeros((), dtype=torch.float64, device=dev)
+    first = None
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    for step in range(n_steps):
+        with torch.no_grad():
+            ps = theta[0].exp()
+            cs.params[0, 0], cs.params[0, 2], cs.params[0, 3] = ps[0], ps[1], ps[2]
+            cs.refl.copy_(theta[1].exp())
+            cs.water[0, :9] = theta[2].exp()
+        plan.forward()
+        loss_dev.zero_()
+        for o, t in zip(plan.sonar_out, tgt_s):
+            r = o["polar"] - t
+            torch.mul(r, 2.0 * scale_s, out=o["grad_polar"])
+            loss_dev += scale_s * torch.dot(r.view(-1), r.view(-1)).double()
+        for o, t in zip(plan.camera_out, tgt_c):
+            r = o["out"] - t
+            torch.mul(r, 2.0 * scale_c, out=o["grad_out"])
+            loss_dev += scale_c * torch.dot(r.view(-1), r.view(-1)).double()
+        plan.backward()
+        if first is None:
+            first = float(loss_dev)
+        with torch.no_grad():
+            g = plan.grad_sonar_params[0]
+            theta[0].grad = torch.stack([g[0], g[2], g[3]]).double() * theta[0].exp()
+            theta[1].grad = plan.grad_refl.double() * theta[1].exp()
+            theta[2].grad = plan.grad_water[0, :9].double() * theta[2].exp()
+        opt.step()
+    torch.cuda.synchronize()
+    t_loop = time.perf_counter() - t1
+    last = float(loss_dev)
+    got = [t.detach().exp().cpu().numpy() for t in theta]
+    rel = lambda a, b: np.abs(a - b) / np.abs(b)
+    names = ["alpha", "sigma_phi", "sigma_sa"]
+    res = {"sonar_frames": n_frames, "camera_frames": n_frames, "steps": n_steps, "optimizer": "Adam lr 1e-2 on log parameters",
+           "loss_first": first, "loss_last": last, "loss_reduction": last / first if first else None,
+           "loop_s": t_loop, "ms_per_adam_step": t_loop / n_steps * 1e3,
+           "rel_err": {**{n: float(v) for n, v in zip(names, rel(got[0], hidden_sonar))},
+                       "refl_max": float(rel(got[1], hidden_refl).max()),
+                       "refl_median": float(np.median(rel(got[1], hidden_refl))),
+                       "beta_d": [float(v) for v in rel(got[2][:3], hidden_water[:3])],
+                       "beta_b": [float(v) for v in rel(got[2][3:6], hidden_water[3:6])],
+                       "b_inf": [float(v) for v in rel(got[2][6:], hidden_water[6:])]},
+           "start_rel_err_max": start_err}
+    log("calibration run, %d + %d frames, %d Adam steps in %.2f s (%.2f ms per step): loss %.3e -> %.3e; "
+        "relative errors %s" % (n_frames, n_frames, n_steps, t_loop, t_loop / n_steps * 1e3, first, last,
+                                res["rel_err"]))
+    plan.close()
+    return res
+
+
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.lower().startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
+def cpu_baseline(budget_s):
+    """The FP64 oracle on this host's cores over a bounded sample of the
+    calibration-scale workload: whole frames (one 2,097,152-return sonar frame
+    forward + backward and one 1920 x 1080 camera frame forward + backward) for
+    about `budget_s` seconds, scaled to returns per second."""
     import oracle
     import workloads as W
-
-    spec = rt.frame.spec
+    frame = W.sonar_c5(n_frames=1)[0]
+    cam = W.make_camera(W.Stream(W.BASE_SEED + 4, 1 << 22), 1080, 1920)
+    w = W.make_water(W.Stream(W.BASE_SEED + 4, 1 << 21))
+    spec = frame.spec
     cfg = oracle.SonarConfig.from_spec(spec)
-    hits = rt.frame.hits
-    gp = W.loss_weights((101, 1), (spec.n_range, spec.n_azimuth))
-    gf = W.loss_weights((101, 2), (spec.fan_h, spec.fan_w))
-    w = rt.water_host
-    gi = W.loss_weights((101, 3), rt.cam.J.shape)
+    hits = frame.hits
+    gp = W.loss_weights((205, 0), (spec.n_range, spec.n_azimuth))
+    gi = W.loss_weights((206, 0), cam.J.shape)
     t0 = time.perf_counter()
     n = 0
     while True:
         oracle.sonar_forward(cfg, hits, hits.refl)
-        oracle.uw_forward(rt.cam.J, rt.cam.depth, w.beta_d, w.beta_b, w.b_inf)
-        oracle.sonar_backward(cfg, hits, hits.refl, gp, gf)
-        oracle.uw_backward(rt.cam.J, rt.cam.depth, w.beta_d, w.beta_b, w.b_inf, gi, True)
+        oracle.uw_forward(cam.J, cam.depth, w.beta_d, w.beta_b, w.b_inf)
+        oracle.sonar_backward(cfg, hits, hits.refl, gp, None)
+        oracle.uw_backward(cam.J, cam.depth, w.beta_d, w.beta_b, w.b_inf, gi, False)
         n += 1
         el = time.perf_counter() - t0
-        if el >= budget_s or n >= 50:
+        if el >= budget_s or n >= 20:
             break
     return {"value": n * hits.n / el, "unit": "returns/s", "cores": oracle.num_threads(), "kind": "oracle",
-            "sample": "%d full step(s) of the real-time workload (sonar fwd+bwd, camera fwd+bwd) in %.1f s"
-                      % (n, el)}
-
-
-def calibration_leg(torch, dev, steps, n_frames):
-    """Calibration scale: n_frames sonar frames of 2048 x 1024 returns (2048 x
-    2048 bins, no fan, 64 materials, gamma speckle) and n_frames 1920 x 1080
-    camera frames, forward and forward + backward through an autotuned plan
-    (polar and image losses).  Four distinct sonar and camera frames are
-    generated and uploaded n_frames / 4 times each (separate device buffers,
-    distinct frame ids, so distinct speckle), which keeps the host-side
-    generation to seconds."""
-    import paper_2503_01074_amd as osm
-    import workloads as W
-    t0 = time.perf_counter()
-    base = W.sonar_c5(n_frames=4)
-    st = W.Stream(W.BASE_SEED + 4, 1 << 21)
-    water_h = W.make_water(st)
-    cams = [W.make_camera(W.Stream(W.BASE_SEED + 4, (1 << 22) + k), 1080, 1920) for k in range(4)]
-    hits, geoms, Js, ds = [], [], [], []
-    for k in range(n_frames):
-        f, c = base[k % 4], cams[k % 4]
-        hits.append(osm.DeviceHits.from_host(f.hits, dev))
-        g = osm.SonarGeometry.from_spec(f.spec, param_row=0)
-        g.frame_id = k
-        geoms.append(g)
-        Js.append(torch.as_tensor(c.J, device=dev))
-        ds.append(torch.as_tensor(c.depth, device=dev))
-    refl = torch.as_tensor(base[0].hits.refl, device=dev)
-    params = osm.sonar_params([osm.sonar_params_from_spec(base[0].spec)], dev)
-    water = osm.water_params([(water_h.beta_d, water_h.beta_b, water_h.b_inf)], dev)
-    plan = osm.Plan(list(zip(geoms, hits)), [(J, d, 0) for J, d in zip(Js, ds)], sonar_params=params, refl=refl,
-                    water=water, backward=True, autotune=True)
-    gp = [torch.as_tensor(W.loss_weights((205, k), (2048, 2048)), device=dev) for k in range(4)]
-    go = [torch.as_tensor(W.loss_weights((206, k), (3, 1080, 1920)), device=dev) for k in range(4)]
-    for k, o in enumerate(plan.sonar_out):
-        o["grad_polar"].copy_(gp[k % 4])
-    for k, o in enumerate(plan.camera_out):
-        o["grad_out"].copy_(go[k % 4])
-    log("C5 leg: %d + %d frames prepared in %.1f s" % (n_frames, n_frames, time.perf_counter() - t0))
-
-    def step():
-        plan.forward()
-        plan.backward()
-    n = max(3, steps // 20)
-    tf = median_time(torch, plan.forward, n, 2, 3)
-    ts = median_time(torch, step, n, 2, 3)
-    n_ret = sum(h.n for h in hits)
-    nb = n_frames * 2048 * 2048
-    npx = n_frames * 1920 * 1080
-    alg_f = 28 * n_ret + 4 * nb + 28 * npx
-    alg_s = alg_f + 28 * n_ret + 4 * nb + 44 * npx
-    shape = plan.shape()
-    log("C5 calibration scale, %d + %d frames: fwd %.3f ms (%.2f TB/s algorithmic, %.2f of 8 TB/s), fwd+bwd "
-        "%.3f ms (%.2f TB/s, %.2f), %.2f G returns/s, shape %s"
-        % (n_frames, n_frames, tf * 1e3, alg_f / tf / 1e12, alg_f / tf / 8e12, ts * 1e3, alg_s / ts / 1e12,
-           alg_s / ts / 8e12, n_ret / ts / 1e9, shape))
-    plan.close()
-    return {"sonar_frames": n_frames, "camera_frames": n_frames, "returns": n_ret, "distinct_frames": 4,
-            "fwd_ms": tf * 1e3, "fwd_bwd_ms": ts * 1e3, "fwd_bwd_returns_per_s": n_ret / ts,
-            "fwd_alg_TBps": alg_f / tf / 1e12, "fwd_bwd_alg_TBps": alg_s / ts / 1e12,
-            "fwd_bwd_hbm_frac": alg_s / ts / (HBM_PEAK_GBS * 1e9), "autotuned_shape": shape}
+            "cpu_model": cpu_model(), "nproc": os.cpu_count(),
+            "sample": "%d sonar frame(s) of the calibration-scale workload (2,097,152 returns, 2048 x 2048 bins, "
+                      "forward + backward) each with one 1920 x 1080 camera frame (forward + backward) in %.1f s; "
+                      "a full step is 64 of each" % (n, el)}
 
 
 def camera_io_leg(torch, dev, steps):
@@ -572,6 +742,7 @@ def camera_io_leg(torch, dev, steps):
             "range_backward_us": round(t_b * 1e6, 2), "range_backward_GBps": rate(8, t_b)}
 
 
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -585,84 +756,95 @@ def main():
     if args.copy_calibration:
         copy_calibration(torch, dev)
         return
+    if args.only == "c2":
+        c2_leg(torch, dev, args.steps)
+        return
+    if args.only == "c3":
+        c3_leg(torch, dev, args.steps)
+        return
+    if args.only == "c4":
+        c4_leg(torch, dev, args.steps)
+        return
+    from paper_2503_01074_amd import _lib
+
+    cs = CalibrationScale(torch, dev, args.c5_frames)
     if args.only == "c5":
-        calibration_leg(torch, dev, args.steps, args.c5_frames)
+        t = timed(torch, cs.step, args.steps, args.warmup)
+        log("calibration-scale step: %.3f ms" % (t * 1e3))
         return
-    if args.only:
-        legs = batched_legs(torch, dev, args.steps, only=args.only)
-        log("done: %s" % ", ".join(sorted(legs)))
-        return
-    log("building workload")
-    rt = RealTimeStep(dev, range_norm=not args.no_range_norm)
 
-    # The step: the plan (frames prepared once, launch shapes autotuned),
-    # forward + backward, K times after W warm-up steps, timed by the host
-    # clock between two device synchronisations.
+    # The step: forward + backward of all frames through the plan, K times
+    # after W warm-up steps, timed by the host clock between two device
+    # synchronisations.
     log("timing %d full steps after %d warm-up" % (args.steps, args.warmup))
-    headline = lambda: rt.plan_step("plan")
-    t_step = timed(torch, headline, args.steps, args.warmup)
-    t_fwd = timed(torch, lambda: rt.plan_forward("plan"), args.steps, args.warmup)
-    log("plan: step %.3f ms, forward %.3f ms, shape %s" % (t_step * 1e3, t_fwd * 1e3, rt.plans["plan"].shape()))
-    # the same step through the plain entry points (one call per entry point)
-    # and through the plan's HIP graphs
-    t_pstep = timed(torch, rt.step, args.steps, args.warmup)
-    t_pfwd = timed(torch, rt.forward, args.steps, args.warmup)
-    t_sonar_fwd = timed(torch, rt.sonar_forward, args.steps, args.warmup)
-    t_gstep = timed(torch, lambda: rt.plan_step("graph"), args.steps, args.warmup)
-    t_gfwd = timed(torch, lambda: rt.plan_forward("graph"), args.steps, args.warmup)
-    log("plain entry points: step %.3f ms, forward %.3f ms, sonar forward %.3f ms; graph plan: step %.3f ms, "
-        "forward %.3f ms" % (t_pstep * 1e3, t_pfwd * 1e3, t_sonar_fwd * 1e3, t_gstep * 1e3, t_gfwd * 1e3))
-    norm = None
-    if "norm" in rt.plans:
-        t_nstep = timed(torch, lambda: rt.plan_step("norm"), args.steps, args.warmup)
-        t_nfwd = timed(torch, lambda: rt.plan_forward("norm"), args.steps, args.warmup)
-        log("with range-wise normalisation: step %.3f ms, forward %.3f ms" % (t_nstep * 1e3, t_nfwd * 1e3))
-        norm = {"step_ms": t_nstep * 1e3, "returns_per_s": rt.n_returns / t_nstep, "fwd_ms": t_nfwd * 1e3}
+    t_step = timed(torch, cs.step, args.steps, args.warmup)
+    t_fwd = timed(torch, cs.forward, args.steps, args.warmup)
+    log("calibration-scale step %.3f ms, forward %.3f ms" % (t_step * 1e3, t_fwd * 1e3))
 
-    # per-entry-point GPU durations from events on the launch stream
-    reps = max(20, args.steps)
-    parts = {
-        "sonar_forward": event_time(torch, rt.sonar_forward, reps),
-        "sonar_backward": event_time(torch, rt.sonar_backward, reps),
-        "uw_forward": event_time(torch, rt.uw_forward, reps),
-        "uw_backward": event_time(torch, rt.uw_backward, reps),
-    }
     # per-kernel durations: the library brackets each launch with HIP events
     # on its stream while tracing is on
-    rt.lib.oceansim_trace_enable(True)
+    reps = max(5, args.steps // 2)
+    _lib.oceansim_trace_enable(True)
     for _ in range(reps):
-        headline()
+        cs.step()
     torch.cuda.synchronize()
-    trace = rt.lib.oceansim_trace_summary()
-    rt.lib.oceansim_trace_enable(False)
+    trace = _lib.oceansim_trace_summary()
+    _lib.oceansim_trace_enable(False)
     kern_us = {k: us / calls for k, (calls, us) in trace.items()}
     dom = max(kern_us, key=lambda k: kern_us[k] * trace[k][0])
-    abytes = rt.algorithmic_bytes()
+    abytes, fwd_bytes, bwd_bytes = cs.algorithmic_bytes()
+    prof = measured_profile()
     dom_bytes = abytes.get(dom)
     achieved = dom_bytes / (kern_us[dom] * 1e-6) / 1e9 if dom_bytes else None
+    traffic = None
+    valu_frac = None
+    if prof and dom in prof:
+        traffic = int(prof[dom]["fetch_bytes"] + prof[dom]["write_bytes"])
+        if prof[dom].get("valu_insts"):
+            valu_frac = round(prof[dom]["valu_insts"] * 64 / (kern_us[dom] * 1e-6) / VALU_PEAK_LANE_OPS, 4)
     roofline = {"bound": "hbm", "kernel": dom,
                 "achieved": None if achieved is None else round(achieved, 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": None if achieved is None else round(achieved / HBM_PEAK_GBS, 4),
-                "traffic": measured_traffic(dom), "bytes_per_launch": dom_bytes, "launch_us": round(kern_us[dom], 2)}
-    kernel_table = {k: {"us": round(kern_us[k], 2), "alg_bytes": abytes.get(k),
-                        "alg_GBps": round(abytes[k] / (kern_us[k] * 1e-6) / 1e9, 1) if k in abytes else None}
-                    for k in sorted(kern_us, key=lambda k: -kern_us[k])}
-    log("kernels (us): " + ", ".join("%s %.2f" % (k, v["us"]) for k, v in kernel_table.items()))
+                "traffic": traffic, "bytes_per_launch": dom_bytes, "launch_us": round(kern_us[dom], 2),
+                "valu_frac": valu_frac}
+    kernel_table = {}
+    for k in sorted(kern_us, key=lambda k: -kern_us[k] * trace[k][0]):
+        row = {"calls_per_step": trace[k][0] / reps, "us": round(kern_us[k], 2), "alg_bytes": abytes.get(k),
+               "alg_GBps": round(abytes[k] / (kern_us[k] * 1e-6) / 1e9, 1) if k in abytes else None}
+        if prof and k in prof:
+            row["traffic_bytes"] = int(prof[k]["fetch_bytes"] + prof[k]["write_bytes"])
+            if prof[k].get("valu_insts"):
+                row["valu_frac"] = round(prof[k]["valu_insts"] * 64 / (kern_us[k] * 1e-6) / VALU_PEAK_LANE_OPS, 3)
+        kernel_table[k] = row
+    log("kernels (us per launch): " + ", ".join("%s %.1f" % (k, v["us"]) for k, v in kernel_table.items()))
+    step_bytes = fwd_bytes + bwd_bytes
+    n_ret = cs.n_returns
+    n_frames = cs.n_frames
+    shape = cs.plan.shape()
+    cs.plan.close()
+    del cs
+    torch.cuda.empty_cache()
 
     extra = {}
     if not args.no_batched:
-        extra = batched_legs(torch, dev, args.steps)
-        extra["calibration_c5"] = calibration_leg(torch, dev, args.steps, args.c5_frames)
+        extra["calibration_c5_adam"] = calibration_run(torch, dev, args.c5_frames, args.calib_steps)
+        torch.cuda.empty_cache()
+        extra["plain_c1"] = c1_leg(torch, dev, args.steps)
+        extra["real_time_c2"] = c2_leg(torch, dev, args.steps)
+        torch.cuda.empty_cache()
+        extra["batched_c3"] = c3_leg(torch, dev, args.steps)
+        torch.cuda.empty_cache()
+        extra["batched_c4"] = c4_leg(torch, dev, args.steps)
+        torch.cuda.empty_cache()
         extra["camera_io"] = camera_io_leg(torch, dev, args.steps)
-        log("camera io: %s" % extra["camera_io"])
     cpu = None
     if not args.no_cpu:
         log("timing the FP64 oracle on the host")
-        cpu = cpu_baseline(rt, args.cpu_seconds)
+        cpu = cpu_baseline(args.cpu_seconds)
 
     line = {
         "metric": "sonar returns/s + frames/s (fwd, fwd+bwd, batched vs plain) at <=1e-5 rel err",
-        "value": rt.n_returns / t_step,
+        "value": n_ret / t_step,
         "unit": "returns/s",
         "n_gpus": 1,
         "steps": args.steps,
@@ -673,21 +855,21 @@ def main():
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": "real-time frame: 131072 sonar returns (1024 beams x 128 rays, r in [1,50) m), "
-                               "1024x1024 polar bins, gamma speckle k=4, 1024x2048 fan, plus Eq. 1 on one "
-                               "1920x1080 RGB frame; forward + backward",
-                   "global_batch": 1, "parallelism": "none (1 GPU)"},
-        "path": "plan (frames prepared once, autotuned launch shapes, camera work inside the sonar binning and return-gather launches)",
-        "frames_per_s": 1.0 / t_step,
-        "fwd_returns_per_s": rt.n_returns / t_fwd,
-        "fwd_frames_per_s": 1.0 / t_fwd,
-        "plain": {"step_ms": t_pstep * 1e3, "returns_per_s": rt.n_returns / t_pstep, "fwd_ms": t_pfwd * 1e3,
-                  "sonar_fwd_only_frames_per_s": 1.0 / t_sonar_fwd},
-        "graph": {"step_ms": t_gstep * 1e3, "returns_per_s": rt.n_returns / t_gstep, "fwd_ms": t_gfwd * 1e3},
-        "range_norm": norm,
+        "config": {"workload": "calibration scale: %d sonar frames x 2,097,152 returns (2048 beams x 1024 rays, "
+                               "r in [0.5,50) m, 64 materials, gamma speckle k=4), 2048x2048 polar bins, no fan, "
+                               "plus Eq. 1 on %d RGB frames of 1920x1080; forward + backward (polar and image "
+                               "losses) through one autotuned plan" % (n_frames, n_frames),
+                   "global_batch": 2 * n_frames, "parallelism": "none (1 GPU)"},
+        "path": "plan (frames prepared once, autotuned launch shapes; backward from the forward's material pairs)",
+        "frames_per_s": 2 * n_frames / t_step,
+        "fwd_ms": t_fwd * 1e3,
+        "fwd_returns_per_s": n_ret / t_fwd,
+        "fwd_frames_per_s": 2 * n_frames / t_fwd,
+        "step_alg_bytes": step_bytes,
+        "step_hbm_frac": round(step_bytes / t_step / (HBM_PEAK_GBS * 1e9), 4),
+        "fwd_hbm_frac": round(fwd_bytes / t_fwd / (HBM_PEAK_GBS * 1e9), 4),
+        "autotuned_shape": shape,
         "copy_GBps": copy_rate(torch, dev),
-        "camera_mpx_per_s_fwd_bwd": rt.npix / t_step / 1e6,
-        "entry_point_us": {k: round(v * 1e6, 2) for k, v in parts.items()},
         "kernels": kernel_table,
         "roofline": roofline,
         "cpu_baseline": cpu,

@@ -291,11 +291,20 @@ int autotune(oceansim_plan *p, hipStream_t st) {
             c.t.chunk = ch;
             cands.push_back(c);
         }
-    size_t ws = 0;
+    // A pair backward runs one workgroup per forward tile: with it, the tile
+    // and chunk sizes are timed on the forward and the backward together.
+    const bool with_bwd = p->pair && (p->flags & OCEANSIM_PLAN_BACKWARD);
+    size_t ws = 0, wsb_pair = 0;
     for (auto &c : cands) {
         int rc = plan_sonar(p->sonar.data(), n, p->n_srows, p->n_mat, false, c.f, &c.t, true, p->pair);
         if (rc) return rc;
         ws = std::max(ws, c.f.bytes);
+        if (with_bwd) {
+            rc = plan_sonar(p->sonar.data(), n, p->n_srows, p->n_mat, true, c.b, &c.t, true, true);
+            if (rc) return rc;
+            attach_fan_transposes(p, c.b);
+            wsb_pair = std::max(wsb_pair, c.b.bytes);
+        }
     }
     // reference outputs
     size_t out_elems = 0;
@@ -303,15 +312,23 @@ int autotune(oceansim_plan *p, hipStream_t st) {
         if (f.polar) out_elems += (size_t)f.n_range * f.n_azimuth;
         if (f.fan) out_elems += (size_t)f.fan_h * f.fan_w;
     }
-    char *tmp = nullptr;
+    char *tmp = nullptr, *tmp_b = nullptr;
     float *ref = nullptr;
     unsigned *bad = nullptr;
     hipError_t e = hipMalloc(&tmp, ws + 256);
     if (e != hipSuccess) return hip_fail(e, "autotune workspace");
+    if (with_bwd) {
+        e = hipMalloc(&tmp_b, wsb_pair + 256);
+        if (e != hipSuccess) {
+            (void)hipFree(tmp);
+            return hip_fail(e, "autotune workspace");
+        }
+    }
     e = hipMalloc(&ref, std::max<size_t>(out_elems, 1) * sizeof(float) + 256);
     if (e == hipSuccess) e = hipMalloc(&bad, sizeof(unsigned));
     if (e != hipSuccess) {
         (void)hipFree(tmp);
+        if (tmp_b) (void)hipFree(tmp_b);
         if (ref) (void)hipFree(ref);
         return hip_fail(e, "autotune buffers");
     }
@@ -343,8 +360,24 @@ int autotune(oceansim_plan *p, hipStream_t st) {
         carve_sonar(c.f, tmp, false);
         e = upload_table(c.f.dev, tmp, c.f.off_table, st);
         const SonarDev *table = reinterpret_cast<const SonarDev *>(tmp + c.f.off_table);
-        auto run = [&]() { return sonar_forward_table(table, n, c.f.grid, p->sp, p->refl, p->n_mat, st); };
-        if (e == hipSuccess) e = run();
+        const SonarDev *table_b = nullptr;
+        if (with_bwd && e == hipSuccess) {
+            carve_sonar(c.b, tmp_b, true);
+            link_pairs(c.b, c.f);
+            e = upload_table(c.b.dev, tmp_b, c.b.off_table, st);
+            table_b = reinterpret_cast<const SonarDev *>(tmp_b + c.b.off_table);
+        }
+        auto fwd = [&]() { return sonar_forward_table(table, n, c.f.grid, p->sp, p->refl, p->n_mat, st); };
+        auto run = [&]() {
+            hipError_t r = fwd();
+            if (r == hipSuccess && table_b)
+                r = sonar_backward_table(table_b, n, c.b.grid, p->sp, p->n_srows, p->refl, p->n_mat,
+                                         reinterpret_cast<double *>(tmp_b + c.b.off_part),
+                                         reinterpret_cast<double *>(tmp_b + c.b.off_refl_part), p->g_sp,
+                                         p->g_refl, st);
+            return r;
+        };
+        if (e == hipSuccess) e = fwd();
         if (e == hipSuccess && k == 0) e = copy_outputs(true);
         unsigned nbad = 0;
         if (e == hipSuccess && k > 0) {
@@ -443,6 +476,7 @@ int autotune(oceansim_plan *p, hipStream_t st) {
     }
     (void)hipStreamSynchronize(st);
     (void)hipFree(tmp);
+    if (tmp_b) (void)hipFree(tmp_b);
     (void)hipFree(ref);
     (void)hipFree(bad);
     if (rc) return rc;

@@ -21,9 +21,10 @@ def test_more_than_one_gpu_is_refused():
 
 @pytest.mark.gpu
 def test_json_line_keys():
-    print("[case] bench.py --steps 3 --warmup 1 --no-batched --no-cpu", flush=True)
+    print("[case] bench.py --steps 3 --warmup 1 --no-batched --no-cpu --c5-frames 4", flush=True)
     r = subprocess.run([sys.executable, "-u", os.path.join(ROOT, "bench.py"), "--steps", "3", "--warmup", "1",
-                        "--no-batched", "--no-cpu"], capture_output=True, text=True, timeout=300)
+                        "--no-batched", "--no-cpu", "--c5-frames", "4"], capture_output=True, text=True,
+                       timeout=300)
     assert r.returncode == 0, r.stderr[-2000:]
     lines = [l for l in r.stdout.splitlines() if l.startswith("{")]
     assert len(lines) == 1
@@ -34,7 +35,8 @@ def test_json_line_keys():
     assert d["n_gpus"] == 1 and d["steps"] == 3 and d["warmup"] == 1
     assert d["unit"] == "returns/s" and d["value"] > 0 and d["higher_is_better"] is True
     assert d["dtype"] == "f32" and d["data"] == "synthetic" and "workload" in d["config"]
-    assert abs(d["value"] * d["ms_per_step"] * 1e-3 - 131072) < 1e-6 * 131072
+    n_ret = 4 * 2048 * 1024
+    assert abs(d["value"] * d["ms_per_step"] * 1e-3 - n_ret) < 1e-6 * n_ret
     rf = d["roofline"]
     for k in ("bound", "achieved", "peak", "unit", "frac", "traffic"):
         assert k in rf, k
