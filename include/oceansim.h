@@ -193,6 +193,23 @@ int oceansim_sonar_render(const oceansim_sonar_frame *frames, int32_t n_frames,
                           const float *refl_dev, int32_t n_materials,
                           void *workspace, size_t workspace_bytes, void *stream);
 
+/* oceansim_sonar_render without allocation and without a workspace argument,
+ * for callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc).  The
+ * scratch memory the kernels need (the binning pass's pairs and per-chunk
+ * offsets, the frame table of a batch, column tables and an internal polar
+ * image where a frame asks for the fan only) is a static device array of
+ * 64 MiB per GPU, held until the process ends; frames that need more (about
+ * 7 M returns in all) are rejected with OCEANSIM_E_UNSUPPORTED before
+ * anything is enqueued.  Nothing in the scratch has to start at zero.  The
+ * array is shared by every call on a GPU: calls that overlap in time on one
+ * GPU (on different streams, or from different threads) race and must be
+ * ordered by the caller.  Otherwise identical to oceansim_sonar_render,
+ * outputs included. */
+int oceansim_sonar_render_noalloc(const oceansim_sonar_frame *frames, int32_t n_frames,
+                                  const oceansim_sonar_params *params_dev, int32_t n_param_rows,
+                                  const float *refl_dev, int32_t n_materials, void *stream);
+
 /* Gradient of L = sum_f <grad_polar_f, polar_f> + <grad_fan_f, fan_f> with
  * respect to the reflectivity table (grad_refl_dev [n_materials]) and every
  * parameter row (grad_params_dev [n_param_rows][OCEANSIM_SONAR_GRAD_WIDTH],

@@ -86,6 +86,7 @@ def _load() -> C.CDLL:
     sig = {
         "oceansim_sonar_workspace_size": [SF, C.c_int32, C.c_int32, C.c_int32, C.POINTER(C.c_size_t)],
         "oceansim_sonar_render": [SF, C.c_int32, _P, C.c_int32, _P, C.c_int32, _P, C.c_size_t, _P],
+        "oceansim_sonar_render_noalloc": [SF, C.c_int32, _P, C.c_int32, _P, C.c_int32, _P],
         "oceansim_sonar_render_backward": [SF, C.c_int32, _P, C.c_int32, _P, C.c_int32, _P, _P, _P,
                                            C.c_size_t, _P],
         "oceansim_uw_workspace_size": [UF, C.c_int32, C.c_int32, C.POINTER(C.c_size_t)],
@@ -121,7 +122,8 @@ def _load() -> C.CDLL:
 lib = _load()
 
 EXPORTED = ("oceansim_last_error", "oceansim_abi_version", "oceansim_sonar_workspace_size",
-            "oceansim_sonar_render", "oceansim_sonar_render_backward", "oceansim_uw_workspace_size",
+            "oceansim_sonar_render", "oceansim_sonar_render_noalloc", "oceansim_sonar_render_backward",
+            "oceansim_uw_workspace_size",
             "oceansim_uw_form", "oceansim_uw_form_backward", "oceansim_fan_stencil_size",
             "oceansim_trace_enable", "oceansim_trace_summary", "oceansim_plan_create",
             "oceansim_plan_forward", "oceansim_plan_backward", "oceansim_plan_shape",
@@ -166,6 +168,13 @@ def oceansim_sonar_render(frames, params_dev: int, n_param_rows: int, refl_dev: 
     ptr, n, _keep = _frames(frames, SonarFrame)
     check(lib.oceansim_sonar_render(ptr, n, params_dev, n_param_rows, refl_dev, n_materials, workspace,
                                     workspace_bytes, stream), "oceansim_sonar_render")
+
+
+def oceansim_sonar_render_noalloc(frames, params_dev: int, n_param_rows: int, refl_dev: int, n_materials: int,
+                                  stream: int) -> None:
+    ptr, n, _keep = _frames(frames, SonarFrame)
+    check(lib.oceansim_sonar_render_noalloc(ptr, n, params_dev, n_param_rows, refl_dev, n_materials, stream),
+          "oceansim_sonar_render_noalloc")
 
 
 def oceansim_sonar_render_backward(frames, params_dev: int, n_param_rows: int, refl_dev: int,

@@ -539,16 +539,14 @@ int oceansim_sonar_workspace_size(const oceansim_sonar_frame *frames, int32_t n_
     return ok();
 }
 
-int oceansim_sonar_render(const oceansim_sonar_frame *frames, int32_t n_frames,
-                          const oceansim_sonar_params *params_dev, int32_t n_param_rows, const float *refl_dev,
-                          int32_t n_materials, void *workspace, size_t workspace_bytes, void *stream) {
-    if (!params_dev) return fail(OCEANSIM_E_INVALID_ARG, "params_dev is NULL");
-    if (!refl_dev) return fail(OCEANSIM_E_INVALID_ARG, "refl_dev is NULL");
-    SonarPlan P;
-    int rc = plan_sonar(frames, n_frames, n_param_rows, n_materials, false, P, nullptr);
-    if (rc) return rc;
-    if (n_frames == 0) return ok();
-    rc = check_ws(workspace, workspace_bytes, P.bytes);
+}  // extern "C"
+
+namespace {
+
+// The sonar forward of planned frames into a checked workspace.
+int render_planned(SonarPlan &P, int32_t n_frames, const oceansim_sonar_params *params_dev, const float *refl_dev,
+                   int32_t n_materials, void *workspace, size_t workspace_bytes, void *stream) {
+    int rc = check_ws(workspace, workspace_bytes, P.bytes);
     if (rc) return rc;
     char *ws = static_cast<char *>(workspace);
     carve_sonar(P, ws, false);
@@ -564,6 +562,70 @@ int oceansim_sonar_render(const oceansim_sonar_frame *frames, int32_t n_frames,
     }
     if (e != hipSuccess) return hip_fail(e, "sonar forward launch");
     return ok();
+}
+
+// Scratch memory of the allocation-free sonar forward: a file-scope device
+// array (one copy per GPU, held until the process ends).  Host code reaches
+// it only through the address hipGetSymbolAddress returns for the current
+// device, kept per device.
+constexpr size_t kNoAllocScratchBytes = (size_t)64 << 20;
+constexpr int kMaxScratchDevices = 64;
+__device__ __align__(256) char scratch[kNoAllocScratchBytes];
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxScratchDevices] = {};
+
+int scratch_of_current_device(void **out) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+    if (dev < 0 || dev >= kMaxScratchDevices)
+        return fail(OCEANSIM_E_UNSUPPORTED, "device %d: the allocation-free entry point serves devices 0..%d", dev,
+                    kMaxScratchDevices - 1);
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return hip_fail(e, "scratch address");
+        if (!p) return fail(OCEANSIM_E_HIP, "scratch address is NULL");
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
+    return OCEANSIM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int oceansim_sonar_render(const oceansim_sonar_frame *frames, int32_t n_frames,
+                          const oceansim_sonar_params *params_dev, int32_t n_param_rows, const float *refl_dev,
+                          int32_t n_materials, void *workspace, size_t workspace_bytes, void *stream) {
+    if (!params_dev) return fail(OCEANSIM_E_INVALID_ARG, "params_dev is NULL");
+    if (!refl_dev) return fail(OCEANSIM_E_INVALID_ARG, "refl_dev is NULL");
+    SonarPlan P;
+    int rc = plan_sonar(frames, n_frames, n_param_rows, n_materials, false, P, nullptr);
+    if (rc) return rc;
+    if (n_frames == 0) return ok();
+    return render_planned(P, n_frames, params_dev, refl_dev, n_materials, workspace, workspace_bytes, stream);
+}
+
+int oceansim_sonar_render_noalloc(const oceansim_sonar_frame *frames, int32_t n_frames,
+                                  const oceansim_sonar_params *params_dev, int32_t n_param_rows,
+                                  const float *refl_dev, int32_t n_materials, void *stream) {
+    if (!params_dev) return fail(OCEANSIM_E_INVALID_ARG, "params_dev is NULL");
+    if (!refl_dev) return fail(OCEANSIM_E_INVALID_ARG, "refl_dev is NULL");
+    SonarPlan P;
+    int rc = plan_sonar(frames, n_frames, n_param_rows, n_materials, false, P, nullptr);
+    if (rc) return rc;
+    if (n_frames == 0) return ok();
+    if (P.bytes > kNoAllocScratchBytes)
+        return fail(OCEANSIM_E_UNSUPPORTED,
+                    "these frames need %zu bytes of scratch; the allocation-free entry point has %zu (use "
+                    "oceansim_sonar_render with a workspace)", P.bytes, kNoAllocScratchBytes);
+    void *ws = nullptr;
+    rc = scratch_of_current_device(&ws);
+    if (rc) return rc;
+    return render_planned(P, n_frames, params_dev, refl_dev, n_materials, ws, kNoAllocScratchBytes, stream);
 }
 
 int oceansim_sonar_render_backward(const oceansim_sonar_frame *frames, int32_t n_frames,
