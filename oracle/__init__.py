@@ -6,8 +6,9 @@ arithmetic lives in ``oceansim_oracle.c`` (plain C, double precision, OpenMP);
 this module only marshals numpy arrays to it with ctypes.  It imports nothing
 from the GPU package.
 
-Paper: arXiv 2503.01074, Sec. III-A.1 Eq. (1) (camera) and Sec. III-A.2
-Eq. (2)-(6) (sonar).
+Paper: arXiv 2503.01074, Sec. III-A.1 Eq. (1) (camera), Sec. III-A.2
+Eq. (2)-(6) (sonar) and the barometer and DVL of Sec. III-A (no equations
+printed: the readings are stated with each function).
 """
 from __future__ import annotations
 
@@ -87,6 +88,14 @@ def _declare(lib):
     lib.orc_uw_backward.restype = None
     lib.orc_num_threads.argtypes = []
     lib.orc_num_threads.restype = C.c_int
+    lib.orc_barometer.argtypes = [C.c_int64, _P, C.c_double, C.c_double, C.c_double, C.c_double, C.c_uint32,
+                                  C.c_uint32, _P]
+    lib.orc_barometer.restype = None
+    lib.orc_dvl_beam.argtypes = [C.c_int, C.c_double, _P]
+    lib.orc_dvl_beam.restype = None
+    lib.orc_dvl.argtypes = [C.c_int32, C.c_int32, _P, _P, _P, C.c_double, C.c_double, C.c_double, C.c_int32,
+                            C.c_double, C.c_double, C.c_double, C.c_double, C.c_uint32, C.c_uint32, _P, _P]
+    lib.orc_dvl.restype = None
 
 
 def _ptr(a):
@@ -282,3 +291,68 @@ def uw_backward(J, depth, beta_d, beta_b, b_inf, g_out, want_image_grads: bool =
     if with_abs:
         return g_par, g_J, g_d, a_par
     return g_par, g_J, g_d
+
+
+# --------------------------------------------------------------------------- #
+# Navigation sensors (Sec. III-A): barometer and DVL                          #
+# --------------------------------------------------------------------------- #
+@dataclass
+class BaroConfig:
+    """Barometer: pressure = p_atm + rho g max(depth, 0) + sigma N(0, 1)."""
+    p_atm: float = 101325.0
+    rho: float = 1025.0
+    g: float = 9.80665
+    sigma: float = 0.0
+    seed_lo: int = 0
+    seed_hi: int = 0
+
+
+def barometer(depth, cfg: BaroConfig):
+    """Pressures [Pa] of the depths [m] (any shape, flattened in C order for
+    the noise counters)."""
+    d = _f32(depth)
+    out = np.empty(d.shape, np.float64)
+    _load().orc_barometer(d.size, _ptr(d), cfg.p_atm, cfg.rho, cfg.g, cfg.sigma, cfg.seed_lo, cfg.seed_hi,
+                          _ptr(out))
+    return out
+
+
+@dataclass
+class DvlConfig:
+    """Four-beam convex Janus DVL with a range-dependent rate and dropout."""
+    janus: float = 30.0 * np.pi / 180.0
+    range_min: float = 0.5
+    range_max: float = 80.0
+    min_beams: int = 3
+    sigma_v: float = 0.0
+    sound_speed: float = 1500.0
+    pings_per_output: float = 8.0
+    period_min: float = 0.125
+    seed_lo: int = 0
+    seed_hi: int = 0
+
+
+def dvl_beams(janus: float):
+    """The four unit beam directions [4, 3] (sensor frame)."""
+    out = np.empty((4, 3), np.float64)
+    b = np.empty(3, np.float64)
+    for i in range(4):
+        _load().orc_dvl_beam(i, janus, _ptr(b))
+        out[i] = b
+    return out
+
+
+def dvl(t, ranges, vel, cfg: DvlConfig):
+    """t [T] seconds, ranges [T, N, 4], vel [T, N, 3] -> (velocity [T, N, 3]
+    float64 with NaN where there is none, status [T, N] int32: 0 none, 1
+    velocity, 2 dropout)."""
+    t = np.ascontiguousarray(t, np.float64)
+    r = _f32(ranges)
+    v = _f32(vel)
+    T, N = r.shape[0], r.shape[1]
+    out = np.empty((T, N, 3), np.float64)
+    st = np.empty((T, N), np.int32)
+    _load().orc_dvl(T, N, _ptr(t), _ptr(r), _ptr(v), cfg.janus, cfg.range_min, cfg.range_max, cfg.min_beams,
+                    cfg.sigma_v, cfg.sound_speed, cfg.pings_per_output, cfg.period_min, cfg.seed_lo, cfg.seed_hi,
+                    _ptr(out), _ptr(st))
+    return out, st

@@ -33,6 +33,11 @@
  *   orc_fan_adjoint     pinned (adjoint identity against orc_fan_forward)
  *   orc_uw_forward      pinned (Eq. 1 special cases)
  *   orc_uw_backward     pinned (FP64 central differences)
+ *   orc_barometer       pinned (hydrostatic closed forms, noise law)
+ *   orc_dvl             pinned (Janus geometry, exact recovery without
+ *                       noise, least squares against a library solver,
+ *                       dropout counts, the measurement schedule in closed
+ *                       form for constant ranges)
  */
 #include <math.h>
 #include <stdint.h>
@@ -692,6 +697,151 @@ void orc_uw_backward(int64_t npix, const float *J, const float *depth, const dou
             g_par_abs[ch] += a_bd;
             g_par_abs[3 + ch] += a_bb;
             g_par_abs[6 + ch] += a_binf;
+        }
+    }
+}
+
+/* ------------------------------------------------------------------------- */
+/* Navigation sensors of Sec. III-A (no equations are printed; the readings  */
+/* are stated here and in the design notes).                                 */
+/* ------------------------------------------------------------------------- */
+
+/* A standard normal from two counter words: Box-Muller, cosine branch. */
+static double orc_gauss(uint32_t w0, uint32_t w1)
+{
+    return sqrt(-2.0 * log(orc_uniform(w0))) * cos(2.0 * ORC_PI * orc_uniform(w1));
+}
+
+/* Barometer: the pressure at depth d below the free surface is the
+ * atmospheric pressure plus the weight of the water column,
+ *   P = p_atm + rho g max(d, 0) + sigma z,
+ * with optional Gaussian noise z ~ N(0, 1) (sigma = 0: none).  Sample k
+ * draws z from Philox4x32-10 counter (k mod 2^32, k / 2^32, 3, 0), words 0
+ * and 1, under key (seed_lo, seed_hi). */
+void orc_barometer(int64_t n, const float *depth, double p_atm, double rho, double g, double sigma,
+                   uint32_t seed_lo, uint32_t seed_hi, double *pressure)
+{
+    const uint32_t key[2] = {seed_lo, seed_hi};
+    for (int64_t k = 0; k < n; ++k) {
+        double d = depth[k];
+        double col = d > 0.0 ? rho * g * d : 0.0;
+        double z = 0.0;
+        if (sigma != 0.0) {
+            uint32_t ctr[4] = {(uint32_t)k, (uint32_t)((uint64_t)k >> 32), 3u, 0u}, w[4];
+            orc_philox4x32_10(ctr, key, w);
+            z = orc_gauss(w[0], w[1]);
+        }
+        pressure[k] = p_atm + col + sigma * z;
+    }
+}
+
+/* Beam i of a four-beam convex Janus array, in the sensor frame (x forward,
+ * y left, z up): tilted by `janus` from the downward vertical, at azimuth
+ * 45 + 90 i degrees. */
+void orc_dvl_beam(int i, double janus, double b[3])
+{
+    double psi = ORC_PI / 4.0 + (ORC_PI / 2.0) * (double)i;
+    b[0] = sin(janus) * cos(psi);
+    b[1] = sin(janus) * sin(psi);
+    b[2] = -cos(janus);
+}
+
+/* DVL over n_ticks ticks (times t[k], seconds, increasing) for n_inst
+ * independent instances.  Inputs per (tick k, instance n): the slant ranges
+ * of the four beams to the bottom, ranges[(k n_inst + n) 4 + i] (metres; not
+ * finite or outside [range_min, range_max]: no return on that beam), and the
+ * true velocity vel[(k n_inst + n) 3 + c] (sensor frame, m/s).
+ *
+ *  - Adaptive rate: the DVL measures when the time since its last
+ *    measurement reaches the ping period of the current altitude,
+ *      T = max(period_min, pings_per_output * 2 r_ref / sound_speed),
+ *    r_ref the largest valid beam range (range_max when no beam is valid),
+ *    i.e. the two-way travel time of the farthest beam times the pings
+ *    averaged into one output; the first tick always measures.
+ *  - Measurement: each valid beam reports the along-beam velocity
+ *    u_i = b_i . v + sigma_v z_i, z_i ~ N(0, 1) from Philox4x32-10 counter
+ *    (k, n, 4, i / 2), words 2 (i mod 2) and 2 (i mod 2) + 1 (Box-Muller,
+ *    cosine branch), key (seed_lo, seed_hi); the velocity is the least-
+ *    squares solution of b_i . x = u_i over the valid beams.
+ *  - Dropout: with fewer than min_beams valid beams the measurement is
+ *    invalid.
+ * Output status[k n_inst + n]: 0 no measurement at this tick, 1 a velocity,
+ * 2 dropout; vout[(k n_inst + n) 3 + c] the velocity (status 1) or NaN. */
+void orc_dvl(int32_t n_ticks, int32_t n_inst, const double *t, const float *ranges, const float *vel,
+             double janus, double range_min, double range_max, int32_t min_beams, double sigma_v,
+             double sound_speed, double pings_per_output, double period_min, uint32_t seed_lo,
+             uint32_t seed_hi, double *vout, int32_t *status)
+{
+    const uint32_t key[2] = {seed_lo, seed_hi};
+    double beams[4][3];
+    for (int i = 0; i < 4; ++i) orc_dvl_beam(i, janus, beams[i]);
+#pragma omp parallel for schedule(static)
+    for (int32_t n = 0; n < n_inst; ++n) {
+        double t_last = 0.0;
+        int have_last = 0;
+        for (int32_t k = 0; k < n_ticks; ++k) {
+            const int64_t row = (int64_t)k * n_inst + n;
+            const float *r = ranges + 4 * row;
+            int valid[4], nv = 0;
+            double r_ref = 0.0;
+            for (int i = 0; i < 4; ++i) {
+                double ri = r[i];
+                valid[i] = isfinite(ri) && ri >= range_min && ri <= range_max;
+                if (valid[i]) {
+                    ++nv;
+                    if (ri > r_ref) r_ref = ri;
+                }
+            }
+            if (nv == 0) r_ref = range_max;
+            double period = pings_per_output * 2.0 * r_ref / sound_speed;
+            if (period < period_min) period = period_min;
+            int due = !have_last || (t[k] - t_last >= period);
+            double *vo = vout + 3 * row;
+            vo[0] = vo[1] = vo[2] = NAN;
+            if (!due) {
+                status[row] = 0;
+                continue;
+            }
+            have_last = 1;
+            t_last = t[k];
+            if (nv < min_beams) {
+                status[row] = 2;
+                continue;
+            }
+            /* normal equations (B^T B) x = B^T u over the valid beams */
+            double A[3][3] = {{0}}, rhs[3] = {0};
+            const float *v = vel + 3 * row;
+            for (int i = 0; i < 4; ++i) {
+                if (!valid[i]) continue;
+                double z = 0.0;
+                if (sigma_v != 0.0) {
+                    uint32_t ctr[4] = {(uint32_t)k, (uint32_t)n, 4u, (uint32_t)(i / 2)}, w[4];
+                    orc_philox4x32_10(ctr, key, w);
+                    z = orc_gauss(w[2 * (i % 2)], w[2 * (i % 2) + 1]);
+                }
+                double u = beams[i][0] * v[0] + beams[i][1] * v[1] + beams[i][2] * v[2] + sigma_v * z;
+                for (int a = 0; a < 3; ++a) {
+                    rhs[a] += beams[i][a] * u;
+                    for (int c = 0; c < 3; ++c) A[a][c] += beams[i][a] * beams[i][c];
+                }
+            }
+            /* Cramer's rule on the symmetric 3 x 3 system */
+            double det = A[0][0] * (A[1][1] * A[2][2] - A[1][2] * A[2][1]) -
+                         A[0][1] * (A[1][0] * A[2][2] - A[1][2] * A[2][0]) +
+                         A[0][2] * (A[1][0] * A[2][1] - A[1][1] * A[2][0]);
+            double x[3];
+            for (int c = 0; c < 3; ++c) {
+                double M[3][3];
+                for (int a = 0; a < 3; ++a)
+                    for (int b = 0; b < 3; ++b) M[a][b] = b == c ? rhs[a] : A[a][b];
+                x[c] = (M[0][0] * (M[1][1] * M[2][2] - M[1][2] * M[2][1]) -
+                        M[0][1] * (M[1][0] * M[2][2] - M[1][2] * M[2][0]) +
+                        M[0][2] * (M[1][0] * M[2][1] - M[1][1] * M[2][0])) / det;
+            }
+            vo[0] = x[0];
+            vo[1] = x[1];
+            vo[2] = x[2];
+            status[row] = 1;
         }
     }
 }
