@@ -652,6 +652,29 @@ def calibration_run(torch, dev, n_frames, n_steps):
     return res
 
 
+def nav_leg(torch, dev, steps):
+    """The navigation sensors: the DVL over 512 ticks for 65536 instances
+    (vehicles or Monte Carlo runs) with ranges drawn over [0, 100] m, and the
+    barometer over 16 M depth samples, with noise."""
+    import paper_2503_01074_amd as osm
+    g = torch.Generator(device="cpu").manual_seed(11)
+    T, N = 512, 65536
+    t = torch.cumsum(torch.full((T,), 0.01, dtype=torch.float64), 0).to(dev)
+    ranges = (torch.rand(T, N, 4, generator=g) * 100.0).to(dev)
+    vel = torch.randn(T, N, 3, generator=g).to(dev)
+    depth = (torch.rand(1 << 24, generator=g) * 500.0).to(dev)
+    reps = max(5, steps // 2)
+    t_dvl = event_time(torch, lambda: osm.dvl(t, ranges, vel, sigma_v=0.01, seed=(1, 2)), reps)
+    t_baro = event_time(torch, lambda: osm.barometer(depth, sigma=20.0, seed=(3, 4)), reps)
+    log("navigation sensors: DVL %d ticks x %d instances %.1f us (%.2f G updates/s); barometer %d samples "
+        "%.1f us" % (T, N, t_dvl * 1e6, T * N / t_dvl / 1e9, depth.numel(), t_baro * 1e6))
+    return {"dvl_ticks": T, "dvl_instances": N, "dvl_us": t_dvl * 1e6, "dvl_updates_per_s": T * N / t_dvl,
+            "dvl_GBps": round(T * N * (16 + 12 + 12 + 4) / t_dvl / 1e9, 1),
+            "barometer_samples": depth.numel(), "barometer_us": t_baro * 1e6,
+            "barometer_samples_per_s": depth.numel() / t_baro,
+            "barometer_GBps": round(depth.numel() * 8 / t_baro / 1e9, 1)}
+
+
 def cpu_model():
     try:
         with open("/proc/cpuinfo") as fh:
@@ -837,6 +860,7 @@ def main():
         extra["batched_c4"] = c4_leg(torch, dev, args.steps)
         torch.cuda.empty_cache()
         extra["camera_io"] = camera_io_leg(torch, dev, args.steps)
+        extra["navigation"] = nav_leg(torch, dev, args.steps)
     cpu = None
     if not args.no_cpu:
         log("timing the FP64 oracle on the host")

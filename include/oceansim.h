@@ -46,7 +46,7 @@
 extern "C" {
 #endif
 
-#define OCEANSIM_ABI_VERSION 3
+#define OCEANSIM_ABI_VERSION 4
 
 typedef enum {
     OCEANSIM_OK = 0,
@@ -324,6 +324,66 @@ typedef struct {
 } oceansim_cam_out_frame;
 
 int oceansim_cam_encode(const oceansim_cam_out_frame *frames, int32_t n_frames, void *stream);
+
+/* ======================================================================== */
+/* Navigation sensors (Sec. III-A): barometer and DVL                       */
+/*                                                                          */
+/* The paper describes both without equations; these are the readings.      */
+/* Random numbers come from Philox4x32-10 as for the sonar speckle, normals */
+/* by Box-Muller (cosine branch) from two words.                            */
+/* ======================================================================== */
+
+/* Barometer: the pressure at depth d (metres below the free surface) is the
+ * atmospheric pressure plus the weight of the water column, with optional
+ * Gaussian noise:  P = p_atm + rho g max(d, 0) + sigma z,  z ~ N(0, 1) from
+ * counter (k mod 2^32, k / 2^32, 3, 0), words 0 and 1, for sample k. */
+typedef struct {
+    double p_atm;        /* Pa, user-defined atmospheric pressure          */
+    double rho;          /* kg / m^3, user-defined water density (>= 0)    */
+    double g;            /* m / s^2 (>= 0)                                  */
+    double sigma;        /* Pa, noise standard deviation (0: none)          */
+    uint32_t seed_lo, seed_hi;
+} oceansim_baro_params;
+
+/* pressure_dev[k] (float32, Pa) for depth_dev[k] (float32, m), k < n;
+ * device buffers, 4-byte aligned; params is host memory.  Asynchronous. */
+int oceansim_barometer(const float *depth_dev, int64_t n, const oceansim_baro_params *params,
+                       float *pressure_dev, void *stream);
+
+/* DVL: a four-beam convex Janus array in the sensor frame (x forward, y
+ * left, z up); beam i is tilted by janus_angle from the downward vertical at
+ * azimuth 45 + 90 i degrees.  Per instance (a vehicle or a Monte Carlo run)
+ * and tick k (times t[k], seconds, increasing, shared by the instances):
+ *  - beam i is valid when its slant range to the bottom is finite and in
+ *    [range_min, range_max];
+ *  - adaptive rate: a measurement is due when t[k] minus the time of the
+ *    instance's last measurement reaches the ping period of the current
+ *    altitude, max(period_min, pings_per_output * 2 r_ref / sound_speed),
+ *    r_ref the largest valid range (range_max without a valid beam),
+ *    evaluated in double precision in that order; the first tick measures;
+ *  - a due measurement with at least min_beams valid beams is the least-
+ *    squares velocity from the valid beams' along-beam velocities
+ *    b_i . v + sigma_v z_i, z_i ~ N(0, 1) from counter (k, n, 4, i / 2),
+ *    words 2 (i mod 2), 2 (i mod 2) + 1 (status 1); with fewer it is a
+ *    dropout (status 2, velocity NaN); no measurement: status 0, NaN.
+ * Layouts (device, tick-major): t [n_ticks] double (8-byte aligned); ranges
+ * [n_ticks][n_inst][4] float (16-byte aligned); velocity and velocity_out
+ * [n_ticks][n_inst][3] float; status [n_ticks][n_inst] int32.  params is
+ * host memory (janus_angle in (0, pi/2), min_beams 3 or 4). */
+typedef struct {
+    double janus_angle;        /* rad                                       */
+    double range_min, range_max;   /* m, operational range of a beam       */
+    int32_t min_beams;         /* valid beams needed for a velocity: 3 or 4 */
+    double sigma_v;            /* m / s, along-beam velocity noise (0: none) */
+    double sound_speed;        /* m / s                                      */
+    double pings_per_output;   /* pings averaged into one output            */
+    double period_min;         /* s, shortest measurement period            */
+    uint32_t seed_lo, seed_hi;
+} oceansim_dvl_params;
+
+int oceansim_dvl(const double *t_dev, const float *ranges_dev, const float *velocity_dev, int32_t n_ticks,
+                 int32_t n_inst, const oceansim_dvl_params *params, float *velocity_out_dev, int32_t *status_dev,
+                 void *stream);
 
 /* ======================================================================== */
 /* Plans: a batch of sonar and camera frames prepared once and launched     */

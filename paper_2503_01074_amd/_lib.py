@@ -67,6 +67,18 @@ class CamOutFrame(C.Structure):
     _fields_ = [("I", _P), ("srgb_out", _P), ("H", C.c_int32), ("W", C.c_int32), ("channels_out", C.c_int32)]
 
 
+class BaroParams(C.Structure):
+    _fields_ = [("p_atm", C.c_double), ("rho", C.c_double), ("g", C.c_double), ("sigma", C.c_double),
+                ("seed_lo", C.c_uint32), ("seed_hi", C.c_uint32)]
+
+
+class DvlParams(C.Structure):
+    _fields_ = [("janus_angle", C.c_double), ("range_min", C.c_double), ("range_max", C.c_double),
+                ("min_beams", C.c_int32), ("sigma_v", C.c_double), ("sound_speed", C.c_double),
+                ("pings_per_output", C.c_double), ("period_min", C.c_double), ("seed_lo", C.c_uint32),
+                ("seed_hi", C.c_uint32)]
+
+
 class OceansimError(RuntimeError):
     def __init__(self, status: int, where: str, text: str):
         super().__init__("%s: %s (%s)" % (where, STATUS_NAMES.get(status, status), text))
@@ -95,6 +107,8 @@ def _load() -> C.CDLL:
         "oceansim_cam_condition": [C.POINTER(CamFrame), C.c_int32, _P],
         "oceansim_cam_condition_backward": [C.POINTER(CamFrame), C.c_int32, _P],
         "oceansim_cam_encode": [C.POINTER(CamOutFrame), C.c_int32, _P],
+        "oceansim_barometer": [_P, C.c_int64, C.POINTER(BaroParams), _P, _P],
+        "oceansim_dvl": [_P, _P, _P, C.c_int32, C.c_int32, C.POINTER(DvlParams), _P, _P, _P],
     }
     for name, args in sig.items():
         fn = getattr(lib, name)
@@ -128,7 +142,7 @@ EXPORTED = ("oceansim_last_error", "oceansim_abi_version", "oceansim_sonar_works
             "oceansim_trace_enable", "oceansim_trace_summary", "oceansim_plan_create",
             "oceansim_plan_forward", "oceansim_plan_backward", "oceansim_plan_shape",
             "oceansim_plan_destroy", "oceansim_cam_condition", "oceansim_cam_condition_backward",
-            "oceansim_cam_encode")
+            "oceansim_cam_encode", "oceansim_barometer", "oceansim_dvl")
 
 PLAN_BACKWARD, PLAN_GRAPH, PLAN_AUTOTUNE = 1, 2, 4
 
@@ -274,3 +288,13 @@ def oceansim_plan_shape(plan: int) -> tuple:
 
 def oceansim_plan_destroy(plan: int) -> None:
     check(lib.oceansim_plan_destroy(plan), "oceansim_plan_destroy")
+
+
+def oceansim_barometer(depth_dev: int, n: int, params: BaroParams, pressure_dev: int, stream: int) -> None:
+    check(lib.oceansim_barometer(depth_dev, n, C.byref(params), pressure_dev, stream), "oceansim_barometer")
+
+
+def oceansim_dvl(t_dev: int, ranges_dev: int, velocity_dev: int, n_ticks: int, n_inst: int, params: DvlParams,
+                 velocity_out_dev: int, status_dev: int, stream: int) -> None:
+    check(lib.oceansim_dvl(t_dev, ranges_dev, velocity_dev, n_ticks, n_inst, C.byref(params), velocity_out_dev,
+                           status_dev, stream), "oceansim_dvl")

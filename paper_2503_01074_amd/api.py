@@ -12,7 +12,8 @@ from typing import List, Optional, Sequence
 import torch
 
 from . import _lib
-from ._lib import (SONAR_GRAD_WIDTH, WATER_GRAD_WIDTH, CamFrame, CamOutFrame, SonarFrame, UwFrame)
+from ._lib import (SONAR_GRAD_WIDTH, WATER_GRAD_WIDTH, BaroParams, CamFrame, CamOutFrame, DvlParams, SonarFrame,
+                   UwFrame)
 
 SONAR_PARAM_WIDTH = 8     # alpha, gain, sigma_phi, sigma_sa, sigma_sm, 3 reserved
 WATER_PARAM_WIDTH = 12    # beta_d[3], beta_b[3], b_inf[3], 3 reserved
@@ -298,6 +299,37 @@ def cam_encode(images: Sequence[torch.Tensor], channels_out: int = 3) -> List[to
 # --------------------------------------------------------------------------- #
 # plans                                                                       #
 # --------------------------------------------------------------------------- #
+def barometer(depth: torch.Tensor, p_atm: float = 101325.0, rho: float = 1025.0, g: float = 9.80665,
+              sigma: float = 0.0, seed: Sequence[int] = (0, 0)) -> torch.Tensor:
+    """Pressures [Pa] (float32, same shape) of depths [m] below the free
+    surface (oceansim_barometer; samples numbered in C order)."""
+    d = depth.contiguous()
+    out = torch.empty_like(d)
+    prm = BaroParams(p_atm, rho, g, sigma, int(seed[0]), int(seed[1]))
+    _lib.oceansim_barometer(_ptr(d), d.numel(), prm, _ptr(out), _stream(d.device))
+    return out
+
+
+def dvl(t: torch.Tensor, ranges: torch.Tensor, velocity: torch.Tensor, janus_angle: float = 0.5235987755982988,
+        range_min: float = 0.5, range_max: float = 80.0, min_beams: int = 3, sigma_v: float = 0.0,
+        sound_speed: float = 1500.0, pings_per_output: float = 8.0, period_min: float = 0.125,
+        seed: Sequence[int] = (0, 0)):
+    """Janus DVL over ticks (oceansim_dvl): t [T] float64, ranges [T, N, 4],
+    velocity [T, N, 3] (device) -> (velocity_out [T, N, 3] with NaN where
+    there is no velocity, status [T, N] int32: 0 none, 1 velocity, 2
+    dropout)."""
+    t = t.contiguous()
+    r = ranges.contiguous()
+    v = velocity.contiguous()
+    T, N = int(r.shape[0]), int(r.shape[1])
+    vo = torch.empty_like(v)
+    st = torch.empty(T, N, dtype=torch.int32, device=v.device)
+    prm = DvlParams(janus_angle, range_min, range_max, min_beams, sigma_v, sound_speed, pings_per_output,
+                    period_min, int(seed[0]), int(seed[1]))
+    _lib.oceansim_dvl(_ptr(t), _ptr(r), _ptr(v), T, N, prm, _ptr(vo), _ptr(st), _stream(v.device))
+    return vo, st
+
+
 class Plan:
     """Sonar and camera frames prepared once and launched many times
     (oceansim_plan_*): frame tables are uploaded once and, with ``graph``,

@@ -19,7 +19,7 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "liboceansim.so")
-SOURCES = ["api.cpp", "plan.cpp", "sonar.hip", "uw.hip", "cam.hip"]
+SOURCES = ["api.cpp", "plan.cpp", "sonar.hip", "uw.hip", "cam.hip", "nav.hip"]
 HEADERS = ["device.hpp", "launch.hpp", "host.hpp", "uw_body.hpp", "reduce_body.hpp"]
 ARCH = os.environ.get("OCEANSIM_ARCH", "gfx950")
 

@@ -27,7 +27,7 @@ def test_exports_every_declared_function():
     for name in sorted(declared):
         assert hasattr(so, name), name
     assert set(lib.EXPORTED) == declared
-    assert lib.oceansim_abi_version() == 3
+    assert lib.oceansim_abi_version() == 4
 
 
 def test_struct_layout_matches_header():
@@ -39,6 +39,8 @@ def test_struct_layout_matches_header():
         "oceansim_uw_frame": lib.UwFrame,
         "oceansim_cam_frame": lib.CamFrame,
         "oceansim_cam_out_frame": lib.CamOutFrame,
+        "oceansim_baro_params": lib.BaroParams,
+        "oceansim_dvl_params": lib.DvlParams,
     }
     lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "oceansim.h"', "int main(void){"]
     for cname, py in structs.items():
@@ -293,3 +295,35 @@ def test_cam_encode_rejections():
         assert text in lib.last_error()
     assert so.oceansim_cam_encode(None, 0, None) == 0
     assert so.oceansim_cam_encode(None, -1, None) == -1
+
+
+@pytest.mark.parametrize("over, text", [({"rho": -1.0}, "rho"), ({"sigma": float("nan")}, "finite"),
+                                        ({"g": float("inf")}, "finite")])
+def test_barometer_rejects(over, text):
+    lib = _lib()
+    p = lib.BaroParams(101325.0, 1025.0, 9.80665, 0.0, 0, 0)
+    for k, v in over.items():
+        setattr(p, k, v)
+    with pytest.raises(lib.OceansimError) as ei:
+        lib.oceansim_barometer(FAKE, 10, p, FAKE, 0)
+    assert ei.value.status == -1 and text in str(ei.value)
+    with pytest.raises(lib.OceansimError) as ei:
+        lib.oceansim_barometer(FAKE, -1, lib.BaroParams(101325.0, 1025.0, 9.8, 0.0, 0, 0), FAKE, 0)
+    assert ei.value.status == -2
+
+
+@pytest.mark.parametrize("over, text", [({"janus_angle": 0.0}, "janus"), ({"janus_angle": 1.6}, "janus"),
+                                        ({"min_beams": 2}, "min_beams"), ({"range_max": 0.1}, "range"),
+                                        ({"sound_speed": 0.0}, "sound_speed"), ({"sigma_v": -0.1}, "sigma_v")])
+def test_dvl_rejects(over, text):
+    lib = _lib()
+    p = lib.DvlParams(0.5236, 0.5, 80.0, 3, 0.0, 1500.0, 8.0, 0.125, 0, 0)
+    for k, v in over.items():
+        setattr(p, k, v)
+    with pytest.raises(lib.OceansimError) as ei:
+        lib.oceansim_dvl(FAKE, FAKE, FAKE, 10, 10, p, FAKE, FAKE, 0)
+    assert ei.value.status == -1 and text in str(ei.value)
+    ok = lib.DvlParams(0.5236, 0.5, 80.0, 3, 0.0, 1500.0, 8.0, 0.125, 0, 0)
+    with pytest.raises(lib.OceansimError) as ei:   # ranges must be 16-byte aligned
+        lib.oceansim_dvl(FAKE, FAKE + 4, FAKE, 10, 10, ok, FAKE, FAKE, 0)
+    assert ei.value.status == -1
