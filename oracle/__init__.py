@@ -96,6 +96,9 @@ def _declare(lib):
     lib.orc_dvl.argtypes = [C.c_int32, C.c_int32, _P, _P, _P, C.c_double, C.c_double, C.c_double, C.c_int32,
                             C.c_double, C.c_double, C.c_double, C.c_double, C.c_uint32, C.c_uint32, _P, _P]
     lib.orc_dvl.restype = None
+    lib.orc_raycast.argtypes = [C.c_int64, _P, C.c_int64, _P, _P, _P, _P, C.c_int32, C.c_int32, C.c_double,
+                                C.c_double, C.c_double, C.c_double, C.c_int64, _P] + [_P] * 8
+    lib.orc_raycast.restype = None
 
 
 def _ptr(a):
@@ -356,3 +359,29 @@ def dvl(t, ranges, vel, cfg: DvlConfig):
                     cfg.sigma_v, cfg.sound_speed, cfg.pings_per_output, cfg.period_min, cfg.seed_lo, cfg.seed_hi,
                     _ptr(out), _ptr(st))
     return out, st
+
+
+# --------------------------------------------------------------------------- #
+# Ray casting of the sonar's returns against a triangle mesh                  #
+# --------------------------------------------------------------------------- #
+def raycast(vertices, triangles, tri_mat, pos, rot, n_beams, n_rays, fov_az, fov_el, t_max, band=1e-5, sel=None):
+    """Brute-force closest hits of the sonar ray pattern (see orc_raycast):
+    returns a dict with x, y, z, nx, ny, nz (float64, sensor frame), mat
+    (int32, -1 = miss) and ambiguous (bool), each [n_beams * n_rays], or only
+    for the return indices in ``sel``."""
+    vv = _f32(vertices).reshape(-1, 3)
+    tt = np.ascontiguousarray(triangles, np.int32).reshape(-1, 3)
+    mm = np.ascontiguousarray(tri_mat, np.int32).reshape(-1)
+    p = _f32(pos).reshape(3)
+    R = _f32(rot).reshape(3, 3)
+    sel_a = None if sel is None else np.ascontiguousarray(sel, np.int64)
+    n = int(n_beams) * int(n_rays) if sel_a is None else sel_a.shape[0]
+    out = {k: np.empty(n, np.float64) for k in ("x", "y", "z", "nx", "ny", "nz")}
+    out["mat"] = np.empty(n, np.int32)
+    amb = np.empty(n, np.uint8)
+    _load().orc_raycast(vv.shape[0], _ptr(vv), tt.shape[0], _ptr(tt), _ptr(mm), _ptr(p), _ptr(R), int(n_beams),
+                        int(n_rays), float(fov_az), float(fov_el), float(t_max), float(band),
+                        0 if sel_a is None else sel_a.shape[0], _ptr(sel_a),
+                        *[_ptr(out[k]) for k in ("x", "y", "z", "nx", "ny", "nz", "mat")], _ptr(amb))
+    out["ambiguous"] = amb.astype(bool)
+    return out

@@ -34,6 +34,8 @@
  *   orc_uw_forward      pinned (Eq. 1 special cases)
  *   orc_uw_backward     pinned (FP64 central differences)
  *   orc_barometer       pinned (hydrostatic closed forms, noise law)
+ *   orc_raycast         pinned (closed forms: planes, boxes, a sphere's
+ *                       tessellation; rays that miss; hit ordering)
  *   orc_dvl             pinned (Janus geometry, exact recovery without
  *                       noise, least squares against a library solver,
  *                       dropout counts, the measurement schedule in closed
@@ -843,6 +845,124 @@ void orc_dvl(int32_t n_ticks, int32_t n_inst, const double *t, const float *rang
             vo[2] = x[2];
             status[row] = 1;
         }
+    }
+}
+
+/* ------------------------------------------------------------------------- */
+/* Ray casting of the sonar's returns (Sec. III-A.2 obtains the returns from */
+/* the renderer's ray tracing): the rays of a beam x elevation pattern from  */
+/* a sensor pose against a triangle mesh, closest hit by brute force over    */
+/* every triangle, in double precision.                                      */
+/*                                                                           */
+/* Pattern: beam b (of n_beams) at azimuth -fov_az/2 + (b + 1/2) fov_az /    */
+/* n_beams, ray r (of n_rays) at elevation -fov_el/2 + (r + 1/2) fov_el /    */
+/* n_rays; direction (cos el cos az, cos el sin az, sin el) in the sensor    */
+/* frame (x forward, y left, z up); return k = b n_rays + r.  Pose: world =  */
+/* R sensor + p (R row-major).  A hit is the nearest point with 0 < t <=     */
+/* t_max on a triangle (edges included); its position is written in the     */
+/* sensor frame (t d), its normal is the triangle's (v1 - v0) x (v2 - v0),   */
+/* normalised and rotated into the sensor frame, and its material that of    */
+/* the triangle; a miss has material -1 and zero coordinates.                */
+/*                                                                           */
+/* Inside test: the signed volumes s_i = d . ((v_j - o) x (v_k - o)) over    */
+/* the edges (j, k) opposite each vertex i; the ray meets the triangle when  */
+/* all three share the sign of their sum (which is d . n), and s_i / sum are */
+/* the barycentric coordinates of the crossing point.  Unlike a solve in the */
+/* triangle's own plane this stays decisive on slivers.                      */
+/*                                                                           */
+/* ambiguous[k] flags rays whose nearest hit lies within `band` (barycentric */
+/* units) of a triangle edge, whose two nearest hits on different triangles */
+/* are closer than band * t, or whose nearest triangle is a sliver          */
+/* (|n| < band L^2, L its longest edge) or is met at grazing incidence       */
+/* (|d . n| < band |n|): there the nearest triangle, or its point and        */
+/* normal, is not decided by the geometry alone at single precision.         */
+/* ------------------------------------------------------------------------- */
+void orc_raycast(int64_t n_vert, const float *vert, int64_t n_tri, const int32_t *tri, const int32_t *tri_mat,
+                 const float *pos, const float *rot, int32_t n_beams, int32_t n_rays, double fov_az,
+                 double fov_el, double t_max, double band, int64_t n_sel, const int64_t *sel, double *x,
+                 double *y, double *z, double *nx, double *ny, double *nz, int32_t *mat, uint8_t *ambiguous)
+{
+    (void)n_vert;
+    /* the returns k = sel[s] (s < n_sel), or all of them (sel NULL); output s */
+    const int64_t n_out = sel ? n_sel : (int64_t)n_beams * n_rays;
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t s = 0; s < n_out; ++s) {
+        const int64_t kk = sel ? sel[s] : s;
+        const int64_t k = s;
+        const int32_t b = (int32_t)(kk / n_rays), r = (int32_t)(kk % n_rays);
+        const double az = -0.5 * fov_az + ((double)b + 0.5) * fov_az / n_beams;
+        const double el = -0.5 * fov_el + ((double)r + 0.5) * fov_el / n_rays;
+        const double ds[3] = {cos(el) * cos(az), cos(el) * sin(az), sin(el)};
+        double dw[3], o[3];
+        for (int i = 0; i < 3; ++i) {
+            dw[i] = rot[3 * i] * ds[0] + rot[3 * i + 1] * ds[1] + rot[3 * i + 2] * ds[2];
+            o[i] = pos[i];
+        }
+        double best = INFINITY, second = INFINITY;
+        int best_amb = 0;
+        int64_t best_tri = -1;
+        double best_n[3] = {0, 0, 0};
+        for (int64_t f = 0; f < n_tri; ++f) {
+            double v[3][3];   /* vertices relative to the ray origin */
+            for (int j = 0; j < 3; ++j) {
+                const float *V = vert + 3 * (int64_t)tri[3 * f + j];
+                for (int i = 0; i < 3; ++i) v[j][i] = (double)V[i] - o[i];
+            }
+            double sv[3];
+            for (int j = 0; j < 3; ++j) {
+                const double *P = v[(j + 1) % 3], *Q = v[(j + 2) % 3];
+                const double c0 = P[1] * Q[2] - P[2] * Q[1];
+                const double c1 = P[2] * Q[0] - P[0] * Q[2];
+                const double c2 = P[0] * Q[1] - P[1] * Q[0];
+                sv[j] = dw[0] * c0 + dw[1] * c1 + dw[2] * c2;
+            }
+            const double tot = sv[0] + sv[1] + sv[2];
+            if (tot == 0.0) continue;   /* degenerate, or the ray runs in the plane */
+            const double u0 = sv[0] / tot, u1 = sv[1] / tot, u2 = sv[2] / tot;
+            if (u0 < 0.0 || u1 < 0.0 || u2 < 0.0) continue;
+            double t = 0.0;
+            for (int i = 0; i < 3; ++i) t += (u0 * v[0][i] + u1 * v[1][i] + u2 * v[2][i]) * dw[i];
+            if (!(t > 0.0 && t <= t_max)) continue;
+            if (t < best) {
+                second = best;
+                best = t;
+                best_tri = f;
+                double e1[3], e2[3], e3[3], n[3];
+                for (int i = 0; i < 3; ++i) {
+                    e1[i] = v[1][i] - v[0][i];
+                    e2[i] = v[2][i] - v[0][i];
+                    e3[i] = v[2][i] - v[1][i];
+                }
+                n[0] = e1[1] * e2[2] - e1[2] * e2[1];
+                n[1] = e1[2] * e2[0] - e1[0] * e2[2];
+                n[2] = e1[0] * e2[1] - e1[1] * e2[0];
+                const double nl = sqrt(n[0] * n[0] + n[1] * n[1] + n[2] * n[2]);
+                const double l2 = fmax(e1[0] * e1[0] + e1[1] * e1[1] + e1[2] * e1[2],
+                                       fmax(e2[0] * e2[0] + e2[1] * e2[1] + e2[2] * e2[2],
+                                            e3[0] * e3[0] + e3[1] * e3[1] + e3[2] * e3[2]));
+                const double dn = n[0] * dw[0] + n[1] * dw[1] + n[2] * dw[2];
+                const double margin = fmin(u0, fmin(u1, u2));
+                best_amb = margin < band || nl < band * l2 || fabs(dn) < band * nl;
+                for (int i = 0; i < 3; ++i) best_n[i] = nl > 0.0 ? n[i] / nl : 0.0;
+            } else if (t < second) {
+                second = t;
+            }
+        }
+        if (best_tri < 0) {
+            x[k] = y[k] = z[k] = nx[k] = ny[k] = nz[k] = 0.0;
+            mat[k] = -1;
+            ambiguous[k] = 0;
+            continue;
+        }
+        x[k] = best * ds[0];
+        y[k] = best * ds[1];
+        z[k] = best * ds[2];
+        /* world normal into the sensor frame: R^T n */
+        nx[k] = rot[0] * best_n[0] + rot[3] * best_n[1] + rot[6] * best_n[2];
+        ny[k] = rot[1] * best_n[0] + rot[4] * best_n[1] + rot[7] * best_n[2];
+        nz[k] = rot[2] * best_n[0] + rot[5] * best_n[1] + rot[8] * best_n[2];
+        mat[k] = tri_mat[best_tri];
+        ambiguous[k] = (best_amb || second - best < band * best) ? 1 : 0;
     }
 }
 

@@ -333,3 +333,83 @@ def sonar_c5(seed: int = BASE_SEED + 4, n_frames: int = 64, beams: int = 2048, r
         h.refl = refl
         frames.append(SonarFrame(spec, h))
     return frames
+
+
+# --------------------------------------------------------------------------- #
+# Procedural scenes for the ray caster.  The paper's scenes (a towing tank, a  #
+# pier, a mall, a wreck) are not available; a seeded seabed heightfield with   #
+# box-shaped structures standing on it stands in for them.                     #
+# --------------------------------------------------------------------------- #
+@dataclass
+class Scene:
+    vertices: np.ndarray      # float32 [V, 3] world coordinates (metres, z up)
+    triangles: np.ndarray     # int32 [T, 3] vertex indices; (v1 - v0) x (v2 - v0) points out of the solid
+    tri_mat: np.ndarray       # int32 [T] material of each triangle
+    refl: np.ndarray          # float32 [M] reflectivity of each material
+
+
+@dataclass
+class SonarPose:
+    pos: np.ndarray           # float32 [3] sensor position (world)
+    rot: np.ndarray           # float32 [3, 3] world = rot @ sensor (x forward, y left, z up)
+
+
+def box_mesh(lo, hi, first_vertex=0):
+    """An axis-aligned box [lo, hi] as 12 outward-facing triangles."""
+    x0, y0, z0 = lo
+    x1, y1, z1 = hi
+    v = np.array([[x0, y0, z0], [x1, y0, z0], [x1, y1, z0], [x0, y1, z0],
+                  [x0, y0, z1], [x1, y0, z1], [x1, y1, z1], [x0, y1, z1]], np.float64)
+    quads = [(0, 3, 2, 1), (4, 5, 6, 7), (0, 1, 5, 4), (2, 3, 7, 6), (1, 2, 6, 5), (0, 4, 7, 3)]
+    tris = []
+    for a, b, c, d in quads:
+        tris += [(a, b, c), (a, c, d)]
+    return v, np.asarray(tris, np.int64) + first_vertex
+
+
+def seabed_scene(seed: int = BASE_SEED + 10, n: int = 256, extent: float = 200.0, depth: float = 20.0,
+                 n_materials: int = 64, n_boxes: int = 16) -> Scene:
+    """A seabed heightfield of n x n vertices over [-extent/2, extent/2]^2 at
+    mean depth `depth` with seeded relief (a few sinusoids, +-2.5 m), materials
+    in 8 x 8 patches, and `n_boxes` axis-aligned boxes (pillars, debris)
+    standing on it ahead of the origin."""
+    st = Stream(seed, 0)
+    xs = np.linspace(-0.5 * extent, 0.5 * extent, n)
+    X, Y = np.meshgrid(xs, xs, indexing="ij")
+    Z = np.full_like(X, -depth)
+    for _ in range(5):
+        kx, ky = st.uniform(-0.15, 0.15, 2)
+        ph = st.uniform(0.0, 2 * np.pi)
+        amp = st.uniform(0.2, 0.5)
+        Z += amp * np.sin(kx * X + ky * Y + ph)
+    verts = [np.stack([X.ravel(), Y.ravel(), Z.ravel()], 1)]
+    idx = np.arange(n * n).reshape(n, n)
+    v00, v10, v01, v11 = idx[:-1, :-1], idx[1:, :-1], idx[:-1, 1:], idx[1:, 1:]
+    # (v00, v10, v11) and (v00, v11, v01): normals point up (+z)
+    tris = [np.stack([v00, v10, v11], -1).reshape(-1, 3), np.stack([v00, v11, v01], -1).reshape(-1, 3)]
+    patch = (np.minimum(idx[:-1, :-1] // n * 8 // (n - 1), 7) * 8 +
+             np.minimum(idx[:-1, :-1] % n * 8 // (n - 1), 7)).reshape(-1) % n_materials
+    mats = [patch, patch]
+    nv = n * n
+    for b in range(n_boxes):
+        cx = st.uniform(8.0, 0.4 * extent)
+        cy = st.uniform(-0.3 * extent, 0.3 * extent)
+        hx, hy = st.uniform(0.5, 4.0, 2)
+        h = st.uniform(1.0, 10.0)
+        v, t = box_mesh((cx - hx, cy - hy, -depth - 3.0), (cx + hx, cy + hy, -depth + h), nv)
+        verts.append(v)
+        tris.append(t)
+        mats.append(np.full(12, int(st.integers(0, n_materials - 1)), np.int64))
+        nv += 8
+    refl = st.uniform(0.1, 1.0, n_materials).astype(np.float32)
+    return Scene(np.concatenate(verts).astype(np.float32), np.concatenate(tris).astype(np.int32),
+                 np.concatenate(mats).astype(np.int32), refl)
+
+
+def sonar_pose(height: float = 8.0, depth: float = 20.0, pitch_deg: float = 15.0, yaw_deg: float = 0.0) -> SonarPose:
+    """The sensor `height` metres above the mean seabed, looking along +x
+    (turned by `yaw_deg`), tilted down by `pitch_deg`."""
+    p, y = np.radians(pitch_deg), np.radians(yaw_deg)
+    pitch = np.array([[np.cos(p), 0.0, np.sin(p)], [0.0, 1.0, 0.0], [-np.sin(p), 0.0, np.cos(p)]])
+    yaw = np.array([[np.cos(y), -np.sin(y), 0.0], [np.sin(y), np.cos(y), 0.0], [0.0, 0.0, 1.0]])
+    return SonarPose(np.array([0.0, 0.0, -depth + height], np.float32), (yaw @ pitch).astype(np.float32))
