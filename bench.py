@@ -52,7 +52,7 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 64 MiB device-to-device copy (counter calibration)")
-    ap.add_argument("--only", choices=["c2", "c3", "c4", "c5"], default=None,
+    ap.add_argument("--only", choices=["c2", "c3", "c4", "c5", "raycast"], default=None,
                     help="only build and run one workload (for profiler runs); prints no JSON line")
     ap.add_argument("--c5-frames", type=int, default=64,
                     help="sonar and camera frames of the calibration-scale workload")
@@ -675,6 +675,86 @@ def nav_leg(torch, dev, steps):
             "barometer_GBps": round(depth.numel() * 8 / t_baro / 1e9, 1)}
 
 
+def kernel_us(torch, fn, reps):
+    """Per-kernel device time of fn (library event tracing): {name: (launches per call, us per call)}."""
+    from paper_2503_01074_amd import _lib
+    fn()
+    torch.cuda.synchronize()
+    _lib.oceansim_trace_enable(True)
+    for _ in range(reps):
+        fn()
+    torch.cuda.synchronize()
+    tr = _lib.oceansim_trace_summary()
+    _lib.oceansim_trace_enable(False)
+    return {k: (calls / reps, us / reps) for k, (calls, us) in tr.items()}
+
+
+def raycast_leg(torch, dev, steps):
+    """Ray casting of the sonar's returns against the seabed scene (a 256 x 256
+    height field over 200 m with 16 boxes: 130242 triangles): the real-time
+    pattern (1024 beams x 128 rays over 130 x 20 degrees, 50 m) from one pose,
+    and 64 poses of the calibration-scale pattern (2048 x 1024 rays) in one
+    call.  Then the sonar forward at real-time settings (1024 x 1024 bins, a
+    1024 x 2048 fan, gamma speckle) on the cast returns against the same
+    number of uniformly drawn returns: binning structured (beam-ordered)
+    input."""
+    import math
+    import paper_2503_01074_amd as osm
+    import workloads as W
+    s = W.seabed_scene()
+    t0 = time.perf_counter()
+    scene = osm.Scene(s.vertices, s.triangles, s.tri_mat)
+    t_build = time.perf_counter() - t0
+    info = scene.info
+    fa, fe = math.radians(130.0), math.radians(20.0)
+    pose = W.sonar_pose()
+    rt = osm.raycast(scene, [(pose.pos, pose.rot)], 1024, 128, fa, fe, 50.0, device=dev)
+    reps = max(10, steps)
+    k_rt = kernel_us(torch, lambda: osm.raycast(scene, [(pose.pos, pose.rot)], 1024, 128, fa, fe, 50.0, out=rt),
+                     reps)
+    t_rt = k_rt["k_raycast"][1] * 1e-6
+    hit_rt = float((rt[0].mat >= 0).float().mean())
+    poses = [W.sonar_pose(height=4.0 + 8.0 * (i % 8) / 7, pitch_deg=5.0 + 25.0 * (i // 8) / 7,
+                          yaw_deg=-60.0 + 120.0 * i / 63) for i in range(64)]
+    pp = [(p.pos, p.rot) for p in poses]
+    big = osm.raycast(scene, pp, 2048, 1024, fa, fe, 50.0, device=dev)
+    k_big = kernel_us(torch, lambda: osm.raycast(scene, pp, 2048, 1024, fa, fe, 50.0, out=big), 3)
+    t_big = k_big["k_raycast"][1] * 1e-6
+    n_big = 64 * 2048 * 1024
+    hit_big = float(sum((h.mat >= 0).sum().item() for h in big) / n_big)
+    del big
+    torch.cuda.empty_cache()
+    log("ray casting: scene of %d triangles built in %.0f ms (depth %d, SAH cost %.1f); 1024 x 128 rays %.1f us "
+        "(%.2f G rays/s, %.0f%% hit); 64 x 2048 x 1024 rays %.2f ms (%.2f G rays/s, %.0f%% hit)"
+        % (info["n_triangles"], t_build * 1e3, info["depth"], info["sah_cost"], t_rt * 1e6,
+           131072 / t_rt / 1e9, 100 * hit_rt, t_big * 1e3, n_big / t_big / 1e9, 100 * hit_big))
+
+    # the sonar forward on the cast returns against uniformly drawn ones
+    frame = W.sonar_c2()[0]
+    spec = frame.spec
+    geom = osm.SonarGeometry.from_spec(spec)
+    params = osm.sonar_params([osm.sonar_params_from_spec(spec)], dev)
+    rnd = osm.DeviceHits.from_host(frame.hits, dev)
+    refl_rnd = torch.as_tensor(frame.hits.refl, device=dev)
+    refl_scn = torch.as_tensor(s.refl, device=dev)
+    ws = torch.empty(1 << 26, dtype=torch.uint8, device=dev)
+    f_cast = kernel_us(torch, lambda: osm.render_sonar([geom], [rt[0]], params, refl_scn, workspace=ws), reps)
+    f_rnd = kernel_us(torch, lambda: osm.render_sonar([geom], [rnd], params, refl_rnd, workspace=ws), reps)
+    sum_us = lambda d: sum(v[1] for v in d.values())
+    log("sonar forward at real-time settings: cast returns %.1f us, uniform returns %.1f us"
+        % (sum_us(f_cast), sum_us(f_rnd)))
+    scene.close()
+    return {"scene_triangles": info["n_triangles"], "bvh_build_ms": round(t_build * 1e3, 1),
+            "bvh_depth": info["depth"], "bvh_sah_cost": round(info["sah_cost"], 2),
+            "bvh_device_bytes": info["device_bytes"],
+            "real_time_rays": 131072, "real_time_us": round(t_rt * 1e6, 2),
+            "real_time_rays_per_s": 131072 / t_rt, "real_time_hit_frac": round(hit_rt, 3),
+            "calibration_rays": n_big, "calibration_ms": round(t_big * 1e3, 3),
+            "calibration_rays_per_s": n_big / t_big, "calibration_hit_frac": round(hit_big, 3),
+            "sonar_fwd_cast_returns_us": {k: round(v[1], 2) for k, v in f_cast.items()},
+            "sonar_fwd_uniform_returns_us": {k: round(v[1], 2) for k, v in f_rnd.items()}}
+
+
 def cpu_model():
     try:
         with open("/proc/cpuinfo") as fh:
@@ -788,6 +868,9 @@ def main():
     if args.only == "c4":
         c4_leg(torch, dev, args.steps)
         return
+    if args.only == "raycast":
+        raycast_leg(torch, dev, args.steps)
+        return
     from paper_2503_01074_amd import _lib
 
     cs = CalibrationScale(torch, dev, args.c5_frames)
@@ -861,6 +944,8 @@ def main():
         torch.cuda.empty_cache()
         extra["camera_io"] = camera_io_leg(torch, dev, args.steps)
         extra["navigation"] = nav_leg(torch, dev, args.steps)
+        extra["ray_casting"] = raycast_leg(torch, dev, args.steps)
+        torch.cuda.empty_cache()
     cpu = None
     if not args.no_cpu:
         log("timing the FP64 oracle on the host")

@@ -46,7 +46,7 @@
 extern "C" {
 #endif
 
-#define OCEANSIM_ABI_VERSION 4
+#define OCEANSIM_ABI_VERSION 5
 
 typedef enum {
     OCEANSIM_OK = 0,
@@ -384,6 +384,90 @@ typedef struct {
 int oceansim_dvl(const double *t_dev, const float *ranges_dev, const float *velocity_dev, int32_t n_ticks,
                  int32_t n_inst, const oceansim_dvl_params *params, float *velocity_out_dev, int32_t *status_dev,
                  void *stream);
+
+/* ======================================================================== */
+/* Ray casting of the sonar's returns (Sec. III-A.2 takes the returns from  */
+/* the renderer's ray tracing against the scene): a triangle mesh held on   */
+/* the device in a bounding-volume hierarchy, and the closest hits of a     */
+/* sonar's beam x elevation ray pattern, written as the return buffers of   */
+/* an oceansim_sonar_frame.                                                 */
+/* ======================================================================== */
+
+typedef struct oceansim_scene oceansim_scene;
+
+/* Builds the hierarchy of a mesh on the host and uploads it to the current
+ * device (synchronously; the scene owns that device memory until
+ * oceansim_scene_destroy).  vertices [n_vertices][3] float32 (world frame,
+ * metres), triangles [n_triangles][3] int32 vertex indices, tri_mat
+ * [n_triangles] int32 material ids: all HOST memory, not retained.  The
+ * normal of a triangle (v0, v1, v2) is (v1 - v0) x (v2 - v0).  Triangles
+ * whose area is negligible at single precision, |(v1 - v0) x (v2 - v0)| <
+ * 2^-20 L^2 with L the longest edge (needles and points), are dropped: no ray
+ * can hit them decidedly.  A mesh of no (kept) triangles is valid: every ray
+ * misses.  Errors: OCEANSIM_E_INVALID_ARG for NULL arrays, an index outside
+ * [0, n_vertices) or a non-finite vertex; OCEANSIM_E_UNSUPPORTED beyond 2^28
+ * triangles or for a coordinate beyond 2^40 in magnitude; OCEANSIM_E_HIP when
+ * the upload fails.  On error *scene is NULL
+ * and nothing stays allocated. */
+int oceansim_scene_create(const float *vertices, int64_t n_vertices, const int32_t *triangles,
+                          const int32_t *tri_mat, int64_t n_triangles, oceansim_scene **scene);
+
+typedef struct {
+    int64_t n_triangles;   /* triangles kept                                  */
+    int64_t n_dropped;     /* degenerate triangles dropped                    */
+    int64_t n_nodes;       /* two-child nodes (each holds both child boxes)   */
+    int64_t n_leaves;
+    int32_t depth;         /* deepest leaf (the root is at depth 0), <= 32    */
+    int32_t max_leaf;      /* most triangles in one leaf (<= 8)               */
+    double sah_cost;       /* surface-area cost of the tree (node visit = 1,  */
+                           /* triangle test = 1), per ray through the root box */
+    uint64_t device_bytes; /* device memory the scene holds                  */
+} oceansim_scene_info;
+
+int oceansim_scene_get_info(const oceansim_scene *scene, oceansim_scene_info *info);
+
+/* The figures oceansim_scene_create would report for this mesh, from a build
+ * on the host alone (no device is touched, nothing stays allocated): sizes
+ * the device memory of a scene before creating it.  Same arguments and
+ * errors as oceansim_scene_create (upload errors aside). */
+int oceansim_scene_measure(const float *vertices, int64_t n_vertices, const int32_t *triangles,
+                           const int32_t *tri_mat, int64_t n_triangles, oceansim_scene_info *info);
+
+/* Frees the scene's device memory (after synchronising the device).  NULL is
+ * accepted. */
+int oceansim_scene_destroy(oceansim_scene *scene);
+
+/* One sensor pose and its ray pattern.  Beam b (of n_beams) points at
+ * azimuth -fov_az/2 + (b + 1/2) fov_az / n_beams, ray r (of n_rays) of a beam
+ * at elevation -fov_el/2 + (r + 1/2) fov_el / n_rays; the direction in the
+ * sensor frame (x forward, y left, z up) is (cos el cos az, cos el sin az,
+ * sin el), and return k = b n_rays + r.  The pose maps the sensor frame into
+ * the world: world = R sensor + pos, R row-major.  The closest hit with
+ * 0 < t <= t_max along the ray (triangle edges included) is written to
+ * return k in the sensor frame: the point t d, the unit normal of the hit
+ * triangle (R^T n), and its material id.  A miss writes material -1 and
+ * zeros.  Output buffers: DEVICE memory, float32 / int32 [n_beams * n_rays],
+ * 4-byte aligned; NULL skips a coordinate or normal output (mat is
+ * required). */
+typedef struct {
+    float pos[3];
+    float rot[9];
+    int32_t n_beams, n_rays;
+    float fov_az, fov_el;   /* rad: fov_az in (0, 2 pi], fov_el in [0, pi)  */
+    float t_max;            /* casting distance, m, > 0                     */
+    float *x, *y, *z, *nx, *ny, *nz;
+    int32_t *mat;
+} oceansim_ray_frame;
+
+/* Casts the ray patterns of n_frames poses (host array, not retained)
+ * against the scene, on `stream` (asynchronous; the scene must outlive the
+ * enqueued work).  Allocates nothing.  Rays of one beam are cast by
+ * neighbouring threads, so the returns come out in beam order.  Errors:
+ * OCEANSIM_E_INVALID_ARG (NULL scene or mat, bad pattern, non-finite pose,
+ * a scene of another device), OCEANSIM_E_UNSUPPORTED beyond 2^31 - 1 rays in a
+ * frame or for a position beyond 2^40 in magnitude. */
+int oceansim_raycast(const oceansim_scene *scene, const oceansim_ray_frame *frames, int32_t n_frames,
+                     void *stream);
 
 /* ======================================================================== */
 /* Plans: a batch of sonar and camera frames prepared once and launched     */

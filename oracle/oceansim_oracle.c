@@ -872,10 +872,13 @@ void orc_dvl(int32_t n_ticks, int32_t n_inst, const double *t, const float *rang
 /*                                                                           */
 /* ambiguous[k] flags rays whose nearest hit lies within `band` (barycentric */
 /* units) of a triangle edge, whose two nearest hits on different triangles */
-/* are closer than band * t, or whose nearest triangle is a sliver          */
+/* are closer than band * t, whose nearest triangle is a sliver             */
 /* (|n| < band L^2, L its longest edge) or is met at grazing incidence       */
-/* (|d . n| < band |n|): there the nearest triangle, or its point and        */
-/* normal, is not decided by the geometry alone at single precision.         */
+/* (|d . n| < band |n|), whose hit lies within band * t_max of the casting   */
+/* distance, or that pass within `band` of the edge of a triangle they miss  */
+/* no farther than their hit (any such triangle, for a ray that misses):     */
+/* there the nearest triangle, or its point and normal, is not decided by    */
+/* the geometry alone at single precision.                                   */
 /* ------------------------------------------------------------------------- */
 void orc_raycast(int64_t n_vert, const float *vert, int64_t n_tri, const int32_t *tri, const int32_t *tri_mat,
                  const float *pos, const float *rot, int32_t n_beams, int32_t n_rays, double fov_az,
@@ -898,7 +901,7 @@ void orc_raycast(int64_t n_vert, const float *vert, int64_t n_tri, const int32_t
             dw[i] = rot[3 * i] * ds[0] + rot[3 * i + 1] * ds[1] + rot[3 * i + 2] * ds[2];
             o[i] = pos[i];
         }
-        double best = INFINITY, second = INFINITY;
+        double best = INFINITY, second = INFINITY, near = INFINITY;
         int best_amb = 0;
         int64_t best_tri = -1;
         double best_n[3] = {0, 0, 0};
@@ -919,10 +922,17 @@ void orc_raycast(int64_t n_vert, const float *vert, int64_t n_tri, const int32_t
             const double tot = sv[0] + sv[1] + sv[2];
             if (tot == 0.0) continue;   /* degenerate, or the ray runs in the plane */
             const double u0 = sv[0] / tot, u1 = sv[1] / tot, u2 = sv[2] / tot;
-            if (u0 < 0.0 || u1 < 0.0 || u2 < 0.0) continue;
+            const double umin = fmin(u0, fmin(u1, u2));
+            if (umin < -band) continue;
             double t = 0.0;
             for (int i = 0; i < 3; ++i) t += (u0 * v[0][i] + u1 * v[1][i] + u2 * v[2][i]) * dw[i];
-            if (!(t > 0.0 && t <= t_max)) continue;
+            if (umin < 0.0 || t > t_max) {
+                /* a near miss (within band of an edge) or a hit just beyond
+                 * the casting distance */
+                if (t > 0.0 && t <= t_max * (1.0 + band)) near = fmin(near, t);
+                continue;
+            }
+            if (!(t > 0.0)) continue;
             if (t < best) {
                 second = best;
                 best = t;
@@ -951,7 +961,7 @@ void orc_raycast(int64_t n_vert, const float *vert, int64_t n_tri, const int32_t
         if (best_tri < 0) {
             x[k] = y[k] = z[k] = nx[k] = ny[k] = nz[k] = 0.0;
             mat[k] = -1;
-            ambiguous[k] = 0;
+            ambiguous[k] = near < INFINITY;
             continue;
         }
         x[k] = best * ds[0];
@@ -962,7 +972,8 @@ void orc_raycast(int64_t n_vert, const float *vert, int64_t n_tri, const int32_t
         ny[k] = rot[1] * best_n[0] + rot[4] * best_n[1] + rot[7] * best_n[2];
         nz[k] = rot[2] * best_n[0] + rot[5] * best_n[1] + rot[8] * best_n[2];
         mat[k] = tri_mat[best_tri];
-        ambiguous[k] = (best_amb || second - best < band * best) ? 1 : 0;
+        ambiguous[k] = (best_amb || second - best < band * best || near <= best * (1.0 + band) ||
+                        best > t_max * (1.0 - band)) ? 1 : 0;
     }
 }
 

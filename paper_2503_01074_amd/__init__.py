@@ -10,7 +10,8 @@ import torch  # noqa: F401,E402
 from . import _lib  # noqa: F401  (fails loudly when the library is not built)
 from ._lib import (OceansimError, SPECKLE_GAMMA, SPECKLE_OFF, SPECKLE_PAPER,  # noqa: F401
                    SONAR_GRAD_COLUMNS, SONAR_GRAD_WIDTH, WATER_GRAD_WIDTH)
-from .api import (DeviceHits, Plan, SonarGeometry, SonarRender, UwForm, render_sonar,  # noqa: F401
+from .api import (DeviceHits, Plan, Scene, SonarGeometry, SonarRender, UwForm, raycast, render_sonar,  # noqa: F401
+                  scene_measure,
                   barometer, cam_condition, cam_condition_backward, cam_encode, dvl,
                   render_sonar_backward, sonar_params, sonar_params_from_spec, uw_form,
                   uw_form_backward, water_params)

@@ -79,6 +79,18 @@ class DvlParams(C.Structure):
                 ("seed_hi", C.c_uint32)]
 
 
+class SceneInfo(C.Structure):
+    _fields_ = [("n_triangles", C.c_int64), ("n_dropped", C.c_int64), ("n_nodes", C.c_int64),
+                ("n_leaves", C.c_int64), ("depth", C.c_int32), ("max_leaf", C.c_int32), ("sah_cost", C.c_double),
+                ("device_bytes", C.c_uint64)]
+
+
+class RayFrame(C.Structure):
+    _fields_ = [("pos", C.c_float * 3), ("rot", C.c_float * 9), ("n_beams", C.c_int32), ("n_rays", C.c_int32),
+                ("fov_az", C.c_float), ("fov_el", C.c_float), ("t_max", C.c_float)] + \
+               [(k, _P) for k in ("x", "y", "z", "nx", "ny", "nz", "mat")]
+
+
 class OceansimError(RuntimeError):
     def __init__(self, status: int, where: str, text: str):
         super().__init__("%s: %s (%s)" % (where, STATUS_NAMES.get(status, status), text))
@@ -109,6 +121,11 @@ def _load() -> C.CDLL:
         "oceansim_cam_encode": [C.POINTER(CamOutFrame), C.c_int32, _P],
         "oceansim_barometer": [_P, C.c_int64, C.POINTER(BaroParams), _P, _P],
         "oceansim_dvl": [_P, _P, _P, C.c_int32, C.c_int32, C.POINTER(DvlParams), _P, _P, _P],
+        "oceansim_scene_create": [_P, C.c_int64, _P, _P, C.c_int64, C.POINTER(_P)],
+        "oceansim_scene_get_info": [_P, C.POINTER(SceneInfo)],
+        "oceansim_scene_measure": [_P, C.c_int64, _P, _P, C.c_int64, C.POINTER(SceneInfo)],
+        "oceansim_scene_destroy": [_P],
+        "oceansim_raycast": [_P, C.POINTER(RayFrame), C.c_int32, _P],
     }
     for name, args in sig.items():
         fn = getattr(lib, name)
@@ -142,7 +159,8 @@ EXPORTED = ("oceansim_last_error", "oceansim_abi_version", "oceansim_sonar_works
             "oceansim_trace_enable", "oceansim_trace_summary", "oceansim_plan_create",
             "oceansim_plan_forward", "oceansim_plan_backward", "oceansim_plan_shape",
             "oceansim_plan_destroy", "oceansim_cam_condition", "oceansim_cam_condition_backward",
-            "oceansim_cam_encode", "oceansim_barometer", "oceansim_dvl")
+            "oceansim_cam_encode", "oceansim_barometer", "oceansim_dvl", "oceansim_scene_create",
+            "oceansim_scene_get_info", "oceansim_scene_measure", "oceansim_scene_destroy", "oceansim_raycast")
 
 PLAN_BACKWARD, PLAN_GRAPH, PLAN_AUTOTUNE = 1, 2, 4
 
@@ -298,3 +316,33 @@ def oceansim_dvl(t_dev: int, ranges_dev: int, velocity_dev: int, n_ticks: int, n
                  velocity_out_dev: int, status_dev: int, stream: int) -> None:
     check(lib.oceansim_dvl(t_dev, ranges_dev, velocity_dev, n_ticks, n_inst, C.byref(params), velocity_out_dev,
                            status_dev, stream), "oceansim_dvl")
+
+
+def oceansim_scene_create(vertices_host: int, n_vertices: int, triangles_host: int, tri_mat_host: int,
+                          n_triangles: int) -> int:
+    out = _P()
+    check(lib.oceansim_scene_create(vertices_host, n_vertices, triangles_host, tri_mat_host, n_triangles,
+                                    C.byref(out)), "oceansim_scene_create")
+    return out.value
+
+
+def oceansim_scene_get_info(scene: int) -> SceneInfo:
+    info = SceneInfo()
+    check(lib.oceansim_scene_get_info(scene, C.byref(info)), "oceansim_scene_get_info")
+    return info
+
+
+def oceansim_scene_measure(vertices_host: int, n_vertices: int, triangles_host: int, tri_mat_host: int,
+                           n_triangles: int) -> SceneInfo:
+    info = SceneInfo()
+    check(lib.oceansim_scene_measure(vertices_host, n_vertices, triangles_host, tri_mat_host, n_triangles,
+                                     C.byref(info)), "oceansim_scene_measure")
+    return info
+
+
+def oceansim_scene_destroy(scene: int) -> None:
+    check(lib.oceansim_scene_destroy(scene), "oceansim_scene_destroy")
+
+
+def oceansim_raycast(scene: int, frames, n_frames: int, stream: int) -> None:
+    check(lib.oceansim_raycast(scene, frames, n_frames, stream), "oceansim_raycast")

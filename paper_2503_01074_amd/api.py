@@ -12,8 +12,8 @@ from typing import List, Optional, Sequence
 import torch
 
 from . import _lib
-from ._lib import (SONAR_GRAD_WIDTH, WATER_GRAD_WIDTH, BaroParams, CamFrame, CamOutFrame, DvlParams, SonarFrame,
-                   UwFrame)
+from ._lib import (SONAR_GRAD_WIDTH, WATER_GRAD_WIDTH, BaroParams, CamFrame, CamOutFrame, DvlParams, RayFrame,
+                   SonarFrame, UwFrame)
 
 SONAR_PARAM_WIDTH = 8     # alpha, gain, sigma_phi, sigma_sa, sigma_sm, 3 reserved
 WATER_PARAM_WIDTH = 12    # beta_d[3], beta_b[3], b_inf[3], 3 reserved
@@ -328,6 +328,85 @@ def dvl(t: torch.Tensor, ranges: torch.Tensor, velocity: torch.Tensor, janus_ang
                     period_min, int(seed[0]), int(seed[1]))
     _lib.oceansim_dvl(_ptr(t), _ptr(r), _ptr(v), T, N, prm, _ptr(vo), _ptr(st), _stream(v.device))
     return vo, st
+
+
+def _mesh_arrays(vertices, triangles, tri_mat):
+    import numpy as np
+    v = np.ascontiguousarray(np.asarray(vertices, dtype=np.float32).reshape(-1, 3))
+    t = np.ascontiguousarray(np.asarray(triangles, dtype=np.int32).reshape(-1, 3))
+    m = np.ascontiguousarray(np.asarray(tri_mat, dtype=np.int32).reshape(-1))
+    if m.shape[0] != t.shape[0]:
+        raise ValueError("tri_mat must have one entry per triangle")
+    return v, t, m
+
+
+def _info_dict(i) -> dict:
+    return {k: getattr(i, k) for k, _ in i._fields_}
+
+
+def scene_measure(vertices, triangles, tri_mat) -> dict:
+    """Figures of the ray-casting hierarchy of a mesh, built on the host only
+    (oceansim_scene_measure): triangles kept and dropped, nodes, leaves,
+    depth, largest leaf, surface-area cost, device bytes."""
+    v, t, m = _mesh_arrays(vertices, triangles, tri_mat)
+    return _info_dict(_lib.oceansim_scene_measure(v.ctypes.data, v.shape[0], t.ctypes.data, m.ctypes.data,
+                                                  t.shape[0]))
+
+
+class Scene:
+    """A triangle mesh in the library's ray-casting hierarchy on the current
+    device (oceansim_scene_create): vertices [V, 3] float32, triangles [T, 3]
+    int32, tri_mat [T] int32, host arrays (numpy or CPU tensors)."""
+
+    def __init__(self, vertices, triangles, tri_mat):
+        v, t, m = _mesh_arrays(vertices, triangles, tri_mat)
+        self.handle = None
+        self.handle = _lib.oceansim_scene_create(v.ctypes.data, v.shape[0], t.ctypes.data, m.ctypes.data,
+                                                 t.shape[0])
+
+    @property
+    def info(self) -> dict:
+        return _info_dict(_lib.oceansim_scene_get_info(self.handle))
+
+    def close(self) -> None:
+        if self.handle:
+            h, self.handle = self.handle, None
+            _lib.oceansim_scene_destroy(h)
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def raycast(scene: Scene, poses: Sequence, n_beams: int, n_rays: int, fov_az: float, fov_el: float,
+            t_max: float, device="cuda", out: Optional[Sequence[DeviceHits]] = None) -> List[DeviceHits]:
+    """Closest hits of a beam x elevation ray pattern from each pose (pos [3],
+    rot [3, 3] row-major, world = rot @ sensor + pos) against the scene
+    (oceansim_raycast): one sensor-frame hit buffer (DeviceHits, return k =
+    beam * n_rays + ray, material -1 for a miss) per pose, in one launch per
+    16 poses on the current stream.  ``out`` reuses existing buffers."""
+    import numpy as np
+    n = int(n_beams) * int(n_rays)
+    res = list(out) if out is not None else []
+    frames = (RayFrame * max(1, len(poses)))()
+    for i, (pos, rot) in enumerate(poses):
+        if out is None:
+            f32 = lambda: torch.empty(n, dtype=torch.float32, device=device)
+            res.append(DeviceHits(f32(), f32(), f32(), f32(), f32(), f32(),
+                                  torch.empty(n, dtype=torch.int32, device=device)))
+        h = res[i]
+        fr = frames[i]
+        fr.pos[:] = [float(v) for v in np.asarray(pos, dtype=np.float64).reshape(3)]
+        fr.rot[:] = [float(v) for v in np.asarray(rot, dtype=np.float64).reshape(9)]
+        fr.n_beams, fr.n_rays = int(n_beams), int(n_rays)
+        fr.fov_az, fr.fov_el, fr.t_max = float(fov_az), float(fov_el), float(t_max)
+        for k in ("x", "y", "z", "nx", "ny", "nz", "mat"):
+            setattr(fr, k, _ptr(getattr(h, k)))
+    dev = res[0].x.device if res else torch.device(device)
+    _lib.oceansim_raycast(scene.handle, frames, len(poses), _stream(dev))
+    return res
 
 
 class Plan:

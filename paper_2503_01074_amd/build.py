@@ -19,8 +19,8 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "liboceansim.so")
-SOURCES = ["api.cpp", "plan.cpp", "sonar.hip", "uw.hip", "cam.hip", "nav.hip"]
-HEADERS = ["device.hpp", "launch.hpp", "host.hpp", "uw_body.hpp", "reduce_body.hpp"]
+SOURCES = ["api.cpp", "plan.cpp", "bvh.cpp", "sonar.hip", "uw.hip", "cam.hip", "nav.hip", "raycast.hip"]
+HEADERS = ["device.hpp", "launch.hpp", "host.hpp", "uw_body.hpp", "reduce_body.hpp", "scene.hpp"]
 ARCH = os.environ.get("OCEANSIM_ARCH", "gfx950")
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

@@ -27,7 +27,7 @@ def test_exports_every_declared_function():
     for name in sorted(declared):
         assert hasattr(so, name), name
     assert set(lib.EXPORTED) == declared
-    assert lib.oceansim_abi_version() == 4
+    assert lib.oceansim_abi_version() == 5
 
 
 def test_struct_layout_matches_header():
@@ -41,6 +41,8 @@ def test_struct_layout_matches_header():
         "oceansim_cam_out_frame": lib.CamOutFrame,
         "oceansim_baro_params": lib.BaroParams,
         "oceansim_dvl_params": lib.DvlParams,
+        "oceansim_scene_info": lib.SceneInfo,
+        "oceansim_ray_frame": lib.RayFrame,
     }
     lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "oceansim.h"', "int main(void){"]
     for cname, py in structs.items():

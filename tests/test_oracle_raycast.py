@@ -142,6 +142,24 @@ def test_ambiguity_flags_shared_edges_slivers_and_grazing():
     off = oracle.raycast(v, t, m, np.array([3.0, -7.0, 0.0], np.float32), down.astype(np.float32), 1, 1, 0.0, 0.0,
                          100.0)
     assert off["mat"][0] == 4 and not off["ambiguous"][0]
+    # a small triangle in front of the square whose edge the ray passes 1e-6 m
+    # beside: a near miss, flagged; 1e-3 m beside: decided
+    for gap, flagged in ((1e-6, True), (1e-3, False)):
+        tv = np.array([[3.0 + gap, -8.0, -2.0], [3.0 + gap, -6.0, -2.0], [4.0, -7.0, -2.0]], np.float32)
+        vv = np.concatenate([v, tv])
+        tt = np.concatenate([t, [[4, 5, 6]]]).astype(np.int32)
+        mm = np.concatenate([m, [8]]).astype(np.int32)
+        nm = oracle.raycast(vv, tt, mm, np.array([3.0, -7.0, 0.0], np.float32), down.astype(np.float32), 1, 1, 0.0,
+                            0.0, 100.0)
+        assert nm["mat"][0] == 4 and bool(nm["ambiguous"][0]) == flagged
+    # a hit just inside the casting distance is flagged; well inside it is not
+    lim = oracle.raycast(v, t, m, np.array([3.0, -7.0, 0.0], np.float32), down.astype(np.float32), 1, 1, 0.0, 0.0,
+                         5.00001)
+    assert lim["mat"][0] == 4 and lim["ambiguous"][0]
+    # and a square just beyond it: a miss, flagged
+    lim = oracle.raycast(v, t, m, np.array([3.0, -7.0, 0.0], np.float32), down.astype(np.float32), 1, 1, 0.0, 0.0,
+                         4.99999)
+    assert lim["mat"][0] == -1 and lim["ambiguous"][0]
     # a needle 10 m long and 1e-7 m wide under the ray: hit, flagged as a sliver
     sv = np.array([[-5.0, -5e-8, -5.0], [5.0, 0.0, -5.0], [-5.0, 5e-8, -5.0]], np.float32)
     st = np.array([[0, 1, 2]], np.int32)

@@ -413,3 +413,20 @@ def sonar_pose(height: float = 8.0, depth: float = 20.0, pitch_deg: float = 15.0
     pitch = np.array([[np.cos(p), 0.0, np.sin(p)], [0.0, 1.0, 0.0], [-np.sin(p), 0.0, np.cos(p)]])
     yaw = np.array([[np.cos(y), -np.sin(y), 0.0], [np.sin(y), np.cos(y), 0.0], [0.0, 0.0, 1.0]])
     return SonarPose(np.array([0.0, 0.0, -depth + height], np.float32), (yaw @ pitch).astype(np.float32))
+
+
+def chain_and_cluster_mesh(seed: int = BASE_SEED + 15, n_chain: int = 68, n_cluster: int = 300000):
+    """An adversarial mesh for hierarchy depth: n_chain triangles along +x at
+    1.5^i (each 1.5 times farther and larger than the last, so a surface-area
+    split peels them off about one level at a time) and n_cluster small
+    triangles (corners within 0.01 of a centre in the unit cube) at the
+    chain's near end.  Returns (vertices float32 [V, 3], triangles int32
+    [T, 3]); coordinates stay below 2^40."""
+    i = np.arange(n_chain)
+    base = np.array([[1.0, 0.0, 0.0], [1.1, 0.0, 0.0], [1.0, 0.1, 0.05]])
+    chain = (1.5 ** i[:, None, None] * base[None]).reshape(-1, 3)
+    st = Stream(seed, 0)
+    c = st.uniform(0.0, 1.0, (n_cluster, 1, 3))
+    cl = (c + st.uniform(-0.01, 0.01, (n_cluster, 3, 3))).reshape(-1, 3)
+    v = np.concatenate([chain, cl]).astype(np.float32)
+    return v, np.arange(v.shape[0], dtype=np.int32).reshape(-1, 3)
