@@ -57,6 +57,10 @@ def parse():
     ap.add_argument("--c5-frames", type=int, default=64,
                     help="sonar and camera frames of the calibration-scale workload")
     ap.add_argument("--calib-steps", type=int, default=200, help="Adam steps of the calibration run")
+    ap.add_argument("--profile-summary", metavar="DIR", default=None,
+                    help="summarise the rocprofv3 counter runs under DIR (fetch/, write/, valu/, cfetch/, "
+                         "cwrite/) into the per-kernel traffic record bench.py reads; needs no GPU")
+    ap.add_argument("--profile-out", default=C5_TRAFFIC_PROFILE, help="where --profile-summary writes")
     return ap.parse_args()
 
 
@@ -84,6 +88,80 @@ def source_digest():
                 h.update(name.encode() + b"\0" + fh.read())
     return h.hexdigest()
 
+
+
+def short_kernel_name(name):
+    """'void osim::(anonymous namespace)::k_tile<Table<SonarDev>, 512>(...)' -> 'k_tile'."""
+    name = name.strip().strip('"').replace("(anonymous namespace)::", "")
+    if name.startswith("void "):
+        name = name[5:]
+    depth, cut = 0, len(name)
+    for i, ch in enumerate(name):
+        if ch in "<(" and depth == 0:
+            cut = i
+            break
+    name = name[:cut]
+    return name.rsplit("::", 1)[-1]
+
+
+def counter_means(directory, counter):
+    """Mean value of one counter per dispatch, by short kernel name, over the
+    rocprofv3 counter-collection CSV files under `directory`."""
+    import csv
+    sums, counts = {}, {}
+    for root, _, files in os.walk(directory):
+        for fn in files:
+            if not fn.endswith("counter_collection.csv"):
+                continue
+            with open(os.path.join(root, fn), newline="") as fh:
+                per_dispatch = {}
+                for row in csv.DictReader(fh):
+                    if row["Counter_Name"] != counter:
+                        continue
+                    key = (row["Dispatch_Id"], short_kernel_name(row["Kernel_Name"]))
+                    per_dispatch[key] = per_dispatch.get(key, 0.0) + float(row["Counter_Value"])
+                for (_, k), v in per_dispatch.items():
+                    sums[k] = sums.get(k, 0.0) + v
+                    counts[k] = counts.get(k, 0) + 1
+    return {k: sums[k] / counts[k] for k in sums}, counts
+
+
+def profile_summary(directory, out_path):
+    """Per-launch HBM bytes and VALU instructions of each kernel from the
+    counter runs under `directory`: FETCH_SIZE and WRITE_SIZE (KiB per
+    dispatch) are scaled by what they read for the 64 MiB copy of
+    --copy-calibration (64 MiB read and 64 MiB written per launch);
+    SQ_INSTS_VALU counts wave instructions.  Writes the record bench.py reads
+    (tagged with the library source digest) and prints a table."""
+    copy_bytes = float(64 << 20)
+    cf, _ = counter_means(os.path.join(directory, "cfetch"), "FETCH_SIZE")
+    cw, _ = counter_means(os.path.join(directory, "cwrite"), "WRITE_SIZE")
+    copy_name = [k for k in cf if "copyBuffer" in k or "copy" in k.lower()]
+    if not copy_name:
+        raise SystemExit("no copy kernel in the calibration runs")
+    fetch_factor = copy_bytes / (cf[copy_name[0]] * 1024.0)
+    write_factor = copy_bytes / (cw[copy_name[0]] * 1024.0)
+    fetch, n = counter_means(os.path.join(directory, "fetch"), "FETCH_SIZE")
+    write, _ = counter_means(os.path.join(directory, "write"), "WRITE_SIZE")
+    valu, _ = counter_means(os.path.join(directory, "valu"), "SQ_INSTS_VALU")
+    kernels = {}
+    for k in sorted(fetch):
+        if k.startswith("__amd") or k not in write:
+            continue
+        kernels[k] = {"fetch_bytes": fetch[k] * 1024.0 * fetch_factor, "write_bytes": write[k] * 1024.0 * write_factor,
+                      "dispatches": n[k]}
+        if k in valu:
+            kernels[k]["valu_insts"] = valu[k]
+    rec = {"source_sha256": source_digest(), "fetch_factor": fetch_factor, "write_factor": write_factor,
+           "kernels": kernels}
+    with open(out_path, "w") as fh:
+        json.dump(rec, fh, indent=1, sort_keys=True)
+    print("fetch factor %.4f, write factor %.4f (copy kernel %s)" % (fetch_factor, write_factor, copy_name[0]))
+    print("| kernel | dispatches | read MB | written MB | VALU instructions (M) |")
+    print("|---|---|---|---|---|")
+    for k, v in kernels.items():
+        print("| %s | %d | %.2f | %.2f | %s |" % (k, v["dispatches"], v["fetch_bytes"] / 1e6, v["write_bytes"] / 1e6,
+                                                 "%.2f" % (v["valu_insts"] / 1e6) if "valu_insts" in v else "-"))
 
 
 def measured_profile():
@@ -848,6 +926,9 @@ def camera_io_leg(torch, dev, steps):
 
 def main():
     args = parse()
+    if args.profile_summary:
+        profile_summary(args.profile_summary, args.profile_out)
+        return
     if args.gpus != 1:
         print("bench.py: this build measures one GPU; --gpus %d is not supported (the path shards by frame "
               "across GPUs, see the design notes)" % args.gpus, file=sys.stderr)
