@@ -15,6 +15,11 @@
 //           bilinear interpolation of the polar image.
 //   k_bin_uw    (plans with camera frames) k_bin plus the camera forward.
 // Backward, per frame:
+//   k_pair_bwd  (plans, tables of at most 64 materials) one workgroup per
+//               forward tile: the tile's polar gradient read once into LDS,
+//               then the adjoint of binning, gain, the multiplicative speckle
+//               and Eq. (2) from the (bin, material) pairs and ranges the
+//               forward left, summed in order-independent 64-bit fixed point.
 //   k_fant_bwd  (plans) rows of the transposed fan operator built at plan
 //               creation: each bin's fan gradient gathered through its
 //               entries in FP64 (a mirrored row yields a bin and its mirror
