@@ -523,7 +523,12 @@ enum {
  * when the environment variable OCEANSIM_TUNE_CACHE names a file, in that
  * JSON file, keyed by GPU architecture, CU count and a size class of the
  * batch.  Tuning runs the launches, so it reads the inputs (which must hold
- * representative returns) and writes the outputs and gradients.  All work of
+ * representative returns) and writes the outputs and gradients.  When the
+ * environment variable OCEANSIM_PLAN_SHAPE is set to "tile_bins,chunk"
+ * (tile_bins 1..16384, chunk 512, 1024, 2048, 4096 or 8192 returns), plans
+ * take that forward tile target and binning chunk instead of the heuristic or
+ * the autotuner (OCEANSIM_E_INVALID_ARG for any other value): it replays a
+ * shape a tuned plan picked, e.g. for tests at the tuned configuration.  All work of
  * creation is done on `stream`, which is synchronised.  Errors: the status
  * codes above; on error *plan is NULL and nothing stays allocated.        */
 int oceansim_plan_create(const oceansim_sonar_frame *sonar, int32_t n_sonar,

@@ -185,7 +185,11 @@ int plan_sonar(const oceansim_sonar_frame *frames, int n_frames, int n_param_row
     P.grid.max_tile_bins = max_tile_bins;
     P.grid.max_tile_bins_b = max_tile_bins_b;
     P.grid.max_n_az = 1;
-    for (int i = 0; i < n_frames; ++i) P.grid.max_n_az = std::max(P.grid.max_n_az, frames[i].n_azimuth);
+    P.grid.wide_col_regs = 1;
+    for (int i = 0; i < n_frames; ++i) {
+        P.grid.max_n_az = std::max(P.grid.max_n_az, frames[i].n_azimuth);
+        if ((4 * kWideThreads) % frames[i].n_azimuth != 0) P.grid.wide_col_regs = 0;
+    }
 
     size_t off = 0;
     auto take = [&](size_t bytes) {

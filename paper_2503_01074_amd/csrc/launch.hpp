@@ -56,6 +56,8 @@ struct SonarGrid {
     int row_blocks;      // backward: one workgroup per range row of the range-normalised frames
     int max_rows_per_tile;   // forward: widest tile (rows) of a range-normalised frame; 0: none
     int pair_bwd;        // backward from the forward's material pairs (k_pair_bwd, one workgroup per forward tile)
+    int wide_col_regs;   // every frame's n_azimuth divides 4 * kWideThreads: in a wide tile each thread
+                         // keeps the same four columns, so their beam-pattern factors live in registers
 };
 
 constexpr int kBwdThreads = 512;   // threads of a backward polar-tile workgroup

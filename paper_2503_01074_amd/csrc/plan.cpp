@@ -797,7 +797,22 @@ int oceansim_plan_create(const oceansim_sonar_frame *sonar, int32_t n_sonar, con
             return rc;
         }
     }
-    if ((flags & OCEANSIM_PLAN_AUTOTUNE) && n_sonar > 0) {
+    const char *shape_env = getenv("OCEANSIM_PLAN_SHAPE");
+    if (shape_env && *shape_env && n_sonar > 0) {
+        // a fixed launch shape "tile_bins,chunk" in place of the heuristic or
+        // the autotuner
+        int tb = 0, ch = 0;
+        if (sscanf(shape_env, "%d,%d", &tb, &ch) != 2 || tb < 1 || tb > kMaxFwdTileBins ||
+            (ch != 512 && ch != 1024 && ch != 2048 && ch != 4096 && ch != 8192)) {
+            free_plan(p);
+            return fail(OCEANSIM_E_INVALID_ARG,
+                        "OCEANSIM_PLAN_SHAPE must be \"tile_bins,chunk\" with tile_bins in 1..%d and chunk one of "
+                        "512, 1024, 2048, 4096, 8192",
+                        kMaxFwdTileBins);
+        }
+        p->tune.fwd_tile_bins = tb;
+        p->tune.chunk = ch;
+    } else if ((flags & OCEANSIM_PLAN_AUTOTUNE) && n_sonar > 0) {
         rc = autotune(p, st);
         if (rc) {
             free_plan(p);

@@ -14,6 +14,8 @@
 //   k_fan   one thread per mirror pair of fan pixels: FP64 polar coordinates,
 //           bilinear interpolation of the polar image.
 //   k_bin_uw    (plans with camera frames) k_bin plus the camera forward.
+//   k_tile_uw   (plans with camera frames and wide tiles) k_tile plus the
+//               camera forward, workgroups of both kinds interleaved.
 // Backward, per frame:
 //   k_pair_bwd  (plans, tables of at most 64 materials) one workgroup per
 //               forward tile: the tile's polar gradient read once into LDS,
@@ -182,7 +184,7 @@ __global__ __launch_bounds__(kBlock) void k_bin_uw(Src src, const oceansim_sonar
     if ((int)blockIdx.x < n_bin_blocks)
         bin_block<Src, kBlock, R>(src, params, refl, n_mat, blockIdx.x);
     else
-        uw_fwd_block<Table<UwDev>, kBlock>(usrc, wparams, blockIdx.x - n_bin_blocks);
+        uw_fwd_block<Table<UwDev>, kBlock>(usrc, wparams, blockIdx.x - n_bin_blocks, threadIdx.x);
 }
 
 // ---------------------------------------------------------------------------
@@ -271,16 +273,17 @@ __device__ __forceinline__ void for_tile_pairs(const SonarDev &f, int tile, int 
 }
 
 // Wave-level stream compaction: every wave walks its share of [0, n), queues
-// the indices x with pred(x) in its own LDS queue (2 x 64 entries) and runs
-// work(x) 64 at a time, so the costly work of the sparse set keeps all lanes
-// busy.  Call from every thread; no workgroup barrier inside.
-template <int NT, class Pred, class Work>
-__device__ __forceinline__ void wave_compact(int n, int *queues, Pred pred, Work work) {
+// the indices x with pred(x) in its own LDS queue (2 x 64 entries of type Q,
+// which must hold n - 1) and runs work(x) 64 at a time, so the costly work of
+// the sparse set keeps all lanes busy.  Call from every thread; no workgroup
+// barrier inside.
+template <int NT, class Q, class Pred, class Work>
+__device__ __forceinline__ void wave_compact(int n, Q *queues, Pred pred, Work work) {
     const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
     constexpr int NW = NT / kWave;
     const int per = ((n + NW - 1) / NW + kWave - 1) / kWave * kWave;
     const int lo = min(w * per, n), hi = min(lo + per, n);
-    int *qw = queues + w * 2 * kWave;
+    Q *qw = queues + w * 2 * kWave;
     int qn = 0;
     auto sync = [&]() __attribute__((always_inline)) {
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -306,13 +309,18 @@ __device__ __forceinline__ void wave_compact(int n, int *queues, Pred pred, Work
     if (lane < qn) work(qw[lane]);
 }
 
-// Forward polar tile `bid` of the launch (NT threads).
-template <class Src, int NT>
+// Forward polar tile `bid` of the launch (NT threads).  COL_REGS: every
+// frame's n_az divides 4 NT, so a thread's groups of four bins (4 NT bins
+// apart) always fall on the same four columns, and their beam-pattern
+// factors are kept in registers instead of an LDS column table (which the
+// launch then does not reserve).
+template <class Src, int NT, bool COL_REGS>
 __device__ __forceinline__ void tile_fwd_block(const Src &src, const oceansim_sonar_params *params, const float *refl,
                                                int n_mat, int bid) {
     extern __shared__ int4 lds_raw[];
     constexpr int NW = NT / kWave;
-    __shared__ int queues[NW * 2 * kWave];
+    __shared__ unsigned short queues[NW * 2 * kWave];   // tile-local bins (< kMaxFwdTileBins)
+    static_assert(kMaxFwdTileBins <= 65536, "queue entries are 16-bit");
     __shared__ float refl_s[kLaneHistMats];
     __shared__ int seg_end[NT], seg_start[NT], wtot[NW];
     int tile;
@@ -329,12 +337,25 @@ __device__ __forceinline__ void tile_fwd_block(const Src &src, const oceansim_so
     const bool matp = f.matp != 0;
     const oceansim_sonar_params pr = params[f.param_row];
     const AddCtx ctx{pr.sigma_sa, 1.0f / pr.sigma_phi};
-    // the column factor exp(-phi_j^2 / sigma_phi) once per column of the tile's rows
-    if (speckle)
-        for (int j = tid; j < f.n_az; j += NT) {
-            const float phi = bin_azimuth(f, j);
-            etab[j] = expf(-(phi * phi) * ctx.inv_sigma_phi);
+    const int q_first = b_lo >> 2, q_last = (b_hi - 1) >> 2;
+    // the column factor exp(-phi_j^2 / sigma_phi): once per column of the
+    // tile's rows in LDS, or for the thread's own four columns in registers
+    float ereg[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+    if (speckle) {
+        if (COL_REGS) {
+            const int j0 = (int)(((long long)(q_first + tid) << 2) % f.n_az);
+#pragma unroll
+            for (int w = 0; w < 4; ++w) {
+                const float phi = bin_azimuth(f, (j0 + w) % f.n_az);
+                ereg[w] = expf(-(phi * phi) * ctx.inv_sigma_phi);
+            }
+        } else {
+            for (int j = tid; j < f.n_az; j += NT) {
+                const float phi = bin_azimuth(f, j);
+                etab[j] = expf(-(phi * phi) * ctx.inv_sigma_phi);
+            }
         }
+    }
     // material pairs carry cos x attenuation: the reflectivity is applied here
     if (matp)
         for (int k = tid; k < n_mat; k += NT) refl_s[k] = refl[k];
@@ -345,7 +366,6 @@ __device__ __forceinline__ void tile_fwd_block(const Src &src, const oceansim_so
     for (int k = tid; k < nbins; k += NT) acc[k] = 0.0f;
     __syncthreads();
 
-    const int q_first = b_lo >> 2, q_last = (b_hi - 1) >> 2;
     // additive term of Eq. (3)-(4) for the group of four consecutive
     // frame-linear bins starting at 4q (one Philox call)
     auto additive_group = [&](int q, float (&add)[4]) __attribute__((always_inline)) {
@@ -358,7 +378,7 @@ __device__ __forceinline__ void tile_fwd_block(const Src &src, const oceansim_so
         for (int w = 0; w < 4; ++w) {
             // R_i (1 + 0.5 E_j sigma_sa rho)
             const float rho = rayleigh_of_word(pick(wd, (uint32_t)w));
-            add[w] = R * (1.0f + 0.5f * etab[j] * (ctx.sigma_sa * rho));
+            add[w] = R * (1.0f + 0.5f * (COL_REGS ? ereg[w] : etab[j]) * (ctx.sigma_sa * rho));
             if (++j == f.n_az) {
                 j = 0;
                 R = range_ramp(f, ++i);
@@ -398,7 +418,7 @@ __device__ __forceinline__ void tile_fwd_block(const Src &src, const oceansim_so
         // that is positive (the maximum over the positive entries: NaN and
         // non-positive values do not count), else the row as it is; acc then
         // holds the normalised Q, so the gain below is 1
-        unsigned *rmax = reinterpret_cast<unsigned *>(etab + f.n_az);   // [rows of the tile]
+        unsigned *rmax = reinterpret_cast<unsigned *>(COL_REGS ? etab : etab + f.n_az);   // [rows of the tile]
         const int rows = nbins / f.n_az;
         for (int r = tid; r < rows; r += NT) rmax[r] = 0u;
         __syncthreads();
@@ -454,10 +474,36 @@ __device__ __forceinline__ void tile_fwd_block(const Src &src, const oceansim_so
     }
 }
 
-template <class Src, int NT>
+template <class Src, int NT, bool COL_REGS>
 __global__ __launch_bounds__(NT) void k_tile(Src src, const oceansim_sonar_params *params, const float *refl,
                                              int n_mat) {
-    tile_fwd_block<Src, NT>(src, params, refl, n_mat, blockIdx.x);
+    tile_fwd_block<Src, NT, COL_REGS>(src, params, refl, n_mat, blockIdx.x);
+}
+
+// k_tile_uw (plans with camera frames and wide tiles): the forward tiles and
+// the camera forward in one launch.  The tiles are bound by their VALU work
+// (speckle draws), the camera by HBM; apart, each leaves the other's unit
+// idle, and two streams do not overlap them (the first launch fills the chip).
+// The camera workgroups are spread evenly through the dispatch order
+// (workgroup x is a camera one when floor((x+1) C / N) > floor(x C / N), C of
+// N in all), so every CU holds both kinds while both last.  A camera
+// workgroup runs two camera blocks of kBlock threads side by side.
+template <class Src, bool COL_REGS>
+__global__ __launch_bounds__(kWideThreads) void k_tile_uw(Src src, const oceansim_sonar_params *params,
+                                                          const float *refl, int n_mat, int n_tile_blocks,
+                                                          int n_cam_groups, Table<UwDev> usrc,
+                                                          const oceansim_water_params *wparams, int n_cam_blocks) {
+    static_assert(kWideThreads == 2 * kBlock, "two camera blocks per wide workgroup");
+    const long long x = blockIdx.x;
+    const long long n = (long long)n_tile_blocks + n_cam_groups;
+    const int c_before = (int)(x * n_cam_groups / n);
+    const int c_upto = (int)((x + 1) * n_cam_groups / n);
+    if (c_upto > c_before) {
+        const int cb = 2 * c_before + (int)(threadIdx.x >= kBlock);
+        if (cb < n_cam_blocks) uw_fwd_block<Table<UwDev>, kBlock>(usrc, wparams, cb, threadIdx.x & (kBlock - 1));
+    } else {
+        tile_fwd_block<Src, kWideThreads, COL_REGS>(src, params, refl, n_mat, (int)(x - c_before));
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -1199,6 +1245,15 @@ __global__ __launch_bounds__(kBlock) void k_ret_uw_bwd(Src src, const oceansim_s
 constexpr double kGammaMax = 16.635532333438686;
 constexpr double kGaussMax = 5.7678665758658466;
 
+// A value known to be the same in every lane of the wave, moved to scalar
+// registers (the compiler cannot prove it for values read back from LDS).
+__device__ __forceinline__ double uniform_f64(double x) {
+    const unsigned long long b = (unsigned long long)__double_as_longlong(x);
+    const unsigned lo = (unsigned)__builtin_amdgcn_readfirstlane((int)(unsigned)b);
+    const unsigned hi = (unsigned)__builtin_amdgcn_readfirstlane((int)(unsigned)(b >> 32));
+    return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
 __device__ __forceinline__ long long scale_round(double x, double scale) {
     return round_to_ll(x * scale);
 }
@@ -1339,8 +1394,11 @@ __global__ __launch_bounds__(kWideThreads) void k_pair_bwd(Src src, const oceans
     const long long n_terms = f.n > 0 ? f.n : 1;
     const int e_refl = fixed_exponent(B_refl, n_terms), e_alpha = fixed_exponent(B_alpha, n_terms);
     const int e_gain = fixed_exponent(B_gain, n_terms), e_ssm = fixed_exponent(B_ssm, n_terms);
-    const double s_refl = ldexp(1.0, min(e_refl, 1000)), s_alpha = ldexp(1.0, min(e_alpha, 1000));
-    const double s_gain = ldexp(1.0, min(e_gain, 1000)), s_ssm = ldexp(1.0, min(e_ssm, 1000));
+    // the scales are the same in every lane: held in scalar registers
+    const double s_refl = uniform_f64(ldexp(1.0, min(e_refl, 1000)));
+    const double s_alpha = uniform_f64(ldexp(1.0, min(e_alpha, 1000)));
+    const double s_gain = uniform_f64(ldexp(1.0, min(e_gain, 1000)));
+    const double s_ssm = uniform_f64(ldexp(1.0, min(e_ssm, 1000)));
     const bool refl_ok = __builtin_isfinite(B_refl);
     const bool paper = f.speckle == SPECKLE_PAPER;
 
@@ -1794,17 +1852,38 @@ static hipError_t launch_fwd(const Src &src, const SonarGrid &g, const oceansim_
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
-    if (with_uw && wide) {
-        hipError_t e = uw_forward_table(uw->table, uw->n, uw->blocks, uw->params, st);
-        if (e != hipSuccess) return e;
+    // LDS of a tile: the histogram, the column table (unless the columns'
+    // factors live in registers), the row maxima
+    const bool wide_tiles = g.max_tile_bins > kMaxTileBins;
+    const bool col_regs = wide_tiles && g.wide_col_regs;
+    const size_t tile_lds = (size_t)g.max_tile_bins * 4 + (col_regs ? 0 : (size_t)g.max_n_az * 4) +
+                            (size_t)g.max_rows_per_tile * 4;
+    if (with_uw && wide && wide_tiles) {
+        // wide tiles and the camera forward side by side in one launch
+        const int groups = (uw->blocks + 1) / 2;
+        if (col_regs)
+            OSIM_LAUNCH("k_tile_uw", (k_tile_uw<Src, true>), dim3(g.tile_blocks + groups), dim3(kWideThreads),
+                        tile_lds, st, src, params, refl, n_mat, g.tile_blocks, groups, Table<UwDev>{uw->table, uw->n},
+                        uw->params, uw->blocks);
+        else
+            OSIM_LAUNCH("k_tile_uw", (k_tile_uw<Src, false>), dim3(g.tile_blocks + groups), dim3(kWideThreads),
+                        tile_lds, st, src, params, refl, n_mat, g.tile_blocks, groups, Table<UwDev>{uw->table, uw->n},
+                        uw->params, uw->blocks);
+    } else {
+        if (with_uw && wide) {
+            hipError_t e = uw_forward_table(uw->table, uw->n, uw->blocks, uw->params, st);
+            if (e != hipSuccess) return e;
+        }
+        if (col_regs)
+            OSIM_LAUNCH("k_tile", (k_tile<Src, kWideThreads, true>), dim3(g.tile_blocks), dim3(kWideThreads),
+                        tile_lds, st, src, params, refl, n_mat);
+        else if (wide_tiles)
+            OSIM_LAUNCH("k_tile", (k_tile<Src, kWideThreads, false>), dim3(g.tile_blocks), dim3(kWideThreads),
+                        tile_lds, st, src, params, refl, n_mat);
+        else
+            OSIM_LAUNCH("k_tile", (k_tile<Src, kBlock, false>), dim3(g.tile_blocks), dim3(kBlock), tile_lds, st, src,
+                        params, refl, n_mat);
     }
-    const size_t tile_lds = (size_t)g.max_tile_bins * 4 + (size_t)g.max_n_az * 4 + (size_t)g.max_rows_per_tile * 4;
-    if (g.max_tile_bins > kMaxTileBins)
-        OSIM_LAUNCH("k_tile", (k_tile<Src, kWideThreads>), dim3(g.tile_blocks), dim3(kWideThreads), tile_lds, st, src,
-                    params, refl, n_mat);
-    else
-        OSIM_LAUNCH("k_tile", (k_tile<Src, kBlock>), dim3(g.tile_blocks), dim3(kBlock), tile_lds, st, src, params,
-                    refl, n_mat);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     if (g.fan_blocks > 0) {

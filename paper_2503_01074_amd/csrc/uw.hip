@@ -13,7 +13,7 @@ namespace osim {
 
 template <class Src>
 __global__ __launch_bounds__(kBlock) void k_uw(Src src, const oceansim_water_params *params) {
-    uw_fwd_block<Src, kBlock>(src, params, blockIdx.x);
+    uw_fwd_block<Src, kBlock>(src, params, blockIdx.x, threadIdx.x);
 }
 
 template <class Src>

@@ -67,10 +67,13 @@ __device__ __forceinline__ float uw_pixel(float J, float d, float bd, float bb, 
     return J * T + bi * S1;
 }
 
-// Workgroup `bid` (of NT threads) of a forward launch over the frames of src:
-// kUwFwdPixelsPerThread pixels per thread, as float4 groups.
+// Workgroup `bid` (of NT threads, this thread being `tx` of them) of a
+// forward launch over the frames of src: kUwFwdPixelsPerThread pixels per
+// thread, as float4 groups.  No barrier: a wider workgroup may run several
+// of these blocks side by side.
 template <class Src, int NT>
-__device__ __forceinline__ void uw_fwd_block(const Src &src, const oceansim_water_params *params, int bid) {
+__device__ __forceinline__ void uw_fwd_block(const Src &src, const oceansim_water_params *params, int bid,
+                                             int tx) {
     int local;
     const int fi = src.locate(bid, 0, local);
     const UwDev f = src.frame(fi);
@@ -87,14 +90,14 @@ __device__ __forceinline__ void uw_fwd_block(const Src &src, const oceansim_wate
         float4 d[kIt], J[kIt][3];
 #pragma unroll
         for (int it = 0; it < kIt; ++it) {
-            const long long p = p0 + ((long long)it * NT + threadIdx.x) * 4;
+            const long long p = p0 + ((long long)it * NT + tx) * 4;
             d[it] = gload((gptr<const float4>)(Dp + p));
 #pragma unroll
             for (int c = 0; c < 3; ++c) J[it][c] = gload((gptr<const float4>)(Jp + c * npix + p));
         }
 #pragma unroll
         for (int it = 0; it < kIt; ++it) {
-            const long long p = p0 + ((long long)it * NT + threadIdx.x) * 4;
+            const long long p = p0 + ((long long)it * NT + tx) * 4;
 #pragma unroll
             for (int c = 0; c < 3; ++c) {
                 float4 o;
@@ -109,7 +112,7 @@ __device__ __forceinline__ void uw_fwd_block(const Src &src, const oceansim_wate
     }
     // ragged tail (or an image whose size is not a multiple of 4): per pixel
     for (int it = 0; it < kIt; ++it) {
-        const long long p = p0 + ((long long)it * NT + threadIdx.x) * 4;
+        const long long p = p0 + ((long long)it * NT + tx) * 4;
         for (long long q = p; q < p + 4 && q < npix; ++q) {
             const float d = Dp[q];
 #pragma unroll

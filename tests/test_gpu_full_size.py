@@ -214,14 +214,21 @@ def test_differentiable_batch_plan():
     plan.close()
 
 
-def test_calibration_shape_plan():
+@pytest.mark.parametrize("shape", [None, "8192,8192"])
+def test_calibration_shape_plan(shape, monkeypatch):
     """Eight frames of the calibration shape (2048 x 1024 returns, 2048 x 2048
     bins, no fan, 64 materials, gamma speckle) and eight 1920 x 1080 camera
     frames through a backward plan (polar loss): two frames' images and all
-    gradients checked."""
+    gradients checked.  Once with the default launch shape and once with the
+    shape the benchmark's autotuned plan runs (8192-bin tiles, 8192-return
+    chunks: wide binning, the tiles and the camera forward in one launch,
+    the pair backward)."""
     import torch
     import paper_2503_01074_amd as osm
-    _say("calibration shape: 8 sonar frames of 2M returns, 2048^2 bins, + 8 camera frames 1080p")
+    if shape:
+        monkeypatch.setenv("OCEANSIM_PLAN_SHAPE", shape)
+    _say("calibration shape: 8 sonar frames of 2M returns, 2048^2 bins, + 8 camera frames 1080p, shape %s"
+         % (shape or "default"))
     frames = W.sonar_c5(n_frames=8)
     st = W.Stream(W.BASE_SEED + 4, 1 << 21)
     water = W.make_water(st)
@@ -238,4 +245,8 @@ def test_calibration_shape_plan():
     torch.cuda.synchronize()
     _check_sonar_forward(plan, frames, refl, [0, 7], "calibration shape")
     _check_backward(plan, frames, refl, gpol, gfan, cams, water, gout, "calibration shape")
+    if shape:
+        tb, ch = (int(v) for v in shape.split(","))
+        got = plan.shape()
+        assert got["fwd_tile_bins"] == tb and got["chunk"] == ch, got
     plan.close()

@@ -289,3 +289,66 @@ def test_autotune_agrees_and_caches(tmp_path, monkeypatch):
     assert again.shape() == shape
     plan.close()
     again.close()
+
+
+@pytest.mark.parametrize("graph", [False, True])
+def test_plan_wide_shape_tiles_and_camera_in_one_launch(graph, monkeypatch):
+    """The launch shape the calibration-scale benchmark runs (8192-bin tiles,
+    8192-return binning chunks), forced on a small mixed batch: wide binning,
+    the wide tiles and the camera forward in one launch (workgroups of both
+    kinds interleaved), the pair backward; frames of 6912 and 5120 bins (one
+    tile each, above the 4096 bins of a narrow tile) with fans, and four
+    camera frames of uneven sizes on two water rows."""
+    import torch
+    import paper_2503_01074_amd as osm
+    monkeypatch.setenv("OCEANSIM_PLAN_SHAPE", "8192,8192")
+    _say("plan, forced wide shape, graph %s" % graph)
+    st = W.Stream(931, 1)
+    common = dict(r_min=0.5, r_max=12.0, sigma_phi=0.3, sigma_sa=0.15, sigma_sm=0.12, seed_lo=23, gamma_k=3)
+    specs = [W.SonarSpec(n_range=96, n_azimuth=72, fan_h=80, fan_w=150, alpha=0.09, gain=1.2,
+                         speckle_mode=W.SPECKLE_GAMMA, frame_id=5, **common),
+             W.SonarSpec(n_range=80, n_azimuth=64, fan_h=64, fan_w=121, alpha=0.05, gain=0.8,
+                         speckle_mode=W.SPECKLE_PAPER, frame_id=6, **common)]
+    frames = [W.SonarFrame(s, W.make_hits(st, s, n, n_materials=9, outside_frac=0.05))
+              for s, n in zip(specs, (20000, 9000))]
+    refl = frames[0].hits.refl
+    for f in frames:
+        f.hits.refl = refl
+    gpol = [W.loss_weights((932, k), (s.n_range, s.n_azimuth)) for k, s in enumerate(specs)]
+    gfan = [W.loss_weights((933, k), (s.fan_h, s.fan_w)) for k, s in enumerate(specs)]
+    cams = [W.make_camera(st, 300, 517, water_row=0), W.make_camera(st, 37, 11, water_row=1),
+            W.make_camera(st, 256, 256, water_row=1), W.make_camera(st, 5, 3, water_row=0)]
+    waters = [W.make_water(st), W.make_water(st)]
+    gout = [W.loss_weights((934, k), c.J.shape) for k, c in enumerate(cams)]
+    geoms = [osm.SonarGeometry.from_spec(f.spec, param_row=k) for k, f in enumerate(frames)]
+    hits = [osm.DeviceHits.from_host(f.hits) for f in frames]
+    params = osm.sonar_params([osm.sonar_params_from_spec(f.spec) for f in frames])
+    Js = [torch.as_tensor(c.J).cuda() for c in cams]
+    ds = [torch.as_tensor(c.depth).cuda() for c in cams]
+    water = osm.water_params([(w.beta_d, w.beta_b, w.b_inf) for w in waters])
+    plan = osm.Plan(list(zip(geoms, hits)), list(zip(Js, ds, [c.water_row for c in cams])), sonar_params=params,
+                    refl=torch.as_tensor(refl).cuda(), water=water, backward=True, graph=graph, bins=True)
+    shape = plan.shape()
+    # the largest tile (one frame's 6912 bins) is wide: above a narrow tile's 4096
+    assert shape["fwd_tile_bins"] == 6912 and shape["chunk"] == 8192, shape
+    for o, gp, gf in zip(plan.sonar_out, gpol, gfan):
+        o["grad_polar"].copy_(torch.as_tensor(gp))
+        o["grad_fan"].copy_(torch.as_tensor(gf))
+    for o, g in zip(plan.camera_out, gout):
+        o["grad_out"].copy_(torch.as_tensor(g))
+    first = None
+    for rep in range(3):
+        plan.forward()
+        plan.backward()
+        torch.cuda.synchronize()
+        _check_against_oracle(plan, frames, refl, gpol, gfan, cams, waters, gout, "wide shape rep %d" % rep)
+        grads = [plan.grad_refl.clone(), plan.grad_sonar_params.clone(), plan.grad_water.clone()]
+        if first is None:
+            first = grads
+        else:
+            for a, b in zip(first, grads):
+                assert torch.equal(a, b), "gradients differ between replays"
+    plan.close()
+    monkeypatch.setenv("OCEANSIM_PLAN_SHAPE", "100,3000")
+    with pytest.raises(osm.OceansimError, match="OCEANSIM_PLAN_SHAPE"):
+        osm.Plan(list(zip(geoms, hits)), sonar_params=params, refl=torch.as_tensor(refl).cuda())
