@@ -1270,7 +1270,11 @@ __device__ __forceinline__ int fixed_exponent(double bound, long long n) {
     return 50 - e - extra;
 }
 
-template <class Src>
+// COL_REGS: every frame's n_az divides 4 kWideThreads, so each thread's groups
+// of four bins fall on the same four columns: their beam-pattern factors are
+// computed once, and the additive adjoint sums g R rho per column, weighted by
+// the column's factors at the end.
+template <class Src, bool COL_REGS>
 __global__ __launch_bounds__(kWideThreads) void k_pair_bwd(Src src, const oceansim_sonar_params *params,
                                                            const float *refl, int n_mat, double *part,
                                                            int slot_base, int n_slots, double *refl_part,
@@ -1316,6 +1320,19 @@ __global__ __launch_bounds__(kWideThreads) void k_pair_bwd(Src src, const oceans
     double g_sphi = 0.0, g_ssa = 0.0;
     float gmax = 0.0f;
     const int q_first = b_lo >> 2, q_last = (b_hi - 1) >> 2;
+    // COL_REGS: the thread's four columns' E_j and phi_j^2 E_j, and per column
+    // the sum of dL/dI~ R_i rho over the thread's rows
+    double ecol[4] = {0.0, 0.0, 0.0, 0.0}, pecol[4] = {0.0, 0.0, 0.0, 0.0}, scol[4] = {0.0, 0.0, 0.0, 0.0};
+    if (COL_REGS && add_adj) {
+        const int j0 = (int)(((long long)(q_first + tid) << 2) % f.n_az);
+#pragma unroll
+        for (int w = 0; w < 4; ++w) {
+            const float phi = bin_azimuth(f, (j0 + w) % f.n_az);
+            const float E = expf(-(phi * phi) * ctx.inv_sigma_phi);
+            ecol[w] = (double)E;
+            pecol[w] = (double)E * ((double)phi * (double)phi);
+        }
+    }
     for (int q = q_first + tid; q <= q_last; q += NT) {
         const int b0 = q << 2;
         bool in[4];
@@ -1342,7 +1359,23 @@ __global__ __launch_bounds__(kWideThreads) void k_pair_bwd(Src src, const oceans
             const float a = __builtin_fabsf(g[w]);
             if (a <= 3.4028235e38f && a > gmax) gmax = a;
         }
-        if (add_adj) {
+        if (add_adj && COL_REGS) {
+            const Words wd = philox((uint32_t)q, f.frame_id, 0u, 0u, f.seed_lo, f.seed_hi);
+            int i = b0 / f.n_az;
+            int j = b0 - i * f.n_az;
+            float R = range_ramp(f, i);
+#pragma unroll
+            for (int w = 0; w < 4; ++w) {
+                if (in[w]) {
+                    const float rho = rayleigh_of_word(pick(wd, (uint32_t)w));
+                    scol[w] += (double)g[w] * (double)R * (double)rho;
+                }
+                if (++j == f.n_az) {
+                    j = 0;
+                    R = range_ramp(f, ++i);
+                }
+            }
+        } else if (add_adj) {
             const Words wd = philox((uint32_t)q, f.frame_id, 0u, 0u, f.seed_lo, f.seed_hi);
             int i = b0 / f.n_az;
             int j = b0 - i * f.n_az;
@@ -1361,6 +1394,14 @@ __global__ __launch_bounds__(kWideThreads) void k_pair_bwd(Src src, const oceans
                     ++i;
                 }
             }
+        }
+    }
+    if (COL_REGS && add_adj) {
+        // d add / d sigma_sa = sum 0.5 g R E rho, d add / d sigma_phi = sum g R E rho dsphi phi^2
+#pragma unroll
+        for (int w = 0; w < 4; ++w) {
+            g_ssa += 0.5 * ecol[w] * scol[w];
+            g_sphi += dsphi * pecol[w] * scol[w];
         }
     }
 #pragma unroll
@@ -1922,9 +1963,14 @@ static hipError_t launch_bwd(const Src &src, int n_frames, const SonarGrid &g,
             if (e != hipSuccess) return e;
         }
         if (g.tile_blocks > 0) {
-            OSIM_LAUNCH("k_pair_bwd", (k_pair_bwd<Src>), dim3(g.tile_blocks), dim3(kWideThreads),
-                        (size_t)g.max_tile_bins * 4, st, src, params, refl, n_mat, part, g.fant_blocks, n_slots,
-                        refl_part, g.tile_blocks);
+            if (g.wide_col_regs)
+                OSIM_LAUNCH("k_pair_bwd", (k_pair_bwd<Src, true>), dim3(g.tile_blocks), dim3(kWideThreads),
+                            (size_t)g.max_tile_bins * 4, st, src, params, refl, n_mat, part, g.fant_blocks, n_slots,
+                            refl_part, g.tile_blocks);
+            else
+                OSIM_LAUNCH("k_pair_bwd", (k_pair_bwd<Src, false>), dim3(g.tile_blocks), dim3(kWideThreads),
+                            (size_t)g.max_tile_bins * 4, st, src, params, refl, n_mat, part, g.fant_blocks, n_slots,
+                            refl_part, g.tile_blocks);
             e = hipGetLastError();
             if (e != hipSuccess) return e;
         }

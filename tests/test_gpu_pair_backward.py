@@ -100,6 +100,31 @@ def test_pair_backward_mixed_batch(mode):
     _check(frames, refl, gpol, gfan, out[0], "mixed batch mode %d" % mode)
 
 
+@pytest.mark.parametrize("mode", [W.SPECKLE_PAPER, W.SPECKLE_GAMMA])
+def test_pair_backward_columns_dividing_2048(mode):
+    """Every frame's azimuth count divides 2048, so the pair backward keeps
+    each thread's four columns' beam-pattern factors in registers: 64, 256,
+    2 and 1 columns (groups of four bins spanning rows), without fans (the
+    additive adjoint runs in the pair backward) and one with a fan."""
+    _say("pair backward: azimuth counts dividing 2048, speckle mode %d" % mode)
+    st = W.Stream(9300 + mode, 1)
+    specs = [_spec(150, 64, mode=mode, frame_id=0), _spec(40, 256, mode=mode, frame_id=1),
+             _spec(333, 2, mode=mode, frame_id=2), _spec(97, 1, mode=mode, frame_id=3),
+             _spec(64, 128, 48, 96, mode=mode, frame_id=4)]
+    frames = [W.SonarFrame(s, W.make_hits(st, s, n, n_materials=13, outside_frac=0.05))
+              for s, n in zip(specs, [7000, 9000, 800, 300, 5000])]
+    refl = frames[0].hits.refl
+    for f in frames:
+        f.hits.refl = refl
+    gpol, gfan = _losses(frames, 9310 + mode)
+    out, polars = _run(frames, refl, gpol, gfan, reps=2)
+    assert np.array_equal(out[1][0], out[0][0]) and np.array_equal(out[1][1], out[0][1])
+    for f, p in zip(frames, polars):
+        want = oracle.sonar_forward(SonarConfig.from_spec(f.spec), f.hits, refl)
+        assert_image_close(p, want["out"], "polar")
+    _check(frames, refl, gpol, gfan, out[0], "columns dividing 2048, mode %d" % mode)
+
+
 def test_pair_backward_bound_edges():
     """Negative attenuation (intensities grow with range), signed and zero
     reflectivities (the cos x attenuation factor, not the intensity, carries
