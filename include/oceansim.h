@@ -516,10 +516,12 @@ enum {
  * (bins), so order the two on one stream.  In a backward plan a frame's
  * grad_fan needs its fan output (OCEANSIM_E_INVALID_ARG otherwise).
  *
- * OCEANSIM_PLAN_AUTOTUNE times the forward launch for a small set of tile
- * and chunk sizes (and, with a backward, the backward for 1, 2 and 4
- * operator rows per thread) and keeps the fastest whose outputs agree with
- * the default shape's (1e-5 relative); results are cached per process and,
+ * OCEANSIM_PLAN_AUTOTUNE times the forward launch (with the plan's camera
+ * frames carried along, and, when the backward runs from the forward's
+ * material pairs, together with that backward) for a small set of tile and
+ * chunk sizes, then, with a fan backward, 1, 2 and 4 operator rows per
+ * thread, and keeps the fastest whose outputs agree with the default shape's
+ * (1e-5 relative); results are cached per process and,
  * when the environment variable OCEANSIM_TUNE_CACHE names a file, in that
  * JSON file, keyed by GPU architecture, CU count and a size class of the
  * batch.  Tuning runs the launches, so it reads the inputs (which must hold

@@ -256,13 +256,13 @@ double time_us(F fn, hipStream_t st) {
     }
     fn();
     (void)hipEventRecord(a, st);
-    for (int k = 0; k < 3; ++k) fn();
+    for (int k = 0; k < 5; ++k) fn();
     (void)hipEventRecord(b, st);
     float ms = 1e30f;
     if (hipEventSynchronize(b) == hipSuccess) (void)hipEventElapsedTime(&ms, a, b);
     (void)hipEventDestroy(a);
     (void)hipEventDestroy(b);
-    return ms * 1e3 / 3.0;
+    return ms * 1e3 / 5.0;
 }
 
 void attach_fan_transposes(const oceansim_plan *p, SonarPlan &P);
@@ -315,12 +315,34 @@ int autotune(oceansim_plan *p, hipStream_t st) {
     char *tmp = nullptr, *tmp_b = nullptr;
     float *ref = nullptr;
     unsigned *bad = nullptr;
+    // with camera frames the forward carries them along (in the binning or
+    // the tile launch, by shape), so candidates are timed with them
+    UwDev *uw_table = nullptr;
+    UwCompanion uwc;
+    if (p->fused && p->uf.blocks > 0) {
+        hipError_t ue = hipMalloc((void **)&uw_table, sizeof(UwDev) * p->uf.dev.size());
+        if (ue == hipSuccess)
+            ue = hipMemcpyAsync(uw_table, p->uf.dev.data(), sizeof(UwDev) * p->uf.dev.size(), hipMemcpyHostToDevice,
+                                st);
+        if (ue != hipSuccess) {
+            if (uw_table) (void)hipFree(uw_table);
+            return hip_fail(ue, "autotune camera table");
+        }
+        uwc.table = uw_table;
+        uwc.n = (int)p->camera.size();
+        uwc.blocks = p->uf.blocks;
+        uwc.params = p->wp;
+    }
     hipError_t e = hipMalloc(&tmp, ws + 256);
-    if (e != hipSuccess) return hip_fail(e, "autotune workspace");
+    if (e != hipSuccess) {
+        if (uw_table) (void)hipFree(uw_table);
+        return hip_fail(e, "autotune workspace");
+    }
     if (with_bwd) {
         e = hipMalloc(&tmp_b, wsb_pair + 256);
         if (e != hipSuccess) {
             (void)hipFree(tmp);
+            if (uw_table) (void)hipFree(uw_table);
             return hip_fail(e, "autotune workspace");
         }
     }
@@ -330,6 +352,7 @@ int autotune(oceansim_plan *p, hipStream_t st) {
         (void)hipFree(tmp);
         if (tmp_b) (void)hipFree(tmp_b);
         if (ref) (void)hipFree(ref);
+        if (uw_table) (void)hipFree(uw_table);
         return hip_fail(e, "autotune buffers");
     }
     auto copy_outputs = [&](bool to_ref) -> hipError_t {
@@ -367,7 +390,9 @@ int autotune(oceansim_plan *p, hipStream_t st) {
             e = upload_table(c.b.dev, tmp_b, c.b.off_table, st);
             table_b = reinterpret_cast<const SonarDev *>(tmp_b + c.b.off_table);
         }
-        auto fwd = [&]() { return sonar_forward_table(table, n, c.f.grid, p->sp, p->refl, p->n_mat, st); };
+        auto fwd = [&]() {
+            return sonar_forward_table(table, n, c.f.grid, p->sp, p->refl, p->n_mat, st, uw_table ? &uwc : nullptr);
+        };
         auto run = [&]() {
             hipError_t r = fwd();
             if (r == hipSuccess && table_b)
@@ -479,6 +504,7 @@ int autotune(oceansim_plan *p, hipStream_t st) {
     if (tmp_b) (void)hipFree(tmp_b);
     (void)hipFree(ref);
     (void)hipFree(bad);
+    if (uw_table) (void)hipFree(uw_table);
     if (rc) return rc;
     p->tune = chosen;
     std::lock_guard<std::mutex> lk(g_tune_mu);
