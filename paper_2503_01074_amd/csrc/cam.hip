@@ -7,7 +7,8 @@
 // moves as dwords (RGB: three per four pixels, RGBA: one dwordx4), planar
 // float images as float4 when the plane size is a multiple of four, depth
 // always as float4.  Decoding is one LDS table lookup per channel; encoding
-// is an 8-step binary search over 255 LDS thresholds that reproduce the
+// takes a first-guess code from the float's exponent and top mantissa bits
+// and one comparison with the next of 255 LDS thresholds that reproduce the
 // double-precision rounding decision exactly (srgb_tables.hpp), so no power
 // function runs on the GPU.  Up to kCamBatch frames travel by value in the
 // kernel arguments: no workspace, no table upload.
@@ -146,11 +147,19 @@ __global__ __launch_bounds__(kCamBlock) void k_cam_cond(CamBatch B) {
     }
 }
 
+static_assert(kSrgbGuessSpan == 1 && kSrgbGuessN % 4 == 0, "one threshold comparison after the guess");
+
 __global__ __launch_bounds__(kCamBlock) void k_cam_encode(OutBatch B) {
-    __shared__ float thr[256];
+    __shared__ float thr[257];                      // thr[256] = +inf: the guess may be 255
+    __shared__ uint32_t guess_w[kSrgbGuessN / 4];   // the first-guess codes, four per word
     const OutDev f = frame_of<OutBatch, OutDev>(B);
     thr[threadIdx.x] = kSrgbThreshold[threadIdx.x];
+    if (threadIdx.x == 0) thr[256] = __builtin_inff();
+    for (int k = threadIdx.x; k < kSrgbGuessN / 4; k += kCamBlock)
+        guess_w[k] = (uint32_t)kSrgbGuess[4 * k] | (uint32_t)kSrgbGuess[4 * k + 1] << 8 |
+                     (uint32_t)kSrgbGuess[4 * k + 2] << 16 | (uint32_t)kSrgbGuess[4 * k + 3] << 24;
     __syncthreads();
+    const unsigned char *guess = reinterpret_cast<const unsigned char *>(guess_w);
     const unsigned p = ((unsigned)(blockIdx.x - f.block0) * kCamBlock + threadIdx.x) * kPix;
     if (p >= f.hw) return;
     const bool full = f.hw - p >= (unsigned)kPix;
@@ -169,11 +178,15 @@ __global__ __launch_bounds__(kCamBlock) void k_cam_encode(OutBatch B) {
         }
 #pragma unroll
         for (int k = 0; k < kPix; ++k) {
-            // the number of thresholds x reaches; NaN reaches none
-            unsigned q = 0;
-#pragma unroll
-            for (unsigned s = 128; s > 0; s >>= 1) q += x[k] >= thr[q + s] ? s : 0u;
-            c[k][ch] = q;
+            // the number of thresholds x reaches (NaN reaches none): below
+            // 2^-13 none, from 1 on all 255; between, the code of x's bucket
+            // (exponent and top seven mantissa bits) and one more comparison
+            const float xv = x[k];
+            int idx = (int)(__float_as_uint(xv) >> 16) - (kSrgbGuessE0 << 7);
+            idx = idx < 0 ? 0 : (idx > kSrgbGuessN - 1 ? kSrgbGuessN - 1 : idx);
+            unsigned q = guess[idx];
+            q += xv >= thr[q + 1] ? 1u : 0u;
+            c[k][ch] = xv >= 1.0f ? 255u : (xv >= 0x1p-13f ? q : 0u);
         }
     }
     if (full && f.ch == 3) {

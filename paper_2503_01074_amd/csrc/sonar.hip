@@ -343,10 +343,12 @@ __device__ __forceinline__ void tile_fwd_block(const Src &src, const oceansim_so
     float ereg[4] = {0.0f, 0.0f, 0.0f, 0.0f};
     if (speckle) {
         if (COL_REGS) {
-            const int j0 = (int)(((long long)(q_first + tid) << 2) % f.n_az);
+            // n_az divides 4 NT, a power of two: the column of bin b is b & (n_az - 1)
+            const int am = f.n_az - 1;
+            const int j0 = ((q_first + tid) << 2) & am;
 #pragma unroll
             for (int w = 0; w < 4; ++w) {
-                const float phi = bin_azimuth(f, (j0 + w) % f.n_az);
+                const float phi = bin_azimuth(f, (j0 + w) & am);
                 ereg[w] = expf(-(phi * phi) * ctx.inv_sigma_phi);
             }
         } else {
@@ -1324,10 +1326,12 @@ __global__ __launch_bounds__(kWideThreads) void k_pair_bwd(Src src, const oceans
     // the sum of dL/dI~ R_i rho over the thread's rows
     double ecol[4] = {0.0, 0.0, 0.0, 0.0}, pecol[4] = {0.0, 0.0, 0.0, 0.0}, scol[4] = {0.0, 0.0, 0.0, 0.0};
     if (COL_REGS && add_adj) {
-        const int j0 = (int)(((long long)(q_first + tid) << 2) % f.n_az);
+        // n_az divides 4 kWideThreads, a power of two: the column of bin b is b & (n_az - 1)
+        const int am = f.n_az - 1;
+        const int j0 = ((q_first + tid) << 2) & am;
 #pragma unroll
         for (int w = 0; w < 4; ++w) {
-            const float phi = bin_azimuth(f, (j0 + w) % f.n_az);
+            const float phi = bin_azimuth(f, (j0 + w) & am);
             const float E = expf(-(phi * phi) * ctx.inv_sigma_phi);
             ecol[w] = (double)E;
             pecol[w] = (double)E * ((double)phi * (double)phi);
