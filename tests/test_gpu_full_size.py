@@ -250,3 +250,83 @@ def test_calibration_shape_plan(shape, monkeypatch):
         got = plan.shape()
         assert got["fwd_tile_bins"] == tb and got["chunk"] == ch, got
     plan.close()
+
+
+def test_calibration_batch_64_frames(monkeypatch):
+    """The benchmark's calibration-scale batch itself: 64 sonar frames of 2M
+    returns (2048 x 2048 bins, 64 materials, gamma speckle) and 64 1920 x 1080
+    camera frames through one backward plan in the benchmark's launch shape
+    (8192-bin tiles, 8192-return chunks).  As in the benchmark, four distinct
+    return sets and images are each used by 16 frames with distinct frame ids
+    (so distinct speckle).  Checked: two sonar frames' bins and polar images
+    and two camera images against the oracle; the gradients against the sum of
+    the gradients of eight plans of eight of these frames each (same frames,
+    frame ids, losses and shape), which the eight-frame calibration-shape test
+    holds to the oracle: the gradient is a sum over frames, and each frame's
+    per-tile fixed-point sums and per-block camera sums are the same numbers
+    in both, so only the final FP64 sums' grouping and the float32 outputs
+    differ (1e-6 of the magnitudes of the eight partial gradients)."""
+    import dataclasses
+    import torch
+    import paper_2503_01074_amd as osm
+    monkeypatch.setenv("OCEANSIM_PLAN_SHAPE", "8192,8192")
+    _say("calibration batch: 64 sonar frames of 2M returns + 64 camera frames 1080p, the benchmark's shape")
+    base = W.sonar_c5(n_frames=4)
+    st = W.Stream(W.BASE_SEED + 4, 1 << 21)
+    water = W.make_water(st)
+    cams4 = [W.make_camera(W.Stream(W.BASE_SEED + 4, (1 << 22) + k), 1080, 1920) for k in range(4)]
+    refl = base[0].hits.refl
+    hits4 = [osm.DeviceHits.from_host(f.hits) for f in base]
+    J4 = [torch.as_tensor(c.J).cuda() for c in cams4]
+    d4 = [torch.as_tensor(c.depth).cuda() for c in cams4]
+    gpol4 = [torch.as_tensor(W.loss_weights((205, k), (2048, 2048))).cuda() for k in range(4)]
+    gout4 = [torch.as_tensor(W.loss_weights((206, k), (3, 1080, 1920))).cuda() for k in range(4)]
+    params = osm.sonar_params([osm.sonar_params_from_spec(base[0].spec)])
+    refl_d = torch.as_tensor(refl).cuda()
+    wt = osm.water_params([(water.beta_d, water.beta_b, water.b_inf)])
+    specs = [dataclasses.replace(base[k % 4].spec, frame_id=k) for k in range(64)]
+
+    def run(ks):
+        sonar = [(osm.SonarGeometry.from_spec(specs[k], param_row=0), hits4[k % 4]) for k in ks]
+        cam = [(J4[k % 4], d4[k % 4], 0) for k in ks]
+        plan = osm.Plan(sonar, cam, sonar_params=params, refl=refl_d, water=wt, backward=True, bins=True)
+        shape = plan.shape()
+        assert shape["fwd_tile_bins"] == 8192 and shape["chunk"] == 8192, shape
+        for o, k in zip(plan.sonar_out, ks):
+            o["grad_polar"].copy_(gpol4[k % 4])
+        for o, k in zip(plan.camera_out, ks):
+            o["grad_out"].copy_(gout4[k % 4])
+        plan.forward()
+        plan.backward()
+        torch.cuda.synchronize()
+        return plan
+
+    plan = run(list(range(64)))
+    for k in (0, 37):
+        o = plan.sonar_out[k]
+        want = oracle.sonar_forward(SonarConfig.from_spec(specs[k]), base[k % 4].hits, refl)
+        np.testing.assert_array_equal(o["bins"].cpu().numpy(), want["bins"], err_msg="bins %d" % k)
+        assert_image_close(o["polar"].cpu().numpy(), want["out"], "64-frame batch polar %d" % k)
+    for k in (5, 62):
+        c = cams4[k % 4]
+        want = oracle.uw_forward(c.J, c.depth, water.beta_d, water.beta_b, water.b_inf)
+        assert_image_close(plan.camera_out[k]["out"].cpu().numpy(), want, "64-frame batch camera %d" % k)
+    g64 = [plan.grad_refl.cpu().numpy().astype(np.float64), plan.grad_sonar_params.cpu().numpy()[0, :5].astype(
+        np.float64), plan.grad_water.cpu().numpy()[0].astype(np.float64)]
+    plan.close()
+    del plan
+    torch.cuda.empty_cache()
+    acc = [np.zeros_like(g) for g in g64]
+    mag = [np.zeros_like(g) for g in g64]
+    for part in range(8):
+        p8 = run(list(range(8 * part, 8 * part + 8)))
+        g8 = [p8.grad_refl.cpu().numpy().astype(np.float64), p8.grad_sonar_params.cpu().numpy()[0, :5].astype(
+            np.float64), p8.grad_water.cpu().numpy()[0].astype(np.float64)]
+        p8.close()
+        for a, m, g in zip(acc, mag, g8):
+            a += g
+            m += np.abs(g)
+    for name, a, m, g in zip(("refl", "sonar params", "water"), acc, mag, g64):
+        assert np.all(np.isfinite(g)), name
+        err = np.abs(g - a)
+        assert np.all(err <= 1e-6 * m + 1e-30), "%s: %s" % (name, np.max(err / np.maximum(m, 1e-30)))
