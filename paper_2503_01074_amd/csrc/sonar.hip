@@ -73,6 +73,7 @@ __device__ __forceinline__ void bin_block(const Src &src, const oceansim_sonar_p
 
     const float alpha = params[f.param_row].alpha;
     const long long base = (long long)local * (R * NT);
+    const float inv_tb = 1.0f / (float)f.tile_bins;
 
     for (int t = tid; t <= n_tiles; t += NT) hist[t] = 0;
     __syncthreads();
@@ -135,9 +136,19 @@ __device__ __forceinline__ void bin_block(const Src &src, const oceansim_sonar_p
                 inten[q] = return_intensity(f, xs[u], ys[u], zs[u], nxs[u], nys[u], nzs[u], rs[u],
                                             matp ? 1.0f : rfs[u], alpha, cosg, att);
                 rr[q] = (float)rs[u];
-                const int i = b / f.n_az;
-                const int t = i / f.rows_per_tile;
-                lbin[q] = (uint32_t)(b - t * f.tile_bins) | (matp ? (uint32_t)ms[u] << 16 : 0u);
+                // tile t = b / tile_bins by a float reciprocal (b < 2^24 and
+                // b / tile_bins < 2^12, so the product is within 2^-11 of the
+                // quotient and one correction step makes it exact)
+                int t = (int)((float)b * inv_tb);
+                int lb = b - t * f.tile_bins;
+                if (lb < 0) {
+                    --t;
+                    lb += f.tile_bins;
+                } else if (lb >= f.tile_bins) {
+                    ++t;
+                    lb -= f.tile_bins;
+                }
+                lbin[q] = (uint32_t)lb | (matp ? (uint32_t)ms[u] << 16 : 0u);
                 trk[q] = (t << 14) | atomicAdd(&hist[t], 1);
             }
         }
