@@ -234,6 +234,7 @@ int plan_sonar(const oceansim_sonar_frame *frames, int n_frames, int n_param_row
         d.fan_blocks = (!backward && fan_out) ? (fr.fan_h + kFanTileV - 1) / kFanTileV * d.fan_bpr : 0;
         d.speckle = fr.speckle_mode;
         d.gamma_k = fr.gamma_k;
+        d.inv_gamma_k = fr.gamma_k > 0 ? 1.0f / (float)fr.gamma_k : 1.0f;
         d.param_row = fr.param_row;
         d.seed_lo = fr.seed_lo;
         d.seed_hi = fr.seed_hi;

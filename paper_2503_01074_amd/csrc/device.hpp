@@ -91,6 +91,7 @@ struct SonarDev {
     int ret_chunk, n_ret_chunks;// returns per backward-gather workgroup, workgroups
     int fan_bpr, fan_blocks;    // fan: workgroup columns (kFanTileU pairs each), workgroups
     int speckle, gamma_k, param_row;
+    float inv_gamma_k;          // 1 / gamma_k
     unsigned seed_lo, seed_hi, frame_id;
     int blk[KIND_COUNT];        // first global workgroup of this frame, per kernel kind
     double r_min, r_max;        // polar grid [r_min, r_max)
@@ -243,7 +244,7 @@ __device__ __forceinline__ float rayleigh_of_word(uint32_t w) {
 }
 
 // Multiplicative speckle factor of bin b and, in PAPER mode, its standard
-// normal draw (Eq. 5-6).  GAMMA: -(1/k) sum ln u_w (a unit-mean Gamma(k, 1/k)).
+// normal draw (Eq. 5-6).  GAMMA: -(1/k) ln prod u_w (a unit-mean Gamma(k, 1/k)).
 __device__ __forceinline__ float speckle_factor(const SonarDev &f, uint32_t b, float sigma_sm,
                                                 float *gauss_out) {
     if (f.speckle == SPECKLE_PAPER) {
@@ -256,18 +257,22 @@ __device__ __forceinline__ float speckle_factor(const SonarDev &f, uint32_t b, f
         return 0.5f + sigma_sm * g;
     }
     if (f.speckle == SPECKLE_GAMMA) {
+        // -ln of the product of each group's (up to four) uniforms: the
+        // uniforms are at least 2^-24, so a group's product is at least
+        // 2^-96, a normal float, and one logarithm serves four draws
         *gauss_out = 0.0f;
         float acc = 0.0f;
         int k = f.gamma_k;
         for (int g = 0; 4 * g < k; ++g) {
             Words w = philox(b, f.frame_id, 2u, (uint32_t)g, f.seed_lo, f.seed_hi);
             int left = k - 4 * g;
-            acc += neg_ln(unit_uniform(w.w0));
-            if (left > 1) acc += neg_ln(unit_uniform(w.w1));
-            if (left > 2) acc += neg_ln(unit_uniform(w.w2));
-            if (left > 3) acc += neg_ln(unit_uniform(w.w3));
+            float prod = unit_uniform(w.w0);
+            if (left > 1) prod *= unit_uniform(w.w1);
+            if (left > 2) prod *= unit_uniform(w.w2);
+            if (left > 3) prod *= unit_uniform(w.w3);
+            acc += neg_ln(prod);
         }
-        return acc / (float)k;
+        return acc * f.inv_gamma_k;
     }
     *gauss_out = 0.0f;
     return 1.0f;
