@@ -270,7 +270,10 @@ __device__ __forceinline__ void for_tile_pairs(const SonarDev &f, int tile, int 
                 int cc = 0;
 #pragma unroll
                 for (int s = NT / 2; s > 0; s >>= 1) cc += seg_end[cc + s - 1] <= k ? s : 0;
-                const long long idx = (long long)(c0 + cc) * f.chunk + seg_start[cc] + k;
+                // below 2^31 (the frame's returns): chunk index and size are
+                // below 2^24, so a 24-bit product gives the chunk's base
+                const uint32_t idx = (uint32_t)__umul24((unsigned)(c0 + cc), (unsigned)f.chunk) +
+                                     (uint32_t)(seg_start[cc] + k);
                 q[u] = gload(f.pairs + idx);
                 rv[u] = WITH_R ? f.pair_r[idx] : 0.0f;
             }
@@ -381,9 +384,20 @@ __device__ __forceinline__ void tile_fwd_block(const Src &src, const oceansim_so
 
     // additive term of Eq. (3)-(4) for the group of four consecutive
     // frame-linear bins starting at 4q (one Philox call)
+    const bool row_groups = COL_REGS && f.n_az >= 4;   // a group lies in one row, whose index is b >> az_shift
+    const int az_shift = __builtin_ctz((unsigned)f.n_az);
     auto additive_group = [&](int q, float (&add)[4]) __attribute__((always_inline)) {
         const int b0 = q << 2;
         const Words wd = philox((uint32_t)q, f.frame_id, 0u, 0u, f.seed_lo, f.seed_hi);
+        if (row_groups) {
+            const float R = range_ramp(f, b0 >> az_shift);
+#pragma unroll
+            for (int w = 0; w < 4; ++w) {
+                const float rho = rayleigh_of_word(pick(wd, (uint32_t)w));
+                add[w] = R * (1.0f + 0.5f * ereg[w] * (ctx.sigma_sa * rho));
+            }
+            return;
+        }
         int i = b0 / f.n_az;
         int j = b0 - i * f.n_az;
         float R = range_ramp(f, i);
@@ -1333,6 +1347,8 @@ __global__ __launch_bounds__(kWideThreads) void k_pair_bwd(Src src, const oceans
     double g_sphi = 0.0, g_ssa = 0.0;
     float gmax = 0.0f;
     const int q_first = b_lo >> 2, q_last = (b_hi - 1) >> 2;
+    const bool row_groups = f.n_az >= 4;   // with COL_REGS: a group of four bins lies in row b >> az_shift
+    const int az_shift = __builtin_ctz((unsigned)f.n_az);
     // COL_REGS: the thread's four columns' E_j and phi_j^2 E_j, and per column
     // the sum of dL/dI~ R_i rho over the thread's rows
     double ecol[4] = {0.0, 0.0, 0.0, 0.0}, pecol[4] = {0.0, 0.0, 0.0, 0.0}, scol[4] = {0.0, 0.0, 0.0, 0.0};
@@ -1374,7 +1390,17 @@ __global__ __launch_bounds__(kWideThreads) void k_pair_bwd(Src src, const oceans
             const float a = __builtin_fabsf(g[w]);
             if (a <= 3.4028235e38f && a > gmax) gmax = a;
         }
-        if (add_adj && COL_REGS) {
+        if (add_adj && COL_REGS && row_groups) {
+            // the group lies in one row
+            const Words wd = philox((uint32_t)q, f.frame_id, 0u, 0u, f.seed_lo, f.seed_hi);
+            const double R = (double)range_ramp(f, b0 >> az_shift);
+#pragma unroll
+            for (int w = 0; w < 4; ++w)
+                if (in[w]) {
+                    const float rho = rayleigh_of_word(pick(wd, (uint32_t)w));
+                    scol[w] += (double)g[w] * R * (double)rho;
+                }
+        } else if (add_adj && COL_REGS) {
             const Words wd = philox((uint32_t)q, f.frame_id, 0u, 0u, f.seed_lo, f.seed_hi);
             int i = b0 / f.n_az;
             int j = b0 - i * f.n_az;
