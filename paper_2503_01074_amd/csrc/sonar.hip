@@ -229,19 +229,20 @@ __device__ __forceinline__ void write_fan_column(const SonarDev &f, int j) {
     cd[2 * j + 1] = cs;
 }
 
-constexpr int kTileLoads = 4;   // pair gathers in flight per thread of a tile
+constexpr int kTileLoads = 8;      // pair gathers in flight per thread of a forward tile
+constexpr int kPairBwdLoads = 4;   // ... of a pair backward tile (more would cost occupancy)
 
 // Visits the pairs of polar tile `tile` of frame f: its segment in every
 // binning chunk, for NT chunks at a time, flattened so that every thread
-// takes pairs (independent loads) whatever the segment lengths, kTileLoads
-// per thread per round (each pair's segment found by a branch-free binary
+// takes pairs (independent loads) whatever the segment lengths, LOADS per
+// thread per round (each pair's segment found by a branch-free binary
 // search of the LDS prefix; indices past the end re-read the last pair and
 // are not visited).  fn(pair, range):
 // WITH_R loads the pair's range from f.pair_r with the pair (else 0).  pre()
 // runs once, after the first offset loads are issued and before they are
 // used: independent arithmetic placed there overlaps their latency.
 // Contains barriers.
-template <int NT, bool WITH_R, class Fn, class Pre>
+template <int NT, int LOADS, bool WITH_R, class Fn, class Pre>
 __device__ __forceinline__ void for_tile_pairs(const SonarDev &f, int tile, int *seg_end, int *seg_start, int *wtot,
                                                Fn fn, Pre pre) {
     const int tid = threadIdx.x;
@@ -260,11 +261,11 @@ __device__ __forceinline__ void for_tile_pairs(const SonarDev &f, int tile, int 
         seg_end[tid] = incl;
         seg_start[tid] = s0 - (incl - len);   // pair index = seg_start[c] + flat index
         __syncthreads();
-        for (int k0 = 0; k0 < total; k0 += NT * kTileLoads) {
-            uint2 q[kTileLoads];
-            float rv[kTileLoads];
+        for (int k0 = 0; k0 < total; k0 += NT * LOADS) {
+            uint2 q[LOADS];
+            float rv[LOADS];
 #pragma unroll
-            for (int u = 0; u < kTileLoads; ++u) {
+            for (int u = 0; u < LOADS; ++u) {
                 const int k = min(k0 + u * NT + tid, total - 1);
                 // the segment holding flat index k: first c with seg_end[c] > k
                 int cc = 0;
@@ -278,7 +279,7 @@ __device__ __forceinline__ void for_tile_pairs(const SonarDev &f, int tile, int 
                 rv[u] = WITH_R ? f.pair_r[idx] : 0.0f;
             }
 #pragma unroll
-            for (int u = 0; u < kTileLoads; ++u)
+            for (int u = 0; u < LOADS; ++u)
                 if (k0 + u * NT + tid < total) fn(q[u], rv[u]);
         }
         __syncthreads();
@@ -416,7 +417,7 @@ __device__ __forceinline__ void tile_fwd_block(const Src &src, const oceansim_so
     // binning by summation of the tile's pairs (and, for a pair backward, the
     // largest |cos x attenuation| among them)
     float cemax = 0.0f;
-    for_tile_pairs<NT, false>(
+    for_tile_pairs<NT, kTileLoads, false>(
         f, tile, seg_end, seg_start, wtot,
         [&](uint2 q, float) __attribute__((always_inline)) {
             const uint32_t lb = matp ? (q.x & 0xffffu) : q.x;
@@ -1490,7 +1491,7 @@ __global__ __launch_bounds__(kWideThreads) void k_pair_bwd(Src src, const oceans
     bool bad_a = !__builtin_isfinite(B_alpha), bad_g = !__builtin_isfinite(B_gain);
     bool bad_s = paper && !__builtin_isfinite(B_ssm);
     const double neg_kappa = -f.kappa;
-    for_tile_pairs<NT, true>(f, tile, seg_end, seg_start, wtot, [&](uint2 pq, float r) __attribute__((always_inline)) {
+    for_tile_pairs<NT, kPairBwdLoads, true>(f, tile, seg_end, seg_start, wtot, [&](uint2 pq, float r) __attribute__((always_inline)) {
         const uint32_t lb = pq.x & 0xffffu;
         const int m = (int)(pq.x >> 16);
         if (lb >= (uint32_t)(b_hi - b_lo) || m >= n_mat) return;
