@@ -204,14 +204,20 @@ __device__ __forceinline__ int Table<UwDev>::locate(int b, int, int &local) cons
 // --------------------------------------------------------------------------
 struct Words { uint32_t w0, w1, w2, w3; };
 
+// a ^ b ^ c in one instruction (gfx950's three-input bit operation with the
+// odd-parity truth table)
+__device__ __forceinline__ uint32_t xor3(uint32_t a, uint32_t b, uint32_t c) {
+    return __builtin_amdgcn_bitop3_b32(a, b, c, 0x96);
+}
+
 __device__ __forceinline__ Words philox(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
                                         uint32_t k0, uint32_t k1) {
 #pragma unroll
     for (int round = 0; round < 10; ++round) {
         uint64_t a = (uint64_t)c0 * 0xD2511F53u;
         uint64_t b = (uint64_t)c2 * 0xCD9E8D57u;
-        uint32_t n0 = (uint32_t)(b >> 32) ^ c1 ^ k0;
-        uint32_t n2 = (uint32_t)(a >> 32) ^ c3 ^ k1;
+        uint32_t n0 = xor3((uint32_t)(b >> 32), c1, k0);
+        uint32_t n2 = xor3((uint32_t)(a >> 32), c3, k1);
         c1 = (uint32_t)b;
         c3 = (uint32_t)a;
         c0 = n0;

@@ -1303,7 +1303,7 @@ __device__ __forceinline__ int fixed_exponent(double bound, long long n) {
 // computed once, and the additive adjoint sums g R rho per column, weighted by
 // the column's factors at the end.
 template <class Src, bool COL_REGS>
-__global__ __launch_bounds__(kWideThreads) void k_pair_bwd(Src src, const oceansim_sonar_params *params,
+__global__ __launch_bounds__(kWideThreads) __attribute__((amdgpu_waves_per_eu(6))) void k_pair_bwd(Src src, const oceansim_sonar_params *params,
                                                            const float *refl, int n_mat, double *part,
                                                            int slot_base, int n_slots, double *refl_part,
                                                            int n_refl_slots) {
