@@ -268,9 +268,14 @@ __device__ __forceinline__ void for_tile_pairs(const SonarDev &f, int tile, int 
             for (int u = 0; u < LOADS; ++u) {
                 const int k = min(k0 + u * NT + tid, total - 1);
                 // the segment holding flat index k: first c with seg_end[c] > k
-                int cc = 0;
+                // (searched in byte offsets, which the LDS reads take directly)
+                uint32_t cb = 0;
 #pragma unroll
-                for (int s = NT / 2; s > 0; s >>= 1) cc += seg_end[cc + s - 1] <= k ? s : 0;
+                for (int s = NT / 2; s > 0; s >>= 1) {
+                    const int e = *(const int *)((const char *)seg_end + cb + 4u * (uint32_t)(s - 1));
+                    cb += e <= k ? 4u * (uint32_t)s : 0u;
+                }
+                const int cc = (int)(cb >> 2);
                 // below 2^31 (the frame's returns): chunk index and size are
                 // below 2^24, so a 24-bit product gives the chunk's base
                 const uint32_t idx = (uint32_t)__umul24((unsigned)(c0 + cc), (unsigned)f.chunk) +
