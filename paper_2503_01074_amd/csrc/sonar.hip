@@ -548,6 +548,14 @@ __device__ __forceinline__ float polar_at(gptr<const float> base, int idx) {
     return *(gptr<const float>)((gptr<const char>)base + (uint32_t)idx * 4u);
 }
 
+// Elements idx and idx + 1 of a polar image (same row) in one load: a pair of
+// floats whose address is 4-byte aligned.
+typedef float f32x2_a4_t __attribute__((ext_vector_type(2), aligned(4)));
+__device__ __forceinline__ float2 polar_pair_at(gptr<const float> base, int idx) {
+    const f32x2_a4_t v = *(gptr<const f32x2_a4_t>)((gptr<const char>)base + (uint32_t)idx * 4u);
+    return make_float2(v.x, v.y);
+}
+
 // IMAGE = false: the stencil records alone (geometry only; the polar image is
 // not read and the fan is not written).
 template <class Src, bool IMAGE = true>
@@ -647,14 +655,24 @@ __global__ __launch_bounds__(kBlock) void k_fan(Src src) {
             for (int k = 0; k < 8; ++k) a[r][k] = 0.0f;
             continue;
         }
-        a[r][0] = polar_at(polar, b0 + jL[r]);
-        a[r][1] = polar_at(polar, b0 + jL[r] + col1);
-        a[r][2] = polar_at(polar, b1 + jL[r]);
-        a[r][3] = polar_at(polar, b1 + jL[r] + col1);
-        a[r][4] = polar_at(polar, b0 + jr);
-        a[r][5] = polar_at(polar, b0 + jr + col1);
-        a[r][6] = polar_at(polar, b1 + jr);
-        a[r][7] = polar_at(polar, b1 + jr + col1);
+        if (col1) {
+            // the two columns of each row are adjacent: one load per row and pixel
+            const float2 p0 = polar_pair_at(polar, b0 + jL[r]), p1 = polar_pair_at(polar, b1 + jL[r]);
+            const float2 p2 = polar_pair_at(polar, b0 + jr), p3 = polar_pair_at(polar, b1 + jr);
+            a[r][0] = p0.x;
+            a[r][1] = p0.y;
+            a[r][2] = p1.x;
+            a[r][3] = p1.y;
+            a[r][4] = p2.x;
+            a[r][5] = p2.y;
+            a[r][6] = p3.x;
+            a[r][7] = p3.y;
+        } else {
+            a[r][0] = a[r][1] = polar_at(polar, b0 + jL[r]);
+            a[r][2] = a[r][3] = polar_at(polar, b1 + jL[r]);
+            a[r][4] = a[r][5] = polar_at(polar, b0 + jr);
+            a[r][6] = a[r][7] = polar_at(polar, b1 + jr);
+        }
     }
     gptr<float> row = fan + (long long)v0 * f.fan_w;
     gptr<int4> rec = f.stencil ? f.stencil + (long long)v0 * f.half_w + u : nullptr;
