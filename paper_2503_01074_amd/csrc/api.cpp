@@ -396,6 +396,13 @@ int plan_uw(const oceansim_uw_frame *frames, int n_frames, int n_param_rows, boo
     if (n_param_rows < 1) return fail(OCEANSIM_E_INVALID_ARG, "n_param_rows must be >= 1");
     P.dev.assign(n_frames, UwDev{});
     int blocks = 0;
+    // forward: pixels per thread from the batch's size (the same for all frames)
+    long long total_px = 0;
+    for (int i = 0; i < n_frames; ++i)
+        if (frames[i].H > 0 && frames[i].W > 0) total_px += (long long)frames[i].H * frames[i].W;
+    int fwd_px = kUwFwdMinPixelsPerThread;
+    while (fwd_px < kUwFwdMaxPixelsPerThread && total_px / ((long long)threads * fwd_px * 2) >= kUwFwdMinBlocks)
+        fwd_px *= 2;
     for (int i = 0; i < n_frames; ++i) {
         const oceansim_uw_frame &fr = frames[i];
         if (fr.H < 1 || fr.W < 1) return fail(OCEANSIM_E_SHAPE, "camera frame %d: H and W must be >= 1", i);
@@ -421,7 +428,8 @@ int plan_uw(const oceansim_uw_frame *frames, int n_frames, int n_param_rows, boo
         d.grad_depth = gcast(fr.grad_depth);
         d.npix = npix;
         d.param_row = fr.param_row;
-        const long long ppb = (long long)threads * (backward ? kUwBwdPixelsPerThread : kUwFwdPixelsPerThread);
+        d.fwd_px = fwd_px;
+        const long long ppb = (long long)threads * (backward ? kUwBwdPixelsPerThread : fwd_px);
         d.n_blocks = (int)((npix + ppb - 1) / ppb);
         d.blk = blocks;
         blocks += d.n_blocks;

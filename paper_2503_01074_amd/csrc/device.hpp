@@ -140,6 +140,7 @@ struct UwDev {
     int param_row;
     int blk;                    // first global workgroup
     int n_blocks;
+    int fwd_px;                 // forward: pixels per thread (4, 8, 16 or 32; the same for every frame of a launch)
 };
 
 // Workgroups are dispatched to the XCDs round-robin (workgroup b to XCD

@@ -133,10 +133,15 @@ hipError_t sonar_backward_table(const SonarDev *t, int n, const SonarGrid &g,
 
 // Camera pixels per thread: one float4 group forward, two backward (the
 // per-workgroup parameter partial sums amortised over 8 pixels).
-constexpr int kUwFwdPixelsPerThread = 4;
+// Camera forward: pixels per thread, 4 for small batches, doubled up to 32
+// while the batch still gives every CU at least kUwFwdMinBlocks / 256
+// workgroups (fewer, longer workgroups: at calibration scale the fused tile
+// and camera launch went from 1890 to 1535 us going from 4 to 32)
+constexpr int kUwFwdMinPixelsPerThread = 4;
+constexpr int kUwFwdMaxPixelsPerThread = 32;
+constexpr long long kUwFwdMinBlocks = 4096;
 constexpr int kUwBwdPixelsPerThread = 8;
 constexpr int kUwBwdLoadsInFlight = 2;
-constexpr int kUwFwdPixelsPerBlock = kBlock * kUwFwdPixelsPerThread;
 constexpr int kUwBwdPixelsPerBlock = kBlock * kUwBwdPixelsPerThread;
 
 hipError_t uw_forward_one(const UwDev &f, int blocks, const oceansim_water_params *params, hipStream_t st);

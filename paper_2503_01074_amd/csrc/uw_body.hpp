@@ -67,10 +67,43 @@ __device__ __forceinline__ float uw_pixel(float J, float d, float bd, float bb, 
     return J * T + bi * S1;
 }
 
+// The full-size camera block body: KIT float4 groups per thread from pixel
+// p0 on, two groups' loads in flight at a time.
+template <int NT, int KIT>
+__device__ __forceinline__ void uw_fwd_groups(gptr<const float> __restrict__ Jp, gptr<const float> __restrict__ Dp,
+                                              gptr<float> __restrict__ Op, long long npix, long long p0, int tx,
+                                              const Water &w) {
+    constexpr int KH = KIT < 2 ? KIT : 2;
+#pragma unroll
+    for (int i0 = 0; i0 < KIT; i0 += KH) {
+        float4 d[KH], J[KH][3];
+#pragma unroll
+        for (int h = 0; h < KH; ++h) {
+            const long long p = p0 + ((long long)(i0 + h) * NT + tx) * 4;
+            d[h] = gload((gptr<const float4>)(Dp + p));
+#pragma unroll
+            for (int c = 0; c < 3; ++c) J[h][c] = gload((gptr<const float4>)(Jp + c * npix + p));
+        }
+#pragma unroll
+        for (int h = 0; h < KH; ++h) {
+            const long long p = p0 + ((long long)(i0 + h) * NT + tx) * 4;
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                float4 o;
+                o.x = uw_pixel(J[h][c].x, d[h].x, w.bd[c], w.bb[c], w.bi[c]);
+                o.y = uw_pixel(J[h][c].y, d[h].y, w.bd[c], w.bb[c], w.bi[c]);
+                o.z = uw_pixel(J[h][c].z, d[h].z, w.bd[c], w.bb[c], w.bi[c]);
+                o.w = uw_pixel(J[h][c].w, d[h].w, w.bd[c], w.bb[c], w.bi[c]);
+                gstore_stream((gptr<float4>)(Op + c * npix + p), o);
+            }
+        }
+    }
+}
+
 // Workgroup `bid` (of NT threads, this thread being `tx` of them) of a
-// forward launch over the frames of src: kUwFwdPixelsPerThread pixels per
-// thread, as float4 groups.  No barrier: a wider workgroup may run several
-// of these blocks side by side.
+// forward launch over the frames of src: f.fwd_px pixels per thread (4, 8,
+// 16 or 32, the same for every frame of the launch), as float4 groups.  No
+// barrier: a wider workgroup may run several of these blocks side by side.
 template <class Src, int NT>
 __device__ __forceinline__ void uw_fwd_block(const Src &src, const oceansim_water_params *params, int bid,
                                              int tx) {
@@ -79,39 +112,24 @@ __device__ __forceinline__ void uw_fwd_block(const Src &src, const oceansim_wate
     const UwDev f = src.frame(fi);
     const Water w = load_water(params, f.param_row);
     const long long npix = f.npix;
-    const long long p0 = (long long)local * (NT * kUwFwdPixelsPerThread);
+    const int px = f.fwd_px;
+    const long long p0 = (long long)local * NT * px;
     // restrict-qualified views (the output never aliases the inputs), so the
-    // loads of every iteration can be in flight before the first store
+    // loads of a group can be in flight before the previous group's stores
     const gptr<const float> __restrict__ Jp = f.J;
     const gptr<const float> __restrict__ Dp = f.depth;
     const gptr<float> __restrict__ Op = f.out;
-    constexpr int kIt = (NT * kUwFwdPixelsPerThread) / (NT * 4);
-    if ((npix & 3) == 0 && p0 + (NT * kUwFwdPixelsPerThread) <= npix) {
-        float4 d[kIt], J[kIt][3];
-#pragma unroll
-        for (int it = 0; it < kIt; ++it) {
-            const long long p = p0 + ((long long)it * NT + tx) * 4;
-            d[it] = gload((gptr<const float4>)(Dp + p));
-#pragma unroll
-            for (int c = 0; c < 3; ++c) J[it][c] = gload((gptr<const float4>)(Jp + c * npix + p));
-        }
-#pragma unroll
-        for (int it = 0; it < kIt; ++it) {
-            const long long p = p0 + ((long long)it * NT + tx) * 4;
-#pragma unroll
-            for (int c = 0; c < 3; ++c) {
-                float4 o;
-                o.x = uw_pixel(J[it][c].x, d[it].x, w.bd[c], w.bb[c], w.bi[c]);
-                o.y = uw_pixel(J[it][c].y, d[it].y, w.bd[c], w.bb[c], w.bi[c]);
-                o.z = uw_pixel(J[it][c].z, d[it].z, w.bd[c], w.bb[c], w.bi[c]);
-                o.w = uw_pixel(J[it][c].w, d[it].w, w.bd[c], w.bb[c], w.bi[c]);
-                gstore_stream((gptr<float4>)(Op + c * npix + p), o);
-            }
+    if ((npix & 3) == 0 && p0 + (long long)NT * px <= npix) {
+        switch (px) {
+            case 32: uw_fwd_groups<NT, 8>(Jp, Dp, Op, npix, p0, tx, w); break;
+            case 16: uw_fwd_groups<NT, 4>(Jp, Dp, Op, npix, p0, tx, w); break;
+            case 8: uw_fwd_groups<NT, 2>(Jp, Dp, Op, npix, p0, tx, w); break;
+            default: uw_fwd_groups<NT, 1>(Jp, Dp, Op, npix, p0, tx, w); break;
         }
         return;
     }
     // ragged tail (or an image whose size is not a multiple of 4): per pixel
-    for (int it = 0; it < kIt; ++it) {
+    for (int it = 0; it < px / 4; ++it) {
         const long long p = p0 + ((long long)it * NT + tx) * 4;
         for (long long q = p; q < p + 4 && q < npix; ++q) {
             const float d = Dp[q];
