@@ -396,13 +396,15 @@ int plan_uw(const oceansim_uw_frame *frames, int n_frames, int n_param_rows, boo
     if (n_param_rows < 1) return fail(OCEANSIM_E_INVALID_ARG, "n_param_rows must be >= 1");
     P.dev.assign(n_frames, UwDev{});
     int blocks = 0;
-    // forward: pixels per thread from the batch's size (the same for all frames)
+    // pixels per thread from the batch's size (the same for all frames)
     long long total_px = 0;
     for (int i = 0; i < n_frames; ++i)
         if (frames[i].H > 0 && frames[i].W > 0) total_px += (long long)frames[i].H * frames[i].W;
-    int fwd_px = kUwFwdMinPixelsPerThread;
-    while (fwd_px < kUwFwdMaxPixelsPerThread && total_px / ((long long)threads * fwd_px * 2) >= kUwFwdMinBlocks)
+    int fwd_px = kUwFwdMinPixelsPerThread, bwd_px = kUwBwdMinPixelsPerThread;
+    while (fwd_px < kUwFwdMaxPixelsPerThread && total_px / ((long long)threads * fwd_px * 2) >= kUwMinBlocks)
         fwd_px *= 2;
+    while (bwd_px < kUwBwdMaxPixelsPerThread && total_px / ((long long)threads * bwd_px * 2) >= kUwMinBlocks)
+        bwd_px *= 2;
     for (int i = 0; i < n_frames; ++i) {
         const oceansim_uw_frame &fr = frames[i];
         if (fr.H < 1 || fr.W < 1) return fail(OCEANSIM_E_SHAPE, "camera frame %d: H and W must be >= 1", i);
@@ -429,7 +431,8 @@ int plan_uw(const oceansim_uw_frame *frames, int n_frames, int n_param_rows, boo
         d.npix = npix;
         d.param_row = fr.param_row;
         d.fwd_px = fwd_px;
-        const long long ppb = (long long)threads * (backward ? kUwBwdPixelsPerThread : fwd_px);
+        d.bwd_px = bwd_px;
+        const long long ppb = (long long)threads * (backward ? bwd_px : fwd_px);
         d.n_blocks = (int)((npix + ppb - 1) / ppb);
         d.blk = blocks;
         blocks += d.n_blocks;

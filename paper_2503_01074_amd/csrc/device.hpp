@@ -141,6 +141,7 @@ struct UwDev {
     int blk;                    // first global workgroup
     int n_blocks;
     int fwd_px;                 // forward: pixels per thread (4, 8, 16 or 32; the same for every frame of a launch)
+    int bwd_px;                 // backward: pixels per thread (8, 16, 32 or 64; likewise)
 };
 
 // Workgroups are dispatched to the XCDs round-robin (workgroup b to XCD
@@ -559,9 +560,12 @@ __device__ __forceinline__ double block_sum(double v, double *sh) {
 
 // N sums over a workgroup with one barrier pair: the same fixed order per
 // sum as block_sum.  `sh` holds N * NT / 64 doubles; thread k < N returns sum k.
+// tx: the thread's index among the NT threads summed (a wider workgroup may
+// run several such groups side by side, each with its own `sh`; every thread
+// of the workgroup must call it, since it contains workgroup barriers).
 template <int N, int NT = kBlock>
-__device__ __forceinline__ double block_sum_n(const double (&v)[N], double *sh) {
-    const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
+__device__ __forceinline__ double block_sum_n(const double (&v)[N], double *sh, int tx) {
+    const int lane = tx & (kWave - 1), wid = tx / kWave;
     __syncthreads();
 #pragma unroll
     for (int k = 0; k < N; ++k) {
@@ -570,9 +574,13 @@ __device__ __forceinline__ double block_sum_n(const double (&v)[N], double *sh) 
     }
     __syncthreads();
     double s = 0.0;
-    if (threadIdx.x < N)
-        for (int k = 0; k < NT / kWave; ++k) s += sh[threadIdx.x * (NT / kWave) + k];
+    if (tx < N)
+        for (int k = 0; k < NT / kWave; ++k) s += sh[tx * (NT / kWave) + k];
     return s;
+}
+template <int N, int NT = kBlock>
+__device__ __forceinline__ double block_sum_n(const double (&v)[N], double *sh) {
+    return block_sum_n<N, NT>(v, sh, (int)threadIdx.x);
 }
 
 // This thread's share of sum_{k < n} get(k) over a workgroup of NT threads

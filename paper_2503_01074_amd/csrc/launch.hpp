@@ -131,18 +131,19 @@ hipError_t sonar_backward_table(const SonarDev *t, int n, const SonarGrid &g,
                                 float *grad_refl, hipStream_t st, SonarReduce *defer = nullptr,
                                 const UwBwdCompanion *uwb = nullptr);
 
-// Camera pixels per thread: one float4 group forward, two backward (the
-// per-workgroup parameter partial sums amortised over 8 pixels).
-// Camera forward: pixels per thread, 4 for small batches, doubled up to 32
-// while the batch still gives every CU at least kUwFwdMinBlocks / 256
-// workgroups (fewer, longer workgroups: at calibration scale the fused tile
-// and camera launch went from 1890 to 1535 us going from 4 to 32)
+// Camera pixels per thread, chosen per launch from the batch's size: the
+// smallest count for small batches, doubled up to the largest while every CU
+// still gets kUwMinBlocks / 256 workgroups.  Fewer, longer workgroups pay
+// where camera workgroups share a launch with sonar tiles, since each holds
+// the tiles' LDS while it waits on memory (at calibration scale the fused
+// tile and camera launch went from 1890 to 1570 us going from 4 to 32
+// pixels per thread).  The backward's per-workgroup partial sums are
+// amortised over at least 8 pixels per thread.
 constexpr int kUwFwdMinPixelsPerThread = 4;
 constexpr int kUwFwdMaxPixelsPerThread = 32;
-constexpr long long kUwFwdMinBlocks = 4096;
-constexpr int kUwBwdPixelsPerThread = 8;
-constexpr int kUwBwdLoadsInFlight = 2;
-constexpr int kUwBwdPixelsPerBlock = kBlock * kUwBwdPixelsPerThread;
+constexpr int kUwBwdMinPixelsPerThread = 8;
+constexpr int kUwBwdMaxPixelsPerThread = 32;
+constexpr long long kUwMinBlocks = 4096;
 
 hipError_t uw_forward_one(const UwDev &f, int blocks, const oceansim_water_params *params, hipStream_t st);
 hipError_t uw_forward_table(const UwDev *t, int n, int blocks, const oceansim_water_params *params,

@@ -268,14 +268,9 @@ __device__ __forceinline__ void for_tile_pairs(const SonarDev &f, int tile, int 
             for (int u = 0; u < LOADS; ++u) {
                 const int k = min(k0 + u * NT + tid, total - 1);
                 // the segment holding flat index k: first c with seg_end[c] > k
-                // (searched in byte offsets, which the LDS reads take directly)
-                uint32_t cb = 0;
+                int cc = 0;
 #pragma unroll
-                for (int s = NT / 2; s > 0; s >>= 1) {
-                    const int e = *(const int *)((const char *)seg_end + cb + 4u * (uint32_t)(s - 1));
-                    cb += e <= k ? 4u * (uint32_t)s : 0u;
-                }
-                const int cc = (int)(cb >> 2);
+                for (int s = NT / 2; s > 0; s >>= 1) cc += seg_end[cc + s - 1] <= k ? s : 0;
                 // below 2^31 (the frame's returns): chunk index and size are
                 // below 2^24, so a 24-bit product gives the chunk's base
                 const uint32_t idx = (uint32_t)__umul24((unsigned)(c0 + cc), (unsigned)f.chunk) +
@@ -1326,10 +1321,9 @@ __device__ __forceinline__ int fixed_exponent(double bound, long long n) {
 // computed once, and the additive adjoint sums g R rho per column, weighted by
 // the column's factors at the end.
 template <class Src, bool COL_REGS>
-__global__ __launch_bounds__(kWideThreads) __attribute__((amdgpu_waves_per_eu(6))) void k_pair_bwd(Src src, const oceansim_sonar_params *params,
-                                                           const float *refl, int n_mat, double *part,
-                                                           int slot_base, int n_slots, double *refl_part,
-                                                           int n_refl_slots) {
+__device__ __forceinline__ void pair_bwd_block(const Src &src, const oceansim_sonar_params *params,
+                                               const float *refl, int n_mat, double *part, int slot_base,
+                                               int n_slots, double *refl_part, int n_refl_slots, int bid) {
     constexpr int NT = kWideThreads;
     constexpr int NW = NT / kWave;
     extern __shared__ int4 lds_raw[];
@@ -1342,7 +1336,6 @@ __global__ __launch_bounds__(kWideThreads) __attribute__((amdgpu_waves_per_eu(6)
     __shared__ double dred[2 * NW];
     __shared__ unsigned bad_any;
     int tile;
-    const int bid = blockIdx.x;
     const int fi = src.locate(bid, KTILE, tile);
     const SonarDev f = src.frame(fi);
     const int tid = threadIdx.x, lane = tid & (kWave - 1), wave = tid / kWave;
@@ -1580,6 +1573,46 @@ __global__ __launch_bounds__(kWideThreads) __attribute__((amdgpu_waves_per_eu(6)
     for (int m = tid; m < n_mat; m += NT) {
         const bool pm = !refl_ok || ((rbad >> m) & 1ull);
         refl_part[(long long)m * n_refl_slots + bid] = pm ? __builtin_nan("") : (double)(long long)racc[m] / s_refl;
+    }
+}
+
+// Held to six waves per SIMD (80 VGPRs) so that three workgroups fit per CU.
+template <class Src, bool COL_REGS>
+__global__ __launch_bounds__(kWideThreads) __attribute__((amdgpu_waves_per_eu(6))) void k_pair_bwd(
+    Src src, const oceansim_sonar_params *params, const float *refl, int n_mat, double *part, int slot_base,
+    int n_slots, double *refl_part, int n_refl_slots) {
+    pair_bwd_block<Src, COL_REGS>(src, params, refl, n_mat, part, slot_base, n_slots, refl_part, n_refl_slots,
+                                  blockIdx.x);
+}
+
+// k_pair_uw_bwd (plans with camera frames): the pair backward tiles and the
+// camera backward in one launch, interleaved through the dispatch order as in
+// k_tile_uw (workgroup x is a camera one when floor((x+1) C / N) >
+// floor(x C / N)), so the VALU-bound tiles and the HBM-bound camera share
+// every CU.  A camera workgroup runs two camera blocks of kBlock threads side
+// by side, one channel's loads in flight at a time (within the tiles'
+// register budget).
+template <class Src, bool COL_REGS>
+__global__ __launch_bounds__(kWideThreads) __attribute__((amdgpu_waves_per_eu(6))) void k_pair_uw_bwd(
+    Src src, const oceansim_sonar_params *params, const float *refl, int n_mat, double *part, int slot_base,
+    int n_slots, double *refl_part, int n_tile_blocks, int n_cam_groups, UwBwdCompanion uw) {
+    static_assert(kWideThreads == 2 * kBlock, "two camera blocks per wide workgroup");
+    const long long x = blockIdx.x;
+    const long long n = (long long)n_tile_blocks + n_cam_groups;
+    const int c_before = (int)(x * n_cam_groups / n);
+    const int c_upto = (int)((x + 1) * n_cam_groups / n);
+    if (c_upto > c_before) {
+        __shared__ double red9[2 * 9 * (kBlock / kWave)];
+        // the same in every lane of a wave: scalar, so the camera frame's
+        // fields load into scalar registers
+        const int half = __builtin_amdgcn_readfirstlane(threadIdx.x >= kBlock ? 1 : 0);
+        const int cb = __builtin_amdgcn_readfirstlane(2 * c_before + half);
+        uw_bwd_block<Table<UwDev>, kBlock, true>(Table<UwDev>{uw.table, uw.n}, uw.params, uw.part, uw.part_row, cb,
+                                                 uw.blocks, red9 + half * 9 * (kBlock / kWave),
+                                                 (int)(threadIdx.x & (kBlock - 1)), cb < uw.blocks);
+    } else {
+        pair_bwd_block<Src, COL_REGS>(src, params, refl, n_mat, part, slot_base, n_slots, refl_part, n_tile_blocks,
+                                      (int)(x - c_before));
     }
 }
 
@@ -2027,21 +2060,39 @@ static hipError_t launch_bwd(const Src &src, int n_frames, const SonarGrid &g,
             e = hipGetLastError();
             if (e != hipSuccess) return e;
         }
-        if (g.tile_blocks > 0) {
+        const bool with_uw = uwb && uwb->blocks > 0;
+        const int groups = with_uw ? (uwb->blocks + 1) / 2 : 0;
+        if (g.tile_blocks > 0 && with_uw && g.tile_blocks >= groups) {
+            // the camera backward interleaved with the pair workgroups, where
+            // these are enough to hide it (the camera part keeps one
+            // channel's loads in flight, slower on its own)
             if (g.wide_col_regs)
-                OSIM_LAUNCH("k_pair_bwd", (k_pair_bwd<Src, true>), dim3(g.tile_blocks), dim3(kWideThreads),
-                            (size_t)g.max_tile_bins * 4, st, src, params, refl, n_mat, part, g.fant_blocks, n_slots,
-                            refl_part, g.tile_blocks);
+                OSIM_LAUNCH("k_pair_uw_bwd", (k_pair_uw_bwd<Src, true>), dim3(g.tile_blocks + groups),
+                            dim3(kWideThreads), (size_t)g.max_tile_bins * 4, st, src, params, refl, n_mat, part,
+                            g.fant_blocks, n_slots, refl_part, g.tile_blocks, groups, *uwb);
             else
-                OSIM_LAUNCH("k_pair_bwd", (k_pair_bwd<Src, false>), dim3(g.tile_blocks), dim3(kWideThreads),
-                            (size_t)g.max_tile_bins * 4, st, src, params, refl, n_mat, part, g.fant_blocks, n_slots,
-                            refl_part, g.tile_blocks);
+                OSIM_LAUNCH("k_pair_uw_bwd", (k_pair_uw_bwd<Src, false>), dim3(g.tile_blocks + groups),
+                            dim3(kWideThreads), (size_t)g.max_tile_bins * 4, st, src, params, refl, n_mat, part,
+                            g.fant_blocks, n_slots, refl_part, g.tile_blocks, groups, *uwb);
             e = hipGetLastError();
             if (e != hipSuccess) return e;
-        }
-        if (uwb && uwb->blocks > 0) {
-            e = uw_backward_table(uwb->table, uwb->n, uwb->blocks, uwb->params, uwb->part, uwb->part_row, st);
-            if (e != hipSuccess) return e;
+        } else {
+            if (g.tile_blocks > 0) {
+                if (g.wide_col_regs)
+                    OSIM_LAUNCH("k_pair_bwd", (k_pair_bwd<Src, true>), dim3(g.tile_blocks), dim3(kWideThreads),
+                                (size_t)g.max_tile_bins * 4, st, src, params, refl, n_mat, part, g.fant_blocks,
+                                n_slots, refl_part, g.tile_blocks);
+                else
+                    OSIM_LAUNCH("k_pair_bwd", (k_pair_bwd<Src, false>), dim3(g.tile_blocks), dim3(kWideThreads),
+                                (size_t)g.max_tile_bins * 4, st, src, params, refl, n_mat, part, g.fant_blocks,
+                                n_slots, refl_part, g.tile_blocks);
+                e = hipGetLastError();
+                if (e != hipSuccess) return e;
+            }
+            if (with_uw) {
+                e = uw_backward_table(uwb->table, uwb->n, uwb->blocks, uwb->params, uwb->part, uwb->part_row, st);
+                if (e != hipSuccess) return e;
+            }
         }
         SonarReduce a;
         a.part = part;

@@ -156,89 +156,136 @@ __device__ __forceinline__ float uw_pixel_bwd(float g, float J, float d, float b
     return g * T;
 }
 
-// Workgroup `bid` (of NT threads) of a backward launch: kUwBwdPixelsPerThread
-// pixels per thread; the nine parameter partial sums of the workgroup go to
+// The full-size camera backward block body: KIT float4 groups per thread
+// from pixel p0 on, two groups' loads in flight at a time (for KIT > 2 an
+// empty asm statement taking the running sums as operands ends each pair of
+// groups, so the next pair's loads are not hoisted above it).
+template <int NT, int KIT>
+__device__ __forceinline__ void uw_bwd_groups(gptr<const float> __restrict__ Jp, gptr<const float> __restrict__ Dp,
+                                              gptr<const float> __restrict__ Gp, gptr<float> __restrict__ GJ,
+                                              gptr<float> __restrict__ GD, long long npix, long long p0, int tx,
+                                              const Water &w, float (&acc)[9]) {
+#pragma unroll
+    for (int i0 = 0; i0 < KIT; i0 += 2) {
+        float4 d[2], J[2][3], g[2][3];
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const long long p = p0 + ((long long)(i0 + h) * NT + tx) * 4;
+            d[h] = gload((gptr<const float4>)(Dp + p));
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                J[h][c] = gload((gptr<const float4>)(Jp + c * npix + p));
+                g[h][c] = gload((gptr<const float4>)(Gp + c * npix + p));
+            }
+        }
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const long long p = p0 + ((long long)(i0 + h) * NT + tx) * 4;
+            float4 gdv = make_float4(0.f, 0.f, 0.f, 0.f);
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                float4 gj;
+                gj.x = uw_pixel_bwd(g[h][c].x, J[h][c].x, d[h].x, w.bd[c], w.bb[c], w.bi[c], acc, c, gdv.x);
+                gj.y = uw_pixel_bwd(g[h][c].y, J[h][c].y, d[h].y, w.bd[c], w.bb[c], w.bi[c], acc, c, gdv.y);
+                gj.z = uw_pixel_bwd(g[h][c].z, J[h][c].z, d[h].z, w.bd[c], w.bb[c], w.bi[c], acc, c, gdv.z);
+                gj.w = uw_pixel_bwd(g[h][c].w, J[h][c].w, d[h].w, w.bd[c], w.bb[c], w.bi[c], acc, c, gdv.w);
+                if (GJ) gstore_stream((gptr<float4>)(GJ + c * npix + p), gj);
+            }
+            if (GD) gstore_stream((gptr<float4>)(GD + p), gdv);
+        }
+        if (i0 + 2 < KIT)
+            __asm__ volatile("" : "+v"(acc[0]), "+v"(acc[1]), "+v"(acc[2]), "+v"(acc[3]), "+v"(acc[4]),
+                             "+v"(acc[5]), "+v"(acc[6]), "+v"(acc[7]), "+v"(acc[8])::"memory");
+    }
+}
+
+// Workgroup `bid` (of NT threads, this thread being `tx` of them) of a
+// backward launch: f.bwd_px pixels per thread, as float4 groups: with 8
+// pixels per thread and PINNED = false, both groups' loads in flight
+// together; otherwise one channel of one group at a time (PINNED: the
+// register budget of launches shared with sonar tiles); the nine parameter partial sums of the workgroup go to
 // part[c * n_slots + bid] (FP64, fixed order) and its parameter row to
-// part_row[bid].
-// `red9` is LDS of 9 * NT / 64 doubles.
-template <class Src, int NT>
+// part_row[bid].  `red9` is LDS of 9 * NT / 64 doubles.  Contains workgroup
+// barriers: in a wider workgroup that runs several such blocks side by side,
+// every thread calls it, those of a block past the last with active = false
+// (no pixels, nothing written).
+template <class Src, int NT, bool PINNED = false>
 __device__ __forceinline__ void uw_bwd_block(const Src &src, const oceansim_water_params *params, double *part,
-                                             int *part_row, int bid, int n_slots, double *red9) {
-    int local;
-    const int fi = src.locate(bid, 0, local);
-    const UwDev f = src.frame(fi);
-    const Water w = load_water(params, f.param_row);
-    const long long npix = f.npix;
-    const long long p0 = (long long)local * (NT * kUwBwdPixelsPerThread);
-    const gptr<const float> __restrict__ Jp = f.J;
-    const gptr<const float> __restrict__ Dp = f.depth;
-    const gptr<const float> __restrict__ Gp = f.grad_out;
-    const gptr<float> __restrict__ GJ = f.grad_J;
-    const gptr<float> __restrict__ GD = f.grad_depth;
-    constexpr int kIt = (NT * kUwBwdPixelsPerThread) / (NT * 4);
-    // float4 iterations whose loads are in flight together: one keeps the
-    // kernel near 64 VGPRs (more waves per SIMD hide the HBM latency better
-    // than more loads per wave)
-    constexpr int kH = kUwBwdLoadsInFlight;
-    static_assert(kIt % kH == 0, "iterations must split into groups of kH");
-    // per-thread partial sums of 8 pixels in FP32 (|error| <= ~5e-7 of the sum
-    // of the magnitudes), then FP64 across threads and workgroups
+                                             int *part_row, int bid, int n_slots, double *red9,
+                                             int tx = (int)threadIdx.x, bool active = true) {
+    // per-thread partial sums in FP32 (|error| <= ~5e-7 of the sum of the
+    // magnitudes per group of pixels), then FP64 across threads and workgroups
     float acc[9];
 #pragma unroll
     for (int k = 0; k < 9; ++k) acc[k] = 0.0f;
-    if ((npix & 3) == 0 && p0 + (NT * kUwBwdPixelsPerThread) <= npix) {
+    int row = 0;
+    if (active) {
+        int local;
+        const int fi = src.locate(bid, 0, local);
+        const UwDev f = src.frame(fi);
+        row = f.param_row;
+        const Water w = load_water(params, f.param_row);
+        const long long npix = f.npix;
+        const int px = f.bwd_px;
+        const int n_it = px / 4;   // even
+        const long long p0 = (long long)local * NT * px;
+        const gptr<const float> __restrict__ Jp = f.J;
+        const gptr<const float> __restrict__ Dp = f.depth;
+        const gptr<const float> __restrict__ Gp = f.grad_out;
+        const gptr<float> __restrict__ GJ = f.grad_J;
+        const gptr<float> __restrict__ GD = f.grad_depth;
+        if ((npix & 3) == 0 && p0 + (long long)NT * px <= npix) {
+            if (!PINNED && n_it == 2) {
+                uw_bwd_groups<NT, 2>(Jp, Dp, Gp, GJ, GD, npix, p0, tx, w, acc);
+            } else {
+                // one channel at a time: the empty asm statements take the
+                // running sums as operands, so each channel's arithmetic is
+                // done before the next channel's loads are issued
+#pragma unroll 1
+                for (int it = 0; it < n_it; ++it) {
+                    const long long p = p0 + ((long long)it * NT + tx) * 4;
+                    const float4 d = gload((gptr<const float4>)(Dp + p));
+                    float4 gdv = make_float4(0.f, 0.f, 0.f, 0.f);
 #pragma unroll
-        for (int it = 0; it < kIt; it += kH) {
-            float4 d[kH], J[kH][3], g[kH][3];
-#pragma unroll
-            for (int h = 0; h < kH; ++h) {
-                const long long p = p0 + ((long long)(it + h) * NT + threadIdx.x) * 4;
-                d[h] = gload((gptr<const float4>)(Dp + p));
-#pragma unroll
-                for (int c = 0; c < 3; ++c) {
-                    J[h][c] = gload((gptr<const float4>)(Jp + c * npix + p));
-                    g[h][c] = gload((gptr<const float4>)(Gp + c * npix + p));
+                    for (int c = 0; c < 3; ++c) {
+                        const float4 J = gload((gptr<const float4>)(Jp + c * npix + p));
+                        const float4 g = gload((gptr<const float4>)(Gp + c * npix + p));
+                        float4 gj;
+                        gj.x = uw_pixel_bwd(g.x, J.x, d.x, w.bd[c], w.bb[c], w.bi[c], acc, c, gdv.x);
+                        gj.y = uw_pixel_bwd(g.y, J.y, d.y, w.bd[c], w.bb[c], w.bi[c], acc, c, gdv.y);
+                        gj.z = uw_pixel_bwd(g.z, J.z, d.z, w.bd[c], w.bb[c], w.bi[c], acc, c, gdv.z);
+                        gj.w = uw_pixel_bwd(g.w, J.w, d.w, w.bd[c], w.bb[c], w.bi[c], acc, c, gdv.w);
+                        if (GJ) gstore_stream((gptr<float4>)(GJ + c * npix + p), gj);
+                        __asm__ volatile("" : "+v"(acc[c]), "+v"(acc[3 + c]), "+v"(acc[6 + c]), "+v"(gdv.x),
+                                         "+v"(gdv.y), "+v"(gdv.z), "+v"(gdv.w)::"memory");
+                    }
+                    if (GD) gstore_stream((gptr<float4>)(GD + p), gdv);
                 }
             }
+        } else {
+            // ragged tail (or an image whose size is not a multiple of 4): per pixel
+            for (int it = 0; it < n_it; ++it) {
+                const long long p = p0 + ((long long)it * NT + tx) * 4;
+                for (long long q = p; q < p + 4 && q < npix; ++q) {
+                    const float d = Dp[q];
+                    float gd = 0.0f;
 #pragma unroll
-            for (int h = 0; h < kH; ++h) {
-                const long long p = p0 + ((long long)(it + h) * NT + threadIdx.x) * 4;
-                float4 gdv = make_float4(0.f, 0.f, 0.f, 0.f);
-#pragma unroll
-                for (int c = 0; c < 3; ++c) {
-                    float4 gj;
-                    gj.x = uw_pixel_bwd(g[h][c].x, J[h][c].x, d[h].x, w.bd[c], w.bb[c], w.bi[c], acc, c, gdv.x);
-                    gj.y = uw_pixel_bwd(g[h][c].y, J[h][c].y, d[h].y, w.bd[c], w.bb[c], w.bi[c], acc, c, gdv.y);
-                    gj.z = uw_pixel_bwd(g[h][c].z, J[h][c].z, d[h].z, w.bd[c], w.bb[c], w.bi[c], acc, c, gdv.z);
-                    gj.w = uw_pixel_bwd(g[h][c].w, J[h][c].w, d[h].w, w.bd[c], w.bb[c], w.bi[c], acc, c, gdv.w);
-                    if (GJ) gstore_stream((gptr<float4>)(GJ + c * npix + p), gj);
+                    for (int c = 0; c < 3; ++c) {
+                        const float gj = uw_pixel_bwd(Gp[c * npix + q], Jp[c * npix + q], d, w.bd[c], w.bb[c],
+                                                      w.bi[c], acc, c, gd);
+                        if (GJ) gstore_stream(GJ + c * npix + q, gj);
+                    }
+                    if (GD) gstore_stream(GD + q, gd);
                 }
-                if (GD) gstore_stream((gptr<float4>)(GD + p), gdv);
-            }
-        }
-    } else {
-        // ragged tail (or an image whose size is not a multiple of 4): per pixel
-        for (int it = 0; it < kIt; ++it) {
-            const long long p = p0 + ((long long)it * NT + threadIdx.x) * 4;
-            for (long long q = p; q < p + 4 && q < npix; ++q) {
-                const float d = Dp[q];
-                float gd = 0.0f;
-#pragma unroll
-                for (int c = 0; c < 3; ++c) {
-                    const float gj = uw_pixel_bwd(Gp[c * npix + q], Jp[c * npix + q], d, w.bd[c], w.bb[c],
-                                                  w.bi[c], acc, c, gd);
-                    if (GJ) gstore_stream(GJ + c * npix + q, gj);
-                }
-                if (GD) gstore_stream(GD + q, gd);
             }
         }
     }
     double accd[9];
 #pragma unroll
     for (int k = 0; k < 9; ++k) accd[k] = (double)acc[k];
-    const double tot = block_sum_n<9, NT>(accd, red9);
-    if (threadIdx.x < 9) part[(long long)threadIdx.x * n_slots + bid] = tot;   // column-major partials
-    if (threadIdx.x == 0) part_row[bid] = f.param_row;
+    const double tot = block_sum_n<9, NT>(accd, red9, tx);
+    if (active && tx < 9) part[(long long)tx * n_slots + bid] = tot;   // column-major partials
+    if (active && tx == 0) part_row[bid] = row;
 }
 
 }  // namespace osim
