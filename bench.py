@@ -427,7 +427,8 @@ class CalibrationScale:
         n, nb, npx = self.n_returns, self.n_bins, self.n_px
         per_kernel = {"k_bin": 28 * n, "k_bin_uw": 28 * n + 28 * npx, "k_tile": 4 * nb, "k_uw": 28 * npx,
                       "k_tile_uw": 4 * nb + 28 * npx,
-                      "k_pair_bwd": 4 * nb + 28 * n, "k_fant_bwd": 4 * nb, "k_ret_bwd": 28 * n,
+                      "k_pair_bwd": 4 * nb + 28 * n, "k_pair_uw_bwd": 4 * nb + 28 * n + 28 * npx,
+                      "k_fant_bwd": 4 * nb, "k_ret_bwd": 28 * n,
                       "k_ret_uw_bwd": 28 * n + 28 * npx, "k_uw_bwd": 28 * npx}
         fwd = 28 * n + 4 * nb + 28 * npx
         bwd = 4 * nb + 28 * n + 28 * npx
