@@ -245,16 +245,17 @@ struct Candidate {
     bool ok = false;
 };
 
-// Times `fn` (3 launches after one warm-up) on stream st, in microseconds.
+// Times `fn` (5 launches after `warm` warm-up launches) on stream st, in
+// microseconds.
 template <class F>
-double time_us(F fn, hipStream_t st) {
+double time_us(F fn, hipStream_t st, int warm = 1) {
     hipEvent_t a, b;
     if (hipEventCreate(&a) != hipSuccess) return 1e30;
     if (hipEventCreate(&b) != hipSuccess) {
         (void)hipEventDestroy(a);
         return 1e30;
     }
-    fn();
+    for (int k = 0; k < warm; ++k) fn();
     (void)hipEventRecord(a, st);
     for (int k = 0; k < 5; ++k) fn();
     (void)hipEventRecord(b, st);
@@ -416,7 +417,10 @@ int autotune(oceansim_plan *p, hipStream_t st) {
             break;
         }
         c.ok = nbad == 0;
-        if (c.ok) c.us = time_us(run, st);
+        // the first candidate also brings the GPU to its working clocks: on a
+        // fresh box the first few large launches run up to a quarter slower,
+        // which would favour the candidates timed later
+        if (c.ok) c.us = time_us(run, st, k == 0 ? 10 : 1);
     }
     size_t best = 0;
     for (size_t k = 1; k < cands.size(); ++k)
