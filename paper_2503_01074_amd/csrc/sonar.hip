@@ -527,7 +527,9 @@ __global__ __launch_bounds__(kWideThreads) void k_tile_uw(Src src, const oceansi
     const int c_before = (int)(x * n_cam_groups / n);
     const int c_upto = (int)((x + 1) * n_cam_groups / n);
     if (c_upto > c_before) {
-        const int cb = 2 * c_before + (int)(threadIdx.x >= kBlock);
+        // the same in every lane of a wave: scalar, so the camera frame's
+        // fields load into scalar registers
+        const int cb = __builtin_amdgcn_readfirstlane(2 * c_before + (int)(threadIdx.x >= kBlock));
         if (cb < n_cam_blocks) uw_fwd_block<Table<UwDev>, kBlock>(usrc, wparams, cb, threadIdx.x & (kBlock - 1));
     } else {
         tile_fwd_block<Src, kWideThreads, COL_REGS>(src, params, refl, n_mat, (int)(x - c_before));
