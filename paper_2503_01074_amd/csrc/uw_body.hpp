@@ -140,13 +140,18 @@ __device__ __forceinline__ void uw_fwd_block(const Src &src, const oceansim_wate
     }
 }
 
+// e^x for x <= 0 as the hardware 2^(x log2 e) with the product rounded to
+// float: within about 1e-6 relative over x in [-20, 0], which the adjoint's
+// tolerance leaves room for (the forward image keeps exp_nonpos).
+__device__ __forceinline__ float exp_nonpos_adj(float x) { return __builtin_amdgcn_exp2f(x * 1.44269502f); }
+
 // Adjoint of Eq. (1) at one pixel and channel; accumulates the parameter
 // gradients and returns dL/dJ, adding this channel's share of dL/dd.
 __device__ __forceinline__ float uw_pixel_bwd(float g, float J, float d, float bd, float bb, float bi,
                                               float acc[9], int c, float &gd) {
-    const float T = exp_nonpos(-bdprod(bd, d));
+    const float T = exp_nonpos_adj(-bdprod(bd, d));
     const float xb = bdprod(bb, d);
-    const float S = exp_nonpos(-xb);
+    const float S = exp_nonpos_adj(-xb);
     const float S1 = one_minus_exp_neg(xb, S);
     // the d-weighted terms vanish where T or S does (0 * inf := 0)
     if (T != 0.0f) acc[c] += g * (-J * T * d);
