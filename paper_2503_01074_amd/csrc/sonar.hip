@@ -229,6 +229,11 @@ __device__ __forceinline__ void write_fan_column(const SonarDev &f, int j) {
     cd[2 * j + 1] = cs;
 }
 
+// Consecutive polar tiles of a frame read neighbouring segments of every
+// binning chunk, so the cache line at each segment boundary is shared by two
+// tiles: the tile kernels give each XCD runs of this many consecutive tiles
+// (read through one L2) instead of every eighth tile.
+constexpr int kTileXcdRun = 16;
 constexpr int kTileLoads = 8;      // pair gathers in flight per thread of a forward tile
 constexpr int kPairBwdLoads = 4;   // ... of a pair backward tile (more would cost occupancy)
 
@@ -505,7 +510,7 @@ __device__ __forceinline__ void tile_fwd_block(const Src &src, const oceansim_so
 template <class Src, int NT, bool COL_REGS>
 __global__ __launch_bounds__(NT) void k_tile(Src src, const oceansim_sonar_params *params, const float *refl,
                                              int n_mat) {
-    tile_fwd_block<Src, NT, COL_REGS>(src, params, refl, n_mat, blockIdx.x);
+    tile_fwd_block<Src, NT, COL_REGS>(src, params, refl, n_mat, xcd_grouped_id<kTileXcdRun>(blockIdx.x, gridDim.x));
 }
 
 // k_tile_uw (plans with camera frames and wide tiles): the forward tiles and
@@ -522,7 +527,7 @@ __global__ __launch_bounds__(kWideThreads) void k_tile_uw(Src src, const oceansi
                                                           int n_cam_groups, Table<UwDev> usrc,
                                                           const oceansim_water_params *wparams, int n_cam_blocks) {
     static_assert(kWideThreads == 2 * kBlock, "two camera blocks per wide workgroup");
-    const long long x = blockIdx.x;
+    const long long x = xcd_grouped_id<kTileXcdRun>(blockIdx.x, gridDim.x);
     const long long n = (long long)n_tile_blocks + n_cam_groups;
     const int c_before = (int)(x * n_cam_groups / n);
     const int c_upto = (int)((x + 1) * n_cam_groups / n);
@@ -1584,7 +1589,7 @@ __global__ __launch_bounds__(kWideThreads) __attribute__((amdgpu_waves_per_eu(6)
     Src src, const oceansim_sonar_params *params, const float *refl, int n_mat, double *part, int slot_base,
     int n_slots, double *refl_part, int n_refl_slots) {
     pair_bwd_block<Src, COL_REGS>(src, params, refl, n_mat, part, slot_base, n_slots, refl_part, n_refl_slots,
-                                  blockIdx.x);
+                                  xcd_grouped_id<kTileXcdRun>(blockIdx.x, gridDim.x));
 }
 
 // k_pair_uw_bwd (plans with camera frames): the pair backward tiles and the
@@ -1599,7 +1604,7 @@ __global__ __launch_bounds__(kWideThreads) __attribute__((amdgpu_waves_per_eu(6)
     Src src, const oceansim_sonar_params *params, const float *refl, int n_mat, double *part, int slot_base,
     int n_slots, double *refl_part, int n_tile_blocks, int n_cam_groups, UwBwdCompanion uw) {
     static_assert(kWideThreads == 2 * kBlock, "two camera blocks per wide workgroup");
-    const long long x = blockIdx.x;
+    const long long x = xcd_grouped_id<kTileXcdRun>(blockIdx.x, gridDim.x);
     const long long n = (long long)n_tile_blocks + n_cam_groups;
     const int c_before = (int)(x * n_cam_groups / n);
     const int c_upto = (int)((x + 1) * n_cam_groups / n);
