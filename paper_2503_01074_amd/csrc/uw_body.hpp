@@ -6,6 +6,8 @@
 //   I_c = J_c exp(-beta_D,c d) + B_inf,c (1 - exp(-beta_B,c d))
 #pragma once
 
+#include <type_traits>
+
 #include "device.hpp"
 #include "launch.hpp"
 
@@ -164,8 +166,9 @@ __device__ __forceinline__ float uw_pixel_bwd(float g, float J, float d, float b
 // The full-size camera backward block body: KIT float4 groups per thread
 // from pixel p0 on, two groups' loads in flight at a time (for KIT > 2 an
 // empty asm statement taking the running sums as operands ends each pair of
-// groups, so the next pair's loads are not hoisted above it).
-template <int NT, int KIT>
+// groups, so the next pair's loads are not hoisted above it).  IMG: image
+// gradients are written (GJ or GD set); without, their terms are not formed.
+template <int NT, int KIT, bool IMG>
 __device__ __forceinline__ void uw_bwd_groups(gptr<const float> __restrict__ Jp, gptr<const float> __restrict__ Dp,
                                               gptr<const float> __restrict__ Gp, gptr<float> __restrict__ GJ,
                                               gptr<float> __restrict__ GD, long long npix, long long p0, int tx,
@@ -194,9 +197,9 @@ __device__ __forceinline__ void uw_bwd_groups(gptr<const float> __restrict__ Jp,
                 gj.y = uw_pixel_bwd(g[h][c].y, J[h][c].y, d[h].y, w.bd[c], w.bb[c], w.bi[c], acc, c, gdv.y);
                 gj.z = uw_pixel_bwd(g[h][c].z, J[h][c].z, d[h].z, w.bd[c], w.bb[c], w.bi[c], acc, c, gdv.z);
                 gj.w = uw_pixel_bwd(g[h][c].w, J[h][c].w, d[h].w, w.bd[c], w.bb[c], w.bi[c], acc, c, gdv.w);
-                if (GJ) gstore_stream((gptr<float4>)(GJ + c * npix + p), gj);
+                if (IMG && GJ) gstore_stream((gptr<float4>)(GJ + c * npix + p), gj);
             }
-            if (GD) gstore_stream((gptr<float4>)(GD + p), gdv);
+            if (IMG && GD) gstore_stream((gptr<float4>)(GD + p), gdv);
         }
         if (i0 + 2 < KIT)
             __asm__ volatile("" : "+v"(acc[0]), "+v"(acc[1]), "+v"(acc[2]), "+v"(acc[3]), "+v"(acc[4]),
@@ -240,32 +243,49 @@ __device__ __forceinline__ void uw_bwd_block(const Src &src, const oceansim_wate
         const gptr<float> __restrict__ GJ = f.grad_J;
         const gptr<float> __restrict__ GD = f.grad_depth;
         if ((npix & 3) == 0 && p0 + (long long)NT * px <= npix) {
+            // without image gradients (GJ and GD null) the code is compiled
+            // without them, so their terms are not formed
+            const bool img = GJ || GD;
             if (!PINNED && n_it == 2) {
-                uw_bwd_groups<NT, 2>(Jp, Dp, Gp, GJ, GD, npix, p0, tx, w, acc);
+                if (img)
+                    uw_bwd_groups<NT, 2, true>(Jp, Dp, Gp, GJ, GD, npix, p0, tx, w, acc);
+                else
+                    uw_bwd_groups<NT, 2, false>(Jp, Dp, Gp, GJ, GD, npix, p0, tx, w, acc);
             } else {
                 // one channel at a time: the empty asm statements take the
                 // running sums as operands, so each channel's arithmetic is
                 // done before the next channel's loads are issued
+                auto channels = [&](auto with_img) __attribute__((always_inline)) {
+                    constexpr bool IMG = decltype(with_img)::value;
 #pragma unroll 1
-                for (int it = 0; it < n_it; ++it) {
-                    const long long p = p0 + ((long long)it * NT + tx) * 4;
-                    const float4 d = gload((gptr<const float4>)(Dp + p));
-                    float4 gdv = make_float4(0.f, 0.f, 0.f, 0.f);
+                    for (int it = 0; it < n_it; ++it) {
+                        const long long p = p0 + ((long long)it * NT + tx) * 4;
+                        const float4 d = gload((gptr<const float4>)(Dp + p));
+                        float4 gdv = make_float4(0.f, 0.f, 0.f, 0.f);
 #pragma unroll
-                    for (int c = 0; c < 3; ++c) {
-                        const float4 J = gload((gptr<const float4>)(Jp + c * npix + p));
-                        const float4 g = gload((gptr<const float4>)(Gp + c * npix + p));
-                        float4 gj;
-                        gj.x = uw_pixel_bwd(g.x, J.x, d.x, w.bd[c], w.bb[c], w.bi[c], acc, c, gdv.x);
-                        gj.y = uw_pixel_bwd(g.y, J.y, d.y, w.bd[c], w.bb[c], w.bi[c], acc, c, gdv.y);
-                        gj.z = uw_pixel_bwd(g.z, J.z, d.z, w.bd[c], w.bb[c], w.bi[c], acc, c, gdv.z);
-                        gj.w = uw_pixel_bwd(g.w, J.w, d.w, w.bd[c], w.bb[c], w.bi[c], acc, c, gdv.w);
-                        if (GJ) gstore_stream((gptr<float4>)(GJ + c * npix + p), gj);
-                        __asm__ volatile("" : "+v"(acc[c]), "+v"(acc[3 + c]), "+v"(acc[6 + c]), "+v"(gdv.x),
-                                         "+v"(gdv.y), "+v"(gdv.z), "+v"(gdv.w)::"memory");
+                        for (int c = 0; c < 3; ++c) {
+                            const float4 J = gload((gptr<const float4>)(Jp + c * npix + p));
+                            const float4 g = gload((gptr<const float4>)(Gp + c * npix + p));
+                            float4 gj;
+                            gj.x = uw_pixel_bwd(g.x, J.x, d.x, w.bd[c], w.bb[c], w.bi[c], acc, c, gdv.x);
+                            gj.y = uw_pixel_bwd(g.y, J.y, d.y, w.bd[c], w.bb[c], w.bi[c], acc, c, gdv.y);
+                            gj.z = uw_pixel_bwd(g.z, J.z, d.z, w.bd[c], w.bb[c], w.bi[c], acc, c, gdv.z);
+                            gj.w = uw_pixel_bwd(g.w, J.w, d.w, w.bd[c], w.bb[c], w.bi[c], acc, c, gdv.w);
+                            if (IMG) {
+                                if (GJ) gstore_stream((gptr<float4>)(GJ + c * npix + p), gj);
+                                __asm__ volatile("" : "+v"(acc[c]), "+v"(acc[3 + c]), "+v"(acc[6 + c]), "+v"(gdv.x),
+                                                 "+v"(gdv.y), "+v"(gdv.z), "+v"(gdv.w)::"memory");
+                            } else {
+                                __asm__ volatile("" : "+v"(acc[c]), "+v"(acc[3 + c]), "+v"(acc[6 + c])::"memory");
+                            }
+                        }
+                        if (IMG && GD) gstore_stream((gptr<float4>)(GD + p), gdv);
                     }
-                    if (GD) gstore_stream((gptr<float4>)(GD + p), gdv);
-                }
+                };
+                if (img)
+                    channels(std::true_type{});
+                else
+                    channels(std::false_type{});
             }
         } else {
             // ragged tail (or an image whose size is not a multiple of 4): per pixel
