@@ -152,10 +152,26 @@ struct UwDev {
 // dealt round-robin (so work that varies smoothly with the id stays balanced
 // across XCDs).  A bijection on [0, n); the last partial round keeps b.
 template <int G>
-__device__ __forceinline__ int xcd_grouped_id(int b, int n) {
+__host__ __device__ __forceinline__ int xcd_grouped_id(int b, int n) {
     constexpr int round = kXcds * G;
     if (b >= n / round * round) return b;
     return b / round * round + (b % kXcds) * G + (b / kXcds) % G;
+}
+
+// Launches that interleave n_tile tile workgroups with n_cam camera
+// workgroups evenly through the dispatch order: workgroup x (of n_tile +
+// n_cam) is camera group floor(x C / N) when floor((x + 1) C / N) >
+// floor(x C / N), else tile x - floor(x C / N) (C = n_cam, N = n_tile +
+// n_cam).  Every tile and every camera group is taken exactly once.
+struct FusedSlot {
+    bool cam;
+    int index;
+};
+__host__ __device__ __forceinline__ FusedSlot fused_slot(long long x, int n_tile, int n_cam) {
+    const long long n = (long long)n_tile + n_cam;
+    const int c_before = (int)(x * n_cam / n);
+    const int c_upto = (int)((x + 1) * n_cam / n);
+    return c_upto > c_before ? FusedSlot{true, c_before} : FusedSlot{false, (int)(x - c_before)};
 }
 
 // Frame sources: a single frame passed by value in the kernel arguments, or a

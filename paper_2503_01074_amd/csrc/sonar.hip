@@ -527,17 +527,14 @@ __global__ __launch_bounds__(kWideThreads) void k_tile_uw(Src src, const oceansi
                                                           int n_cam_groups, Table<UwDev> usrc,
                                                           const oceansim_water_params *wparams, int n_cam_blocks) {
     static_assert(kWideThreads == 2 * kBlock, "two camera blocks per wide workgroup");
-    const long long x = xcd_grouped_id<kTileXcdRun>(blockIdx.x, gridDim.x);
-    const long long n = (long long)n_tile_blocks + n_cam_groups;
-    const int c_before = (int)(x * n_cam_groups / n);
-    const int c_upto = (int)((x + 1) * n_cam_groups / n);
-    if (c_upto > c_before) {
+    const FusedSlot slot = fused_slot(xcd_grouped_id<kTileXcdRun>(blockIdx.x, gridDim.x), n_tile_blocks, n_cam_groups);
+    if (slot.cam) {
         // the same in every lane of a wave: scalar, so the camera frame's
         // fields load into scalar registers
-        const int cb = __builtin_amdgcn_readfirstlane(2 * c_before + (int)(threadIdx.x >= kBlock));
+        const int cb = __builtin_amdgcn_readfirstlane(2 * slot.index + (int)(threadIdx.x >= kBlock));
         if (cb < n_cam_blocks) uw_fwd_block<Table<UwDev>, kBlock>(usrc, wparams, cb, threadIdx.x & (kBlock - 1));
     } else {
-        tile_fwd_block<Src, kWideThreads, COL_REGS>(src, params, refl, n_mat, (int)(x - c_before));
+        tile_fwd_block<Src, kWideThreads, COL_REGS>(src, params, refl, n_mat, slot.index);
     }
 }
 
@@ -1604,22 +1601,19 @@ __global__ __launch_bounds__(kWideThreads) __attribute__((amdgpu_waves_per_eu(6)
     Src src, const oceansim_sonar_params *params, const float *refl, int n_mat, double *part, int slot_base,
     int n_slots, double *refl_part, int n_tile_blocks, int n_cam_groups, UwBwdCompanion uw) {
     static_assert(kWideThreads == 2 * kBlock, "two camera blocks per wide workgroup");
-    const long long x = xcd_grouped_id<kTileXcdRun>(blockIdx.x, gridDim.x);
-    const long long n = (long long)n_tile_blocks + n_cam_groups;
-    const int c_before = (int)(x * n_cam_groups / n);
-    const int c_upto = (int)((x + 1) * n_cam_groups / n);
-    if (c_upto > c_before) {
+    const FusedSlot slot = fused_slot(xcd_grouped_id<kTileXcdRun>(blockIdx.x, gridDim.x), n_tile_blocks, n_cam_groups);
+    if (slot.cam) {
         __shared__ double red9[2 * 9 * (kBlock / kWave)];
         // the same in every lane of a wave: scalar, so the camera frame's
         // fields load into scalar registers
         const int half = __builtin_amdgcn_readfirstlane(threadIdx.x >= kBlock ? 1 : 0);
-        const int cb = __builtin_amdgcn_readfirstlane(2 * c_before + half);
+        const int cb = __builtin_amdgcn_readfirstlane(2 * slot.index + half);
         uw_bwd_block<Table<UwDev>, kBlock, true>(Table<UwDev>{uw.table, uw.n}, uw.params, uw.part, uw.part_row, cb,
                                                  uw.blocks, red9 + half * 9 * (kBlock / kWave),
                                                  (int)(threadIdx.x & (kBlock - 1)), cb < uw.blocks);
     } else {
         pair_bwd_block<Src, COL_REGS>(src, params, refl, n_mat, part, slot_base, n_slots, refl_part, n_tile_blocks,
-                                      (int)(x - c_before));
+                                      slot.index);
     }
 }
 
