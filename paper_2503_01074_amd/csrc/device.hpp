@@ -158,6 +158,48 @@ __host__ __device__ __forceinline__ int xcd_grouped_id(int b, int n) {
     return b / round * round + (b % kXcds) * G + (b / kXcds) % G;
 }
 
+// Flat walk over NT segments laid end to end (segment c holds flat indices
+// [seg_end[c - 1], seg_end[c]), seg_end the inclusive prefix of the
+// lengths, total the last entry): a coarse map of 2 NT entries finds the
+// segment of a flat index k without a full binary search.  Entry j holds the
+// segment of flat index j << shift (shift the smallest with (total - 1) >>
+// shift < 2 NT - 1) and entry n_map the segment of the last index; each
+// non-empty segment writes its own entries.
+__host__ __device__ __forceinline__ int seg_map_shift(int total, int map_entries) {
+    int shift = 0;
+    while (((total - 1) >> shift) >= map_entries - 1) ++shift;
+    return shift;
+}
+__host__ __device__ __forceinline__ void seg_map_fill(unsigned short *map, int seg, int excl, int incl, int total,
+                                                      int shift) {
+    if (incl <= excl) return;
+    for (int j = (int)(((long long)excl + (1LL << shift) - 1) >> shift); ((long long)j << shift) < incl; ++j)
+        map[j] = (unsigned short)seg;
+    if (incl == total) map[((total - 1) >> shift) + 1] = (unsigned short)seg;
+}
+// The segment holding flat index k < total: first c with seg_end[c] > k.  It
+// lies between the map's entries around k; three branch-free steps cover
+// eight segments, a loop the rare wider spans (empty segments between).
+template <int NT>
+__host__ __device__ __forceinline__ int seg_find(const int *seg_end, const unsigned short *map, int shift, int k) {
+    const int lo = map[k >> shift], hi = map[(k >> shift) + 1];
+    int cc = lo;
+#pragma unroll
+    for (int s = 4; s > 0; s >>= 1) cc += seg_end[min(cc + s - 1, NT - 1)] <= k ? s : 0;
+    if (hi - lo >= 8) {
+        int a = lo, b = hi;
+        while (a < b) {
+            const int m = (a + b) >> 1;
+            if (seg_end[m] <= k)
+                a = m + 1;
+            else
+                b = m;
+        }
+        cc = a;
+    }
+    return cc;
+}
+
 // Launches that interleave n_tile tile workgroups with n_cam camera
 // workgroups evenly through the dispatch order: workgroup x (of n_tile +
 // n_cam) is camera group floor(x C / N) when floor((x + 1) C / N) >

@@ -240,16 +240,17 @@ constexpr int kPairBwdLoads = 4;   // ... of a pair backward tile (more would co
 // Visits the pairs of polar tile `tile` of frame f: its segment in every
 // binning chunk, for NT chunks at a time, flattened so that every thread
 // takes pairs (independent loads) whatever the segment lengths, LOADS per
-// thread per round (each pair's segment found by a branch-free binary
-// search of the LDS prefix; indices past the end re-read the last pair and
-// are not visited).  fn(pair, range):
+// thread per round (each pair's segment found from a coarse LDS map of the
+// flat range, built with the prefix, and a short search of the prefix;
+// indices past the end re-read the last pair and are not visited).
+// seg_map: LDS of 2 NT entries.  fn(pair, range):
 // WITH_R loads the pair's range from f.pair_r with the pair (else 0).  pre()
 // runs once, after the first offset loads are issued and before they are
 // used: independent arithmetic placed there overlaps their latency.
 // Contains barriers.
 template <int NT, int LOADS, bool WITH_R, class Fn, class Pre>
 __device__ __forceinline__ void for_tile_pairs(const SonarDev &f, int tile, int *seg_end, int *seg_start, int *wtot,
-                                               Fn fn, Pre pre) {
+                                               unsigned short *seg_map, Fn fn, Pre pre) {
     const int tid = threadIdx.x;
     const int stride = f.n_tiles + 1;
     for (int c0 = 0; c0 < f.n_chunks; c0 += NT) {
@@ -265,6 +266,9 @@ __device__ __forceinline__ void for_tile_pairs(const SonarDev &f, int tile, int 
         const int incl = block_inclusive_scan1<NT>(len, wtot, total);
         seg_end[tid] = incl;
         seg_start[tid] = s0 - (incl - len);   // pair index = seg_start[c] + flat index
+        // the coarse segment map of the flat range (shift: the same in every lane)
+        const int shift = seg_map_shift(total, 2 * NT);
+        seg_map_fill(seg_map, tid, incl - len, incl, total, shift);
         __syncthreads();
         for (int k0 = 0; k0 < total; k0 += NT * LOADS) {
             uint2 q[LOADS];
@@ -272,10 +276,7 @@ __device__ __forceinline__ void for_tile_pairs(const SonarDev &f, int tile, int 
 #pragma unroll
             for (int u = 0; u < LOADS; ++u) {
                 const int k = min(k0 + u * NT + tid, total - 1);
-                // the segment holding flat index k: first c with seg_end[c] > k
-                int cc = 0;
-#pragma unroll
-                for (int s = NT / 2; s > 0; s >>= 1) cc += seg_end[cc + s - 1] <= k ? s : 0;
+                const int cc = seg_find<NT>(seg_end, seg_map, shift, k);   // the segment holding k
                 // below 2^31 (the frame's returns): chunk index and size are
                 // below 2^24, so a 24-bit product gives the chunk's base
                 const uint32_t idx = (uint32_t)__umul24((unsigned)(c0 + cc), (unsigned)f.chunk) +
@@ -340,6 +341,7 @@ __device__ __forceinline__ void tile_fwd_block(const Src &src, const oceansim_so
     extern __shared__ int4 lds_raw[];
     constexpr int NW = NT / kWave;
     __shared__ unsigned short queues[NW * 2 * kWave];   // tile-local bins (< kMaxFwdTileBins)
+    static_assert(NW * 2 * kWave >= 2 * NT, "the queues hold the pair walk's segment map");
     static_assert(kMaxFwdTileBins <= 65536, "queue entries are 16-bit");
     __shared__ float refl_s[kLaneHistMats];
     __shared__ int seg_end[NT], seg_start[NT], wtot[NW];
@@ -423,7 +425,7 @@ __device__ __forceinline__ void tile_fwd_block(const Src &src, const oceansim_so
     // largest |cos x attenuation| among them)
     float cemax = 0.0f;
     for_tile_pairs<NT, kTileLoads, false>(
-        f, tile, seg_end, seg_start, wtot,
+        f, tile, seg_end, seg_start, wtot, queues,   // the queues serve as the segment map until the compaction
         [&](uint2 q, float) __attribute__((always_inline)) {
             const uint32_t lb = matp ? (q.x & 0xffffu) : q.x;
             if (lb >= (uint32_t)nbins) return;
@@ -1332,6 +1334,7 @@ __device__ __forceinline__ void pair_bwd_block(const Src &src, const oceansim_so
     constexpr int NW = NT / kWave;
     extern __shared__ int4 lds_raw[];
     __shared__ int seg_end[NT], seg_start[NT], wtot[NW];
+    __shared__ unsigned short seg_map[2 * NT];
     __shared__ float refl_s[kLaneHistMats];
     __shared__ unsigned long long racc[kLaneHistMats];
     __shared__ unsigned long long rbad;
@@ -1511,7 +1514,7 @@ __device__ __forceinline__ void pair_bwd_block(const Src &src, const oceansim_so
     bool bad_a = !__builtin_isfinite(B_alpha), bad_g = !__builtin_isfinite(B_gain);
     bool bad_s = paper && !__builtin_isfinite(B_ssm);
     const double neg_kappa = -f.kappa;
-    for_tile_pairs<NT, kPairBwdLoads, true>(f, tile, seg_end, seg_start, wtot, [&](uint2 pq, float r) __attribute__((always_inline)) {
+    for_tile_pairs<NT, kPairBwdLoads, true>(f, tile, seg_end, seg_start, wtot, seg_map, [&](uint2 pq, float r) __attribute__((always_inline)) {
         const uint32_t lb = pq.x & 0xffffu;
         const int m = (int)(pq.x >> 16);
         if (lb >= (uint32_t)(b_hi - b_lo) || m >= n_mat) return;
