@@ -1528,7 +1528,14 @@ __device__ __forceinline__ void pair_bwd_block(const Src &src, const oceansim_so
         const double xr = gI * (double)ce;
         const double xa = gI * (double)I * (neg_kappa * (double)r);
         const double xg = gq * (double)I;
-        const double xs = paper ? (double)g * (double)G * (double)I * (double)z : 0.0;
+        if (paper) {
+            // the speckle mode is a frame's, the same across the wave: the
+            // empty asm statement keeps this a branch (not computed and
+            // discarded for the other modes)
+            __asm__ volatile("");
+            const double xs = (double)g * (double)G * (double)I * (double)z;
+            if (__builtin_isfinite(xs)) a_ssm += scale_round(xs, s_ssm); else bad_s = true;
+        }
         if (__builtin_isfinite(xr)) {
             const long long v = scale_round(xr, s_refl);
             if (v != 0) atomicAdd(&racc[m], (unsigned long long)v);
@@ -1537,7 +1544,6 @@ __device__ __forceinline__ void pair_bwd_block(const Src &src, const oceansim_so
         }
         if (__builtin_isfinite(xa)) a_alpha += scale_round(xa, s_alpha); else bad_a = true;
         if (__builtin_isfinite(xg)) a_gain += scale_round(xg, s_gain); else bad_g = true;
-        if (__builtin_isfinite(xs)) a_ssm += scale_round(xs, s_ssm); else bad_s = true;
     }, []() {});
 
     // 4. workgroup sums (integers: any order; doubles: a fixed order)
