@@ -422,6 +422,43 @@ int autotune(oceansim_plan *p, hipStream_t st) {
         // which would favour the candidates timed later
         if (c.ok) c.us = time_us(run, st, k == 0 ? 10 : 1);
     }
+    // One pass over the candidates is at the mercy of clock and power drift
+    // along the sweep: the three fastest are timed again, interleaved over
+    // three rounds, and each keeps its best time.
+    if (rc == OCEANSIM_OK) {
+        std::vector<size_t> top;
+        for (size_t k = 0; k < cands.size(); ++k)
+            if (cands[k].ok) top.push_back(k);
+        std::sort(top.begin(), top.end(), [&](size_t a, size_t b) { return cands[a].us < cands[b].us; });
+        if (top.size() > 3) top.resize(3);
+        for (int round = 0; round < 3 && top.size() > 1; ++round)
+            for (size_t k : top) {
+                Candidate &c = cands[k];
+                carve_sonar(c.f, tmp, false);
+                e = upload_table(c.f.dev, tmp, c.f.off_table, st);
+                const SonarDev *table = reinterpret_cast<const SonarDev *>(tmp + c.f.off_table);
+                const SonarDev *table_b = nullptr;
+                if (with_bwd && e == hipSuccess) {
+                    carve_sonar(c.b, tmp_b, true);
+                    link_pairs(c.b, c.f);
+                    e = upload_table(c.b.dev, tmp_b, c.b.off_table, st);
+                    table_b = reinterpret_cast<const SonarDev *>(tmp_b + c.b.off_table);
+                }
+                if (e != hipSuccess) break;
+                auto run = [&]() {
+                    hipError_t r = sonar_forward_table(table, n, c.f.grid, p->sp, p->refl, p->n_mat, st,
+                                                       uw_table ? &uwc : nullptr);
+                    if (r == hipSuccess && table_b)
+                        r = sonar_backward_table(table_b, n, c.b.grid, p->sp, p->n_srows, p->refl, p->n_mat,
+                                                 reinterpret_cast<double *>(tmp_b + c.b.off_part),
+                                                 reinterpret_cast<double *>(tmp_b + c.b.off_refl_part), p->g_sp,
+                                                 p->g_refl, st);
+                    return r;
+                };
+                c.us = std::min(c.us, time_us(run, st));
+            }
+        if (e != hipSuccess) rc = hip_fail(e, "autotune re-timing");
+    }
     size_t best = 0;
     for (size_t k = 1; k < cands.size(); ++k)
         if (cands[k].ok && cands[k].us < cands[best].us) best = k;
