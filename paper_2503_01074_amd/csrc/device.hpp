@@ -304,9 +304,11 @@ __device__ __forceinline__ float neg_ln(float u) {
     return -__builtin_amdgcn_logf(u) * 0.69314718055994531f;
 }
 
-// Unit Rayleigh variate of bin b (additive stream, Eq. 4 with sigma = 1).
+// Unit Rayleigh variate of bin b (additive stream, Eq. 4 with sigma = 1):
+// sqrt(-2 ln u), the factor 2 folded into the constant of neg_ln (scaling by
+// two is exact, so this is sqrt(2 neg_ln(u)) bit for bit).
 __device__ __forceinline__ float rayleigh_of_word(uint32_t w) {
-    return __builtin_amdgcn_sqrtf(2.0f * neg_ln(unit_uniform(w)));
+    return __builtin_amdgcn_sqrtf(__builtin_amdgcn_logf(unit_uniform(w)) * -1.38629436111989062f);
 }
 
 // Multiplicative speckle factor of bin b and, in PAPER mode, its standard

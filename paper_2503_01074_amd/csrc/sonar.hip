@@ -1374,8 +1374,10 @@ __device__ __forceinline__ void pair_bwd_block(const Src &src, const oceansim_so
     const bool row_groups = f.n_az >= 4;   // with COL_REGS: a group of four bins lies in row b >> az_shift
     const int az_shift = __builtin_ctz((unsigned)f.n_az);
     // COL_REGS: the thread's four columns' E_j and phi_j^2 E_j, and per column
-    // the sum of dL/dI~ R_i rho over the thread's rows
-    double ecol[4] = {0.0, 0.0, 0.0, 0.0}, pecol[4] = {0.0, 0.0, 0.0, 0.0}, scol[4] = {0.0, 0.0, 0.0, 0.0};
+    // the sum of dL/dI~ R_i rho over the thread's rows (a few groups per
+    // thread: summed in FP32, then combined in FP64)
+    double ecol[4] = {0.0, 0.0, 0.0, 0.0}, pecol[4] = {0.0, 0.0, 0.0, 0.0};
+    float scol[4] = {0.0f, 0.0f, 0.0f, 0.0f};
     if (COL_REGS && add_adj) {
         // n_az divides 4 kWideThreads, a power of two: the column of bin b is b & (n_az - 1)
         const int am = f.n_az - 1;
@@ -1408,21 +1410,24 @@ __device__ __forceinline__ void pair_bwd_block(const Src &src, const oceansim_so
             for (int w = 0; w < 4; ++w) g[w] = in[w] ? gsrc[b0 + w] : 0.0f;
         }
 #pragma unroll
-        for (int w = 0; w < 4; ++w) {
-            if (!in[w]) continue;
-            gt[b0 + w - b_lo] = g[w];
-            const float a = __builtin_fabsf(g[w]);
-            if (a <= 3.4028235e38f && a > gmax) gmax = a;
+        for (int w = 0; w < 4; ++w)
+            if (in[w]) gt[b0 + w - b_lo] = g[w];
+        {
+            // the largest finite |dL/dI~| (bins outside the tile read as 0)
+            float a[4];
+#pragma unroll
+            for (int w = 0; w < 4; ++w) a[w] = __builtin_fabsf(g[w]) <= 3.4028235e38f ? __builtin_fabsf(g[w]) : 0.0f;
+            gmax = fmaxf(gmax, fmaxf(fmaxf(a[0], a[1]), fmaxf(a[2], a[3])));
         }
         if (add_adj && COL_REGS && row_groups) {
             // the group lies in one row
             const Words wd = philox((uint32_t)q, f.frame_id, 0u, 0u, f.seed_lo, f.seed_hi);
-            const double R = (double)range_ramp(f, b0 >> az_shift);
+            const float R = range_ramp(f, b0 >> az_shift);
 #pragma unroll
             for (int w = 0; w < 4; ++w)
                 if (in[w]) {
                     const float rho = rayleigh_of_word(pick(wd, (uint32_t)w));
-                    scol[w] += (double)g[w] * R * (double)rho;
+                    scol[w] = __builtin_fmaf(g[w] * rho, R, scol[w]);
                 }
         } else if (add_adj && COL_REGS) {
             const Words wd = philox((uint32_t)q, f.frame_id, 0u, 0u, f.seed_lo, f.seed_hi);
@@ -1433,7 +1438,7 @@ __device__ __forceinline__ void pair_bwd_block(const Src &src, const oceansim_so
             for (int w = 0; w < 4; ++w) {
                 if (in[w]) {
                     const float rho = rayleigh_of_word(pick(wd, (uint32_t)w));
-                    scol[w] += (double)g[w] * (double)R * (double)rho;
+                    scol[w] = __builtin_fmaf(g[w] * rho, R, scol[w]);
                 }
                 if (++j == f.n_az) {
                     j = 0;
@@ -1465,8 +1470,8 @@ __device__ __forceinline__ void pair_bwd_block(const Src &src, const oceansim_so
         // d add / d sigma_sa = sum 0.5 g R E rho, d add / d sigma_phi = sum g R E rho dsphi phi^2
 #pragma unroll
         for (int w = 0; w < 4; ++w) {
-            g_ssa += 0.5 * ecol[w] * scol[w];
-            g_sphi += dsphi * pecol[w] * scol[w];
+            g_ssa += 0.5 * ecol[w] * (double)scol[w];
+            g_sphi += dsphi * pecol[w] * (double)scol[w];
         }
     }
 #pragma unroll
