@@ -1312,13 +1312,15 @@ __device__ __forceinline__ long long scale_round(double x, double scale) {
 
 // 2^sc with |x| * 2^sc < 2^(50 - extra) for |x| <= bound, where 2^extra
 // covers the number of terms (n <= 2^(11 + extra)), so that a sum of up to n
-// scaled terms stays below 2^61.
-__device__ __forceinline__ int fixed_exponent(double bound, long long n) {
+// scaled terms stays below 2^61.  fixed_extra: extra for n terms (lg, the
+// smallest with 2^lg >= n, at most 62, from the leading zeros of n - 1).
+__device__ __forceinline__ int fixed_extra(long long n) {
+    const int lg = n <= 1 ? 0 : min(62, 64 - __builtin_clzll((unsigned long long)(n - 1)));
+    return lg > 11 ? lg - 11 : 0;
+}
+__device__ __forceinline__ int fixed_exponent(double bound, int extra) {
     int e = 0;
     if (bound > 0.0) frexp(bound, &e);   // bound < 2^e
-    int lg = 0;
-    while ((1LL << lg) < n && lg < 62) ++lg;
-    const int extra = lg > 11 ? lg - 11 : 0;
     return 50 - e - extra;
 }
 
@@ -1338,7 +1340,7 @@ __device__ __forceinline__ void pair_bwd_block(const Src &src, const oceansim_so
     __shared__ float refl_s[kLaneHistMats];
     __shared__ unsigned long long racc[kLaneHistMats];
     __shared__ unsigned long long rbad;
-    __shared__ float wmax[NW];
+    __shared__ float wmax[NW], wrmax[NW];
     __shared__ long long lred[3 * NW];
     __shared__ double dred[2 * NW];
     __shared__ unsigned bad_any;
@@ -1352,9 +1354,13 @@ __device__ __forceinline__ void pair_bwd_block(const Src &src, const oceansim_so
     float *gt = reinterpret_cast<float *>(lds_raw);   // [tile_bins]: dL/d(polar image) of the tile's bins
     const oceansim_sonar_params pr = params[f.param_row];
     const float G = pr.gain;
+    float rl = 0.0f;   // the largest finite |reflectivity| among the thread's materials
     for (int k = tid; k < n_mat; k += NT) {
-        refl_s[k] = refl[k];
+        const float r = refl[k];
+        refl_s[k] = r;
         racc[k] = 0ull;
+        const float a = __builtin_fabsf(r);
+        if (a <= 3.4028235e38f && a > rl) rl = a;
     }
     if (tid == 0) {
         rbad = 0ull;
@@ -1475,16 +1481,20 @@ __device__ __forceinline__ void pair_bwd_block(const Src &src, const oceansim_so
         }
     }
 #pragma unroll
-    for (int off = 32; off > 0; off >>= 1) gmax = fmaxf(gmax, __shfl_down(gmax, off, kWave));
-    if (lane == 0) wmax[wave] = gmax;
+    for (int off = 32; off > 0; off >>= 1) {
+        gmax = fmaxf(gmax, __shfl_down(gmax, off, kWave));
+        rl = fmaxf(rl, __shfl_down(rl, off, kWave));
+    }
+    if (lane == 0) {
+        wmax[wave] = gmax;
+        wrmax[wave] = rl;
+    }
     __syncthreads();
-    float Mg = 0.0f;
+    float Mg = 0.0f, Rmax = 0.0f;
 #pragma unroll
-    for (int k = 0; k < NW; ++k) Mg = fmaxf(Mg, wmax[k]);
-    float Rmax = 0.0f;
-    for (int k = 0; k < n_mat; ++k) {
-        const float a = __builtin_fabsf(refl_s[k]);
-        if (a <= 3.4028235e38f && a > Rmax) Rmax = a;
+    for (int k = 0; k < NW; ++k) {
+        Mg = fmaxf(Mg, wmax[k]);
+        Rmax = fmaxf(Rmax, wrmax[k]);
     }
 
     // 2. bounds of one return's contributions in this tile, and their scales
@@ -1502,9 +1512,9 @@ __device__ __forceinline__ void pair_bwd_block(const Src &src, const oceansim_so
     const double B_alpha = B_refl * (double)Rmax * f.kappa * r_hi * 1.001;        // |dL/dI I kappa r|
     const double B_gain = safety * Mm * (double)Mg * (double)Rmax * Emax;          // |dL/dQ I|
     const double B_ssm = safety * (double)Mg * absG * (double)Rmax * Emax * kGaussMax;   // |g G I z|
-    const long long n_terms = f.n > 0 ? f.n : 1;
-    const int e_refl = fixed_exponent(B_refl, n_terms), e_alpha = fixed_exponent(B_alpha, n_terms);
-    const int e_gain = fixed_exponent(B_gain, n_terms), e_ssm = fixed_exponent(B_ssm, n_terms);
+    const int extra = fixed_extra(f.n > 0 ? f.n : 1);
+    const int e_refl = fixed_exponent(B_refl, extra), e_alpha = fixed_exponent(B_alpha, extra);
+    const int e_gain = fixed_exponent(B_gain, extra), e_ssm = fixed_exponent(B_ssm, extra);
     // the scales are the same in every lane: held in scalar registers
     const double s_refl = uniform_f64(ldexp(1.0, min(e_refl, 1000)));
     const double s_alpha = uniform_f64(ldexp(1.0, min(e_alpha, 1000)));
