@@ -387,7 +387,12 @@ __device__ __forceinline__ void tile_fwd_block(const Src &src, const oceansim_so
     // side job for the fan launch that follows: {sin, cos} of the column-centre azimuths
     if (f.cols)
         for (int j = tile * NT + tid; j < f.n_az; j += f.n_tiles * NT) write_fan_column(f, j);
-    for (int k = tid; k < nbins; k += NT) acc[k] = 0.0f;
+    // the histogram starts 16-byte aligned: 16-byte stores while nbins is a
+    // multiple of four (acc is followed by the column table)
+    if ((nbins & 3) == 0)
+        for (int k = 4 * tid; k < nbins; k += 4 * NT) *reinterpret_cast<float4 *>(acc + k) = make_float4(0.f, 0.f, 0.f, 0.f);
+    else
+        for (int k = tid; k < nbins; k += NT) acc[k] = 0.0f;
     __syncthreads();
 
     // additive term of Eq. (3)-(4) for the group of four consecutive
@@ -484,15 +489,25 @@ __device__ __forceinline__ void tile_fwd_block(const Src &src, const oceansim_so
     }
 
     // out = Q m + additive term (speckle) or G P, groups of four bins, float4 stores
+    const bool acc_aligned = (b_lo & 3) == 0;   // a group's four bins are one 16-byte LDS load
     auto store_group = [&](int q, const float (&add)[4]) __attribute__((always_inline)) {
         const int b0 = q << 2;
         float out[4];
         bool in[4];
+        const bool full = b0 >= b_lo && b0 + 3 < b_hi;
+        float a[4];
+        if (full && acc_aligned) {
+            const float4 v = *reinterpret_cast<const float4 *>(acc + (b0 - b_lo));
+            a[0] = v.x;
+            a[1] = v.y;
+            a[2] = v.z;
+            a[3] = v.w;
+        }
 #pragma unroll
         for (int w = 0; w < 4; ++w) {
-            in[w] = b0 + w >= b_lo && b0 + w < b_hi;
-            const float a = in[w] ? acc[b0 + w - b_lo] : 0.0f;
-            out[w] = speckle ? a + add[w] : G * a;
+            in[w] = full || (b0 + w >= b_lo && b0 + w < b_hi);
+            if (!(full && acc_aligned)) a[w] = in[w] ? acc[b0 + w - b_lo] : 0.0f;
+            out[w] = speckle ? a[w] + add[w] : G * a[w];
         }
         if (in[0] && in[3]) {
             gstore((gptr<float4>)(f.polar + b0), make_float4(out[0], out[1], out[2], out[3]));
@@ -1415,9 +1430,14 @@ __device__ __forceinline__ void pair_bwd_block(const Src &src, const oceansim_so
 #pragma unroll
             for (int w = 0; w < 4; ++w) g[w] = in[w] ? gsrc[b0 + w] : 0.0f;
         }
+        if (in[0] && in[3] && (b_lo & 3) == 0) {
+            // one 16-byte LDS store (gt starts 16-byte aligned)
+            *reinterpret_cast<float4 *>(gt + (b0 - b_lo)) = make_float4(g[0], g[1], g[2], g[3]);
+        } else {
 #pragma unroll
-        for (int w = 0; w < 4; ++w)
-            if (in[w]) gt[b0 + w - b_lo] = g[w];
+            for (int w = 0; w < 4; ++w)
+                if (in[w]) gt[b0 + w - b_lo] = g[w];
+        }
         {
             // the largest finite |dL/dI~| (bins outside the tile read as 0)
             float a[4];
