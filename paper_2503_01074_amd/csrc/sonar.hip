@@ -233,7 +233,7 @@ __device__ __forceinline__ void write_fan_column(const SonarDev &f, int j) {
 // binning chunk, so the cache line at each segment boundary is shared by two
 // tiles: the tile kernels give each XCD runs of this many consecutive tiles
 // (read through one L2) instead of every eighth tile.
-constexpr int kTileXcdRun = 16;
+constexpr int kTileXcdRun = 8;
 constexpr int kTileLoads = 8;      // pair gathers in flight per thread of a forward tile
 constexpr int kPairBwdLoads = 4;   // ... of a pair backward tile (more would cost occupancy)
 
